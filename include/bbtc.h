@@ -1,0 +1,194 @@
+/*
+ * bbtc.h -- C ABI of the MI355X block-based triangle counting library.
+ *
+ * Method: Yasar, Rajamanickam, Berry, Catalyurek, "Block-Based Triangle
+ * Counting Algorithm for Heterogeneous Environments" (arXiv 2009.12457).
+ *
+ *   - Vertices are renumbered in non-decreasing degree order and every edge
+ *     is kept once, from the lower to the higher rank (Sec. 2 and 4.1).
+ *   - The rank range is cut into p contiguous parts V_0..V_{p-1} with one cut
+ *     vector for rows and columns (symmetric rectilinear partition, Sec. 4.1);
+ *     block G_ab holds the edges from V_a to V_b, a <= b.
+ *   - Every triple i <= j <= k is a task over the blocks G_ij, G_jk, G_ik
+ *     (Sec. 4.2, Alg. 4), |T| = p(p+1)(p+2)/6.
+ *   - A task counts, for each u in V_i and each v in N(G_ij,u), the common
+ *     elements of N(G_ik,u) and N(G_jk,v) (Sec. 4.3, the Intersect and HMap
+ *     per-task algorithms).  Each triangle is counted by exactly one task, so
+ *     the total is the sum of the per-task counts.
+ *
+ * All counting is exact 64-bit integer arithmetic.
+ *
+ * Conventions for every entry point:
+ *   - No exception crosses this boundary; every call returns a status and a
+ *     failing call leaves a message for bbtc_last_error() on that thread.
+ *   - Input buffers stay owned by the caller and may be freed as soon as the
+ *     call returns (the library copies what it keeps).
+ *   - A plan owns all of its host and device memory; it is used by one stream
+ *     at a time.  Different plans may be used concurrently.
+ *   - `stream` arguments are hipStream_t values passed as void* (NULL = the
+ *     null stream).
+ */
+#ifndef BBTC_H_
+#define BBTC_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t bbtc_status;
+#define BBTC_OK 0
+#define BBTC_EINVAL (-1)  /* malformed graph, options or arguments */
+#define BBTC_ENOMEM (-2)  /* a host or device allocation failed */
+#define BBTC_EBUDGET (-3) /* the device budget cannot hold even one unit of work */
+#define BBTC_EDEVICE (-4) /* a HIP call failed */
+#define BBTC_ESTATE (-5)  /* the call does not fit the plan's state */
+
+/* bbtc_csr.flags */
+#define BBTC_CSR_DEVICE 1u  /* rowptr/colidx are device pointers (else host) */
+#define BBTC_CSR_TRUSTED 2u /* skip the O(nnz log d) symmetry check */
+
+/*
+ * A simple undirected graph G=(V,E) (Sec. 2) as a symmetric CSR: both
+ * directions of every edge are stored, each row strictly increasing, no
+ * self-loops.  n = |V| < 2^31; nnz = 2|E| and |E| < 2^32.
+ * rowptr has n+1 entries of rowptr_bits (32 or 64) bits, rowptr[0] = 0 and
+ * rowptr[n] = nnz.  colidx has nnz entries in [0, n).
+ * Host inputs are validated on the host before any device call; device
+ * inputs are validated by a kernel.  Either way a violation returns
+ * BBTC_EINVAL.
+ */
+typedef struct bbtc_csr {
+  int64_t n;
+  int64_t nnz;
+  const void* rowptr;
+  int32_t rowptr_bits;
+  uint32_t flags;
+  const int32_t* colidx;
+} bbtc_csr;
+
+/* bbtc_options.mode */
+#define BBTC_MODE_PERSISTENT 0      /* one work-stealing launch over all tasks */
+#define BBTC_MODE_PLAIN_INTERSECT 1 /* one launch per task, list intersection */
+#define BBTC_MODE_PLAIN_HMAP 2      /* one launch per task, LDS hash/bitmap */
+
+/* bbtc_options.cut_mode */
+#define BBTC_CUT_BALANCED 0 /* parts of ~m/p oriented entries each */
+#define BBTC_CUT_UNIFORM 1  /* parts of ~n/p vertices each */
+
+/*
+ * Tuning knobs.  None of them changes any result: every choice counts each
+ * triangle exactly once.  Zero selects the library default.
+ *   p             blocks per side, 1 <= p <= min(n, 2048); 0 = p from the
+ *                 average degree (Sec. 7.2 suggests p near the average degree).
+ *   wave_min      rows u with d(G_ij,u) >= wave_min are processed by a whole
+ *                 64-lane wavefront; shorter rows by one lane each.
+ *   hash_min      wavefront rows with |N(G_ik,u)| >= hash_min probe an LDS hash
+ *                 or bitmap of N(G_ik,u) (the HMap form); shorter ones binary
+ *                 search a sorted LDS copy (the Intersect form).  -1 = never.
+ *   grid          workgroups of the persistent launch; 0 = by occupancy.
+ *   item_rows     rows of G_ij per persistent work item.
+ *   device_budget_bytes  upper bound on the plan's device memory (0 = none).
+ */
+typedef struct bbtc_options {
+  int32_t p;
+  int32_t cut_mode;
+  int32_t mode;
+  int32_t wave_min;
+  int32_t hash_min;
+  int32_t grid;
+  int32_t item_rows;
+  int32_t reserved0;
+  int64_t device_budget_bytes;
+} bbtc_options;
+
+/* Task kinds: EMPTY tasks have an empty block and count 0 without work. */
+#define BBTC_TASK_EMPTY 0
+#define BBTC_TASK_WORK 1
+
+/*
+ * One task {i,j,k}, i <= j <= k (Sec. 4.2).  `est` is the workload estimate
+ * |E(G_ij)| * max(delta(G_ik), delta(G_jk)) with delta(G_ab) = |E(G_ab)|/|V_a|
+ * (Sec. 5), used only to order the work (non-increasing, ties by (i,j,k)).
+ */
+typedef struct bbtc_task {
+  int32_t i, j, k;
+  int32_t kind;
+  double est;
+} bbtc_task;
+
+/* Plan statistics (the quantities of the complexity analysis, Sec. 4.4). */
+typedef struct bbtc_stats {
+  int64_t n, m, p;
+  int64_t ntasks, work_tasks, nitems;
+  int64_t m_max;        /* largest block |E(G_ab)| */
+  double m_avg;         /* 2m / (p(p+1)) */
+  double lambda;        /* m_max / m_avg */
+  int64_t d_max;        /* largest oriented degree */
+  int64_t d_max_block;  /* largest partial degree d(G_ab,u) */
+  double c;             /* d_max / d_max_block */
+  int64_t wedges;       /* sum over oriented edges (u,v) of d(G,v): the probe volume */
+  int64_t bytes_colidx; /* 4 * (p+2) * m: each task's three blocks read once */
+  int64_t bytes_rowidx; /* block row-index bytes the tasks read */
+  int64_t bytes_total;  /* bytes_colidx + bytes_rowidx + 8 |T| */
+  int64_t footprint;    /* device bytes held by the plan */
+  double partition_ms;  /* wall time of the last bbtc_partition */
+} bbtc_stats;
+
+typedef struct bbtc_plan bbtc_plan;
+
+/* Fills `opt` with the defaults (all knobs 0 = automatic, persistent mode). */
+void bbtc_options_default(bbtc_options* opt);
+
+/*
+ * Degree ordering, orientation, symmetric rectilinear cut, block row
+ * indices and the task list (Sec. 4.1, 4.2, 5), all computed on the device.
+ * If *plan is NULL a new plan is created, otherwise it is rebuilt in place,
+ * reusing its device buffers when they are large enough.  Returns when the
+ * plan is ready (the call synchronises `stream`).  On failure *plan is left
+ * as it was (a new plan is not created).
+ */
+bbtc_status bbtc_partition(const bbtc_csr* g, const bbtc_options* opt, void* stream, bbtc_plan** plan);
+
+/*
+ * Counts every task of the plan (Sec. 4.3) and the total.  d_per_task is
+ * device memory for ntasks uint64 in the order of bbtc_plan_tasks; d_total
+ * is device memory for one uint64.  Both are overwritten.  Asynchronous:
+ * results are valid once `stream` has completed the enqueued work.
+ */
+bbtc_status bbtc_count(bbtc_plan* plan, void* stream, uint64_t* d_per_task, uint64_t* d_total);
+
+/*
+ * Several plans counted by shared persistent launches (continuous batching).
+ * d_per_task[q] and d_totals + q receive plan q's results, exactly as
+ * bbtc_count would.  Plans must not be in use on another stream.
+ */
+bbtc_status bbtc_count_multi(bbtc_plan* const* plans, int32_t nplans, void* stream,
+                             uint64_t* const* d_per_task, uint64_t* d_totals);
+
+/* Borrowed host views, valid until the plan is rebuilt or destroyed. */
+bbtc_status bbtc_plan_tasks(const bbtc_plan* plan, const bbtc_task** tasks, int64_t* ntasks);
+bbtc_status bbtc_plan_cuts(const bbtc_plan* plan, const int32_t** cuts, int32_t* p);
+/* Block sizes |E(G_ab)|, a <= b, row-major: p(p+1)/2 entries. */
+bbtc_status bbtc_plan_block_nnz(const bbtc_plan* plan, const int64_t** nnz, int64_t* nblocks);
+bbtc_status bbtc_plan_stats(const bbtc_plan* plan, bbtc_stats* out);
+
+/*
+ * Copies of device-resident plan arrays into caller memory (host or device),
+ * enqueued on `stream` and complete when it is.
+ *   perm: n int32, the rank of each original vertex id.
+ *   orow: n+1 uint32 and ocol: m int32, the oriented CSR in rank space.
+ */
+bbtc_status bbtc_plan_copy_perm(const bbtc_plan* plan, int32_t* dst, void* stream);
+bbtc_status bbtc_plan_copy_oriented(const bbtc_plan* plan, uint32_t* orow, int32_t* ocol, void* stream);
+
+void bbtc_plan_destroy(bbtc_plan* plan);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* bbtc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BBTC_H_ */

@@ -1,0 +1,98 @@
+// Device helpers shared by the preprocessing and counting kernels (gfx950,
+// 64-lane wavefronts).  Internal to the library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bbtc {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+// Orders LDS traffic of one wavefront: every lane's earlier LDS writes are
+// visible to every lane's later LDS reads.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
+  return (uint32_t)__popcll(mask & __lanemask_lt());
+}
+
+// Inclusive prefix sum over the 64 lanes of a wavefront.
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v) {
+  const int l = lane_id();
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    uint32_t t = __shfl_up(v, o, kWave);
+    if (l >= o) v += t;
+  }
+  return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_incl_scan_u64(unsigned long long v) {
+  const int l = lane_id();
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    unsigned long long t = __shfl_up(v, o, kWave);
+    if (l >= o) v += t;
+  }
+  return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    uint32_t t = __shfl_xor(v, o, kWave);
+    v = t > v ? t : v;
+  }
+  return v;
+}
+
+// Exclusive scan of one value per thread over a 256-thread workgroup.
+// `lds` needs 4 slots.  Contains barriers: call from uniform control flow.
+template <typename T>
+__device__ __forceinline__ T block256_excl_scan(T v, T* lds, T* total) {
+  const int l = lane_id(), w = threadIdx.x / kWave;
+  T inc;
+  if constexpr (sizeof(T) == 8)
+    inc = (T)wave_incl_scan_u64((unsigned long long)v);
+  else
+    inc = (T)wave_incl_scan_u32((uint32_t)v);
+  if (l == kWave - 1) lds[w] = inc;
+  __syncthreads();
+  T off = 0, tot = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    T s = lds[q];
+    if (q < w) off += s;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return off + inc - v;
+}
+
+__device__ __forceinline__ unsigned long long block256_sum_u64(unsigned long long v,
+                                                               unsigned long long* lds) {
+  v = wave_sum_u64(v);
+  const int w = threadIdx.x / kWave;
+  if (lane_id() == 0) lds[w] = v;
+  __syncthreads();
+  unsigned long long s = lds[0] + lds[1] + lds[2] + lds[3];
+  __syncthreads();
+  return s;
+}
+
+}  // namespace bbtc

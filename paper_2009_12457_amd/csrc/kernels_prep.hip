@@ -1,0 +1,512 @@
+// Preprocessing kernels: input validation, degree ordering, orientation, the
+// symmetric rectilinear cut and the block row index (arXiv 2009.12457,
+// Sec. 2 and 4.1).  Everything runs on the device; the host only sizes
+// buffers between steps.
+#include <algorithm>
+
+#include "bbtc_internal.h"
+#include "dev_common.h"
+
+namespace bbtc {
+
+namespace {
+
+inline unsigned grid_for(uint64_t work_items, unsigned per_block, unsigned cap = 1u << 20) {
+  uint64_t g = (work_items + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+// Wave-per-row grid: enough waves to fill the chip several times over.
+constexpr unsigned kRowGrid = 8192;  // workgroups (4 waves each)
+
+// ------------------------------------------------------------ validation
+// Checks a symmetric CSR: rows within [0, nnz], entries in [0, n), strictly
+// increasing, no self-loop, and (optionally) every (x,y) mirrored by (y,x).
+// Every index is clamped before use, so malformed input cannot read out of
+// bounds.  Error bits: 1 range, 2 order, 4 self-loop, 8 rowptr, 16 asymmetric.
+template <typename RP>
+__global__ __launch_bounds__(kThreads) void k_validate(const RP* __restrict__ rowptr,
+                                                       const int32_t* __restrict__ colidx, int64_t n,
+                                                       int64_t nnz, int symmetric, uint32_t* err) {
+  const int l = lane_id();
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  uint32_t e = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if ((int64_t)rowptr[0] != 0 || (int64_t)rowptr[n] != nnz) e |= 8;
+  }
+  for (int64_t x = wave; x < n; x += nwaves) {
+    int64_t b = (int64_t)rowptr[x], en = (int64_t)rowptr[x + 1];
+    if (b < 0 || en < b || en > nnz) {
+      e |= 8;
+      continue;
+    }
+    for (int64_t base = b; base < en; base += kWave) {
+      int64_t q = base + l;
+      if (q >= en) continue;
+      int32_t y = colidx[q];
+      if (y < 0 || y >= n) {
+        e |= 1;
+        continue;
+      }
+      if (y == x) e |= 4;
+      if (q > b && colidx[q - 1] >= y) e |= 2;
+      if (symmetric) {
+        int64_t lo = (int64_t)rowptr[y], hi = (int64_t)rowptr[y + 1];
+        if (lo < 0 || hi < lo || hi > nnz) {
+          e |= 8;
+          continue;
+        }
+        while (lo < hi) {  // lower_bound of x in row y
+          int64_t mid = (lo + hi) >> 1;
+          if (colidx[mid] < x) lo = mid + 1; else hi = mid;
+        }
+        if (lo >= (int64_t)rowptr[y + 1] || colidx[lo] != x) e |= 16;
+      }
+    }
+  }
+  if (e) atomicOr(err, e);
+}
+
+template <typename RP>
+__global__ __launch_bounds__(kThreads) void k_degkey(const RP* __restrict__ rowptr, int64_t n, int idbits,
+                                                     uint64_t* __restrict__ keys) {
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t d = (uint64_t)((int64_t)rowptr[x + 1] - (int64_t)rowptr[x]);
+    keys[x] = (d << idbits) | (uint64_t)x;
+  }
+}
+
+// ------------------------------------------------------------ prefix scan
+__device__ __forceinline__ uint32_t tile_load(const uint32_t* in, uint64_t i, uint64_t count) {
+  return i < count ? in[i] : 0u;
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_reduce(const uint32_t* __restrict__ in, uint64_t count,
+                                                          uint32_t* __restrict__ partial) {
+  __shared__ uint32_t lds[4];
+  const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+  uint32_t s = 0;
+#pragma unroll
+  for (int r = 0; r < kScanItems; ++r) s += tile_load(in, base + (uint64_t)r * kThreads + threadIdx.x, count);
+  uint32_t tot;
+  block256_excl_scan<uint32_t>(s, lds, &tot);
+  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+// One workgroup: exclusive scan of the tile sums in place, grand total to *total.
+__global__ __launch_bounds__(kThreads) void k_scan_spine(uint32_t* __restrict__ partial, uint64_t nparts,
+                                                         uint32_t* __restrict__ total) {
+  __shared__ uint32_t lds[4];
+  uint32_t carry = 0;
+  for (uint64_t base = 0; base < nparts; base += kThreads) {
+    uint64_t i = base + threadIdx.x;
+    uint32_t v = i < nparts ? partial[i] : 0u;
+    uint32_t tot;
+    uint32_t ex = block256_excl_scan<uint32_t>(v, lds, &tot);
+    if (i < nparts) partial[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) *total = carry;
+}
+
+// Blocked arrangement: thread t owns items [t*kScanItems, (t+1)*kScanItems).
+__global__ __launch_bounds__(kThreads) void k_scan_down(const uint32_t* in, uint32_t* out, uint64_t count,
+                                                        const uint32_t* __restrict__ partial) {
+  __shared__ uint32_t lds[4];
+  const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  uint32_t s = 0;
+#pragma unroll
+  for (int r = 0; r < kScanItems; ++r) {
+    v[r] = tile_load(in, base + r, count);
+    s += v[r];
+  }
+  uint32_t tot;
+  uint32_t run = partial[blockIdx.x] + block256_excl_scan<uint32_t>(s, lds, &tot);
+#pragma unroll
+  for (int r = 0; r < kScanItems; ++r) {
+    if (base + r < count) out[base + r] = run;
+    run += v[r];
+  }
+}
+
+// ------------------------------------------------------------ radix sort
+// Stable LSD radix sort of 64-bit keys, 8 bits per pass: per-tile digit
+// histograms, one global exclusive scan over (digit, tile), then a stable
+// scatter in which every key's rank among equal digits follows input order.
+__global__ __launch_bounds__(kThreads) void k_radix_hist(const uint64_t* __restrict__ keys, uint64_t count,
+                                                         int shift, uint32_t* __restrict__ hist, uint32_t ntiles) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const uint64_t base = (uint64_t)blockIdx.x * kRadixTile;
+  for (int r = 0; r < kRadixItems; ++r) {
+    uint64_t i = base + (uint64_t)r * kThreads + threadIdx.x;
+    if (i < count) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[(uint64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint64_t* __restrict__ kin,
+                                                            uint64_t* __restrict__ kout, uint64_t count, int shift,
+                                                            const uint32_t* __restrict__ hist, uint32_t ntiles) {
+  __shared__ uint32_t next[256];     // next output slot per digit for this tile
+  __shared__ uint32_t wbase[4][256]; // per-wave counts, then per-wave bases
+  const int t = threadIdx.x, w = t / kWave;
+  next[t] = hist[(uint64_t)t * ntiles + blockIdx.x];
+  const uint64_t base = (uint64_t)blockIdx.x * kRadixTile;
+  for (int r = 0; r < kRadixItems; ++r) {
+    const uint64_t i = base + (uint64_t)r * kThreads + t;
+    const bool valid = i < count;
+    const uint64_t key = valid ? kin[i] : 0ull;
+    const uint32_t d = (uint32_t)(key >> shift) & 255u;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) wbase[q][t] = 0;
+    __syncthreads();
+    uint64_t same = ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const bool on = (d >> bit) & 1u;
+      const uint64_t b = ballot(on);
+      same &= on ? b : ~b;
+    }
+    const uint32_t below = lanes_below(same);
+    if (valid && below == 0) wbase[w][d] = (uint32_t)__popcll(same);
+    __syncthreads();
+    {  // thread t owns digit t
+      uint32_t c0 = wbase[0][t], c1 = wbase[1][t], c2 = wbase[2][t], c3 = wbase[3][t];
+      uint32_t b0 = next[t];
+      wbase[0][t] = b0;
+      wbase[1][t] = b0 + c0;
+      wbase[2][t] = b0 + c0 + c1;
+      wbase[3][t] = b0 + c0 + c1 + c2;
+      next[t] = b0 + c0 + c1 + c2 + c3;
+    }
+    __syncthreads();
+    const uint32_t dst = wbase[w][d] + below;
+    if (valid && dst < count) kout[dst] = key;
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_perm(const uint64_t* __restrict__ keys, int64_t n, uint64_t mask,
+                                                   int32_t* __restrict__ order, int32_t* __restrict__ perm) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t x = (int64_t)(keys[r] & mask);
+    if (x < n) {
+      order[r] = (int32_t)x;
+      perm[x] = (int32_t)r;
+    }
+  }
+}
+
+// ------------------------------------------------------------ orientation
+// One wavefront per original vertex x: its neighbours y with rank(y) >
+// rank(x) form the oriented row of rank(x).
+template <typename RP>
+__global__ __launch_bounds__(kThreads) void k_outdeg(const RP* __restrict__ rowptr, const int32_t* __restrict__ colidx,
+                                                     int64_t n, const int32_t* __restrict__ perm,
+                                                     uint32_t* __restrict__ od) {
+  const int l = lane_id();
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  for (int64_t x = wave; x < n; x += nwaves) {
+    const int32_t r = perm[x];
+    if (r < 0 || r >= n) continue;
+    const int64_t b = (int64_t)rowptr[x], e = (int64_t)rowptr[x + 1];
+    uint32_t c = 0;
+    for (int64_t base = b; base < e; base += kWave) {
+      int64_t q = base + l;
+      bool up = q < e && perm[colidx[q]] > r;
+      c += (uint32_t)__popcll(ballot(up));
+    }
+    if (l == 0) od[r] = c;
+  }
+}
+
+template <typename RP>
+__global__ __launch_bounds__(kThreads) void k_fill(const RP* __restrict__ rowptr, const int32_t* __restrict__ colidx,
+                                                   int64_t n, const int32_t* __restrict__ perm,
+                                                   const uint32_t* __restrict__ orow, int idbits,
+                                                   uint64_t* __restrict__ keys, uint64_t cap) {
+  const int l = lane_id();
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  for (int64_t x = wave; x < n; x += nwaves) {
+    const int32_t r = perm[x];
+    if (r < 0 || r >= n) continue;
+    const int64_t b = (int64_t)rowptr[x], e = (int64_t)rowptr[x + 1];
+    uint64_t pos = orow[r];
+    const uint64_t hi = (uint64_t)r << idbits;
+    for (int64_t base = b; base < e; base += kWave) {
+      int64_t q = base + l;
+      int32_t ry = q < e ? perm[colidx[q]] : -1;
+      bool up = ry > r;
+      uint64_t mask = ballot(up);
+      const uint64_t dst = pos + lanes_below(mask);
+      if (up && dst < cap) keys[dst] = hi | (uint64_t)ry;
+      pos += (uint64_t)__popcll(mask);
+    }
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_unpack(const uint64_t* __restrict__ keys, uint64_t m, uint64_t mask,
+                                                     int32_t* __restrict__ ocol) {
+  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (uint64_t)gridDim.x * blockDim.x)
+    ocol[e] = (int32_t)(keys[e] & mask);
+}
+
+// ------------------------------------------------------------ cut vector
+// c_0 = 0, c_p = n; balanced: c_i = the smallest x > c_{i-1} with
+// orow[x] >= ceil(i*m/p); uniform: c_i = floor(i*n/p).  Either is clamped
+// into [c_{i-1}+1, n-(p-i)] so that no part is empty.
+__global__ void k_cuts(const uint32_t* __restrict__ orow, int64_t n, int32_t p, int mode, int32_t* __restrict__ cuts) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  const uint64_t m = orow[n];
+  int64_t prev = 0;
+  cuts[0] = 0;
+  for (int32_t i = 1; i < p; ++i) {
+    int64_t c;
+    if (mode == BBTC_CUT_UNIFORM) {
+      c = (int64_t)i * n / p;
+    } else {
+      const uint64_t target = ((uint64_t)i * m + (uint64_t)p - 1) / (uint64_t)p;
+      int64_t lo = prev + 1, hi = n;
+      while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if ((uint64_t)orow[mid] < target) lo = mid + 1; else hi = mid;
+      }
+      c = lo;
+    }
+    if (c < prev + 1) c = prev + 1;
+    if (c > n - (p - i)) c = n - (p - i);
+    cuts[i] = (int32_t)c;
+    prev = c;
+  }
+  cuts[p] = (int32_t)n;
+}
+
+// ------------------------------------------------------------ block row index
+// Workgroup per chunk of kPrepRows consecutive rows of one part a; thread per
+// row.  The thread walks its sorted row once against the cut vector, writing
+// the row's block boundaries (bot) and counting per block the entries and the
+// non-empty rows.
+__device__ __forceinline__ int chunk_part(const int32_t* chunk0, int32_t p, int32_t c) {
+  int lo = 0, hi = p;  // largest a with chunk0[a] <= c
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (chunk0[mid] <= c) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(kThreads) void k_bot(BlockBuild bb) {
+  __shared__ uint32_t s_nnz[kMaxP];
+  __shared__ uint32_t s_nzr[kMaxP];
+  __shared__ uint32_t s_dmax, s_dfull;
+  const int32_t p = bb.p;
+  const int a = chunk_part(bb.chunk0, p, blockIdx.x);
+  const int lc = blockIdx.x - bb.chunk0[a];
+  const int nch = bb.chunk0[a + 1] - bb.chunk0[a];
+  const int nb = p - a;  // blocks (a,a)..(a,p-1)
+  for (int b = threadIdx.x; b < nb; b += kThreads) s_nnz[b] = s_nzr[b] = 0;
+  if (threadIdx.x == 0) s_dmax = s_dfull = 0;
+  __syncthreads();
+  const int64_t ca = bb.cuts[a];
+  const int64_t u = ca + (int64_t)lc * kPrepRows + threadIdx.x;
+  if (u < bb.cuts[a + 1]) {
+    const uint32_t rb = bb.orow[u], re = bb.orow[u + 1];
+    uint32_t* out = bb.bot + bb.botp[a] + (uint64_t)(u - ca) * (uint64_t)(nb + 1);
+    out[0] = rb;
+    uint32_t ptr = rb, prev = rb, dmax = 0;
+    for (int b = a + 1; b <= p; ++b) {
+      if (b == p) {
+        ptr = re;
+      } else {
+        const int32_t cb = bb.cuts[b];
+        if (re - ptr > 16) {  // long remainder: binary search
+          uint32_t lo = ptr, hi = re;
+          while (lo < hi) {
+            uint32_t mid = (lo + hi) >> 1;
+            if (bb.ocol[mid] < cb) lo = mid + 1; else hi = mid;
+          }
+          ptr = lo;
+        } else {
+          while (ptr < re && bb.ocol[ptr] < cb) ++ptr;
+        }
+      }
+      out[b - a] = ptr;
+      const uint32_t len = ptr - prev;
+      if (len) {
+        atomicAdd(&s_nnz[b - 1 - a], len);
+        atomicAdd(&s_nzr[b - 1 - a], 1u);
+        dmax = len > dmax ? len : dmax;
+      }
+      prev = ptr;
+    }
+    if (dmax) atomicMax(&s_dmax, dmax);
+    if (re > rb) atomicMax(&s_dfull, re - rb);
+  }
+  __syncthreads();
+  const int64_t bid0 = block_id(p, a, a);
+  for (int b = threadIdx.x; b < nb; b += kThreads) {
+    if (s_nnz[b]) {
+      atomicAdd(&bb.bnnz[bid0 + b], (unsigned long long)s_nnz[b]);
+      atomicAdd(&bb.bnzr[bid0 + b], (unsigned long long)s_nzr[b]);
+    }
+    bb.ccnt[bb.ccbase[a] + (uint64_t)b * nch + lc] = s_nzr[b];
+  }
+  if (threadIdx.x == 0) {
+    if (s_dmax) atomicMax(bb.dmax_block, s_dmax);
+    if (s_dfull) atomicMax(bb.dmax_block + 1, s_dfull);
+  }
+}
+
+// Same chunk mapping: writes each block's non-empty rows in increasing order
+// at the offsets given by the scanned chunk counters.
+__global__ __launch_bounds__(kThreads) void k_arow(BlockBuild bb) {
+  __shared__ uint32_t lds[4];
+  const int32_t p = bb.p;
+  const int a = chunk_part(bb.chunk0, p, blockIdx.x);
+  const int lc = blockIdx.x - bb.chunk0[a];
+  const int nch = bb.chunk0[a + 1] - bb.chunk0[a];
+  const int nb = p - a;
+  const int64_t ca = bb.cuts[a];
+  const int64_t u = ca + (int64_t)lc * kPrepRows + threadIdx.x;
+  const bool valid = u < bb.cuts[a + 1];
+  const uint32_t* row = bb.bot + bb.botp[a] + (uint64_t)(valid ? u - ca : 0) * (uint64_t)(nb + 1);
+  uint32_t lo = valid ? row[0] : 0u;
+  for (int b = 0; b < nb; ++b) {
+    uint32_t hi = valid ? row[b + 1] : 0u;
+    uint32_t f = (valid && hi > lo) ? 1u : 0u;
+    uint32_t tot;
+    uint32_t off = block256_excl_scan<uint32_t>(f, lds, &tot);
+    if (f) bb.arow[bb.ccoff[bb.ccbase[a] + (uint64_t)b * nch + lc] + off] = (int32_t)u;
+    lo = hi;
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ launchers
+hipError_t launch_validate(const void* rowptr, int rp64, const int32_t* colidx, int64_t n, int64_t nnz,
+                               int symmetric, uint32_t* err, hipStream_t s) {
+  if (rp64)
+    hipLaunchKernelGGL(k_validate<int64_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int64_t*)rowptr, colidx, n,
+                       nnz, symmetric, err);
+  else
+    hipLaunchKernelGGL(k_validate<int32_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int32_t*)rowptr, colidx, n,
+                       nnz, symmetric, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_degkey(const void* rowptr, int rp64, int64_t n, int idbits, uint64_t* keys, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  unsigned g = grid_for((uint64_t)n, kThreads, 65536);
+  if (rp64)
+    hipLaunchKernelGGL(k_degkey<int64_t>, dim3(g), dim3(kThreads), 0, s, (const int64_t*)rowptr, n, idbits, keys);
+  else
+    hipLaunchKernelGGL(k_degkey<int32_t>, dim3(g), dim3(kThreads), 0, s, (const int32_t*)rowptr, n, idbits, keys);
+  return hipGetLastError();
+}
+
+size_t scan_partial_entries(uint64_t count) { return (size_t)((count + kScanTile - 1) / kScanTile) + 1; }
+
+size_t radix_hist_entries(uint64_t count) {
+  uint64_t ntiles = (count + kRadixTile - 1) / kRadixTile;
+  return (size_t)(256 * ntiles + 1);
+}
+
+hipError_t scan_u32(const uint32_t* in, uint32_t* out, uint64_t count, uint32_t* partial, hipStream_t s) {
+  uint64_t nparts = (count + kScanTile - 1) / kScanTile;
+  if (nparts == 0) {
+    return hipMemsetAsync(out, 0, sizeof(uint32_t), s);
+  }
+  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nparts), dim3(kThreads), 0, s, in, count, partial);
+  hipLaunchKernelGGL(k_scan_spine, dim3(1), dim3(kThreads), 0, s, partial, nparts, out + count);
+  hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nparts), dim3(kThreads), 0, s, in, out, count,
+                     (const uint32_t*)partial);
+  return hipGetLastError();
+}
+
+hipError_t radix_sort_u64(uint64_t* a, uint64_t* b, uint64_t count, int bits, uint32_t* hist, uint32_t* partial,
+                          uint64_t** result, hipStream_t s) {
+  uint64_t* src = a;
+  uint64_t* dst = b;
+  if (count > 1) {
+    const uint64_t ntiles = (count + kRadixTile - 1) / kRadixTile;
+    for (int shift = 0; shift < bits; shift += 8) {
+      hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)ntiles), dim3(kThreads), 0, s, src, count, shift, hist,
+                         (uint32_t)ntiles);
+      hipError_t e = scan_u32(hist, hist, 256 * ntiles, partial, s);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)ntiles), dim3(kThreads), 0, s, src, dst, count, shift,
+                         hist, (uint32_t)ntiles);
+      std::swap(src, dst);
+    }
+  }
+  *result = src;
+  return hipGetLastError();
+}
+
+hipError_t launch_perm(const uint64_t* keys, int64_t n, int idbits, int32_t* order, int32_t* perm, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const uint64_t mask = (idbits >= 64) ? ~0ull : ((1ull << idbits) - 1);
+  hipLaunchKernelGGL(k_perm, dim3(grid_for((uint64_t)n, kThreads, 65536)), dim3(kThreads), 0, s, keys, n, mask, order,
+                     perm);
+  return hipGetLastError();
+}
+
+hipError_t launch_outdeg(const void* rowptr, int rp64, const int32_t* colidx, int64_t n, const int32_t* perm,
+                         uint32_t* od, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (rp64)
+    hipLaunchKernelGGL(k_outdeg<int64_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int64_t*)rowptr, colidx, n,
+                       perm, od);
+  else
+    hipLaunchKernelGGL(k_outdeg<int32_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int32_t*)rowptr, colidx, n,
+                       perm, od);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(const void* rowptr, int rp64, const int32_t* colidx, int64_t n, const int32_t* perm,
+                       const uint32_t* orow, int idbits, uint64_t* keys, uint64_t cap, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (rp64)
+    hipLaunchKernelGGL(k_fill<int64_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int64_t*)rowptr, colidx, n, perm,
+                       orow, idbits, keys, cap);
+  else
+    hipLaunchKernelGGL(k_fill<int32_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int32_t*)rowptr, colidx, n, perm,
+                       orow, idbits, keys, cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack(const uint64_t* keys, uint64_t m, int idbits, int32_t* ocol, hipStream_t s) {
+  if (m == 0) return hipSuccess;
+  const uint64_t mask = (1ull << idbits) - 1;
+  hipLaunchKernelGGL(k_unpack, dim3(grid_for(m, kThreads, 65536)), dim3(kThreads), 0, s, keys, m, mask, ocol);
+  return hipGetLastError();
+}
+
+hipError_t launch_cuts(const uint32_t* orow, int64_t n, int32_t p, int mode, int32_t* cuts, hipStream_t s) {
+  hipLaunchKernelGGL(k_cuts, dim3(1), dim3(64), 0, s, orow, n, p, mode, cuts);
+  return hipGetLastError();
+}
+
+hipError_t launch_bot(const BlockBuild& bb, hipStream_t s) {
+  if (bb.nchunks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bot, dim3(bb.nchunks), dim3(kThreads), 0, s, bb);
+  return hipGetLastError();
+}
+
+hipError_t launch_arow(const BlockBuild& bb, hipStream_t s) {
+  if (bb.nchunks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_arow, dim3(bb.nchunks), dim3(kThreads), 0, s, bb);
+  return hipGetLastError();
+}
+
+}  // namespace bbtc

@@ -1,0 +1,82 @@
+"""CPU-side checks of the C ABI: the library loads, exports every declared
+symbol, and host-side validation rejects malformed input before any device
+call (no GPU is needed for these)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2009_12457_amd as bb
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "bbtc.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bbtc_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert "bbtc_partition" in names and "bbtc_count" in names
+    lib = ctypes.CDLL(bb.LIB_PATH)
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(bb._SIGS), "binding and header disagree"
+
+
+def test_struct_sizes_match_header_layout():
+    assert ctypes.sizeof(bb.bbtc_csr) == 40
+    assert ctypes.sizeof(bb.bbtc_options) == 40
+    assert ctypes.sizeof(bb.bbtc_task) == 24
+
+
+def test_options_default():
+    o = bb.bbtc_options_default()
+    assert (o.p, o.mode, o.cut_mode, o.wave_min, o.hash_min, o.device_budget_bytes) == (0, 0, 0, 0, 0, 0)
+
+
+def _expect_einval(n, rowptr, colidx, **opts):
+    with pytest.raises(bb.BbtcError) as ei:
+        bb.bbtc_partition(n, np.asarray(rowptr, np.int64), np.asarray(colidx, np.int32),
+                          options=bb.bbtc_options_default(**opts))
+    assert ei.value.status == bb.BBTC_EINVAL, str(ei.value)
+    return str(ei.value)
+
+
+def test_host_validation_rejects_malformed_csr():
+    assert "self-loop" in _expect_einval(3, [0, 2, 3, 4], [0, 1, 0, 0])
+    assert "symmetric" in _expect_einval(3, [0, 1, 2, 2], [1, 2])
+    assert "increasing" in _expect_einval(3, [0, 2, 3, 4], [2, 1, 0, 0])
+    assert "increasing" in _expect_einval(3, [0, 2, 3, 4], [1, 1, 0, 0])  # duplicate
+    assert "range" in _expect_einval(3, [0, 1, 2, 2], [1, 7])
+    assert "rowptr" in _expect_einval(3, [1, 1, 2, 2], [1, 0])
+    assert "rowptr[n]" in _expect_einval(3, [0, 1, 2, 3], [1, 0])
+    assert "non-decreasing" in _expect_einval(3, [0, 2, 1, 2], [1, 0])
+
+
+def test_option_and_size_checks():
+    rp, ci = [0, 1, 2, 2], [1, 0]
+    assert "p must" in _expect_einval(3, rp, ci, p=4)      # p > n
+    assert "p must" in _expect_einval(3, rp, ci, p=-1)
+    assert "p must" in _expect_einval(3000, np.zeros(3001), [], p=2049)  # above the supported maximum
+    assert "cut_mode" in _expect_einval(3, rp, ci, cut_mode=7)
+    assert "mode" in _expect_einval(3, rp, ci, mode=9)
+    assert "negative" in _expect_einval(3, rp, ci, wave_min=-3)
+    assert "n must" in _expect_einval(0, [0], [])
+    assert "even" in _expect_einval(2, [0, 1, 1], [1])
+
+
+def test_rowptr_bits_check():
+    g = bb.bbtc_csr(n=2, nnz=2, rowptr=None, rowptr_bits=16, flags=0, colidx=None)
+    h = ctypes.c_void_p()
+    st = bb._lib.bbtc_partition(ctypes.byref(g), None, None, ctypes.byref(h))
+    assert st == bb.BBTC_EINVAL and not h.value
+
+
+def test_count_on_missing_plan_is_estate():
+    st = bb._lib.bbtc_count(None, None, None, None)
+    assert st == bb.BBTC_ESTATE

@@ -1,0 +1,222 @@
+"""GPU parity: the HIP path against the CPU oracle, element by element.
+
+Every comparison is exact (integer counts): the per-task vector (mapped by
+(i,j,k)), the total, the degree order, the oriented CSR, the cut vector and
+the block sizes.  All calls go through the C ABI (ctypes binding).
+"""
+import itertools
+
+import numpy as np
+import pytest
+import torch
+
+import graphgen
+import oracle
+import paper_2009_12457_amd as bb
+
+pytestmark = pytest.mark.gpu
+
+MODES = {"persistent": bb.BBTC_MODE_PERSISTENT, "intersect": bb.BBTC_MODE_PLAIN_INTERSECT,
+         "hmap": bb.BBTC_MODE_PLAIN_HMAP}
+
+_ORACLES = {}
+
+
+def oracle_for(g):
+    key = (g.name, g.n, int(g.rowptr[-1]))
+    if key not in _ORACLES or not g.name:
+        _ORACLES[key] = oracle.OracleGraph.from_graph(g)
+    return _ORACLES[key]
+
+
+def alg4_positions(p, tasks):
+    """Alg. 4 index of each (i,j,k) row of `tasks`."""
+    base = np.zeros((p, p), np.int64)
+    t = 0
+    for i in range(p):
+        for j in range(i, p):
+            base[i, j] = t
+            t += p - j
+    return base[tasks["i"], tasks["j"]] + (tasks["k"] - tasks["j"])
+
+
+def run(g, device_input=True, trusted=False, **opts):
+    n, rp, ci = bb.csr_of(g, "cuda" if device_input else None)
+    plan = bb.bbtc_partition(n, rp, ci, options=bb.bbtc_options_default(**opts), trusted=trusted)
+    per, tot = bb.bbtc_count(plan)
+    torch.cuda.synchronize()
+    return plan, per.cpu().numpy().view(np.uint64)[:plan.ntasks].copy(), int(tot.item())
+
+
+def check(g, plan, per, tot, cut_mode=bb.BBTC_CUT_BALANCED, deep=True):
+    og = oracle_for(g)
+    st = plan.stats()
+    p = int(st["p"])
+    cuts = plan.cuts()
+    assert np.array_equal(cuts, og.cuts(p, cut_mode)), "cut vector differs from the oracle's"
+    want_tot, want_per, want_bn = og.tasks(p, cuts)
+    tasks = plan.tasks()
+    assert len(tasks) == p * (p + 1) * (p + 2) // 6
+    pos = alg4_positions(p, tasks)
+    assert np.array_equal(np.sort(pos), np.arange(len(tasks))), "task list is not a permutation of Alg. 4"
+    got = np.zeros(len(tasks), np.uint64)
+    got[pos] = per
+    assert tot == want_tot, (tot, want_tot)
+    assert np.array_equal(got, want_per), "per-task counts differ"
+    assert np.array_equal(plan.block_nnz().astype(np.uint64), want_bn)
+    assert st["m"] == og.m
+    # LPT order: non-increasing estimate
+    assert np.all(np.diff(tasks["est"]) <= 0)
+    assert np.all(per[tasks["kind"] == bb.BBTC_TASK_EMPTY] == 0)
+    if deep:
+        assert np.array_equal(plan.perm(), og.rank()), "degree order differs"
+        orow, ocol = plan.oriented()
+        w_orow, w_ocol = og.oriented()
+        assert np.array_equal(orow.astype(np.int64), w_orow)
+        assert np.array_equal(ocol, w_ocol)
+
+
+# ---------------------------------------------------------------- C1
+@pytest.mark.parametrize("mode", list(MODES))
+def test_er2000_p4_all_modes(mode):
+    g = graphgen.workload("er2000")
+    plan, per, tot = run(g, p=4, mode=MODES[mode])
+    check(g, plan, per, tot)
+
+
+# ---------------------------------------------------------------- closed forms / edge cases
+def small_graph(n, edges, name=""):
+    e = np.asarray(edges, np.int64).reshape(-1, 2)
+    return graphgen.from_edges(n, e[:, 0], e[:, 1], name=name)
+
+
+def test_closed_forms_every_p():
+    from math import comb
+    cases = [
+        ("K40", 40, [(x, y) for x in range(40) for y in range(x + 1, 40)], comb(40, 3)),
+        ("W12", 13, [(x, (x + 1) % 12) for x in range(12)] + [(12, x) for x in range(12)], 12),
+        ("F7", 15, [e for t in range(7) for e in ((0, 2 * t + 1), (0, 2 * t + 2), (2 * t + 1, 2 * t + 2))], 7),
+        ("K5,6", 11, [(x, 5 + y) for x in range(5) for y in range(6)], 0),
+        ("K3,4,5", 12, [(x, y) for P, Q in itertools.combinations([range(0, 3), range(3, 7), range(7, 12)], 2)
+                        for x in P for y in Q], 60),
+    ]
+    for name, n, edges, want in cases:
+        g = small_graph(n, edges, name)
+        for p in sorted({1, 2, 3, n}):
+            for mode in MODES.values():
+                plan, per, tot = run(g, p=p, mode=mode)
+                assert tot == want, (name, p, mode)
+                check(g, plan, per, tot, deep=(p == 2))
+
+
+def test_empty_and_tiny_graphs():
+    for n, edges in [(1, []), (2, []), (7, []), (2, [(0, 1)]), (3, [(0, 1), (1, 2), (0, 2)]), (9, [(0, 8)])]:
+        g = small_graph(n, edges if edges else np.zeros((0, 2), np.int64))
+        for p in sorted({1, n}):
+            for mode in MODES.values():
+                plan, per, tot = run(g, device_input=(p == 1), p=p, mode=mode)
+                check(g, plan, per, tot)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_small_graphs(seed):
+    rng = np.random.default_rng(500 + seed)
+    n = int(rng.integers(3, 70))
+    e = rng.integers(0, n, size=(int(rng.integers(n, 8 * n)), 2))
+    g = graphgen.from_edges(n, e[:, 0], e[:, 1])
+    for p in sorted({1, 2, 5, n}):
+        p = min(p, n)
+        plan, per, tot = run(g, p=p, mode=MODES[["persistent", "intersect", "hmap"][seed % 3]],
+                             wave_min=int(rng.integers(1, 6)), hash_min=int(rng.choice([-1, 1, 3])))
+        check(g, plan, per, tot, deep=(p == 2))
+
+
+# ---------------------------------------------------------------- R-MAT sweeps
+@pytest.mark.parametrize("name", ["rmat10", "rmat12", "rmat14_ef8"])
+@pytest.mark.parametrize("p", [1, 4, 16, 61])
+def test_rmat_modes_and_p(name, p):
+    g = graphgen.workload(name)
+    for mode in MODES.values():
+        plan, per, tot = run(g, p=p, mode=mode)
+        check(g, plan, per, tot, deep=(p == 4 and mode == bb.BBTC_MODE_PERSISTENT))
+
+
+@pytest.mark.parametrize("wave_min,hash_min,item_rows", [(1, -1, 7), (1, 1, 1000), (3, 2, 256), (1000000, -1, 64),
+                                                         (2, 1000000, 32)])
+def test_row_mappings_are_exact(wave_min, hash_min, item_rows):
+    g = graphgen.workload("rmat13")
+    for p in (3, 20):
+        plan, per, tot = run(g, p=p, wave_min=wave_min, hash_min=hash_min, item_rows=item_rows)
+        check(g, plan, per, tot, deep=False)
+
+
+def test_uniform_cuts():
+    g = graphgen.workload("rmat12")
+    for p in (2, 9, 32):
+        plan, per, tot = run(g, p=p, cut_mode=bb.BBTC_CUT_UNIFORM)
+        check(g, plan, per, tot, cut_mode=bb.BBTC_CUT_UNIFORM, deep=False)
+
+
+def test_er_bitmap_and_hash_paths():
+    """Wide parts (|V_k| above the LDS bitmap) force the open-addressing hash."""
+    g = graphgen.er(200000, 24.0 / 199999, 9)
+    for p in (1, 2):  # parts of >= 100K vertices: hash; hash_min=1 routes every wave row there
+        plan, per, tot = run(g, p=p, wave_min=1, hash_min=1)
+        check(g, plan, per, tot, deep=False)
+
+
+def test_host_and_device_inputs_agree():
+    g = graphgen.workload("rmat12")
+    a = run(g, device_input=True, p=8)
+    b_ = run(g, device_input=False, p=8)
+    assert a[2] == b_[2] and np.array_equal(a[1], b_[1])
+    check(g, *a)
+
+
+def test_int32_rowptr_input():
+    g = graphgen.workload("rmat11")
+    plan = bb.bbtc_partition(g.n, torch.from_numpy(g.rowptr.astype(np.int32)).cuda(),
+                             torch.from_numpy(g.colidx).cuda(), options=bb.bbtc_options_default(p=6))
+    per, tot = bb.bbtc_count(plan)
+    torch.cuda.synchronize()
+    check(g, plan, per.cpu().numpy().view(np.uint64)[:plan.ntasks], int(tot.item()), deep=False)
+
+
+def test_repeat_and_rebuild_in_place():
+    g1 = graphgen.workload("rmat12")
+    g2 = graphgen.workload("er2000")
+    n, rp, ci = bb.csr_of(g1, "cuda")
+    plan = bb.bbtc_partition(n, rp, ci, options=bb.bbtc_options_default(p=10))
+    r = [bb.bbtc_count(plan) for _ in range(3)]
+    torch.cuda.synchronize()
+    vals = [(x[0].cpu().numpy().copy(), int(x[1].item())) for x in r]
+    for v in vals[1:]:
+        assert v[1] == vals[0][1] and np.array_equal(v[0], vals[0][0])
+    check(g1, plan, vals[0][0].view(np.uint64)[:plan.ntasks], vals[0][1], deep=False)
+    n2, rp2, ci2 = bb.csr_of(g2, "cuda")
+    plan = bb.bbtc_partition(n2, rp2, ci2, options=bb.bbtc_options_default(p=3), plan=plan)
+    per, tot = bb.bbtc_count(plan)
+    torch.cuda.synchronize()
+    check(g2, plan, per.cpu().numpy().view(np.uint64)[:plan.ntasks], int(tot.item()))
+
+
+def test_device_validation_rejects_bad_input():
+    cases = {
+        "self-loop": (3, [0, 2, 3, 4], [0, 1, 0, 0]),
+        "asymmetric": (3, [0, 1, 2, 2], [1, 2]),
+        "unsorted": (3, [0, 2, 3, 4], [2, 1, 0, 0]),
+        "range": (3, [0, 1, 2, 2], [1, 7]),
+    }
+    for name, (n, rp, ci) in cases.items():
+        with pytest.raises(bb.BbtcError) as ei:
+            bb.bbtc_partition(n, torch.tensor(rp, dtype=torch.int64, device="cuda"),
+                              torch.tensor(ci, dtype=torch.int32, device="cuda"))
+        assert ei.value.status == bb.BBTC_EINVAL, name
+
+
+# ---------------------------------------------------------------- C2 at full size
+@pytest.mark.parametrize("mode", list(MODES))
+def test_rmat20_p16_full_parity(mode):
+    g = graphgen.workload("rmat20")
+    plan, per, tot = run(g, trusted=True, p=16, mode=MODES[mode])
+    check(g, plan, per, tot, deep=(mode == "persistent"))
