@@ -1,0 +1,190 @@
+"""Benchmark: block-based triangle counting on one MI355X.
+
+One step = the whole hot path on a device-resident symmetric CSR: degree
+ordering, orientation, the p x p symmetric rectilinear cut, block row index
+and task list (bbtc_partition), then the batched persistent count of every
+task (bbtc_count).  `value` = undirected edges per second of that step.
+
+Also reported, from the same run: the count alone for the batched
+(persistent, work-stealing) kernel and for the unbatched one-launch-per-task
+Intersect and HMap forms; the roofline of the dominant kernel; and the CPU
+oracle timed on the host (a baseline, not the target).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rmat20]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "edges/s + HBM GB/s fraction, batched vs plain bbTC; p99 request latency"
+HBM_PEAK_GBS = 8000.0
+WORKLOADS = {
+    # name: (generator key, p, description)
+    "rmat20": ("rmat20", 16, "R-MAT scale 20, edge factor 16, (a,b,c,d)=(.57,.19,.19,.05), seed 20; p=16"),
+    "er2000": ("er2000", 4, "Erdos-Renyi G(2000, 0.005), seed 1; p=4"),
+    "rmat24": ("rmat24", 64, "R-MAT scale 24, edge factor 16, (a,b,c,d)=(.57,.19,.19,.05), seed 24; p=64"),
+    "er24": ("er24", 64, "Erdos-Renyi n=2^24, average degree 32, seed 2; p=64"),
+}
+PMC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2009_12457_amd", "csrc", "kernels_count.hip")
+
+
+def kernel_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def timed(fn, reps, sync):
+    ts = []
+    for _ in range(reps):
+        sync()
+        t = time.perf_counter()
+        fn()
+        sync()
+        ts.append(time.perf_counter() - t)
+    return ts
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="rmat20", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-only", action="store_true", help="only the timed steps (for rocprofv3 runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): this build has no multi-GPU path; "
+              f"the per-GPU share is the single-GPU workload.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_2009_12457_amd as bb
+
+    gname, p, desc = WORKLOADS[args.workload]
+    g = graphgen.workload(gname)
+    n, rp, ci = bb.csr_of(g, "cuda")
+    stream = torch.cuda.current_stream()
+    sync = torch.cuda.synchronize
+    opt = bb.bbtc_options_default(p=p, mode=bb.BBTC_MODE_PERSISTENT)
+    plan = bb.bbtc_partition(n, rp, ci, options=opt, trusted=True)
+    per, tot = bb.bbtc_count(plan)
+    sync()
+
+    def step():
+        bb.bbtc_partition(n, rp, ci, options=opt, trusted=True, plan=plan)
+        bb.bbtc_count(plan, per, tot)
+
+    for _ in range(args.warmup):
+        step()
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    sync()
+    elapsed = time.perf_counter() - t0
+    triangles = int(tot.item())
+    st = plan.stats()
+    m = int(st["m"])
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = m * args.steps / elapsed
+    if args.profile_only:
+        print(json.dumps({"workload": args.workload, "ms_per_step": ms_per_step, "triangles": triangles}))
+        return
+
+    # ---- count alone: batched persistent kernel timed with HIP events on its stream
+    reps = max(args.steps, 5)
+    ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
+    ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
+    bb.bbtc_count(plan, per, tot)
+    for r in range(reps):
+        ev0[r].record(stream)
+        bb.bbtc_count(plan, per, tot)
+        ev1[r].record(stream)
+    sync()
+    count_ms = [a.elapsed_time(b) for a, b in zip(ev0, ev1)]
+    count_ms_med = float(np.median(count_ms))
+    part_ms = [float(x) * 1e3 for x in timed(lambda: bb.bbtc_partition(n, rp, ci, options=opt, trusted=True,
+                                                                         plan=plan), 5, sync)]
+
+    # ---- unbatched baselines: one launch per task (Intersect, HMap)
+    plain = {}
+    for name, mode in (("plain_intersect", bb.BBTC_MODE_PLAIN_INTERSECT), ("plain_hmap", bb.BBTC_MODE_PLAIN_HMAP)):
+        o2 = bb.bbtc_options_default(p=p, mode=mode)
+        pl2 = bb.bbtc_partition(n, rp, ci, options=o2, trusted=True)
+        pt2, tt2 = bb.bbtc_count(pl2)
+        sync()
+        ts = timed(lambda: bb.bbtc_count(pl2, pt2, tt2), 3, sync)
+        if int(tt2.item()) != triangles:
+            raise SystemExit(f"{name} disagrees: {int(tt2.item())} vs {triangles}")
+        plain[name] = {"count_ms": float(np.median(ts)) * 1e3, "edges_per_s": m / float(np.median(ts))}
+        pl2.destroy()
+
+    # ---- roofline of the dominant kernel (the persistent count)
+    alg_bytes = int(st["bytes_total"])
+    achieved = alg_bytes / (count_ms_med * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(PMC_FILE):
+        try:
+            rec = json.load(open(PMC_FILE)).get(args.workload)
+            if rec and rec.get("kernel_sha") == kernel_hash():
+                traffic = rec["hbm_bytes_per_launch"]
+        except Exception:
+            traffic = None
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic}
+
+    # ---- CPU oracle on the host (a baseline, not the target)
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = oracle.max_threads()
+        t = time.perf_counter()
+        og = oracle.OracleGraph.from_graph(g)
+        otot, _, _ = og.tasks(p, og.cuts(p), threads=threads)
+        dt = time.perf_counter() - t
+        if otot != triangles:
+            raise SystemExit(f"oracle disagrees: {otot} vs {triangles}")
+        cpu = {"value": m / dt, "unit": "edges/s", "cores": threads, "kind": "oracle",
+               "sample": f"whole {args.workload} graph once: canonicalise, degree order, orient and per-task count "
+                         f"(p={p}), {dt:.2f} s"}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": desc, "n": int(st["n"]), "m": m, "p": int(st["p"]), "tasks": int(st["ntasks"]),
+                   "work_items": int(st["nitems"]), "triangles": triangles, "lambda": round(st["lambda"], 3),
+                   "c": round(st["c"], 3), "parallelism": "single GPU"},
+        "step_breakdown_ms": {"partition": float(np.median(part_ms)), "count_batched": count_ms_med},
+        "batched_count_edges_per_s": m / (count_ms_med * 1e-3),
+        "plain": plain,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "paper_context": "paper Table 4, scale20 R-MAT (different generator/seed): 0.079 s copy-included on "
+                         "2x20-core Xeon + up to 8x V100 = 2.0e8 edges/s; context only",
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -82,13 +82,17 @@ typedef struct bbtc_csr {
  * triangle exactly once.  Zero selects the library default.
  *   p             blocks per side, 1 <= p <= min(n, 2048); 0 = p from the
  *                 average degree (Sec. 7.2 suggests p near the average degree).
- *   wave_min      rows u with d(G_ij,u) >= wave_min are processed by a whole
- *                 64-lane wavefront; shorter rows by one lane each.
- *   hash_min      wavefront rows with |N(G_ik,u)| >= hash_min probe an LDS hash
- *                 or bitmap of N(G_ik,u) (the HMap form); shorter ones binary
- *                 search a sorted LDS copy (the Intersect form).  -1 = never.
+ *   wave_min      a column v of G_ij whose in-neighbours in V_i plus |N(G_jk,v)|
+ *                 reach wave_min is processed by a whole 64-lane wavefront;
+ *                 smaller ones by one lane each.
+ *   hash_min      wavefront columns with |N(G_jk,v)| >= hash_min stage it as an
+ *                 LDS bitmap over V_k or an LDS hash (the HMap form); shorter
+ *                 ones as a sorted LDS copy probed by binary search (the
+ *                 Intersect form).  -1 = never.
  *   grid          workgroups of the persistent launch; 0 = by occupancy.
- *   item_rows     rows of G_ij per persistent work item.
+ *   item_rows     active columns of G_ij per persistent work item.
+ *   graph         0: the persistent count (reset + launch) is captured once
+ *                 in a hipGraph and replayed; -1: launched directly.
  *   device_budget_bytes  upper bound on the plan's device memory (0 = none).
  */
 typedef struct bbtc_options {
@@ -99,7 +103,7 @@ typedef struct bbtc_options {
   int32_t hash_min;
   int32_t grid;
   int32_t item_rows;
-  int32_t reserved0;
+  int32_t graph;
   int64_t device_budget_bytes;
 } bbtc_options;
 

@@ -48,7 +48,7 @@ class bbtc_csr(ctypes.Structure):
 class bbtc_options(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int32), ("cut_mode", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("wave_min", ctypes.c_int32), ("hash_min", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("item_rows", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("item_rows", ctypes.c_int32), ("graph", ctypes.c_int32),
                 ("device_budget_bytes", ctypes.c_int64)]
 
 

@@ -13,6 +13,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <thread>
@@ -87,15 +88,15 @@ struct bbtc_plan {
   DevBuf<int32_t> in_col;
   DevBuf<uint64_t> keys_a, keys_b;
   DevBuf<uint32_t> hist, partial;
-  DevBuf<int32_t> perm, order, ocol, cuts, chunk0, arow;
-  DevBuf<uint32_t> od, orow, bot, ccnt, ccoff, dmax, cursor, err;
-  DevBuf<uint64_t> ccbase, botp, arp;
-  DevBuf<unsigned long long> bnnz, bnzr;
+  DevBuf<int32_t> perm, order, ocol, icol, cuts, chunk0, acol;
+  DevBuf<uint32_t> od, idg, orow, irow, longrows, hugerows, bot, tbot, ccnt, ccoff, dmax, cursor, err;
+  DevBuf<uint64_t> ccbase, botp, tbotp, acp;
+  DevBuf<unsigned long long> bnnz, bnzr, bnzc;
   DevBuf<DevTask> tasks;
   DevBuf<DevItem> items;
   // host
   std::vector<int32_t> h_cuts;
-  std::vector<int64_t> h_nnz, h_nzr;
+  std::vector<int64_t> h_nnz, h_nzr, h_nzc;  // nzc in column-major block order
   std::vector<bbtc_task> h_tasks;  // plan order (LPT)
   std::vector<DevTask> h_dtasks;   // same order
   std::vector<int32_t> h_work;     // plan-order indices of WORK tasks
@@ -104,29 +105,45 @@ struct bbtc_plan {
   int ncu = 0, blocks_per_cu = 0;
   hipStream_t side[4] = {nullptr, nullptr, nullptr, nullptr};
   hipEvent_t ev_fork = nullptr, ev_join[4] = {nullptr, nullptr, nullptr, nullptr};
+  // captured persistent count, valid for the output pointers it was made with
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  uint64_t* g_per = nullptr;
+  uint64_t* g_tot = nullptr;
   bbtc_stats stats{};
 
+  void drop_graph() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+    g_per = g_tot = nullptr;
+  }
+
   ~bbtc_plan() {
+    drop_graph();
     for (int q = 0; q < 4; ++q) {
       if (side[q]) (void)hipStreamDestroy(side[q]);
       if (ev_join[q]) (void)hipEventDestroy(ev_join[q]);
     }
     if (ev_fork) (void)hipEventDestroy(ev_fork);
-    DevBuf<char>* cb[] = {&in_rowptr};
-    for (auto* b : cb) b->release();
-    in_col.release(); keys_a.release(); keys_b.release(); hist.release(); partial.release();
-    perm.release(); order.release(); ocol.release(); cuts.release(); chunk0.release(); arow.release();
-    od.release(); orow.release(); bot.release(); ccnt.release(); ccoff.release(); dmax.release();
-    cursor.release(); err.release(); ccbase.release(); botp.release(); arp.release();
-    bnnz.release(); bnzr.release(); tasks.release(); items.release();
+    in_rowptr.release(); in_col.release(); keys_a.release(); keys_b.release(); hist.release(); partial.release();
+    perm.release(); order.release(); ocol.release(); icol.release(); cuts.release(); chunk0.release();
+    acol.release(); od.release(); idg.release(); orow.release(); irow.release(); longrows.release();
+    hugerows.release();
+    bot.release(); tbot.release(); ccnt.release(); ccoff.release(); dmax.release(); cursor.release();
+    err.release(); ccbase.release(); botp.release(); tbotp.release(); acp.release(); bnnz.release();
+    bnzr.release(); bnzc.release(); tasks.release(); items.release();
   }
 
   size_t footprint() const {
     return in_rowptr.bytes() + in_col.bytes() + keys_a.bytes() + keys_b.bytes() + hist.bytes() + partial.bytes() +
-           perm.bytes() + order.bytes() + ocol.bytes() + cuts.bytes() + chunk0.bytes() + arow.bytes() + od.bytes() +
-           orow.bytes() + bot.bytes() + ccnt.bytes() + ccoff.bytes() + dmax.bytes() + cursor.bytes() + err.bytes() +
-           ccbase.bytes() + botp.bytes() + arp.bytes() + bnnz.bytes() + bnzr.bytes() + tasks.bytes() +
-           items.bytes();
+           perm.bytes() + order.bytes() + ocol.bytes() + icol.bytes() + cuts.bytes() + chunk0.bytes() +
+           acol.bytes() + od.bytes() + idg.bytes() + orow.bytes() + irow.bytes() + longrows.bytes() +
+           hugerows.bytes() + bot.bytes() +
+           tbot.bytes() + ccnt.bytes() + ccoff.bytes() + dmax.bytes() + cursor.bytes() + err.bytes() +
+           ccbase.bytes() + botp.bytes() + tbotp.bytes() + acp.bytes() + bnnz.bytes() + bnzr.bytes() +
+           bnzc.bytes() + tasks.bytes() + items.bytes();
   }
 };
 
@@ -221,9 +238,13 @@ PlanCtx plan_ctx(const bbtc_plan* pl, uint64_t* per_task, uint64_t* total) {
   c.g.botp = pl->botp.ptr;
   c.g.bot = pl->bot.ptr;
   c.g.ocol = pl->ocol.ptr;
-  c.g.arp = pl->arp.ptr;
-  c.g.arow = pl->arow.ptr;
+  c.g.tbotp = pl->tbotp.ptr;
+  c.g.tbot = pl->tbot.ptr;
+  c.g.icol = pl->icol.ptr;
+  c.g.acp = pl->acp.ptr;
+  c.g.acol = pl->acol.ptr;
   c.tasks = pl->tasks.ptr;
+  c.ntasks = (int64_t)pl->h_tasks.size();
   c.per_task = per_task;
   c.total = total;
   c.wave_min = eff_wave_min(pl->opt);
@@ -234,7 +255,7 @@ PlanCtx plan_ctx(const bbtc_plan* pl, uint64_t* per_task, uint64_t* total) {
 // ------------------------------------------------------------ task list
 // Alg. 4 order, the Sec. 5 estimate, kinds, and the non-increasing order by
 // estimate (ties kept in Alg. 4 order); work items split each task's active
-// rows of G_ij into pieces of item_rows rows.
+// columns of G_ij into pieces of item_rows columns.
 void compose_tasks(bbtc_plan* pl) {
   const int64_t p = pl->p;
   std::vector<bbtc_task> all;
@@ -267,7 +288,7 @@ void compose_tasks(bbtc_plan* pl) {
     pl->h_dtasks[q] = DevTask{t.i, t.j, t.k, (int32_t)q};
     if (t.kind == BBTC_TASK_WORK) {
       pl->h_work.push_back((int32_t)q);
-      const uint32_t rows = (uint32_t)pl->h_nzr[block_id(p, t.i, t.j)];
+      const uint32_t rows = (uint32_t)pl->h_nzc[col_block_id(t.i, t.j)];
       for (uint32_t lo = 0; lo < rows; lo += step)
         pl->h_items.push_back(DevItem{0, (int32_t)q, lo, std::min(rows, lo + step)});
     }
@@ -290,6 +311,7 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   if (opt.mode < BBTC_MODE_PERSISTENT || opt.mode > BBTC_MODE_PLAIN_HMAP) return fail(BBTC_EINVAL, "bad mode");
   if (opt.wave_min < 0 || opt.grid < 0 || opt.item_rows < 0 || opt.device_budget_bytes < 0 || opt.hash_min < -1)
     return fail(BBTC_EINVAL, "negative option");
+  if (opt.graph != 0 && opt.graph != -1) return fail(BBTC_EINVAL, "graph must be 0 or -1");
   const bool on_device = (g->flags & BBTC_CSR_DEVICE) != 0;
   const bool symmetric_check = (g->flags & BBTC_CSR_TRUSTED) == 0;
   const int rp64 = g->rowptr_bits == 64;
@@ -302,6 +324,7 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   }
 
   pl->ready = false;
+  pl->drop_graph();
   pl->opt = opt;
   pl->n = n;
   if (!pl->ncu) {
@@ -343,37 +366,52 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   pl->idbits = bits_for((uint64_t)(n - 1));
   const int kbits = 2 * pl->idbits;
   const uint64_t mmax = (uint64_t)nnz / 2;
-  const uint64_t kcap = std::max<uint64_t>((uint64_t)n, mmax);
-  HIP_TRY(pl->keys_a.ensure(kcap), "alloc keys");
-  HIP_TRY(pl->keys_b.ensure(kcap), "alloc keys");
-  HIP_TRY(pl->hist.ensure(radix_hist_entries(kcap)), "alloc hist");
-  HIP_TRY(pl->partial.ensure(scan_partial_entries(std::max<uint64_t>(radix_hist_entries(kcap), (uint64_t)n + 1)) +
+  HIP_TRY(pl->keys_a.ensure((size_t)n), "alloc keys");
+  HIP_TRY(pl->keys_b.ensure((size_t)n), "alloc keys");
+  HIP_TRY(pl->hist.ensure(radix_hist_entries((uint64_t)n)), "alloc hist");
+  HIP_TRY(pl->partial.ensure(scan_partial_entries(std::max<uint64_t>(radix_hist_entries((uint64_t)n), (uint64_t)n + 1)) +
                              4096),
           "alloc partial");
   HIP_TRY(pl->perm.ensure((size_t)n), "alloc perm");
   HIP_TRY(pl->order.ensure((size_t)n), "alloc order");
   HIP_TRY(pl->od.ensure((size_t)n), "alloc od");
+  HIP_TRY(pl->idg.ensure((size_t)n), "alloc idg");
   HIP_TRY(pl->orow.ensure((size_t)n + 1), "alloc orow");
+  HIP_TRY(pl->irow.ensure((size_t)n + 1), "alloc irow");
+  HIP_TRY(pl->longrows.ensure((size_t)n), "alloc");
+  HIP_TRY(pl->hugerows.ensure((size_t)n), "alloc");
+  HIP_TRY(pl->err.ensure(4), "alloc");
   uint64_t* sorted = nullptr;
   HIP_TRY(launch_degkey(rowptr, rp64, n, pl->idbits, pl->keys_a.ptr, s), "degkey");
   HIP_TRY(radix_sort_u64(pl->keys_a.ptr, pl->keys_b.ptr, (uint64_t)n, kbits, pl->hist.ptr, pl->partial.ptr, &sorted, s),
           "degree sort");
   HIP_TRY(launch_perm(sorted, n, pl->idbits, pl->order.ptr, pl->perm.ptr, s), "perm");
 
-  // ---- orientation: N(G,u) = higher-ranked neighbours, rows sorted ----
-  HIP_TRY(launch_outdeg(rowptr, rp64, col, n, pl->perm.ptr, pl->od.ptr, s), "outdeg");
-  HIP_TRY(scan_u32(pl->od.ptr, pl->orow.ptr, (uint64_t)n, pl->partial.ptr, s), "scan outdeg");
-  uint32_t m32 = 0;
-  HIP_TRY(hipMemcpyAsync(&m32, pl->orow.ptr + n, 4, hipMemcpyDeviceToHost, s), "D2H m");
+  // ---- orientation: out-rows (higher ranks) and in-rows (lower ranks) ----
+  HIP_TRY(launch_degs(rowptr, rp64, col, n, pl->perm.ptr, pl->od.ptr, pl->idg.ptr, s), "degrees");
+  HIP_TRY(scan_u32(pl->od.ptr, pl->orow.ptr, (uint64_t)n, pl->partial.ptr, s), "scan out-degrees");
+  HIP_TRY(scan_u32(pl->idg.ptr, pl->irow.ptr, (uint64_t)n, pl->partial.ptr, s), "scan in-degrees");
+  uint32_t mm[2] = {0, 0};
+  HIP_TRY(hipMemcpyAsync(&mm[0], pl->orow.ptr + n, 4, hipMemcpyDeviceToHost, s), "D2H m");
+  HIP_TRY(hipMemcpyAsync(&mm[1], pl->irow.ptr + n, 4, hipMemcpyDeviceToHost, s), "D2H m");
   HIP_TRY(hipStreamSynchronize(s), "sync");
-  const uint64_t m = m32;
-  if (m > mmax) return fail(BBTC_EINVAL, "input is not symmetric");
+  const uint64_t m = mm[0];
+  if (m > mmax || mm[1] != mm[0]) return fail(BBTC_EINVAL, "input is not symmetric");
   pl->m = (int64_t)m;
   HIP_TRY(pl->ocol.ensure((size_t)m), "alloc ocol");
-  HIP_TRY(launch_fill(rowptr, rp64, col, n, pl->perm.ptr, pl->orow.ptr, pl->idbits, pl->keys_a.ptr, m, s), "fill");
-  HIP_TRY(radix_sort_u64(pl->keys_a.ptr, pl->keys_b.ptr, m, kbits, pl->hist.ptr, pl->partial.ptr, &sorted, s),
-          "row sort");
-  HIP_TRY(launch_unpack(sorted, m, pl->idbits, pl->ocol.ptr, s), "unpack");
+  HIP_TRY(pl->icol.ensure((size_t)m), "alloc icol");
+  HIP_TRY(launch_fill(rowptr, rp64, col, n, pl->perm.ptr, pl->orow.ptr, pl->irow.ptr, pl->ocol.ptr, pl->icol.ptr, s),
+          "fill");
+  // acol is not built yet: its m entries serve as the huge-row sort scratch
+  HIP_TRY(pl->acol.ensure((size_t)m), "alloc active columns");
+  HIP_TRY(hipMemsetAsync(pl->err.ptr, 0, 8, s), "memset");
+  HIP_TRY(launch_segsort(pl->orow.ptr, pl->ocol.ptr, n, pl->idbits, pl->longrows.ptr, pl->hugerows.ptr, pl->err.ptr,
+                         pl->acol.ptr, s),
+          "sort out-rows");
+  HIP_TRY(hipMemsetAsync(pl->err.ptr, 0, 8, s), "memset");
+  HIP_TRY(launch_segsort(pl->irow.ptr, pl->icol.ptr, n, pl->idbits, pl->longrows.ptr, pl->hugerows.ptr, pl->err.ptr,
+                         pl->acol.ptr, s),
+          "sort in-rows");
 
   // ---- cut vector (Sec. 4.1) ----
   int32_t p = opt.p;
@@ -391,42 +429,49 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
           "D2H cuts");
   HIP_TRY(hipStreamSynchronize(s), "sync");
 
-  // ---- block row index ----
+  // ---- block row index (out side) and active columns (in side) ----
   const int64_t nb = (int64_t)p * (p + 1) / 2;
   std::vector<int32_t> chunk0((size_t)p + 1);
-  std::vector<uint64_t> ccbase((size_t)p + 1), botp((size_t)p + 1);
+  std::vector<uint64_t> ccbase((size_t)p + 1), botp((size_t)p + 1), tbotp((size_t)p + 1);
   int64_t nch = 0;
-  uint64_t cc = 0, bp = 0;
+  uint64_t cc = 0, bp = 0, tp = 0;
   for (int32_t a = 0; a < p; ++a) {
     const int64_t va = pl->h_cuts[a + 1] - pl->h_cuts[a];
     const int64_t ca = (va + kPrepRows - 1) / kPrepRows;
     chunk0[a] = (int32_t)nch;
     ccbase[a] = cc;
     botp[a] = bp;
+    tbotp[a] = tp;
     nch += ca;
-    cc += (uint64_t)(p - a) * (uint64_t)ca;
+    cc += (uint64_t)(a + 1) * (uint64_t)ca;
     bp += (uint64_t)(p - a + 1) * (uint64_t)va;
+    tp += (uint64_t)(a + 2) * (uint64_t)va;
   }
   chunk0[p] = (int32_t)nch;
   ccbase[p] = cc;
   botp[p] = bp;
+  tbotp[p] = tp;
   pl->ccount = (int64_t)cc;
   HIP_TRY(pl->chunk0.ensure((size_t)p + 1), "alloc");
   HIP_TRY(pl->ccbase.ensure((size_t)p + 1), "alloc");
   HIP_TRY(pl->botp.ensure((size_t)p + 1), "alloc");
+  HIP_TRY(pl->tbotp.ensure((size_t)p + 1), "alloc");
   HIP_TRY(pl->bot.ensure((size_t)bp), "alloc block row index");
+  HIP_TRY(pl->tbot.ensure((size_t)tp), "alloc block column index");
   HIP_TRY(pl->bnnz.ensure((size_t)nb), "alloc");
   HIP_TRY(pl->bnzr.ensure((size_t)nb), "alloc");
+  HIP_TRY(pl->bnzc.ensure((size_t)nb), "alloc");
   HIP_TRY(pl->ccnt.ensure((size_t)cc + 1), "alloc");
   HIP_TRY(pl->ccoff.ensure((size_t)cc + 1), "alloc");
   HIP_TRY(pl->dmax.ensure(2), "alloc");
-  HIP_TRY(pl->arow.ensure((size_t)m), "alloc active rows");
   if (pl->partial.cap < scan_partial_entries(cc)) HIP_TRY(pl->partial.ensure(scan_partial_entries(cc) + 4096), "alloc");
   HIP_TRY(hipMemcpyAsync(pl->chunk0.ptr, chunk0.data(), sizeof(int32_t) * (p + 1), hipMemcpyHostToDevice, s), "H2D");
   HIP_TRY(hipMemcpyAsync(pl->ccbase.ptr, ccbase.data(), sizeof(uint64_t) * (p + 1), hipMemcpyHostToDevice, s), "H2D");
   HIP_TRY(hipMemcpyAsync(pl->botp.ptr, botp.data(), sizeof(uint64_t) * (p + 1), hipMemcpyHostToDevice, s), "H2D");
+  HIP_TRY(hipMemcpyAsync(pl->tbotp.ptr, tbotp.data(), sizeof(uint64_t) * (p + 1), hipMemcpyHostToDevice, s), "H2D");
   HIP_TRY(hipMemsetAsync(pl->bnnz.ptr, 0, sizeof(unsigned long long) * nb, s), "memset");
   HIP_TRY(hipMemsetAsync(pl->bnzr.ptr, 0, sizeof(unsigned long long) * nb, s), "memset");
+  HIP_TRY(hipMemsetAsync(pl->bnzc.ptr, 0, sizeof(unsigned long long) * nb, s), "memset");
   HIP_TRY(hipMemsetAsync(pl->dmax.ptr, 0, sizeof(uint32_t) * 2, s), "memset");
   BlockBuild bb;
   bb.p = p;
@@ -438,35 +483,43 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   bb.ocol = pl->ocol.ptr;
   bb.botp = pl->botp.ptr;
   bb.bot = pl->bot.ptr;
+  bb.irow = pl->irow.ptr;
+  bb.icol = pl->icol.ptr;
+  bb.tbotp = pl->tbotp.ptr;
+  bb.tbot = pl->tbot.ptr;
   bb.bnnz = pl->bnnz.ptr;
   bb.bnzr = pl->bnzr.ptr;
+  bb.bnzc = pl->bnzc.ptr;
   bb.ccnt = pl->ccnt.ptr;
   bb.dmax_block = pl->dmax.ptr;
   bb.ccoff = pl->ccoff.ptr;
-  bb.arow = pl->arow.ptr;
+  bb.acol = pl->acol.ptr;
   HIP_TRY(launch_bot(bb, s), "block row index");
+  HIP_TRY(launch_tbot(bb, s), "block column index");
   HIP_TRY(scan_u32(pl->ccnt.ptr, pl->ccoff.ptr, cc, pl->partial.ptr, s), "scan chunk counters");
-  HIP_TRY(launch_arow(bb, s), "active rows");
-  std::vector<unsigned long long> hn((size_t)nb), hz((size_t)nb);
+  HIP_TRY(launch_acol(bb, s), "active columns");
+  std::vector<unsigned long long> hn((size_t)nb), hz((size_t)nb), hc((size_t)nb);
   uint32_t hd[2] = {0, 0};
   HIP_TRY(hipMemcpyAsync(hn.data(), pl->bnnz.ptr, sizeof(unsigned long long) * nb, hipMemcpyDeviceToHost, s), "D2H");
   HIP_TRY(hipMemcpyAsync(hz.data(), pl->bnzr.ptr, sizeof(unsigned long long) * nb, hipMemcpyDeviceToHost, s), "D2H");
+  HIP_TRY(hipMemcpyAsync(hc.data(), pl->bnzc.ptr, sizeof(unsigned long long) * nb, hipMemcpyDeviceToHost, s), "D2H");
   HIP_TRY(hipMemcpyAsync(hd, pl->dmax.ptr, sizeof(uint32_t) * 2, hipMemcpyDeviceToHost, s), "D2H");
   HIP_TRY(hipStreamSynchronize(s), "sync");
   pl->h_nnz.assign(hn.begin(), hn.end());
   pl->h_nzr.assign(hz.begin(), hz.end());
+  pl->h_nzc.assign(hc.begin(), hc.end());
 
   // ---- tasks (Alg. 4) and work items ----
-  std::vector<uint64_t> arp((size_t)nb + 1);
-  arp[0] = 0;
-  for (int64_t b = 0; b < nb; ++b) arp[b + 1] = arp[b] + (uint64_t)pl->h_nzr[b];
+  std::vector<uint64_t> acp((size_t)nb + 1);
+  acp[0] = 0;
+  for (int64_t b = 0; b < nb; ++b) acp[b + 1] = acp[b] + (uint64_t)pl->h_nzc[b];
   compose_tasks(pl);
   const int64_t nt = (int64_t)pl->h_tasks.size();
-  HIP_TRY(pl->arp.ensure((size_t)nb + 1), "alloc");
+  HIP_TRY(pl->acp.ensure((size_t)nb + 1), "alloc");
   HIP_TRY(pl->tasks.ensure((size_t)nt), "alloc tasks");
   HIP_TRY(pl->items.ensure(pl->h_items.size()), "alloc items");
   HIP_TRY(pl->cursor.ensure(1), "alloc");
-  HIP_TRY(hipMemcpyAsync(pl->arp.ptr, arp.data(), sizeof(uint64_t) * (nb + 1), hipMemcpyHostToDevice, s), "H2D");
+  HIP_TRY(hipMemcpyAsync(pl->acp.ptr, acp.data(), sizeof(uint64_t) * (nb + 1), hipMemcpyHostToDevice, s), "H2D");
   HIP_TRY(hipMemcpyAsync(pl->tasks.ptr, pl->h_dtasks.data(), sizeof(DevTask) * nt, hipMemcpyHostToDevice, s), "H2D");
   if (!pl->h_items.empty())
     HIP_TRY(hipMemcpyAsync(pl->items.ptr, pl->h_items.data(), sizeof(DevItem) * pl->h_items.size(),
@@ -505,6 +558,85 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   st.partition_ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   pl->ready = true;
+  return BBTC_OK;
+}
+
+// Shared state of multi-plan launches: device copies of the plan contexts and
+// of the merged work list, filled from pinned host staging.
+struct MultiState {
+  std::mutex mu;
+  DevBuf<PlanCtx> ctxs;
+  DevBuf<DevItem> items;
+  DevBuf<uint32_t> cursor;
+  PlanCtx* h_ctx = nullptr;
+  DevItem* h_items = nullptr;
+  size_t cap_ctx = 0, cap_items = 0;
+  hipEvent_t copied = nullptr;
+  bool pending = false;
+  int ncu = 0, bpc = 0;
+};
+MultiState g_multi;
+
+bbtc_status count_multi_impl(bbtc_plan* const* plans, int32_t nplans, hipStream_t s, uint64_t* const* d_per_task,
+                             uint64_t* d_totals) {
+  MultiState& M = g_multi;
+  std::lock_guard<std::mutex> lock(M.mu);
+  if (!M.copied) {
+    HIP_TRY(hipEventCreateWithFlags(&M.copied, hipEventDisableTiming), "hipEventCreate");
+    M.ncu = plans[0]->ncu;
+    M.bpc = plans[0]->blocks_per_cu;
+  }
+  if (M.pending) {  // the staging buffers may still be read by the last copy
+    HIP_TRY(hipEventSynchronize(M.copied), "event sync");
+    M.pending = false;
+  }
+  size_t nitems = 0;
+  for (int32_t q = 0; q < nplans; ++q) nitems += plans[q]->h_items.size();
+  if (M.cap_ctx < (size_t)nplans) {
+    if (M.h_ctx) (void)hipHostFree(M.h_ctx);
+    M.h_ctx = nullptr;
+    HIP_TRY(hipHostMalloc((void**)&M.h_ctx, sizeof(PlanCtx) * nplans, hipHostMallocDefault), "pinned alloc");
+    M.cap_ctx = (size_t)nplans;
+  }
+  if (M.cap_items < nitems) {
+    if (M.h_items) (void)hipHostFree(M.h_items);
+    M.h_items = nullptr;
+    HIP_TRY(hipHostMalloc((void**)&M.h_items, sizeof(DevItem) * nitems, hipHostMallocDefault), "pinned alloc");
+    M.cap_items = nitems;
+  }
+  // heavier plans first (sum of task estimates), each plan's items in its own order
+  std::vector<std::pair<double, int32_t>> order;
+  for (int32_t q = 0; q < nplans; ++q) {
+    double w = 0;
+    for (const auto& t : plans[q]->h_tasks) w += t.est;
+    order.push_back({-w, q});
+  }
+  std::stable_sort(order.begin(), order.end());
+  size_t at = 0;
+  for (int32_t q = 0; q < nplans; ++q) M.h_ctx[q] = plan_ctx(plans[q], d_per_task[q], d_totals + q);
+  for (const auto& pr : order) {
+    for (DevItem it : plans[pr.second]->h_items) {
+      it.plan = pr.second;
+      M.h_items[at++] = it;
+    }
+  }
+  HIP_TRY(M.ctxs.ensure((size_t)nplans), "alloc");
+  HIP_TRY(M.items.ensure(std::max<size_t>(nitems, 1)), "alloc");
+  HIP_TRY(M.cursor.ensure(1), "alloc");
+  HIP_TRY(hipMemcpyAsync(M.ctxs.ptr, M.h_ctx, sizeof(PlanCtx) * nplans, hipMemcpyHostToDevice, s), "H2D");
+  if (nitems) HIP_TRY(hipMemcpyAsync(M.items.ptr, M.h_items, sizeof(DevItem) * nitems, hipMemcpyHostToDevice, s), "H2D");
+  HIP_TRY(hipEventRecord(M.copied, s), "event");
+  M.pending = true;
+  HIP_TRY(launch_reset_multi(M.ctxs.ptr, nplans, M.cursor.ptr, s), "reset");
+  if (nitems == 0) return BBTC_OK;
+  CountParams cp;
+  std::memset(&cp, 0, sizeof(cp));
+  cp.many = M.ctxs.ptr;
+  cp.items = M.items.ptr;
+  cp.nitems = (uint32_t)nitems;
+  cp.cursor = M.cursor.ptr;
+  int grid = (int)std::min<int64_t>((int64_t)M.bpc * M.ncu, (int64_t)nitems);
+  HIP_TRY(launch_count_persistent(cp, grid, true, s), "count");
   return BBTC_OK;
 }
 
@@ -547,7 +679,8 @@ bbtc_status bbtc_count(bbtc_plan* pl, void* stream, uint64_t* d_per_task, uint64
   if (!d_total || (!d_per_task && !pl->h_tasks.empty())) return fail(BBTC_EINVAL, "null output");
   hipStream_t s = (hipStream_t)stream;
   const int64_t nt = (int64_t)pl->h_tasks.size();
-  HIP_TRY(launch_reset(d_per_task, nt, d_total, pl->cursor.ptr, s), "reset");
+  const bool graphed = pl->opt.mode == BBTC_MODE_PERSISTENT && pl->opt.graph == 0 && !pl->h_items.empty();
+  if (!graphed) HIP_TRY(launch_reset(d_per_task, nt, d_total, pl->cursor.ptr, s), "reset");
   CountParams cp;
   cp.one = plan_ctx(pl, d_per_task, d_total);
   cp.many = nullptr;
@@ -558,18 +691,39 @@ bbtc_status bbtc_count(bbtc_plan* pl, void* stream, uint64_t* d_per_task, uint64
     if (cp.nitems == 0) return BBTC_OK;
     int grid = pl->opt.grid > 0 ? pl->opt.grid : pl->blocks_per_cu * pl->ncu;
     grid = (int)std::min<int64_t>(grid, (int64_t)cp.nitems);
-    HIP_TRY(launch_count_persistent(cp, grid, false, s), "count");
+    if (pl->opt.graph == -1) {
+      HIP_TRY(launch_count_persistent(cp, grid, false, s), "count");
+      return BBTC_OK;
+    }
+    if (!pl->gexec || pl->g_per != d_per_task || pl->g_tot != d_total) {
+      // capture {reset kernel, persistent count} on a plan-owned stream
+      pl->drop_graph();
+      hipStream_t cs = pl->side[0];
+      HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
+      hipError_t e1 = launch_reset(d_per_task, nt, d_total, pl->cursor.ptr, cs);
+      hipError_t e2 = e1 == hipSuccess ? launch_count_persistent(cp, grid, false, cs) : e1;
+      hipGraph_t gr = nullptr;
+      hipError_t e3 = hipStreamEndCapture(cs, &gr);
+      if (e2 != hipSuccess || e3 != hipSuccess) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return hip_fail(e2 != hipSuccess ? e2 : e3, "capture count");
+      }
+      pl->graph = gr;
+      HIP_TRY(hipGraphInstantiate(&pl->gexec, pl->graph, nullptr, nullptr, 0), "instantiate graph");
+      pl->g_per = d_per_task;
+      pl->g_tot = d_total;
+    }
+    HIP_TRY(hipGraphLaunch(pl->gexec, s), "graph launch");
     return BBTC_OK;
   }
   // plain: one launch per task, round-robin over four side streams
   HIP_TRY(hipEventRecord(pl->ev_fork, s), "event");
   for (int q = 0; q < 4; ++q) HIP_TRY(hipStreamWaitEvent(pl->side[q], pl->ev_fork, 0), "wait");
-  const int64_t p = pl->p;
   for (size_t w = 0; w < pl->h_work.size(); ++w) {
     const int32_t t = pl->h_work[w];
     const bbtc_task& tk = pl->h_tasks[t];
-    const uint32_t rows = (uint32_t)pl->h_nzr[block_id(p, tk.i, tk.j)];
-    HIP_TRY(launch_count_task(cp, t, rows, pl->side[w % 4]), "count task");
+    const uint32_t cols = (uint32_t)pl->h_nzc[col_block_id(tk.i, tk.j)];
+    HIP_TRY(launch_count_task(cp, t, cols, pl->side[w % 4]), "count task");
   }
   for (int q = 0; q < 4; ++q) {
     HIP_TRY(hipEventRecord(pl->ev_join[q], pl->side[q]), "event");
@@ -582,11 +736,16 @@ bbtc_status bbtc_count_multi(bbtc_plan* const* plans, int32_t nplans, void* stre
                              uint64_t* d_totals) {
   g_err.clear();
   if (nplans < 0 || (nplans > 0 && (!plans || !d_per_task || !d_totals))) return fail(BBTC_EINVAL, "null argument");
+  if (nplans == 0) return BBTC_OK;
   for (int32_t q = 0; q < nplans; ++q) {
-    bbtc_status st = bbtc_count(plans[q], stream, d_per_task[q], d_totals + q);
-    if (st != BBTC_OK) return st;
+    if (!plans[q] || !plans[q]->ready) return fail(BBTC_ESTATE, "plan is not ready");
+    if (!d_per_task[q]) return fail(BBTC_EINVAL, "null output");
   }
-  return BBTC_OK;
+  try {
+    return count_multi_impl(plans, nplans, (hipStream_t)stream, d_per_task, d_totals);
+  } catch (const std::bad_alloc&) {
+    return fail(BBTC_ENOMEM, "host allocation failed");
+  }
 }
 
 bbtc_status bbtc_plan_tasks(const bbtc_plan* pl, const bbtc_task** tasks, int64_t* ntasks) {

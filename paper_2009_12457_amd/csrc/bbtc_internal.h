@@ -21,8 +21,8 @@ struct DevTask {
   int32_t i, j, k, out;
 };
 
-// One unit of persistent work: rows [lo, hi) of the active-row list of block
-// (i,j) of task `task` of plan `plan` (plan is 0 for single-plan launches).
+// One unit of persistent work: entries [lo, hi) of the active-column list of
+// block (i,j) of task `task` of plan `plan` (plan is 0 for single-plan launches).
 struct DevItem {
   int32_t plan;
   int32_t task;
@@ -35,23 +35,31 @@ struct DevItem {
 //           b-a is the first position of N(G,u) whose column is >= cuts[b],
 //           so N(G_ab,u) = ocol[bot[b-a] .. bot[b-a+1]).  Rows of part a start
 //           at element botp[a] and are (p-a+1) entries apart.
-//   arow  : per block (a,b), the rows u of V_a with N(G_ab,u) non-empty, in
-//           increasing order, starting at arp[bid(a,b)].
+//   icol  : in-rows: for each rank v, the ranks u < v adjacent to v, ascending.
+//   tbot  : for v in part b, (b+2) positions in icol; entry a is the first
+//           in-neighbour of rank >= cuts[a], so the in-slice of v in block
+//           (a,b) is icol[tbot[a] .. tbot[a+1]).  Part b starts at tbotp[b].
+//   acol  : per block (a,b), the columns v of V_b with a non-empty in-slice
+//           in increasing order, starting at acp[cid(a,b)], cid = b(b+1)/2+a.
 struct GraphView {
   int32_t p;
-  uint32_t m;  // entries of ocol
+  uint32_t m;  // entries of ocol (and of icol)
   const int32_t* cuts;
   const uint64_t* botp;
   const uint32_t* bot;
   const int32_t* ocol;
-  const uint64_t* arp;
-  const int32_t* arow;
+  const uint64_t* tbotp;
+  const uint32_t* tbot;
+  const int32_t* icol;
+  const uint64_t* acp;   // column-major block order
+  const int32_t* acol;
 };
 
 // Everything a counting kernel needs about one plan.
 struct PlanCtx {
   GraphView g;
   const DevTask* tasks;
+  int64_t ntasks;
   uint64_t* per_task;
   uint64_t* total;
   int32_t wave_min;
@@ -69,6 +77,7 @@ struct CountParams {
 __host__ __device__ inline int64_t block_id(int64_t p, int64_t a, int64_t b) {
   return a * p - a * (a - 1) / 2 + (b - a);
 }
+__host__ __device__ inline int64_t col_block_id(int64_t a, int64_t b) { return b * (b + 1) / 2 + a; }
 
 // ---- launchers (kernels_prep.hip) ----
 hipError_t launch_validate(const void* rowptr, int rp64, const int32_t* colidx, int64_t n, int64_t nnz,
@@ -83,11 +92,15 @@ hipError_t radix_sort_u64(uint64_t* a, uint64_t* b, uint64_t count, int bits, ui
 // out[0..count] = exclusive scan of in[0..count), out[count] = total.
 hipError_t scan_u32(const uint32_t* in, uint32_t* out, uint64_t count, uint32_t* partial, hipStream_t s);
 hipError_t launch_perm(const uint64_t* keys, int64_t n, int idbits, int32_t* order, int32_t* perm, hipStream_t s);
-hipError_t launch_outdeg(const void* rowptr, int rp64, const int32_t* colidx, int64_t n, const int32_t* perm,
-                         uint32_t* od, hipStream_t s);
+hipError_t launch_degs(const void* rowptr, int rp64, const int32_t* colidx, int64_t n, const int32_t* perm,
+                       uint32_t* od, uint32_t* idg, hipStream_t s);
 hipError_t launch_fill(const void* rowptr, int rp64, const int32_t* colidx, int64_t n, const int32_t* perm,
-                       const uint32_t* orow, int idbits, uint64_t* keys, uint64_t cap, hipStream_t s);
-hipError_t launch_unpack(const uint64_t* keys, uint64_t m, int idbits, int32_t* ocol, hipStream_t s);
+                       const uint32_t* orow, const uint32_t* irow, int32_t* ocol, int32_t* icol, hipStream_t s);
+// Sorts every row of a CSR in place; values have at most `bits` bits.
+// longrows and hugerows need nrows entries each, q[0..1] must be zero, and
+// scratch needs rp[nrows] entries.
+hipError_t launch_segsort(const uint32_t* rp, int32_t* col, int64_t nrows, int bits, uint32_t* longrows,
+                          uint32_t* hugerows, uint32_t* q, int32_t* scratch, hipStream_t s);
 hipError_t launch_cuts(const uint32_t* orow, int64_t n, int32_t p, int mode, int32_t* cuts, hipStream_t s);
 
 struct BlockBuild {
@@ -95,24 +108,32 @@ struct BlockBuild {
   int32_t nchunks;           // total row chunks (kPrepRows rows each, within one part)
   const int32_t* cuts;       // p+1
   const int32_t* chunk0;     // p+1: first chunk of each part
-  const uint64_t* ccbase;    // p: start of part a's chunk counters
+  const uint64_t* ccbase;    // p+1: start of part b's chunk counters (in side)
   const uint32_t* orow;
   const int32_t* ocol;
   const uint64_t* botp;
   uint32_t* bot;
-  unsigned long long* bnnz;  // nb
-  unsigned long long* bnzr;  // nb
-  uint32_t* ccnt;            // per (part a, block b, chunk) active-row counts
-  uint32_t* dmax_block;
-  const uint32_t* ccoff;     // exclusive scan of ccnt (for the fill)
-  int32_t* arow;
+  const uint32_t* irow;
+  const int32_t* icol;
+  const uint64_t* tbotp;
+  uint32_t* tbot;
+  unsigned long long* bnnz;  // nb, row-major block order
+  unsigned long long* bnzr;  // nb, row-major block order
+  unsigned long long* bnzc;  // nb, column-major block order cid(a,b) = b(b+1)/2 + a
+  uint32_t* ccnt;            // per (part b, block (a,b), chunk) active-column counts
+  uint32_t* dmax_block;      // [0] longest block slice, [1] longest oriented row
+  const uint32_t* ccoff;     // exclusive scan of ccnt
+  int32_t* acol;             // active columns, column-major block order
 };
 hipError_t launch_bot(const BlockBuild& bb, hipStream_t s);
-hipError_t launch_arow(const BlockBuild& bb, hipStream_t s);
+hipError_t launch_tbot(const BlockBuild& bb, hipStream_t s);
+hipError_t launch_acol(const BlockBuild& bb, hipStream_t s);
 
 // ---- launchers (kernels_count.hip) ----
 hipError_t launch_reset(uint64_t* per_task, int64_t ntasks, uint64_t* total, uint32_t* cursor, hipStream_t s);
 hipError_t launch_count_task(const CountParams& cp, int32_t task, uint32_t nrows, hipStream_t s);
+// Zeroes the outputs of every plan of a multi-plan launch and the cursor.
+hipError_t launch_reset_multi(const PlanCtx* ctxs, int32_t nplans, uint32_t* cursor, hipStream_t s);
 hipError_t launch_count_persistent(const CountParams& cp, int grid, bool multi, hipStream_t s);
 int count_persistent_blocks_per_cu();
 

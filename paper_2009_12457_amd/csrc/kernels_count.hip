@@ -1,22 +1,23 @@
 // Per-task triangle counting kernels (arXiv 2009.12457, Sec. 4.3).
 //
-// A task {i,j,k} counts, for every u in V_i and v in N(G_ij,u), the common
-// elements of N(G_ik,u) and N(G_jk,v).  Only rows u of the active-row list of
-// block (i,j) are visited (others have N(G_ij,u) empty); rows with N(G_ik,u)
-// empty are skipped.
+// A task {i,j,k} sums |N(G_ik,u) cap N(G_jk,v)| over the edges (u,v) of G_ij.
+// The kernels visit those edges grouped by their head v (the columns of G_ij
+// that have an in-neighbour in V_i, from the active-column list) rather than
+// by their tail u: the sum is the same, and the list N(G_jk,v), which is the
+// long one under degree ordering, is staged once per v and probed by the
+// short lists N(G_ik,u) of all of v's in-neighbours u in V_i.
 //
-// Two row mappings (the split is a tuning knob; both are exact):
-//   * light rows (d(G_ij,u) < wave_min): one lane per row, a two-pointer
-//     count of sorted lists (the list intersection of Alg. 1);
-//   * heavy rows: one 64-lane wavefront per row.  N(G_ik,u) is staged in LDS
-//     once, the lanes flatten the probe space {(v,w): v in N(G_ij,u),
-//     w in N(G_jk,v)} with a wavefront prefix sum, and each probe w is tested
-//     against the staged row:
+// Two mappings (a tuning knob; both exact):
+//   * light columns (|in_i(v)| + |N(G_jk,v)| < wave_min): one lane per v, a
+//     two-pointer count of the sorted lists (Alg. 1) for each u;
+//   * heavy columns: one 64-lane wavefront per v.  N(G_jk,v) is staged in LDS,
+//     the lanes flatten the probe space {(u,w): u in in_i(v), w in N(G_ik,u)}
+//     with a wavefront prefix sum, and each w is tested against the stage:
 //       - Intersect form: binary search of a sorted LDS copy;
 //       - HMap form: a dense bitmap over the columns of V_k (the paper's dense
 //         hash map of the block's column range) when |V_k| fits in LDS, else
-//         an open-addressing LDS hash of N(G_ik,u).
-//     Rows longer than the LDS buffer are staged in disjoint pieces; a probe
+//         an open-addressing LDS hash of N(G_jk,v).
+//     Lists longer than the LDS buffer are staged in disjoint pieces; a probe
 //     matches at most one piece, so the count stays exact.
 #include "bbtc_internal.h"
 #include "dev_common.h"
@@ -32,9 +33,9 @@ static_assert((1 << kHashBits) == kABuf, "hash table fills the wave buffer");
 
 struct CountLds {
   uint32_t abuf[4][kABuf];  // per wave: sorted copy / bitmap / hash; all-zero between rows
-  uint32_t sc0[4][kWave];   // per wave: start of N(G_jk,v) for the batch's lanes
+  uint32_t sc0[4][kWave];   // per wave: start of N(G_ik,u) for the batch's lanes
   uint32_t sex[4][kWave];   // per wave: exclusive prefix of the batch's lengths
-  uint32_t q[kThreads][4];  // heavy-row queue: sb0, sb1, sa0, sa1
+  uint32_t q[kThreads][4];  // heavy-column queue: i0, i1, c0, c1
   uint32_t qn;
   uint32_t item;
   unsigned long long red[4];
@@ -42,11 +43,13 @@ struct CountLds {
 
 struct TaskCtx {
   int32_t ci, cj, ck, ck1;
-  int32_t dj, dk, dkj;      // j-i, k-i, k-j
-  uint32_t stri, strj;      // bot row strides of parts i and j
+  int32_t i, dk, dkj;       // i, k-i, k-j
+  uint32_t stri, strj;      // out-side row strides of parts i and j
+  uint32_t tstrj;           // in-side row stride of part j
   const uint32_t* boti;
   const uint32_t* botj;
-  const int32_t* ar;        // active rows of block (i,j)
+  const uint32_t* tbotj;
+  const int32_t* ac;        // active columns of block (i,j)
 };
 
 __device__ __forceinline__ TaskCtx make_ctx(const GraphView& g, const DevTask& t) {
@@ -55,40 +58,42 @@ __device__ __forceinline__ TaskCtx make_ctx(const GraphView& g, const DevTask& t
   c.cj = g.cuts[t.j];
   c.ck = g.cuts[t.k];
   c.ck1 = g.cuts[t.k + 1];
-  c.dj = t.j - t.i;
+  c.i = t.i;
   c.dk = t.k - t.i;
   c.dkj = t.k - t.j;
   c.stri = (uint32_t)(g.p - t.i + 1);
   c.strj = (uint32_t)(g.p - t.j + 1);
+  c.tstrj = (uint32_t)(t.j + 2);
   c.boti = g.bot + g.botp[t.i];
   c.botj = g.bot + g.botp[t.j];
-  c.ar = g.arow + g.arp[block_id(g.p, t.i, t.j)];
+  c.tbotj = g.tbot + g.tbotp[t.j];
+  c.ac = g.acol + g.acp[col_block_id(t.i, t.j)];
   return c;
 }
 
-// |N(G_ik,u) cap N(G_jk,v)| summed over v in N(G_ij,u), one lane.
-__device__ __forceinline__ uint64_t light_row(const int32_t* __restrict__ col, const TaskCtx& c, uint32_t sb0,
-                                              uint32_t sb1, uint32_t sa0, uint32_t sa1) {
+// |N(G_ik,u) cap N(G_jk,v)| summed over the in-neighbours u of v in V_i, one lane.
+__device__ __forceinline__ uint64_t light_col(const int32_t* __restrict__ col, const int32_t* __restrict__ icol,
+                                              const TaskCtx& c, uint32_t i0, uint32_t i1, uint32_t c0, uint32_t c1) {
   uint64_t cnt = 0;
-  for (uint32_t e = sb0; e < sb1; ++e) {
-    const int32_t v = col[e];
-    const uint32_t* vr = c.botj + (uint64_t)(v - c.cj) * c.strj;
-    uint32_t b = vr[c.dkj];
-    const uint32_t be = vr[c.dkj + 1];
-    if (b >= be) continue;
-    uint32_t a = sa0;
+  for (uint32_t e = i0; e < i1; ++e) {
+    const int32_t u = icol[e];
+    const uint32_t* ur = c.boti + (uint64_t)(u - c.ci) * c.stri;
+    uint32_t a = ur[c.dk];
+    const uint32_t ae = ur[c.dk + 1];
+    if (a >= ae) continue;
+    uint32_t b = c0;
     int32_t x = col[a], y = col[b];
     while (true) {
       if (x == y) {
         ++cnt;
-        if (++a >= sa1 || ++b >= be) break;
+        if (++a >= ae || ++b >= c1) break;
         x = col[a];
         y = col[b];
       } else if (x < y) {
-        if (++a >= sa1) break;
+        if (++a >= ae) break;
         x = col[a];
       } else {
-        if (++b >= be) break;
+        if (++b >= c1) break;
         y = col[b];
       }
     }
@@ -98,54 +103,55 @@ __device__ __forceinline__ uint64_t light_row(const int32_t* __restrict__ col, c
 
 __device__ __forceinline__ uint32_t hash_slot(uint32_t w) { return (w * 0x9E3779B1u) >> (32 - kHashBits); }
 
-// One wavefront counts one heavy row.  Wave-uniform arguments.
-__device__ uint64_t heavy_row(const int32_t* __restrict__ col, const TaskCtx& c, uint32_t sb0, uint32_t sb1,
-                              uint32_t sa0, uint32_t sa1, bool use_hash, uint32_t mcol, uint32_t* abuf,
-                              uint32_t* sc0, uint32_t* sex) {
+// One wavefront counts one heavy column v.  Wave-uniform arguments:
+// in-slice [i0,i1) of icol and N(G_jk,v) = ocol[c0..c1).
+__device__ uint64_t heavy_col(const int32_t* __restrict__ col, const int32_t* __restrict__ icol, const TaskCtx& c,
+                              uint32_t i0, uint32_t i1, uint32_t c0, uint32_t c1, bool use_hash, uint32_t mcol,
+                              uint32_t* abuf, uint32_t* sa0, uint32_t* sex) {
   const int l = lane_id();
   uint64_t cnt = 0;
-  // 0: sorted copy + binary search, 1: bitmap over V_k, 2: hash of the row
+  // 0: sorted copy + binary search, 1: bitmap over V_k, 2: hash of the list
   int mode = 0;
   uint32_t piece = kABuf;
   if (use_hash) {
     if ((uint32_t)(c.ck1 - c.ck) <= kBitmapBits) {
       mode = 1;
-      piece = sa1 - sa0;
+      piece = c1 - c0;
     } else {
       mode = 2;
       piece = kABuf / 2;
     }
   }
-  for (uint32_t a_lo = sa0; a_lo < sa1; a_lo += piece) {
-    const uint32_t an = min(piece, sa1 - a_lo);
+  for (uint32_t s_lo = c0; s_lo < c1; s_lo += piece) {
+    const uint32_t sn = min(piece, c1 - s_lo);
     if (mode == 0) {
-      for (uint32_t t = l; t < an; t += kWave) abuf[t] = (uint32_t)col[a_lo + t];
+      for (uint32_t t = l; t < sn; t += kWave) abuf[t] = (uint32_t)col[s_lo + t];
     } else if (mode == 1) {
-      for (uint32_t t = l; t < an; t += kWave) {
-        const uint32_t x = (uint32_t)(col[a_lo + t] - c.ck);
+      for (uint32_t t = l; t < sn; t += kWave) {
+        const uint32_t x = (uint32_t)(col[s_lo + t] - c.ck);
         atomicOr(&abuf[x >> 5], 1u << (x & 31));
       }
     } else {
-      for (uint32_t t = l; t < an; t += kWave) {
-        const uint32_t key = (uint32_t)col[a_lo + t] + 1u;  // 0 marks an empty slot
+      for (uint32_t t = l; t < sn; t += kWave) {
+        const uint32_t key = (uint32_t)col[s_lo + t] + 1u;  // 0 marks an empty slot
         uint32_t s = hash_slot(key - 1u);
         for (int guard = 0; guard < kABuf && atomicCAS(&abuf[s], 0u, key) != 0u; ++guard) s = (s + 1) & (kABuf - 1);
       }
     }
     wave_sync();
-    const int32_t amin = col[a_lo], amax = col[a_lo + an - 1];
-    for (uint32_t eb = sb0; eb < sb1; eb += kWave) {
+    const int32_t smin = col[s_lo], smax = col[s_lo + sn - 1];
+    for (uint32_t eb = i0; eb < i1; eb += kWave) {
       const uint32_t e = eb + l;
-      uint32_t len = 0, c0 = 0;
-      if (e < sb1) {
-        const int32_t v = col[e];
-        const uint32_t* vr = c.botj + (uint64_t)(v - c.cj) * c.strj;
-        c0 = vr[c.dkj];
-        len = vr[c.dkj + 1] - c0;
+      uint32_t len = 0, a0 = 0;
+      if (e < i1) {
+        const int32_t u = icol[e];
+        const uint32_t* ur = c.boti + (uint64_t)(u - c.ci) * c.stri;
+        a0 = ur[c.dk];
+        len = ur[c.dk + 1] - a0;
       }
       const uint32_t inc = wave_incl_scan_u32(len);
       const uint32_t tot = __shfl(inc, kWave - 1, kWave);
-      sc0[l] = c0;
+      sa0[l] = a0;
       sex[l] = inc - len;
       wave_sync();
       for (uint32_t qb = 0; qb < tot; qb += kWave) {
@@ -156,16 +162,16 @@ __device__ uint64_t heavy_row(const int32_t* __restrict__ col, const TaskCtx& c,
             const int mid = (lo + hi + 1) >> 1;
             if (sex[mid] <= q) lo = mid; else hi = mid - 1;
           }
-          const uint32_t src = sc0[lo] + (q - sex[lo]);
+          const uint32_t src = sa0[lo] + (q - sex[lo]);
           const int32_t w = col[src < mcol ? src : mcol - 1];
-          if (w >= amin && w <= amax) {
+          if (w >= smin && w <= smax) {
             if (mode == 0) {
-              uint32_t x = 0, y = an;
+              uint32_t x = 0, y = sn;
               while (x < y) {
                 const uint32_t mid = (x + y) >> 1;
                 if (abuf[mid] < (uint32_t)w) x = mid + 1; else y = mid;
               }
-              cnt += (x < an && abuf[x] == (uint32_t)w) ? 1u : 0u;
+              cnt += (x < sn && abuf[x] == (uint32_t)w) ? 1u : 0u;
             } else if (mode == 1) {
               const uint32_t x = (uint32_t)(w - c.ck);
               cnt += (abuf[x >> 5] >> (x & 31)) & 1u;
@@ -173,9 +179,9 @@ __device__ uint64_t heavy_row(const int32_t* __restrict__ col, const TaskCtx& c,
               const uint32_t key = (uint32_t)w + 1u;
               uint32_t s = hash_slot((uint32_t)w);
               for (int guard = 0; guard < kABuf; ++guard) {
-                const uint32_t k = abuf[s];
-                if (k == key) { ++cnt; break; }
-                if (k == 0u) break;
+                const uint32_t kk = abuf[s];
+                if (kk == key) { ++cnt; break; }
+                if (kk == 0u) break;
                 s = (s + 1) & (kABuf - 1);
               }
             }
@@ -186,9 +192,9 @@ __device__ uint64_t heavy_row(const int32_t* __restrict__ col, const TaskCtx& c,
     }
     // restore the all-zero buffer
     if (mode == 0) {
-      for (uint32_t t = l; t < an; t += kWave) abuf[t] = 0;
+      for (uint32_t t = l; t < sn; t += kWave) abuf[t] = 0;
     } else if (mode == 1) {
-      for (uint32_t t = l; t < an; t += kWave) abuf[(uint32_t)(col[a_lo + t] - c.ck) >> 5] = 0;
+      for (uint32_t t = l; t < sn; t += kWave) abuf[(uint32_t)(col[s_lo + t] - c.ck) >> 5] = 0;
     } else {
       for (uint32_t t = l; t < kABuf; t += kWave) abuf[t] = 0;
     }
@@ -197,35 +203,40 @@ __device__ uint64_t heavy_row(const int32_t* __restrict__ col, const TaskCtx& c,
   return cnt;
 }
 
-// Rows [lo, hi) of the task's active-row list, by the whole workgroup.
-__device__ uint64_t process_rows(const PlanCtx& cp, const TaskCtx& c, uint32_t lo, uint32_t hi, CountLds& s) {
+// Active columns [lo, hi) of block (i,j), by the whole workgroup.
+__device__ uint64_t process_cols(const PlanCtx& cp, const TaskCtx& c, uint32_t lo, uint32_t hi, CountLds& s) {
   const int t = threadIdx.x, w = t / kWave;
   const int32_t* __restrict__ col = cp.g.ocol;
+  const int32_t* __restrict__ icol = cp.g.icol;
   uint64_t cnt = 0;
   for (uint32_t base = lo; base < hi; base += kThreads) {
     const uint32_t x = base + t;
     if (x < hi) {
-      const int32_t u = c.ar[x];
-      const uint32_t* ur = c.boti + (uint64_t)(u - c.ci) * c.stri;
-      const uint32_t sb0 = ur[c.dj], sb1 = ur[c.dj + 1], sa0 = ur[c.dk], sa1 = ur[c.dk + 1];
-      if (sa1 > sa0 && sb1 > sb0) {
-        if (sb1 - sb0 >= (uint32_t)cp.wave_min) {
-          const uint32_t qi = atomicAdd(&s.qn, 1u);
-          s.q[qi][0] = sb0;
-          s.q[qi][1] = sb1;
-          s.q[qi][2] = sa0;
-          s.q[qi][3] = sa1;
-        } else {
-          cnt += light_row(col, c, sb0, sb1, sa0, sa1);
+      const int32_t v = c.ac[x];
+      const uint32_t* vr = c.botj + (uint64_t)(v - c.cj) * c.strj;
+      const uint32_t c0 = vr[c.dkj], c1 = vr[c.dkj + 1];
+      if (c1 > c0) {
+        const uint32_t* tr = c.tbotj + (uint64_t)(v - c.cj) * c.tstrj;
+        const uint32_t i0 = tr[c.i], i1 = tr[c.i + 1];
+        if (i1 > i0) {
+          if ((i1 - i0) + (c1 - c0) >= (uint32_t)cp.wave_min) {
+            const uint32_t qi = atomicAdd(&s.qn, 1u);
+            s.q[qi][0] = i0;
+            s.q[qi][1] = i1;
+            s.q[qi][2] = c0;
+            s.q[qi][3] = c1;
+          } else {
+            cnt += light_col(col, icol, c, i0, i1, c0, c1);
+          }
         }
       }
     }
     __syncthreads();
     const uint32_t nq = s.qn;
     for (uint32_t h = w; h < nq; h += 4) {
-      const uint32_t sb0 = s.q[h][0], sb1 = s.q[h][1], sa0 = s.q[h][2], sa1 = s.q[h][3];
-      const bool use_hash = cp.hash_min >= 0 && (sa1 - sa0) >= (uint32_t)cp.hash_min;
-      cnt += heavy_row(col, c, sb0, sb1, sa0, sa1, use_hash, cp.g.m, s.abuf[w], s.sc0[w], s.sex[w]);
+      const uint32_t i0 = s.q[h][0], i1 = s.q[h][1], c0 = s.q[h][2], c1 = s.q[h][3];
+      const bool use_hash = cp.hash_min >= 0 && (c1 - c0) >= (uint32_t)cp.hash_min;
+      cnt += heavy_col(col, icol, c, i0, i1, c0, c1, use_hash, cp.g.m, s.abuf[w], s.sc0[w], s.sex[w]);
     }
     __syncthreads();
     if (t == 0) s.qn = 0;
@@ -250,7 +261,7 @@ __device__ __forceinline__ void flush(const PlanCtx& cp, int32_t out, uint64_t c
 }
 
 // One launch per task (the unbatched form): workgroup b takes rows
-// [b*256, b*256+256) of the task's active rows.
+// [b*256, b*256+256) of the task's active columns.
 __global__ __launch_bounds__(kThreads) void k_count_task(CountParams cp, int32_t task, uint32_t nrows) {
   __shared__ CountLds s;
   init_lds(s);
@@ -259,7 +270,7 @@ __global__ __launch_bounds__(kThreads) void k_count_task(CountParams cp, int32_t
   const TaskCtx c = make_ctx(pc.g, t);
   const uint32_t lo = blockIdx.x * kThreads;
   const uint32_t hi = min(nrows, lo + kThreads);
-  const uint64_t cnt = process_rows(pc, c, lo, hi, s);
+  const uint64_t cnt = process_cols(pc, c, lo, hi, s);
   flush(pc, t.out, cnt, s);
 }
 
@@ -279,7 +290,7 @@ __global__ __launch_bounds__(kThreads) void k_count_persistent(CountParams cp) {
     const PlanCtx pc = MULTI ? cp.many[item.plan] : cp.one;
     const DevTask t = pc.tasks[item.task];
     const TaskCtx c = make_ctx(pc.g, t);
-    const uint64_t cnt = process_rows(pc, c, item.lo, item.hi, s);
+    const uint64_t cnt = process_cols(pc, c, item.lo, item.hi, s);
     flush(pc, t.out, cnt, s);
   }
 }
@@ -294,7 +305,22 @@ __global__ __launch_bounds__(kThreads) void k_reset(uint64_t* per_task, int64_t 
   }
 }
 
+__global__ __launch_bounds__(kThreads) void k_reset_multi(const PlanCtx* ctxs, int32_t nplans, uint32_t* cursor) {
+  for (int32_t q = blockIdx.x; q < nplans; q += gridDim.x) {
+    const PlanCtx c = ctxs[q];
+    for (int64_t t = threadIdx.x; t < c.ntasks; t += kThreads) c.per_task[t] = 0;
+    if (threadIdx.x == 0) *c.total = 0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *cursor = 0;
+}
+
 }  // namespace
+
+hipError_t launch_reset_multi(const PlanCtx* ctxs, int32_t nplans, uint32_t* cursor, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset_multi, dim3(nplans > 0 ? (nplans < 1024 ? nplans : 1024) : 1), dim3(kThreads), 0, s, ctxs,
+                     nplans, cursor);
+  return hipGetLastError();
+}
 
 hipError_t launch_reset(uint64_t* per_task, int64_t ntasks, uint64_t* total, uint32_t* cursor, hipStream_t s) {
   int64_t g = (ntasks + kThreads - 1) / kThreads;

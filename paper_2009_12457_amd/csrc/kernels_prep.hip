@@ -205,12 +205,12 @@ __global__ __launch_bounds__(kThreads) void k_perm(const uint64_t* __restrict__ 
 }
 
 // ------------------------------------------------------------ orientation
-// One wavefront per original vertex x: its neighbours y with rank(y) >
-// rank(x) form the oriented row of rank(x).
+// One wavefront per original vertex x of rank r: neighbours y with rank(y) > r
+// form the out-row N(G,r), the others the in-row of r.
 template <typename RP>
-__global__ __launch_bounds__(kThreads) void k_outdeg(const RP* __restrict__ rowptr, const int32_t* __restrict__ colidx,
-                                                     int64_t n, const int32_t* __restrict__ perm,
-                                                     uint32_t* __restrict__ od) {
+__global__ __launch_bounds__(kThreads) void k_degs(const RP* __restrict__ rowptr, const int32_t* __restrict__ colidx,
+                                                   int64_t n, const int32_t* __restrict__ perm,
+                                                   uint32_t* __restrict__ od, uint32_t* __restrict__ idg) {
   const int l = lane_id();
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
@@ -224,15 +224,21 @@ __global__ __launch_bounds__(kThreads) void k_outdeg(const RP* __restrict__ rowp
       bool up = q < e && perm[colidx[q]] > r;
       c += (uint32_t)__popcll(ballot(up));
     }
-    if (l == 0) od[r] = c;
+    if (l == 0) {
+      od[r] = c;
+      idg[r] = (uint32_t)(e - b) - c;
+    }
   }
 }
 
+// Scatters rank ids into the out- and in-rows (order within a row follows the
+// input row; the rows are sorted afterwards).  Writes are bounded by the row
+// extents computed from the same predicate.
 template <typename RP>
 __global__ __launch_bounds__(kThreads) void k_fill(const RP* __restrict__ rowptr, const int32_t* __restrict__ colidx,
                                                    int64_t n, const int32_t* __restrict__ perm,
-                                                   const uint32_t* __restrict__ orow, int idbits,
-                                                   uint64_t* __restrict__ keys, uint64_t cap) {
+                                                   const uint32_t* __restrict__ orow, const uint32_t* __restrict__ irow,
+                                                   int32_t* __restrict__ ocol, int32_t* __restrict__ icol) {
   const int l = lane_id();
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
@@ -240,24 +246,173 @@ __global__ __launch_bounds__(kThreads) void k_fill(const RP* __restrict__ rowptr
     const int32_t r = perm[x];
     if (r < 0 || r >= n) continue;
     const int64_t b = (int64_t)rowptr[x], e = (int64_t)rowptr[x + 1];
-    uint64_t pos = orow[r];
-    const uint64_t hi = (uint64_t)r << idbits;
+    uint32_t po = orow[r], pi = irow[r];
+    const uint32_t po_end = orow[r + 1], pi_end = irow[r + 1];
     for (int64_t base = b; base < e; base += kWave) {
-      int64_t q = base + l;
-      int32_t ry = q < e ? perm[colidx[q]] : -1;
-      bool up = ry > r;
-      uint64_t mask = ballot(up);
-      const uint64_t dst = pos + lanes_below(mask);
-      if (up && dst < cap) keys[dst] = hi | (uint64_t)ry;
-      pos += (uint64_t)__popcll(mask);
+      const int64_t q = base + l;
+      const int32_t ry = q < e ? perm[colidx[q]] : -1;
+      const bool up = ry > r;
+      const bool down = q < e && !up;
+      const uint64_t mu = ballot(up), md = ballot(down);
+      const uint32_t du = po + lanes_below(mu), dd = pi + lanes_below(md);
+      if (up && du < po_end) ocol[du] = ry;
+      if (down && dd < pi_end) icol[dd] = ry;
+      po += (uint32_t)__popcll(mu);
+      pi += (uint32_t)__popcll(md);
     }
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_unpack(const uint64_t* __restrict__ keys, uint64_t m, uint64_t mask,
-                                                     int32_t* __restrict__ ocol) {
-  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (uint64_t)gridDim.x * blockDim.x)
-    ocol[e] = (int32_t)(keys[e] & mask);
+// ------------------------------------------------------------ row sort
+// Bitonic sort of buf[0..N), N a power of two, by `nthr` cooperating threads
+// numbered tid; SYNC orders LDS between stages.
+template <typename SYNC>
+__device__ __forceinline__ void bitonic_lds(int32_t* buf, uint32_t N, uint32_t tid, uint32_t nthr, SYNC sync) {
+  for (uint32_t k = 2; k <= N; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint32_t q = tid; q < (N >> 1); q += nthr) {
+        const uint32_t i = ((q & ~(j - 1)) << 1) | (q & (j - 1));
+        const uint32_t ixj = i | j;
+        const int32_t a = buf[i], c = buf[ixj];
+        const bool up = (i & k) == 0;
+        if ((a > c) == up) {
+          buf[i] = c;
+          buf[ixj] = a;
+        }
+      }
+      sync();
+    }
+  }
+}
+
+constexpr uint32_t kSegWave = 1024;    // longest row sorted by one wavefront
+constexpr uint32_t kSegBlock = 16384;  // longest row sorted by one workgroup
+
+__device__ __forceinline__ uint32_t pow2_at_least(uint32_t x) {
+  uint32_t n = 2;
+  while (n < x) n <<= 1;
+  return n;
+}
+
+// Wavefront per row; longer rows are queued: up to kSegBlock entries for
+// k_segsort_long, beyond that for k_segsort_huge.  q[0] counts the long rows,
+// q[1] the huge ones; both lists have room for every row.
+__global__ __launch_bounds__(kThreads) void k_segsort(const uint32_t* __restrict__ rp, int32_t* __restrict__ col,
+                                                      int64_t nrows, uint32_t* __restrict__ longrows,
+                                                      uint32_t* __restrict__ hugerows, uint32_t* __restrict__ q) {
+  __shared__ int32_t buf[4][kSegWave];
+  const int l = lane_id(), w = threadIdx.x / kWave;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  int32_t* b = buf[w];
+  for (int64_t r = wave; r < nrows; r += nwaves) {
+    const uint32_t s = rp[r], len = rp[r + 1] - s;
+    if (len <= 1) continue;
+    if (len > kSegWave) {
+      if (l == 0) {
+        if (len > kSegBlock) hugerows[atomicAdd(&q[1], 1u)] = (uint32_t)r;
+        else longrows[atomicAdd(&q[0], 1u)] = (uint32_t)r;
+      }
+      continue;
+    }
+    const uint32_t N = pow2_at_least(len);
+    for (uint32_t t = l; t < N; t += kWave) b[t] = t < len ? col[s + t] : 0x7FFFFFFF;
+    wave_sync();
+    bitonic_lds(b, N, (uint32_t)l, kWave, wave_sync);
+    for (uint32_t t = l; t < len; t += kWave) col[s + t] = b[t];
+    wave_sync();
+  }
+}
+
+// Workgroup per queued long row (up to kSegBlock entries).
+__global__ __launch_bounds__(kThreads) void k_segsort_long(const uint32_t* __restrict__ rp, int32_t* __restrict__ col,
+                                                           const uint32_t* __restrict__ longrows,
+                                                           const uint32_t* __restrict__ q) {
+  __shared__ int32_t buf[kSegBlock];
+  const uint32_t cnt = q[0];
+  for (uint32_t qi = blockIdx.x; qi < cnt; qi += gridDim.x) {
+    const uint32_t r = longrows[qi];
+    const uint32_t s = rp[r], len = rp[r + 1] - s;
+    if (len > kSegBlock) continue;
+    const uint32_t N = pow2_at_least(len);
+    for (uint32_t t = threadIdx.x; t < N; t += kThreads) buf[t] = t < len ? col[s + t] : 0x7FFFFFFF;
+    __syncthreads();
+    bitonic_lds(buf, N, threadIdx.x, kThreads, [] __device__() { __syncthreads(); });
+    for (uint32_t t = threadIdx.x; t < len; t += kThreads) col[s + t] = buf[t];
+    __syncthreads();
+  }
+}
+
+// Workgroup per queued huge row: LSD radix sort of the row, 8 bits per pass,
+// ping-ponging with scratch[rp[r] .. rp[r+1]) (rows own disjoint scratch, so
+// rows sort concurrently).  Each pass histograms the row, scans the 256 bins
+// and scatters tile by tile in input order, which keeps every pass stable.
+__global__ __launch_bounds__(kThreads) void k_segsort_huge(const uint32_t* __restrict__ rp, int32_t* __restrict__ col,
+                                                           int32_t* __restrict__ scratch,
+                                                           const uint32_t* __restrict__ hugerows,
+                                                           const uint32_t* __restrict__ q, int bits) {
+  __shared__ uint32_t hist[256];
+  __shared__ uint32_t wcnt[4][256];
+  __shared__ uint32_t lds[4];
+  const int t = threadIdx.x, w = t / kWave;
+  const uint32_t cnt = q[1];
+  for (uint32_t qi = blockIdx.x; qi < cnt; qi += gridDim.x) {
+    const uint32_t r = hugerows[qi];
+    const uint32_t s = rp[r], len = rp[r + 1] - s;
+    uint32_t* src = (uint32_t*)col + s;
+    uint32_t* dst = (uint32_t*)scratch + s;
+    int passes = 0;
+    for (int shift = 0; shift < bits; shift += 8, ++passes) {
+      hist[t] = 0;
+      __syncthreads();
+      for (uint32_t e = t; e < len; e += kThreads) atomicAdd(&hist[(src[e] >> shift) & 255u], 1u);
+      __syncthreads();
+      uint32_t tot;
+      const uint32_t base = block256_excl_scan<uint32_t>(hist[t], lds, &tot);
+      __syncthreads();
+      hist[t] = base;  // next output slot per digit
+      __syncthreads();
+      for (uint32_t tb = 0; tb < len; tb += kThreads) {
+        const uint32_t e = tb + t;
+        const bool valid = e < len;
+        const uint32_t key = valid ? src[e] : 0u;
+        const uint32_t d = (key >> shift) & 255u;
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) wcnt[qq][t] = 0;
+        __syncthreads();
+        uint64_t same = ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+          const bool on = (d >> bit) & 1u;
+          const uint64_t bm = ballot(on);
+          same &= on ? bm : ~bm;
+        }
+        const uint32_t below = lanes_below(same);
+        if (valid && below == 0) wcnt[w][d] = (uint32_t)__popcll(same);
+        __syncthreads();
+        {
+          const uint32_t c0 = wcnt[0][t], c1 = wcnt[1][t], c2 = wcnt[2][t], c3 = wcnt[3][t];
+          const uint32_t b0 = hist[t];
+          wcnt[0][t] = b0;
+          wcnt[1][t] = b0 + c0;
+          wcnt[2][t] = b0 + c0 + c1;
+          wcnt[3][t] = b0 + c0 + c1 + c2;
+          hist[t] = b0 + c0 + c1 + c2 + c3;
+        }
+        __syncthreads();
+        const uint32_t pos = wcnt[w][d] + below;
+        if (valid && pos < len) dst[pos] = key;
+        __syncthreads();
+      }
+      uint32_t* tmp = src;
+      src = dst;
+      dst = tmp;
+    }
+    if (passes & 1) {  // result is in scratch: copy back
+      for (uint32_t e = t; e < len; e += kThreads) ((uint32_t*)col)[s + e] = ((uint32_t*)scratch)[s + e];
+    }
+    __syncthreads();
+  }
 }
 
 // ------------------------------------------------------------ cut vector
@@ -291,10 +446,8 @@ __global__ void k_cuts(const uint32_t* __restrict__ orow, int64_t n, int32_t p, 
 }
 
 // ------------------------------------------------------------ block row index
-// Workgroup per chunk of kPrepRows consecutive rows of one part a; thread per
-// row.  The thread walks its sorted row once against the cut vector, writing
-// the row's block boundaries (bot) and counting per block the entries and the
-// non-empty rows.
+// Workgroup per chunk of kPrepRows consecutive rows of one part; thread per
+// row.  chunk0[a] is the first chunk of part a.
 __device__ __forceinline__ int chunk_part(const int32_t* chunk0, int32_t p, int32_t c) {
   int lo = 0, hi = p;  // largest a with chunk0[a] <= c
   while (hi - lo > 1) {
@@ -304,6 +457,22 @@ __device__ __forceinline__ int chunk_part(const int32_t* chunk0, int32_t p, int3
   return lo;
 }
 
+// First position in sorted col[ptr..re) whose value is >= key.
+__device__ __forceinline__ uint32_t seek(const int32_t* __restrict__ col, uint32_t ptr, uint32_t re, int32_t key) {
+  if (re - ptr > 16) {
+    uint32_t lo = ptr, hi = re;
+    while (lo < hi) {
+      uint32_t mid = (lo + hi) >> 1;
+      if (col[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+  }
+  while (ptr < re && col[ptr] < key) ++ptr;
+  return ptr;
+}
+
+// Out side: the row of u in part a gets its block boundaries for b = a..p;
+// per block the entries, the non-empty rows and the longest slice are counted.
 __global__ __launch_bounds__(kThreads) void k_bot(BlockBuild bb) {
   __shared__ uint32_t s_nnz[kMaxP];
   __shared__ uint32_t s_nzr[kMaxP];
@@ -311,7 +480,6 @@ __global__ __launch_bounds__(kThreads) void k_bot(BlockBuild bb) {
   const int32_t p = bb.p;
   const int a = chunk_part(bb.chunk0, p, blockIdx.x);
   const int lc = blockIdx.x - bb.chunk0[a];
-  const int nch = bb.chunk0[a + 1] - bb.chunk0[a];
   const int nb = p - a;  // blocks (a,a)..(a,p-1)
   for (int b = threadIdx.x; b < nb; b += kThreads) s_nnz[b] = s_nzr[b] = 0;
   if (threadIdx.x == 0) s_dmax = s_dfull = 0;
@@ -324,21 +492,7 @@ __global__ __launch_bounds__(kThreads) void k_bot(BlockBuild bb) {
     out[0] = rb;
     uint32_t ptr = rb, prev = rb, dmax = 0;
     for (int b = a + 1; b <= p; ++b) {
-      if (b == p) {
-        ptr = re;
-      } else {
-        const int32_t cb = bb.cuts[b];
-        if (re - ptr > 16) {  // long remainder: binary search
-          uint32_t lo = ptr, hi = re;
-          while (lo < hi) {
-            uint32_t mid = (lo + hi) >> 1;
-            if (bb.ocol[mid] < cb) lo = mid + 1; else hi = mid;
-          }
-          ptr = lo;
-        } else {
-          while (ptr < re && bb.ocol[ptr] < cb) ++ptr;
-        }
-      }
+      ptr = (b == p) ? re : seek(bb.ocol, ptr, re, bb.cuts[b]);
       out[b - a] = ptr;
       const uint32_t len = ptr - prev;
       if (len) {
@@ -358,7 +512,6 @@ __global__ __launch_bounds__(kThreads) void k_bot(BlockBuild bb) {
       atomicAdd(&bb.bnnz[bid0 + b], (unsigned long long)s_nnz[b]);
       atomicAdd(&bb.bnzr[bid0 + b], (unsigned long long)s_nzr[b]);
     }
-    bb.ccnt[bb.ccbase[a] + (uint64_t)b * nch + lc] = s_nzr[b];
   }
   if (threadIdx.x == 0) {
     if (s_dmax) atomicMax(bb.dmax_block, s_dmax);
@@ -366,26 +519,60 @@ __global__ __launch_bounds__(kThreads) void k_bot(BlockBuild bb) {
   }
 }
 
-// Same chunk mapping: writes each block's non-empty rows in increasing order
-// at the offsets given by the scanned chunk counters.
-__global__ __launch_bounds__(kThreads) void k_arow(BlockBuild bb) {
+// In side: the in-row of v in part b gets its boundaries for parts a = 0..b+1
+// (entry a = first in-neighbour of rank >= cuts[a]); per block (a,b) the
+// columns with a non-empty in-slice are counted, per chunk as well.
+__global__ __launch_bounds__(kThreads) void k_tbot(BlockBuild bb) {
+  __shared__ uint32_t s_nzc[kMaxP];
+  const int32_t p = bb.p;
+  const int b = chunk_part(bb.chunk0, p, blockIdx.x);
+  const int lc = blockIdx.x - bb.chunk0[b];
+  const int nch = bb.chunk0[b + 1] - bb.chunk0[b];
+  const int na = b + 1;  // blocks (0,b)..(b,b)
+  for (int a = threadIdx.x; a < na; a += kThreads) s_nzc[a] = 0;
+  __syncthreads();
+  const int64_t cb = bb.cuts[b];
+  const int64_t v = cb + (int64_t)lc * kPrepRows + threadIdx.x;
+  if (v < bb.cuts[b + 1]) {
+    const uint32_t rb = bb.irow[v], re = bb.irow[v + 1];
+    uint32_t* out = bb.tbot + bb.tbotp[b] + (uint64_t)(v - cb) * (uint64_t)(na + 1);
+    out[0] = rb;
+    uint32_t ptr = rb, prev = rb;
+    for (int a = 1; a <= na; ++a) {
+      ptr = (a == na) ? re : seek(bb.icol, ptr, re, bb.cuts[a]);
+      out[a] = ptr;
+      if (ptr > prev) atomicAdd(&s_nzc[a - 1], 1u);
+      prev = ptr;
+    }
+  }
+  __syncthreads();
+  const int64_t cid0 = (int64_t)b * (b + 1) / 2;
+  for (int a = threadIdx.x; a < na; a += kThreads) {
+    if (s_nzc[a]) atomicAdd(&bb.bnzc[cid0 + a], (unsigned long long)s_nzc[a]);
+    bb.ccnt[bb.ccbase[b] + (uint64_t)a * nch + lc] = s_nzc[a];
+  }
+}
+
+// Writes, for every block (a,b), its columns v with a non-empty in-slice in
+// increasing order at the offsets given by the scanned chunk counters.
+__global__ __launch_bounds__(kThreads) void k_acol(BlockBuild bb) {
   __shared__ uint32_t lds[4];
   const int32_t p = bb.p;
-  const int a = chunk_part(bb.chunk0, p, blockIdx.x);
-  const int lc = blockIdx.x - bb.chunk0[a];
-  const int nch = bb.chunk0[a + 1] - bb.chunk0[a];
-  const int nb = p - a;
-  const int64_t ca = bb.cuts[a];
-  const int64_t u = ca + (int64_t)lc * kPrepRows + threadIdx.x;
-  const bool valid = u < bb.cuts[a + 1];
-  const uint32_t* row = bb.bot + bb.botp[a] + (uint64_t)(valid ? u - ca : 0) * (uint64_t)(nb + 1);
+  const int b = chunk_part(bb.chunk0, p, blockIdx.x);
+  const int lc = blockIdx.x - bb.chunk0[b];
+  const int nch = bb.chunk0[b + 1] - bb.chunk0[b];
+  const int na = b + 1;
+  const int64_t cb = bb.cuts[b];
+  const int64_t v = cb + (int64_t)lc * kPrepRows + threadIdx.x;
+  const bool valid = v < bb.cuts[b + 1];
+  const uint32_t* row = bb.tbot + bb.tbotp[b] + (uint64_t)(valid ? v - cb : 0) * (uint64_t)(na + 1);
   uint32_t lo = valid ? row[0] : 0u;
-  for (int b = 0; b < nb; ++b) {
-    uint32_t hi = valid ? row[b + 1] : 0u;
-    uint32_t f = (valid && hi > lo) ? 1u : 0u;
+  for (int a = 0; a < na; ++a) {
+    const uint32_t hi = valid ? row[a + 1] : 0u;
+    const uint32_t f = (valid && hi > lo) ? 1u : 0u;
     uint32_t tot;
-    uint32_t off = block256_excl_scan<uint32_t>(f, lds, &tot);
-    if (f) bb.arow[bb.ccoff[bb.ccbase[a] + (uint64_t)b * nch + lc] + off] = (int32_t)u;
+    const uint32_t off = block256_excl_scan<uint32_t>(f, lds, &tot);
+    if (f) bb.acol[bb.ccoff[bb.ccbase[b] + (uint64_t)a * nch + lc] + off] = (int32_t)v;
     lo = hi;
   }
 }
@@ -394,7 +581,7 @@ __global__ __launch_bounds__(kThreads) void k_arow(BlockBuild bb) {
 
 // ------------------------------------------------------------ launchers
 hipError_t launch_validate(const void* rowptr, int rp64, const int32_t* colidx, int64_t n, int64_t nnz,
-                               int symmetric, uint32_t* err, hipStream_t s) {
+                           int symmetric, uint32_t* err, hipStream_t s) {
   if (rp64)
     hipLaunchKernelGGL(k_validate<int64_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int64_t*)rowptr, colidx, n,
                        nnz, symmetric, err);
@@ -461,34 +648,38 @@ hipError_t launch_perm(const uint64_t* keys, int64_t n, int idbits, int32_t* ord
   return hipGetLastError();
 }
 
-hipError_t launch_outdeg(const void* rowptr, int rp64, const int32_t* colidx, int64_t n, const int32_t* perm,
-                         uint32_t* od, hipStream_t s) {
+hipError_t launch_degs(const void* rowptr, int rp64, const int32_t* colidx, int64_t n, const int32_t* perm,
+                       uint32_t* od, uint32_t* idg, hipStream_t s) {
   if (n == 0) return hipSuccess;
   if (rp64)
-    hipLaunchKernelGGL(k_outdeg<int64_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int64_t*)rowptr, colidx, n,
-                       perm, od);
+    hipLaunchKernelGGL(k_degs<int64_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int64_t*)rowptr, colidx, n, perm,
+                       od, idg);
   else
-    hipLaunchKernelGGL(k_outdeg<int32_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int32_t*)rowptr, colidx, n,
-                       perm, od);
+    hipLaunchKernelGGL(k_degs<int32_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int32_t*)rowptr, colidx, n, perm,
+                       od, idg);
   return hipGetLastError();
 }
 
 hipError_t launch_fill(const void* rowptr, int rp64, const int32_t* colidx, int64_t n, const int32_t* perm,
-                       const uint32_t* orow, int idbits, uint64_t* keys, uint64_t cap, hipStream_t s) {
+                       const uint32_t* orow, const uint32_t* irow, int32_t* ocol, int32_t* icol, hipStream_t s) {
   if (n == 0) return hipSuccess;
   if (rp64)
     hipLaunchKernelGGL(k_fill<int64_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int64_t*)rowptr, colidx, n, perm,
-                       orow, idbits, keys, cap);
+                       orow, irow, ocol, icol);
   else
     hipLaunchKernelGGL(k_fill<int32_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int32_t*)rowptr, colidx, n, perm,
-                       orow, idbits, keys, cap);
+                       orow, irow, ocol, icol);
   return hipGetLastError();
 }
 
-hipError_t launch_unpack(const uint64_t* keys, uint64_t m, int idbits, int32_t* ocol, hipStream_t s) {
-  if (m == 0) return hipSuccess;
-  const uint64_t mask = (1ull << idbits) - 1;
-  hipLaunchKernelGGL(k_unpack, dim3(grid_for(m, kThreads, 65536)), dim3(kThreads), 0, s, keys, m, mask, ocol);
+hipError_t launch_segsort(const uint32_t* rp, int32_t* col, int64_t nrows, int bits, uint32_t* longrows,
+                          uint32_t* hugerows, uint32_t* q, int32_t* scratch, hipStream_t s) {
+  if (nrows == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_segsort, dim3(kRowGrid), dim3(kThreads), 0, s, rp, col, nrows, longrows, hugerows, q);
+  hipLaunchKernelGGL(k_segsort_long, dim3(1024), dim3(kThreads), 0, s, rp, col, (const uint32_t*)longrows,
+                     (const uint32_t*)q);
+  hipLaunchKernelGGL(k_segsort_huge, dim3(256), dim3(kThreads), 0, s, rp, col, scratch, (const uint32_t*)hugerows,
+                     (const uint32_t*)q, bits);
   return hipGetLastError();
 }
 
@@ -503,9 +694,15 @@ hipError_t launch_bot(const BlockBuild& bb, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_arow(const BlockBuild& bb, hipStream_t s) {
+hipError_t launch_tbot(const BlockBuild& bb, hipStream_t s) {
   if (bb.nchunks == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_arow, dim3(bb.nchunks), dim3(kThreads), 0, s, bb);
+  hipLaunchKernelGGL(k_tbot, dim3(bb.nchunks), dim3(kThreads), 0, s, bb);
+  return hipGetLastError();
+}
+
+hipError_t launch_acol(const BlockBuild& bb, hipStream_t s) {
+  if (bb.nchunks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_acol, dim3(bb.nchunks), dim3(kThreads), 0, s, bb);
   return hipGetLastError();
 }
 

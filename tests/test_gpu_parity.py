@@ -220,3 +220,62 @@ def test_rmat20_p16_full_parity(mode):
     g = graphgen.workload("rmat20")
     plan, per, tot = run(g, trusted=True, p=16, mode=MODES[mode])
     check(g, plan, per, tot, deep=(mode == "persistent"))
+
+
+# ---------------------------------------------------------------- graphs and shared launches
+def test_graph_replays_match_eager():
+    """The captured count is replayed several times with eager launches and
+    other device work in between; every replay must equal the eager result."""
+    g = graphgen.workload("rmat14_ef8")
+    n, rp, ci = bb.csr_of(g, "cuda")
+    pg = bb.bbtc_partition(n, rp, ci, options=bb.bbtc_options_default(p=12, graph=0))
+    pe = bb.bbtc_partition(n, rp, ci, options=bb.bbtc_options_default(p=12, graph=-1))
+    other = graphgen.workload("rmat12")
+    n2, rp2, ci2 = bb.csr_of(other, "cuda")
+    per_g = torch.empty(pg.ntasks, dtype=torch.int64, device="cuda")
+    tot_g = torch.empty(1, dtype=torch.int64, device="cuda")
+    per_e, tot_e = bb.bbtc_count(pe)
+    torch.cuda.synchronize()
+    ref = (per_e.cpu().clone(), int(tot_e.item()))
+    check(g, pe, ref[0].numpy().view(np.uint64)[:pe.ntasks], ref[1], deep=False)
+    scratch = None
+    for r in range(5):
+        per_g.fill_(-1)
+        bb.bbtc_count(pg, per_g, tot_g)
+        torch.cuda.synchronize()
+        assert int(tot_g.item()) == ref[1], r
+        assert torch.equal(per_g.cpu(), ref[0]), r
+        scratch = bb.bbtc_partition(n2, rp2, ci2, options=bb.bbtc_options_default(p=5), plan=scratch)
+        bb.bbtc_count(scratch)
+        bb.bbtc_count(pe, per_e, tot_e)
+        torch.cuda.synchronize()
+        assert torch.equal(per_e.cpu(), ref[0])
+    # new output buffers force a new capture
+    per2, tot2 = bb.bbtc_count(pg)
+    torch.cuda.synchronize()
+    assert int(tot2.item()) == ref[1] and torch.equal(per2.cpu(), ref[0])
+
+
+def test_count_multi_matches_alone():
+    """Each plan's result is the same alone and in a shared launch."""
+    specs = [("rmat12", 7, bb.BBTC_MODE_PERSISTENT), ("er2000", 4, bb.BBTC_MODE_PLAIN_HMAP),
+             ("rmat14_ef8", 16, bb.BBTC_MODE_PERSISTENT), ("rmat10", 1, bb.BBTC_MODE_PLAIN_INTERSECT)]
+    graphs, plans, alone = [], [], []
+    for name, p, mode in specs:
+        g = graphgen.workload(name)
+        plan, per, tot = run(g, p=p, mode=mode)
+        check(g, plan, per, tot, deep=False)
+        graphs.append(g)
+        plans.append(plan)
+        alone.append((per, tot))
+    for rep in range(3):
+        pers, tots = bb.bbtc_count_multi(plans)
+        torch.cuda.synchronize()
+        for q, plan in enumerate(plans):
+            got = pers[q].cpu().numpy().view(np.uint64)[:plan.ntasks]
+            assert int(tots[q].item()) == alone[q][1], (rep, q)
+            assert np.array_equal(got, alone[q][0]), (rep, q)
+    # subsets and repeats in one launch
+    pers, tots = bb.bbtc_count_multi([plans[2], plans[0]])
+    torch.cuda.synchronize()
+    assert int(tots[0].item()) == alone[2][1] and int(tots[1].item()) == alone[0][1]
