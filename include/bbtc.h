@@ -171,6 +171,20 @@ bbtc_status bbtc_count(bbtc_plan* plan, void* stream, uint64_t* d_per_task, uint
 bbtc_status bbtc_count_multi(bbtc_plan* const* plans, int32_t nplans, void* stream,
                              uint64_t* const* d_per_task, uint64_t* d_totals);
 
+/*
+ * Autotuner.  Picks p, wave_min and hash_min for this graph by timing the
+ * persistent count (HIP events on `stream`, median of `reps` launches after
+ * one warm-up) by coordinate descent: first p over {p0/4, p0/2, p0, 2*p0}
+ * (p0 = base->p, or the average degree when base->p is 0: Sec. 7.2 of the
+ * paper suggests p near the average degree), then wave_min over
+ * {2, 8, 32, 128}, then hash_min over {-1, 1, 32, 256}.  The other fields of
+ * *base are kept.  Every candidate gives identical counts; only time differs.
+ * On success *out holds the chosen options and *best_ms (if not NULL) the
+ * count time with them.  Synchronises `stream`.
+ */
+bbtc_status bbtc_autotune(const bbtc_csr* g, const bbtc_options* base, int32_t reps, void* stream,
+                          bbtc_options* out, double* best_ms);
+
 /* Borrowed host views, valid until the plan is rebuilt or destroyed. */
 bbtc_status bbtc_plan_tasks(const bbtc_plan* plan, const bbtc_task** tasks, int64_t* ntasks);
 bbtc_status bbtc_plan_cuts(const bbtc_plan* plan, const int32_t** cuts, int32_t* p);

@@ -76,6 +76,8 @@ _SIGS = {
                                         ctypes.POINTER(_P)]),
     "bbtc_count": (ctypes.c_int32, [_P, _P, _P, _P]),
     "bbtc_count_multi": (ctypes.c_int32, [ctypes.POINTER(_P), ctypes.c_int32, _P, ctypes.POINTER(_P), _P]),
+    "bbtc_autotune": (ctypes.c_int32, [ctypes.POINTER(bbtc_csr), ctypes.POINTER(bbtc_options), ctypes.c_int32, _P,
+                                       ctypes.POINTER(bbtc_options), ctypes.POINTER(ctypes.c_double)]),
     "bbtc_plan_tasks": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.POINTER(bbtc_task)),
                                          ctypes.POINTER(ctypes.c_int64)]),
     "bbtc_plan_cuts": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.POINTER(ctypes.c_int32)),
@@ -93,7 +95,7 @@ _SIGS = {
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built (run __graft_entry__.build() or "
-                          f"python -m paper_2009_12457_amd.build)")
+                          f"python paper_2009_12457_amd/build.py)")
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in _SIGS.items():
         fn = getattr(lib, name)
@@ -239,6 +241,51 @@ class Plan:
             pass
 
 
+def _csr_struct(n, rowptr, colidx, trusted):
+    rp, rp_dev, rp_size, keep_rp = _array_ptr(rowptr)
+    ci, ci_dev, ci_size, keep_ci = _array_ptr(colidx)
+    if rp_size not in (4, 8) or ci_size != 4:
+        raise TypeError("rowptr must be int32/int64 and colidx int32")
+    if rp_dev != ci_dev:
+        raise ValueError("rowptr and colidx must both be on the host or both on the device")
+    nnz = int(keep_ci.shape[0])
+    g = bbtc_csr(n=int(n), nnz=nnz, rowptr=rp, rowptr_bits=8 * rp_size,
+                 flags=(BBTC_CSR_DEVICE if rp_dev else 0) | (BBTC_CSR_TRUSTED if trusted else 0),
+                 colidx=ci if nnz else None)
+    return g, (keep_rp, keep_ci)
+
+
+def bbtc_autotune(n, rowptr, colidx, base=None, reps: int = 3, stream=None, trusted: bool = False,
+                  cache_path: str | None = None):
+    """Chosen options (and count ms) for this graph; optionally cached in a
+    JSON file keyed by a signature of the graph (n, nnz, degree moments)."""
+    import json
+    key = None
+    if cache_path:
+        import torch
+        rp = rowptr if isinstance(rowptr, np.ndarray) else rowptr.detach().cpu().numpy()
+        deg = np.diff(rp.astype(np.int64))
+        key = f"n{int(n)}-nnz{int(rp[-1])}-d2{int((deg * deg).sum())}-dmax{int(deg.max()) if len(deg) else 0}"
+        if base is not None:
+            key += f"-p{base.p}-cut{base.cut_mode}"
+        if os.path.exists(cache_path):
+            cache = json.load(open(cache_path))
+            if key in cache:
+                rec = cache[key]
+                return bbtc_options_default(**rec["options"]), rec["ms"]
+    g, keep = _csr_struct(n, rowptr, colidx, trusted)
+    out = bbtc_options()
+    ms = ctypes.c_double()
+    _check(_lib.bbtc_autotune(ctypes.byref(g), ctypes.byref(base) if base is not None else None, int(reps),
+                              _stream_handle(stream), ctypes.byref(out), ctypes.byref(ms)), "bbtc_autotune")
+    if cache_path:
+        cache = json.load(open(cache_path)) if os.path.exists(cache_path) else {}
+        cache[key] = {"options": {f: getattr(out, f) for f, _ in bbtc_options._fields_}, "ms": ms.value}
+        with open(cache_path, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+    return out, ms.value
+
+
 def bbtc_partition(n, rowptr, colidx, options=None, stream=None, plan: Plan | None = None,
                    trusted: bool = False) -> Plan:
     """Builds (or rebuilds in place) a plan for a symmetric CSR graph.
@@ -246,20 +293,10 @@ def bbtc_partition(n, rowptr, colidx, options=None, stream=None, plan: Plan | No
     rowptr/colidx: numpy arrays (host) or torch tensors (host or device);
     rowptr int32 or int64, colidx int32.
     """
-    rp, rp_dev, rp_size, keep_rp = _array_ptr(rowptr)
-    ci, ci_dev, ci_size, keep_ci = _array_ptr(colidx)
-    if rp_size not in (4, 8) or ci_size != 4:
-        raise TypeError("rowptr must be int32/int64 and colidx int32")
-    if rp_dev != ci_dev:
-        raise ValueError("rowptr and colidx must both be on the host or both on the device")
-    nnz = int(keep_ci.shape[0]) if hasattr(keep_ci, "shape") else len(keep_ci)
-    g = bbtc_csr(n=int(n), nnz=nnz, rowptr=rp, rowptr_bits=8 * rp_size,
-                 flags=(BBTC_CSR_DEVICE if rp_dev else 0) | (BBTC_CSR_TRUSTED if trusted else 0),
-                 colidx=ci if nnz else None)
+    g, keep = _csr_struct(n, rowptr, colidx, trusted)
     opt = options if options is not None else bbtc_options_default()
     h = ctypes.c_void_p(plan.handle.value if plan is not None else None)
-    st = _lib.bbtc_partition(ctypes.byref(g), ctypes.byref(opt), _stream_handle(stream) if rp_dev or plan else
-                             _stream_handle(stream), ctypes.byref(h))
+    st = _lib.bbtc_partition(ctypes.byref(g), ctypes.byref(opt), _stream_handle(stream), ctypes.byref(h))
     _check(st, "bbtc_partition")
     if plan is not None:
         plan._h = h

@@ -1,6 +1,6 @@
 """Builds libbbtc.so (HIP for gfx950) in this package directory.
 
-Usage: python -m paper_2009_12457_amd.build
+Usage: python paper_2009_12457_amd/build.py  (runs without importing the package)
 """
 import os
 import subprocess

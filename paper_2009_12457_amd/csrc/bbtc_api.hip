@@ -94,6 +94,7 @@ struct bbtc_plan {
   DevBuf<unsigned long long> bnnz, bnzr, bnzc;
   DevBuf<DevTask> tasks;
   DevBuf<DevItem> items;
+  DevBuf<HeavyCol> heavy;
   // host
   std::vector<int32_t> h_cuts;
   std::vector<int64_t> h_nnz, h_nzr, h_nzc;  // nzc in column-major block order
@@ -101,6 +102,9 @@ struct bbtc_plan {
   std::vector<DevTask> h_dtasks;   // same order
   std::vector<int32_t> h_work;     // plan-order indices of WORK tasks
   std::vector<DevItem> h_items;
+  std::vector<HeavyCol> h_heavy;   // hub columns, sorted by (block, column)
+  std::vector<int64_t> h_hub_first, h_hub_count;  // per plan-order task: its hub items
+  uint32_t split = 0;              // in-slice length above which a column is a hub
   int64_t ccount = 0;              // number of chunk counters
   int ncu = 0, blocks_per_cu = 0;
   hipStream_t side[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -133,7 +137,7 @@ struct bbtc_plan {
     hugerows.release();
     bot.release(); tbot.release(); ccnt.release(); ccoff.release(); dmax.release(); cursor.release();
     err.release(); ccbase.release(); botp.release(); tbotp.release(); acp.release(); bnnz.release();
-    bnzr.release(); bnzc.release(); tasks.release(); items.release();
+    bnzr.release(); bnzc.release(); tasks.release(); items.release(); heavy.release();
   }
 
   size_t footprint() const {
@@ -143,7 +147,7 @@ struct bbtc_plan {
            hugerows.bytes() + bot.bytes() +
            tbot.bytes() + ccnt.bytes() + ccoff.bytes() + dmax.bytes() + cursor.bytes() + err.bytes() +
            ccbase.bytes() + botp.bytes() + tbotp.bytes() + acp.bytes() + bnnz.bytes() + bnzr.bytes() +
-           bnzc.bytes() + tasks.bytes() + items.bytes();
+           bnzc.bytes() + tasks.bytes() + items.bytes() + heavy.bytes();
   }
 };
 
@@ -221,6 +225,8 @@ void fill_defaults(bbtc_options* o) {
 constexpr int kDefaultWaveMin = 16;
 constexpr int kDefaultHashMin = 64;
 constexpr int kDefaultItemRows = 256;
+constexpr uint32_t kHubSplit = 512;   // in-slice length above which a column is split
+constexpr uint32_t kHubChunk = 1024;  // in-neighbours per hub work item
 
 int eff_wave_min(const bbtc_options& o) { return o.wave_min > 0 ? o.wave_min : kDefaultWaveMin; }
 int eff_hash_min(const bbtc_options& o) {
@@ -249,6 +255,8 @@ PlanCtx plan_ctx(const bbtc_plan* pl, uint64_t* per_task, uint64_t* total) {
   c.total = total;
   c.wave_min = eff_wave_min(pl->opt);
   c.hash_min = eff_hash_min(pl->opt);
+  c.split = pl->split;
+  c.pad = 0;
   return c;
 }
 
@@ -281,17 +289,36 @@ void compose_tasks(bbtc_plan* pl) {
   pl->h_dtasks.resize(all.size());
   pl->h_work.clear();
   pl->h_items.clear();
-  const uint32_t step = (uint32_t)(pl->opt.item_rows > 0 ? pl->opt.item_rows : kDefaultItemRows);
+  pl->h_hub_first.assign(all.size(), 0);
+  pl->h_hub_count.assign(all.size(), 0);
   for (size_t q = 0; q < idx.size(); ++q) {
     const bbtc_task& t = all[idx[q]];
     pl->h_tasks[q] = t;
     pl->h_dtasks[q] = DevTask{t.i, t.j, t.k, (int32_t)q};
-    if (t.kind == BBTC_TASK_WORK) {
-      pl->h_work.push_back((int32_t)q);
-      const uint32_t rows = (uint32_t)pl->h_nzc[col_block_id(t.i, t.j)];
-      for (uint32_t lo = 0; lo < rows; lo += step)
-        pl->h_items.push_back(DevItem{0, (int32_t)q, lo, std::min(rows, lo + step)});
+    if (t.kind == BBTC_TASK_WORK) pl->h_work.push_back((int32_t)q);
+  }
+  // hub columns of each block (h_heavy is sorted by block)
+  const int64_t nb = p * (p + 1) / 2;
+  std::vector<int64_t> hstart((size_t)nb + 1, 0);
+  for (const HeavyCol& hc : pl->h_heavy) hstart[hc.cid + 1]++;
+  for (int64_t b = 0; b < nb; ++b) hstart[b + 1] += hstart[b];
+  // hub chunks first (heaviest tasks first), then the column ranges
+  for (int32_t q : pl->h_work) {
+    const bbtc_task& t = pl->h_tasks[q];
+    const int64_t cid = col_block_id(t.i, t.j);
+    pl->h_hub_first[q] = (int64_t)pl->h_items.size();
+    for (int64_t r = hstart[cid]; r < hstart[cid + 1]; ++r) {
+      const HeavyCol& hc = pl->h_heavy[r];
+      for (uint32_t lo = 0; lo < hc.cnt; lo += kHubChunk)
+        pl->h_items.push_back(DevItem{0, q, lo, std::min(hc.cnt, lo + kHubChunk), hc.v, 0});
     }
+    pl->h_hub_count[q] = (int64_t)pl->h_items.size() - pl->h_hub_first[q];
+  }
+  const uint32_t step = (uint32_t)(pl->opt.item_rows > 0 ? pl->opt.item_rows : kDefaultItemRows);
+  for (int32_t q : pl->h_work) {
+    const bbtc_task& t = pl->h_tasks[q];
+    const uint32_t cols = (uint32_t)pl->h_nzc[col_block_id(t.i, t.j)];
+    for (uint32_t lo = 0; lo < cols; lo += step) pl->h_items.push_back(DevItem{0, q, lo, std::min(cols, lo + step), -1, 0});
   }
 }
 
@@ -494,12 +521,22 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   bb.dmax_block = pl->dmax.ptr;
   bb.ccoff = pl->ccoff.ptr;
   bb.acol = pl->acol.ptr;
+  pl->split = kHubSplit;
+  const uint64_t hcap = m / kHubSplit + 1;
+  HIP_TRY(pl->heavy.ensure((size_t)hcap), "alloc");
+  HIP_TRY(hipMemsetAsync(pl->err.ptr + 2, 0, 4, s), "memset");
+  bb.split = pl->split;
+  bb.heavy = pl->heavy.ptr;
+  bb.nheavy = pl->err.ptr + 2;
+  bb.heavy_cap = (uint32_t)hcap;
   HIP_TRY(launch_bot(bb, s), "block row index");
   HIP_TRY(launch_tbot(bb, s), "block column index");
   HIP_TRY(scan_u32(pl->ccnt.ptr, pl->ccoff.ptr, cc, pl->partial.ptr, s), "scan chunk counters");
   HIP_TRY(launch_acol(bb, s), "active columns");
   std::vector<unsigned long long> hn((size_t)nb), hz((size_t)nb), hc((size_t)nb);
   uint32_t hd[2] = {0, 0};
+  uint32_t nheavy = 0;
+  HIP_TRY(hipMemcpyAsync(&nheavy, pl->err.ptr + 2, 4, hipMemcpyDeviceToHost, s), "D2H");
   HIP_TRY(hipMemcpyAsync(hn.data(), pl->bnnz.ptr, sizeof(unsigned long long) * nb, hipMemcpyDeviceToHost, s), "D2H");
   HIP_TRY(hipMemcpyAsync(hz.data(), pl->bnzr.ptr, sizeof(unsigned long long) * nb, hipMemcpyDeviceToHost, s), "D2H");
   HIP_TRY(hipMemcpyAsync(hc.data(), pl->bnzc.ptr, sizeof(unsigned long long) * nb, hipMemcpyDeviceToHost, s), "D2H");
@@ -508,6 +545,16 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   pl->h_nnz.assign(hn.begin(), hn.end());
   pl->h_nzr.assign(hz.begin(), hz.end());
   pl->h_nzc.assign(hc.begin(), hc.end());
+  if (nheavy > hcap) return fail(BBTC_EDEVICE, "hub column list overflow");
+  pl->h_heavy.resize(nheavy);
+  if (nheavy) {
+    HIP_TRY(hipMemcpyAsync(pl->h_heavy.data(), pl->heavy.ptr, sizeof(HeavyCol) * nheavy, hipMemcpyDeviceToHost, s),
+            "D2H");
+    HIP_TRY(hipStreamSynchronize(s), "sync");
+    std::sort(pl->h_heavy.begin(), pl->h_heavy.end(), [](const HeavyCol& a, const HeavyCol& b) {
+      return a.cid != b.cid ? a.cid < b.cid : a.v < b.v;
+    });
+  }
 
   // ---- tasks (Alg. 4) and work items ----
   std::vector<uint64_t> acp((size_t)nb + 1);
@@ -561,19 +608,25 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   return BBTC_OK;
 }
 
-// Shared state of multi-plan launches: device copies of the plan contexts and
-// of the merged work list, filled from pinned host staging.
-struct MultiState {
-  std::mutex mu;
+// State of multi-plan launches: device copies of the plan contexts and of the
+// merged work list, filled from pinned host staging.  A ring of slots lets
+// several shared launches be in flight at once (on different streams); a slot
+// is reused only after the launch that last used it has finished.
+struct MultiSlot {
   DevBuf<PlanCtx> ctxs;
   DevBuf<DevItem> items;
   DevBuf<uint32_t> cursor;
   PlanCtx* h_ctx = nullptr;
   DevItem* h_items = nullptr;
   size_t cap_ctx = 0, cap_items = 0;
-  hipEvent_t copied = nullptr;
-  bool pending = false;
-  int ncu = 0, bpc = 0;
+  hipEvent_t done = nullptr;
+  bool used = false;
+};
+constexpr int kMultiSlots = 8;
+struct MultiState {
+  std::mutex mu;
+  MultiSlot slot[kMultiSlots];
+  int next = 0;
 };
 MultiState g_multi;
 
@@ -581,28 +634,23 @@ bbtc_status count_multi_impl(bbtc_plan* const* plans, int32_t nplans, hipStream_
                              uint64_t* d_totals) {
   MultiState& M = g_multi;
   std::lock_guard<std::mutex> lock(M.mu);
-  if (!M.copied) {
-    HIP_TRY(hipEventCreateWithFlags(&M.copied, hipEventDisableTiming), "hipEventCreate");
-    M.ncu = plans[0]->ncu;
-    M.bpc = plans[0]->blocks_per_cu;
-  }
-  if (M.pending) {  // the staging buffers may still be read by the last copy
-    HIP_TRY(hipEventSynchronize(M.copied), "event sync");
-    M.pending = false;
-  }
+  MultiSlot& S = M.slot[M.next];
+  M.next = (M.next + 1) % kMultiSlots;
+  if (!S.done) HIP_TRY(hipEventCreateWithFlags(&S.done, hipEventDisableTiming), "hipEventCreate");
+  if (S.used) HIP_TRY(hipEventSynchronize(S.done), "event sync");  // staging and buffers are free again
   size_t nitems = 0;
   for (int32_t q = 0; q < nplans; ++q) nitems += plans[q]->h_items.size();
-  if (M.cap_ctx < (size_t)nplans) {
-    if (M.h_ctx) (void)hipHostFree(M.h_ctx);
-    M.h_ctx = nullptr;
-    HIP_TRY(hipHostMalloc((void**)&M.h_ctx, sizeof(PlanCtx) * nplans, hipHostMallocDefault), "pinned alloc");
-    M.cap_ctx = (size_t)nplans;
+  if (S.cap_ctx < (size_t)nplans) {
+    if (S.h_ctx) (void)hipHostFree(S.h_ctx);
+    S.h_ctx = nullptr;
+    HIP_TRY(hipHostMalloc((void**)&S.h_ctx, sizeof(PlanCtx) * nplans, hipHostMallocDefault), "pinned alloc");
+    S.cap_ctx = (size_t)nplans;
   }
-  if (M.cap_items < nitems) {
-    if (M.h_items) (void)hipHostFree(M.h_items);
-    M.h_items = nullptr;
-    HIP_TRY(hipHostMalloc((void**)&M.h_items, sizeof(DevItem) * nitems, hipHostMallocDefault), "pinned alloc");
-    M.cap_items = nitems;
+  if (S.cap_items < nitems) {
+    if (S.h_items) (void)hipHostFree(S.h_items);
+    S.h_items = nullptr;
+    HIP_TRY(hipHostMalloc((void**)&S.h_items, sizeof(DevItem) * nitems, hipHostMallocDefault), "pinned alloc");
+    S.cap_items = nitems;
   }
   // heavier plans first (sum of task estimates), each plan's items in its own order
   std::vector<std::pair<double, int32_t>> order;
@@ -613,30 +661,32 @@ bbtc_status count_multi_impl(bbtc_plan* const* plans, int32_t nplans, hipStream_
   }
   std::stable_sort(order.begin(), order.end());
   size_t at = 0;
-  for (int32_t q = 0; q < nplans; ++q) M.h_ctx[q] = plan_ctx(plans[q], d_per_task[q], d_totals + q);
+  for (int32_t q = 0; q < nplans; ++q) S.h_ctx[q] = plan_ctx(plans[q], d_per_task[q], d_totals + q);
   for (const auto& pr : order) {
     for (DevItem it : plans[pr.second]->h_items) {
       it.plan = pr.second;
-      M.h_items[at++] = it;
+      S.h_items[at++] = it;
     }
   }
-  HIP_TRY(M.ctxs.ensure((size_t)nplans), "alloc");
-  HIP_TRY(M.items.ensure(std::max<size_t>(nitems, 1)), "alloc");
-  HIP_TRY(M.cursor.ensure(1), "alloc");
-  HIP_TRY(hipMemcpyAsync(M.ctxs.ptr, M.h_ctx, sizeof(PlanCtx) * nplans, hipMemcpyHostToDevice, s), "H2D");
-  if (nitems) HIP_TRY(hipMemcpyAsync(M.items.ptr, M.h_items, sizeof(DevItem) * nitems, hipMemcpyHostToDevice, s), "H2D");
-  HIP_TRY(hipEventRecord(M.copied, s), "event");
-  M.pending = true;
-  HIP_TRY(launch_reset_multi(M.ctxs.ptr, nplans, M.cursor.ptr, s), "reset");
-  if (nitems == 0) return BBTC_OK;
-  CountParams cp;
-  std::memset(&cp, 0, sizeof(cp));
-  cp.many = M.ctxs.ptr;
-  cp.items = M.items.ptr;
-  cp.nitems = (uint32_t)nitems;
-  cp.cursor = M.cursor.ptr;
-  int grid = (int)std::min<int64_t>((int64_t)M.bpc * M.ncu, (int64_t)nitems);
-  HIP_TRY(launch_count_persistent(cp, grid, true, s), "count");
+  HIP_TRY(S.ctxs.ensure((size_t)nplans), "alloc");
+  HIP_TRY(S.items.ensure(std::max<size_t>(nitems, 1)), "alloc");
+  HIP_TRY(S.cursor.ensure(1), "alloc");
+  HIP_TRY(hipMemcpyAsync(S.ctxs.ptr, S.h_ctx, sizeof(PlanCtx) * nplans, hipMemcpyHostToDevice, s), "H2D");
+  if (nitems) HIP_TRY(hipMemcpyAsync(S.items.ptr, S.h_items, sizeof(DevItem) * nitems, hipMemcpyHostToDevice, s), "H2D");
+  HIP_TRY(launch_reset_multi(S.ctxs.ptr, nplans, S.cursor.ptr, s), "reset");
+  if (nitems) {
+    CountParams cp;
+    std::memset(&cp, 0, sizeof(cp));
+    cp.many = S.ctxs.ptr;
+    cp.items = S.items.ptr;
+    cp.nitems = (uint32_t)nitems;
+    cp.cursor = S.cursor.ptr;
+    const int ncu = plans[0]->ncu, bpc = plans[0]->blocks_per_cu;
+    int grid = (int)std::min<int64_t>((int64_t)bpc * ncu, (int64_t)nitems);
+    HIP_TRY(launch_count_persistent(cp, grid, true, s), "count");
+  }
+  HIP_TRY(hipEventRecord(S.done, s), "event");
+  S.used = true;
   return BBTC_OK;
 }
 
@@ -724,6 +774,8 @@ bbtc_status bbtc_count(bbtc_plan* pl, void* stream, uint64_t* d_per_task, uint64
     const bbtc_task& tk = pl->h_tasks[t];
     const uint32_t cols = (uint32_t)pl->h_nzc[col_block_id(tk.i, tk.j)];
     HIP_TRY(launch_count_task(cp, t, cols, pl->side[w % 4]), "count task");
+    HIP_TRY(launch_count_items(cp, (uint32_t)pl->h_hub_first[t], (uint32_t)pl->h_hub_count[t], pl->side[w % 4]),
+            "count hub columns");
   }
   for (int q = 0; q < 4; ++q) {
     HIP_TRY(hipEventRecord(pl->ev_join[q], pl->side[q]), "event");
@@ -746,6 +798,104 @@ bbtc_status bbtc_count_multi(bbtc_plan* const* plans, int32_t nplans, void* stre
   } catch (const std::bad_alloc&) {
     return fail(BBTC_ENOMEM, "host allocation failed");
   }
+}
+
+bbtc_status bbtc_autotune(const bbtc_csr* g, const bbtc_options* base, int32_t reps, void* stream, bbtc_options* out,
+                          double* best_ms) {
+  g_err.clear();
+  if (!g || !out) return fail(BBTC_EINVAL, "null argument");
+  if (reps < 1 || reps > 100) return fail(BBTC_EINVAL, "reps must be in [1, 100]");
+  hipStream_t s = (hipStream_t)stream;
+  bbtc_options cur;
+  if (base) cur = *base; else fill_defaults(&cur);
+  cur.mode = BBTC_MODE_PERSISTENT;
+  bbtc_plan* pl = nullptr;
+  uint64_t* d_out = nullptr;
+  size_t d_cap = 0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  bbtc_status st = BBTC_OK;
+  double best = 1e300;
+  bbtc_options best_opt = cur;
+  // time one candidate; returns the median count time in ms (or a status < 0)
+  auto measure = [&](const bbtc_options& o, double* ms) -> bbtc_status {
+    bbtc_status r = bbtc_partition(g, &o, stream, &pl);
+    if (r != BBTC_OK) return r;
+    const size_t need = pl->h_tasks.size() + 1;
+    if (need > d_cap) {
+      if (d_out) (void)hipFree(d_out);
+      d_out = nullptr;
+      HIP_TRY(hipMalloc((void**)&d_out, need * sizeof(uint64_t)), "alloc");
+      d_cap = need;
+    }
+    uint64_t* tot = d_out + (need - 1);
+    r = bbtc_count(pl, stream, d_out, tot);
+    if (r != BBTC_OK) return r;
+    std::vector<float> t;
+    for (int q = 0; q < reps; ++q) {
+      HIP_TRY(hipEventRecord(e0, s), "event");
+      r = bbtc_count(pl, stream, d_out, tot);
+      if (r != BBTC_OK) return r;
+      HIP_TRY(hipEventRecord(e1, s), "event");
+      HIP_TRY(hipEventSynchronize(e1), "event sync");
+      float v = 0;
+      HIP_TRY(hipEventElapsedTime(&v, e0, e1), "event time");
+      t.push_back(v);
+    }
+    std::sort(t.begin(), t.end());
+    *ms = t[t.size() / 2];
+    return BBTC_OK;
+  };
+  try {
+    HIP_TRY(hipEventCreate(&e0), "event");
+    HIP_TRY(hipEventCreate(&e1), "event");
+    // p0: requested, or from the average degree (needs n and nnz only)
+    int32_t p0 = cur.p;
+    if (p0 <= 0) {
+      const double avg = g->n > 0 ? (double)g->nnz / (double)g->n : 1.0;
+      p0 = std::max(1, (int32_t)std::lround(avg));
+    }
+    const int64_t pmax = std::min<int64_t>(g->n, kMaxP);
+    std::vector<int32_t> ps;
+    for (int32_t c : {p0 / 4, p0 / 2, p0, 2 * p0}) {
+      int32_t q = (int32_t)std::max<int64_t>(1, std::min<int64_t>(c, pmax));
+      if (std::find(ps.begin(), ps.end(), q) == ps.end()) ps.push_back(q);
+    }
+    for (int32_t q : ps) {
+      bbtc_options o = cur;
+      o.p = q;
+      double ms = 0;
+      st = measure(o, &ms);
+      if (st != BBTC_OK) break;
+      if (ms < best) { best = ms; best_opt = o; }
+    }
+    for (int32_t wm : {2, 8, 32, 128}) {
+      if (st != BBTC_OK) break;
+      bbtc_options o = best_opt;
+      o.wave_min = wm;
+      double ms = 0;
+      st = measure(o, &ms);
+      if (st == BBTC_OK && ms < best) { best = ms; best_opt = o; }
+    }
+    for (int32_t hm : {-1, 1, 32, 256}) {
+      if (st != BBTC_OK) break;
+      bbtc_options o = best_opt;
+      o.hash_min = hm;
+      double ms = 0;
+      st = measure(o, &ms);
+      if (st == BBTC_OK && ms < best) { best = ms; best_opt = o; }
+    }
+  } catch (const std::bad_alloc&) {
+    st = fail(BBTC_ENOMEM, "host allocation failed");
+  }
+  std::string msg = g_err;
+  if (pl) bbtc_plan_destroy(pl);
+  if (d_out) (void)hipFree(d_out);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (st != BBTC_OK) return fail(st, msg);
+  *out = best_opt;
+  if (best_ms) *best_ms = best;
+  return BBTC_OK;
 }
 
 bbtc_status bbtc_plan_tasks(const bbtc_plan* pl, const bbtc_task** tasks, int64_t* ntasks) {

@@ -21,12 +21,26 @@ struct DevTask {
   int32_t i, j, k, out;
 };
 
-// One unit of persistent work: entries [lo, hi) of the active-column list of
-// block (i,j) of task `task` of plan `plan` (plan is 0 for single-plan launches).
+// One unit of persistent work of task `task` of plan `plan` (plan is 0 for
+// single-plan launches):
+//   v < 0 : entries [lo, hi) of the active-column list of block (i,j);
+//   v >= 0: in-neighbours [lo, hi) (relative to the start of the in-slice)
+//           of one column v of G_ij whose in-slice is longer than the split
+//           threshold; such columns are skipped by column-range items.
 struct DevItem {
   int32_t plan;
   int32_t task;
   uint32_t lo, hi;
+  int32_t v;
+  int32_t pad;
+};
+
+// A column v of block (a,b) whose in-slice from V_a has more than `split`
+// entries (collected while the active columns are written).
+struct HeavyCol {
+  uint32_t cid;  // column-major block id of (a,b)
+  int32_t v;
+  uint32_t cnt;  // in-slice length
 };
 
 // Device view of the blocked graph (stripe layout plus block row index).
@@ -64,6 +78,8 @@ struct PlanCtx {
   uint64_t* total;
   int32_t wave_min;
   int32_t hash_min;  // < 0: never
+  uint32_t split;    // columns with longer in-slices come as split items
+  int32_t pad;
 };
 
 struct CountParams {
@@ -124,6 +140,10 @@ struct BlockBuild {
   uint32_t* dmax_block;      // [0] longest block slice, [1] longest oriented row
   const uint32_t* ccoff;     // exclusive scan of ccnt
   int32_t* acol;             // active columns, column-major block order
+  uint32_t split;            // in-slice length above which a column is recorded as heavy
+  HeavyCol* heavy;           // room for m/split + 1 records
+  uint32_t* nheavy;
+  uint32_t heavy_cap;
 };
 hipError_t launch_bot(const BlockBuild& bb, hipStream_t s);
 hipError_t launch_tbot(const BlockBuild& bb, hipStream_t s);
@@ -135,6 +155,8 @@ hipError_t launch_count_task(const CountParams& cp, int32_t task, uint32_t nrows
 // Zeroes the outputs of every plan of a multi-plan launch and the cursor.
 hipError_t launch_reset_multi(const PlanCtx* ctxs, int32_t nplans, uint32_t* cursor, hipStream_t s);
 hipError_t launch_count_persistent(const CountParams& cp, int grid, bool multi, hipStream_t s);
+// Items [first, first+count) of cp.items, one workgroup each.
+hipError_t launch_count_items(const CountParams& cp, uint32_t first, uint32_t count, hipStream_t s);
 int count_persistent_blocks_per_cu();
 
 }  // namespace bbtc

@@ -7,18 +7,21 @@
 // long one under degree ordering, is staged once per v and probed by the
 // short lists N(G_ik,u) of all of v's in-neighbours u in V_i.
 //
-// Two mappings (a tuning knob; both exact):
+// Three mappings (tuning knobs; all exact):
 //   * light columns (|in_i(v)| + |N(G_jk,v)| < wave_min): one lane per v, a
-//     two-pointer count of the sorted lists (Alg. 1) for each u;
-//   * heavy columns: one 64-lane wavefront per v.  N(G_jk,v) is staged in LDS,
-//     the lanes flatten the probe space {(u,w): u in in_i(v), w in N(G_ik,u)}
-//     with a wavefront prefix sum, and each w is tested against the stage:
-//       - Intersect form: binary search of a sorted LDS copy;
-//       - HMap form: a dense bitmap over the columns of V_k (the paper's dense
-//         hash map of the block's column range) when |V_k| fits in LDS, else
-//         an open-addressing LDS hash of N(G_jk,v).
-//     Lists longer than the LDS buffer are staged in disjoint pieces; a probe
-//     matches at most one piece, so the count stays exact.
+//     two-pointer count of the sorted lists (Alg. 1) for each in-neighbour u;
+//   * medium columns: one 64-lane wavefront per v; N(G_jk,v) is staged in LDS
+//     and every lane walks the N(G_ik,u) of its own in-neighbours, testing
+//     each w against the stage;
+//   * hub columns (in-slice longer than `split`): the host cuts the in-slice
+//     into chunks that are separate work items; a whole workgroup stages
+//     N(G_jk,v) once and its 256 lanes share the chunk's in-neighbours.
+// The stage is either the Intersect form (a sorted LDS copy, binary search)
+// or the HMap form (a dense LDS bitmap over the columns of V_k -- the paper's
+// dense hash map of the block's column range -- or, when V_k is too wide for
+// LDS, an open-addressing LDS hash).  Lists longer than the LDS buffer are
+// staged in disjoint pieces; a probe matches at most one piece, so the count
+// stays exact.
 #include "bbtc_internal.h"
 #include "dev_common.h"
 
@@ -32,10 +35,8 @@ constexpr int kHashBits = 11;                 // 2^11 = kABuf hash slots
 static_assert((1 << kHashBits) == kABuf, "hash table fills the wave buffer");
 
 struct CountLds {
-  uint32_t abuf[4][kABuf];  // per wave: sorted copy / bitmap / hash; all-zero between rows
-  uint32_t sc0[4][kWave];   // per wave: start of N(G_ik,u) for the batch's lanes
-  uint32_t sex[4][kWave];   // per wave: exclusive prefix of the batch's lengths
-  uint32_t q[kThreads][4];  // heavy-column queue: i0, i1, c0, c1
+  uint32_t abuf[4][kABuf];  // per wave: sorted copy / bitmap / hash; all-zero between uses
+  uint32_t q[kThreads][4];  // medium-column queue: i0, i1, c0, c1
   uint32_t qn;
   uint32_t item;
   unsigned long long red[4];
@@ -103,107 +104,114 @@ __device__ __forceinline__ uint64_t light_col(const int32_t* __restrict__ col, c
 
 __device__ __forceinline__ uint32_t hash_slot(uint32_t w) { return (w * 0x9E3779B1u) >> (32 - kHashBits); }
 
-// One wavefront counts one heavy column v.  Wave-uniform arguments:
-// in-slice [i0,i1) of icol and N(G_jk,v) = ocol[c0..c1).
-__device__ uint64_t heavy_col(const int32_t* __restrict__ col, const int32_t* __restrict__ icol, const TaskCtx& c,
-                              uint32_t i0, uint32_t i1, uint32_t c0, uint32_t c1, bool use_hash, uint32_t mcol,
-                              uint32_t* abuf, uint32_t* sa0, uint32_t* sex) {
-  const int l = lane_id();
-  uint64_t cnt = 0;
-  // 0: sorted copy + binary search, 1: bitmap over V_k, 2: hash of the list
-  int mode = 0;
-  uint32_t piece = kABuf;
-  if (use_hash) {
-    if ((uint32_t)(c.ck1 - c.ck) <= kBitmapBits) {
-      mode = 1;
-      piece = c1 - c0;
-    } else {
-      mode = 2;
-      piece = kABuf / 2;
+// How a stage of N(G_jk,v) is held: 0 sorted copy, 1 bitmap over V_k, 2 hash.
+struct Stage {
+  int mode;
+  uint32_t piece;  // entries staged at a time
+};
+
+__device__ __forceinline__ Stage pick_stage(const TaskCtx& c, bool use_hash, uint32_t len) {
+  if (!use_hash) return Stage{0, (uint32_t)kABuf};
+  if ((uint32_t)(c.ck1 - c.ck) <= kBitmapBits) return Stage{1, len};
+  return Stage{2, (uint32_t)kABuf / 2};
+}
+
+// Fills buf with col[lo, lo+sn) by `nthr` cooperating threads numbered tid.
+__device__ __forceinline__ void stage_fill(const Stage& st, uint32_t* buf, const int32_t* __restrict__ col,
+                                           uint32_t lo, uint32_t sn, int32_t ck, uint32_t tid, uint32_t nthr) {
+  if (st.mode == 0) {
+    for (uint32_t t = tid; t < sn; t += nthr) buf[t] = (uint32_t)col[lo + t];
+  } else if (st.mode == 1) {
+    for (uint32_t t = tid; t < sn; t += nthr) {
+      const uint32_t x = (uint32_t)(col[lo + t] - ck);
+      atomicOr(&buf[x >> 5], 1u << (x & 31));
+    }
+  } else {
+    for (uint32_t t = tid; t < sn; t += nthr) {
+      const uint32_t key = (uint32_t)col[lo + t] + 1u;  // 0 marks an empty slot
+      uint32_t s = hash_slot(key - 1u);
+      for (int guard = 0; guard < kABuf && atomicCAS(&buf[s], 0u, key) != 0u; ++guard) s = (s + 1) & (kABuf - 1);
     }
   }
-  for (uint32_t s_lo = c0; s_lo < c1; s_lo += piece) {
-    const uint32_t sn = min(piece, c1 - s_lo);
-    if (mode == 0) {
-      for (uint32_t t = l; t < sn; t += kWave) abuf[t] = (uint32_t)col[s_lo + t];
-    } else if (mode == 1) {
-      for (uint32_t t = l; t < sn; t += kWave) {
-        const uint32_t x = (uint32_t)(col[s_lo + t] - c.ck);
-        atomicOr(&abuf[x >> 5], 1u << (x & 31));
-      }
-    } else {
-      for (uint32_t t = l; t < sn; t += kWave) {
-        const uint32_t key = (uint32_t)col[s_lo + t] + 1u;  // 0 marks an empty slot
-        uint32_t s = hash_slot(key - 1u);
-        for (int guard = 0; guard < kABuf && atomicCAS(&abuf[s], 0u, key) != 0u; ++guard) s = (s + 1) & (kABuf - 1);
-      }
+}
+
+// Restores the all-zero buffer after stage_fill.
+__device__ __forceinline__ void stage_clear(const Stage& st, uint32_t* buf, const int32_t* __restrict__ col,
+                                            uint32_t lo, uint32_t sn, int32_t ck, uint32_t tid, uint32_t nthr) {
+  if (st.mode == 0) {
+    for (uint32_t t = tid; t < sn; t += nthr) buf[t] = 0;
+  } else if (st.mode == 1) {
+    for (uint32_t t = tid; t < sn; t += nthr) buf[(uint32_t)(col[lo + t] - ck) >> 5] = 0;
+  } else {
+    for (uint32_t t = tid; t < (uint32_t)kABuf; t += nthr) buf[t] = 0;
+  }
+}
+
+__device__ __forceinline__ uint32_t stage_has(const Stage& st, const uint32_t* buf, uint32_t sn, int32_t w,
+                                              int32_t ck) {
+  if (st.mode == 0) {
+    uint32_t x = 0, y = sn;
+    while (x < y) {
+      const uint32_t mid = (x + y) >> 1;
+      if (buf[mid] < (uint32_t)w) x = mid + 1; else y = mid;
     }
+    return (x < sn && buf[x] == (uint32_t)w) ? 1u : 0u;
+  }
+  if (st.mode == 1) {
+    const uint32_t x = (uint32_t)(w - ck);
+    return (buf[x >> 5] >> (x & 31)) & 1u;
+  }
+  const uint32_t key = (uint32_t)w + 1u;
+  uint32_t s = hash_slot((uint32_t)w);
+  for (int guard = 0; guard < kABuf; ++guard) {
+    const uint32_t kk = buf[s];
+    if (kk == key) return 1u;
+    if (kk == 0u) return 0u;
+    s = (s + 1) & (kABuf - 1);
+  }
+  return 0u;
+}
+
+// Each thread tid of `nthr` walks the in-neighbours icol[e], e in [i0+tid, i1)
+// step nthr, and tests every w of N(G_ik,u) in [smin, smax] against the stage.
+__device__ __forceinline__ uint64_t probe_in(const int32_t* __restrict__ col, const int32_t* __restrict__ icol,
+                                             const TaskCtx& c, uint32_t i0, uint32_t i1, const Stage& st,
+                                             const uint32_t* buf, uint32_t sn, int32_t smin, int32_t smax,
+                                             uint32_t tid, uint32_t nthr) {
+  uint64_t cnt = 0;
+  for (uint32_t e = i0 + tid; e < i1; e += nthr) {
+    const int32_t u = icol[e];
+    const uint32_t* ur = c.boti + (uint64_t)(u - c.ci) * c.stri;
+    const uint32_t a0 = ur[c.dk], a1 = ur[c.dk + 1];
+    for (uint32_t a = a0; a < a1; ++a) {
+      const int32_t w = col[a];
+      if (w > smax) break;  // N(G_ik,u) is ascending
+      if (w >= smin) cnt += stage_has(st, buf, sn, w, c.ck);
+    }
+  }
+  return cnt;
+}
+
+// One wavefront: in-slice [i0,i1) of v against N(G_jk,v) = ocol[c0..c1).
+__device__ uint64_t wave_col(const int32_t* __restrict__ col, const int32_t* __restrict__ icol, const TaskCtx& c,
+                             uint32_t i0, uint32_t i1, uint32_t c0, uint32_t c1, bool use_hash, uint32_t* abuf) {
+  const uint32_t l = (uint32_t)lane_id();
+  uint64_t cnt = 0;
+  const Stage st = pick_stage(c, use_hash, c1 - c0);
+  for (uint32_t s_lo = c0; s_lo < c1; s_lo += st.piece) {
+    const uint32_t sn = min(st.piece, c1 - s_lo);
+    stage_fill(st, abuf, col, s_lo, sn, c.ck, l, kWave);
     wave_sync();
-    const int32_t smin = col[s_lo], smax = col[s_lo + sn - 1];
-    for (uint32_t eb = i0; eb < i1; eb += kWave) {
-      const uint32_t e = eb + l;
-      uint32_t len = 0, a0 = 0;
-      if (e < i1) {
-        const int32_t u = icol[e];
-        const uint32_t* ur = c.boti + (uint64_t)(u - c.ci) * c.stri;
-        a0 = ur[c.dk];
-        len = ur[c.dk + 1] - a0;
-      }
-      const uint32_t inc = wave_incl_scan_u32(len);
-      const uint32_t tot = __shfl(inc, kWave - 1, kWave);
-      sa0[l] = a0;
-      sex[l] = inc - len;
-      wave_sync();
-      for (uint32_t qb = 0; qb < tot; qb += kWave) {
-        const uint32_t q = qb + l;
-        if (q < tot) {
-          int lo = 0, hi = kWave - 1;  // owner: the largest lane o with sex[o] <= q
-          while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (sex[mid] <= q) lo = mid; else hi = mid - 1;
-          }
-          const uint32_t src = sa0[lo] + (q - sex[lo]);
-          const int32_t w = col[src < mcol ? src : mcol - 1];
-          if (w >= smin && w <= smax) {
-            if (mode == 0) {
-              uint32_t x = 0, y = sn;
-              while (x < y) {
-                const uint32_t mid = (x + y) >> 1;
-                if (abuf[mid] < (uint32_t)w) x = mid + 1; else y = mid;
-              }
-              cnt += (x < sn && abuf[x] == (uint32_t)w) ? 1u : 0u;
-            } else if (mode == 1) {
-              const uint32_t x = (uint32_t)(w - c.ck);
-              cnt += (abuf[x >> 5] >> (x & 31)) & 1u;
-            } else {
-              const uint32_t key = (uint32_t)w + 1u;
-              uint32_t s = hash_slot((uint32_t)w);
-              for (int guard = 0; guard < kABuf; ++guard) {
-                const uint32_t kk = abuf[s];
-                if (kk == key) { ++cnt; break; }
-                if (kk == 0u) break;
-                s = (s + 1) & (kABuf - 1);
-              }
-            }
-          }
-        }
-      }
-      wave_sync();
-    }
-    // restore the all-zero buffer
-    if (mode == 0) {
-      for (uint32_t t = l; t < sn; t += kWave) abuf[t] = 0;
-    } else if (mode == 1) {
-      for (uint32_t t = l; t < sn; t += kWave) abuf[(uint32_t)(col[s_lo + t] - c.ck) >> 5] = 0;
-    } else {
-      for (uint32_t t = l; t < kABuf; t += kWave) abuf[t] = 0;
-    }
+    cnt += probe_in(col, icol, c, i0, i1, st, abuf, sn, col[s_lo], col[s_lo + sn - 1], l, kWave);
+    wave_sync();
+    stage_clear(st, abuf, col, s_lo, sn, c.ck, l, kWave);
     wave_sync();
   }
   return cnt;
 }
 
-// Active columns [lo, hi) of block (i,j), by the whole workgroup.
+// Active columns [lo, hi) of block (i,j), by the whole workgroup.  Columns
+// with in-slices longer than cp.split are left to their split items.
 __device__ uint64_t process_cols(const PlanCtx& cp, const TaskCtx& c, uint32_t lo, uint32_t hi, CountLds& s) {
   const int t = threadIdx.x, w = t / kWave;
   const int32_t* __restrict__ col = cp.g.ocol;
@@ -218,7 +226,7 @@ __device__ uint64_t process_cols(const PlanCtx& cp, const TaskCtx& c, uint32_t l
       if (c1 > c0) {
         const uint32_t* tr = c.tbotj + (uint64_t)(v - c.cj) * c.tstrj;
         const uint32_t i0 = tr[c.i], i1 = tr[c.i + 1];
-        if (i1 > i0) {
+        if (i1 > i0 && (cp.split == 0 || i1 - i0 <= cp.split)) {
           if ((i1 - i0) + (c1 - c0) >= (uint32_t)cp.wave_min) {
             const uint32_t qi = atomicAdd(&s.qn, 1u);
             s.q[qi][0] = i0;
@@ -236,10 +244,38 @@ __device__ uint64_t process_cols(const PlanCtx& cp, const TaskCtx& c, uint32_t l
     for (uint32_t h = w; h < nq; h += 4) {
       const uint32_t i0 = s.q[h][0], i1 = s.q[h][1], c0 = s.q[h][2], c1 = s.q[h][3];
       const bool use_hash = cp.hash_min >= 0 && (c1 - c0) >= (uint32_t)cp.hash_min;
-      cnt += heavy_col(col, icol, c, i0, i1, c0, c1, use_hash, cp.g.m, s.abuf[w], s.sc0[w], s.sex[w]);
+      cnt += wave_col(col, icol, c, i0, i1, c0, c1, use_hash, s.abuf[w]);
     }
     __syncthreads();
     if (t == 0) s.qn = 0;
+    __syncthreads();
+  }
+  return cnt;
+}
+
+// One chunk [lo, hi) of the in-slice of hub column v, by the whole workgroup
+// (N(G_jk,v) staged once in the first wave's buffer, read by all four waves).
+__device__ uint64_t hub_chunk(const PlanCtx& cp, const TaskCtx& c, int32_t v, uint32_t lo, uint32_t hi,
+                              CountLds& s) {
+  const int32_t* __restrict__ col = cp.g.ocol;
+  const int32_t* __restrict__ icol = cp.g.icol;
+  const uint32_t* vr = c.botj + (uint64_t)(v - c.cj) * c.strj;
+  const uint32_t c0 = vr[c.dkj], c1 = vr[c.dkj + 1];
+  const uint32_t* tr = c.tbotj + (uint64_t)(v - c.cj) * c.tstrj;
+  const uint32_t ib = tr[c.i], ie = tr[c.i + 1];
+  const uint32_t i0 = min(ib + lo, ie), i1 = min(ib + hi, ie);
+  uint64_t cnt = 0;
+  if (c1 <= c0 || i1 <= i0) return 0;  // uniform across the workgroup
+  const bool use_hash = cp.hash_min >= 0 && (c1 - c0) >= (uint32_t)cp.hash_min;
+  const Stage st = pick_stage(c, use_hash, c1 - c0);
+  uint32_t* buf = s.abuf[0];
+  for (uint32_t s_lo = c0; s_lo < c1; s_lo += st.piece) {
+    const uint32_t sn = min(st.piece, c1 - s_lo);
+    stage_fill(st, buf, col, s_lo, sn, c.ck, threadIdx.x, kThreads);
+    __syncthreads();
+    cnt += probe_in(col, icol, c, i0, i1, st, buf, sn, col[s_lo], col[s_lo + sn - 1], threadIdx.x, kThreads);
+    __syncthreads();
+    stage_clear(st, buf, col, s_lo, sn, c.ck, threadIdx.x, kThreads);
     __syncthreads();
   }
   return cnt;
@@ -260,18 +296,36 @@ __device__ __forceinline__ void flush(const PlanCtx& cp, int32_t out, uint64_t c
   }
 }
 
-// One launch per task (the unbatched form): workgroup b takes rows
-// [b*256, b*256+256) of the task's active columns.
-__global__ __launch_bounds__(kThreads) void k_count_task(CountParams cp, int32_t task, uint32_t nrows) {
+__device__ __forceinline__ uint64_t run_item(const PlanCtx& pc, const DevItem& item, CountLds& s, int32_t* out) {
+  const DevTask t = pc.tasks[item.task];
+  const TaskCtx c = make_ctx(pc.g, t);
+  *out = t.out;
+  if (item.v >= 0) return hub_chunk(pc, c, item.v, item.lo, item.hi, s);
+  return process_cols(pc, c, item.lo, item.hi, s);
+}
+
+// One launch per task (the unbatched form): workgroup b takes active columns
+// [b*256, b*256+256) of the task; hub columns go to k_count_items launches.
+__global__ __launch_bounds__(kThreads) void k_count_task(CountParams cp, int32_t task, uint32_t ncols) {
   __shared__ CountLds s;
   init_lds(s);
   const PlanCtx& pc = cp.one;
-  const DevTask t = pc.tasks[task];
-  const TaskCtx c = make_ctx(pc.g, t);
-  const uint32_t lo = blockIdx.x * kThreads;
-  const uint32_t hi = min(nrows, lo + kThreads);
-  const uint64_t cnt = process_cols(pc, c, lo, hi, s);
-  flush(pc, t.out, cnt, s);
+  const DevItem item{0, task, blockIdx.x * (uint32_t)kThreads, min(ncols, (blockIdx.x + 1) * (uint32_t)kThreads), -1,
+                     0};
+  int32_t out = 0;
+  const uint64_t cnt = run_item(pc, item, s, &out);
+  flush(pc, out, cnt, s);
+}
+
+// Items [first, first + gridDim.x) of the item list, one workgroup each.
+__global__ __launch_bounds__(kThreads) void k_count_items(CountParams cp, uint32_t first) {
+  __shared__ CountLds s;
+  init_lds(s);
+  const PlanCtx& pc = cp.one;
+  const DevItem item = cp.items[first + blockIdx.x];
+  int32_t out = 0;
+  const uint64_t cnt = run_item(pc, item, s, &out);
+  flush(pc, out, cnt, s);
 }
 
 // Persistent work-stealing form: every workgroup claims work items from a
@@ -288,10 +342,9 @@ __global__ __launch_bounds__(kThreads) void k_count_persistent(CountParams cp) {
     if (it >= cp.nitems) break;
     const DevItem item = cp.items[it];
     const PlanCtx pc = MULTI ? cp.many[item.plan] : cp.one;
-    const DevTask t = pc.tasks[item.task];
-    const TaskCtx c = make_ctx(pc.g, t);
-    const uint64_t cnt = process_cols(pc, c, item.lo, item.hi, s);
-    flush(pc, t.out, cnt, s);
+    int32_t out = 0;
+    const uint64_t cnt = run_item(pc, item, s, &out);
+    flush(pc, out, cnt, s);
   }
 }
 
@@ -330,10 +383,16 @@ hipError_t launch_reset(uint64_t* per_task, int64_t ntasks, uint64_t* total, uin
   return hipGetLastError();
 }
 
-hipError_t launch_count_task(const CountParams& cp, int32_t task, uint32_t nrows, hipStream_t s) {
-  if (nrows == 0) return hipSuccess;
-  const unsigned g = (nrows + kThreads - 1) / kThreads;
-  hipLaunchKernelGGL(k_count_task, dim3(g), dim3(kThreads), 0, s, cp, task, nrows);
+hipError_t launch_count_task(const CountParams& cp, int32_t task, uint32_t ncols, hipStream_t s) {
+  if (ncols == 0) return hipSuccess;
+  const unsigned g = (ncols + kThreads - 1) / kThreads;
+  hipLaunchKernelGGL(k_count_task, dim3(g), dim3(kThreads), 0, s, cp, task, ncols);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_items(const CountParams& cp, uint32_t first, uint32_t count, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_count_items, dim3(count), dim3(kThreads), 0, s, cp, first);
   return hipGetLastError();
 }
 

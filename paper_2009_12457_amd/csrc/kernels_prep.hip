@@ -572,7 +572,13 @@ __global__ __launch_bounds__(kThreads) void k_acol(BlockBuild bb) {
     const uint32_t f = (valid && hi > lo) ? 1u : 0u;
     uint32_t tot;
     const uint32_t off = block256_excl_scan<uint32_t>(f, lds, &tot);
-    if (f) bb.acol[bb.ccoff[bb.ccbase[b] + (uint64_t)a * nch + lc] + off] = (int32_t)v;
+    if (f) {
+      bb.acol[bb.ccoff[bb.ccbase[b] + (uint64_t)a * nch + lc] + off] = (int32_t)v;
+      if (bb.split && hi - lo > bb.split) {
+        const uint32_t r = atomicAdd(bb.nheavy, 1u);
+        if (r < bb.heavy_cap) bb.heavy[r] = HeavyCol{(uint32_t)col_block_id(a, b), (int32_t)v, hi - lo};
+      }
+    }
     lo = hi;
   }
 }

@@ -279,3 +279,19 @@ def test_count_multi_matches_alone():
     pers, tots = bb.bbtc_count_multi([plans[2], plans[0]])
     torch.cuda.synchronize()
     assert int(tots[0].item()) == alone[2][1] and int(tots[1].item()) == alone[0][1]
+
+
+def test_hub_columns_are_split_exactly():
+    """A hub with thousands of in-neighbours is cut into chunked work items."""
+    n = 3000
+    wheel = small_graph(n + 1, [(x, (x + 1) % n) for x in range(n)] + [(n, x) for x in range(n)], "W3000")
+    k = 1500
+    friend = small_graph(2 * k + 1, [e for t in range(k) for e in ((0, 2 * t + 1), (0, 2 * t + 2),
+                                                                    (2 * t + 1, 2 * t + 2))], "F1500")
+    for g, want in ((wheel, n), (friend, k)):
+        for p in (1, 2, 7):
+            for mode in MODES.values():
+                for hash_min in (-1, 1):
+                    plan, per, tot = run(g, p=p, mode=mode, hash_min=hash_min, wave_min=4)
+                    assert tot == want
+                    check(g, plan, per, tot, deep=(p == 2 and mode == 0))

@@ -1,0 +1,94 @@
+"""Continuous-batching server: every result is exact and identical alone and
+in the mix; admission by HBM footprint; oversized requests are rejected."""
+import numpy as np
+import pytest
+import torch
+
+import graphgen
+import oracle
+import paper_2009_12457_amd as bb
+from paper_2009_12457_amd import serve
+
+pytestmark = pytest.mark.gpu
+
+
+def pool():
+    gs = [graphgen.rmat(s, ef, 100 + s * 7 + ef) for s, ef in [(9, 8), (10, 16), (11, 12), (12, 8), (13, 16),
+                                                               (12, 32), (10, 4), (14, 8)]]
+    gs += [graphgen.er(n, d / (n - 1), 300 + n) for n, d in [(3000, 8), (10000, 24), (20000, 12), (5000, 40)]]
+    return gs
+
+
+def oracle_result(g, p):
+    og = oracle.OracleGraph.from_graph(g)
+    return og.tasks(p, og.cuts(p))
+
+
+def by_ijk(res):
+    t = res.tasks
+    return {(int(a), int(b), int(c)): int(v) for a, b, c, v in zip(t["i"], t["j"], t["k"], res.per_task)}
+
+
+def test_server_results_exact_alone_and_in_mix():
+    gs = pool()
+    srv = serve.Server(hbm_budget_bytes=8 << 30, compute_streams=2)
+    try:
+        # burst: everything in flight together, then a trickle
+        futs = [srv.submit(g.n, g.rowptr, g.colidx) for g in gs]
+        futs += [srv.submit(g.n, g.rowptr, g.colidx) for g in gs[::3]]
+        mixed = [f.result(timeout=120) for f in futs]
+    finally:
+        srv.close()
+    assert srv.launches >= 1
+    graphs = gs + gs[::3]
+    alone = {}
+    for g, r in zip(graphs, mixed):
+        p = int(r.tasks["k"].max()) + 1
+        key = (g.name, p)
+        if key not in alone:
+            # the same request alone: its own plan, its own launch
+            n, rp, ci = bb.csr_of(g, "cuda")
+            plan = bb.bbtc_partition(n, rp, ci, options=bb.bbtc_options_default(p=p), trusted=True)
+            per, tot = bb.bbtc_count(plan)
+            torch.cuda.synchronize()
+            pa = per.cpu().numpy().view(np.uint64)[:plan.ntasks].copy()
+            ta = plan.tasks()
+            alone[key] = (int(tot.item()), {(int(a), int(b), int(c)): int(v)
+                                            for a, b, c, v in zip(ta["i"], ta["j"], ta["k"], pa)})
+        tot_a, per_a = alone[key]
+        assert r.total == tot_a
+        assert by_ijk(r) == per_a
+        want_tot, want_per, _ = oracle_result(g, p)
+        assert r.total == want_tot
+        tl = oracle.task_list(p)
+        assert by_ijk(r) == {tuple(int(x) for x in ijk): int(v) for ijk, v in zip(tl, want_per)}
+
+
+def test_server_budget_admission_and_rejection():
+    gs = pool()[:6]
+    need = [serve.footprint_estimate(g.n, len(g.colidx), max(1, round(len(g.colidx) / g.n))) for g in gs]
+    budget = max(need) + 1  # only about one request fits at a time
+    srv = serve.Server(hbm_budget_bytes=budget, compute_streams=2)
+    try:
+        big = graphgen.rmat(16, 16, 5)
+        f_big = srv.submit(big.n, big.rowptr, big.colidx)
+        futs = [srv.submit(g.n, g.rowptr, g.colidx) for g in gs]
+        res = [f.result(timeout=120) for f in futs]
+        with pytest.raises(bb.BbtcError) as ei:
+            f_big.result(timeout=60)
+        assert ei.value.status == bb.BBTC_EBUDGET
+    finally:
+        srv.close()
+    for g, r in zip(gs, res):
+        p = int(r.tasks["k"].max()) + 1
+        assert r.total == oracle_result(g, p)[0]
+    assert srv.in_use == 0
+
+
+def test_plain_fcfs_matches_oracle():
+    gs = pool()[:4]
+    reqs = [(0.0, g.n, g.rowptr, g.colidx) for g in gs]
+    out = serve.serve_plain(reqs)
+    for g, r in zip(gs, out):
+        p = int(r.tasks["k"].max()) + 1
+        assert r.total == oracle_result(g, p)[0]
