@@ -314,11 +314,20 @@ void compose_tasks(bbtc_plan* pl) {
     }
     pl->h_hub_count[q] = (int64_t)pl->h_items.size() - pl->h_hub_first[q];
   }
+  // column ranges sized by the task's estimated work per active column, so
+  // that dense tasks spread over many workgroups (at most item_rows columns)
   const uint32_t step = (uint32_t)(pl->opt.item_rows > 0 ? pl->opt.item_rows : kDefaultItemRows);
+  double est_sum = 0;
+  for (int32_t q : pl->h_work) est_sum += pl->h_tasks[q].est;
+  const double target = est_sum / (double)std::max<int64_t>(1, (int64_t)pl->blocks_per_cu * pl->ncu * 16);
   for (int32_t q : pl->h_work) {
     const bbtc_task& t = pl->h_tasks[q];
     const uint32_t cols = (uint32_t)pl->h_nzc[col_block_id(t.i, t.j)];
-    for (uint32_t lo = 0; lo < cols; lo += step) pl->h_items.push_back(DevItem{0, q, lo, std::min(cols, lo + step), -1, 0});
+    if (cols == 0) continue;
+    const double per_col = t.est / (double)cols;
+    uint32_t n = step;
+    if (per_col > 0 && target > 0) n = (uint32_t)std::max(1.0, std::min((double)step, target / per_col));
+    for (uint32_t lo = 0; lo < cols; lo += n) pl->h_items.push_back(DevItem{0, q, lo, std::min(cols, lo + n), -1, 0});
   }
 }
 
@@ -380,9 +389,12 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
     rowptr = pl->in_rowptr.ptr;
     col = pl->in_col.ptr;
   } else {
-    HIP_TRY(pl->err.ensure(1), "alloc");
-    HIP_TRY(hipMemsetAsync(pl->err.ptr, 0, 4, s), "memset");
-    HIP_TRY(launch_validate(rowptr, rp64, col, n, nnz, symmetric_check, pl->err.ptr, s), "validate");
+    HIP_TRY(pl->err.ensure(8), "alloc");
+    HIP_TRY(pl->longrows.ensure((size_t)n), "alloc");
+    HIP_TRY(hipMemsetAsync(pl->err.ptr, 0, 8 * sizeof(uint32_t), s), "memset");
+    HIP_TRY(launch_validate(rowptr, rp64, col, n, nnz, symmetric_check, pl->err.ptr, pl->longrows.ptr, pl->err.ptr + 4,
+                            s),
+            "validate");
     uint32_t e = 0;
     HIP_TRY(hipMemcpyAsync(&e, pl->err.ptr, 4, hipMemcpyDeviceToHost, s), "D2H err");
     HIP_TRY(hipStreamSynchronize(s), "sync");
@@ -407,7 +419,8 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   HIP_TRY(pl->irow.ensure((size_t)n + 1), "alloc irow");
   HIP_TRY(pl->longrows.ensure((size_t)n), "alloc");
   HIP_TRY(pl->hugerows.ensure((size_t)n), "alloc");
-  HIP_TRY(pl->err.ensure(4), "alloc");
+  HIP_TRY(pl->err.ensure(8), "alloc");
+  HIP_TRY(hipMemsetAsync(pl->err.ptr, 0, 8 * sizeof(uint32_t), s), "memset");
   uint64_t* sorted = nullptr;
   HIP_TRY(launch_degkey(rowptr, rp64, n, pl->idbits, pl->keys_a.ptr, s), "degkey");
   HIP_TRY(radix_sort_u64(pl->keys_a.ptr, pl->keys_b.ptr, (uint64_t)n, kbits, pl->hist.ptr, pl->partial.ptr, &sorted, s),
@@ -415,7 +428,9 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   HIP_TRY(launch_perm(sorted, n, pl->idbits, pl->order.ptr, pl->perm.ptr, s), "perm");
 
   // ---- orientation: out-rows (higher ranks) and in-rows (lower ranks) ----
-  HIP_TRY(launch_degs(rowptr, rp64, col, n, pl->perm.ptr, pl->od.ptr, pl->idg.ptr, s), "degrees");
+  // err[4]: rows too long for one lane, listed in longrows by launch_degs
+  HIP_TRY(launch_degs(rowptr, rp64, col, n, pl->perm.ptr, pl->od.ptr, pl->idg.ptr, pl->longrows.ptr, pl->err.ptr + 4, s),
+          "degrees");
   HIP_TRY(scan_u32(pl->od.ptr, pl->orow.ptr, (uint64_t)n, pl->partial.ptr, s), "scan out-degrees");
   HIP_TRY(scan_u32(pl->idg.ptr, pl->irow.ptr, (uint64_t)n, pl->partial.ptr, s), "scan in-degrees");
   uint32_t mm[2] = {0, 0};
@@ -427,7 +442,8 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   pl->m = (int64_t)m;
   HIP_TRY(pl->ocol.ensure((size_t)m), "alloc ocol");
   HIP_TRY(pl->icol.ensure((size_t)m), "alloc icol");
-  HIP_TRY(launch_fill(rowptr, rp64, col, n, pl->perm.ptr, pl->orow.ptr, pl->irow.ptr, pl->ocol.ptr, pl->icol.ptr, s),
+  HIP_TRY(launch_fill(rowptr, rp64, col, n, pl->perm.ptr, pl->orow.ptr, pl->irow.ptr, pl->ocol.ptr, pl->icol.ptr,
+                      pl->longrows.ptr, pl->err.ptr + 4, s),
           "fill");
   // acol is not built yet: its m entries serve as the huge-row sort scratch
   HIP_TRY(pl->acol.ensure((size_t)m), "alloc active columns");

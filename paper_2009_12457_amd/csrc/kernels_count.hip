@@ -11,11 +11,11 @@
 //   * light columns (|in_i(v)| + |N(G_jk,v)| < wave_min): one lane per v, a
 //     two-pointer count of the sorted lists (Alg. 1) for each in-neighbour u;
 //   * medium columns: one 64-lane wavefront per v; N(G_jk,v) is staged in LDS
-//     and every lane walks the N(G_ik,u) of its own in-neighbours, testing
-//     each w against the stage;
+//     and the lanes share the probes of all in-neighbours u (segments of
+//     kSeg entries of the N(G_ik,u), handed out by a wavefront prefix sum);
 //   * hub columns (in-slice longer than `split`): the host cuts the in-slice
 //     into chunks that are separate work items; a whole workgroup stages
-//     N(G_jk,v) once and its 256 lanes share the chunk's in-neighbours.
+//     N(G_jk,v) once and its four wavefronts share the chunk's in-neighbours.
 // The stage is either the Intersect form (a sorted LDS copy, binary search)
 // or the HMap form (a dense LDS bitmap over the columns of V_k -- the paper's
 // dense hash map of the block's column range -- or, when V_k is too wide for
@@ -34,8 +34,13 @@ constexpr uint32_t kBitmapBits = kABuf * 32;  // bitmap capacity in columns
 constexpr int kHashBits = 11;                 // 2^11 = kABuf hash slots
 static_assert((1 << kHashBits) == kABuf, "hash table fills the wave buffer");
 
+constexpr uint32_t kSeg = 4;  // probes per flattened work unit
+
 struct CountLds {
   uint32_t abuf[4][kABuf];  // per wave: sorted copy / bitmap / hash; all-zero between uses
+  uint32_t sa0[4][kWave];   // per wave: start of N(G_ik,u) for the batch's lanes
+  uint32_t sa1[4][kWave];   // per wave: end of N(G_ik,u)
+  uint32_t sex[4][kWave];   // per wave: exclusive prefix of the batch's segment counts
   uint32_t q[kThreads][4];  // medium-column queue: i0, i1, c0, c1
   uint32_t qn;
   uint32_t item;
@@ -172,29 +177,58 @@ __device__ __forceinline__ uint32_t stage_has(const Stage& st, const uint32_t* b
   return 0u;
 }
 
-// Each thread tid of `nthr` walks the in-neighbours icol[e], e in [i0+tid, i1)
-// step nthr, and tests every w of N(G_ik,u) in [smin, smax] against the stage.
-__device__ __forceinline__ uint64_t probe_in(const int32_t* __restrict__ col, const int32_t* __restrict__ icol,
-                                             const TaskCtx& c, uint32_t i0, uint32_t i1, const Stage& st,
-                                             const uint32_t* buf, uint32_t sn, int32_t smin, int32_t smax,
-                                             uint32_t tid, uint32_t nthr) {
+// One wavefront tests every w of N(G_ik,u) in [smin, smax], for the
+// in-neighbours u = icol[i0..i1), against the stage.  The probe space is cut
+// into segments of kSeg consecutive entries of one N(G_ik,u); a wavefront
+// prefix sum over the segment counts of 64 in-neighbours at a time lets all
+// lanes share the segments, however unequal the lists are.
+__device__ uint64_t probe_flat(const int32_t* __restrict__ col, const int32_t* __restrict__ icol, const TaskCtx& c,
+                               uint32_t i0, uint32_t i1, const Stage& st, const uint32_t* buf, uint32_t sn,
+                               int32_t smin, int32_t smax, uint32_t* sa0, uint32_t* sa1, uint32_t* sex) {
+  const uint32_t l = (uint32_t)lane_id();
   uint64_t cnt = 0;
-  for (uint32_t e = i0 + tid; e < i1; e += nthr) {
-    const int32_t u = icol[e];
-    const uint32_t* ur = c.boti + (uint64_t)(u - c.ci) * c.stri;
-    const uint32_t a0 = ur[c.dk], a1 = ur[c.dk + 1];
-    for (uint32_t a = a0; a < a1; ++a) {
-      const int32_t w = col[a];
-      if (w > smax) break;  // N(G_ik,u) is ascending
-      if (w >= smin) cnt += stage_has(st, buf, sn, w, c.ck);
+  for (uint32_t eb = i0; eb < i1; eb += kWave) {
+    const uint32_t e = eb + l;
+    uint32_t a0 = 0, a1 = 0;
+    if (e < i1) {
+      const int32_t u = icol[e];
+      const uint32_t* ur = c.boti + (uint64_t)(u - c.ci) * c.stri;
+      a0 = ur[c.dk];
+      a1 = ur[c.dk + 1];
     }
+    const uint32_t nseg = (a1 - a0 + kSeg - 1) / kSeg;
+    const uint32_t inc = wave_incl_scan_u32(nseg);
+    const uint32_t tot = __shfl(inc, kWave - 1, kWave);
+    sa0[l] = a0;
+    sa1[l] = a1;
+    sex[l] = inc - nseg;
+    wave_sync();
+    for (uint32_t qb = 0; qb < tot; qb += kWave) {
+      const uint32_t q = qb + l;
+      if (q < tot) {
+        int lo = 0, hi = kWave - 1;  // owner: the largest lane o with sex[o] <= q
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (sex[mid] <= q) lo = mid; else hi = mid - 1;
+        }
+        const uint32_t s0 = sa0[lo] + (q - sex[lo]) * kSeg;
+        const uint32_t s1 = min(s0 + kSeg, sa1[lo]);
+        for (uint32_t a = s0; a < s1; ++a) {
+          const int32_t w = col[a];
+          if (w > smax) break;  // N(G_ik,u) is ascending
+          if (w >= smin) cnt += stage_has(st, buf, sn, w, c.ck);
+        }
+      }
+    }
+    wave_sync();
   }
   return cnt;
 }
 
 // One wavefront: in-slice [i0,i1) of v against N(G_jk,v) = ocol[c0..c1).
 __device__ uint64_t wave_col(const int32_t* __restrict__ col, const int32_t* __restrict__ icol, const TaskCtx& c,
-                             uint32_t i0, uint32_t i1, uint32_t c0, uint32_t c1, bool use_hash, uint32_t* abuf) {
+                             uint32_t i0, uint32_t i1, uint32_t c0, uint32_t c1, bool use_hash, uint32_t* abuf,
+                             uint32_t* sa0, uint32_t* sa1, uint32_t* sex) {
   const uint32_t l = (uint32_t)lane_id();
   uint64_t cnt = 0;
   const Stage st = pick_stage(c, use_hash, c1 - c0);
@@ -202,8 +236,7 @@ __device__ uint64_t wave_col(const int32_t* __restrict__ col, const int32_t* __r
     const uint32_t sn = min(st.piece, c1 - s_lo);
     stage_fill(st, abuf, col, s_lo, sn, c.ck, l, kWave);
     wave_sync();
-    cnt += probe_in(col, icol, c, i0, i1, st, abuf, sn, col[s_lo], col[s_lo + sn - 1], l, kWave);
-    wave_sync();
+    cnt += probe_flat(col, icol, c, i0, i1, st, abuf, sn, col[s_lo], col[s_lo + sn - 1], sa0, sa1, sex);
     stage_clear(st, abuf, col, s_lo, sn, c.ck, l, kWave);
     wave_sync();
   }
@@ -244,7 +277,7 @@ __device__ uint64_t process_cols(const PlanCtx& cp, const TaskCtx& c, uint32_t l
     for (uint32_t h = w; h < nq; h += 4) {
       const uint32_t i0 = s.q[h][0], i1 = s.q[h][1], c0 = s.q[h][2], c1 = s.q[h][3];
       const bool use_hash = cp.hash_min >= 0 && (c1 - c0) >= (uint32_t)cp.hash_min;
-      cnt += wave_col(col, icol, c, i0, i1, c0, c1, use_hash, s.abuf[w]);
+      cnt += wave_col(col, icol, c, i0, i1, c0, c1, use_hash, s.abuf[w], s.sa0[w], s.sa1[w], s.sex[w]);
     }
     __syncthreads();
     if (t == 0) s.qn = 0;
@@ -253,12 +286,14 @@ __device__ uint64_t process_cols(const PlanCtx& cp, const TaskCtx& c, uint32_t l
   return cnt;
 }
 
-// One chunk [lo, hi) of the in-slice of hub column v, by the whole workgroup
-// (N(G_jk,v) staged once in the first wave's buffer, read by all four waves).
+// One chunk [lo, hi) of the in-slice of hub column v, by the whole workgroup:
+// N(G_jk,v) is staged once in the first wave's buffer and each of the four
+// wavefronts probes a quarter of the chunk's in-neighbours against it.
 __device__ uint64_t hub_chunk(const PlanCtx& cp, const TaskCtx& c, int32_t v, uint32_t lo, uint32_t hi,
                               CountLds& s) {
   const int32_t* __restrict__ col = cp.g.ocol;
   const int32_t* __restrict__ icol = cp.g.icol;
+  const int w = threadIdx.x / kWave;
   const uint32_t* vr = c.botj + (uint64_t)(v - c.cj) * c.strj;
   const uint32_t c0 = vr[c.dkj], c1 = vr[c.dkj + 1];
   const uint32_t* tr = c.tbotj + (uint64_t)(v - c.cj) * c.tstrj;
@@ -266,6 +301,8 @@ __device__ uint64_t hub_chunk(const PlanCtx& cp, const TaskCtx& c, int32_t v, ui
   const uint32_t i0 = min(ib + lo, ie), i1 = min(ib + hi, ie);
   uint64_t cnt = 0;
   if (c1 <= c0 || i1 <= i0) return 0;  // uniform across the workgroup
+  const uint32_t per = (i1 - i0 + 3) / 4;
+  const uint32_t w0 = min(i0 + per * w, i1), w1 = min(w0 + per, i1);
   const bool use_hash = cp.hash_min >= 0 && (c1 - c0) >= (uint32_t)cp.hash_min;
   const Stage st = pick_stage(c, use_hash, c1 - c0);
   uint32_t* buf = s.abuf[0];
@@ -273,7 +310,7 @@ __device__ uint64_t hub_chunk(const PlanCtx& cp, const TaskCtx& c, int32_t v, ui
     const uint32_t sn = min(st.piece, c1 - s_lo);
     stage_fill(st, buf, col, s_lo, sn, c.ck, threadIdx.x, kThreads);
     __syncthreads();
-    cnt += probe_in(col, icol, c, i0, i1, st, buf, sn, col[s_lo], col[s_lo + sn - 1], threadIdx.x, kThreads);
+    cnt += probe_flat(col, icol, c, w0, w1, st, buf, sn, col[s_lo], col[s_lo + sn - 1], s.sa0[w], s.sa1[w], s.sex[w]);
     __syncthreads();
     stage_clear(st, buf, col, s_lo, sn, c.ck, threadIdx.x, kThreads);
     __syncthreads();

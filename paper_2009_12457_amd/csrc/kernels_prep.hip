@@ -26,46 +26,71 @@ constexpr unsigned kRowGrid = 8192;  // workgroups (4 waves each)
 // increasing, no self-loop, and (optionally) every (x,y) mirrored by (y,x).
 // Every index is clamped before use, so malformed input cannot read out of
 // bounds.  Error bits: 1 range, 2 order, 4 self-loop, 8 rowptr, 16 asymmetric.
+//
+// Row kernels here come in two forms: one lane per row for rows of at most
+// kLaneRow entries (longer rows are appended to a list), and one wavefront
+// per listed row.
+constexpr int64_t kLaneRow = 64;
+
 template <typename RP>
-__global__ __launch_bounds__(kThreads) void k_validate(const RP* __restrict__ rowptr,
-                                                       const int32_t* __restrict__ colidx, int64_t n,
-                                                       int64_t nnz, int symmetric, uint32_t* err) {
-  const int l = lane_id();
-  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+__device__ __forceinline__ uint32_t check_entry(const RP* __restrict__ rowptr, const int32_t* __restrict__ colidx,
+                                                int64_t n, int64_t nnz, int symmetric, int64_t x, int64_t b, int64_t q) {
+  uint32_t e = 0;
+  const int32_t y = colidx[q];
+  if (y < 0 || y >= n) return 1;
+  if (y == x) e |= 4;
+  if (q > b && colidx[q - 1] >= y) e |= 2;
+  if (symmetric) {
+    int64_t lo = (int64_t)rowptr[y], hi = (int64_t)rowptr[y + 1];
+    if (lo < 0 || hi < lo || hi > nnz) return e | 8;
+    const int64_t end = hi;
+    while (lo < hi) {  // lower_bound of x in row y
+      int64_t mid = (lo + hi) >> 1;
+      if (colidx[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    if (lo >= end || colidx[lo] != x) e |= 16;
+  }
+  return e;
+}
+
+template <typename RP>
+__global__ __launch_bounds__(kThreads) void k_validate_lane(const RP* __restrict__ rowptr,
+                                                            const int32_t* __restrict__ colidx, int64_t n, int64_t nnz,
+                                                            int symmetric, uint32_t* err, uint32_t* list,
+                                                            uint32_t* nlist) {
   uint32_t e = 0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     if ((int64_t)rowptr[0] != 0 || (int64_t)rowptr[n] != nnz) e |= 8;
   }
-  for (int64_t x = wave; x < n; x += nwaves) {
-    int64_t b = (int64_t)rowptr[x], en = (int64_t)rowptr[x + 1];
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = (int64_t)rowptr[x], en = (int64_t)rowptr[x + 1];
     if (b < 0 || en < b || en > nnz) {
       e |= 8;
       continue;
     }
-    for (int64_t base = b; base < en; base += kWave) {
-      int64_t q = base + l;
-      if (q >= en) continue;
-      int32_t y = colidx[q];
-      if (y < 0 || y >= n) {
-        e |= 1;
-        continue;
-      }
-      if (y == x) e |= 4;
-      if (q > b && colidx[q - 1] >= y) e |= 2;
-      if (symmetric) {
-        int64_t lo = (int64_t)rowptr[y], hi = (int64_t)rowptr[y + 1];
-        if (lo < 0 || hi < lo || hi > nnz) {
-          e |= 8;
-          continue;
-        }
-        while (lo < hi) {  // lower_bound of x in row y
-          int64_t mid = (lo + hi) >> 1;
-          if (colidx[mid] < x) lo = mid + 1; else hi = mid;
-        }
-        if (lo >= (int64_t)rowptr[y + 1] || colidx[lo] != x) e |= 16;
-      }
+    if (en - b > kLaneRow) {
+      list[atomicAdd(nlist, 1u)] = (uint32_t)x;
+      continue;
     }
+    for (int64_t q = b; q < en; ++q) e |= check_entry(rowptr, colidx, n, nnz, symmetric, x, b, q);
+  }
+  if (e) atomicOr(err, e);
+}
+
+template <typename RP>
+__global__ __launch_bounds__(kThreads) void k_validate_wave(const RP* __restrict__ rowptr,
+                                                            const int32_t* __restrict__ colidx, int64_t n, int64_t nnz,
+                                                            int symmetric, uint32_t* err, const uint32_t* list,
+                                                            const uint32_t* nlist) {
+  const int l = lane_id();
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  const int64_t cnt = *nlist;
+  uint32_t e = 0;
+  for (int64_t r = wave; r < cnt; r += nwaves) {
+    const int64_t x = list[r];
+    const int64_t b = (int64_t)rowptr[x], en = (int64_t)rowptr[x + 1];
+    for (int64_t q = b + l; q < en; q += kWave) e |= check_entry(rowptr, colidx, n, nnz, symmetric, x, b, q);
   }
   if (e) atomicOr(err, e);
 }
@@ -205,23 +230,46 @@ __global__ __launch_bounds__(kThreads) void k_perm(const uint64_t* __restrict__ 
 }
 
 // ------------------------------------------------------------ orientation
-// One wavefront per original vertex x of rank r: neighbours y with rank(y) > r
-// form the out-row N(G,r), the others the in-row of r.
+// For original vertex x of rank r: neighbours y with rank(y) > r form the
+// out-row N(G,r), the others the in-row of r.
 template <typename RP>
-__global__ __launch_bounds__(kThreads) void k_degs(const RP* __restrict__ rowptr, const int32_t* __restrict__ colidx,
-                                                   int64_t n, const int32_t* __restrict__ perm,
-                                                   uint32_t* __restrict__ od, uint32_t* __restrict__ idg) {
-  const int l = lane_id();
-  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
-  for (int64_t x = wave; x < n; x += nwaves) {
+__global__ __launch_bounds__(kThreads) void k_degs_lane(const RP* __restrict__ rowptr,
+                                                        const int32_t* __restrict__ colidx, int64_t n,
+                                                        const int32_t* __restrict__ perm, uint32_t* __restrict__ od,
+                                                        uint32_t* __restrict__ idg, uint32_t* list, uint32_t* nlist) {
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
     const int32_t r = perm[x];
     if (r < 0 || r >= n) continue;
     const int64_t b = (int64_t)rowptr[x], e = (int64_t)rowptr[x + 1];
+    if (e - b > kLaneRow) {
+      list[atomicAdd(nlist, 1u)] = (uint32_t)x;
+      continue;
+    }
+    uint32_t c = 0;
+    for (int64_t q = b; q < e; ++q) c += perm[colidx[q]] > r ? 1u : 0u;
+    od[r] = c;
+    idg[r] = (uint32_t)(e - b) - c;
+  }
+}
+
+template <typename RP>
+__global__ __launch_bounds__(kThreads) void k_degs_wave(const RP* __restrict__ rowptr,
+                                                        const int32_t* __restrict__ colidx,
+                                                        const int32_t* __restrict__ perm, uint32_t* __restrict__ od,
+                                                        uint32_t* __restrict__ idg, const uint32_t* list,
+                                                        const uint32_t* nlist) {
+  const int l = lane_id();
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  const int64_t cnt = *nlist;
+  for (int64_t i = wave; i < cnt; i += nwaves) {
+    const int64_t x = list[i];
+    const int32_t r = perm[x];
+    const int64_t b = (int64_t)rowptr[x], e = (int64_t)rowptr[x + 1];
     uint32_t c = 0;
     for (int64_t base = b; base < e; base += kWave) {
-      int64_t q = base + l;
-      bool up = q < e && perm[colidx[q]] > r;
+      const int64_t q = base + l;
+      const bool up = q < e && perm[colidx[q]] > r;
       c += (uint32_t)__popcll(ballot(up));
     }
     if (l == 0) {
@@ -232,19 +280,50 @@ __global__ __launch_bounds__(kThreads) void k_degs(const RP* __restrict__ rowptr
 }
 
 // Scatters rank ids into the out- and in-rows (order within a row follows the
-// input row; the rows are sorted afterwards).  Writes are bounded by the row
+// input row; rows are sorted afterwards).  Writes are bounded by the row
 // extents computed from the same predicate.
 template <typename RP>
-__global__ __launch_bounds__(kThreads) void k_fill(const RP* __restrict__ rowptr, const int32_t* __restrict__ colidx,
-                                                   int64_t n, const int32_t* __restrict__ perm,
-                                                   const uint32_t* __restrict__ orow, const uint32_t* __restrict__ irow,
-                                                   int32_t* __restrict__ ocol, int32_t* __restrict__ icol) {
+__global__ __launch_bounds__(kThreads) void k_fill_lane(const RP* __restrict__ rowptr,
+                                                        const int32_t* __restrict__ colidx, int64_t n,
+                                                        const int32_t* __restrict__ perm,
+                                                        const uint32_t* __restrict__ orow,
+                                                        const uint32_t* __restrict__ irow, int32_t* __restrict__ ocol,
+                                                        int32_t* __restrict__ icol) {
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t r = perm[x];
+    if (r < 0 || r >= n) continue;
+    const int64_t b = (int64_t)rowptr[x], e = (int64_t)rowptr[x + 1];
+    if (e - b > kLaneRow) continue;  // handled by k_fill_wave
+    uint32_t po = orow[r], pi = irow[r];
+    const uint32_t po_end = orow[r + 1], pi_end = irow[r + 1];
+    for (int64_t q = b; q < e; ++q) {
+      const int32_t ry = perm[colidx[q]];
+      if (ry > r) {
+        if (po < po_end) ocol[po] = ry;
+        ++po;
+      } else {
+        if (pi < pi_end) icol[pi] = ry;
+        ++pi;
+      }
+    }
+  }
+}
+
+template <typename RP>
+__global__ __launch_bounds__(kThreads) void k_fill_wave(const RP* __restrict__ rowptr,
+                                                        const int32_t* __restrict__ colidx,
+                                                        const int32_t* __restrict__ perm,
+                                                        const uint32_t* __restrict__ orow,
+                                                        const uint32_t* __restrict__ irow, int32_t* __restrict__ ocol,
+                                                        int32_t* __restrict__ icol, const uint32_t* list,
+                                                        const uint32_t* nlist) {
   const int l = lane_id();
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
-  for (int64_t x = wave; x < n; x += nwaves) {
+  const int64_t cnt = *nlist;
+  for (int64_t i = wave; i < cnt; i += nwaves) {
+    const int64_t x = list[i];
     const int32_t r = perm[x];
-    if (r < 0 || r >= n) continue;
     const int64_t b = (int64_t)rowptr[x], e = (int64_t)rowptr[x + 1];
     uint32_t po = orow[r], pi = irow[r];
     const uint32_t po_end = orow[r + 1], pi_end = irow[r + 1];
@@ -587,13 +666,19 @@ __global__ __launch_bounds__(kThreads) void k_acol(BlockBuild bb) {
 
 // ------------------------------------------------------------ launchers
 hipError_t launch_validate(const void* rowptr, int rp64, const int32_t* colidx, int64_t n, int64_t nnz,
-                           int symmetric, uint32_t* err, hipStream_t s) {
-  if (rp64)
-    hipLaunchKernelGGL(k_validate<int64_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int64_t*)rowptr, colidx, n,
-                       nnz, symmetric, err);
-  else
-    hipLaunchKernelGGL(k_validate<int32_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int32_t*)rowptr, colidx, n,
-                       nnz, symmetric, err);
+                           int symmetric, uint32_t* err, uint32_t* list, uint32_t* nlist, hipStream_t s) {
+  const unsigned g = grid_for((uint64_t)n, kThreads, 65536);
+  if (rp64) {
+    hipLaunchKernelGGL(k_validate_lane<int64_t>, dim3(g), dim3(kThreads), 0, s, (const int64_t*)rowptr, colidx, n, nnz,
+                       symmetric, err, list, nlist);
+    hipLaunchKernelGGL(k_validate_wave<int64_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int64_t*)rowptr, colidx,
+                       n, nnz, symmetric, err, (const uint32_t*)list, (const uint32_t*)nlist);
+  } else {
+    hipLaunchKernelGGL(k_validate_lane<int32_t>, dim3(g), dim3(kThreads), 0, s, (const int32_t*)rowptr, colidx, n, nnz,
+                       symmetric, err, list, nlist);
+    hipLaunchKernelGGL(k_validate_wave<int32_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int32_t*)rowptr, colidx,
+                       n, nnz, symmetric, err, (const uint32_t*)list, (const uint32_t*)nlist);
+  }
   return hipGetLastError();
 }
 
@@ -655,26 +740,39 @@ hipError_t launch_perm(const uint64_t* keys, int64_t n, int idbits, int32_t* ord
 }
 
 hipError_t launch_degs(const void* rowptr, int rp64, const int32_t* colidx, int64_t n, const int32_t* perm,
-                       uint32_t* od, uint32_t* idg, hipStream_t s) {
+                       uint32_t* od, uint32_t* idg, uint32_t* list, uint32_t* nlist, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  if (rp64)
-    hipLaunchKernelGGL(k_degs<int64_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int64_t*)rowptr, colidx, n, perm,
-                       od, idg);
-  else
-    hipLaunchKernelGGL(k_degs<int32_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int32_t*)rowptr, colidx, n, perm,
-                       od, idg);
+  const unsigned g = grid_for((uint64_t)n, kThreads, 65536);
+  if (rp64) {
+    hipLaunchKernelGGL(k_degs_lane<int64_t>, dim3(g), dim3(kThreads), 0, s, (const int64_t*)rowptr, colidx, n, perm, od,
+                       idg, list, nlist);
+    hipLaunchKernelGGL(k_degs_wave<int64_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int64_t*)rowptr, colidx, perm,
+                       od, idg, (const uint32_t*)list, (const uint32_t*)nlist);
+  } else {
+    hipLaunchKernelGGL(k_degs_lane<int32_t>, dim3(g), dim3(kThreads), 0, s, (const int32_t*)rowptr, colidx, n, perm, od,
+                       idg, list, nlist);
+    hipLaunchKernelGGL(k_degs_wave<int32_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int32_t*)rowptr, colidx, perm,
+                       od, idg, (const uint32_t*)list, (const uint32_t*)nlist);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_fill(const void* rowptr, int rp64, const int32_t* colidx, int64_t n, const int32_t* perm,
-                       const uint32_t* orow, const uint32_t* irow, int32_t* ocol, int32_t* icol, hipStream_t s) {
+                       const uint32_t* orow, const uint32_t* irow, int32_t* ocol, int32_t* icol, const uint32_t* list,
+                       const uint32_t* nlist, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  if (rp64)
-    hipLaunchKernelGGL(k_fill<int64_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int64_t*)rowptr, colidx, n, perm,
+  const unsigned g = grid_for((uint64_t)n, kThreads, 65536);
+  if (rp64) {
+    hipLaunchKernelGGL(k_fill_lane<int64_t>, dim3(g), dim3(kThreads), 0, s, (const int64_t*)rowptr, colidx, n, perm,
                        orow, irow, ocol, icol);
-  else
-    hipLaunchKernelGGL(k_fill<int32_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int32_t*)rowptr, colidx, n, perm,
+    hipLaunchKernelGGL(k_fill_wave<int64_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int64_t*)rowptr, colidx, perm,
+                       orow, irow, ocol, icol, list, nlist);
+  } else {
+    hipLaunchKernelGGL(k_fill_lane<int32_t>, dim3(g), dim3(kThreads), 0, s, (const int32_t*)rowptr, colidx, n, perm,
                        orow, irow, ocol, icol);
+    hipLaunchKernelGGL(k_fill_wave<int32_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int32_t*)rowptr, colidx, perm,
+                       orow, irow, ocol, icol, list, nlist);
+  }
   return hipGetLastError();
 }
 
