@@ -59,7 +59,21 @@ def main():
     ap.add_argument("--workload", default="rmat20", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-only", action="store_true", help="only the timed steps (for rocprofv3 runs)")
+    ap.add_argument("--autotune", choices=["auto", "on", "off"], default="auto",
+                    help="pick p and the row-mapping knobs with bbtc_autotune (auto: on for the 2^24 workloads)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run 10 plain device-to-device copies of BYTES bytes (counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        a = torch.empty(args.calibrate_copy // 4, dtype=torch.int32, device="cuda").fill_(1)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(10):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": args.calibrate_copy, "copies": 10}))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): this build has no multi-GPU path; "
               f"the per-GPU share is the single-GPU workload.", file=sys.stderr)
@@ -77,6 +91,13 @@ def main():
     stream = torch.cuda.current_stream()
     sync = torch.cuda.synchronize
     opt = bb.bbtc_options_default(p=p, mode=bb.BBTC_MODE_PERSISTENT)
+    tuned = None
+    if args.autotune == "on" or (args.autotune == "auto" and args.workload in ("rmat24", "er24")):
+        t = time.perf_counter()
+        opt, tuned_ms = bb.bbtc_autotune(n, rp, ci, base=opt, reps=3, trusted=True)
+        tuned = {"p": opt.p, "wave_min": opt.wave_min, "hash_min": opt.hash_min, "count_ms": tuned_ms,
+                 "tuning_s": time.perf_counter() - t}
+        p = opt.p
     plan = bb.bbtc_partition(n, rp, ci, options=opt, trusted=True)
     per, tot = bb.bbtc_count(plan)
     sync()
@@ -120,7 +141,7 @@ def main():
     # ---- unbatched baselines: one launch per task (Intersect, HMap)
     plain = {}
     for name, mode in (("plain_intersect", bb.BBTC_MODE_PLAIN_INTERSECT), ("plain_hmap", bb.BBTC_MODE_PLAIN_HMAP)):
-        o2 = bb.bbtc_options_default(p=p, mode=mode)
+        o2 = bb.bbtc_options_default(p=p, mode=mode, wave_min=opt.wave_min)
         pl2 = bb.bbtc_partition(n, rp, ci, options=o2, trusted=True)
         pt2, tt2 = bb.bbtc_count(pl2)
         sync()
@@ -176,6 +197,7 @@ def main():
                    "work_items": int(st["nitems"]), "triangles": triangles, "lambda": round(st["lambda"], 3),
                    "c": round(st["c"], 3), "parallelism": "single GPU"},
         "step_breakdown_ms": {"partition": float(np.median(part_ms)), "count_batched": count_ms_med},
+        "autotuned": tuned,
         "batched_count_edges_per_s": m / (count_ms_med * 1e-3),
         "plain": plain,
         "roofline": roofline,

@@ -93,7 +93,14 @@ typedef struct bbtc_csr {
  *   item_rows     active columns of G_ij per persistent work item.
  *   graph         0: the persistent count (reset + launch) is captured once
  *                 in a hipGraph and replayed; -1: launched directly.
- *   device_budget_bytes  upper bound on the plan's device memory (0 = none).
+ *   device_budget_bytes  upper bound on the device memory of the count phase
+ *                 (0 = none).  A plan over the budget keeps its rows in pinned
+ *                 host memory and streams, per block pair (i,j), the three row
+ *                 stripes its tasks read (out-rows of V_i and V_j, in-rows of
+ *                 V_j) into a device cache of stripe slots (Sec. 4.1: a task
+ *                 needs only its three blocks).  bbtc_partition itself runs
+ *                 with the whole graph on the device.  Fewer than three slots
+ *                 within the budget: BBTC_EBUDGET.
  */
 typedef struct bbtc_options {
   int32_t p;
@@ -138,6 +145,10 @@ typedef struct bbtc_stats {
   int64_t bytes_total;  /* bytes_colidx + bytes_rowidx + 8 |T| */
   int64_t footprint;    /* device bytes held by the plan */
   double partition_ms;  /* wall time of the last bbtc_partition */
+  int64_t streamed;     /* 1: over the device budget, stripes stream from pinned host memory */
+  int64_t stripe_slots; /* stripes the device cache holds (streamed plans) */
+  int64_t stripe_bytes; /* bytes per stripe slot */
+  int64_t stripe_uploads; /* stripe uploads by the last bbtc_count (streamed plans) */
 } bbtc_stats;
 
 typedef struct bbtc_plan bbtc_plan;

@@ -63,7 +63,9 @@ class bbtc_stats(ctypes.Structure):
                 ("m_avg", ctypes.c_double), ("lambda_", ctypes.c_double), ("d_max", ctypes.c_int64),
                 ("d_max_block", ctypes.c_int64), ("c", ctypes.c_double), ("wedges", ctypes.c_int64),
                 ("bytes_colidx", ctypes.c_int64), ("bytes_rowidx", ctypes.c_int64),
-                ("bytes_total", ctypes.c_int64), ("footprint", ctypes.c_int64), ("partition_ms", ctypes.c_double)]
+                ("bytes_total", ctypes.c_int64), ("footprint", ctypes.c_int64), ("partition_ms", ctypes.c_double),
+                ("streamed", ctypes.c_int64), ("stripe_slots", ctypes.c_int64), ("stripe_bytes", ctypes.c_int64),
+                ("stripe_uploads", ctypes.c_int64)]
 
 
 TASK_DTYPE = np.dtype([("i", np.int32), ("j", np.int32), ("k", np.int32), ("kind", np.int32), ("est", np.float64)])

@@ -103,12 +103,49 @@ struct bbtc_plan {
   std::vector<int32_t> h_work;     // plan-order indices of WORK tasks
   std::vector<DevItem> h_items;
   std::vector<HeavyCol> h_heavy;   // hub columns, sorted by (block, column)
-  std::vector<int64_t> h_hub_first, h_hub_count;  // per plan-order task: its hub items
+  std::vector<int64_t> h_hub_first, h_hub_count;  // per plan-order task: its range of work items
   uint32_t split = 0;              // in-slice length above which a column is a hub
   int64_t ccount = 0;              // number of chunk counters
   int ncu = 0, blocks_per_cu = 0;
   hipStream_t side[4] = {nullptr, nullptr, nullptr, nullptr};
   hipEvent_t ev_fork = nullptr, ev_join[4] = {nullptr, nullptr, nullptr, nullptr};
+  // ---- budgeted streaming of the count phase (see stream_setup)
+  bool streamed = false;
+  int32_t* h_ocol = nullptr;     // pinned host copies of the count-phase arrays
+  int32_t* h_icol = nullptr;
+  uint32_t* h_bot = nullptr;
+  uint32_t* h_tbot = nullptr;
+  uint32_t* h_orow = nullptr;
+  std::vector<uint64_t> h_botp, h_tbotp, ocut, icut;  // part offsets; orow/irow at the cuts
+  DevBuf<char> cache;            // nslots stripes of slot_bytes each
+  size_t slot_bytes = 0;
+  struct Slot {
+    int key = -1;                // 2a: out-stripe of part a, 2a+1: in-stripe of part a
+    uint64_t last = 0;
+    bool used = false;           // a kernel has read it (released is recorded)
+    hipEvent_t ready = nullptr, released = nullptr;
+  };
+  std::vector<Slot> slots;
+  uint64_t clock = 0;
+  std::vector<std::pair<int32_t, int32_t>> groups;  // block pairs (i,j), i-major
+  std::vector<int64_t> group_first, group_count;    // their ranges of the item list
+  int64_t copies = 0;            // stripe uploads by the last streamed count
+  void drop_stream() {
+    for (auto& s : slots) {
+      if (s.ready) (void)hipEventDestroy(s.ready);
+      if (s.released) (void)hipEventDestroy(s.released);
+    }
+    slots.clear();
+    cache.release();
+    if (h_ocol) (void)hipHostFree(h_ocol);
+    if (h_icol) (void)hipHostFree(h_icol);
+    if (h_bot) (void)hipHostFree(h_bot);
+    if (h_tbot) (void)hipHostFree(h_tbot);
+    if (h_orow) (void)hipHostFree(h_orow);
+    h_ocol = h_icol = nullptr;
+    h_bot = h_tbot = h_orow = nullptr;
+    streamed = false;
+  }
   // captured persistent count, valid for the output pointers it was made with
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -126,6 +163,7 @@ struct bbtc_plan {
 
   ~bbtc_plan() {
     drop_graph();
+    drop_stream();
     for (int q = 0; q < 4; ++q) {
       if (side[q]) (void)hipStreamDestroy(side[q]);
       if (ev_join[q]) (void)hipEventDestroy(ev_join[q]);
@@ -147,7 +185,7 @@ struct bbtc_plan {
            hugerows.bytes() + bot.bytes() +
            tbot.bytes() + ccnt.bytes() + ccoff.bytes() + dmax.bytes() + cursor.bytes() + err.bytes() +
            ccbase.bytes() + botp.bytes() + tbotp.bytes() + acp.bytes() + bnnz.bytes() + bnzr.bytes() +
-           bnzc.bytes() + tasks.bytes() + items.bytes() + heavy.bytes();
+           bnzc.bytes() + tasks.bytes() + items.bytes() + heavy.bytes() + cache.bytes();
   }
 };
 
@@ -240,6 +278,9 @@ PlanCtx plan_ctx(const bbtc_plan* pl, uint64_t* per_task, uint64_t* total) {
   PlanCtx c;
   c.g.p = pl->p;
   c.g.m = (uint32_t)pl->m;
+  c.g.gi = c.g.gj = -1;
+  c.g.colI = c.g.colJ = c.g.icolJ = nullptr;
+  c.g.botI = c.g.botJ = c.g.tbotJ = nullptr;
   c.g.cuts = pl->cuts.ptr;
   c.g.botp = pl->botp.ptr;
   c.g.bot = pl->bot.ptr;
@@ -302,7 +343,15 @@ void compose_tasks(bbtc_plan* pl) {
   std::vector<int64_t> hstart((size_t)nb + 1, 0);
   for (const HeavyCol& hc : pl->h_heavy) hstart[hc.cid + 1]++;
   for (int64_t b = 0; b < nb; ++b) hstart[b + 1] += hstart[b];
-  // hub chunks first (heaviest tasks first), then the column ranges
+  // Work items, task by task in plan order (heaviest first): the task's hub
+  // chunks, then its active columns in ranges sized by the task's estimated
+  // work per column so that dense tasks spread over many workgroups (at most
+  // item_rows columns per range).  The persistent kernel walks the whole list;
+  // the plain form launches each task's range of the list on its own.
+  const uint32_t step = (uint32_t)(pl->opt.item_rows > 0 ? pl->opt.item_rows : kDefaultItemRows);
+  double est_sum = 0;
+  for (int32_t q : pl->h_work) est_sum += pl->h_tasks[q].est;
+  const double target = est_sum / (double)std::max<int64_t>(1, (int64_t)pl->blocks_per_cu * pl->ncu * 16);
   for (int32_t q : pl->h_work) {
     const bbtc_task& t = pl->h_tasks[q];
     const int64_t cid = col_block_id(t.i, t.j);
@@ -312,23 +361,223 @@ void compose_tasks(bbtc_plan* pl) {
       for (uint32_t lo = 0; lo < hc.cnt; lo += kHubChunk)
         pl->h_items.push_back(DevItem{0, q, lo, std::min(hc.cnt, lo + kHubChunk), hc.v, 0});
     }
+    const uint32_t cols = (uint32_t)pl->h_nzc[cid];
+    const double per_col = cols ? t.est / (double)cols : 0.0;
+    uint32_t nper = step;
+    if (per_col > 0 && target > 0) nper = (uint32_t)std::max(1.0, std::min((double)step, target / per_col));
+    for (uint32_t lo = 0; lo < cols; lo += nper)
+      pl->h_items.push_back(DevItem{0, q, lo, std::min(cols, lo + nper), -1, 0});
     pl->h_hub_count[q] = (int64_t)pl->h_items.size() - pl->h_hub_first[q];
   }
-  // column ranges sized by the task's estimated work per active column, so
-  // that dense tasks spread over many workgroups (at most item_rows columns)
-  const uint32_t step = (uint32_t)(pl->opt.item_rows > 0 ? pl->opt.item_rows : kDefaultItemRows);
-  double est_sum = 0;
-  for (int32_t q : pl->h_work) est_sum += pl->h_tasks[q].est;
-  const double target = est_sum / (double)std::max<int64_t>(1, (int64_t)pl->blocks_per_cu * pl->ncu * 16);
-  for (int32_t q : pl->h_work) {
-    const bbtc_task& t = pl->h_tasks[q];
-    const uint32_t cols = (uint32_t)pl->h_nzc[col_block_id(t.i, t.j)];
-    if (cols == 0) continue;
-    const double per_col = t.est / (double)cols;
-    uint32_t n = step;
-    if (per_col > 0 && target > 0) n = (uint32_t)std::max(1.0, std::min((double)step, target / per_col));
-    for (uint32_t lo = 0; lo < cols; lo += n) pl->h_items.push_back(DevItem{0, q, lo, std::min(cols, lo + n), -1, 0});
+}
+
+// ------------------------------------------------------------ streaming
+// The count phase needs, for the tasks of block pair (i,j), only three row
+// stripes: the out-rows of V_i and of V_j with their block boundaries, and
+// the in-rows of V_j with theirs (plus the active columns of G_ij, which stay
+// resident).  When the plan exceeds the device budget, those arrays move to
+// pinned host memory, the device keeps a cache of equal-size stripe slots
+// within the budget, and bbtc_count walks the block pairs i-major (the out-
+// stripe of V_i stays cached across its pairs), uploading stripes on a side
+// stream, gated by events, one pair ahead of the kernels.
+template <typename T>
+bbtc_status to_pinned(T** dst, const T* src, size_t n, hipStream_t s) {
+  HIP_TRY(hipHostMalloc((void**)dst, std::max<size_t>(n, 1) * sizeof(T), hipHostMallocDefault), "pinned alloc");
+  if (n) HIP_TRY(hipMemcpyAsync(*dst, src, n * sizeof(T), hipMemcpyDeviceToHost, s), "D2H");
+  return BBTC_OK;
+}
+
+size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+size_t stripe_bytes(const bbtc_plan* pl, int key) {
+  const int a = key >> 1;
+  if ((key & 1) == 0)
+    return align16(4 * (pl->ocut[a + 1] - pl->ocut[a])) + 4 * (pl->h_botp[a + 1] - pl->h_botp[a]);
+  return align16(4 * (pl->icut[a + 1] - pl->icut[a])) + 4 * (pl->h_tbotp[a + 1] - pl->h_tbotp[a]);
+}
+
+bbtc_status stream_setup(bbtc_plan* pl, hipStream_t s) {
+  const int32_t p = pl->p;
+  const int64_t n = pl->n;
+  // orow/irow at the cut points
+  std::vector<uint32_t> oro(n + 1), iro(n + 1);
+  HIP_TRY(hipMemcpyAsync(oro.data(), pl->orow.ptr, 4 * (n + 1), hipMemcpyDeviceToHost, s), "D2H");
+  HIP_TRY(hipMemcpyAsync(iro.data(), pl->irow.ptr, 4 * (n + 1), hipMemcpyDeviceToHost, s), "D2H");
+  HIP_TRY(hipStreamSynchronize(s), "sync");
+  pl->ocut.assign(p + 1, 0);
+  pl->icut.assign(p + 1, 0);
+  for (int32_t a = 0; a <= p; ++a) {
+    pl->ocut[a] = oro[pl->h_cuts[a]];
+    pl->icut[a] = iro[pl->h_cuts[a]];
   }
+  pl->h_botp.assign(p + 1, 0);
+  pl->h_tbotp.assign(p + 1, 0);
+  HIP_TRY(hipMemcpyAsync(pl->h_botp.data(), pl->botp.ptr, 8 * (p + 1), hipMemcpyDeviceToHost, s), "D2H");
+  HIP_TRY(hipMemcpyAsync(pl->h_tbotp.data(), pl->tbotp.ptr, 8 * (p + 1), hipMemcpyDeviceToHost, s), "D2H");
+  HIP_TRY(hipStreamSynchronize(s), "sync");
+  size_t slot = 0;
+  for (int key = 0; key < 2 * p; ++key) slot = std::max(slot, stripe_bytes(pl, key));
+  pl->slot_bytes = align16(std::max<size_t>(slot, 16));
+  bbtc_status st;
+  if ((st = to_pinned(&pl->h_ocol, pl->ocol.ptr, (size_t)pl->m, s)) != BBTC_OK) return st;
+  if ((st = to_pinned(&pl->h_icol, pl->icol.ptr, (size_t)pl->m, s)) != BBTC_OK) return st;
+  if ((st = to_pinned(&pl->h_bot, pl->bot.ptr, (size_t)pl->h_botp[p], s)) != BBTC_OK) return st;
+  if ((st = to_pinned(&pl->h_tbot, pl->tbot.ptr, (size_t)pl->h_tbotp[p], s)) != BBTC_OK) return st;
+  if ((st = to_pinned(&pl->h_orow, pl->orow.ptr, (size_t)n + 1, s)) != BBTC_OK) return st;
+  HIP_TRY(hipStreamSynchronize(s), "sync");
+  pl->streamed = true;
+  // release everything the count phase does not read
+  pl->ocol.release(); pl->icol.release(); pl->bot.release(); pl->tbot.release();
+  pl->keys_a.release(); pl->keys_b.release(); pl->hist.release(); pl->partial.release();
+  pl->od.release(); pl->idg.release(); pl->orow.release(); pl->irow.release(); pl->order.release();
+  pl->longrows.release(); pl->hugerows.release(); pl->ccnt.release(); pl->ccoff.release();
+  pl->in_rowptr.release(); pl->in_col.release(); pl->heavy.release(); pl->chunk0.release(); pl->ccbase.release();
+  pl->bnnz.release(); pl->bnzr.release(); pl->bnzc.release();
+  // group the work items by block pair, i-major
+  std::vector<DevItem> items = pl->h_items;
+  auto pair_of = [&](const DevItem& it) {
+    const bbtc_task& t = pl->h_tasks[it.task];
+    return (int64_t)t.i * p + t.j;
+  };
+  std::stable_sort(items.begin(), items.end(),
+                   [&](const DevItem& x, const DevItem& y) { return pair_of(x) < pair_of(y); });
+  pl->groups.clear();
+  pl->group_first.clear();
+  pl->group_count.clear();
+  for (size_t q = 0; q < items.size(); ++q) {
+    const int64_t key = pair_of(items[q]);
+    if (pl->groups.empty() || (int64_t)pl->groups.back().first * p + pl->groups.back().second != key) {
+      pl->groups.push_back({(int32_t)(key / p), (int32_t)(key % p)});
+      pl->group_first.push_back((int64_t)q);
+      pl->group_count.push_back(0);
+    }
+    pl->group_count.back()++;
+  }
+  pl->h_items = items;
+  HIP_TRY(hipMemcpyAsync(pl->items.ptr, items.data(), sizeof(DevItem) * items.size(), hipMemcpyHostToDevice, s),
+          "H2D");
+  HIP_TRY(hipStreamSynchronize(s), "sync");
+  // the stripe cache takes what the budget leaves
+  const int64_t fixed = (int64_t)pl->footprint();
+  const int64_t room = pl->opt.device_budget_bytes - fixed;
+  const int64_t nslots = room > 0 ? room / (int64_t)pl->slot_bytes : 0;
+  if (nslots < 3)
+    return fail(BBTC_EBUDGET, "device budget holds " + std::to_string(nslots) + " stripe slots of " +
+                                  std::to_string(pl->slot_bytes) + " B besides " + std::to_string(fixed) +
+                                  " B of resident data; a block pair needs 3");
+  const int64_t use = std::min<int64_t>(nslots, 2 * p);
+  HIP_TRY(pl->cache.ensure((size_t)use * pl->slot_bytes), "alloc stripe cache");
+  pl->slots.assign((size_t)use, bbtc_plan::Slot());
+  for (auto& sl : pl->slots) {
+    HIP_TRY(hipEventCreateWithFlags(&sl.ready, hipEventDisableTiming), "event");
+    HIP_TRY(hipEventCreateWithFlags(&sl.released, hipEventDisableTiming), "event");
+  }
+  return BBTC_OK;
+}
+
+// Returns the slot holding stripe `key`, uploading it (on `cs`) if needed,
+// never evicting a slot listed in `keep`.  -1 if every slot is kept.
+int stripe_slot(bbtc_plan* pl, int key, const std::vector<int>& keep, hipStream_t cs, bbtc_status* st) {
+  *st = BBTC_OK;
+  int victim = -1;
+  for (size_t q = 0; q < pl->slots.size(); ++q)
+    if (pl->slots[q].key == key) {
+      pl->slots[q].last = ++pl->clock;
+      return (int)q;
+    }
+  for (size_t q = 0; q < pl->slots.size(); ++q) {
+    if (std::find(keep.begin(), keep.end(), (int)q) != keep.end()) continue;
+    if (victim < 0 || pl->slots[q].last < pl->slots[victim].last) victim = (int)q;
+  }
+  if (victim < 0) return -1;
+  bbtc_plan::Slot& sl = pl->slots[victim];
+  hipError_t e = hipSuccess;
+  if (sl.used) e = hipStreamWaitEvent(cs, sl.released, 0);  // kernels reading the old stripe are done
+  char* base = pl->cache.ptr + (size_t)victim * pl->slot_bytes;
+  const int a = key >> 1;
+  if (e == hipSuccess) {
+    if ((key & 1) == 0) {
+      const size_t nc = pl->ocut[a + 1] - pl->ocut[a], nb = pl->h_botp[a + 1] - pl->h_botp[a];
+      if (nc) e = hipMemcpyAsync(base, pl->h_ocol + pl->ocut[a], 4 * nc, hipMemcpyHostToDevice, cs);
+      if (e == hipSuccess && nb)
+        e = hipMemcpyAsync(base + align16(4 * nc), pl->h_bot + pl->h_botp[a], 4 * nb, hipMemcpyHostToDevice, cs);
+    } else {
+      const size_t nc = pl->icut[a + 1] - pl->icut[a], nb = pl->h_tbotp[a + 1] - pl->h_tbotp[a];
+      if (nc) e = hipMemcpyAsync(base, pl->h_icol + pl->icut[a], 4 * nc, hipMemcpyHostToDevice, cs);
+      if (e == hipSuccess && nb)
+        e = hipMemcpyAsync(base + align16(4 * nc), pl->h_tbot + pl->h_tbotp[a], 4 * nb, hipMemcpyHostToDevice, cs);
+    }
+  }
+  if (e == hipSuccess) e = hipEventRecord(sl.ready, cs);
+  if (e != hipSuccess) {
+    *st = hip_fail(e, "stripe upload");
+    return -1;
+  }
+  sl.key = key;
+  sl.last = ++pl->clock;
+  pl->copies++;
+  return victim;
+}
+
+bbtc_status count_streamed(bbtc_plan* pl, hipStream_t s, uint64_t* d_per_task, uint64_t* d_total) {
+  const int64_t nt = (int64_t)pl->h_tasks.size();
+  HIP_TRY(launch_reset(d_per_task, nt, d_total, pl->cursor.ptr, s), "reset");
+  hipStream_t cs = pl->side[1];
+  pl->copies = 0;
+  // earlier uploads may still be pending against an older count
+  const int grid_max = pl->blocks_per_cu * pl->ncu;
+  for (size_t g = 0; g < pl->groups.size(); ++g) {
+    const int32_t i = pl->groups[g].first, j = pl->groups[g].second;
+    const int need[3] = {2 * i, 2 * j, 2 * j + 1};
+    std::vector<int> keep;
+    int slot[3];
+    bbtc_status st = BBTC_OK;
+    for (int q = 0; q < 3; ++q) {
+      slot[q] = stripe_slot(pl, need[q], keep, cs, &st);
+      if (st != BBTC_OK) return st;
+      if (slot[q] < 0) return fail(BBTC_EBUDGET, "stripe cache too small for one block pair");
+      keep.push_back(slot[q]);
+    }
+    for (int q = 0; q < 3; ++q) HIP_TRY(hipStreamWaitEvent(s, pl->slots[slot[q]].ready, 0), "wait");
+    // prefetch the next pair's stripes into slots this pair does not use
+    if (g + 1 < pl->groups.size()) {
+      const int32_t i2 = pl->groups[g + 1].first, j2 = pl->groups[g + 1].second;
+      const int nx[3] = {2 * i2, 2 * j2, 2 * j2 + 1};
+      std::vector<int> keep2 = keep;
+      for (int q = 0; q < 3; ++q) {
+        const int sl = stripe_slot(pl, nx[q], keep2, cs, &st);
+        if (st != BBTC_OK) return st;
+        if (sl < 0) break;
+        keep2.push_back(sl);
+      }
+    }
+    CountParams cp;
+    std::memset(&cp, 0, sizeof(cp));
+    cp.one = plan_ctx(pl, d_per_task, d_total);
+    cp.one.g.gi = i;
+    cp.one.g.gj = j;
+    auto base = [&](int q) { return pl->cache.ptr + (size_t)slot[q] * pl->slot_bytes; };
+    const size_t nci = pl->ocut[i + 1] - pl->ocut[i], ncj = pl->ocut[j + 1] - pl->ocut[j];
+    const size_t nij = pl->icut[j + 1] - pl->icut[j];
+    // shifted so that absolute positions index the cached stripe
+    cp.one.g.colI = (const int32_t*)base(0) - pl->ocut[i];
+    cp.one.g.botI = (const uint32_t*)(base(0) + align16(4 * nci));
+    cp.one.g.colJ = (const int32_t*)base(1) - pl->ocut[j];
+    cp.one.g.botJ = (const uint32_t*)(base(1) + align16(4 * ncj));
+    cp.one.g.icolJ = (const int32_t*)base(2) - pl->icut[j];
+    cp.one.g.tbotJ = (const uint32_t*)(base(2) + align16(4 * nij));
+    cp.items = pl->items.ptr + pl->group_first[g];
+    cp.nitems = (uint32_t)pl->group_count[g];
+    cp.cursor = pl->cursor.ptr;
+    HIP_TRY(launch_reset(nullptr, 0, nullptr, pl->cursor.ptr, s), "cursor");  // cursor only
+    const int grid = (int)std::min<int64_t>(grid_max, (int64_t)cp.nitems);
+    HIP_TRY(launch_count_persistent(cp, grid, false, s), "count");
+    for (int q = 0; q < 3; ++q) {
+      HIP_TRY(hipEventRecord(pl->slots[slot[q]].released, s), "event");
+      pl->slots[slot[q]].used = true;
+    }
+  }
+  return BBTC_OK;
 }
 
 bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStream_t s, bbtc_plan* pl) {
@@ -361,6 +610,7 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
 
   pl->ready = false;
   pl->drop_graph();
+  pl->drop_stream();
   pl->opt = opt;
   pl->n = n;
   if (!pl->ncu) {
@@ -615,8 +865,9 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   st.bytes_total = st.bytes_colidx + st.bytes_rowidx + 8 * nt;
   st.footprint = (int64_t)pl->footprint();
   if (opt.device_budget_bytes > 0 && st.footprint > opt.device_budget_bytes) {
-    // The resident layout does not fit; streaming of stripes is handled by
-    // the budgeted count path.  Report the footprint, keep the plan.
+    bbtc_status sst = stream_setup(pl, s);
+    if (sst != BBTC_OK) return sst;
+    st.footprint = (int64_t)pl->footprint();
   }
   st.partition_ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -744,6 +995,7 @@ bbtc_status bbtc_count(bbtc_plan* pl, void* stream, uint64_t* d_per_task, uint64
   if (!pl || !pl->ready) return fail(BBTC_ESTATE, "plan is not ready");
   if (!d_total || (!d_per_task && !pl->h_tasks.empty())) return fail(BBTC_EINVAL, "null output");
   hipStream_t s = (hipStream_t)stream;
+  if (pl->streamed) return count_streamed(pl, s, d_per_task, d_total);
   const int64_t nt = (int64_t)pl->h_tasks.size();
   const bool graphed = pl->opt.mode == BBTC_MODE_PERSISTENT && pl->opt.graph == 0 && !pl->h_items.empty();
   if (!graphed) HIP_TRY(launch_reset(d_per_task, nt, d_total, pl->cursor.ptr, s), "reset");
@@ -787,11 +1039,8 @@ bbtc_status bbtc_count(bbtc_plan* pl, void* stream, uint64_t* d_per_task, uint64
   for (int q = 0; q < 4; ++q) HIP_TRY(hipStreamWaitEvent(pl->side[q], pl->ev_fork, 0), "wait");
   for (size_t w = 0; w < pl->h_work.size(); ++w) {
     const int32_t t = pl->h_work[w];
-    const bbtc_task& tk = pl->h_tasks[t];
-    const uint32_t cols = (uint32_t)pl->h_nzc[col_block_id(tk.i, tk.j)];
-    HIP_TRY(launch_count_task(cp, t, cols, pl->side[w % 4]), "count task");
     HIP_TRY(launch_count_items(cp, (uint32_t)pl->h_hub_first[t], (uint32_t)pl->h_hub_count[t], pl->side[w % 4]),
-            "count hub columns");
+            "count task");
   }
   for (int q = 0; q < 4; ++q) {
     HIP_TRY(hipEventRecord(pl->ev_join[q], pl->side[q]), "event");
@@ -807,6 +1056,7 @@ bbtc_status bbtc_count_multi(bbtc_plan* const* plans, int32_t nplans, void* stre
   if (nplans == 0) return BBTC_OK;
   for (int32_t q = 0; q < nplans; ++q) {
     if (!plans[q] || !plans[q]->ready) return fail(BBTC_ESTATE, "plan is not ready");
+    if (plans[q]->streamed) return fail(BBTC_ESTATE, "a streamed (over-budget) plan cannot join a shared launch");
     if (!d_per_task[q]) return fail(BBTC_EINVAL, "null output");
   }
   try {
@@ -942,6 +1192,10 @@ bbtc_status bbtc_plan_stats(const bbtc_plan* pl, bbtc_stats* out) {
   if (!pl || !pl->ready) return fail(BBTC_ESTATE, "plan is not ready");
   if (!out) return fail(BBTC_EINVAL, "null argument");
   *out = pl->stats;
+  out->streamed = pl->streamed ? 1 : 0;
+  out->stripe_slots = (int64_t)pl->slots.size();
+  out->stripe_bytes = (int64_t)pl->slot_bytes;
+  out->stripe_uploads = pl->copies;
   return BBTC_OK;
 }
 
@@ -956,9 +1210,10 @@ bbtc_status bbtc_plan_copy_oriented(const bbtc_plan* pl, uint32_t* orow, int32_t
   if (!pl || !pl->ready) return fail(BBTC_ESTATE, "plan is not ready");
   if (!orow || (pl->m > 0 && !ocol)) return fail(BBTC_EINVAL, "null argument");
   hipStream_t s = (hipStream_t)stream;
-  HIP_TRY(hipMemcpyAsync(orow, pl->orow.ptr, sizeof(uint32_t) * (pl->n + 1), hipMemcpyDefault, s), "copy");
-  if (pl->m > 0)
-    HIP_TRY(hipMemcpyAsync(ocol, pl->ocol.ptr, sizeof(int32_t) * pl->m, hipMemcpyDefault, s), "copy");
+  const uint32_t* src_row = pl->streamed ? pl->h_orow : pl->orow.ptr;
+  const int32_t* src_col = pl->streamed ? pl->h_ocol : pl->ocol.ptr;
+  HIP_TRY(hipMemcpyAsync(orow, src_row, sizeof(uint32_t) * (pl->n + 1), hipMemcpyDefault, s), "copy");
+  if (pl->m > 0) HIP_TRY(hipMemcpyAsync(ocol, src_col, sizeof(int32_t) * pl->m, hipMemcpyDefault, s), "copy");
   return BBTC_OK;
 }
 

@@ -58,6 +58,18 @@ struct HeavyCol {
 struct GraphView {
   int32_t p;
   uint32_t m;  // entries of ocol (and of icol)
+  // Streamed launches cover the tasks of one block pair (gi, gj) and read the
+  // rows of parts gi and gj from cached stripes: colI/colJ/icolJ are shifted
+  // so that the absolute positions held in bot/tbot index them, botI/botJ and
+  // tbotJ point at the first block-boundary row of the part.  gi < 0: the
+  // whole graph is resident and the fields below are used instead.
+  int32_t gi, gj;
+  const int32_t* colI;
+  const int32_t* colJ;
+  const int32_t* icolJ;
+  const uint32_t* botI;
+  const uint32_t* botJ;
+  const uint32_t* tbotJ;
   const int32_t* cuts;
   const uint64_t* botp;
   const uint32_t* bot;
@@ -154,7 +166,6 @@ hipError_t launch_acol(const BlockBuild& bb, hipStream_t s);
 
 // ---- launchers (kernels_count.hip) ----
 hipError_t launch_reset(uint64_t* per_task, int64_t ntasks, uint64_t* total, uint32_t* cursor, hipStream_t s);
-hipError_t launch_count_task(const CountParams& cp, int32_t task, uint32_t nrows, hipStream_t s);
 // Zeroes the outputs of every plan of a multi-plan launch and the cursor.
 hipError_t launch_reset_multi(const PlanCtx* ctxs, int32_t nplans, uint32_t* cursor, hipStream_t s);
 hipError_t launch_count_persistent(const CountParams& cp, int grid, bool multi, hipStream_t s);

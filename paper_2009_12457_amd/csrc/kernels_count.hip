@@ -55,6 +55,9 @@ struct TaskCtx {
   const uint32_t* boti;
   const uint32_t* botj;
   const uint32_t* tbotj;
+  const int32_t* coli;      // out-rows of part i (N(G_ik,u)), absolute positions
+  const int32_t* colj;      // out-rows of part j (N(G_jk,v)), absolute positions
+  const int32_t* icolj;     // in-rows of part j, absolute positions
   const int32_t* ac;        // active columns of block (i,j)
 };
 
@@ -70,37 +73,50 @@ __device__ __forceinline__ TaskCtx make_ctx(const GraphView& g, const DevTask& t
   c.stri = (uint32_t)(g.p - t.i + 1);
   c.strj = (uint32_t)(g.p - t.j + 1);
   c.tstrj = (uint32_t)(t.j + 2);
-  c.boti = g.bot + g.botp[t.i];
-  c.botj = g.bot + g.botp[t.j];
-  c.tbotj = g.tbot + g.tbotp[t.j];
+  if (g.gi >= 0) {  // streamed: the launch's parts come from cached stripes
+    c.boti = g.botI;
+    c.botj = g.botJ;
+    c.tbotj = g.tbotJ;
+    c.coli = g.colI;
+    c.colj = g.colJ;
+    c.icolj = g.icolJ;
+  } else {
+    c.boti = g.bot + g.botp[t.i];
+    c.botj = g.bot + g.botp[t.j];
+    c.tbotj = g.tbot + g.tbotp[t.j];
+    c.coli = g.ocol;
+    c.colj = g.ocol;
+    c.icolj = g.icol;
+  }
   c.ac = g.acol + g.acp[col_block_id(t.i, t.j)];
   return c;
 }
 
 // |N(G_ik,u) cap N(G_jk,v)| summed over the in-neighbours u of v in V_i, one lane.
-__device__ __forceinline__ uint64_t light_col(const int32_t* __restrict__ col, const int32_t* __restrict__ icol,
-                                              const TaskCtx& c, uint32_t i0, uint32_t i1, uint32_t c0, uint32_t c1) {
+__device__ __forceinline__ uint64_t light_col(const TaskCtx& c, uint32_t i0, uint32_t i1, uint32_t c0, uint32_t c1) {
+  const int32_t* __restrict__ acol = c.coli;
+  const int32_t* __restrict__ ccol = c.colj;
   uint64_t cnt = 0;
   for (uint32_t e = i0; e < i1; ++e) {
-    const int32_t u = icol[e];
+    const int32_t u = c.icolj[e];
     const uint32_t* ur = c.boti + (uint64_t)(u - c.ci) * c.stri;
     uint32_t a = ur[c.dk];
     const uint32_t ae = ur[c.dk + 1];
     if (a >= ae) continue;
     uint32_t b = c0;
-    int32_t x = col[a], y = col[b];
+    int32_t x = acol[a], y = ccol[b];
     while (true) {
       if (x == y) {
         ++cnt;
         if (++a >= ae || ++b >= c1) break;
-        x = col[a];
-        y = col[b];
+        x = acol[a];
+        y = ccol[b];
       } else if (x < y) {
         if (++a >= ae) break;
-        x = col[a];
+        x = acol[a];
       } else {
         if (++b >= c1) break;
-        y = col[b];
+        y = ccol[b];
       }
     }
   }
@@ -182,9 +198,10 @@ __device__ __forceinline__ uint32_t stage_has(const Stage& st, const uint32_t* b
 // into segments of kSeg consecutive entries of one N(G_ik,u); a wavefront
 // prefix sum over the segment counts of 64 in-neighbours at a time lets all
 // lanes share the segments, however unequal the lists are.
-__device__ uint64_t probe_flat(const int32_t* __restrict__ col, const int32_t* __restrict__ icol, const TaskCtx& c,
-                               uint32_t i0, uint32_t i1, const Stage& st, const uint32_t* buf, uint32_t sn,
-                               int32_t smin, int32_t smax, uint32_t* sa0, uint32_t* sa1, uint32_t* sex) {
+__device__ uint64_t probe_flat(const TaskCtx& c, uint32_t i0, uint32_t i1, const Stage& st, const uint32_t* buf,
+                               uint32_t sn, int32_t smin, int32_t smax, uint32_t* sa0, uint32_t* sa1, uint32_t* sex) {
+  const int32_t* __restrict__ col = c.coli;
+  const int32_t* __restrict__ icol = c.icolj;
   const uint32_t l = (uint32_t)lane_id();
   uint64_t cnt = 0;
   for (uint32_t eb = i0; eb < i1; eb += kWave) {
@@ -226,9 +243,9 @@ __device__ uint64_t probe_flat(const int32_t* __restrict__ col, const int32_t* _
 }
 
 // One wavefront: in-slice [i0,i1) of v against N(G_jk,v) = ocol[c0..c1).
-__device__ uint64_t wave_col(const int32_t* __restrict__ col, const int32_t* __restrict__ icol, const TaskCtx& c,
-                             uint32_t i0, uint32_t i1, uint32_t c0, uint32_t c1, bool use_hash, uint32_t* abuf,
-                             uint32_t* sa0, uint32_t* sa1, uint32_t* sex) {
+__device__ uint64_t wave_col(const TaskCtx& c, uint32_t i0, uint32_t i1, uint32_t c0, uint32_t c1, bool use_hash,
+                             uint32_t* abuf, uint32_t* sa0, uint32_t* sa1, uint32_t* sex) {
+  const int32_t* __restrict__ col = c.colj;
   const uint32_t l = (uint32_t)lane_id();
   uint64_t cnt = 0;
   const Stage st = pick_stage(c, use_hash, c1 - c0);
@@ -236,7 +253,7 @@ __device__ uint64_t wave_col(const int32_t* __restrict__ col, const int32_t* __r
     const uint32_t sn = min(st.piece, c1 - s_lo);
     stage_fill(st, abuf, col, s_lo, sn, c.ck, l, kWave);
     wave_sync();
-    cnt += probe_flat(col, icol, c, i0, i1, st, abuf, sn, col[s_lo], col[s_lo + sn - 1], sa0, sa1, sex);
+    cnt += probe_flat(c, i0, i1, st, abuf, sn, col[s_lo], col[s_lo + sn - 1], sa0, sa1, sex);
     stage_clear(st, abuf, col, s_lo, sn, c.ck, l, kWave);
     wave_sync();
   }
@@ -247,8 +264,6 @@ __device__ uint64_t wave_col(const int32_t* __restrict__ col, const int32_t* __r
 // with in-slices longer than cp.split are left to their split items.
 __device__ uint64_t process_cols(const PlanCtx& cp, const TaskCtx& c, uint32_t lo, uint32_t hi, CountLds& s) {
   const int t = threadIdx.x, w = t / kWave;
-  const int32_t* __restrict__ col = cp.g.ocol;
-  const int32_t* __restrict__ icol = cp.g.icol;
   uint64_t cnt = 0;
   for (uint32_t base = lo; base < hi; base += kThreads) {
     const uint32_t x = base + t;
@@ -267,7 +282,7 @@ __device__ uint64_t process_cols(const PlanCtx& cp, const TaskCtx& c, uint32_t l
             s.q[qi][2] = c0;
             s.q[qi][3] = c1;
           } else {
-            cnt += light_col(col, icol, c, i0, i1, c0, c1);
+            cnt += light_col(c, i0, i1, c0, c1);
           }
         }
       }
@@ -277,7 +292,7 @@ __device__ uint64_t process_cols(const PlanCtx& cp, const TaskCtx& c, uint32_t l
     for (uint32_t h = w; h < nq; h += 4) {
       const uint32_t i0 = s.q[h][0], i1 = s.q[h][1], c0 = s.q[h][2], c1 = s.q[h][3];
       const bool use_hash = cp.hash_min >= 0 && (c1 - c0) >= (uint32_t)cp.hash_min;
-      cnt += wave_col(col, icol, c, i0, i1, c0, c1, use_hash, s.abuf[w], s.sa0[w], s.sa1[w], s.sex[w]);
+      cnt += wave_col(c, i0, i1, c0, c1, use_hash, s.abuf[w], s.sa0[w], s.sa1[w], s.sex[w]);
     }
     __syncthreads();
     if (t == 0) s.qn = 0;
@@ -291,8 +306,7 @@ __device__ uint64_t process_cols(const PlanCtx& cp, const TaskCtx& c, uint32_t l
 // wavefronts probes a quarter of the chunk's in-neighbours against it.
 __device__ uint64_t hub_chunk(const PlanCtx& cp, const TaskCtx& c, int32_t v, uint32_t lo, uint32_t hi,
                               CountLds& s) {
-  const int32_t* __restrict__ col = cp.g.ocol;
-  const int32_t* __restrict__ icol = cp.g.icol;
+  const int32_t* __restrict__ col = c.colj;
   const int w = threadIdx.x / kWave;
   const uint32_t* vr = c.botj + (uint64_t)(v - c.cj) * c.strj;
   const uint32_t c0 = vr[c.dkj], c1 = vr[c.dkj + 1];
@@ -310,7 +324,7 @@ __device__ uint64_t hub_chunk(const PlanCtx& cp, const TaskCtx& c, int32_t v, ui
     const uint32_t sn = min(st.piece, c1 - s_lo);
     stage_fill(st, buf, col, s_lo, sn, c.ck, threadIdx.x, kThreads);
     __syncthreads();
-    cnt += probe_flat(col, icol, c, w0, w1, st, buf, sn, col[s_lo], col[s_lo + sn - 1], s.sa0[w], s.sa1[w], s.sex[w]);
+    cnt += probe_flat(c, w0, w1, st, buf, sn, col[s_lo], col[s_lo + sn - 1], s.sa0[w], s.sa1[w], s.sex[w]);
     __syncthreads();
     stage_clear(st, buf, col, s_lo, sn, c.ck, threadIdx.x, kThreads);
     __syncthreads();
@@ -339,19 +353,6 @@ __device__ __forceinline__ uint64_t run_item(const PlanCtx& pc, const DevItem& i
   *out = t.out;
   if (item.v >= 0) return hub_chunk(pc, c, item.v, item.lo, item.hi, s);
   return process_cols(pc, c, item.lo, item.hi, s);
-}
-
-// One launch per task (the unbatched form): workgroup b takes active columns
-// [b*256, b*256+256) of the task; hub columns go to k_count_items launches.
-__global__ __launch_bounds__(kThreads) void k_count_task(CountParams cp, int32_t task, uint32_t ncols) {
-  __shared__ CountLds s;
-  init_lds(s);
-  const PlanCtx& pc = cp.one;
-  const DevItem item{0, task, blockIdx.x * (uint32_t)kThreads, min(ncols, (blockIdx.x + 1) * (uint32_t)kThreads), -1,
-                     0};
-  int32_t out = 0;
-  const uint64_t cnt = run_item(pc, item, s, &out);
-  flush(pc, out, cnt, s);
 }
 
 // Items [first, first + gridDim.x) of the item list, one workgroup each.
@@ -390,7 +391,7 @@ __global__ __launch_bounds__(kThreads) void k_reset(uint64_t* per_task, int64_t 
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntasks; t += (int64_t)gridDim.x * blockDim.x)
     per_task[t] = 0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    *total = 0;
+    if (total) *total = 0;
     if (cursor) *cursor = 0;
   }
 }
@@ -417,13 +418,6 @@ hipError_t launch_reset(uint64_t* per_task, int64_t ntasks, uint64_t* total, uin
   if (g < 1) g = 1;
   if (g > 4096) g = 4096;
   hipLaunchKernelGGL(k_reset, dim3((unsigned)g), dim3(kThreads), 0, s, per_task, ntasks, total, cursor);
-  return hipGetLastError();
-}
-
-hipError_t launch_count_task(const CountParams& cp, int32_t task, uint32_t ncols, hipStream_t s) {
-  if (ncols == 0) return hipSuccess;
-  const unsigned g = (ncols + kThreads - 1) / kThreads;
-  hipLaunchKernelGGL(k_count_task, dim3(g), dim3(kThreads), 0, s, cp, task, ncols);
   return hipGetLastError();
 }
 
