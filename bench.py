@@ -51,6 +51,79 @@ def timed(fn, reps, sync):
     return ts
 
 
+def serving_pool(kind, seed=5):
+    """Seeded request pool: each entry (name, n, rowptr, colidx)."""
+    import numpy as np
+
+    import graphgen
+    rng = np.random.default_rng(seed)
+    if kind == "full":
+        size, scales, nlog = 128, (12, 22), (4.0, 6.0)
+    else:
+        size, scales, nlog = 32, (10, 16), (4.0, 5.0)
+    pool = []
+    for q in range(size):
+        if rng.integers(2) == 0:
+            s = int(rng.integers(scales[0], scales[1] + 1))
+            ef = int(rng.integers(8, 33))
+            g = graphgen.rmat(s, ef, 1000 + q)
+        else:
+            nn = int(10 ** rng.uniform(*nlog))
+            deg = int(rng.integers(8, 65))
+            g = graphgen.er_avgdeg(nn, deg, 1000 + q)
+        pool.append(g)
+    return pool
+
+
+def serving_bench(kind):
+    """Poisson arrivals (200/s, seed 5) over the pool: batched continuous
+    serving vs first-come first-served plain per-request counting."""
+    import numpy as np
+    import torch
+
+    import paper_2009_12457_amd as bb
+    from paper_2009_12457_amd import serve
+
+    pool = serving_pool(kind)
+    rng = np.random.default_rng(5)
+    nreq, warm = (2200, 200) if kind == "full" else (600, 100)
+    gaps = rng.exponential(1.0 / 200.0, size=nreq)
+    offs = np.cumsum(gaps) - gaps[0]
+    pick = rng.integers(len(pool), size=nreq)
+    trace = [(float(offs[r]), pool[pick[r]].n, pool[pick[r]].rowptr, pool[pick[r]].colidx) for r in range(nreq)]
+    # each pool graph counted alone once (the reference for "same alone and in the mix")
+    alone = {}
+    for q, g in enumerate(pool):
+        p = max(1, min(g.n, int(round(len(g.colidx) / max(g.n, 1)))))
+        plan = bb.bbtc_partition(g.n, g.rowptr, g.colidx, options=bb.bbtc_options_default(p=p), trusted=True)
+        _, tot = bb.bbtc_count(plan)
+        torch.cuda.synchronize()
+        alone[q] = int(tot.item())
+        plan.destroy()
+    edges = sum(len(t[3]) // 2 for t in trace[warm:])
+    out = {"pool": kind, "pool_graphs": len(pool), "requests": nreq - warm, "warmup": warm, "rate_per_s": 200,
+           "mean_edges_per_request": edges / (nreq - warm)}
+    srv = serve.Server(hbm_budget_bytes=64 << 30, compute_streams=2)
+    t0 = time.perf_counter()
+    try:
+        res = serve.run_trace(srv, trace)
+    finally:
+        srv.close()
+    span = max(r.done for r in res[warm:]) - min(r.arrival for r in res[warm:])
+    for r, q in zip(res, pick):
+        if r.total != alone[int(q)]:
+            raise SystemExit(f"served result differs from the alone count for pool graph {int(q)}")
+    out["batched"] = dict(serve.latency_summary(res, warm), edges_per_s=edges / span, launches=srv.launches,
+                          wall_s=time.perf_counter() - t0)
+    res_p = serve.serve_plain(trace)
+    span_p = max(r.done for r in res_p[warm:]) - min(r.arrival for r in res_p[warm:])
+    for r, q in zip(res_p, pick):
+        if r.total != alone[int(q)]:
+            raise SystemExit(f"plain result differs from the alone count for pool graph {int(q)}")
+    out["plain"] = dict(serve.latency_summary(res_p, warm), edges_per_s=edges / span_p)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -61,6 +134,9 @@ def main():
     ap.add_argument("--profile-only", action="store_true", help="only the timed steps (for rocprofv3 runs)")
     ap.add_argument("--autotune", choices=["auto", "on", "off"], default="auto",
                     help="pick p and the row-mapping knobs with bbtc_autotune (auto: on for the 2^24 workloads)")
+    ap.add_argument("--serving", choices=["quick", "full", "off"], default="quick",
+                    help="serving measurement: quick (small pool, 600 requests), full (the 128-graph pool of "
+                         "R-MAT scale 12-22 / ER 1e4-1e6, 2000 requests after 200 warm-up) or off")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run 10 plain device-to-device copies of BYTES bytes (counter calibration)")
     args = ap.parse_args()
@@ -180,6 +256,8 @@ def main():
                "sample": f"whole {args.workload} graph once: canonicalise, degree order, orient and per-task count "
                          f"(p={p}), {dt:.2f} s"}
 
+    serving = serving_bench(args.serving) if args.serving != "off" else None
+
     out = {
         "metric": METRIC,
         "value": value,
@@ -202,6 +280,7 @@ def main():
         "plain": plain,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "serving": serving,
         "paper_context": "paper Table 4, scale20 R-MAT (different generator/seed): 0.079 s copy-included on "
                          "2x20-core Xeon + up to 8x V100 = 2.0e8 edges/s; context only",
     }
