@@ -261,7 +261,7 @@ void fill_defaults(bbtc_options* o) {
 }
 
 constexpr int kDefaultWaveMin = 16;
-constexpr int kDefaultHashMin = 64;
+constexpr int kDefaultHashMin = 16;
 constexpr int kDefaultItemRows = 256;
 constexpr uint32_t kHubSplit = 512;   // in-slice length above which a column is split
 constexpr uint32_t kHubChunk = 1024;  // in-neighbours per hub work item
@@ -433,6 +433,18 @@ bbtc_status stream_setup(bbtc_plan* pl, hipStream_t s) {
   pl->longrows.release(); pl->hugerows.release(); pl->ccnt.release(); pl->ccoff.release();
   pl->in_rowptr.release(); pl->in_col.release(); pl->heavy.release(); pl->chunk0.release(); pl->ccbase.release();
   pl->bnnz.release(); pl->bnzr.release(); pl->bnzc.release();
+  {  // keep only the used part of the active-column array (its capacity was m)
+    size_t used = 0;
+    for (int64_t v : pl->h_nzc) used += (size_t)v;
+    DevBuf<int32_t> exact;
+    HIP_TRY(exact.ensure(used), "alloc active columns");
+    if (used) HIP_TRY(hipMemcpyAsync(exact.ptr, pl->acol.ptr, 4 * used, hipMemcpyDeviceToDevice, s), "D2D");
+    HIP_TRY(hipStreamSynchronize(s), "sync");
+    pl->acol.release();
+    pl->acol = exact;
+    exact.ptr = nullptr;
+    exact.cap = 0;
+  }
   // group the work items by block pair, i-major
   std::vector<DevItem> items = pl->h_items;
   auto pair_of = [&](const DevItem& it) {

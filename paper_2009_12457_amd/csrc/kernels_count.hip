@@ -29,10 +29,14 @@ namespace bbtc {
 
 namespace {
 
-constexpr int kABuf = 2048;                   // LDS words per wavefront
+#ifndef BBTC_STAGE_WORDS
+#define BBTC_STAGE_WORDS 2048
+#endif
+constexpr int kABuf = BBTC_STAGE_WORDS;       // LDS words per wavefront
 constexpr uint32_t kBitmapBits = kABuf * 32;  // bitmap capacity in columns
-constexpr int kHashBits = 11;                 // 2^11 = kABuf hash slots
-static_assert((1 << kHashBits) == kABuf, "hash table fills the wave buffer");
+constexpr int log2i(int x) { return x <= 1 ? 0 : 1 + log2i(x / 2); }
+constexpr int kHashBits = log2i(kABuf);       // kABuf hash slots
+static_assert((1 << kHashBits) == kABuf, "stage size must be a power of two");
 
 constexpr uint32_t kSeg = 4;  // probes per flattened work unit
 

@@ -17,9 +17,15 @@ def count(plan):
     return per.cpu().numpy().view(np.uint64)[:plan.ntasks].copy(), int(tot.item())
 
 
-@pytest.mark.parametrize("name,p", [("rmat16", 12), ("rmat14_ef8", 5), ("er2000", 4)])
+def _graph(name):
+    if name == "er200k":
+        return graphgen.er(200000, 16.0 / 199999, 3)
+    return graphgen.workload(name)
+
+
+@pytest.mark.parametrize("name,p", [("rmat16", 12), ("rmat14_ef8", 5), ("er200k", 8)])
 def test_streamed_equals_resident(name, p):
-    g = graphgen.workload(name)
+    g = _graph(name)
     n, rp, ci = bb.csr_of(g, "cuda")
     res = bb.bbtc_partition(n, rp, ci, options=bb.bbtc_options_default(p=p), trusted=True)
     per_r, tot_r = count(res)
