@@ -30,7 +30,7 @@ namespace bbtc {
 namespace {
 
 #ifndef BBTC_STAGE_WORDS
-#define BBTC_STAGE_WORDS 2048
+#define BBTC_STAGE_WORDS 1024
 #endif
 constexpr int kABuf = BBTC_STAGE_WORDS;       // LDS words per wavefront
 constexpr uint32_t kBitmapBits = kABuf * 32;  // bitmap capacity in columns
