@@ -653,9 +653,11 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   } else {
     HIP_TRY(pl->err.ensure(8), "alloc");
     HIP_TRY(pl->longrows.ensure((size_t)n), "alloc");
+    HIP_TRY(pl->hugerows.ensure((size_t)n), "alloc");
+    HIP_TRY(pl->irow.ensure((size_t)n + 1), "alloc");  // chunk-prefix scratch for the validation kernels
     HIP_TRY(hipMemsetAsync(pl->err.ptr, 0, 8 * sizeof(uint32_t), s), "memset");
     HIP_TRY(launch_validate(rowptr, rp64, col, n, nnz, symmetric_check, pl->err.ptr, pl->longrows.ptr, pl->err.ptr + 4,
-                            s),
+                            pl->hugerows.ptr, pl->err.ptr + 5, pl->irow.ptr, s),
             "validate");
     uint32_t e = 0;
     HIP_TRY(hipMemcpyAsync(&e, pl->err.ptr, 4, hipMemcpyDeviceToHost, s), "D2H err");
@@ -691,7 +693,9 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
 
   // ---- orientation: out-rows (higher ranks) and in-rows (lower ranks) ----
   // err[4]: rows too long for one lane, listed in longrows by launch_degs
-  HIP_TRY(launch_degs(rowptr, rp64, col, n, pl->perm.ptr, pl->od.ptr, pl->idg.ptr, pl->longrows.ptr, pl->err.ptr + 4, s),
+  // err[4], err[5]: rows too long for one lane / huge rows, listed by launch_degs
+  HIP_TRY(launch_degs(rowptr, rp64, col, n, pl->perm.ptr, pl->od.ptr, pl->idg.ptr, pl->longrows.ptr, pl->err.ptr + 4,
+                      pl->hugerows.ptr, pl->err.ptr + 5, (uint32_t*)pl->keys_b.ptr, s),
           "degrees");
   HIP_TRY(scan_u32(pl->od.ptr, pl->orow.ptr, (uint64_t)n, pl->partial.ptr, s), "scan out-degrees");
   HIP_TRY(scan_u32(pl->idg.ptr, pl->irow.ptr, (uint64_t)n, pl->partial.ptr, s), "scan in-degrees");
@@ -704,8 +708,12 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   pl->m = (int64_t)m;
   HIP_TRY(pl->ocol.ensure((size_t)m), "alloc ocol");
   HIP_TRY(pl->icol.ensure((size_t)m), "alloc icol");
+  // od/idg are consumed (scanned): reuse them as the huge rows' fill cursors
+  HIP_TRY(hipMemsetAsync(pl->od.ptr, 0, sizeof(uint32_t) * n, s), "memset");
+  HIP_TRY(hipMemsetAsync(pl->idg.ptr, 0, sizeof(uint32_t) * n, s), "memset");
   HIP_TRY(launch_fill(rowptr, rp64, col, n, pl->perm.ptr, pl->orow.ptr, pl->irow.ptr, pl->ocol.ptr, pl->icol.ptr,
-                      pl->longrows.ptr, pl->err.ptr + 4, s),
+                      pl->longrows.ptr, pl->err.ptr + 4, pl->hugerows.ptr, pl->err.ptr + 5,
+                      (const uint32_t*)pl->keys_b.ptr, pl->od.ptr, pl->idg.ptr, s),
           "fill");
   // acol is not built yet: its m entries serve as the huge-row sort scratch
   HIP_TRY(pl->acol.ensure((size_t)m), "alloc active columns");

@@ -108,10 +108,13 @@ __host__ __device__ inline int64_t block_id(int64_t p, int64_t a, int64_t b) {
 __host__ __device__ inline int64_t col_block_id(int64_t a, int64_t b) { return b * (b + 1) / 2 + a; }
 
 // ---- launchers (kernels_prep.hip) ----
-// Row kernels take a scratch list (n entries) and a zeroed counter for the
-// rows longer than a lane handles; launch_fill reuses the list of launch_degs.
+// Row kernels take two scratch lists (n entries each) with zeroed counters:
+// rows longer than a lane handles, and huge rows cut into chunks (hpref:
+// n+1 scratch words for the chunk prefix); launch_fill reuses the lists and
+// prefix of launch_degs.
 hipError_t launch_validate(const void* rowptr, int rp64, const int32_t* colidx, int64_t n, int64_t nnz,
-                           int symmetric, uint32_t* err, uint32_t* list, uint32_t* nlist, hipStream_t s);
+                           int symmetric, uint32_t* err, uint32_t* list, uint32_t* nlist, uint32_t* hlist,
+                           uint32_t* nhlist, uint32_t* hpref, hipStream_t s);
 hipError_t launch_degkey(const void* rowptr, int rp64, int64_t n, int idbits, uint64_t* keys, hipStream_t s);
 // Sorts keys[0..count) by their low `bits` bits; the result ends in *result
 // (one of a or b).  hist/partial are scratch sized by radix_scratch_*().
@@ -123,10 +126,13 @@ hipError_t radix_sort_u64(uint64_t* a, uint64_t* b, uint64_t count, int bits, ui
 hipError_t scan_u32(const uint32_t* in, uint32_t* out, uint64_t count, uint32_t* partial, hipStream_t s);
 hipError_t launch_perm(const uint64_t* keys, int64_t n, int idbits, int32_t* order, int32_t* perm, hipStream_t s);
 hipError_t launch_degs(const void* rowptr, int rp64, const int32_t* colidx, int64_t n, const int32_t* perm,
-                       uint32_t* od, uint32_t* idg, uint32_t* list, uint32_t* nlist, hipStream_t s);
+                       uint32_t* od, uint32_t* idg, uint32_t* list, uint32_t* nlist, uint32_t* hlist,
+                       uint32_t* nhlist, uint32_t* hpref, hipStream_t s);
+// cur_o/cur_i: zeroed fill cursors of the huge rows (indexed by position in hlist).
 hipError_t launch_fill(const void* rowptr, int rp64, const int32_t* colidx, int64_t n, const int32_t* perm,
                        const uint32_t* orow, const uint32_t* irow, int32_t* ocol, int32_t* icol, const uint32_t* list,
-                       const uint32_t* nlist, hipStream_t s);
+                       const uint32_t* nlist, const uint32_t* hlist, const uint32_t* nhlist, const uint32_t* hpref,
+                       uint32_t* cur_o, uint32_t* cur_i, hipStream_t s);
 // Sorts every row of a CSR in place; values have at most `bits` bits.
 // longrows and hugerows need nrows entries each, q[0..1] must be zero, and
 // scratch needs rp[nrows] entries.

@@ -234,11 +234,12 @@ __device__ uint64_t probe_flat(const TaskCtx& c, uint32_t i0, uint32_t i1, const
         }
         const uint32_t s0 = sa0[lo] + (q - sex[lo]) * kSeg;
         const uint32_t s1 = min(s0 + kSeg, sa1[lo]);
-        for (uint32_t a = s0; a < s1; ++a) {
-          const int32_t w = col[a];
-          if (w > smax) break;  // N(G_ik,u) is ascending
-          if (w >= smin) cnt += stage_has(st, buf, sn, w, c.ck);
-        }
+        int32_t w[kSeg];
+#pragma unroll
+        for (uint32_t t = 0; t < kSeg; ++t) w[t] = (s0 + t < s1) ? col[s0 + t] : smax + 1;  // loads issued together
+#pragma unroll
+        for (uint32_t t = 0; t < kSeg; ++t)
+          if (w[t] >= smin && w[t] <= smax) cnt += stage_has(st, buf, sn, w[t], c.ck);
       }
     }
     wave_sync();

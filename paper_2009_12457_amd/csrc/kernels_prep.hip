@@ -30,7 +30,52 @@ constexpr unsigned kRowGrid = 8192;  // workgroups (4 waves each)
 // Row kernels here come in two forms: one lane per row for rows of at most
 // kLaneRow entries (longer rows are appended to a list), and one wavefront
 // per listed row.
-constexpr int64_t kLaneRow = 64;
+constexpr int64_t kLaneRow = 64;     // longest row handled by one lane
+constexpr int64_t kWaveRow = 4096;   // longest row handled by one wavefront
+constexpr int64_t kRowChunk = 2048;  // entries of a huge row per wavefront work unit
+
+// Lists: rows of (kLaneRow, kWaveRow] entries go to `list` (one wavefront
+// each), longer rows to `hlist`, which is short (the hubs): its rows are cut
+// into chunks of kRowChunk entries, and a wavefront finds its chunks by
+// walking that list.
+// hpref[q] = chunks of hlist rows before position q (q = 0..hcnt), written by
+// k_hprefix; work unit u belongs to the row q with hpref[q] <= u < hpref[q+1].
+template <typename RP>
+__global__ __launch_bounds__(kThreads) void k_hprefix(const RP* __restrict__ rowptr, const uint32_t* hlist,
+                                                      const uint32_t* nhlist, uint32_t* hpref) {
+  __shared__ uint32_t lds[4];
+  const uint32_t cnt = *nhlist;
+  uint32_t carry = 0;
+  for (uint32_t base = 0; base < cnt; base += kThreads) {
+    const uint32_t q = base + threadIdx.x;
+    uint32_t nch = 0;
+    if (q < cnt) {
+      const int64_t r = hlist[q];
+      nch = (uint32_t)((((int64_t)rowptr[r + 1] - (int64_t)rowptr[r]) + kRowChunk - 1) / kRowChunk);
+    }
+    uint32_t tot;
+    const uint32_t ex = block256_excl_scan<uint32_t>(nch, lds, &tot);
+    if (q < cnt) hpref[q] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) hpref[cnt] = carry;
+}
+
+template <typename RP>
+__device__ __forceinline__ void unit_of(const RP* __restrict__ rowptr, const uint32_t* hlist, const uint32_t* hpref,
+                                        uint32_t cnt, uint32_t u, uint32_t* li, int64_t* x, int64_t* b, int64_t* e) {
+  uint32_t lo = 0, hi = cnt - 1;  // the largest q with hpref[q] <= u
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) >> 1;
+    if (hpref[mid] <= u) lo = mid; else hi = mid - 1;
+  }
+  const int64_t r = hlist[lo];
+  const int64_t rb = (int64_t)rowptr[r], re = (int64_t)rowptr[r + 1];
+  *li = lo;
+  *x = r;
+  *b = rb + (int64_t)(u - hpref[lo]) * kRowChunk;
+  *e = min(re, *b + kRowChunk);
+}
 
 template <typename RP>
 __device__ __forceinline__ uint32_t check_entry(const RP* __restrict__ rowptr, const int32_t* __restrict__ colidx,
@@ -57,7 +102,7 @@ template <typename RP>
 __global__ __launch_bounds__(kThreads) void k_validate_lane(const RP* __restrict__ rowptr,
                                                             const int32_t* __restrict__ colidx, int64_t n, int64_t nnz,
                                                             int symmetric, uint32_t* err, uint32_t* list,
-                                                            uint32_t* nlist) {
+                                                            uint32_t* nlist, uint32_t* hlist, uint32_t* nhlist) {
   uint32_t e = 0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     if ((int64_t)rowptr[0] != 0 || (int64_t)rowptr[n] != nnz) e |= 8;
@@ -66,6 +111,10 @@ __global__ __launch_bounds__(kThreads) void k_validate_lane(const RP* __restrict
     const int64_t b = (int64_t)rowptr[x], en = (int64_t)rowptr[x + 1];
     if (b < 0 || en < b || en > nnz) {
       e |= 8;
+      continue;
+    }
+    if (en - b > kWaveRow) {
+      hlist[atomicAdd(nhlist, 1u)] = (uint32_t)x;
       continue;
     }
     if (en - b > kLaneRow) {
@@ -81,16 +130,26 @@ template <typename RP>
 __global__ __launch_bounds__(kThreads) void k_validate_wave(const RP* __restrict__ rowptr,
                                                             const int32_t* __restrict__ colidx, int64_t n, int64_t nnz,
                                                             int symmetric, uint32_t* err, const uint32_t* list,
-                                                            const uint32_t* nlist) {
+                                                            const uint32_t* nlist, const uint32_t* hlist,
+                                                            const uint32_t* nhlist, const uint32_t* hpref) {
   const int l = lane_id();
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
-  const int64_t cnt = *nlist;
   uint32_t e = 0;
+  const int64_t cnt = *nlist;
   for (int64_t r = wave; r < cnt; r += nwaves) {
     const int64_t x = list[r];
     const int64_t b = (int64_t)rowptr[x], en = (int64_t)rowptr[x + 1];
     for (int64_t q = b + l; q < en; q += kWave) e |= check_entry(rowptr, colidx, n, nnz, symmetric, x, b, q);
+  }
+  const uint32_t hcnt = *nhlist;
+  const uint32_t units = hcnt ? hpref[hcnt] : 0u;
+  for (uint32_t u = (uint32_t)wave; u < units; u += (uint32_t)nwaves) {
+    uint32_t li;
+    int64_t x, b, en;
+    unit_of(rowptr, hlist, hpref, hcnt, u, &li, &x, &b, &en);
+    const int64_t rb = (int64_t)rowptr[x];
+    for (int64_t q = b + l; q < en; q += kWave) e |= check_entry(rowptr, colidx, n, nnz, symmetric, x, rb, q);
   }
   if (e) atomicOr(err, e);
 }
@@ -236,11 +295,18 @@ template <typename RP>
 __global__ __launch_bounds__(kThreads) void k_degs_lane(const RP* __restrict__ rowptr,
                                                         const int32_t* __restrict__ colidx, int64_t n,
                                                         const int32_t* __restrict__ perm, uint32_t* __restrict__ od,
-                                                        uint32_t* __restrict__ idg, uint32_t* list, uint32_t* nlist) {
+                                                        uint32_t* __restrict__ idg, uint32_t* list, uint32_t* nlist,
+                                                        uint32_t* hlist, uint32_t* nhlist) {
   for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
     const int32_t r = perm[x];
     if (r < 0 || r >= n) continue;
     const int64_t b = (int64_t)rowptr[x], e = (int64_t)rowptr[x + 1];
+    if (e - b > kWaveRow) {
+      od[r] = 0;
+      idg[r] = 0;
+      hlist[atomicAdd(nhlist, 1u)] = (uint32_t)x;
+      continue;
+    }
     if (e - b > kLaneRow) {
       list[atomicAdd(nlist, 1u)] = (uint32_t)x;
       continue;
@@ -252,12 +318,15 @@ __global__ __launch_bounds__(kThreads) void k_degs_lane(const RP* __restrict__ r
   }
 }
 
+// Listed rows: one wavefront per row; huge rows: chunks counted by different
+// wavefronts and added to od/idg, which k_degs_lane zeroed for them.
 template <typename RP>
 __global__ __launch_bounds__(kThreads) void k_degs_wave(const RP* __restrict__ rowptr,
                                                         const int32_t* __restrict__ colidx,
                                                         const int32_t* __restrict__ perm, uint32_t* __restrict__ od,
                                                         uint32_t* __restrict__ idg, const uint32_t* list,
-                                                        const uint32_t* nlist) {
+                                                        const uint32_t* nlist, const uint32_t* hlist,
+                                                        const uint32_t* nhlist, const uint32_t* hpref) {
   const int l = lane_id();
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
@@ -269,12 +338,28 @@ __global__ __launch_bounds__(kThreads) void k_degs_wave(const RP* __restrict__ r
     uint32_t c = 0;
     for (int64_t base = b; base < e; base += kWave) {
       const int64_t q = base + l;
-      const bool up = q < e && perm[colidx[q]] > r;
-      c += (uint32_t)__popcll(ballot(up));
+      c += (uint32_t)__popcll(ballot(q < e && perm[colidx[q]] > r));
     }
     if (l == 0) {
       od[r] = c;
       idg[r] = (uint32_t)(e - b) - c;
+    }
+  }
+  const uint32_t hcnt = *nhlist;
+  const uint32_t units = hcnt ? hpref[hcnt] : 0u;
+  for (uint32_t u = (uint32_t)wave; u < units; u += (uint32_t)nwaves) {
+    uint32_t li;
+    int64_t x, b, e;
+    unit_of(rowptr, hlist, hpref, hcnt, u, &li, &x, &b, &e);
+    const int32_t r = perm[x];
+    uint32_t c = 0;
+    for (int64_t base = b; base < e; base += kWave) {
+      const int64_t q = base + l;
+      c += (uint32_t)__popcll(ballot(q < e && perm[colidx[q]] > r));
+    }
+    if (l == 0) {
+      atomicAdd(&od[r], c);
+      atomicAdd(&idg[r], (uint32_t)(e - b) - c);
     }
   }
 }
@@ -293,7 +378,7 @@ __global__ __launch_bounds__(kThreads) void k_fill_lane(const RP* __restrict__ r
     const int32_t r = perm[x];
     if (r < 0 || r >= n) continue;
     const int64_t b = (int64_t)rowptr[x], e = (int64_t)rowptr[x + 1];
-    if (e - b > kLaneRow) continue;  // handled by k_fill_wave
+    if (e - b > kLaneRow) continue;  // listed rows: k_fill_wave
     uint32_t po = orow[r], pi = irow[r];
     const uint32_t po_end = orow[r + 1], pi_end = irow[r + 1];
     for (int64_t q = b; q < e; ++q) {
@@ -309,6 +394,11 @@ __global__ __launch_bounds__(kThreads) void k_fill_lane(const RP* __restrict__ r
   }
 }
 
+// Listed rows: one wavefront per row (ballot compaction keeps input order).
+// Huge rows: chunks reserve their slots with atomics on per-row cursors
+// (cur_o/cur_i, zeroed, indexed by position in hlist), so the order inside
+// such a row depends on timing; every row is sorted afterwards, which makes
+// the result exact and deterministic.
 template <typename RP>
 __global__ __launch_bounds__(kThreads) void k_fill_wave(const RP* __restrict__ rowptr,
                                                         const int32_t* __restrict__ colidx,
@@ -316,7 +406,9 @@ __global__ __launch_bounds__(kThreads) void k_fill_wave(const RP* __restrict__ r
                                                         const uint32_t* __restrict__ orow,
                                                         const uint32_t* __restrict__ irow, int32_t* __restrict__ ocol,
                                                         int32_t* __restrict__ icol, const uint32_t* list,
-                                                        const uint32_t* nlist) {
+                                                        const uint32_t* nlist, const uint32_t* hlist,
+                                                        const uint32_t* nhlist, const uint32_t* hpref, uint32_t* cur_o,
+                                                        uint32_t* cur_i) {
   const int l = lane_id();
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
@@ -327,6 +419,40 @@ __global__ __launch_bounds__(kThreads) void k_fill_wave(const RP* __restrict__ r
     const int64_t b = (int64_t)rowptr[x], e = (int64_t)rowptr[x + 1];
     uint32_t po = orow[r], pi = irow[r];
     const uint32_t po_end = orow[r + 1], pi_end = irow[r + 1];
+    for (int64_t base = b; base < e; base += kWave) {
+      const int64_t q = base + l;
+      const int32_t ry = q < e ? perm[colidx[q]] : -1;
+      const bool up = ry > r;
+      const bool down = q < e && !up;
+      const uint64_t mu = ballot(up), md = ballot(down);
+      const uint32_t du = po + lanes_below(mu), dd = pi + lanes_below(md);
+      if (up && du < po_end) ocol[du] = ry;
+      if (down && dd < pi_end) icol[dd] = ry;
+      po += (uint32_t)__popcll(mu);
+      pi += (uint32_t)__popcll(md);
+    }
+  }
+  const uint32_t hcnt = *nhlist;
+  const uint32_t units = hcnt ? hpref[hcnt] : 0u;
+  for (uint32_t u = (uint32_t)wave; u < units; u += (uint32_t)nwaves) {
+    uint32_t li;
+    int64_t x, b, e;
+    unit_of(rowptr, hlist, hpref, hcnt, u, &li, &x, &b, &e);
+    const int32_t r = perm[x];
+    const uint32_t ob = orow[r], ib = irow[r];
+    const uint32_t po_end = orow[r + 1], pi_end = irow[r + 1];
+    uint32_t nu = 0;
+    for (int64_t base = b; base < e; base += kWave) {
+      const int64_t q = base + l;
+      nu += (uint32_t)__popcll(ballot(q < e && perm[colidx[q]] > r));
+    }
+    uint32_t po = 0, pi = 0;
+    if (l == 0) {
+      po = ob + atomicAdd(&cur_o[li], nu);
+      pi = ib + atomicAdd(&cur_i[li], (uint32_t)(e - b) - nu);
+    }
+    po = __shfl(po, 0, kWave);
+    pi = __shfl(pi, 0, kWave);
     for (int64_t base = b; base < e; base += kWave) {
       const int64_t q = base + l;
       const int32_t ry = q < e ? perm[colidx[q]] : -1;
@@ -666,18 +792,25 @@ __global__ __launch_bounds__(kThreads) void k_acol(BlockBuild bb) {
 
 // ------------------------------------------------------------ launchers
 hipError_t launch_validate(const void* rowptr, int rp64, const int32_t* colidx, int64_t n, int64_t nnz,
-                           int symmetric, uint32_t* err, uint32_t* list, uint32_t* nlist, hipStream_t s) {
+                           int symmetric, uint32_t* err, uint32_t* list, uint32_t* nlist, uint32_t* hlist,
+                           uint32_t* nhlist, uint32_t* hpref, hipStream_t s) {
   const unsigned g = grid_for((uint64_t)n, kThreads, 65536);
   if (rp64) {
     hipLaunchKernelGGL(k_validate_lane<int64_t>, dim3(g), dim3(kThreads), 0, s, (const int64_t*)rowptr, colidx, n, nnz,
-                       symmetric, err, list, nlist);
+                       symmetric, err, list, nlist, hlist, nhlist);
+    hipLaunchKernelGGL(k_hprefix<int64_t>, dim3(1), dim3(kThreads), 0, s, (const int64_t*)rowptr, (const uint32_t*)hlist,
+                       (const uint32_t*)nhlist, hpref);
     hipLaunchKernelGGL(k_validate_wave<int64_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int64_t*)rowptr, colidx,
-                       n, nnz, symmetric, err, (const uint32_t*)list, (const uint32_t*)nlist);
+                       n, nnz, symmetric, err, (const uint32_t*)list, (const uint32_t*)nlist, (const uint32_t*)hlist,
+                       (const uint32_t*)nhlist, (const uint32_t*)hpref);
   } else {
     hipLaunchKernelGGL(k_validate_lane<int32_t>, dim3(g), dim3(kThreads), 0, s, (const int32_t*)rowptr, colidx, n, nnz,
-                       symmetric, err, list, nlist);
+                       symmetric, err, list, nlist, hlist, nhlist);
+    hipLaunchKernelGGL(k_hprefix<int32_t>, dim3(1), dim3(kThreads), 0, s, (const int32_t*)rowptr, (const uint32_t*)hlist,
+                       (const uint32_t*)nhlist, hpref);
     hipLaunchKernelGGL(k_validate_wave<int32_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int32_t*)rowptr, colidx,
-                       n, nnz, symmetric, err, (const uint32_t*)list, (const uint32_t*)nlist);
+                       n, nnz, symmetric, err, (const uint32_t*)list, (const uint32_t*)nlist, (const uint32_t*)hlist,
+                       (const uint32_t*)nhlist, (const uint32_t*)hpref);
   }
   return hipGetLastError();
 }
@@ -740,38 +873,46 @@ hipError_t launch_perm(const uint64_t* keys, int64_t n, int idbits, int32_t* ord
 }
 
 hipError_t launch_degs(const void* rowptr, int rp64, const int32_t* colidx, int64_t n, const int32_t* perm,
-                       uint32_t* od, uint32_t* idg, uint32_t* list, uint32_t* nlist, hipStream_t s) {
+                       uint32_t* od, uint32_t* idg, uint32_t* list, uint32_t* nlist, uint32_t* hlist,
+                       uint32_t* nhlist, uint32_t* hpref, hipStream_t s) {
   if (n == 0) return hipSuccess;
   const unsigned g = grid_for((uint64_t)n, kThreads, 65536);
   if (rp64) {
     hipLaunchKernelGGL(k_degs_lane<int64_t>, dim3(g), dim3(kThreads), 0, s, (const int64_t*)rowptr, colidx, n, perm, od,
-                       idg, list, nlist);
+                       idg, list, nlist, hlist, nhlist);
+    hipLaunchKernelGGL(k_hprefix<int64_t>, dim3(1), dim3(kThreads), 0, s, (const int64_t*)rowptr, (const uint32_t*)hlist,
+                       (const uint32_t*)nhlist, hpref);
     hipLaunchKernelGGL(k_degs_wave<int64_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int64_t*)rowptr, colidx, perm,
-                       od, idg, (const uint32_t*)list, (const uint32_t*)nlist);
+                       od, idg, (const uint32_t*)list, (const uint32_t*)nlist, (const uint32_t*)hlist,
+                       (const uint32_t*)nhlist, (const uint32_t*)hpref);
   } else {
     hipLaunchKernelGGL(k_degs_lane<int32_t>, dim3(g), dim3(kThreads), 0, s, (const int32_t*)rowptr, colidx, n, perm, od,
-                       idg, list, nlist);
+                       idg, list, nlist, hlist, nhlist);
+    hipLaunchKernelGGL(k_hprefix<int32_t>, dim3(1), dim3(kThreads), 0, s, (const int32_t*)rowptr, (const uint32_t*)hlist,
+                       (const uint32_t*)nhlist, hpref);
     hipLaunchKernelGGL(k_degs_wave<int32_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int32_t*)rowptr, colidx, perm,
-                       od, idg, (const uint32_t*)list, (const uint32_t*)nlist);
+                       od, idg, (const uint32_t*)list, (const uint32_t*)nlist, (const uint32_t*)hlist,
+                       (const uint32_t*)nhlist, (const uint32_t*)hpref);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_fill(const void* rowptr, int rp64, const int32_t* colidx, int64_t n, const int32_t* perm,
                        const uint32_t* orow, const uint32_t* irow, int32_t* ocol, int32_t* icol, const uint32_t* list,
-                       const uint32_t* nlist, hipStream_t s) {
+                       const uint32_t* nlist, const uint32_t* hlist, const uint32_t* nhlist, const uint32_t* hpref,
+                       uint32_t* cur_o, uint32_t* cur_i, hipStream_t s) {
   if (n == 0) return hipSuccess;
   const unsigned g = grid_for((uint64_t)n, kThreads, 65536);
   if (rp64) {
     hipLaunchKernelGGL(k_fill_lane<int64_t>, dim3(g), dim3(kThreads), 0, s, (const int64_t*)rowptr, colidx, n, perm,
                        orow, irow, ocol, icol);
     hipLaunchKernelGGL(k_fill_wave<int64_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int64_t*)rowptr, colidx, perm,
-                       orow, irow, ocol, icol, list, nlist);
+                       orow, irow, ocol, icol, list, nlist, hlist, nhlist, hpref, cur_o, cur_i);
   } else {
     hipLaunchKernelGGL(k_fill_lane<int32_t>, dim3(g), dim3(kThreads), 0, s, (const int32_t*)rowptr, colidx, n, perm,
                        orow, irow, ocol, icol);
     hipLaunchKernelGGL(k_fill_wave<int32_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int32_t*)rowptr, colidx, perm,
-                       orow, irow, ocol, icol, list, nlist);
+                       orow, irow, ocol, icol, list, nlist, hlist, nhlist, hpref, cur_o, cur_i);
   }
   return hipGetLastError();
 }
