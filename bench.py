@@ -51,28 +51,37 @@ def timed(fn, reps, sync):
     return ts
 
 
+SERVING = {
+    # kind: (pool graphs, R-MAT scales, ER log10 n range, requests, warm-up requests)
+    "mix": (64, (12, 22), (4.0, 6.0), 400, 50),
+    "quick": (32, (10, 16), (4.0, 5.0), 600, 100),
+}
+
+
 def serving_pool(kind, seed=5):
-    """Seeded request pool: each entry (name, n, rowptr, colidx)."""
+    """Seeded request pool: half R-MAT (scale uniform in the range, edge factor
+    uniform in 8..32), half Erdos-Renyi (n log-uniform in the range, average
+    degree uniform in 8..64).  Graphs are generated on host threads."""
+    import concurrent.futures
+
     import numpy as np
 
     import graphgen
+    size, scales, nlog, _, _ = SERVING[kind]
     rng = np.random.default_rng(seed)
-    if kind == "full":
-        size, scales, nlog = 128, (12, 22), (4.0, 6.0)
-    else:
-        size, scales, nlog = 32, (10, 16), (4.0, 5.0)
-    pool = []
+    specs = []
     for q in range(size):
         if rng.integers(2) == 0:
-            s = int(rng.integers(scales[0], scales[1] + 1))
-            ef = int(rng.integers(8, 33))
-            g = graphgen.rmat(s, ef, 1000 + q)
+            specs.append(("rmat", int(rng.integers(scales[0], scales[1] + 1)), int(rng.integers(8, 33)), 1000 + q))
         else:
-            nn = int(10 ** rng.uniform(*nlog))
-            deg = int(rng.integers(8, 65))
-            g = graphgen.er_avgdeg(nn, deg, 1000 + q)
-        pool.append(g)
-    return pool
+            specs.append(("er", int(10 ** rng.uniform(*nlog)), int(rng.integers(8, 65)), 1000 + q))
+
+    def make(s):
+        kind_, a, b, sd = s
+        return graphgen.rmat(a, b, sd) if kind_ == "rmat" else graphgen.er_avgdeg(a, b, sd)
+
+    with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        return list(ex.map(make, specs))
 
 
 def serving_bench(kind):
@@ -84,26 +93,31 @@ def serving_bench(kind):
     import paper_2009_12457_amd as bb
     from paper_2009_12457_amd import serve
 
+    t_gen = time.perf_counter()
     pool = serving_pool(kind)
+    t_gen = time.perf_counter() - t_gen
+    _, _, _, nreq, warm = SERVING[kind]
     rng = np.random.default_rng(5)
-    nreq, warm = (2200, 200) if kind == "full" else (600, 100)
     gaps = rng.exponential(1.0 / 200.0, size=nreq)
     offs = np.cumsum(gaps) - gaps[0]
     pick = rng.integers(len(pool), size=nreq)
     trace = [(float(offs[r]), pool[pick[r]].n, pool[pick[r]].rowptr, pool[pick[r]].colidx) for r in range(nreq)]
     # each pool graph counted alone once (the reference for "same alone and in the mix")
     alone = {}
+    plan = None
     for q, g in enumerate(pool):
-        p = max(1, min(g.n, int(round(len(g.colidx) / max(g.n, 1)))))
-        plan = bb.bbtc_partition(g.n, g.rowptr, g.colidx, options=bb.bbtc_options_default(p=p), trusted=True)
+        plan = bb.bbtc_partition(g.n, g.rowptr, g.colidx, options=bb.bbtc_options_default(p=serve.default_p(
+            g.n, len(g.colidx))), trusted=True, plan=plan)
         _, tot = bb.bbtc_count(plan)
         torch.cuda.synchronize()
         alone[q] = int(tot.item())
-        plan.destroy()
+    plan.destroy()
+    sizes = np.array([len(g.colidx) // 2 for g in pool])
     edges = sum(len(t[3]) // 2 for t in trace[warm:])
-    out = {"pool": kind, "pool_graphs": len(pool), "requests": nreq - warm, "warmup": warm, "rate_per_s": 200,
-           "mean_edges_per_request": edges / (nreq - warm)}
-    srv = serve.Server(hbm_budget_bytes=64 << 30, compute_streams=2)
+    out = {"pool": kind, "pool_graphs": len(pool), "pool_edges_min": int(sizes.min()),
+           "pool_edges_max": int(sizes.max()), "pool_generation_s": round(t_gen, 2), "requests": nreq - warm,
+           "warmup": warm, "rate_per_s": 200, "mean_edges_per_request": edges / (nreq - warm)}
+    srv = serve.Server(hbm_budget_bytes=64 << 30, compute_streams=2, partition_workers=3)
     t0 = time.perf_counter()
     try:
         res = serve.run_trace(srv, trace)
@@ -114,13 +128,16 @@ def serving_bench(kind):
         if r.total != alone[int(q)]:
             raise SystemExit(f"served result differs from the alone count for pool graph {int(q)}")
     out["batched"] = dict(serve.latency_summary(res, warm), edges_per_s=edges / span, launches=srv.launches,
+                          plans_created=srv.plans_created, plans_released=srv.pool.released,
                           wall_s=time.perf_counter() - t0)
+    t0 = time.perf_counter()
     res_p = serve.serve_plain(trace)
     span_p = max(r.done for r in res_p[warm:]) - min(r.arrival for r in res_p[warm:])
     for r, q in zip(res_p, pick):
         if r.total != alone[int(q)]:
             raise SystemExit(f"plain result differs from the alone count for pool graph {int(q)}")
-    out["plain"] = dict(serve.latency_summary(res_p, warm), edges_per_s=edges / span_p)
+    out["plain"] = dict(serve.latency_summary(res_p, warm), edges_per_s=edges / span_p,
+                        wall_s=time.perf_counter() - t0)
     return out
 
 
@@ -134,9 +151,9 @@ def main():
     ap.add_argument("--profile-only", action="store_true", help="only the timed steps (for rocprofv3 runs)")
     ap.add_argument("--autotune", choices=["auto", "on", "off"], default="auto",
                     help="pick p and the row-mapping knobs with bbtc_autotune (auto: on for the 2^24 workloads)")
-    ap.add_argument("--serving", choices=["quick", "full", "off"], default="quick",
-                    help="serving measurement: quick (small pool, 600 requests), full (the 128-graph pool of "
-                         "R-MAT scale 12-22 / ER 1e4-1e6, 2000 requests after 200 warm-up) or off")
+    ap.add_argument("--serving", choices=["mix", "quick", "off"], default="mix",
+                    help="serving measurement: mix (64-graph pool of R-MAT scale 12-22 / ER n=1e4-1e6, 400 "
+                         "requests after 50 warm-up), quick (small graphs) or off")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run 10 plain device-to-device copies of BYTES bytes (counter calibration)")
     args = ap.parse_args()

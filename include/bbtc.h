@@ -82,9 +82,11 @@ typedef struct bbtc_csr {
  * triangle exactly once.  Zero selects the library default.
  *   p             blocks per side, 1 <= p <= min(n, 2048); 0 = p from the
  *                 average degree (Sec. 7.2 suggests p near the average degree).
- *   wave_min      a column v of G_ij whose in-neighbours in V_i plus |N(G_jk,v)|
- *                 reach wave_min is processed by a whole 64-lane wavefront;
- *                 smaller ones by one lane each.
+ *   wave_min      a column v of G_ij whose list N(G_jk,v) has at least
+ *                 wave_min entries (capped at 4096) is staged alone and
+ *                 probed by a whole 64-lane wavefront; shorter lists of the
+ *                 columns a workgroup holds are staged together, sorted, and
+ *                 probed by binary search by all its lanes.
  *   hash_min      wavefront columns with |N(G_jk,v)| >= hash_min stage it as an
  *                 LDS bitmap over V_k or an LDS hash (the HMap form); shorter
  *                 ones as a sorted LDS copy probed by binary search (the
@@ -188,7 +190,7 @@ bbtc_status bbtc_count_multi(bbtc_plan* const* plans, int32_t nplans, void* stre
  * one warm-up) by coordinate descent: first p over {p0/4, p0/2, p0, 2*p0}
  * (p0 = base->p, or the average degree when base->p is 0: Sec. 7.2 of the
  * paper suggests p near the average degree), then wave_min over
- * {2, 8, 32, 128}, then hash_min over {-1, 1, 32, 256}.  The other fields of
+ * {64, 256, 1024, 4096}, then hash_min over {-1, 1, 32, 256}.  The other fields of
  * *base are kept.  Every candidate gives identical counts; only time differs.
  * On success *out holds the chosen options and *best_ms (if not NULL) the
  * count time with them.  Synchronises `stream`.

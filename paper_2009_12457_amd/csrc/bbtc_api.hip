@@ -94,6 +94,7 @@ struct bbtc_plan {
   DevBuf<unsigned long long> bnnz, bnzr, bnzc;
   DevBuf<DevTask> tasks;
   DevBuf<DevItem> items;
+  DevBuf<DevItem> xitems;          // the same items as per-XCD queues (persistent launches)
   DevBuf<HeavyCol> heavy;
   // host
   std::vector<int32_t> h_cuts;
@@ -102,6 +103,8 @@ struct bbtc_plan {
   std::vector<DevTask> h_dtasks;   // same order
   std::vector<int32_t> h_work;     // plan-order indices of WORK tasks
   std::vector<DevItem> h_items;
+  std::vector<DevItem> h_xitems;   // queue x = h_xitems[qbeg[x], qbeg[x] + qlen[x])
+  uint32_t nq = 1, qbeg[kMaxQueues] = {0}, qlen[kMaxQueues] = {0};
   std::vector<HeavyCol> h_heavy;   // hub columns, sorted by (block, column)
   std::vector<int64_t> h_hub_first, h_hub_count;  // per plan-order task: its range of work items
   uint32_t split = 0;              // in-slice length above which a column is a hub
@@ -175,7 +178,7 @@ struct bbtc_plan {
     hugerows.release();
     bot.release(); tbot.release(); ccnt.release(); ccoff.release(); dmax.release(); cursor.release();
     err.release(); ccbase.release(); botp.release(); tbotp.release(); acp.release(); bnnz.release();
-    bnzr.release(); bnzc.release(); tasks.release(); items.release(); heavy.release();
+    bnzr.release(); bnzc.release(); tasks.release(); items.release(); xitems.release(); heavy.release();
   }
 
   size_t footprint() const {
@@ -185,7 +188,7 @@ struct bbtc_plan {
            hugerows.bytes() + bot.bytes() +
            tbot.bytes() + ccnt.bytes() + ccoff.bytes() + dmax.bytes() + cursor.bytes() + err.bytes() +
            ccbase.bytes() + botp.bytes() + tbotp.bytes() + acp.bytes() + bnnz.bytes() + bnzr.bytes() +
-           bnzc.bytes() + tasks.bytes() + items.bytes() + heavy.bytes() + cache.bytes();
+           bnzc.bytes() + tasks.bytes() + items.bytes() + xitems.bytes() + heavy.bytes() + cache.bytes();
   }
 };
 
@@ -260,7 +263,7 @@ void fill_defaults(bbtc_options* o) {
   o->cut_mode = BBTC_CUT_BALANCED;
 }
 
-constexpr int kDefaultWaveMin = 16;
+constexpr int kDefaultWaveMin = 64;
 constexpr int kDefaultHashMin = 16;
 constexpr int kDefaultItemRows = 256;
 constexpr uint32_t kHubSplit = 512;   // in-slice length above which a column is split
@@ -371,6 +374,67 @@ void compose_tasks(bbtc_plan* pl) {
   }
 }
 
+// The persistent launch walks the same work items as kMaxQueues queues, one
+// per XCD (each XCD has its own L2).  The probes of task (i,j,k) gather rows
+// of G_ik, so the tasks sharing (i,k) stay on one XCD and run back to back
+// there: groups go, heaviest first, to the least loaded queue.  A task heavier
+// than half a queue's fair share has its items dealt over all queues instead.
+// Workgroups drain their own XCD's queue and then help the others, so the
+// split changes only locality, never what is counted.
+void compose_queues(bbtc_plan* pl) {
+  const int X = kMaxQueues;
+  const int64_t p = pl->p;
+  double total = 0;
+  for (int32_t q : pl->h_work) total += pl->h_tasks[q].est;
+  const double fair = total / X;
+  std::vector<std::vector<DevItem>> qs(X);
+  std::vector<double> load(X, 0.0);
+  auto least = [&]() { return (int)(std::min_element(load.begin(), load.end()) - load.begin()); };
+  std::vector<std::vector<int32_t>> grp((size_t)(p * (p + 1) / 2));
+  std::vector<double> gload(grp.size(), 0.0);
+  for (int32_t q : pl->h_work) {  // plan order: heaviest first
+    const bbtc_task& t = pl->h_tasks[q];
+    const int64_t f = pl->h_hub_first[q], c = pl->h_hub_count[q];
+    if (t.est > fair / 2 && c > 1) {
+      const double w = t.est / (double)c;
+      for (int64_t r = 0; r < c; ++r) {
+        const int x = least();
+        qs[x].push_back(pl->h_items[f + r]);
+        load[x] += w;
+      }
+    } else {
+      const int64_t g = block_id(p, t.i, t.k);
+      grp[g].push_back(q);
+      gload[g] += t.est;
+    }
+  }
+  std::vector<int64_t> gs;
+  for (size_t g = 0; g < grp.size(); ++g)
+    if (!grp[g].empty()) gs.push_back((int64_t)g);
+  std::stable_sort(gs.begin(), gs.end(), [&](int64_t a, int64_t b) { return gload[a] > gload[b]; });
+  for (int64_t g : gs) {
+    const int x = least();
+    for (int32_t q : grp[g])
+      for (int64_t r = 0; r < pl->h_hub_count[q]; ++r) qs[x].push_back(pl->h_items[pl->h_hub_first[q] + r]);
+    load[x] += gload[g];
+  }
+  pl->h_xitems.clear();
+  pl->h_xitems.reserve(pl->h_items.size());
+  pl->nq = X;
+  for (int x = 0; x < X; ++x) {
+    pl->qbeg[x] = (uint32_t)pl->h_xitems.size();
+    pl->qlen[x] = (uint32_t)qs[x].size();
+    pl->h_xitems.insert(pl->h_xitems.end(), qs[x].begin(), qs[x].end());
+  }
+}
+
+// A launch over items[0, nitems) as a single queue.
+void one_queue(CountParams& cp) {
+  cp.nq = 1;
+  for (int x = 0; x < kMaxQueues; ++x) cp.qbeg[x] = cp.qlen[x] = 0;
+  cp.qlen[0] = cp.nitems;
+}
+
 // ------------------------------------------------------------ streaming
 // The count phase needs, for the tasks of block pair (i,j), only three row
 // stripes: the out-rows of V_i and of V_j with their block boundaries, and
@@ -389,10 +453,15 @@ bbtc_status to_pinned(T** dst, const T* src, size_t n, hipStream_t s) {
 
 size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
+// An out-stripe starts (ocut & 3) words into its slot, so that positions that
+// are multiples of 4 in the whole oriented CSR stay 16-byte aligned (the
+// counting kernels read out-rows in aligned 16-byte blocks).
+size_t out_head(const bbtc_plan* pl, int a) { return (size_t)(pl->ocut[a] & 3); }
+
 size_t stripe_bytes(const bbtc_plan* pl, int key) {
   const int a = key >> 1;
   if ((key & 1) == 0)
-    return align16(4 * (pl->ocut[a + 1] - pl->ocut[a])) + 4 * (pl->h_botp[a + 1] - pl->h_botp[a]);
+    return align16(4 * (out_head(pl, a) + pl->ocut[a + 1] - pl->ocut[a])) + 4 * (pl->h_botp[a + 1] - pl->h_botp[a]);
   return align16(4 * (pl->icut[a + 1] - pl->icut[a])) + 4 * (pl->h_tbotp[a + 1] - pl->h_tbotp[a]);
 }
 
@@ -510,9 +579,11 @@ int stripe_slot(bbtc_plan* pl, int key, const std::vector<int>& keep, hipStream_
   if (e == hipSuccess) {
     if ((key & 1) == 0) {
       const size_t nc = pl->ocut[a + 1] - pl->ocut[a], nb = pl->h_botp[a + 1] - pl->h_botp[a];
-      if (nc) e = hipMemcpyAsync(base, pl->h_ocol + pl->ocut[a], 4 * nc, hipMemcpyHostToDevice, cs);
+      const size_t hd = out_head(pl, a);
+      if (nc) e = hipMemcpyAsync(base + 4 * hd, pl->h_ocol + pl->ocut[a], 4 * nc, hipMemcpyHostToDevice, cs);
       if (e == hipSuccess && nb)
-        e = hipMemcpyAsync(base + align16(4 * nc), pl->h_bot + pl->h_botp[a], 4 * nb, hipMemcpyHostToDevice, cs);
+        e = hipMemcpyAsync(base + align16(4 * (hd + nc)), pl->h_bot + pl->h_botp[a], 4 * nb, hipMemcpyHostToDevice,
+                           cs);
     } else {
       const size_t nc = pl->icut[a + 1] - pl->icut[a], nb = pl->h_tbotp[a + 1] - pl->h_tbotp[a];
       if (nc) e = hipMemcpyAsync(base, pl->h_icol + pl->icut[a], 4 * nc, hipMemcpyHostToDevice, cs);
@@ -572,15 +643,17 @@ bbtc_status count_streamed(bbtc_plan* pl, hipStream_t s, uint64_t* d_per_task, u
     const size_t nci = pl->ocut[i + 1] - pl->ocut[i], ncj = pl->ocut[j + 1] - pl->ocut[j];
     const size_t nij = pl->icut[j + 1] - pl->icut[j];
     // shifted so that absolute positions index the cached stripe
-    cp.one.g.colI = (const int32_t*)base(0) - pl->ocut[i];
-    cp.one.g.botI = (const uint32_t*)(base(0) + align16(4 * nci));
-    cp.one.g.colJ = (const int32_t*)base(1) - pl->ocut[j];
-    cp.one.g.botJ = (const uint32_t*)(base(1) + align16(4 * ncj));
+    const size_t hi = out_head(pl, i), hj = out_head(pl, j);
+    cp.one.g.colI = (const int32_t*)base(0) + hi - pl->ocut[i];
+    cp.one.g.botI = (const uint32_t*)(base(0) + align16(4 * (hi + nci)));
+    cp.one.g.colJ = (const int32_t*)base(1) + hj - pl->ocut[j];
+    cp.one.g.botJ = (const uint32_t*)(base(1) + align16(4 * (hj + ncj)));
     cp.one.g.icolJ = (const int32_t*)base(2) - pl->icut[j];
     cp.one.g.tbotJ = (const uint32_t*)(base(2) + align16(4 * nij));
     cp.items = pl->items.ptr + pl->group_first[g];
     cp.nitems = (uint32_t)pl->group_count[g];
     cp.cursor = pl->cursor.ptr;
+    one_queue(cp);
     HIP_TRY(launch_reset(nullptr, 0, nullptr, pl->cursor.ptr, s), "cursor");  // cursor only
     const int grid = (int)std::min<int64_t>(grid_max, (int64_t)cp.nitems);
     HIP_TRY(launch_count_persistent(cp, grid, false, s), "count");
@@ -706,7 +779,8 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   const uint64_t m = mm[0];
   if (m > mmax || mm[1] != mm[0]) return fail(BBTC_EINVAL, "input is not symmetric");
   pl->m = (int64_t)m;
-  HIP_TRY(pl->ocol.ensure((size_t)m), "alloc ocol");
+  // + 4: the counting kernels read out-rows in aligned 16-byte blocks
+  HIP_TRY(pl->ocol.ensure((size_t)m + 4), "alloc ocol");
   HIP_TRY(pl->icol.ensure((size_t)m), "alloc icol");
   // od/idg are consumed (scanned): reuse them as the huge rows' fill cursors
   HIP_TRY(hipMemsetAsync(pl->od.ptr, 0, sizeof(uint32_t) * n, s), "memset");
@@ -721,10 +795,6 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   HIP_TRY(launch_segsort(pl->orow.ptr, pl->ocol.ptr, n, pl->idbits, pl->longrows.ptr, pl->hugerows.ptr, pl->err.ptr,
                          pl->acol.ptr, s),
           "sort out-rows");
-  HIP_TRY(hipMemsetAsync(pl->err.ptr, 0, 8, s), "memset");
-  HIP_TRY(launch_segsort(pl->irow.ptr, pl->icol.ptr, n, pl->idbits, pl->longrows.ptr, pl->hugerows.ptr, pl->err.ptr,
-                         pl->acol.ptr, s),
-          "sort in-rows");
 
   // ---- cut vector (Sec. 4.1) ----
   int32_t p = opt.p;
@@ -737,6 +807,11 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   pl->opt.p = p;
   HIP_TRY(pl->cuts.ensure((size_t)p + 1), "alloc cuts");
   HIP_TRY(launch_cuts(pl->orow.ptr, n, p, opt.cut_mode, pl->cuts.ptr, s), "cuts");
+  // in-rows: grouped by the part of each in-neighbour (all the counting needs)
+  HIP_TRY(hipMemsetAsync(pl->err.ptr, 0, 8, s), "memset");
+  HIP_TRY(launch_inrows(pl->irow.ptr, pl->icol.ptr, n, pl->longrows.ptr, pl->hugerows.ptr, pl->err.ptr, pl->acol.ptr,
+                        pl->cuts.ptr, p, s),
+          "group in-rows");
   pl->h_cuts.assign((size_t)p + 1, 0);
   HIP_TRY(hipMemcpyAsync(pl->h_cuts.data(), pl->cuts.ptr, sizeof(int32_t) * (p + 1), hipMemcpyDeviceToHost, s),
           "D2H cuts");
@@ -847,17 +922,23 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   acp[0] = 0;
   for (int64_t b = 0; b < nb; ++b) acp[b + 1] = acp[b] + (uint64_t)pl->h_nzc[b];
   compose_tasks(pl);
+  compose_queues(pl);
   const int64_t nt = (int64_t)pl->h_tasks.size();
   HIP_TRY(pl->acp.ensure((size_t)nb + 1), "alloc");
   HIP_TRY(pl->tasks.ensure((size_t)nt), "alloc tasks");
   HIP_TRY(pl->items.ensure(pl->h_items.size()), "alloc items");
-  HIP_TRY(pl->cursor.ensure(1), "alloc");
+  HIP_TRY(pl->xitems.ensure(pl->h_xitems.size()), "alloc items");
+  HIP_TRY(pl->cursor.ensure(kMaxQueues), "alloc");
   HIP_TRY(hipMemcpyAsync(pl->acp.ptr, acp.data(), sizeof(uint64_t) * (nb + 1), hipMemcpyHostToDevice, s), "H2D");
   HIP_TRY(hipMemcpyAsync(pl->tasks.ptr, pl->h_dtasks.data(), sizeof(DevTask) * nt, hipMemcpyHostToDevice, s), "H2D");
-  if (!pl->h_items.empty())
+  if (!pl->h_items.empty()) {
     HIP_TRY(hipMemcpyAsync(pl->items.ptr, pl->h_items.data(), sizeof(DevItem) * pl->h_items.size(),
                            hipMemcpyHostToDevice, s),
             "H2D");
+    HIP_TRY(hipMemcpyAsync(pl->xitems.ptr, pl->h_xitems.data(), sizeof(DevItem) * pl->h_xitems.size(),
+                           hipMemcpyHostToDevice, s),
+            "H2D");
+  }
   HIP_TRY(hipStreamSynchronize(s), "sync");
 
   // ---- statistics (Sec. 4.4 quantities and the byte model) ----
@@ -957,7 +1038,7 @@ bbtc_status count_multi_impl(bbtc_plan* const* plans, int32_t nplans, hipStream_
   }
   HIP_TRY(S.ctxs.ensure((size_t)nplans), "alloc");
   HIP_TRY(S.items.ensure(std::max<size_t>(nitems, 1)), "alloc");
-  HIP_TRY(S.cursor.ensure(1), "alloc");
+  HIP_TRY(S.cursor.ensure(kMaxQueues), "alloc");
   HIP_TRY(hipMemcpyAsync(S.ctxs.ptr, S.h_ctx, sizeof(PlanCtx) * nplans, hipMemcpyHostToDevice, s), "H2D");
   if (nitems) HIP_TRY(hipMemcpyAsync(S.items.ptr, S.h_items, sizeof(DevItem) * nitems, hipMemcpyHostToDevice, s), "H2D");
   HIP_TRY(launch_reset_multi(S.ctxs.ptr, nplans, S.cursor.ptr, s), "reset");
@@ -968,6 +1049,7 @@ bbtc_status count_multi_impl(bbtc_plan* const* plans, int32_t nplans, hipStream_
     cp.items = S.items.ptr;
     cp.nitems = (uint32_t)nitems;
     cp.cursor = S.cursor.ptr;
+    one_queue(cp);
     const int ncu = plans[0]->ncu, bpc = plans[0]->blocks_per_cu;
     int grid = (int)std::min<int64_t>((int64_t)bpc * ncu, (int64_t)nitems);
     HIP_TRY(launch_count_persistent(cp, grid, true, s), "count");
@@ -1025,8 +1107,15 @@ bbtc_status bbtc_count(bbtc_plan* pl, void* stream, uint64_t* d_per_task, uint64
   cp.items = pl->items.ptr;
   cp.nitems = (uint32_t)pl->h_items.size();
   cp.cursor = pl->cursor.ptr;
+  one_queue(cp);
   if (pl->opt.mode == BBTC_MODE_PERSISTENT) {
     if (cp.nitems == 0) return BBTC_OK;
+    cp.items = pl->xitems.ptr;
+    cp.nq = pl->nq;
+    for (int x = 0; x < kMaxQueues; ++x) {
+      cp.qbeg[x] = pl->qbeg[x];
+      cp.qlen[x] = pl->qlen[x];
+    }
     int grid = pl->opt.grid > 0 ? pl->opt.grid : pl->blocks_per_cu * pl->ncu;
     grid = (int)std::min<int64_t>(grid, (int64_t)cp.nitems);
     if (pl->opt.graph == -1) {
@@ -1154,7 +1243,7 @@ bbtc_status bbtc_autotune(const bbtc_csr* g, const bbtc_options* base, int32_t r
       if (st != BBTC_OK) break;
       if (ms < best) { best = ms; best_opt = o; }
     }
-    for (int32_t wm : {2, 8, 32, 128}) {
+    for (int32_t wm : {64, 256, 1024, 4096}) {
       if (st != BBTC_OK) break;
       bbtc_options o = best_opt;
       o.wave_min = wm;

@@ -94,12 +94,19 @@ struct PlanCtx {
   int32_t pad;
 };
 
+// Work queues of a persistent launch: one per XCD (8 on MI355X, each with its
+// own L2); a workgroup drains the queue of its own XCD first, then the others.
+constexpr int kMaxQueues = 8;
+
 struct CountParams {
   PlanCtx one;            // the plan of a single-plan launch
   const PlanCtx* many;    // device array, indexed by DevItem::plan (multi-plan launch)
   const DevItem* items;
   uint32_t nitems;
-  uint32_t* cursor;
+  uint32_t* cursor;       // kMaxQueues claim counters, zeroed by the reset kernels
+  uint32_t nq;            // queues in use, 1..kMaxQueues
+  uint32_t qbeg[kMaxQueues];  // queue x = items[qbeg[x], qbeg[x] + qlen[x])
+  uint32_t qlen[kMaxQueues];
 };
 
 __host__ __device__ inline int64_t block_id(int64_t p, int64_t a, int64_t b) {
@@ -138,6 +145,10 @@ hipError_t launch_fill(const void* rowptr, int rp64, const int32_t* colidx, int6
 // scratch needs rp[nrows] entries.
 hipError_t launch_segsort(const uint32_t* rp, int32_t* col, int64_t nrows, int bits, uint32_t* longrows,
                           uint32_t* hugerows, uint32_t* q, int32_t* scratch, hipStream_t s);
+// In-rows grouped by part (short rows fully sorted, long ones by a counting
+// pass over the parts of cuts[0..p]).
+hipError_t launch_inrows(const uint32_t* rp, int32_t* col, int64_t nrows, uint32_t* longrows, uint32_t* hugerows,
+                         uint32_t* q, int32_t* scratch, const int32_t* cuts, int32_t p, hipStream_t s);
 hipError_t launch_cuts(const uint32_t* orow, int64_t n, int32_t p, int mode, int32_t* cuts, hipStream_t s);
 
 struct BlockBuild {

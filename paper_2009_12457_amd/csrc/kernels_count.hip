@@ -8,15 +8,19 @@
 // short lists N(G_ik,u) of all of v's in-neighbours u in V_i.
 //
 // Three mappings (tuning knobs; all exact):
-//   * light columns (|in_i(v)| + |N(G_jk,v)| < wave_min): one lane per v, a
-//     two-pointer count of the sorted lists (Alg. 1) for each in-neighbour u;
-//   * medium columns: one 64-lane wavefront per v; N(G_jk,v) is staged in LDS
-//     and the lanes share the probes of all in-neighbours u (segments of
-//     kSeg entries of the N(G_ik,u), handed out by a wavefront prefix sum);
+//   * short columns (|N(G_jk,v)| < wave_min): the columns of one pass of the
+//     workgroup are packed into windows; a window's lists are copied, sorted,
+//     into one workgroup-wide LDS stage, and the probes of all in-neighbours
+//     of all its columns are flattened over the 256 threads (segments of kSeg
+//     entries, owners found by binary search over LDS prefix arrays), each a
+//     binary search in its own column's piece of the stage;
+//   * long columns: one 64-lane wavefront per v stages N(G_jk,v) alone and
+//     the lanes share the probes of all in-neighbours u (the same segments,
+//     handed out by a wavefront prefix sum);
 //   * hub columns (in-slice longer than `split`): the host cuts the in-slice
 //     into chunks that are separate work items; a whole workgroup stages
 //     N(G_jk,v) once and its four wavefronts share the chunk's in-neighbours.
-// The stage is either the Intersect form (a sorted LDS copy, binary search)
+// A column's own stage is either the Intersect form// The stage is either the Intersect form (a sorted LDS copy, binary search)
 // or the HMap form (a dense LDS bitmap over the columns of V_k -- the paper's
 // dense hash map of the block's column range -- or, when V_k is too wide for
 // LDS, an open-addressing LDS hash).  Lists longer than the LDS buffer are
@@ -30,7 +34,7 @@ namespace bbtc {
 namespace {
 
 #ifndef BBTC_STAGE_WORDS
-#define BBTC_STAGE_WORDS 1024
+#define BBTC_STAGE_WORDS 512
 #endif
 constexpr int kABuf = BBTC_STAGE_WORDS;       // LDS words per wavefront
 constexpr uint32_t kBitmapBits = kABuf * 32;  // bitmap capacity in columns
@@ -38,14 +42,59 @@ constexpr int log2i(int x) { return x <= 1 ? 0 : 1 + log2i(x / 2); }
 constexpr int kHashBits = log2i(kABuf);       // kABuf hash slots
 static_assert((1 << kHashBits) == kABuf, "stage size must be a power of two");
 
-constexpr uint32_t kSeg = 4;  // probes per flattened work unit
+// Probes per flattened work unit: one 16-byte aligned block of an out-row,
+// read by a single 128-bit load (the blocks of N(G_ik,u) are aligned on the
+// absolute positions of the oriented CSR, whose base is 16-byte aligned).
+constexpr uint32_t kSeg = 4;
+
+// Segments covering the aligned blocks of col[a0, a1).
+__device__ __forceinline__ uint32_t seg_count(uint32_t a0, uint32_t a1) {
+  return a1 > a0 ? (a1 - (a0 & ~(kSeg - 1)) + kSeg - 1) / kSeg : 0u;
+}
+
+// Segment q of col[a0, a1): entries whose position is outside [a0, a1) come
+// back as 0xFFFFFFFF, above every vertex id.
+__device__ __forceinline__ void load_seg(const int32_t* __restrict__ col, uint32_t a0, uint32_t a1, uint32_t q,
+                                         uint32_t w[kSeg]) {
+  const uint32_t s0 = (a0 & ~(kSeg - 1)) + q * kSeg;
+  const int4 v = *reinterpret_cast<const int4*>(col + s0);
+  w[0] = (uint32_t)v.x;
+  w[1] = (uint32_t)v.y;
+  w[2] = (uint32_t)v.z;
+  w[3] = (uint32_t)v.w;
+#pragma unroll
+  for (uint32_t x = 0; x < kSeg; ++x)
+    if (s0 + x < a0 || s0 + x >= a1) w[x] = 0xFFFFFFFFu;
+}
+
+constexpr uint32_t kShareCap = 4 * kABuf;  // words of the workgroup-wide stage
+
+struct WaveScratch {        // per wave: one batch of 64 in-neighbours
+  uint32_t sa0[4][kWave];   // start of N(G_ik,u)
+  uint32_t sa1[4][kWave];   // end of N(G_ik,u)
+  uint32_t sex[4][kWave];   // exclusive prefix of the segment counts
+};
+struct ShareScratch {       // whole workgroup: one chunk of 256 in-neighbours
+  uint32_t a0[kThreads];    // start of N(G_ik,u)
+  uint32_t a1[kThreads];    // end of N(G_ik,u)
+  uint32_t col[kThreads];   // short column (index into the packed list) of u
+  uint32_t ex[kThreads];    // exclusive prefix of the segment counts
+};
 
 struct CountLds {
-  uint32_t abuf[4][kABuf];  // per wave: sorted copy / bitmap / hash; all-zero between uses
-  uint32_t sa0[4][kWave];   // per wave: start of N(G_ik,u) for the batch's lanes
-  uint32_t sa1[4][kWave];   // per wave: end of N(G_ik,u)
-  uint32_t sex[4][kWave];   // per wave: exclusive prefix of the batch's segment counts
-  uint32_t q[kThreads][4];  // medium-column queue: i0, i1, c0, c1
+  union {
+    uint32_t abuf[4][kABuf];       // per wave: sorted copy / bitmap / hash of one list
+    uint32_t sbuf[kShareCap];      // workgroup: sorted lists of a window of short columns
+  };                               // all-zero between uses
+  union {
+    WaveScratch w;
+    ShareScratch b;
+  };
+  uint32_t c0s[kThreads];          // short columns of a pass, packed: start of N(G_jk,v)
+  uint32_t i0s[kThreads];          // start of the in-slice
+  uint32_t soff[kThreads + 1];     // exclusive prefix of list lengths
+  uint32_t ioff[kThreads + 1];     // exclusive prefix of in-slice lengths
+  uint32_t q[kThreads];            // long columns of a pass (active-column index)
   uint32_t qn;
   uint32_t item;
   unsigned long long red[4];
@@ -96,38 +145,17 @@ __device__ __forceinline__ TaskCtx make_ctx(const GraphView& g, const DevTask& t
   return c;
 }
 
-// |N(G_ik,u) cap N(G_jk,v)| summed over the in-neighbours u of v in V_i, one lane.
-__device__ __forceinline__ uint64_t light_col(const TaskCtx& c, uint32_t i0, uint32_t i1, uint32_t c0, uint32_t c1) {
-  const int32_t* __restrict__ acol = c.coli;
-  const int32_t* __restrict__ ccol = c.colj;
-  uint64_t cnt = 0;
-  for (uint32_t e = i0; e < i1; ++e) {
-    const int32_t u = c.icolj[e];
-    const uint32_t* ur = c.boti + (uint64_t)(u - c.ci) * c.stri;
-    uint32_t a = ur[c.dk];
-    const uint32_t ae = ur[c.dk + 1];
-    if (a >= ae) continue;
-    uint32_t b = c0;
-    int32_t x = acol[a], y = ccol[b];
-    while (true) {
-      if (x == y) {
-        ++cnt;
-        if (++a >= ae || ++b >= c1) break;
-        x = acol[a];
-        y = ccol[b];
-      } else if (x < y) {
-        if (++a >= ae) break;
-        x = acol[a];
-      } else {
-        if (++b >= c1) break;
-        y = ccol[b];
-      }
-    }
-  }
-  return cnt;
-}
-
 __device__ __forceinline__ uint32_t hash_slot(uint32_t w) { return (w * 0x9E3779B1u) >> (32 - kHashBits); }
+
+// Largest k in [a, b) with off[k] <= x (off non-decreasing, off[a] <= x).
+__device__ __forceinline__ uint32_t owner_of(const uint32_t* off, uint32_t a, uint32_t b, uint32_t x) {
+  uint32_t lo = a, hi = b - 1;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= x) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
 
 // How a stage of N(G_jk,v) is held: 0 sorted copy, 1 bitmap over V_k, 2 hash.
 struct Stage {
@@ -217,7 +245,7 @@ __device__ uint64_t probe_flat(const TaskCtx& c, uint32_t i0, uint32_t i1, const
       a0 = ur[c.dk];
       a1 = ur[c.dk + 1];
     }
-    const uint32_t nseg = (a1 - a0 + kSeg - 1) / kSeg;
+    const uint32_t nseg = seg_count(a0, a1);
     const uint32_t inc = wave_incl_scan_u32(nseg);
     const uint32_t tot = __shfl(inc, kWave - 1, kWave);
     sa0[l] = a0;
@@ -227,19 +255,12 @@ __device__ uint64_t probe_flat(const TaskCtx& c, uint32_t i0, uint32_t i1, const
     for (uint32_t qb = 0; qb < tot; qb += kWave) {
       const uint32_t q = qb + l;
       if (q < tot) {
-        int lo = 0, hi = kWave - 1;  // owner: the largest lane o with sex[o] <= q
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (sex[mid] <= q) lo = mid; else hi = mid - 1;
-        }
-        const uint32_t s0 = sa0[lo] + (q - sex[lo]) * kSeg;
-        const uint32_t s1 = min(s0 + kSeg, sa1[lo]);
-        int32_t w[kSeg];
-#pragma unroll
-        for (uint32_t t = 0; t < kSeg; ++t) w[t] = (s0 + t < s1) ? col[s0 + t] : smax + 1;  // loads issued together
+        const uint32_t o = owner_of(sex, 0, kWave, q);
+        uint32_t w[kSeg];
+        load_seg(col, sa0[o], sa1[o], q - sex[o], w);
 #pragma unroll
         for (uint32_t t = 0; t < kSeg; ++t)
-          if (w[t] >= smin && w[t] <= smax) cnt += stage_has(st, buf, sn, w[t], c.ck);
+          if (w[t] >= (uint32_t)smin && w[t] <= (uint32_t)smax) cnt += stage_has(st, buf, sn, (int32_t)w[t], c.ck);
       }
     }
     wave_sync();
@@ -265,41 +286,147 @@ __device__ uint64_t wave_col(const TaskCtx& c, uint32_t i0, uint32_t i1, uint32_
   return cnt;
 }
 
-// Active columns [lo, hi) of block (i,j), by the whole workgroup.  Columns
-// with in-slices longer than cp.split are left to their split items.
-__device__ uint64_t process_cols(const PlanCtx& cp, const TaskCtx& c, uint32_t lo, uint32_t hi, CountLds& s) {
-  const int t = threadIdx.x, w = t / kWave;
+// Bounds of active column x of block (i,j): N(G_jk,v) = col[c0,c1) and the
+// in-slice [i0,i1) of v in V_i.
+__device__ __forceinline__ void col_bounds(const TaskCtx& c, uint32_t x, uint32_t& c0, uint32_t& c1, uint32_t& i0,
+                                           uint32_t& i1) {
+  const int32_t v = c.ac[x];
+  const uint32_t* vr = c.botj + (uint64_t)(v - c.cj) * c.strj;
+  const uint32_t* tr = c.tbotj + (uint64_t)(v - c.cj) * c.tstrj;
+  c0 = vr[c.dkj];
+  c1 = vr[c.dkj + 1];
+  i0 = tr[c.i];
+  i1 = tr[c.i + 1];
+}
+
+// 1 if w is in the sorted run buf[lo, hi).
+__device__ __forceinline__ uint32_t run_has(const uint32_t* buf, uint32_t lo, uint32_t hi, uint32_t w) {
+  const uint32_t end = hi;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (buf[mid] < w) lo = mid + 1; else hi = mid;
+  }
+  return (lo < end && buf[lo] == w) ? 1u : 0u;
+}
+
+// The packed short columns [0, ns) of a pass (bounds in c0s/i0s, prefixes in
+// soff/ioff), by the whole workgroup, window by window: a window is the
+// longest run of columns whose lists fit kShareCap words together.
+__device__ uint64_t short_cols(const TaskCtx& c, CountLds& s, uint32_t ns) {
+  const int32_t* __restrict__ colj = c.colj;
+  const int32_t* __restrict__ coli = c.coli;
+  const int32_t* __restrict__ icol = c.icolj;
+  const uint32_t t = threadIdx.x;
   uint64_t cnt = 0;
-  for (uint32_t base = lo; base < hi; base += kThreads) {
-    const uint32_t x = base + t;
-    if (x < hi) {
-      const int32_t v = c.ac[x];
-      const uint32_t* vr = c.botj + (uint64_t)(v - c.cj) * c.strj;
-      const uint32_t c0 = vr[c.dkj], c1 = vr[c.dkj + 1];
-      if (c1 > c0) {
-        const uint32_t* tr = c.tbotj + (uint64_t)(v - c.cj) * c.tstrj;
-        const uint32_t i0 = tr[c.i], i1 = tr[c.i + 1];
-        if (i1 > i0 && (cp.split == 0 || i1 - i0 <= cp.split)) {
-          if ((i1 - i0) + (c1 - c0) >= (uint32_t)cp.wave_min) {
-            const uint32_t qi = atomicAdd(&s.qn, 1u);
-            s.q[qi][0] = i0;
-            s.q[qi][1] = i1;
-            s.q[qi][2] = c0;
-            s.q[qi][3] = c1;
-          } else {
-            cnt += light_col(c, i0, i1, c0, c1);
+  for (uint32_t a = 0; a < ns;) {  // uniform across the workgroup
+    const uint32_t sbase = s.soff[a];
+    uint32_t b = a + 1, hi = ns;  // largest b in [a+1, ns] with soff[b] - sbase <= kShareCap
+    while (b < hi) {
+      const uint32_t mid = (b + hi + 1) >> 1;
+      if (s.soff[mid] - sbase <= kShareCap) b = mid; else hi = mid - 1;
+    }
+    const uint32_t span = s.soff[b] - sbase;
+    for (uint32_t g = t; g < span; g += kThreads) {
+      const uint32_t k = owner_of(s.soff, a, b, sbase + g);
+      s.sbuf[g] = (uint32_t)colj[s.c0s[k] + (sbase + g - s.soff[k])];
+    }
+    __syncthreads();
+    const uint32_t iend = s.ioff[b];
+    for (uint32_t eb = s.ioff[a]; eb < iend; eb += kThreads) {  // uniform
+      const uint32_t e = eb + t;
+      uint32_t a0 = 0, a1 = 0, k = 0;
+      if (e < iend) {
+        k = owner_of(s.ioff, a, b, e);
+        const int32_t u = icol[s.i0s[k] + (e - s.ioff[k])];
+        const uint32_t* ur = c.boti + (uint64_t)(u - c.ci) * c.stri;
+        a0 = ur[c.dk];
+        a1 = ur[c.dk + 1];
+      }
+      const uint32_t nseg = seg_count(a0, a1);
+      uint32_t tot;
+      const uint32_t ex = block256_excl_scan(nseg, (uint32_t*)s.red, &tot);
+      s.b.a0[t] = a0;
+      s.b.a1[t] = a1;
+      s.b.col[t] = k;
+      s.b.ex[t] = ex;
+      __syncthreads();
+      for (uint32_t qb = 0; qb < tot; qb += 2 * kThreads) {  // two segments per thread per round
+        uint32_t w[2][kSeg], rlo[2], rhi[2];
+#pragma unroll
+        for (uint32_t h = 0; h < 2; ++h) {
+          const uint32_t q = qb + h * kThreads + t;
+          rlo[h] = rhi[h] = 0;
+          if (q < tot) {
+            const uint32_t o = owner_of(s.b.ex, 0, kThreads, q);
+            const uint32_t k2 = s.b.col[o];
+            rlo[h] = s.soff[k2] - sbase;
+            rhi[h] = s.soff[k2 + 1] - sbase;
+            load_seg(coli, s.b.a0[o], s.b.a1[o], q - s.b.ex[o], w[h]);
+          }
+        }
+#pragma unroll
+        for (uint32_t h = 0; h < 2; ++h) {
+          if (rhi[h] > rlo[h]) {
+            const uint32_t wmin = s.sbuf[rlo[h]], wmax = s.sbuf[rhi[h] - 1];
+#pragma unroll
+            for (uint32_t x = 0; x < kSeg; ++x)
+              if (w[h][x] >= wmin && w[h][x] <= wmax) cnt += run_has(s.sbuf, rlo[h], rhi[h], w[h][x]);
           }
         }
       }
+      __syncthreads();
+    }
+    for (uint32_t g = t; g < span; g += kThreads) s.sbuf[g] = 0;
+    __syncthreads();
+    a = b;
+  }
+  return cnt;
+}
+
+// Active columns [lo, hi) of block (i,j), by the whole workgroup, 256 per
+// pass.  Columns with in-slices longer than cp.split are left to their split
+// items; columns whose lists reach wave_min get a wavefront of their own, the
+// others are packed for short_cols.
+__device__ uint64_t process_cols(const PlanCtx& cp, const TaskCtx& c, uint32_t lo, uint32_t hi, CountLds& s) {
+  const int t = threadIdx.x, w = t / kWave;
+  const uint32_t own_min = min((uint32_t)cp.wave_min, kShareCap);
+  uint64_t cnt = 0;
+  for (uint32_t base = lo; base < hi; base += kThreads) {
+    const uint32_t x = base + t;
+    uint32_t c0 = 0, c1 = 0, i0 = 0, i1 = 0;
+    if (x < hi) col_bounds(c, x, c0, c1, i0, i1);
+    const bool live = c1 > c0 && i1 > i0 && (cp.split == 0 || i1 - i0 <= cp.split);
+    // in-slices up to 2^24 keep the packed prefix below in range
+    const bool own = live && ((c1 - c0) >= own_min || (i1 - i0) >= (1u << 24) / kThreads);
+    if (own) s.q[atomicAdd(&s.qn, 1u)] = x;
+    const bool sh = live && !own;
+    // one 64-bit scan packs: count (bits 0-8), in-slice length (9-33), list length (34-63)
+    const unsigned long long pk =
+        sh ? (1ull | ((unsigned long long)(i1 - i0) << 9) | ((unsigned long long)(c1 - c0) << 34)) : 0ull;
+    unsigned long long tot;
+    const unsigned long long ex = block256_excl_scan(pk, s.red, &tot);
+    const uint32_t ns = (uint32_t)(tot & 511u);
+    if (sh) {
+      const uint32_t k = (uint32_t)(ex & 511u);
+      s.c0s[k] = c0;
+      s.i0s[k] = i0;
+      s.soff[k] = (uint32_t)(ex >> 34);
+      s.ioff[k] = (uint32_t)((ex >> 9) & 0x1FFFFFFu);
+    }
+    if (t == 0) {
+      s.soff[ns] = (uint32_t)(tot >> 34);
+      s.ioff[ns] = (uint32_t)((tot >> 9) & 0x1FFFFFFu);
     }
     __syncthreads();
     const uint32_t nq = s.qn;
     for (uint32_t h = w; h < nq; h += 4) {
-      const uint32_t i0 = s.q[h][0], i1 = s.q[h][1], c0 = s.q[h][2], c1 = s.q[h][3];
-      const bool use_hash = cp.hash_min >= 0 && (c1 - c0) >= (uint32_t)cp.hash_min;
-      cnt += wave_col(c, i0, i1, c0, c1, use_hash, s.abuf[w], s.sa0[w], s.sa1[w], s.sex[w]);
+      uint32_t qc0, qc1, qi0, qi1;
+      col_bounds(c, s.q[h], qc0, qc1, qi0, qi1);
+      const bool use_hash = cp.hash_min >= 0 && (qc1 - qc0) >= (uint32_t)cp.hash_min;
+      cnt += wave_col(c, qi0, qi1, qc0, qc1, use_hash, s.abuf[w], s.w.sa0[w], s.w.sa1[w], s.w.sex[w]);
     }
-    __syncthreads();
+    __syncthreads();  // the per-wave stages are clear again before the shared one is filled
+    if (ns) cnt += short_cols(c, s, ns);
     if (t == 0) s.qn = 0;
     __syncthreads();
   }
@@ -329,7 +456,8 @@ __device__ uint64_t hub_chunk(const PlanCtx& cp, const TaskCtx& c, int32_t v, ui
     const uint32_t sn = min(st.piece, c1 - s_lo);
     stage_fill(st, buf, col, s_lo, sn, c.ck, threadIdx.x, kThreads);
     __syncthreads();
-    cnt += probe_flat(c, w0, w1, st, buf, sn, col[s_lo], col[s_lo + sn - 1], s.sa0[w], s.sa1[w], s.sex[w]);
+    cnt += probe_flat(c, w0, w1, st, buf, sn, col[s_lo], col[s_lo + sn - 1], s.w.sa0[w], s.w.sa1[w],
+                      s.w.sex[w]);
     __syncthreads();
     stage_clear(st, buf, col, s_lo, sn, c.ck, threadIdx.x, kThreads);
     __syncthreads();
@@ -361,7 +489,10 @@ __device__ __forceinline__ uint64_t run_item(const PlanCtx& pc, const DevItem& i
 }
 
 // Items [first, first + gridDim.x) of the item list, one workgroup each.
-__global__ __launch_bounds__(kThreads) void k_count_items(CountParams cp, uint32_t first) {
+// Eight workgroups per CU fit the LDS; the register budget is held to match.
+#define BBTC_COUNT_KERNEL __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8)))
+
+BBTC_COUNT_KERNEL void k_count_items(CountParams cp, uint32_t first) {
   __shared__ CountLds s;
   init_lds(s);
   const PlanCtx& pc = cp.one;
@@ -374,11 +505,25 @@ __global__ __launch_bounds__(kThreads) void k_count_items(CountParams cp, uint32
 // Persistent work-stealing form: every workgroup claims work items from a
 // global cursor until none are left.  MULTI: items of several plans.
 template <bool MULTI>
-__global__ __launch_bounds__(kThreads) void k_count_persistent(CountParams cp) {
+BBTC_COUNT_KERNEL void k_count_persistent(CountParams cp) {
   __shared__ CountLds s;
   init_lds(s);
+  // workgroups are dispatched to the XCDs round robin: start on this one's queue
+  uint32_t x = blockIdx.x % cp.nq, tried = 0;
   while (true) {
-    if (threadIdx.x == 0) s.item = atomicAdd(cp.cursor, 1u);
+    if (threadIdx.x == 0) {
+      uint32_t it = 0xFFFFFFFFu;
+      while (tried < cp.nq) {
+        const uint32_t r = atomicAdd(&cp.cursor[x], 1u);
+        if (r < cp.qlen[x]) {
+          it = cp.qbeg[x] + r;
+          break;
+        }
+        ++tried;  // this queue is drained: move on to the next
+        x = x + 1 == cp.nq ? 0 : x + 1;
+      }
+      s.item = it;
+    }
     __syncthreads();
     const uint32_t it = s.item;
     __syncthreads();
@@ -395,9 +540,9 @@ __global__ __launch_bounds__(kThreads) void k_reset(uint64_t* per_task, int64_t 
                                                     uint32_t* cursor) {
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntasks; t += (int64_t)gridDim.x * blockDim.x)
     per_task[t] = 0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    if (total) *total = 0;
-    if (cursor) *cursor = 0;
+  if (blockIdx.x == 0 && threadIdx.x < kMaxQueues) {
+    if (total && threadIdx.x == 0) *total = 0;
+    if (cursor) cursor[threadIdx.x] = 0;
   }
 }
 
@@ -407,7 +552,7 @@ __global__ __launch_bounds__(kThreads) void k_reset_multi(const PlanCtx* ctxs, i
     for (int64_t t = threadIdx.x; t < c.ntasks; t += kThreads) c.per_task[t] = 0;
     if (threadIdx.x == 0) *c.total = 0;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) *cursor = 0;
+  if (blockIdx.x == 0 && threadIdx.x < kMaxQueues) cursor[threadIdx.x] = 0;
 }
 
 }  // namespace

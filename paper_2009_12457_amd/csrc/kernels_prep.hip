@@ -624,30 +624,104 @@ __global__ __launch_bounds__(kThreads) void k_segsort_huge(const uint32_t* __res
 // c_0 = 0, c_p = n; balanced: c_i = the smallest x > c_{i-1} with
 // orow[x] >= ceil(i*m/p); uniform: c_i = floor(i*n/p).  Either is clamped
 // into [c_{i-1}+1, n-(p-i)] so that no part is empty.
-__global__ void k_cuts(const uint32_t* __restrict__ orow, int64_t n, int32_t p, int mode, int32_t* __restrict__ cuts) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+// The balanced searches are independent (the smallest x > c_{i-1} with
+// orow[x] >= t_i is max(c_{i-1}+1, smallest x >= 1 with orow[x] >= t_i), as
+// orow is non-decreasing), so they run in parallel; one thread then applies
+// the clamps in order.
+__global__ __launch_bounds__(kThreads) void k_cuts(const uint32_t* __restrict__ orow, int64_t n, int32_t p, int mode,
+                                                   int32_t* __restrict__ cuts) {
+  __shared__ int32_t c[kMaxP + 1];
   const uint64_t m = orow[n];
-  int64_t prev = 0;
-  cuts[0] = 0;
-  for (int32_t i = 1; i < p; ++i) {
-    int64_t c;
+  for (int32_t i = threadIdx.x + 1; i < p; i += kThreads) {
+    int64_t x;
     if (mode == BBTC_CUT_UNIFORM) {
-      c = (int64_t)i * n / p;
+      x = (int64_t)i * n / p;
     } else {
       const uint64_t target = ((uint64_t)i * m + (uint64_t)p - 1) / (uint64_t)p;
-      int64_t lo = prev + 1, hi = n;
+      int64_t lo = 1, hi = n;
       while (lo < hi) {
-        int64_t mid = (lo + hi) >> 1;
+        const int64_t mid = (lo + hi) >> 1;
         if ((uint64_t)orow[mid] < target) lo = mid + 1; else hi = mid;
       }
-      c = lo;
+      x = lo;
     }
-    if (c < prev + 1) c = prev + 1;
-    if (c > n - (p - i)) c = n - (p - i);
-    cuts[i] = (int32_t)c;
-    prev = c;
+    c[i] = (int32_t)x;
   }
-  cuts[p] = (int32_t)n;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t prev = 0;
+    cuts[0] = 0;
+    for (int32_t i = 1; i < p; ++i) {
+      int64_t x = c[i];
+      if (x < prev + 1) x = prev + 1;
+      if (x > n - (p - i)) x = n - (p - i);
+      cuts[i] = (int32_t)x;
+      prev = x;
+    }
+    cuts[p] = (int32_t)n;
+  }
+}
+
+// ------------------------------------------------------------ in-rows by part
+// The counting kernels need an in-row only grouped by the part of each entry
+// (parts in increasing order), not sorted.  Listed rows (the long and huge
+// ones left by k_segsort) are grouped by one counting pass per row: histogram
+// of part ids in LDS, scan, scatter into scratch[rp[r] .. rp[r+1]) (rows own
+// disjoint ranges), copy back.  The order inside a part is left to timing.
+__device__ __forceinline__ int32_t part_of(const int32_t* scut, int32_t p, int32_t v) {
+  int32_t lo = 0, hi = p - 1;  // largest a with scut[a] <= v
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (scut[mid] <= v) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(kThreads) void k_group_parts(const uint32_t* __restrict__ rp, int32_t* __restrict__ col,
+                                                          int32_t* __restrict__ scratch,
+                                                          const uint32_t* __restrict__ rows,
+                                                          const uint32_t* __restrict__ nrows,
+                                                          const int32_t* __restrict__ cuts, int32_t p) {
+  __shared__ int32_t scut[kMaxP + 1];
+  __shared__ uint32_t bins[kMaxP];
+  __shared__ uint32_t lds[4];
+  const int t = threadIdx.x;
+  for (int a = t; a <= p; a += kThreads) scut[a] = cuts[a];
+  const uint32_t cnt = *nrows;
+  const int per = (p + kThreads - 1) / kThreads;  // bins per thread in the scan
+  __syncthreads();
+  for (uint32_t qi = blockIdx.x; qi < cnt; qi += gridDim.x) {
+    const uint32_t r = rows[qi];
+    const uint32_t s = rp[r], len = rp[r + 1] - s;
+    for (int a = t; a < p; a += kThreads) bins[a] = 0;
+    __syncthreads();
+    for (uint32_t e = t; e < len; e += kThreads) atomicAdd(&bins[part_of(scut, p, col[s + e])], 1u);
+    __syncthreads();
+    uint32_t sum = 0;
+    for (int k = 0; k < per; ++k) {
+      const int a = t * per + k;
+      if (a < p) sum += bins[a];
+    }
+    uint32_t tot;
+    uint32_t off = block256_excl_scan<uint32_t>(sum, lds, &tot);
+    for (int k = 0; k < per; ++k) {  // bins become the next free slot of each part
+      const int a = t * per + k;
+      if (a < p) {
+        const uint32_t b = bins[a];
+        bins[a] = off;
+        off += b;
+      }
+    }
+    __syncthreads();
+    for (uint32_t e = t; e < len; e += kThreads) {
+      const int32_t v = col[s + e];
+      const uint32_t pos = atomicAdd(&bins[part_of(scut, p, v)], 1u);
+      if (pos < len) scratch[s + pos] = v;
+    }
+    __syncthreads();
+    for (uint32_t e = t; e < len; e += kThreads) col[s + e] = scratch[s + e];
+    __syncthreads();
+  }
 }
 
 // ------------------------------------------------------------ block row index
@@ -929,7 +1003,18 @@ hipError_t launch_segsort(const uint32_t* rp, int32_t* col, int64_t nrows, int b
 }
 
 hipError_t launch_cuts(const uint32_t* orow, int64_t n, int32_t p, int mode, int32_t* cuts, hipStream_t s) {
-  hipLaunchKernelGGL(k_cuts, dim3(1), dim3(64), 0, s, orow, n, p, mode, cuts);
+  hipLaunchKernelGGL(k_cuts, dim3(1), dim3(kThreads), 0, s, orow, n, p, mode, cuts);
+  return hipGetLastError();
+}
+
+hipError_t launch_inrows(const uint32_t* rp, int32_t* col, int64_t nrows, uint32_t* longrows, uint32_t* hugerows,
+                         uint32_t* q, int32_t* scratch, const int32_t* cuts, int32_t p, hipStream_t s) {
+  if (nrows == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_segsort, dim3(kRowGrid), dim3(kThreads), 0, s, rp, col, nrows, longrows, hugerows, q);
+  hipLaunchKernelGGL(k_group_parts, dim3(1024), dim3(kThreads), 0, s, rp, col, scratch, (const uint32_t*)longrows,
+                     (const uint32_t*)q, cuts, p);
+  hipLaunchKernelGGL(k_group_parts, dim3(256), dim3(kThreads), 0, s, rp, col, scratch, (const uint32_t*)hugerows,
+                     (const uint32_t*)(q + 1), cuts, p);
   return hipGetLastError();
 }
 

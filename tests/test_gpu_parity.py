@@ -127,7 +127,7 @@ def test_random_small_graphs(seed):
     for p in sorted({1, 2, 5, n}):
         p = min(p, n)
         plan, per, tot = run(g, p=p, mode=MODES[["persistent", "intersect", "hmap"][seed % 3]],
-                             wave_min=int(rng.integers(1, 6)), hash_min=int(rng.choice([-1, 1, 3])))
+                             wave_min=int(rng.choice([1, 3, 64, 4096])), hash_min=int(rng.choice([-1, 1, 3])))
         check(g, plan, per, tot, deep=(p == 2))
 
 
@@ -142,7 +142,8 @@ def test_rmat_modes_and_p(name, p):
 
 
 @pytest.mark.parametrize("wave_min,hash_min,item_rows", [(1, -1, 7), (1, 1, 1000), (3, 2, 256), (1000000, -1, 64),
-                                                         (2, 1000000, 32)])
+                                                         (2, 1000000, 32), (4096, 1, 256), (4096, -1, 33),
+                                                         (64, 1, 256), (8, -1, 3)])
 def test_row_mappings_are_exact(wave_min, hash_min, item_rows):
     g = graphgen.workload("rmat13")
     for p in (3, 20):
@@ -295,3 +296,20 @@ def test_hub_columns_are_split_exactly():
                     plan, per, tot = run(g, p=p, mode=mode, hash_min=hash_min, wave_min=4)
                     assert tot == want
                     check(g, plan, per, tot, deep=(p == 2 and mode == 0))
+
+
+def test_huge_in_rows_grouped_by_part():
+    """In-rows longer than 16384 entries (the hub of a wheel or a friendship
+    graph) are grouped by part in one counting pass; counts stay exact, with
+    hubs both inside one part and across many."""
+    n = 20000
+    wheel = small_graph(n + 1, [(x, (x + 1) % n) for x in range(n)] + [(n, x) for x in range(n)], "W20000")
+    k = 9000
+    friend = small_graph(2 * k + 1, [e for t in range(k) for e in ((0, 2 * t + 1), (0, 2 * t + 2),
+                                                                    (2 * t + 1, 2 * t + 2))], "F9000")
+    for g, want in ((wheel, n), (friend, k)):
+        for p in (1, 3, 16, 200):
+            for mode in MODES.values():
+                plan, per, tot = run(g, p=p, mode=mode)
+                assert tot == want
+                check(g, plan, per, tot, deep=(p == 3 and mode == 0))
