@@ -89,7 +89,7 @@ struct bbtc_plan {
   DevBuf<uint64_t> keys_a, keys_b;
   DevBuf<uint32_t> hist, partial;
   DevBuf<int32_t> perm, order, ocol, icol, cuts, chunk0, acol;
-  DevBuf<uint32_t> od, idg, orow, irow, longrows, hugerows, bot, tbot, ccnt, ccoff, dmax, cursor, err;
+  DevBuf<uint32_t> od, idg, orow, irow, midrows, longrows, hugerows, bot, tbot, ccnt, ccoff, dmax, cursor, err;
   DevBuf<uint64_t> ccbase, botp, tbotp, acp;
   DevBuf<unsigned long long> bnnz, bnzr, bnzc;
   DevBuf<DevTask> tasks;
@@ -174,7 +174,8 @@ struct bbtc_plan {
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     in_rowptr.release(); in_col.release(); keys_a.release(); keys_b.release(); hist.release(); partial.release();
     perm.release(); order.release(); ocol.release(); icol.release(); cuts.release(); chunk0.release();
-    acol.release(); od.release(); idg.release(); orow.release(); irow.release(); longrows.release();
+    acol.release(); od.release(); idg.release(); orow.release(); irow.release(); midrows.release();
+    longrows.release();
     hugerows.release();
     bot.release(); tbot.release(); ccnt.release(); ccoff.release(); dmax.release(); cursor.release();
     err.release(); ccbase.release(); botp.release(); tbotp.release(); acp.release(); bnnz.release();
@@ -184,7 +185,7 @@ struct bbtc_plan {
   size_t footprint() const {
     return in_rowptr.bytes() + in_col.bytes() + keys_a.bytes() + keys_b.bytes() + hist.bytes() + partial.bytes() +
            perm.bytes() + order.bytes() + ocol.bytes() + icol.bytes() + cuts.bytes() + chunk0.bytes() +
-           acol.bytes() + od.bytes() + idg.bytes() + orow.bytes() + irow.bytes() + longrows.bytes() +
+           acol.bytes() + od.bytes() + idg.bytes() + orow.bytes() + irow.bytes() + midrows.bytes() + longrows.bytes() +
            hugerows.bytes() + bot.bytes() +
            tbot.bytes() + ccnt.bytes() + ccoff.bytes() + dmax.bytes() + cursor.bytes() + err.bytes() +
            ccbase.bytes() + botp.bytes() + tbotp.bytes() + acp.bytes() + bnnz.bytes() + bnzr.bytes() +
@@ -791,9 +792,10 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
           "fill");
   // acol is not built yet: its m entries serve as the huge-row sort scratch
   HIP_TRY(pl->acol.ensure((size_t)m), "alloc active columns");
-  HIP_TRY(hipMemsetAsync(pl->err.ptr, 0, 8, s), "memset");
-  HIP_TRY(launch_segsort(pl->orow.ptr, pl->ocol.ptr, n, pl->idbits, pl->longrows.ptr, pl->hugerows.ptr, pl->err.ptr,
-                         pl->acol.ptr, s),
+  HIP_TRY(pl->midrows.ensure((size_t)n), "alloc");
+  HIP_TRY(hipMemsetAsync(pl->err.ptr, 0, 12, s), "memset");
+  HIP_TRY(launch_segsort(pl->orow.ptr, pl->ocol.ptr, n, pl->idbits, pl->midrows.ptr, pl->longrows.ptr,
+                         pl->hugerows.ptr, pl->err.ptr, pl->acol.ptr, s),
           "sort out-rows");
 
   // ---- cut vector (Sec. 4.1) ----
@@ -808,9 +810,9 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   HIP_TRY(pl->cuts.ensure((size_t)p + 1), "alloc cuts");
   HIP_TRY(launch_cuts(pl->orow.ptr, n, p, opt.cut_mode, pl->cuts.ptr, s), "cuts");
   // in-rows: grouped by the part of each in-neighbour (all the counting needs)
-  HIP_TRY(hipMemsetAsync(pl->err.ptr, 0, 8, s), "memset");
-  HIP_TRY(launch_inrows(pl->irow.ptr, pl->icol.ptr, n, pl->longrows.ptr, pl->hugerows.ptr, pl->err.ptr, pl->acol.ptr,
-                        pl->cuts.ptr, p, s),
+  HIP_TRY(hipMemsetAsync(pl->err.ptr, 0, 12, s), "memset");
+  HIP_TRY(launch_inrows(pl->irow.ptr, pl->icol.ptr, n, pl->midrows.ptr, pl->longrows.ptr, pl->hugerows.ptr,
+                        pl->err.ptr, pl->acol.ptr, pl->cuts.ptr, p, s),
           "group in-rows");
   pl->h_cuts.assign((size_t)p + 1, 0);
   HIP_TRY(hipMemcpyAsync(pl->h_cuts.data(), pl->cuts.ptr, sizeof(int32_t) * (p + 1), hipMemcpyDeviceToHost, s),

@@ -143,12 +143,13 @@ hipError_t launch_fill(const void* rowptr, int rp64, const int32_t* colidx, int6
 // Sorts every row of a CSR in place; values have at most `bits` bits.
 // longrows and hugerows need nrows entries each, q[0..1] must be zero, and
 // scratch needs rp[nrows] entries.
-hipError_t launch_segsort(const uint32_t* rp, int32_t* col, int64_t nrows, int bits, uint32_t* longrows,
-                          uint32_t* hugerows, uint32_t* q, int32_t* scratch, hipStream_t s);
+hipError_t launch_segsort(const uint32_t* rp, int32_t* col, int64_t nrows, int bits, uint32_t* midrows,
+                          uint32_t* longrows, uint32_t* hugerows, uint32_t* q, int32_t* scratch, hipStream_t s);
 // In-rows grouped by part (short rows fully sorted, long ones by a counting
 // pass over the parts of cuts[0..p]).
-hipError_t launch_inrows(const uint32_t* rp, int32_t* col, int64_t nrows, uint32_t* longrows, uint32_t* hugerows,
-                         uint32_t* q, int32_t* scratch, const int32_t* cuts, int32_t p, hipStream_t s);
+hipError_t launch_inrows(const uint32_t* rp, int32_t* col, int64_t nrows, uint32_t* midrows, uint32_t* longrows,
+                         uint32_t* hugerows, uint32_t* q, int32_t* scratch, const int32_t* cuts, int32_t p,
+                         hipStream_t s);
 hipError_t launch_cuts(const uint32_t* orow, int64_t n, int32_t p, int mode, int32_t* cuts, hipStream_t s);
 
 struct BlockBuild {

@@ -225,16 +225,76 @@ __device__ __forceinline__ uint32_t stage_has(const Stage& st, const uint32_t* b
   return 0u;
 }
 
-// One wavefront tests every w of N(G_ik,u) in [smin, smax], for the
-// in-neighbours u = icol[i0..i1), against the stage.  The probe space is cut
-// into segments of kSeg consecutive entries of one N(G_ik,u); a wavefront
-// prefix sum over the segment counts of 64 in-neighbours at a time lets all
-// lanes share the segments, however unequal the lists are.
+// Wavefront probes use wider segments: kSegW entries, two aligned 16-byte
+// blocks (the second is read only if it holds part of the list).
+constexpr uint32_t kSegW = 8;
+
+__device__ __forceinline__ uint32_t seg_count_w(uint32_t a0, uint32_t a1) {
+  return a1 > a0 ? (a1 - (a0 & ~(kSeg - 1)) + kSegW - 1) / kSegW : 0u;
+}
+
+__device__ __forceinline__ void load_seg_w(const int32_t* __restrict__ col, uint32_t a0, uint32_t a1, uint32_t q,
+                                           uint32_t w[kSegW]) {
+  const uint32_t s0 = (a0 & ~(kSeg - 1)) + q * kSegW;
+  const int4 v0 = *reinterpret_cast<const int4*>(col + s0);
+  int4 v1 = make_int4(-1, -1, -1, -1);
+  if (s0 + kSeg < a1) v1 = *reinterpret_cast<const int4*>(col + s0 + kSeg);
+  w[0] = (uint32_t)v0.x;
+  w[1] = (uint32_t)v0.y;
+  w[2] = (uint32_t)v0.z;
+  w[3] = (uint32_t)v0.w;
+  w[4] = (uint32_t)v1.x;
+  w[5] = (uint32_t)v1.y;
+  w[6] = (uint32_t)v1.z;
+  w[7] = (uint32_t)v1.w;
+#pragma unroll
+  for (uint32_t x = 0; x < kSegW; ++x)
+    if (s0 + x < a0 || s0 + x >= a1) w[x] = 0xFFFFFFFFu;
+}
+
+// The probe rounds of one batch: segment q of the batch goes to lane q mod 64;
+// its owner (the in-neighbour whose list holds it) is found by binary search
+// over the batch's exclusive prefix of segment counts.  MODE is the stage
+// form: 1 = bitmap over V_k (every list entry lies in V_k, so the only test
+// is the masked tail), otherwise entries outside [smin, smax] cannot match.
+template <int MODE>
+__device__ __forceinline__ uint32_t probe_rounds(const int32_t* __restrict__ col, uint32_t tot, const uint32_t* sa0,
+                                                 const uint32_t* sa1, const uint32_t* sex, const Stage& st,
+                                                 const uint32_t* buf, uint32_t sn, uint32_t smin, uint32_t smax,
+                                                 int32_t ck, uint32_t width) {
+  const uint32_t l = (uint32_t)lane_id();
+  uint32_t cnt = 0;
+  for (uint32_t qb = 0; qb < tot; qb += kWave) {
+    const uint32_t q = qb + l;
+    if (q < tot) {
+      const uint32_t o = owner_of(sex, 0, kWave, q);
+      uint32_t w[kSegW];
+      load_seg_w(col, sa0[o], sa1[o], q - sex[o], w);
+#pragma unroll
+      for (uint32_t t = 0; t < kSegW; ++t) {
+        if (MODE == 1) {
+          const uint32_t x = w[t] - (uint32_t)ck;
+          if (x < width) cnt += (buf[x >> 5] >> (x & 31)) & 1u;
+        } else if (w[t] >= smin && w[t] <= smax) {
+          cnt += stage_has(st, buf, sn, (int32_t)w[t], ck);
+        }
+      }
+    }
+  }
+  return cnt;
+}
+
+// One wavefront tests every w of N(G_ik,u), for the in-neighbours
+// u = icol[i0..i1), against the stage.  The probe space is cut into segments
+// of kSegW consecutive entries of one N(G_ik,u); a wavefront prefix sum over
+// the segment counts of 64 in-neighbours at a time lets all lanes share the
+// segments, however unequal the lists are.
 __device__ uint64_t probe_flat(const TaskCtx& c, uint32_t i0, uint32_t i1, const Stage& st, const uint32_t* buf,
                                uint32_t sn, int32_t smin, int32_t smax, uint32_t* sa0, uint32_t* sa1, uint32_t* sex) {
   const int32_t* __restrict__ col = c.coli;
   const int32_t* __restrict__ icol = c.icolj;
   const uint32_t l = (uint32_t)lane_id();
+  const uint32_t width = (uint32_t)(c.ck1 - c.ck);
   uint64_t cnt = 0;
   for (uint32_t eb = i0; eb < i1; eb += kWave) {
     const uint32_t e = eb + l;
@@ -245,24 +305,17 @@ __device__ uint64_t probe_flat(const TaskCtx& c, uint32_t i0, uint32_t i1, const
       a0 = ur[c.dk];
       a1 = ur[c.dk + 1];
     }
-    const uint32_t nseg = seg_count(a0, a1);
+    const uint32_t nseg = seg_count_w(a0, a1);
     const uint32_t inc = wave_incl_scan_u32(nseg);
     const uint32_t tot = __shfl(inc, kWave - 1, kWave);
     sa0[l] = a0;
     sa1[l] = a1;
     sex[l] = inc - nseg;
     wave_sync();
-    for (uint32_t qb = 0; qb < tot; qb += kWave) {
-      const uint32_t q = qb + l;
-      if (q < tot) {
-        const uint32_t o = owner_of(sex, 0, kWave, q);
-        uint32_t w[kSeg];
-        load_seg(col, sa0[o], sa1[o], q - sex[o], w);
-#pragma unroll
-        for (uint32_t t = 0; t < kSeg; ++t)
-          if (w[t] >= (uint32_t)smin && w[t] <= (uint32_t)smax) cnt += stage_has(st, buf, sn, (int32_t)w[t], c.ck);
-      }
-    }
+    if (st.mode == 1)
+      cnt += probe_rounds<1>(col, tot, sa0, sa1, sex, st, buf, sn, (uint32_t)smin, (uint32_t)smax, c.ck, width);
+    else
+      cnt += probe_rounds<0>(col, tot, sa0, sa1, sex, st, buf, sn, (uint32_t)smin, (uint32_t)smax, c.ck, width);
     wave_sync();
   }
   return cnt;

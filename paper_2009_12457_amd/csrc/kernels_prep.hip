@@ -499,27 +499,79 @@ __device__ __forceinline__ uint32_t pow2_at_least(uint32_t x) {
   return n;
 }
 
-// Wavefront per row; longer rows are queued: up to kSegBlock entries for
-// k_segsort_long, beyond that for k_segsort_huge.  q[0] counts the long rows,
-// q[1] the huge ones; both lists have room for every row.
+constexpr uint32_t kSegLane = 16;  // longest row sorted by one lane, in registers
+
+// Bitonic network over v[0..kSegLane) held in registers (indices are
+// compile-time constants once the loops are unrolled).
+__device__ __forceinline__ void bitonic_regs(int32_t (&v)[kSegLane]) {
+#pragma unroll
+  for (uint32_t k = 2; k <= kSegLane; k <<= 1) {
+#pragma unroll
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+      for (uint32_t i = 0; i < kSegLane; ++i) {
+        const uint32_t ixj = i ^ j;
+        if (ixj > i) {
+          const int32_t a = v[i], c = v[ixj];
+          const bool up = (i & k) == 0;
+          const bool sw = up ? (a > c) : (a < c);
+          v[i] = sw ? c : a;
+          v[ixj] = sw ? a : c;
+        }
+      }
+    }
+  }
+}
+
+// Rows in groups of 64 consecutive rows per wavefront: a row of at most
+// kSegLane entries is sorted by its own lane in registers; longer rows are
+// queued: up to kSegWave entries for k_segsort_mid, up to kSegBlock for
+// k_segsort_long, beyond that for k_segsort_huge.  q[2], q[0] and q[1]
+// count them; every list has room for every row.
 __global__ __launch_bounds__(kThreads) void k_segsort(const uint32_t* __restrict__ rp, int32_t* __restrict__ col,
-                                                      int64_t nrows, uint32_t* __restrict__ longrows,
+                                                      int64_t nrows, uint32_t* __restrict__ midrows,
+                                                      uint32_t* __restrict__ longrows,
                                                       uint32_t* __restrict__ hugerows, uint32_t* __restrict__ q) {
+  const int l = lane_id();
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  for (int64_t g = wave * kWave; g < nrows; g += nwaves * kWave) {
+    const int64_t r = g + l;
+    if (r >= nrows) continue;
+    const uint32_t s = rp[r], len = rp[r + 1] - s;
+    if (len <= 1) continue;
+    if (len <= kSegLane) {
+      int32_t v[kSegLane];
+#pragma unroll
+      for (uint32_t t = 0; t < kSegLane; ++t) v[t] = t < len ? col[s + t] : 0x7FFFFFFF;
+      bitonic_regs(v);
+#pragma unroll
+      for (uint32_t t = 0; t < kSegLane; ++t)
+        if (t < len) col[s + t] = v[t];
+    } else if (len <= kSegWave) {
+      midrows[atomicAdd(&q[2], 1u)] = (uint32_t)r;
+    } else if (len <= kSegBlock) {
+      longrows[atomicAdd(&q[0], 1u)] = (uint32_t)r;
+    } else {
+      hugerows[atomicAdd(&q[1], 1u)] = (uint32_t)r;
+    }
+  }
+}
+
+// Wavefront per queued row of up to kSegWave entries: bitonic sort in LDS.
+__global__ __launch_bounds__(kThreads) void k_segsort_mid(const uint32_t* __restrict__ rp, int32_t* __restrict__ col,
+                                                          const uint32_t* __restrict__ midrows,
+                                                          const uint32_t* __restrict__ q) {
   __shared__ int32_t buf[4][kSegWave];
   const int l = lane_id(), w = threadIdx.x / kWave;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
   int32_t* b = buf[w];
-  for (int64_t r = wave; r < nrows; r += nwaves) {
+  const uint32_t cnt = q[2];
+  for (int64_t i = wave; i < cnt; i += nwaves) {
+    const uint32_t r = midrows[i];
     const uint32_t s = rp[r], len = rp[r + 1] - s;
-    if (len <= 1) continue;
-    if (len > kSegWave) {
-      if (l == 0) {
-        if (len > kSegBlock) hugerows[atomicAdd(&q[1], 1u)] = (uint32_t)r;
-        else longrows[atomicAdd(&q[0], 1u)] = (uint32_t)r;
-      }
-      continue;
-    }
+    if (len > kSegWave) continue;
     const uint32_t N = pow2_at_least(len);
     for (uint32_t t = l; t < N; t += kWave) b[t] = t < len ? col[s + t] : 0x7FFFFFFF;
     wave_sync();
@@ -677,25 +729,54 @@ __device__ __forceinline__ int32_t part_of(const int32_t* scut, int32_t p, int32
   return lo;
 }
 
-__global__ __launch_bounds__(kThreads) void k_group_parts(const uint32_t* __restrict__ rp, int32_t* __restrict__ col,
-                                                          int32_t* __restrict__ scratch,
-                                                          const uint32_t* __restrict__ rows,
-                                                          const uint32_t* __restrict__ nrows,
-                                                          const int32_t* __restrict__ cuts, int32_t p) {
+// Exclusive scan of one value per thread over an NT-thread workgroup; `lds`
+// needs NT/64 slots.  Contains barriers: call from uniform control flow.
+template <int NT>
+__device__ __forceinline__ uint32_t block_excl_scan_n(uint32_t v, uint32_t* lds, uint32_t* total) {
+  const int l = lane_id(), w = threadIdx.x / kWave;
+  const uint32_t inc = wave_incl_scan_u32(v);
+  if (l == kWave - 1) lds[w] = inc;
+  __syncthreads();
+  uint32_t off = 0, tot = 0;
+#pragma unroll
+  for (int q = 0; q < NT / kWave; ++q) {
+    const uint32_t x = lds[q];
+    if (q < w) off += x;
+    tot += x;
+  }
+  __syncthreads();
+  *total = tot;
+  return off + inc - v;
+}
+
+constexpr int kGroupUnroll = 4;  // entries per thread in flight in k_group_parts
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_group_parts(const uint32_t* __restrict__ rp, int32_t* __restrict__ col,
+                                                    int32_t* __restrict__ scratch, const uint32_t* __restrict__ rows,
+                                                    const uint32_t* __restrict__ nrows,
+                                                    const int32_t* __restrict__ cuts, int32_t p) {
   __shared__ int32_t scut[kMaxP + 1];
   __shared__ uint32_t bins[kMaxP];
-  __shared__ uint32_t lds[4];
+  __shared__ uint32_t lds[NT / kWave];
   const int t = threadIdx.x;
-  for (int a = t; a <= p; a += kThreads) scut[a] = cuts[a];
+  for (int a = t; a <= p; a += NT) scut[a] = cuts[a];
   const uint32_t cnt = *nrows;
-  const int per = (p + kThreads - 1) / kThreads;  // bins per thread in the scan
+  const int per = (p + NT - 1) / NT;  // bins per thread in the scan
   __syncthreads();
   for (uint32_t qi = blockIdx.x; qi < cnt; qi += gridDim.x) {
     const uint32_t r = rows[qi];
     const uint32_t s = rp[r], len = rp[r + 1] - s;
-    for (int a = t; a < p; a += kThreads) bins[a] = 0;
+    for (int a = t; a < p; a += NT) bins[a] = 0;
     __syncthreads();
-    for (uint32_t e = t; e < len; e += kThreads) atomicAdd(&bins[part_of(scut, p, col[s + e])], 1u);
+    for (uint32_t e0 = t; e0 < len; e0 += kGroupUnroll * NT) {
+      int32_t v[kGroupUnroll];
+#pragma unroll
+      for (int k = 0; k < kGroupUnroll; ++k) v[k] = e0 + k * NT < len ? col[s + e0 + k * NT] : -1;
+#pragma unroll
+      for (int k = 0; k < kGroupUnroll; ++k)
+        if (v[k] >= 0) atomicAdd(&bins[part_of(scut, p, v[k])], 1u);
+    }
     __syncthreads();
     uint32_t sum = 0;
     for (int k = 0; k < per; ++k) {
@@ -703,7 +784,7 @@ __global__ __launch_bounds__(kThreads) void k_group_parts(const uint32_t* __rest
       if (a < p) sum += bins[a];
     }
     uint32_t tot;
-    uint32_t off = block256_excl_scan<uint32_t>(sum, lds, &tot);
+    uint32_t off = block_excl_scan_n<NT>(sum, lds, &tot);
     for (int k = 0; k < per; ++k) {  // bins become the next free slot of each part
       const int a = t * per + k;
       if (a < p) {
@@ -713,13 +794,20 @@ __global__ __launch_bounds__(kThreads) void k_group_parts(const uint32_t* __rest
       }
     }
     __syncthreads();
-    for (uint32_t e = t; e < len; e += kThreads) {
-      const int32_t v = col[s + e];
-      const uint32_t pos = atomicAdd(&bins[part_of(scut, p, v)], 1u);
-      if (pos < len) scratch[s + pos] = v;
+    for (uint32_t e0 = t; e0 < len; e0 += kGroupUnroll * NT) {
+      int32_t v[kGroupUnroll];
+#pragma unroll
+      for (int k = 0; k < kGroupUnroll; ++k) v[k] = e0 + k * NT < len ? col[s + e0 + k * NT] : -1;
+#pragma unroll
+      for (int k = 0; k < kGroupUnroll; ++k) {
+        if (v[k] >= 0) {
+          const uint32_t pos = atomicAdd(&bins[part_of(scut, p, v[k])], 1u);
+          if (pos < len) scratch[s + pos] = v[k];
+        }
+      }
     }
     __syncthreads();
-    for (uint32_t e = t; e < len; e += kThreads) col[s + e] = scratch[s + e];
+    for (uint32_t e = t; e < len; e += NT) col[s + e] = scratch[s + e];
     __syncthreads();
   }
 }
@@ -991,10 +1079,13 @@ hipError_t launch_fill(const void* rowptr, int rp64, const int32_t* colidx, int6
   return hipGetLastError();
 }
 
-hipError_t launch_segsort(const uint32_t* rp, int32_t* col, int64_t nrows, int bits, uint32_t* longrows,
-                          uint32_t* hugerows, uint32_t* q, int32_t* scratch, hipStream_t s) {
+hipError_t launch_segsort(const uint32_t* rp, int32_t* col, int64_t nrows, int bits, uint32_t* midrows,
+                          uint32_t* longrows, uint32_t* hugerows, uint32_t* q, int32_t* scratch, hipStream_t s) {
   if (nrows == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_segsort, dim3(kRowGrid), dim3(kThreads), 0, s, rp, col, nrows, longrows, hugerows, q);
+  hipLaunchKernelGGL(k_segsort, dim3(grid_for((uint64_t)nrows, kThreads, kRowGrid)), dim3(kThreads), 0, s, rp, col,
+                     nrows, midrows, longrows, hugerows, q);
+  hipLaunchKernelGGL(k_segsort_mid, dim3(kRowGrid), dim3(kThreads), 0, s, rp, col, (const uint32_t*)midrows,
+                     (const uint32_t*)q);
   hipLaunchKernelGGL(k_segsort_long, dim3(1024), dim3(kThreads), 0, s, rp, col, (const uint32_t*)longrows,
                      (const uint32_t*)q);
   hipLaunchKernelGGL(k_segsort_huge, dim3(256), dim3(kThreads), 0, s, rp, col, scratch, (const uint32_t*)hugerows,
@@ -1007,13 +1098,17 @@ hipError_t launch_cuts(const uint32_t* orow, int64_t n, int32_t p, int mode, int
   return hipGetLastError();
 }
 
-hipError_t launch_inrows(const uint32_t* rp, int32_t* col, int64_t nrows, uint32_t* longrows, uint32_t* hugerows,
-                         uint32_t* q, int32_t* scratch, const int32_t* cuts, int32_t p, hipStream_t s) {
+hipError_t launch_inrows(const uint32_t* rp, int32_t* col, int64_t nrows, uint32_t* midrows, uint32_t* longrows,
+                         uint32_t* hugerows, uint32_t* q, int32_t* scratch, const int32_t* cuts, int32_t p,
+                         hipStream_t s) {
   if (nrows == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_segsort, dim3(kRowGrid), dim3(kThreads), 0, s, rp, col, nrows, longrows, hugerows, q);
-  hipLaunchKernelGGL(k_group_parts, dim3(1024), dim3(kThreads), 0, s, rp, col, scratch, (const uint32_t*)longrows,
-                     (const uint32_t*)q, cuts, p);
-  hipLaunchKernelGGL(k_group_parts, dim3(256), dim3(kThreads), 0, s, rp, col, scratch, (const uint32_t*)hugerows,
+  hipLaunchKernelGGL(k_segsort, dim3(grid_for((uint64_t)nrows, kThreads, kRowGrid)), dim3(kThreads), 0, s, rp, col,
+                     nrows, midrows, longrows, hugerows, q);
+  hipLaunchKernelGGL(k_segsort_mid, dim3(kRowGrid), dim3(kThreads), 0, s, rp, col, (const uint32_t*)midrows,
+                     (const uint32_t*)q);
+  hipLaunchKernelGGL(k_group_parts<kThreads>, dim3(1024), dim3(kThreads), 0, s, rp, col, scratch,
+                     (const uint32_t*)longrows, (const uint32_t*)q, cuts, p);
+  hipLaunchKernelGGL(k_group_parts<1024>, dim3(256), dim3(1024), 0, s, rp, col, scratch, (const uint32_t*)hugerows,
                      (const uint32_t*)(q + 1), cuts, p);
   return hipGetLastError();
 }

@@ -46,7 +46,7 @@ def footprint_estimate(n: int, nnz: int, p: int) -> int:
     vertex each), tasks and items."""
     m = nnz // 2
     ntasks = p * (p + 1) * (p + 2) // 6
-    return 12 * m + 4 * nnz + 64 * n + 8 * (p + 1) * n + 64 * ntasks + (1 << 20)
+    return 12 * m + 4 * nnz + 72 * n + 8 * (p + 1) * n + 64 * ntasks + (1 << 20)
 
 
 def default_p(n: int, nnz: int) -> int:
