@@ -9,23 +9,24 @@
 //
 // Three mappings (tuning knobs; all exact):
 //   * short columns (|N(G_jk,v)| < wave_min): the columns of one pass of the
-//     workgroup are packed into windows; a window's lists are copied, sorted,
-//     into one workgroup-wide LDS stage, and the probes of all in-neighbours
-//     of all its columns are flattened over the 256 threads (segments of kSeg
-//     entries, owners found by binary search over LDS prefix arrays), each a
-//     binary search in its own column's piece of the stage;
+//     workgroup are packed and split into four runs, one per wavefront; a
+//     wavefront copies the sorted lists of a window of its columns side by
+//     side into its LDS stage and flattens the probes of all their
+//     in-neighbours over its 64 lanes (segments of kSegW entries, owners
+//     found by binary search over LDS prefix arrays), each probe a binary
+//     search in its own column's run;
 //   * long columns: one 64-lane wavefront per v stages N(G_jk,v) alone and
 //     the lanes share the probes of all in-neighbours u (the same segments,
 //     handed out by a wavefront prefix sum);
 //   * hub columns (in-slice longer than `split`): the host cuts the in-slice
 //     into chunks that are separate work items; a whole workgroup stages
 //     N(G_jk,v) once and its four wavefronts share the chunk's in-neighbours.
-// A column's own stage is either the Intersect form// The stage is either the Intersect form (a sorted LDS copy, binary search)
-// or the HMap form (a dense LDS bitmap over the columns of V_k -- the paper's
-// dense hash map of the block's column range -- or, when V_k is too wide for
-// LDS, an open-addressing LDS hash).  Lists longer than the LDS buffer are
-// staged in disjoint pieces; a probe matches at most one piece, so the count
-// stays exact.
+// A column's own stage is either the Intersect form (a sorted LDS copy,
+// binary search) or the HMap form (a dense LDS bitmap over the columns of
+// V_k -- the paper's dense hash map of the block's column range -- or, when
+// V_k is too wide for LDS, an open-addressing LDS hash).  Lists longer than
+// the LDS buffer are staged in disjoint pieces; a probe matches at most one
+// piece, so the count stays exact.
 #include "bbtc_internal.h"
 #include "dev_common.h"
 
@@ -67,29 +68,16 @@ __device__ __forceinline__ void load_seg(const int32_t* __restrict__ col, uint32
     if (s0 + x < a0 || s0 + x >= a1) w[x] = 0xFFFFFFFFu;
 }
 
-constexpr uint32_t kShareCap = 4 * kABuf;  // words of the workgroup-wide stage
-
 struct WaveScratch {        // per wave: one batch of 64 in-neighbours
   uint32_t sa0[4][kWave];   // start of N(G_ik,u)
   uint32_t sa1[4][kWave];   // end of N(G_ik,u)
   uint32_t sex[4][kWave];   // exclusive prefix of the segment counts
-};
-struct ShareScratch {       // whole workgroup: one chunk of 256 in-neighbours
-  uint32_t a0[kThreads];    // start of N(G_ik,u)
-  uint32_t a1[kThreads];    // end of N(G_ik,u)
-  uint32_t col[kThreads];   // short column (index into the packed list) of u
-  uint32_t ex[kThreads];    // exclusive prefix of the segment counts
+  uint32_t scol[4][kWave];  // short columns: the packed column of u
 };
 
 struct CountLds {
-  union {
-    uint32_t abuf[4][kABuf];       // per wave: sorted copy / bitmap / hash of one list
-    uint32_t sbuf[kShareCap];      // workgroup: sorted lists of a window of short columns
-  };                               // all-zero between uses
-  union {
-    WaveScratch w;
-    ShareScratch b;
-  };
+  uint32_t abuf[4][kABuf];         // per wave: sorted copy / bitmap / hash; all-zero between uses
+  WaveScratch w;
   uint32_t c0s[kThreads];          // short columns of a pass, packed: start of N(G_jk,v)
   uint32_t i0s[kThreads];          // start of the in-slice
   uint32_t soff[kThreads + 1];     // exclusive prefix of list lengths
@@ -362,75 +350,74 @@ __device__ __forceinline__ uint32_t run_has(const uint32_t* buf, uint32_t lo, ui
   return (lo < end && buf[lo] == w) ? 1u : 0u;
 }
 
-// The packed short columns [0, ns) of a pass (bounds in c0s/i0s, prefixes in
-// soff/ioff), by the whole workgroup, window by window: a window is the
-// longest run of columns whose lists fit kShareCap words together.
-__device__ uint64_t short_cols(const TaskCtx& c, CountLds& s, uint32_t ns) {
+// Packed short columns [a0, b0) of a pass (bounds in c0s/i0s, prefixes in
+// soff/ioff), by one wavefront, window by window: a window is the longest run
+// of columns whose lists fit the wavefront's stage together.  The lists are
+// copied, sorted, side by side; every probe is a binary search in its own
+// column's run.
+__device__ uint64_t short_cols(const TaskCtx& c, CountLds& s, uint32_t a0, uint32_t b0, int w) {
   const int32_t* __restrict__ colj = c.colj;
   const int32_t* __restrict__ coli = c.coli;
   const int32_t* __restrict__ icol = c.icolj;
-  const uint32_t t = threadIdx.x;
+  const uint32_t l = (uint32_t)lane_id();
+  uint32_t* stage = s.abuf[w];
+  uint32_t* sa0 = s.w.sa0[w];
+  uint32_t* sa1 = s.w.sa1[w];
+  uint32_t* sex = s.w.sex[w];
+  uint32_t* scol = s.w.scol[w];
   uint64_t cnt = 0;
-  for (uint32_t a = 0; a < ns;) {  // uniform across the workgroup
+  for (uint32_t a = a0; a < b0;) {  // uniform across the wavefront
     const uint32_t sbase = s.soff[a];
-    uint32_t b = a + 1, hi = ns;  // largest b in [a+1, ns] with soff[b] - sbase <= kShareCap
+    uint32_t b = a + 1, hi = b0;  // largest b in [a+1, b0] with soff[b] - sbase <= kABuf
     while (b < hi) {
       const uint32_t mid = (b + hi + 1) >> 1;
-      if (s.soff[mid] - sbase <= kShareCap) b = mid; else hi = mid - 1;
+      if (s.soff[mid] - sbase <= (uint32_t)kABuf) b = mid; else hi = mid - 1;
     }
     const uint32_t span = s.soff[b] - sbase;
-    for (uint32_t g = t; g < span; g += kThreads) {
+    for (uint32_t g = l; g < span; g += kWave) {
       const uint32_t k = owner_of(s.soff, a, b, sbase + g);
-      s.sbuf[g] = (uint32_t)colj[s.c0s[k] + (sbase + g - s.soff[k])];
+      stage[g] = (uint32_t)colj[s.c0s[k] + (sbase + g - s.soff[k])];
     }
-    __syncthreads();
+    wave_sync();
     const uint32_t iend = s.ioff[b];
-    for (uint32_t eb = s.ioff[a]; eb < iend; eb += kThreads) {  // uniform
-      const uint32_t e = eb + t;
-      uint32_t a0 = 0, a1 = 0, k = 0;
+    for (uint32_t eb = s.ioff[a]; eb < iend; eb += kWave) {  // uniform
+      const uint32_t e = eb + l;
+      uint32_t u0 = 0, u1 = 0, k = a;
       if (e < iend) {
         k = owner_of(s.ioff, a, b, e);
         const int32_t u = icol[s.i0s[k] + (e - s.ioff[k])];
         const uint32_t* ur = c.boti + (uint64_t)(u - c.ci) * c.stri;
-        a0 = ur[c.dk];
-        a1 = ur[c.dk + 1];
+        u0 = ur[c.dk];
+        u1 = ur[c.dk + 1];
       }
-      const uint32_t nseg = seg_count(a0, a1);
-      uint32_t tot;
-      const uint32_t ex = block256_excl_scan(nseg, (uint32_t*)s.red, &tot);
-      s.b.a0[t] = a0;
-      s.b.a1[t] = a1;
-      s.b.col[t] = k;
-      s.b.ex[t] = ex;
-      __syncthreads();
-      for (uint32_t qb = 0; qb < tot; qb += 2 * kThreads) {  // two segments per thread per round
-        uint32_t w[2][kSeg], rlo[2], rhi[2];
+      const uint32_t nseg = seg_count_w(u0, u1);
+      const uint32_t inc = wave_incl_scan_u32(nseg);
+      const uint32_t tot = __shfl(inc, kWave - 1, kWave);
+      sa0[l] = u0;
+      sa1[l] = u1;
+      sex[l] = inc - nseg;
+      scol[l] = k;
+      wave_sync();
+      uint32_t lc = 0;
+      for (uint32_t qb = 0; qb < tot; qb += kWave) {
+        const uint32_t q = qb + l;
+        if (q < tot) {
+          const uint32_t o = owner_of(sex, 0, kWave, q);
+          const uint32_t k2 = scol[o];
+          const uint32_t lo = s.soff[k2] - sbase, hi2 = s.soff[k2 + 1] - sbase;
+          uint32_t wv[kSegW];
+          load_seg_w(coli, sa0[o], sa1[o], q - sex[o], wv);
+          const uint32_t wmin = stage[lo], wmax = stage[hi2 - 1];
 #pragma unroll
-        for (uint32_t h = 0; h < 2; ++h) {
-          const uint32_t q = qb + h * kThreads + t;
-          rlo[h] = rhi[h] = 0;
-          if (q < tot) {
-            const uint32_t o = owner_of(s.b.ex, 0, kThreads, q);
-            const uint32_t k2 = s.b.col[o];
-            rlo[h] = s.soff[k2] - sbase;
-            rhi[h] = s.soff[k2 + 1] - sbase;
-            load_seg(coli, s.b.a0[o], s.b.a1[o], q - s.b.ex[o], w[h]);
-          }
-        }
-#pragma unroll
-        for (uint32_t h = 0; h < 2; ++h) {
-          if (rhi[h] > rlo[h]) {
-            const uint32_t wmin = s.sbuf[rlo[h]], wmax = s.sbuf[rhi[h] - 1];
-#pragma unroll
-            for (uint32_t x = 0; x < kSeg; ++x)
-              if (w[h][x] >= wmin && w[h][x] <= wmax) cnt += run_has(s.sbuf, rlo[h], rhi[h], w[h][x]);
-          }
+          for (uint32_t x = 0; x < kSegW; ++x)
+            if (wv[x] >= wmin && wv[x] <= wmax) lc += run_has(stage, lo, hi2, wv[x]);
         }
       }
-      __syncthreads();
+      cnt += lc;
+      wave_sync();
     }
-    for (uint32_t g = t; g < span; g += kThreads) s.sbuf[g] = 0;
-    __syncthreads();
+    for (uint32_t g = l; g < span; g += kWave) stage[g] = 0;
+    wave_sync();
     a = b;
   }
   return cnt;
@@ -438,11 +425,12 @@ __device__ uint64_t short_cols(const TaskCtx& c, CountLds& s, uint32_t ns) {
 
 // Active columns [lo, hi) of block (i,j), by the whole workgroup, 256 per
 // pass.  Columns with in-slices longer than cp.split are left to their split
-// items; columns whose lists reach wave_min get a wavefront of their own, the
-// others are packed for short_cols.
+// items; columns whose lists reach wave_min get a wavefront of their own (a
+// shared queue hands them out), the others are packed and split into four
+// runs of about equal in-slice volume, one per wavefront (short_cols).
 __device__ uint64_t process_cols(const PlanCtx& cp, const TaskCtx& c, uint32_t lo, uint32_t hi, CountLds& s) {
   const int t = threadIdx.x, w = t / kWave;
-  const uint32_t own_min = min((uint32_t)cp.wave_min, kShareCap);
+  const uint32_t own_min = min((uint32_t)cp.wave_min, (uint32_t)kABuf);
   uint64_t cnt = 0;
   for (uint32_t base = lo; base < hi; base += kThreads) {
     const uint32_t x = base + t;
@@ -478,8 +466,23 @@ __device__ uint64_t process_cols(const PlanCtx& cp, const TaskCtx& c, uint32_t l
       const bool use_hash = cp.hash_min >= 0 && (qc1 - qc0) >= (uint32_t)cp.hash_min;
       cnt += wave_col(c, qi0, qi1, qc0, qc1, use_hash, s.abuf[w], s.w.sa0[w], s.w.sa1[w], s.w.sex[w]);
     }
-    __syncthreads();  // the per-wave stages are clear again before the shared one is filled
-    if (ns) cnt += short_cols(c, s, ns);
+    if (ns) {
+      // this wavefront's run: the columns whose in-slices start in its quarter
+      const uint32_t itot = s.ioff[ns];
+      uint32_t ab[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const uint32_t target = (uint32_t)(((uint64_t)itot * (uint32_t)(w + h)) / 4u);
+        uint32_t x0 = 0, x1 = ns;  // first column with ioff >= target
+        while (x0 < x1) {
+          const uint32_t mid = (x0 + x1) >> 1;
+          if (s.ioff[mid] < target) x0 = mid + 1; else x1 = mid;
+        }
+        ab[h] = (w + h == 4) ? ns : x0;
+      }
+      if (ab[0] < ab[1]) cnt += short_cols(c, s, ab[0], ab[1], w);
+    }
+    __syncthreads();
     if (t == 0) s.qn = 0;
     __syncthreads();
   }
