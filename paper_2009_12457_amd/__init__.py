@@ -95,6 +95,12 @@ _SIGS = {
 
 
 def _load():
+    # torch first: libbbtc.so then binds to the HIP runtime that torch has
+    # already loaded (same soname), so one runtime owns every device pointer
+    # and stream in the process.  Loaded the other way round, the process
+    # would hold two runtimes and the library would not recognise torch's
+    # allocations.
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built (run __graft_entry__.build() or "
                           f"python paper_2009_12457_amd/build.py)")

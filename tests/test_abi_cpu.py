@@ -80,3 +80,17 @@ def test_rowptr_bits_check():
 def test_count_on_missing_plan_is_estate():
     st = bb._lib.bbtc_count(None, None, None, None)
     assert st == bb.BBTC_ESTATE
+
+
+def test_one_hip_runtime_whatever_the_import_order():
+    """Importing the package before torch must not load a second HIP runtime:
+    the library has to recognise torch's device pointers and streams."""
+    import subprocess
+    import sys
+    code = ("import paper_2009_12457_amd\nimport torch\n"
+            "print(sorted({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=600)
+    assert out.returncode == 0, out.stderr
+    libs = eval(out.stdout.strip().splitlines()[-1])
+    assert len(libs) == 1, libs
