@@ -55,9 +55,10 @@ typedef int32_t bbtc_status;
  * self-loops.  n = |V| < 2^31; nnz = 2|E| and |E| < 2^32.
  * rowptr has n+1 entries of rowptr_bits (32 or 64) bits, rowptr[0] = 0 and
  * rowptr[n] = nnz.  colidx has nnz entries in [0, n).
- * Host inputs are validated on the host before any device call; device
- * inputs are validated by a kernel.  Either way a violation returns
- * BBTC_EINVAL.
+ * Host inputs are validated on the host before any device call (with
+ * BBTC_CSR_TRUSTED only their rowptr; their entries are then checked by a
+ * kernel right after the upload); device inputs are validated by a kernel.
+ * Either way a violation returns BBTC_EINVAL.
  */
 typedef struct bbtc_csr {
   int64_t n;

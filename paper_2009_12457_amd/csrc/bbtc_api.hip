@@ -196,12 +196,16 @@ struct bbtc_plan {
 namespace {
 
 // ------------------------------------------------------------ host validation
+// rows == false: only rowptr (O(n)); the entries are then checked by the
+// device validation kernels after the upload.
 template <typename RP>
-bbtc_status validate_host(const RP* rowptr, const int32_t* col, int64_t n, int64_t nnz, bool symmetric) {
+bbtc_status validate_host(const RP* rowptr, const int32_t* col, int64_t n, int64_t nnz, bool symmetric,
+                          bool rows = true) {
   if ((int64_t)rowptr[0] != 0) return fail(BBTC_EINVAL, "rowptr[0] must be 0");
   if ((int64_t)rowptr[n] != nnz) return fail(BBTC_EINVAL, "rowptr[n] must equal nnz");
   for (int64_t x = 0; x < n; ++x)
     if ((int64_t)rowptr[x + 1] < (int64_t)rowptr[x]) return fail(BBTC_EINVAL, "rowptr must be non-decreasing");
+  if (!rows) return BBTC_OK;
   unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   if (n < 100000) nt = 1;
   std::vector<uint32_t> bad(nt, 0);
@@ -687,8 +691,10 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   const bool symmetric_check = (g->flags & BBTC_CSR_TRUSTED) == 0;
   const int rp64 = g->rowptr_bits == 64;
   if (!on_device) {
-    bbtc_status st = rp64 ? validate_host((const int64_t*)g->rowptr, g->colidx, n, nnz, symmetric_check)
-                          : validate_host((const int32_t*)g->rowptr, g->colidx, n, nnz, symmetric_check);
+    // trusted host input: rowptr here, the entries on the device after the upload
+    const bool rows = symmetric_check;
+    bbtc_status st = rp64 ? validate_host((const int64_t*)g->rowptr, g->colidx, n, nnz, symmetric_check, rows)
+                          : validate_host((const int32_t*)g->rowptr, g->colidx, n, nnz, symmetric_check, rows);
     if (st != BBTC_OK) return st;
   } else if (!is_device_pointer(g->rowptr) || (nnz > 0 && !is_device_pointer(g->colidx))) {
     return fail(BBTC_EINVAL, "BBTC_CSR_DEVICE set but rowptr/colidx are not device memory");
@@ -724,7 +730,8 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
       HIP_TRY(hipMemcpyAsync(pl->in_col.ptr, g->colidx, (size_t)nnz * 4, hipMemcpyHostToDevice, s), "H2D colidx");
     rowptr = pl->in_rowptr.ptr;
     col = pl->in_col.ptr;
-  } else {
+  }
+  if (on_device || !symmetric_check) {  // entries not yet checked on the host
     HIP_TRY(pl->err.ensure(8), "alloc");
     HIP_TRY(pl->longrows.ensure((size_t)n), "alloc");
     HIP_TRY(pl->hugerows.ensure((size_t)n), "alloc");

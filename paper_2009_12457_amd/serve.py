@@ -50,8 +50,14 @@ def footprint_estimate(n: int, nnz: int, p: int) -> int:
 
 
 def default_p(n: int, nnz: int) -> int:
-    """Block count prior: about the average degree (Sec. 6)."""
-    return max(1, min(int(n), int(round(nnz / max(int(n), 1)))))
+    """Block count for a request, by edge count: 4 below 4M edges, 8 below
+    24M, else 16 (measured partition + count time over R-MAT scale 12-22 and
+    Erdos-Renyi n = 1e4-1e6 graphs on MI355X; the paper's prior, p near the
+    average degree, was up to 3x slower on the small and medium graphs of
+    this mix)."""
+    m = int(nnz) // 2
+    p = 4 if m < (4 << 20) else 8 if m < (24 << 20) else 16
+    return max(1, min(int(n), p))
 
 
 @dataclass
@@ -62,6 +68,7 @@ class Result:
     tasks: np.ndarray
     arrival: float
     done: float
+    stamps: dict = field(default_factory=dict)  # admitted / partitioned / launched (perf_counter seconds)
 
     @property
     def latency(self) -> float:
@@ -79,6 +86,7 @@ class _Req:
     future: concurrent.futures.Future
     need: int = 0
     charge: int = 0  # bytes counted against the budget while in flight
+    stamps: dict = field(default_factory=dict)
     plan: object = None
     event: object = None
     tasks: object = None
@@ -159,7 +167,7 @@ class PlanPool:
 
 
 class Server:
-    def __init__(self, hbm_budget_bytes: int, compute_streams: int = 2, partition_workers: int = 3, p: int = 0,
+    def __init__(self, hbm_budget_bytes: int, compute_streams: int = 2, partition_workers: int = 8, p: int = 0,
                  max_batch: int = 256, options=None):
         import torch
         self.torch = torch
@@ -242,6 +250,7 @@ class Server:
         if got is None:
             return False
         req.plan, req.charge = got
+        req.stamps["admitted"] = time.perf_counter()
         self.waiting.popleft()
         self.admitted.append(req)
         self.cv.notify_all()
@@ -266,6 +275,7 @@ class Server:
                 held = int(req.plan.stats()["footprint"])
                 req.event = self.torch.cuda.Event()
                 req.event.record(stream)
+                req.stamps["partitioned"] = time.perf_counter()
             except Exception as e:  # invalid input etc.: fail this request only
                 err = e
             with self.cv:
@@ -285,8 +295,10 @@ class Server:
                 return False
             reqs, self.ready = self.ready[:self.max_batch], self.ready[self.max_batch:]
             stream = self.free_streams.popleft()
+        now = time.perf_counter()
         for r in reqs:  # plans were built on the workers' streams
             stream.wait_event(r.event)
+            r.stamps["launched"] = now
         with torch.cuda.stream(stream):
             pers = [torch.empty(max(r.plan.ntasks, 1), dtype=torch.int64, device="cuda") for r in reqs]
             totals = torch.empty(len(reqs), dtype=torch.int64, device="cuda")
@@ -314,7 +326,7 @@ class Server:
                 finished = []
                 for q, r in enumerate(b.reqs):
                     per = b.per_host[q].numpy().view(np.uint64)[:r.plan.ntasks].copy()
-                    finished.append((r, Result(r.rid, int(tot[q]), per, r.tasks, r.arrival, now)))
+                    finished.append((r, Result(r.rid, int(tot[q]), per, r.tasks, r.arrival, now, r.stamps)))
                 with self.cv:
                     for r, _ in finished:
                         self.pool.give_back(r.plan, r.charge)
@@ -395,3 +407,19 @@ def latency_summary(results, warmup: int = 0):
         return {}
     return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "mean_ms": float(lat.mean()), "requests": int(len(lat))}
+
+
+def stage_summary(results, warmup: int = 0):
+    """Mean time (ms) a served request spends waiting for admission, being
+    partitioned, waiting for its launch, and on the GPU until its results are
+    on the host."""
+    keys = ("admitted", "partitioned", "launched")
+    rs = [r for r in results[warmup:] if all(k in r.stamps for k in keys)]
+    if not rs:
+        return {}
+    def mean(f):
+        return float(np.mean([f(r) for r in rs]) * 1e3)
+    return {"admission_wait_ms": mean(lambda r: r.stamps["admitted"] - r.arrival),
+            "partition_ms": mean(lambda r: r.stamps["partitioned"] - r.stamps["admitted"]),
+            "launch_wait_ms": mean(lambda r: r.stamps["launched"] - r.stamps["partitioned"]),
+            "count_ms": mean(lambda r: r.done - r.stamps["launched"])}

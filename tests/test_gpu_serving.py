@@ -66,7 +66,7 @@ def test_server_results_exact_alone_and_in_mix():
 
 def test_server_budget_admission_and_rejection():
     gs = pool()[:6]
-    need = [serve.footprint_estimate(g.n, len(g.colidx), max(1, round(len(g.colidx) / g.n))) for g in gs]
+    need = [serve.footprint_estimate(g.n, len(g.colidx), serve.default_p(g.n, len(g.colidx))) for g in gs]
     budget = max(need) + 1  # only about one request fits at a time
     srv = serve.Server(hbm_budget_bytes=budget, compute_streams=2)
     try:

@@ -106,9 +106,10 @@ def test_conservation_random_sequences():
 
 
 def test_footprint_estimate_and_p_prior():
-    assert default_p(1000, 32000) == 32
-    assert default_p(10, 2) == 1
-    assert default_p(5, 200) == 5  # never more parts than vertices
+    assert default_p(1000, 32000) == 4
+    assert default_p(10, 2) == 4 and default_p(3, 4) == 3  # never more parts than vertices
+    assert default_p(1 << 20, 2 * (8 << 20)) == 8
+    assert default_p(1 << 22, 2 * (64 << 20)) == 16
     a = footprint_estimate(1 << 16, 1 << 20, 16)
     b = footprint_estimate(1 << 16, 1 << 21, 16)
     assert b - a == 12 * (1 << 19) + 4 * (1 << 20)
