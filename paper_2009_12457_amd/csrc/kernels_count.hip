@@ -38,10 +38,9 @@ namespace {
 #define BBTC_STAGE_WORDS 512
 #endif
 constexpr int kABuf = BBTC_STAGE_WORDS;       // LDS words per wavefront
-constexpr uint32_t kBitmapBits = kABuf * 32;  // bitmap capacity in columns
+constexpr uint32_t kGroupWords = 4 * kABuf;   // the four wavefront buffers as one workgroup stage
 constexpr int log2i(int x) { return x <= 1 ? 0 : 1 + log2i(x / 2); }
-constexpr int kHashBits = log2i(kABuf);       // kABuf hash slots
-static_assert((1 << kHashBits) == kABuf, "stage size must be a power of two");
+static_assert((1 << log2i(kABuf)) == kABuf, "stage size must be a power of two");
 
 // Probes per flattened work unit: one 16-byte aligned block of an out-row,
 // read by a single 128-bit load (the blocks of N(G_ik,u) are aligned on the
@@ -82,8 +81,9 @@ struct CountLds {
   uint32_t i0s[kThreads];          // start of the in-slice
   uint32_t soff[kThreads + 1];     // exclusive prefix of list lengths
   uint32_t ioff[kThreads + 1];     // exclusive prefix of in-slice lengths
-  uint32_t q[kThreads];            // long columns of a pass (active-column index)
-  uint32_t qn;
+  uint32_t q[kThreads];            // long columns of a pass (active-column index): from the
+                                   // front those of one wavefront, from the back the wide ones
+  uint32_t qn, qw;
   uint32_t item;
   unsigned long long red[4];
 };
@@ -133,7 +133,7 @@ __device__ __forceinline__ TaskCtx make_ctx(const GraphView& g, const DevTask& t
   return c;
 }
 
-__device__ __forceinline__ uint32_t hash_slot(uint32_t w) { return (w * 0x9E3779B1u) >> (32 - kHashBits); }
+__device__ __forceinline__ uint32_t hash_slot(uint32_t w, int hbits) { return (w * 0x9E3779B1u) >> (32 - hbits); }
 
 // Largest k in [a, b) with off[k] <= x (off non-decreasing, off[a] <= x).
 __device__ __forceinline__ uint32_t owner_of(const uint32_t* off, uint32_t a, uint32_t b, uint32_t x) {
@@ -145,16 +145,29 @@ __device__ __forceinline__ uint32_t owner_of(const uint32_t* off, uint32_t a, ui
   return lo;
 }
 
-// How a stage of N(G_jk,v) is held: 0 sorted copy, 1 bitmap over V_k, 2 hash.
+// How a stage of N(G_jk,v) is held in a buffer of nw words (a power of
+// two): 0 sorted copy, 1 bitmap over V_k, 2 open-addressing hash at load at
+// most 1/2.
 struct Stage {
   int mode;
   uint32_t piece;  // entries staged at a time
+  uint32_t nw;     // buffer words
+  int hbits;       // log2(nw)
 };
 
+template <uint32_t NW>
 __device__ __forceinline__ Stage pick_stage(const TaskCtx& c, bool use_hash, uint32_t len) {
-  if (!use_hash) return Stage{0, (uint32_t)kABuf};
-  if ((uint32_t)(c.ck1 - c.ck) <= kBitmapBits) return Stage{1, len};
-  return Stage{2, (uint32_t)kABuf / 2};
+  constexpr int hb = log2i((int)NW);
+  if (!use_hash) return Stage{0, NW, NW, hb};
+  if ((uint32_t)(c.ck1 - c.ck) <= NW * 32u) return Stage{1, len, NW, hb};
+  return Stage{2, NW / 2, NW, hb};
+}
+
+// Pieces a list of len entries needs in a buffer of NW words.
+template <uint32_t NW>
+__device__ __forceinline__ uint32_t pieces(const TaskCtx& c, bool use_hash, uint32_t len) {
+  const Stage st = pick_stage<NW>(c, use_hash, len);
+  return (len + st.piece - 1) / st.piece;
 }
 
 // Fills buf with col[lo, lo+sn) by `nthr` cooperating threads numbered tid.
@@ -170,8 +183,8 @@ __device__ __forceinline__ void stage_fill(const Stage& st, uint32_t* buf, const
   } else {
     for (uint32_t t = tid; t < sn; t += nthr) {
       const uint32_t key = (uint32_t)col[lo + t] + 1u;  // 0 marks an empty slot
-      uint32_t s = hash_slot(key - 1u);
-      for (int guard = 0; guard < kABuf && atomicCAS(&buf[s], 0u, key) != 0u; ++guard) s = (s + 1) & (kABuf - 1);
+      uint32_t s = hash_slot(key - 1u, st.hbits);
+      for (uint32_t guard = 0; guard < st.nw && atomicCAS(&buf[s], 0u, key) != 0u; ++guard) s = (s + 1) & (st.nw - 1);
     }
   }
 }
@@ -184,7 +197,7 @@ __device__ __forceinline__ void stage_clear(const Stage& st, uint32_t* buf, cons
   } else if (st.mode == 1) {
     for (uint32_t t = tid; t < sn; t += nthr) buf[(uint32_t)(col[lo + t] - ck) >> 5] = 0;
   } else {
-    for (uint32_t t = tid; t < (uint32_t)kABuf; t += nthr) buf[t] = 0;
+    for (uint32_t t = tid; t < st.nw; t += nthr) buf[t] = 0;
   }
 }
 
@@ -203,12 +216,12 @@ __device__ __forceinline__ uint32_t stage_has(const Stage& st, const uint32_t* b
     return (buf[x >> 5] >> (x & 31)) & 1u;
   }
   const uint32_t key = (uint32_t)w + 1u;
-  uint32_t s = hash_slot((uint32_t)w);
-  for (int guard = 0; guard < kABuf; ++guard) {
+  uint32_t s = hash_slot((uint32_t)w, st.hbits);
+  for (uint32_t guard = 0; guard < st.nw; ++guard) {
     const uint32_t kk = buf[s];
     if (kk == key) return 1u;
     if (kk == 0u) return 0u;
-    s = (s + 1) & (kABuf - 1);
+    s = (s + 1) & (st.nw - 1);
   }
   return 0u;
 }
@@ -315,7 +328,7 @@ __device__ uint64_t wave_col(const TaskCtx& c, uint32_t i0, uint32_t i1, uint32_
   const int32_t* __restrict__ col = c.colj;
   const uint32_t l = (uint32_t)lane_id();
   uint64_t cnt = 0;
-  const Stage st = pick_stage(c, use_hash, c1 - c0);
+  const Stage st = pick_stage<kABuf>(c, use_hash, c1 - c0);
   for (uint32_t s_lo = c0; s_lo < c1; s_lo += st.piece) {
     const uint32_t sn = min(st.piece, c1 - s_lo);
     stage_fill(st, abuf, col, s_lo, sn, c.ck, l, kWave);
@@ -423,11 +436,16 @@ __device__ uint64_t short_cols(const TaskCtx& c, CountLds& s, uint32_t a0, uint3
   return cnt;
 }
 
+__device__ uint64_t group_col(const PlanCtx& cp, const TaskCtx& c, uint32_t i0, uint32_t i1, uint32_t c0, uint32_t c1,
+                              CountLds& s);
+
 // Active columns [lo, hi) of block (i,j), by the whole workgroup, 256 per
 // pass.  Columns with in-slices longer than cp.split are left to their split
 // items; columns whose lists reach wave_min get a wavefront of their own (a
-// shared queue hands them out), the others are packed and split into four
-// runs of about equal in-slice volume, one per wavefront (short_cols).
+// shared queue hands them out) or, if only the four buffers together hold
+// their list in fewer pieces, the whole workgroup; the others are packed and
+// split into four runs of about equal in-slice volume, one per wavefront
+// (short_cols).
 __device__ uint64_t process_cols(const PlanCtx& cp, const TaskCtx& c, uint32_t lo, uint32_t hi, CountLds& s) {
   const int t = threadIdx.x, w = t / kWave;
   const uint32_t own_min = min((uint32_t)cp.wave_min, (uint32_t)kABuf);
@@ -439,7 +457,16 @@ __device__ uint64_t process_cols(const PlanCtx& cp, const TaskCtx& c, uint32_t l
     const bool live = c1 > c0 && i1 > i0 && (cp.split == 0 || i1 - i0 <= cp.split);
     // in-slices up to 2^24 keep the packed prefix below in range
     const bool own = live && ((c1 - c0) >= own_min || (i1 - i0) >= (1u << 24) / kThreads);
-    if (own) s.q[atomicAdd(&s.qn, 1u)] = x;
+    if (own) {
+      // lists that a wavefront's buffer holds only in pieces go to the whole
+      // workgroup when its four buffers need fewer pieces
+      const bool use_hash = cp.hash_min >= 0 && (c1 - c0) >= (uint32_t)cp.hash_min;
+      const uint32_t pw = pieces<kABuf>(c, use_hash, c1 - c0);
+      if (pw > 1 && pieces<kGroupWords>(c, use_hash, c1 - c0) < pw)
+        s.q[kThreads - 1 - atomicAdd(&s.qw, 1u)] = x;
+      else
+        s.q[atomicAdd(&s.qn, 1u)] = x;
+    }
     const bool sh = live && !own;
     // one 64-bit scan packs: count (bits 0-8), in-slice length (9-33), list length (34-63)
     const unsigned long long pk =
@@ -482,32 +509,33 @@ __device__ uint64_t process_cols(const PlanCtx& cp, const TaskCtx& c, uint32_t l
       }
       if (ab[0] < ab[1]) cnt += short_cols(c, s, ab[0], ab[1], w);
     }
-    __syncthreads();
-    if (t == 0) s.qn = 0;
+    __syncthreads();  // every wavefront buffer is clear again: they form one stage now
+    const uint32_t nwide = s.qw;
+    for (uint32_t h = 0; h < nwide; ++h) {
+      uint32_t qc0, qc1, qi0, qi1;
+      col_bounds(c, s.q[kThreads - 1 - h], qc0, qc1, qi0, qi1);
+      cnt += group_col(cp, c, qi0, qi1, qc0, qc1, s);
+    }
+    if (t == 0) s.qn = s.qw = 0;
     __syncthreads();
   }
   return cnt;
 }
 
-// One chunk [lo, hi) of the in-slice of hub column v, by the whole workgroup:
-// N(G_jk,v) is staged once in the first wave's buffer and each of the four
-// wavefronts probes a quarter of the chunk's in-neighbours against it.
-__device__ uint64_t hub_chunk(const PlanCtx& cp, const TaskCtx& c, int32_t v, uint32_t lo, uint32_t hi,
+// In-slice [i0, i1) of column v against N(G_jk,v) = col[c0, c1), by the
+// whole workgroup: the four wavefront buffers form one stage of kGroupWords
+// words (all zero on entry and on exit), filled once per piece by all
+// threads, and each wavefront probes a quarter of the in-neighbours.
+__device__ uint64_t group_col(const PlanCtx& cp, const TaskCtx& c, uint32_t i0, uint32_t i1, uint32_t c0, uint32_t c1,
                               CountLds& s) {
   const int32_t* __restrict__ col = c.colj;
   const int w = threadIdx.x / kWave;
-  const uint32_t* vr = c.botj + (uint64_t)(v - c.cj) * c.strj;
-  const uint32_t c0 = vr[c.dkj], c1 = vr[c.dkj + 1];
-  const uint32_t* tr = c.tbotj + (uint64_t)(v - c.cj) * c.tstrj;
-  const uint32_t ib = tr[c.i], ie = tr[c.i + 1];
-  const uint32_t i0 = min(ib + lo, ie), i1 = min(ib + hi, ie);
   uint64_t cnt = 0;
-  if (c1 <= c0 || i1 <= i0) return 0;  // uniform across the workgroup
   const uint32_t per = (i1 - i0 + 3) / 4;
   const uint32_t w0 = min(i0 + per * w, i1), w1 = min(w0 + per, i1);
   const bool use_hash = cp.hash_min >= 0 && (c1 - c0) >= (uint32_t)cp.hash_min;
-  const Stage st = pick_stage(c, use_hash, c1 - c0);
-  uint32_t* buf = s.abuf[0];
+  const Stage st = pick_stage<kGroupWords>(c, use_hash, c1 - c0);
+  uint32_t* buf = &s.abuf[0][0];
   for (uint32_t s_lo = c0; s_lo < c1; s_lo += st.piece) {
     const uint32_t sn = min(st.piece, c1 - s_lo);
     stage_fill(st, buf, col, s_lo, sn, c.ck, threadIdx.x, kThreads);
@@ -521,10 +549,22 @@ __device__ uint64_t hub_chunk(const PlanCtx& cp, const TaskCtx& c, int32_t v, ui
   return cnt;
 }
 
+// One chunk [lo, hi) of the in-slice of hub column v, by the whole workgroup.
+__device__ uint64_t hub_chunk(const PlanCtx& cp, const TaskCtx& c, int32_t v, uint32_t lo, uint32_t hi,
+                              CountLds& s) {
+  const uint32_t* vr = c.botj + (uint64_t)(v - c.cj) * c.strj;
+  const uint32_t c0 = vr[c.dkj], c1 = vr[c.dkj + 1];
+  const uint32_t* tr = c.tbotj + (uint64_t)(v - c.cj) * c.tstrj;
+  const uint32_t ib = tr[c.i], ie = tr[c.i + 1];
+  const uint32_t i0 = min(ib + lo, ie), i1 = min(ib + hi, ie);
+  if (c1 <= c0 || i1 <= i0) return 0;  // uniform across the workgroup
+  return group_col(cp, c, i0, i1, c0, c1, s);
+}
+
 __device__ __forceinline__ void init_lds(CountLds& s) {
   uint32_t* a = &s.abuf[0][0];
   for (int t = threadIdx.x; t < 4 * kABuf; t += kThreads) a[t] = 0;
-  if (threadIdx.x == 0) s.qn = 0;
+  if (threadIdx.x == 0) s.qn = s.qw = 0;
   __syncthreads();
 }
 
