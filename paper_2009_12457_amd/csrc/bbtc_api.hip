@@ -731,7 +731,10 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
     rowptr = pl->in_rowptr.ptr;
     col = pl->in_col.ptr;
   }
-  if (on_device || !symmetric_check) {  // entries not yet checked on the host
+  // Untrusted device input: the validation kernels (with the symmetry check).
+  // Trusted input (host or device): the degree pass checks the rest below.
+  const int check_in_degs = symmetric_check ? 0 : 1;
+  if (on_device && symmetric_check) {
     HIP_TRY(pl->err.ensure(8), "alloc");
     HIP_TRY(pl->longrows.ensure((size_t)n), "alloc");
     HIP_TRY(pl->hugerows.ensure((size_t)n), "alloc");
@@ -775,15 +778,18 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   // ---- orientation: out-rows (higher ranks) and in-rows (lower ranks) ----
   // err[4]: rows too long for one lane, listed in longrows by launch_degs
   // err[4], err[5]: rows too long for one lane / huge rows, listed by launch_degs
-  HIP_TRY(launch_degs(rowptr, rp64, col, n, pl->perm.ptr, pl->od.ptr, pl->idg.ptr, pl->longrows.ptr, pl->err.ptr + 4,
-                      pl->hugerows.ptr, pl->err.ptr + 5, (uint32_t*)pl->keys_b.ptr, s),
+  HIP_TRY(launch_degs(rowptr, rp64, col, n, nnz, pl->perm.ptr, pl->od.ptr, pl->idg.ptr, pl->longrows.ptr,
+                      pl->err.ptr + 4, pl->hugerows.ptr, pl->err.ptr + 5, (uint32_t*)pl->keys_b.ptr, pl->err.ptr,
+                      check_in_degs, s),
           "degrees");
   HIP_TRY(scan_u32(pl->od.ptr, pl->orow.ptr, (uint64_t)n, pl->partial.ptr, s), "scan out-degrees");
   HIP_TRY(scan_u32(pl->idg.ptr, pl->irow.ptr, (uint64_t)n, pl->partial.ptr, s), "scan in-degrees");
-  uint32_t mm[2] = {0, 0};
+  uint32_t mm[3] = {0, 0, 0};
   HIP_TRY(hipMemcpyAsync(&mm[0], pl->orow.ptr + n, 4, hipMemcpyDeviceToHost, s), "D2H m");
   HIP_TRY(hipMemcpyAsync(&mm[1], pl->irow.ptr + n, 4, hipMemcpyDeviceToHost, s), "D2H m");
+  HIP_TRY(hipMemcpyAsync(&mm[2], pl->err.ptr, 4, hipMemcpyDeviceToHost, s), "D2H err");
   HIP_TRY(hipStreamSynchronize(s), "sync");
+  if (mm[2]) return decode_device_err(mm[2]);
   const uint64_t m = mm[0];
   if (m > mmax || mm[1] != mm[0]) return fail(BBTC_EINVAL, "input is not symmetric");
   pl->m = (int64_t)m;

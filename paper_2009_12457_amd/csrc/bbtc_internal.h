@@ -132,9 +132,9 @@ hipError_t radix_sort_u64(uint64_t* a, uint64_t* b, uint64_t count, int bits, ui
 // out[0..count] = exclusive scan of in[0..count), out[count] = total.
 hipError_t scan_u32(const uint32_t* in, uint32_t* out, uint64_t count, uint32_t* partial, hipStream_t s);
 hipError_t launch_perm(const uint64_t* keys, int64_t n, int idbits, int32_t* order, int32_t* perm, hipStream_t s);
-hipError_t launch_degs(const void* rowptr, int rp64, const int32_t* colidx, int64_t n, const int32_t* perm,
-                       uint32_t* od, uint32_t* idg, uint32_t* list, uint32_t* nlist, uint32_t* hlist,
-                       uint32_t* nhlist, uint32_t* hpref, hipStream_t s);
+hipError_t launch_degs(const void* rowptr, int rp64, const int32_t* colidx, int64_t n, int64_t nnz,
+                       const int32_t* perm, uint32_t* od, uint32_t* idg, uint32_t* list, uint32_t* nlist,
+                       uint32_t* hlist, uint32_t* nhlist, uint32_t* hpref, uint32_t* err, int check, hipStream_t s);
 // cur_o/cur_i: zeroed fill cursors of the huge rows (indexed by position in hlist).
 hipError_t launch_fill(const void* rowptr, int rp64, const int32_t* colidx, int64_t n, const int32_t* perm,
                        const uint32_t* orow, const uint32_t* irow, int32_t* ocol, int32_t* icol, const uint32_t* list,

@@ -291,16 +291,40 @@ __global__ __launch_bounds__(kThreads) void k_perm(const uint64_t* __restrict__ 
 // ------------------------------------------------------------ orientation
 // For original vertex x of rank r: neighbours y with rank(y) > r form the
 // out-row N(G,r), the others the in-row of r.
+// With `check` set, the degree pass also validates the input (every check
+// but symmetry): rowptr bounds per row (a bad row is skipped, its entries
+// never read), column range (a bad entry is not used as an index), self-
+// loops and strictly increasing rows, ORed into err as the validation
+// kernels do.
+template <typename RP>
+__device__ __forceinline__ uint32_t entry_flags(const int32_t* __restrict__ colidx, int64_t n, int64_t x,
+                                                int64_t rb, int64_t q, int32_t y) {
+  if (y < 0 || y >= n) return 1;
+  uint32_t e = 0;
+  if (y == x) e |= 4;
+  if (q > rb && colidx[q - 1] >= y) e |= 2;
+  return e;
+}
+
 template <typename RP>
 __global__ __launch_bounds__(kThreads) void k_degs_lane(const RP* __restrict__ rowptr,
-                                                        const int32_t* __restrict__ colidx, int64_t n,
+                                                        const int32_t* __restrict__ colidx, int64_t n, int64_t nnz,
                                                         const int32_t* __restrict__ perm, uint32_t* __restrict__ od,
                                                         uint32_t* __restrict__ idg, uint32_t* list, uint32_t* nlist,
-                                                        uint32_t* hlist, uint32_t* nhlist) {
+                                                        uint32_t* hlist, uint32_t* nhlist, uint32_t* err, int check) {
+  uint32_t bad = 0;
+  if (check && blockIdx.x == 0 && threadIdx.x == 0) {
+    if ((int64_t)rowptr[0] != 0 || (int64_t)rowptr[n] != nnz) bad |= 8;
+  }
   for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
     const int32_t r = perm[x];
     if (r < 0 || r >= n) continue;
     const int64_t b = (int64_t)rowptr[x], e = (int64_t)rowptr[x + 1];
+    if (check && (b < 0 || e < b || e > nnz)) {
+      bad |= 8;
+      od[r] = idg[r] = 0;
+      continue;
+    }
     if (e - b > kWaveRow) {
       od[r] = 0;
       idg[r] = 0;
@@ -312,24 +336,35 @@ __global__ __launch_bounds__(kThreads) void k_degs_lane(const RP* __restrict__ r
       continue;
     }
     uint32_t c = 0;
-    for (int64_t q = b; q < e; ++q) c += perm[colidx[q]] > r ? 1u : 0u;
+    for (int64_t q = b; q < e; ++q) {
+      const int32_t y = colidx[q];
+      if (check) {
+        const uint32_t f = entry_flags<RP>(colidx, n, x, b, q, y);
+        bad |= f;
+        if (f & 1) continue;
+      }
+      c += perm[y] > r ? 1u : 0u;
+    }
     od[r] = c;
     idg[r] = (uint32_t)(e - b) - c;
   }
+  if (bad) atomicOr(err, bad);
 }
 
 // Listed rows: one wavefront per row; huge rows: chunks counted by different
 // wavefronts and added to od/idg, which k_degs_lane zeroed for them.
 template <typename RP>
 __global__ __launch_bounds__(kThreads) void k_degs_wave(const RP* __restrict__ rowptr,
-                                                        const int32_t* __restrict__ colidx,
+                                                        const int32_t* __restrict__ colidx, int64_t n,
                                                         const int32_t* __restrict__ perm, uint32_t* __restrict__ od,
                                                         uint32_t* __restrict__ idg, const uint32_t* list,
                                                         const uint32_t* nlist, const uint32_t* hlist,
-                                                        const uint32_t* nhlist, const uint32_t* hpref) {
+                                                        const uint32_t* nhlist, const uint32_t* hpref, uint32_t* err,
+                                                        int check) {
   const int l = lane_id();
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  uint32_t bad = 0;
   const int64_t cnt = *nlist;
   for (int64_t i = wave; i < cnt; i += nwaves) {
     const int64_t x = list[i];
@@ -338,7 +373,14 @@ __global__ __launch_bounds__(kThreads) void k_degs_wave(const RP* __restrict__ r
     uint32_t c = 0;
     for (int64_t base = b; base < e; base += kWave) {
       const int64_t q = base + l;
-      c += (uint32_t)__popcll(ballot(q < e && perm[colidx[q]] > r));
+      bool up = false;
+      if (q < e) {
+        const int32_t y = colidx[q];
+        const uint32_t f = check ? entry_flags<RP>(colidx, n, x, b, q, y) : 0u;
+        bad |= f;
+        up = !(f & 1) && perm[y] > r;
+      }
+      c += (uint32_t)__popcll(ballot(up));
     }
     if (l == 0) {
       od[r] = c;
@@ -352,16 +394,25 @@ __global__ __launch_bounds__(kThreads) void k_degs_wave(const RP* __restrict__ r
     int64_t x, b, e;
     unit_of(rowptr, hlist, hpref, hcnt, u, &li, &x, &b, &e);
     const int32_t r = perm[x];
+    const int64_t rb = (int64_t)rowptr[x];
     uint32_t c = 0;
     for (int64_t base = b; base < e; base += kWave) {
       const int64_t q = base + l;
-      c += (uint32_t)__popcll(ballot(q < e && perm[colidx[q]] > r));
+      bool up = false;
+      if (q < e) {
+        const int32_t y = colidx[q];
+        const uint32_t f = check ? entry_flags<RP>(colidx, n, x, rb, q, y) : 0u;
+        bad |= f;
+        up = !(f & 1) && perm[y] > r;
+      }
+      c += (uint32_t)__popcll(ballot(up));
     }
     if (l == 0) {
       atomicAdd(&od[r], c);
       atomicAdd(&idg[r], (uint32_t)(e - b) - c);
     }
   }
+  if (bad) atomicOr(err, bad);
 }
 
 // Scatters rank ids into the out- and in-rows (order within a row follows the
@@ -558,7 +609,8 @@ __global__ __launch_bounds__(kThreads) void k_segsort(const uint32_t* __restrict
   }
 }
 
-// Wavefront per queued row of up to kSegWave entries: bitonic sort in LDS.
+// Wavefront per queued row of up to kSegWave entries: bitonic sort across the
+// lanes' registers for rows of up to 64 entries, in LDS beyond.
 __global__ __launch_bounds__(kThreads) void k_segsort_mid(const uint32_t* __restrict__ rp, int32_t* __restrict__ col,
                                                           const uint32_t* __restrict__ midrows,
                                                           const uint32_t* __restrict__ q) {
@@ -572,6 +624,20 @@ __global__ __launch_bounds__(kThreads) void k_segsort_mid(const uint32_t* __rest
     const uint32_t r = midrows[i];
     const uint32_t s = rp[r], len = rp[r + 1] - s;
     if (len > kSegWave) continue;
+    if (len <= (uint32_t)kWave) {  // one entry per lane: bitonic network over the lanes
+      int32_t x = (uint32_t)l < len ? col[s + l] : 0x7FFFFFFF;
+#pragma unroll
+      for (uint32_t k = 2; k <= (uint32_t)kWave; k <<= 1) {
+#pragma unroll
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+          const int32_t y = __shfl_xor(x, (int)j, kWave);
+          const bool up = ((uint32_t)l & k) == 0, low = ((uint32_t)l & j) == 0;
+          x = (low == up) ? min(x, y) : max(x, y);
+        }
+      }
+      if ((uint32_t)l < len) col[s + l] = x;
+      continue;
+    }
     const uint32_t N = pow2_at_least(len);
     for (uint32_t t = l; t < N; t += kWave) b[t] = t < len ? col[s + t] : 0x7FFFFFFF;
     wave_sync();
@@ -1034,27 +1100,27 @@ hipError_t launch_perm(const uint64_t* keys, int64_t n, int idbits, int32_t* ord
   return hipGetLastError();
 }
 
-hipError_t launch_degs(const void* rowptr, int rp64, const int32_t* colidx, int64_t n, const int32_t* perm,
-                       uint32_t* od, uint32_t* idg, uint32_t* list, uint32_t* nlist, uint32_t* hlist,
-                       uint32_t* nhlist, uint32_t* hpref, hipStream_t s) {
+hipError_t launch_degs(const void* rowptr, int rp64, const int32_t* colidx, int64_t n, int64_t nnz,
+                       const int32_t* perm, uint32_t* od, uint32_t* idg, uint32_t* list, uint32_t* nlist,
+                       uint32_t* hlist, uint32_t* nhlist, uint32_t* hpref, uint32_t* err, int check, hipStream_t s) {
   if (n == 0) return hipSuccess;
   const unsigned g = grid_for((uint64_t)n, kThreads, 65536);
   if (rp64) {
-    hipLaunchKernelGGL(k_degs_lane<int64_t>, dim3(g), dim3(kThreads), 0, s, (const int64_t*)rowptr, colidx, n, perm, od,
-                       idg, list, nlist, hlist, nhlist);
+    hipLaunchKernelGGL(k_degs_lane<int64_t>, dim3(g), dim3(kThreads), 0, s, (const int64_t*)rowptr, colidx, n, nnz,
+                       perm, od, idg, list, nlist, hlist, nhlist, err, check);
     hipLaunchKernelGGL(k_hprefix<int64_t>, dim3(1), dim3(kThreads), 0, s, (const int64_t*)rowptr, (const uint32_t*)hlist,
                        (const uint32_t*)nhlist, hpref);
-    hipLaunchKernelGGL(k_degs_wave<int64_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int64_t*)rowptr, colidx, perm,
-                       od, idg, (const uint32_t*)list, (const uint32_t*)nlist, (const uint32_t*)hlist,
-                       (const uint32_t*)nhlist, (const uint32_t*)hpref);
+    hipLaunchKernelGGL(k_degs_wave<int64_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int64_t*)rowptr, colidx, n,
+                       perm, od, idg, (const uint32_t*)list, (const uint32_t*)nlist, (const uint32_t*)hlist,
+                       (const uint32_t*)nhlist, (const uint32_t*)hpref, err, check);
   } else {
-    hipLaunchKernelGGL(k_degs_lane<int32_t>, dim3(g), dim3(kThreads), 0, s, (const int32_t*)rowptr, colidx, n, perm, od,
-                       idg, list, nlist, hlist, nhlist);
+    hipLaunchKernelGGL(k_degs_lane<int32_t>, dim3(g), dim3(kThreads), 0, s, (const int32_t*)rowptr, colidx, n, nnz,
+                       perm, od, idg, list, nlist, hlist, nhlist, err, check);
     hipLaunchKernelGGL(k_hprefix<int32_t>, dim3(1), dim3(kThreads), 0, s, (const int32_t*)rowptr, (const uint32_t*)hlist,
                        (const uint32_t*)nhlist, hpref);
-    hipLaunchKernelGGL(k_degs_wave<int32_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int32_t*)rowptr, colidx, perm,
-                       od, idg, (const uint32_t*)list, (const uint32_t*)nlist, (const uint32_t*)hlist,
-                       (const uint32_t*)nhlist, (const uint32_t*)hpref);
+    hipLaunchKernelGGL(k_degs_wave<int32_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int32_t*)rowptr, colidx, n,
+                       perm, od, idg, (const uint32_t*)list, (const uint32_t*)nlist, (const uint32_t*)hlist,
+                       (const uint32_t*)nhlist, (const uint32_t*)hpref, err, check);
   }
   return hipGetLastError();
 }

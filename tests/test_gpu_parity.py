@@ -215,10 +215,23 @@ def test_device_validation_rejects_bad_input():
         assert ei.value.status == bb.BBTC_EINVAL, name
         if name == "asymmetric":
             continue  # trusted input skips exactly this check
-        # trusted host input: rowptr checked on the host, entries by the kernel after the upload
+        # trusted input: rowptr (host input: on the host) and entries checked by the degree pass
+        for dev in (None, "cuda"):
+            rpt = torch.tensor(rp, dtype=torch.int64, device=dev)
+            cit = torch.tensor(ci, dtype=torch.int32, device=dev)
+            with pytest.raises(bb.BbtcError) as ei:
+                bb.bbtc_partition(n, rpt, cit, trusted=True)
+            assert ei.value.status == bb.BBTC_EINVAL, (name, dev)
+    # malformed rowptr of trusted device input, and a huge unsorted row
+    bad_rp = [(3, [0, 2, 1, 2], [1, 0]), (3, [0, 1, 2, 9], [1, 0])]
+    big = 5000
+    rows = [list(range(2, big + 1)) + [1]] + [[0]] * big  # a star whose huge row 0 is unsorted
+    bad_rp.append((big + 1, np.cumsum([0] + [len(r) for r in rows]).tolist(), sum(rows, [])))
+    for n, rp, ci in bad_rp:
         with pytest.raises(bb.BbtcError) as ei:
-            bb.bbtc_partition(n, np.asarray(rp, np.int64), np.asarray(ci, np.int32), trusted=True)
-        assert ei.value.status == bb.BBTC_EINVAL, name
+            bb.bbtc_partition(n, torch.tensor(rp, dtype=torch.int64, device="cuda"),
+                              torch.tensor(ci, dtype=torch.int32, device="cuda"), trusted=True)
+        assert ei.value.status == bb.BBTC_EINVAL
 
 
 # ---------------------------------------------------------------- C2 at full size
