@@ -103,7 +103,8 @@ struct bbtc_plan {
   std::vector<DevTask> h_dtasks;   // same order
   std::vector<int32_t> h_work;     // plan-order indices of WORK tasks
   std::vector<DevItem> h_items;
-  std::vector<DevItem> h_xitems;   // queue x = h_xitems[qbeg[x], qbeg[x] + qlen[x])
+  DevItem* h_xq = nullptr;         // pinned: queue x = h_xq[qbeg[x], qbeg[x] + qlen[x])
+  size_t xq_cap = 0;
   uint32_t nq = 1, qbeg[kMaxQueues] = {0}, qlen[kMaxQueues] = {0};
   std::vector<HeavyCol> h_heavy;   // hub columns, sorted by (block, column)
   std::vector<int64_t> h_hub_first, h_hub_count;  // per plan-order task: its range of work items
@@ -154,6 +155,10 @@ struct bbtc_plan {
   hipGraphExec_t gexec = nullptr;
   uint64_t* g_per = nullptr;
   uint64_t* g_tot = nullptr;
+  // outputs of the last direct launch since the graph was dropped: a graph is
+  // captured only once the same outputs are counted into a second time
+  uint64_t* d_per = nullptr;
+  uint64_t* d_tot = nullptr;
   bbtc_stats stats{};
 
   void drop_graph() {
@@ -162,11 +167,13 @@ struct bbtc_plan {
     gexec = nullptr;
     graph = nullptr;
     g_per = g_tot = nullptr;
+    d_per = d_tot = nullptr;
   }
 
   ~bbtc_plan() {
     drop_graph();
     drop_stream();
+    if (h_xq) (void)hipHostFree(h_xq);
     for (int q = 0; q < 4; ++q) {
       if (side[q]) (void)hipStreamDestroy(side[q]);
       if (ev_join[q]) (void)hipEventDestroy(ev_join[q]);
@@ -386,17 +393,19 @@ void compose_tasks(bbtc_plan* pl) {
 // than half a queue's fair share has its items dealt over all queues instead.
 // Workgroups drain their own XCD's queue and then help the others, so the
 // split changes only locality, never what is counted.
-void compose_queues(bbtc_plan* pl) {
+bbtc_status compose_queues(bbtc_plan* pl) {
   const int X = kMaxQueues;
   const int64_t p = pl->p;
+  const size_t ni = pl->h_items.size();
   double total = 0;
   for (int32_t q : pl->h_work) total += pl->h_tasks[q].est;
   const double fair = total / X;
-  std::vector<std::vector<DevItem>> qs(X);
   std::vector<double> load(X, 0.0);
   auto least = [&]() { return (int)(std::min_element(load.begin(), load.end()) - load.begin()); };
-  std::vector<std::vector<int32_t>> grp((size_t)(p * (p + 1) / 2));
-  std::vector<double> gload(grp.size(), 0.0);
+  std::vector<uint8_t> qof(ni, 0);  // queue of each item (plan order)
+  std::vector<int64_t> gfirst((size_t)(p * (p + 1) / 2), -1), gnext(pl->h_tasks.size(), -1);
+  std::vector<double> gload(gfirst.size(), 0.0);
+  std::vector<int64_t> glast(gfirst.size(), -1);
   for (int32_t q : pl->h_work) {  // plan order: heaviest first
     const bbtc_task& t = pl->h_tasks[q];
     const int64_t f = pl->h_hub_first[q], c = pl->h_hub_count[q];
@@ -404,33 +413,73 @@ void compose_queues(bbtc_plan* pl) {
       const double w = t.est / (double)c;
       for (int64_t r = 0; r < c; ++r) {
         const int x = least();
-        qs[x].push_back(pl->h_items[f + r]);
+        qof[(size_t)(f + r)] = (uint8_t)x;
         load[x] += w;
       }
-    } else {
+    } else {  // chain the task into its (i,k) group, keeping plan order
       const int64_t g = block_id(p, t.i, t.k);
-      grp[g].push_back(q);
+      if (gfirst[g] < 0) gfirst[g] = q; else gnext[glast[g]] = q;
+      glast[g] = q;
       gload[g] += t.est;
     }
   }
   std::vector<int64_t> gs;
-  for (size_t g = 0; g < grp.size(); ++g)
-    if (!grp[g].empty()) gs.push_back((int64_t)g);
+  for (size_t g = 0; g < gfirst.size(); ++g)
+    if (gfirst[g] >= 0) gs.push_back((int64_t)g);
   std::stable_sort(gs.begin(), gs.end(), [&](int64_t a, int64_t b) { return gload[a] > gload[b]; });
+  std::vector<std::vector<int64_t>> gq(X);
   for (int64_t g : gs) {
     const int x = least();
-    for (int32_t q : grp[g])
-      for (int64_t r = 0; r < pl->h_hub_count[q]; ++r) qs[x].push_back(pl->h_items[pl->h_hub_first[q] + r]);
+    gq[x].push_back(g);
     load[x] += gload[g];
   }
-  pl->h_xitems.clear();
-  pl->h_xitems.reserve(pl->h_items.size());
+  if (pl->xq_cap < std::max<size_t>(ni, 1)) {
+    if (pl->h_xq) (void)hipHostFree(pl->h_xq);
+    pl->h_xq = nullptr;
+    pl->xq_cap = 0;
+    const size_t cap = std::max<size_t>(ni, 1) + ni / 4;
+    HIP_TRY(hipHostMalloc((void**)&pl->h_xq, sizeof(DevItem) * cap, hipHostMallocDefault), "pinned alloc");
+    pl->xq_cap = cap;
+  }
+  // grouped tasks take their group's queue; then one counting pass and one scatter
+  for (int x = 0; x < X; ++x)
+    for (int64_t g : gq[x])
+      for (int64_t q = gfirst[g]; q >= 0; q = gnext[q]) {
+        const int64_t f = pl->h_hub_first[q], c = pl->h_hub_count[q];
+        for (int64_t r = 0; r < c; ++r) qof[(size_t)(f + r)] = (uint8_t)(x + X);  // X..2X-1: after the wide items
+      }
+  std::vector<size_t> cnt(2 * X, 0);
+  for (int32_t q : pl->h_work) {
+    const int64_t f = pl->h_hub_first[q], c = pl->h_hub_count[q];
+    for (int64_t r = 0; r < c; ++r) cnt[qof[(size_t)(f + r)]]++;
+  }
+  std::vector<size_t> at(2 * X, 0);
+  size_t pos = 0;
   pl->nq = X;
   for (int x = 0; x < X; ++x) {
-    pl->qbeg[x] = (uint32_t)pl->h_xitems.size();
-    pl->qlen[x] = (uint32_t)qs[x].size();
-    pl->h_xitems.insert(pl->h_xitems.end(), qs[x].begin(), qs[x].end());
+    pl->qbeg[x] = (uint32_t)pos;
+    at[x] = pos;
+    pos += cnt[x];
+    at[x + X] = pos;
+    pos += cnt[x + X];
+    pl->qlen[x] = (uint32_t)(pos - pl->qbeg[x]);
   }
+  // wide items in plan order, then the groups in assignment order (plan order inside a group)
+  for (int32_t q : pl->h_work) {
+    const int64_t f = pl->h_hub_first[q], c = pl->h_hub_count[q];
+    for (int64_t r = 0; r < c; ++r) {
+      const uint8_t k = qof[(size_t)(f + r)];
+      if (k < X) pl->h_xq[at[k]++] = pl->h_items[(size_t)(f + r)];
+    }
+  }
+  for (int x = 0; x < X; ++x)
+    for (int64_t g : gq[x])
+      for (int64_t q = gfirst[g]; q >= 0; q = gnext[q]) {
+        const int64_t f = pl->h_hub_first[q], c = pl->h_hub_count[q];
+        std::memcpy(pl->h_xq + at[x + X], pl->h_items.data() + f, sizeof(DevItem) * (size_t)c);
+        at[x + X] += (size_t)c;
+      }
+  return BBTC_OK;
 }
 
 // A launch over items[0, nitems) as a single queue.
@@ -540,6 +589,8 @@ bbtc_status stream_setup(bbtc_plan* pl, hipStream_t s) {
     pl->group_count.back()++;
   }
   pl->h_items = items;
+  pl->xitems.release();  // streamed launches walk the plan order, pair by pair
+  HIP_TRY(pl->items.ensure(items.size()), "alloc items");
   HIP_TRY(hipMemcpyAsync(pl->items.ptr, items.data(), sizeof(DevItem) * items.size(), hipMemcpyHostToDevice, s),
           "H2D");
   HIP_TRY(hipStreamSynchronize(s), "sync");
@@ -937,22 +988,27 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   acp[0] = 0;
   for (int64_t b = 0; b < nb; ++b) acp[b + 1] = acp[b] + (uint64_t)pl->h_nzc[b];
   compose_tasks(pl);
-  compose_queues(pl);
+  // the persistent launch reads the per-XCD queues, the plain one the plan order
+  const bool queued = opt.mode == BBTC_MODE_PERSISTENT;
+  if (queued) {
+    bbtc_status qst = compose_queues(pl);
+    if (qst != BBTC_OK) return qst;
+  }
   const int64_t nt = (int64_t)pl->h_tasks.size();
   HIP_TRY(pl->acp.ensure((size_t)nb + 1), "alloc");
   HIP_TRY(pl->tasks.ensure((size_t)nt), "alloc tasks");
-  HIP_TRY(pl->items.ensure(pl->h_items.size()), "alloc items");
-  HIP_TRY(pl->xitems.ensure(pl->h_xitems.size()), "alloc items");
+  HIP_TRY((queued ? pl->xitems : pl->items).ensure(pl->h_items.size()), "alloc items");
   HIP_TRY(pl->cursor.ensure(kMaxQueues), "alloc");
   HIP_TRY(hipMemcpyAsync(pl->acp.ptr, acp.data(), sizeof(uint64_t) * (nb + 1), hipMemcpyHostToDevice, s), "H2D");
   HIP_TRY(hipMemcpyAsync(pl->tasks.ptr, pl->h_dtasks.data(), sizeof(DevTask) * nt, hipMemcpyHostToDevice, s), "H2D");
   if (!pl->h_items.empty()) {
-    HIP_TRY(hipMemcpyAsync(pl->items.ptr, pl->h_items.data(), sizeof(DevItem) * pl->h_items.size(),
-                           hipMemcpyHostToDevice, s),
-            "H2D");
-    HIP_TRY(hipMemcpyAsync(pl->xitems.ptr, pl->h_xitems.data(), sizeof(DevItem) * pl->h_xitems.size(),
-                           hipMemcpyHostToDevice, s),
-            "H2D");
+    if (queued)
+      HIP_TRY(hipMemcpyAsync(pl->xitems.ptr, pl->h_xq, sizeof(DevItem) * pl->h_items.size(), hipMemcpyHostToDevice, s),
+              "H2D");
+    else
+      HIP_TRY(hipMemcpyAsync(pl->items.ptr, pl->h_items.data(), sizeof(DevItem) * pl->h_items.size(),
+                             hipMemcpyHostToDevice, s),
+              "H2D");
   }
   HIP_TRY(hipStreamSynchronize(s), "sync");
 
@@ -1133,11 +1189,17 @@ bbtc_status bbtc_count(bbtc_plan* pl, void* stream, uint64_t* d_per_task, uint64
     }
     int grid = pl->opt.grid > 0 ? pl->opt.grid : pl->blocks_per_cu * pl->ncu;
     grid = (int)std::min<int64_t>(grid, (int64_t)cp.nitems);
-    if (pl->opt.graph == -1) {
+    const bool have_graph = pl->gexec && pl->g_per == d_per_task && pl->g_tot == d_total;
+    const bool repeat = pl->d_per == d_per_task && pl->d_tot == d_total;
+    if (pl->opt.graph == -1 || (!have_graph && !repeat)) {
+      // first count of this plan into these outputs: launching beats capturing
+      if (graphed) HIP_TRY(launch_reset(d_per_task, nt, d_total, pl->cursor.ptr, s), "reset");
       HIP_TRY(launch_count_persistent(cp, grid, false, s), "count");
+      pl->d_per = d_per_task;
+      pl->d_tot = d_total;
       return BBTC_OK;
     }
-    if (!pl->gexec || pl->g_per != d_per_task || pl->g_tot != d_total) {
+    if (!have_graph) {
       // capture {reset kernel, persistent count} on a plan-owned stream
       pl->drop_graph();
       hipStream_t cs = pl->side[0];

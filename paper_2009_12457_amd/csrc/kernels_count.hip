@@ -145,6 +145,16 @@ __device__ __forceinline__ uint32_t owner_of(const uint32_t* off, uint32_t a, ui
   return lo;
 }
 
+// Largest o in [0, 64) with off[o] <= x (off non-decreasing, off[0] <= x):
+// six fixed halving steps, no data-dependent loop.
+__device__ __forceinline__ uint32_t owner64(const uint32_t* off, uint32_t x) {
+  uint32_t lo = 0;
+#pragma unroll
+  for (uint32_t step = kWave / 2; step > 0; step >>= 1)
+    if (off[lo + step] <= x) lo += step;
+  return lo;
+}
+
 // How a stage of N(G_jk,v) is held in a buffer of nw words (a power of
 // two): 0 sorted copy, 1 bitmap over V_k, 2 open-addressing hash at load at
 // most 1/2.
@@ -248,16 +258,20 @@ __device__ __forceinline__ void load_seg_w(const int32_t* __restrict__ col, uint
   w[5] = (uint32_t)v1.y;
   w[6] = (uint32_t)v1.z;
   w[7] = (uint32_t)v1.w;
+  // valid positions of the segment as a bit mask: [a0 - s0, a1 - s0) within [0, 8)
+  const uint32_t lo = a0 > s0 ? a0 - s0 : 0u, hi = min(a1 - s0, kSegW);
+  const uint32_t vm = ((1u << hi) - 1u) & ~((1u << lo) - 1u);
 #pragma unroll
   for (uint32_t x = 0; x < kSegW; ++x)
-    if (s0 + x < a0 || s0 + x >= a1) w[x] = 0xFFFFFFFFu;
+    if (!((vm >> x) & 1u)) w[x] = 0xFFFFFFFFu;
 }
 
 // The probe rounds of one batch: segment q of the batch goes to lane q mod 64;
 // its owner (the in-neighbour whose list holds it) is found by binary search
 // over the batch's exclusive prefix of segment counts.  MODE is the stage
-// form: 1 = bitmap over V_k (every list entry lies in V_k, so the only test
-// is the masked tail), otherwise entries outside [smin, smax] cannot match.
+// form, fixed for the whole loop: 1 = bitmap over V_k (every list entry lies
+// in V_k, so the only test is the masked tail), 2 = hash, 0 = sorted copy;
+// for 0 and 2 entries outside [smin, smax] cannot match and are skipped.
 template <int MODE>
 __device__ __forceinline__ uint32_t probe_rounds(const int32_t* __restrict__ col, uint32_t tot, const uint32_t* sa0,
                                                  const uint32_t* sa1, const uint32_t* sex, const Stage& st,
@@ -268,7 +282,7 @@ __device__ __forceinline__ uint32_t probe_rounds(const int32_t* __restrict__ col
   for (uint32_t qb = 0; qb < tot; qb += kWave) {
     const uint32_t q = qb + l;
     if (q < tot) {
-      const uint32_t o = owner_of(sex, 0, kWave, q);
+      const uint32_t o = owner64(sex, q);
       uint32_t w[kSegW];
       load_seg_w(col, sa0[o], sa1[o], q - sex[o], w);
 #pragma unroll
@@ -277,7 +291,26 @@ __device__ __forceinline__ uint32_t probe_rounds(const int32_t* __restrict__ col
           const uint32_t x = w[t] - (uint32_t)ck;
           if (x < width) cnt += (buf[x >> 5] >> (x & 31)) & 1u;
         } else if (w[t] >= smin && w[t] <= smax) {
-          cnt += stage_has(st, buf, sn, (int32_t)w[t], ck);
+          if (MODE == 2) {
+            const uint32_t key = w[t] + 1u;
+            uint32_t h = hash_slot(w[t], st.hbits);
+            for (uint32_t guard = 0; guard < st.nw; ++guard) {
+              const uint32_t kk = buf[h];
+              if (kk == key) {
+                ++cnt;
+                break;
+              }
+              if (kk == 0u) break;
+              h = (h + 1) & (st.nw - 1);
+            }
+          } else {
+            uint32_t x = 0, y = sn;
+            while (x < y) {
+              const uint32_t mid = (x + y) >> 1;
+              if (buf[mid] < w[t]) x = mid + 1; else y = mid;
+            }
+            cnt += (x < sn && buf[x] == w[t]) ? 1u : 0u;
+          }
         }
       }
     }
@@ -315,6 +348,8 @@ __device__ uint64_t probe_flat(const TaskCtx& c, uint32_t i0, uint32_t i1, const
     wave_sync();
     if (st.mode == 1)
       cnt += probe_rounds<1>(col, tot, sa0, sa1, sex, st, buf, sn, (uint32_t)smin, (uint32_t)smax, c.ck, width);
+    else if (st.mode == 2)
+      cnt += probe_rounds<2>(col, tot, sa0, sa1, sex, st, buf, sn, (uint32_t)smin, (uint32_t)smax, c.ck, width);
     else
       cnt += probe_rounds<0>(col, tot, sa0, sa1, sex, st, buf, sn, (uint32_t)smin, (uint32_t)smax, c.ck, width);
     wave_sync();
@@ -415,7 +450,7 @@ __device__ uint64_t short_cols(const TaskCtx& c, CountLds& s, uint32_t a0, uint3
       for (uint32_t qb = 0; qb < tot; qb += kWave) {
         const uint32_t q = qb + l;
         if (q < tot) {
-          const uint32_t o = owner_of(sex, 0, kWave, q);
+          const uint32_t o = owner64(sex, q);
           const uint32_t k2 = scol[o];
           const uint32_t lo = s.soff[k2] - sbase, hi2 = s.soff[k2 + 1] - sbase;
           uint32_t wv[kSegW];
