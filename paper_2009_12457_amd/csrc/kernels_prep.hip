@@ -306,47 +306,109 @@ __device__ __forceinline__ uint32_t entry_flags(const int32_t* __restrict__ coli
   return e;
 }
 
+// Rows of at most kLaneRow entries are handled 64 consecutive rows per
+// wavefront with their entries spread over the lanes ("flattened"): a
+// wavefront prefix sum of the row lengths gives each lane its entry, the
+// owner row follows by binary search over the prefix, and per-row counts and
+// positions come from ballots over the runs of equal owners.
+struct FlatRows {
+  uint32_t off[kWave];  // exclusive prefix of the group's lane-row lengths
+  int64_t beg[kWave];   // first entry of each row in colidx
+  int32_t rank[kWave];  // rank of each row (perm)
+  uint32_t c0[kWave];   // per row: running count / next out-row slot
+  uint32_t c1[kWave];   // per row: next in-row slot
+};
+
+__device__ __forceinline__ uint32_t owner_lane(const uint32_t* off, uint32_t f) {
+  uint32_t lo = 0;
+#pragma unroll
+  for (uint32_t step = kWave / 2; step > 0; step >>= 1)
+    if (off[lo + step] <= f) lo += step;
+  return lo;
+}
+
+// Lanes of the run (equal owner) that lane l belongs to, within one chunk of
+// 64 flattened entries: `heads` marks the first lane of every run.
+__device__ __forceinline__ uint64_t run_mask(uint64_t heads, int l) {
+  const uint64_t below = (l == 63) ? ~0ull : ((1ull << (l + 1)) - 1);  // lanes 0..l
+  const uint64_t h = heads & below;
+  const int first = 63 - __clzll(h);  // the run's head (lane 0 is always a head)
+  const uint64_t after = heads & ~below;
+  const int next = after ? __ffsll((unsigned long long)after) - 1 : 64;
+  const uint64_t upto = (next == 64) ? ~0ull : ((1ull << next) - 1);
+  return upto & ~((1ull << first) - 1);
+}
+
 template <typename RP>
 __global__ __launch_bounds__(kThreads) void k_degs_lane(const RP* __restrict__ rowptr,
                                                         const int32_t* __restrict__ colidx, int64_t n, int64_t nnz,
                                                         const int32_t* __restrict__ perm, uint32_t* __restrict__ od,
                                                         uint32_t* __restrict__ idg, uint32_t* list, uint32_t* nlist,
                                                         uint32_t* hlist, uint32_t* nhlist, uint32_t* err, int check) {
+  __shared__ FlatRows fr[kThreads / kWave];
+  const int l = lane_id();
+  FlatRows& F = fr[threadIdx.x / kWave];
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
   uint32_t bad = 0;
   if (check && blockIdx.x == 0 && threadIdx.x == 0) {
     if ((int64_t)rowptr[0] != 0 || (int64_t)rowptr[n] != nnz) bad |= 8;
   }
-  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t r = perm[x];
-    if (r < 0 || r >= n) continue;
-    const int64_t b = (int64_t)rowptr[x], e = (int64_t)rowptr[x + 1];
-    if (check && (b < 0 || e < b || e > nnz)) {
-      bad |= 8;
-      od[r] = idg[r] = 0;
-      continue;
-    }
-    if (e - b > kWaveRow) {
-      od[r] = 0;
-      idg[r] = 0;
-      hlist[atomicAdd(nhlist, 1u)] = (uint32_t)x;
-      continue;
-    }
-    if (e - b > kLaneRow) {
-      list[atomicAdd(nlist, 1u)] = (uint32_t)x;
-      continue;
-    }
-    uint32_t c = 0;
-    for (int64_t q = b; q < e; ++q) {
-      const int32_t y = colidx[q];
-      if (check) {
-        const uint32_t f = entry_flags<RP>(colidx, n, x, b, q, y);
-        bad |= f;
-        if (f & 1) continue;
+  for (int64_t x0 = wave * kWave; x0 < n; x0 += nwaves * kWave) {  // uniform per wavefront
+    const int64_t x = x0 + l;
+    int32_t r = -1;
+    int64_t b = 0, e = 0;
+    bool mine = false;  // a lane row: counted by this group
+    if (x < n) {
+      r = perm[x];
+      b = (int64_t)rowptr[x];
+      e = (int64_t)rowptr[x + 1];
+      if (r >= 0 && r < n) {
+        if (check && (b < 0 || e < b || e > nnz)) {
+          bad |= 8;
+          od[r] = idg[r] = 0;
+        } else if (e - b > kWaveRow) {
+          od[r] = idg[r] = 0;
+          hlist[atomicAdd(nhlist, 1u)] = (uint32_t)x;
+        } else if (e - b > kLaneRow) {
+          list[atomicAdd(nlist, 1u)] = (uint32_t)x;
+        } else {
+          mine = true;
+        }
       }
-      c += perm[y] > r ? 1u : 0u;
     }
-    od[r] = c;
-    idg[r] = (uint32_t)(e - b) - c;
+    const uint32_t len = mine ? (uint32_t)(e - b) : 0u;
+    const uint32_t inc = wave_incl_scan_u32(len);
+    const uint32_t tot = __shfl(inc, kWave - 1, kWave);
+    F.off[l] = inc - len;
+    F.beg[l] = b;
+    F.rank[l] = r;
+    F.c0[l] = 0;
+    wave_sync();
+    for (uint32_t fb = 0; fb < tot; fb += kWave) {
+      const uint32_t f = fb + l;
+      const bool act = f < tot;
+      uint32_t o = 0;
+      bool up = false;
+      if (act) {
+        o = owner_lane(F.off, f);
+        const int64_t rb = F.beg[o], q = rb + (f - F.off[o]);
+        const int32_t y = colidx[q];
+        uint32_t fl = 0;
+        if (check) fl = entry_flags<RP>(colidx, n, x0 + o, rb, q, y);
+        bad |= fl;
+        up = !(fl & 1) && perm[y] > F.rank[o];
+      }
+      const uint64_t heads = ballot(act && (l == 0 || f == F.off[o]));
+      const uint64_t ups = ballot(up);
+      if (act && ((heads >> l) & 1ull)) atomicAdd(&F.c0[o], (uint32_t)__popcll(ups & run_mask(heads, l)));
+    }
+    wave_sync();
+    if (mine) {
+      od[r] = F.c0[l];
+      idg[r] = len - F.c0[l];
+    }
+    wave_sync();
   }
   if (bad) atomicOr(err, bad);
 }
@@ -425,23 +487,67 @@ __global__ __launch_bounds__(kThreads) void k_fill_lane(const RP* __restrict__ r
                                                         const uint32_t* __restrict__ orow,
                                                         const uint32_t* __restrict__ irow, int32_t* __restrict__ ocol,
                                                         int32_t* __restrict__ icol) {
-  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t r = perm[x];
-    if (r < 0 || r >= n) continue;
-    const int64_t b = (int64_t)rowptr[x], e = (int64_t)rowptr[x + 1];
-    if (e - b > kLaneRow) continue;  // listed rows: k_fill_wave
-    uint32_t po = orow[r], pi = irow[r];
-    const uint32_t po_end = orow[r + 1], pi_end = irow[r + 1];
-    for (int64_t q = b; q < e; ++q) {
-      const int32_t ry = perm[colidx[q]];
-      if (ry > r) {
-        if (po < po_end) ocol[po] = ry;
-        ++po;
-      } else {
-        if (pi < pi_end) icol[pi] = ry;
-        ++pi;
-      }
+  __shared__ FlatRows fr[kThreads / kWave];
+  __shared__ uint32_t lim[kThreads / kWave][2][kWave];  // per row: end of its out- and in-row
+  const int l = lane_id(), w = threadIdx.x / kWave;
+  FlatRows& F = fr[w];
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  for (int64_t x0 = wave * kWave; x0 < n; x0 += nwaves * kWave) {  // uniform per wavefront
+    const int64_t x = x0 + l;
+    int32_t r = -1;
+    int64_t b = 0, e = 0;
+    bool mine = false;
+    if (x < n) {
+      r = perm[x];
+      b = (int64_t)rowptr[x];
+      e = (int64_t)rowptr[x + 1];
+      mine = r >= 0 && r < n && e - b >= 0 && e - b <= kLaneRow;  // listed rows: k_fill_wave
     }
+    const uint32_t len = mine ? (uint32_t)(e - b) : 0u;
+    const uint32_t inc = wave_incl_scan_u32(len);
+    const uint32_t tot = __shfl(inc, kWave - 1, kWave);
+    F.off[l] = inc - len;
+    F.beg[l] = b;
+    F.rank[l] = r;
+    F.c0[l] = mine ? orow[r] : 0u;
+    F.c1[l] = mine ? irow[r] : 0u;
+    lim[w][0][l] = mine ? orow[r + 1] : 0u;
+    lim[w][1][l] = mine ? irow[r + 1] : 0u;
+    wave_sync();
+    for (uint32_t fb = 0; fb < tot; fb += kWave) {
+      const uint32_t f = fb + l;
+      const bool act = f < tot;
+      uint32_t o = 0;
+      int32_t ry = 0;
+      bool up = false;
+      if (act) {
+        o = owner_lane(F.off, f);
+        ry = perm[colidx[F.beg[o] + (f - F.off[o])]];
+        up = ry > F.rank[o];
+      }
+      const uint64_t heads = ballot(act && (l == 0 || f == F.off[o]));
+      const uint64_t ups = ballot(act && up), downs = ballot(act && !up);
+      if (act) {
+        const uint64_t run = run_mask(heads, l);
+        const uint64_t before = run & ((1ull << l) - 1);  // lanes of my run below me
+        if (up) {
+          const uint32_t d = F.c0[o] + (uint32_t)__popcll(ups & before);
+          if (d < lim[w][0][o]) ocol[d] = ry;
+        } else {
+          const uint32_t d = F.c1[o] + (uint32_t)__popcll(downs & before);
+          if (d < lim[w][1][o]) icol[d] = ry;
+        }
+      }
+      wave_sync();  // every lane has read the counters before the heads advance them
+      if (act && ((heads >> l) & 1ull)) {
+        const uint64_t run = run_mask(heads, l);
+        F.c0[o] += (uint32_t)__popcll(ups & run);
+        F.c1[o] += (uint32_t)__popcll(downs & run);
+      }
+      wave_sync();
+    }
+    wave_sync();
   }
 }
 
