@@ -413,6 +413,37 @@ __global__ __launch_bounds__(kThreads) void k_degs_lane(const RP* __restrict__ r
   if (bad) atomicOr(err, bad);
 }
 
+constexpr int kUnroll = 4;  // 64-entry chunks of a row in flight per wavefront step
+
+// This lane's count of entries q in [b, e) (row x of rank r, starting at rb)
+// with a higher-ranked neighbour; with `check`, the entry checks are ORed
+// into *bad.  Loads of kUnroll chunks are issued before any is used.
+template <typename RP>
+__device__ __forceinline__ uint32_t count_up(const int32_t* __restrict__ colidx, int64_t n,
+                                             const int32_t* __restrict__ perm, int64_t x, int32_t r, int64_t rb,
+                                             int64_t b, int64_t e, int check, uint32_t* bad) {
+  const int l = lane_id();
+  uint32_t c = 0;
+  for (int64_t base = b; base < e; base += kUnroll * kWave) {
+    int32_t y[kUnroll];
+#pragma unroll
+    for (int k = 0; k < kUnroll; ++k) {
+      const int64_t q = base + k * kWave + l;
+      y[k] = q < e ? colidx[q] : -1;
+    }
+#pragma unroll
+    for (int k = 0; k < kUnroll; ++k) {
+      const int64_t q = base + k * kWave + l;
+      if (q < e) {
+        const uint32_t f = check ? entry_flags<RP>(colidx, n, x, rb, q, y[k]) : 0u;
+        *bad |= f;
+        if (!(f & 1) && perm[y[k]] > r) ++c;
+      }
+    }
+  }
+  return c;
+}
+
 // Listed rows: one wavefront per row; huge rows: chunks counted by different
 // wavefronts and added to od/idg, which k_degs_lane zeroed for them.
 template <typename RP>
@@ -432,18 +463,7 @@ __global__ __launch_bounds__(kThreads) void k_degs_wave(const RP* __restrict__ r
     const int64_t x = list[i];
     const int32_t r = perm[x];
     const int64_t b = (int64_t)rowptr[x], e = (int64_t)rowptr[x + 1];
-    uint32_t c = 0;
-    for (int64_t base = b; base < e; base += kWave) {
-      const int64_t q = base + l;
-      bool up = false;
-      if (q < e) {
-        const int32_t y = colidx[q];
-        const uint32_t f = check ? entry_flags<RP>(colidx, n, x, b, q, y) : 0u;
-        bad |= f;
-        up = !(f & 1) && perm[y] > r;
-      }
-      c += (uint32_t)__popcll(ballot(up));
-    }
+    const uint32_t c = (uint32_t)wave_sum_u64(count_up<RP>(colidx, n, perm, x, r, b, b, e, check, &bad));
     if (l == 0) {
       od[r] = c;
       idg[r] = (uint32_t)(e - b) - c;
@@ -457,18 +477,7 @@ __global__ __launch_bounds__(kThreads) void k_degs_wave(const RP* __restrict__ r
     unit_of(rowptr, hlist, hpref, hcnt, u, &li, &x, &b, &e);
     const int32_t r = perm[x];
     const int64_t rb = (int64_t)rowptr[x];
-    uint32_t c = 0;
-    for (int64_t base = b; base < e; base += kWave) {
-      const int64_t q = base + l;
-      bool up = false;
-      if (q < e) {
-        const int32_t y = colidx[q];
-        const uint32_t f = check ? entry_flags<RP>(colidx, n, x, rb, q, y) : 0u;
-        bad |= f;
-        up = !(f & 1) && perm[y] > r;
-      }
-      c += (uint32_t)__popcll(ballot(up));
-    }
+    const uint32_t c = (uint32_t)wave_sum_u64(count_up<RP>(colidx, n, perm, x, r, rb, b, e, check, &bad));
     if (l == 0) {
       atomicAdd(&od[r], c);
       atomicAdd(&idg[r], (uint32_t)(e - b) - c);
@@ -551,6 +560,39 @@ __global__ __launch_bounds__(kThreads) void k_fill_lane(const RP* __restrict__ r
   }
 }
 
+// Entries [b, e) of a row of rank r, by one wavefront: higher-ranked
+// neighbours go to ocol from po on, the others to icol from pi on, in input
+// order (ballot compaction); kUnroll chunks are gathered before any is
+// written.  Writes stop at po_end / pi_end.
+__device__ __forceinline__ void scatter_run(const int32_t* __restrict__ colidx, const int32_t* __restrict__ perm,
+                                            int32_t r, int64_t b, int64_t e, uint32_t po, uint32_t pi,
+                                            uint32_t po_end, uint32_t pi_end, int32_t* __restrict__ ocol,
+                                            int32_t* __restrict__ icol) {
+  const int l = lane_id();
+  for (int64_t base = b; base < e; base += kUnroll * kWave) {
+    int32_t ry[kUnroll];
+#pragma unroll
+    for (int k = 0; k < kUnroll; ++k) {
+      const int64_t q = base + k * kWave + l;
+      ry[k] = q < e ? colidx[q] : -1;
+    }
+#pragma unroll
+    for (int k = 0; k < kUnroll; ++k) ry[k] = ry[k] >= 0 ? perm[ry[k]] : -1;
+#pragma unroll
+    for (int k = 0; k < kUnroll; ++k) {
+      const int64_t q = base + k * kWave + l;
+      const bool up = ry[k] > r;
+      const bool down = q < e && !up;
+      const uint64_t mu = ballot(up), md = ballot(down);
+      const uint32_t du = po + lanes_below(mu), dd = pi + lanes_below(md);
+      if (up && du < po_end) ocol[du] = ry[k];
+      if (down && dd < pi_end) icol[dd] = ry[k];
+      po += (uint32_t)__popcll(mu);
+      pi += (uint32_t)__popcll(md);
+    }
+  }
+}
+
 // Listed rows: one wavefront per row (ballot compaction keeps input order).
 // Huge rows: chunks reserve their slots with atomics on per-row cursors
 // (cur_o/cur_i, zeroed, indexed by position in hlist), so the order inside
@@ -574,20 +616,7 @@ __global__ __launch_bounds__(kThreads) void k_fill_wave(const RP* __restrict__ r
     const int64_t x = list[i];
     const int32_t r = perm[x];
     const int64_t b = (int64_t)rowptr[x], e = (int64_t)rowptr[x + 1];
-    uint32_t po = orow[r], pi = irow[r];
-    const uint32_t po_end = orow[r + 1], pi_end = irow[r + 1];
-    for (int64_t base = b; base < e; base += kWave) {
-      const int64_t q = base + l;
-      const int32_t ry = q < e ? perm[colidx[q]] : -1;
-      const bool up = ry > r;
-      const bool down = q < e && !up;
-      const uint64_t mu = ballot(up), md = ballot(down);
-      const uint32_t du = po + lanes_below(mu), dd = pi + lanes_below(md);
-      if (up && du < po_end) ocol[du] = ry;
-      if (down && dd < pi_end) icol[dd] = ry;
-      po += (uint32_t)__popcll(mu);
-      pi += (uint32_t)__popcll(md);
-    }
+    scatter_run(colidx, perm, r, b, e, orow[r], irow[r], orow[r + 1], irow[r + 1], ocol, icol);
   }
   const uint32_t hcnt = *nhlist;
   const uint32_t units = hcnt ? hpref[hcnt] : 0u;
@@ -598,11 +627,9 @@ __global__ __launch_bounds__(kThreads) void k_fill_wave(const RP* __restrict__ r
     const int32_t r = perm[x];
     const uint32_t ob = orow[r], ib = irow[r];
     const uint32_t po_end = orow[r + 1], pi_end = irow[r + 1];
-    uint32_t nu = 0;
-    for (int64_t base = b; base < e; base += kWave) {
-      const int64_t q = base + l;
-      nu += (uint32_t)__popcll(ballot(q < e && perm[colidx[q]] > r));
-    }
+    uint32_t nb = 0;
+    const uint32_t nu =
+        (uint32_t)wave_sum_u64(count_up<RP>(colidx, 0, perm, x, r, b, b, e, 0, &nb));
     uint32_t po = 0, pi = 0;
     if (l == 0) {
       po = ob + atomicAdd(&cur_o[li], nu);
@@ -610,18 +637,7 @@ __global__ __launch_bounds__(kThreads) void k_fill_wave(const RP* __restrict__ r
     }
     po = __shfl(po, 0, kWave);
     pi = __shfl(pi, 0, kWave);
-    for (int64_t base = b; base < e; base += kWave) {
-      const int64_t q = base + l;
-      const int32_t ry = q < e ? perm[colidx[q]] : -1;
-      const bool up = ry > r;
-      const bool down = q < e && !up;
-      const uint64_t mu = ballot(up), md = ballot(down);
-      const uint32_t du = po + lanes_below(mu), dd = pi + lanes_below(md);
-      if (up && du < po_end) ocol[du] = ry;
-      if (down && dd < pi_end) icol[dd] = ry;
-      po += (uint32_t)__popcll(mu);
-      pi += (uint32_t)__popcll(md);
-    }
+    scatter_run(colidx, perm, r, b, e, po, pi, po_end, pi_end, ocol, icol);
   }
 }
 
