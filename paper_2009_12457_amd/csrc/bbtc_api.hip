@@ -278,8 +278,9 @@ void fill_defaults(bbtc_options* o) {
 constexpr int kDefaultWaveMin = 64;
 constexpr int kDefaultHashMin = 16;
 constexpr int kDefaultItemRows = 256;
-constexpr uint32_t kHubSplit = 512;   // in-slice length above which a column is split
+constexpr uint32_t kHubSplit = 256;   // in-slice length above which a column is split
 constexpr uint32_t kHubChunk = 1024;  // in-neighbours per hub work item
+constexpr int kItemsPerBlock = 32;    // work items per resident workgroup (by estimated work)
 
 int eff_wave_min(const bbtc_options& o) { return o.wave_min > 0 ? o.wave_min : kDefaultWaveMin; }
 int eff_hash_min(const bbtc_options& o) {
@@ -366,7 +367,7 @@ void compose_tasks(bbtc_plan* pl) {
   const uint32_t step = (uint32_t)(pl->opt.item_rows > 0 ? pl->opt.item_rows : kDefaultItemRows);
   double est_sum = 0;
   for (int32_t q : pl->h_work) est_sum += pl->h_tasks[q].est;
-  const double target = est_sum / (double)std::max<int64_t>(1, (int64_t)pl->blocks_per_cu * pl->ncu * 16);
+  const double target = est_sum / (double)std::max<int64_t>(1, (int64_t)pl->blocks_per_cu * pl->ncu * kItemsPerBlock);
   for (int32_t q : pl->h_work) {
     const bbtc_task& t = pl->h_tasks[q];
     const int64_t cid = col_block_id(t.i, t.j);
