@@ -107,7 +107,11 @@ struct bbtc_plan {
   size_t xq_cap = 0;
   uint32_t nq = 1, qbeg[kMaxQueues] = {0}, qlen[kMaxQueues] = {0};
   std::vector<HeavyCol> h_heavy;   // hub columns, sorted by (block, column)
-  std::vector<int64_t> h_hub_first, h_hub_count;  // per plan-order task: its range of work items
+  std::vector<int64_t> h_hub_first, h_hub_count;  // per plan-order task: its range of h_items
+  // per plan-order task: work items, columns per range item; hub records per block
+  std::vector<uint32_t> h_nitem, h_nper;
+  std::vector<int64_t> h_hstart;
+  size_t nitems = 0;                // work items of the plan (either layout)
   uint32_t split = 0;              // in-slice length above which a column is a hub
   int64_t ccount = 0;              // number of chunk counters
   int ncu = 0, blocks_per_cu = 0;
@@ -319,8 +323,7 @@ PlanCtx plan_ctx(const bbtc_plan* pl, uint64_t* per_task, uint64_t* total) {
 
 // ------------------------------------------------------------ task list
 // Alg. 4 order, the Sec. 5 estimate, kinds, and the non-increasing order by
-// estimate (ties kept in Alg. 4 order); work items split each task's active
-// columns of G_ij into pieces of item_rows columns.
+// estimate (ties kept in Alg. 4 order); the number of work items per task.
 void compose_tasks(bbtc_plan* pl) {
   const int64_t p = pl->p;
   std::vector<bbtc_task> all;
@@ -346,44 +349,79 @@ void compose_tasks(bbtc_plan* pl) {
   pl->h_dtasks.resize(all.size());
   pl->h_work.clear();
   pl->h_items.clear();
-  pl->h_hub_first.assign(all.size(), 0);
-  pl->h_hub_count.assign(all.size(), 0);
+  pl->h_hub_first.clear();
+  pl->h_hub_count.clear();
   for (size_t q = 0; q < idx.size(); ++q) {
     const bbtc_task& t = all[idx[q]];
     pl->h_tasks[q] = t;
     pl->h_dtasks[q] = DevTask{t.i, t.j, t.k, (int32_t)q};
     if (t.kind == BBTC_TASK_WORK) pl->h_work.push_back((int32_t)q);
   }
-  // hub columns of each block (h_heavy is sorted by block)
+  // hub columns of each block
   const int64_t nb = p * (p + 1) / 2;
-  std::vector<int64_t> hstart((size_t)nb + 1, 0);
-  for (const HeavyCol& hc : pl->h_heavy) hstart[hc.cid + 1]++;
-  for (int64_t b = 0; b < nb; ++b) hstart[b + 1] += hstart[b];
-  // Work items, task by task in plan order (heaviest first): the task's hub
-  // chunks, then its active columns in ranges sized by the task's estimated
-  // work per column so that dense tasks spread over many workgroups (at most
-  // item_rows columns per range).  The persistent kernel walks the whole list;
-  // the plain form launches each task's range of the list on its own.
+  pl->h_hstart.assign((size_t)nb + 1, 0);
+  for (const HeavyCol& hc : pl->h_heavy) pl->h_hstart[hc.cid + 1]++;
+  for (int64_t b = 0; b < nb; ++b) pl->h_hstart[b + 1] += pl->h_hstart[b];
+  {  // group the hub records by block (counting sort; their order inside a block is free)
+    std::vector<HeavyCol> g(pl->h_heavy.size());
+    std::vector<int64_t> at(pl->h_hstart.begin(), pl->h_hstart.end() - 1);
+    for (const HeavyCol& hc : pl->h_heavy) g[(size_t)at[hc.cid]++] = hc;
+    pl->h_heavy.swap(g);
+  }
+  // Work items per task (emitted later, in the layout the launch needs): the
+  // task's hub chunks, then its active columns in ranges sized by the task's
+  // estimated work per column so that dense tasks spread over many
+  // workgroups (at most item_rows columns per range).
   const uint32_t step = (uint32_t)(pl->opt.item_rows > 0 ? pl->opt.item_rows : kDefaultItemRows);
   double est_sum = 0;
   for (int32_t q : pl->h_work) est_sum += pl->h_tasks[q].est;
   const double target = est_sum / (double)std::max<int64_t>(1, (int64_t)pl->blocks_per_cu * pl->ncu * kItemsPerBlock);
+  pl->h_nitem.assign(all.size(), 0);
+  pl->h_nper.assign(all.size(), 0);
+  pl->nitems = 0;
   for (int32_t q : pl->h_work) {
     const bbtc_task& t = pl->h_tasks[q];
     const int64_t cid = col_block_id(t.i, t.j);
-    pl->h_hub_first[q] = (int64_t)pl->h_items.size();
-    for (int64_t r = hstart[cid]; r < hstart[cid + 1]; ++r) {
-      const HeavyCol& hc = pl->h_heavy[r];
-      for (uint32_t lo = 0; lo < hc.cnt; lo += kHubChunk)
-        pl->h_items.push_back(DevItem{0, q, lo, std::min(hc.cnt, lo + kHubChunk), hc.v, 0});
-    }
+    uint32_t c = 0;
+    for (int64_t r = pl->h_hstart[cid]; r < pl->h_hstart[cid + 1]; ++r)
+      c += (pl->h_heavy[r].cnt + kHubChunk - 1) / kHubChunk;
     const uint32_t cols = (uint32_t)pl->h_nzc[cid];
     const double per_col = cols ? t.est / (double)cols : 0.0;
     uint32_t nper = step;
     if (per_col > 0 && target > 0) nper = (uint32_t)std::max(1.0, std::min((double)step, target / per_col));
-    for (uint32_t lo = 0; lo < cols; lo += nper)
-      pl->h_items.push_back(DevItem{0, q, lo, std::min(cols, lo + nper), -1, 0});
-    pl->h_hub_count[q] = (int64_t)pl->h_items.size() - pl->h_hub_first[q];
+    c += (cols + nper - 1) / nper;
+    pl->h_nitem[q] = c;
+    pl->h_nper[q] = nper;
+    pl->nitems += c;
+  }
+}
+
+// Writes the work items of plan-order task q to out (h_nitem[q] of them).
+void emit_items(const bbtc_plan* pl, int32_t q, DevItem* out) {
+  const bbtc_task& t = pl->h_tasks[q];
+  const int64_t cid = col_block_id(t.i, t.j);
+  size_t at = 0;
+  for (int64_t r = pl->h_hstart[cid]; r < pl->h_hstart[cid + 1]; ++r) {
+    const HeavyCol& hc = pl->h_heavy[r];
+    for (uint32_t lo = 0; lo < hc.cnt; lo += kHubChunk)
+      out[at++] = DevItem{0, q, lo, std::min(hc.cnt, lo + kHubChunk), hc.v, 0};
+  }
+  const uint32_t cols = (uint32_t)pl->h_nzc[cid], nper = pl->h_nper[q];
+  for (uint32_t lo = 0; lo < cols; lo += nper) out[at++] = DevItem{0, q, lo, std::min(cols, lo + nper), -1, 0};
+}
+
+// The items in plan order, each task's contiguous (the plain launches and the
+// streamed walk use this layout).
+void compose_plan_order(bbtc_plan* pl) {
+  pl->h_items.resize(pl->nitems);
+  pl->h_hub_first.assign(pl->h_tasks.size(), 0);
+  pl->h_hub_count.assign(pl->h_tasks.size(), 0);
+  size_t at = 0;
+  for (int32_t q : pl->h_work) {
+    pl->h_hub_first[q] = (int64_t)at;
+    pl->h_hub_count[q] = pl->h_nitem[q];
+    emit_items(pl, q, pl->h_items.data() + at);
+    at += pl->h_nitem[q];
   }
 }
 
@@ -397,24 +435,28 @@ void compose_tasks(bbtc_plan* pl) {
 bbtc_status compose_queues(bbtc_plan* pl) {
   const int X = kMaxQueues;
   const int64_t p = pl->p;
-  const size_t ni = pl->h_items.size();
+  const size_t ni = pl->nitems;
   double total = 0;
   for (int32_t q : pl->h_work) total += pl->h_tasks[q].est;
   const double fair = total / X;
   std::vector<double> load(X, 0.0);
   auto least = [&]() { return (int)(std::min_element(load.begin(), load.end()) - load.begin()); };
-  std::vector<uint8_t> qof(ni, 0);  // queue of each item (plan order)
+  std::vector<size_t> wide_cnt(X, 0), group_cnt(X, 0);
+  std::vector<int32_t> wide;  // tasks dealt over all queues, plan order
   std::vector<int64_t> gfirst((size_t)(p * (p + 1) / 2), -1), gnext(pl->h_tasks.size(), -1);
-  std::vector<double> gload(gfirst.size(), 0.0);
   std::vector<int64_t> glast(gfirst.size(), -1);
+  std::vector<double> gload(gfirst.size(), 0.0);
+  std::vector<size_t> gitems(gfirst.size(), 0);
   for (int32_t q : pl->h_work) {  // plan order: heaviest first
     const bbtc_task& t = pl->h_tasks[q];
-    const int64_t f = pl->h_hub_first[q], c = pl->h_hub_count[q];
+    const uint32_t c = pl->h_nitem[q];
     if (t.est > fair / 2 && c > 1) {
+      // each item to the least loaded queue
+      wide.push_back(q);
       const double w = t.est / (double)c;
-      for (int64_t r = 0; r < c; ++r) {
+      for (uint32_t r = 0; r < c; ++r) {
         const int x = least();
-        qof[(size_t)(f + r)] = (uint8_t)x;
+        wide_cnt[x]++;
         load[x] += w;
       }
     } else {  // chain the task into its (i,k) group, keeping plan order
@@ -422,16 +464,18 @@ bbtc_status compose_queues(bbtc_plan* pl) {
       if (gfirst[g] < 0) gfirst[g] = q; else gnext[glast[g]] = q;
       glast[g] = q;
       gload[g] += t.est;
+      gitems[g] += c;
     }
   }
   std::vector<int64_t> gs;
   for (size_t g = 0; g < gfirst.size(); ++g)
     if (gfirst[g] >= 0) gs.push_back((int64_t)g);
   std::stable_sort(gs.begin(), gs.end(), [&](int64_t a, int64_t b) { return gload[a] > gload[b]; });
-  std::vector<std::vector<int64_t>> gq(X);
+  std::vector<int> gq(gfirst.size(), 0);
   for (int64_t g : gs) {
     const int x = least();
-    gq[x].push_back(g);
+    gq[g] = x;
+    group_cnt[x] += gitems[g];
     load[x] += gload[g];
   }
   if (pl->xq_cap < std::max<size_t>(ni, 1)) {
@@ -442,44 +486,37 @@ bbtc_status compose_queues(bbtc_plan* pl) {
     HIP_TRY(hipHostMalloc((void**)&pl->h_xq, sizeof(DevItem) * cap, hipHostMallocDefault), "pinned alloc");
     pl->xq_cap = cap;
   }
-  // grouped tasks take their group's queue; then one counting pass and one scatter
-  for (int x = 0; x < X; ++x)
-    for (int64_t g : gq[x])
-      for (int64_t q = gfirst[g]; q >= 0; q = gnext[q]) {
-        const int64_t f = pl->h_hub_first[q], c = pl->h_hub_count[q];
-        for (int64_t r = 0; r < c; ++r) qof[(size_t)(f + r)] = (uint8_t)(x + X);  // X..2X-1: after the wide items
-      }
-  std::vector<size_t> cnt(2 * X, 0);
-  for (int32_t q : pl->h_work) {
-    const int64_t f = pl->h_hub_first[q], c = pl->h_hub_count[q];
-    for (int64_t r = 0; r < c; ++r) cnt[qof[(size_t)(f + r)]]++;
-  }
+  // queue x: its share of the wide tasks' items, then its groups in order
   std::vector<size_t> at(2 * X, 0);
   size_t pos = 0;
   pl->nq = X;
   for (int x = 0; x < X; ++x) {
     pl->qbeg[x] = (uint32_t)pos;
     at[x] = pos;
-    pos += cnt[x];
+    pos += wide_cnt[x];
     at[x + X] = pos;
-    pos += cnt[x + X];
+    pos += group_cnt[x];
     pl->qlen[x] = (uint32_t)(pos - pl->qbeg[x]);
   }
-  // wide items in plan order, then the groups in assignment order (plan order inside a group)
-  for (int32_t q : pl->h_work) {
-    const int64_t f = pl->h_hub_first[q], c = pl->h_hub_count[q];
-    for (int64_t r = 0; r < c; ++r) {
-      const uint8_t k = qof[(size_t)(f + r)];
-      if (k < X) pl->h_xq[at[k]++] = pl->h_items[(size_t)(f + r)];
+  std::fill(load.begin(), load.end(), 0.0);  // replay the dealing of the wide items
+  std::vector<DevItem> tmp;
+  for (int32_t q : wide) {
+    const uint32_t c = pl->h_nitem[q];
+    tmp.resize(c);
+    emit_items(pl, q, tmp.data());
+    const double w = pl->h_tasks[q].est / (double)c;
+    for (uint32_t r = 0; r < c; ++r) {
+      const int x = least();
+      pl->h_xq[at[x]++] = tmp[r];
+      load[x] += w;
     }
   }
-  for (int x = 0; x < X; ++x)
-    for (int64_t g : gq[x])
-      for (int64_t q = gfirst[g]; q >= 0; q = gnext[q]) {
-        const int64_t f = pl->h_hub_first[q], c = pl->h_hub_count[q];
-        std::memcpy(pl->h_xq + at[x + X], pl->h_items.data() + f, sizeof(DevItem) * (size_t)c);
-        at[x + X] += (size_t)c;
-      }
+  for (int64_t g : gs)
+    for (int64_t q = gfirst[g]; q >= 0; q = gnext[q]) {
+      const int x = gq[g] + X;
+      emit_items(pl, (int32_t)q, pl->h_xq + at[x]);
+      at[x] += pl->h_nitem[q];
+    }
   return BBTC_OK;
 }
 
@@ -570,6 +607,7 @@ bbtc_status stream_setup(bbtc_plan* pl, hipStream_t s) {
     exact.cap = 0;
   }
   // group the work items by block pair, i-major
+  if (pl->h_items.size() != pl->nitems) compose_plan_order(pl);
   std::vector<DevItem> items = pl->h_items;
   auto pair_of = [&](const DevItem& it) {
     const bbtc_task& t = pl->h_tasks[it.task];
@@ -979,9 +1017,6 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
     HIP_TRY(hipMemcpyAsync(pl->h_heavy.data(), pl->heavy.ptr, sizeof(HeavyCol) * nheavy, hipMemcpyDeviceToHost, s),
             "D2H");
     HIP_TRY(hipStreamSynchronize(s), "sync");
-    std::sort(pl->h_heavy.begin(), pl->h_heavy.end(), [](const HeavyCol& a, const HeavyCol& b) {
-      return a.cid != b.cid ? a.cid < b.cid : a.v < b.v;
-    });
   }
 
   // ---- tasks (Alg. 4) and work items ----
@@ -994,17 +1029,19 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   if (queued) {
     bbtc_status qst = compose_queues(pl);
     if (qst != BBTC_OK) return qst;
+  } else {
+    compose_plan_order(pl);
   }
   const int64_t nt = (int64_t)pl->h_tasks.size();
   HIP_TRY(pl->acp.ensure((size_t)nb + 1), "alloc");
   HIP_TRY(pl->tasks.ensure((size_t)nt), "alloc tasks");
-  HIP_TRY((queued ? pl->xitems : pl->items).ensure(pl->h_items.size()), "alloc items");
+  HIP_TRY((queued ? pl->xitems : pl->items).ensure(pl->nitems), "alloc items");
   HIP_TRY(pl->cursor.ensure(kMaxQueues), "alloc");
   HIP_TRY(hipMemcpyAsync(pl->acp.ptr, acp.data(), sizeof(uint64_t) * (nb + 1), hipMemcpyHostToDevice, s), "H2D");
   HIP_TRY(hipMemcpyAsync(pl->tasks.ptr, pl->h_dtasks.data(), sizeof(DevTask) * nt, hipMemcpyHostToDevice, s), "H2D");
-  if (!pl->h_items.empty()) {
+  if (pl->nitems) {
     if (queued)
-      HIP_TRY(hipMemcpyAsync(pl->xitems.ptr, pl->h_xq, sizeof(DevItem) * pl->h_items.size(), hipMemcpyHostToDevice, s),
+      HIP_TRY(hipMemcpyAsync(pl->xitems.ptr, pl->h_xq, sizeof(DevItem) * pl->nitems, hipMemcpyHostToDevice, s),
               "H2D");
     else
       HIP_TRY(hipMemcpyAsync(pl->items.ptr, pl->h_items.data(), sizeof(DevItem) * pl->h_items.size(),
@@ -1021,7 +1058,7 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   st.p = p;
   st.ntasks = nt;
   st.work_tasks = (int64_t)pl->h_work.size();
-  st.nitems = (int64_t)pl->h_items.size();
+  st.nitems = (int64_t)pl->nitems;
   for (auto v : pl->h_nnz) st.m_max = std::max<int64_t>(st.m_max, v);
   st.m_avg = 2.0 * (double)m / ((double)p * (double)(p + 1));
   st.lambda = st.m_avg > 0 ? (double)st.m_max / st.m_avg : 0.0;
@@ -1079,7 +1116,7 @@ bbtc_status count_multi_impl(bbtc_plan* const* plans, int32_t nplans, hipStream_
   if (!S.done) HIP_TRY(hipEventCreateWithFlags(&S.done, hipEventDisableTiming), "hipEventCreate");
   if (S.used) HIP_TRY(hipEventSynchronize(S.done), "event sync");  // staging and buffers are free again
   size_t nitems = 0;
-  for (int32_t q = 0; q < nplans; ++q) nitems += plans[q]->h_items.size();
+  for (int32_t q = 0; q < nplans; ++q) nitems += plans[q]->nitems;
   if (S.cap_ctx < (size_t)nplans) {
     if (S.h_ctx) (void)hipHostFree(S.h_ctx);
     S.h_ctx = nullptr;
@@ -1103,7 +1140,10 @@ bbtc_status count_multi_impl(bbtc_plan* const* plans, int32_t nplans, hipStream_
   size_t at = 0;
   for (int32_t q = 0; q < nplans; ++q) S.h_ctx[q] = plan_ctx(plans[q], d_per_task[q], d_totals + q);
   for (const auto& pr : order) {
-    for (DevItem it : plans[pr.second]->h_items) {
+    const bbtc_plan* pq = plans[pr.second];
+    const DevItem* src = pq->h_items.size() == pq->nitems ? pq->h_items.data() : pq->h_xq;
+    for (size_t r = 0; r < pq->nitems; ++r) {
+      DevItem it = src[r];
       it.plan = pr.second;
       S.h_items[at++] = it;
     }
@@ -1171,13 +1211,13 @@ bbtc_status bbtc_count(bbtc_plan* pl, void* stream, uint64_t* d_per_task, uint64
   hipStream_t s = (hipStream_t)stream;
   if (pl->streamed) return count_streamed(pl, s, d_per_task, d_total);
   const int64_t nt = (int64_t)pl->h_tasks.size();
-  const bool graphed = pl->opt.mode == BBTC_MODE_PERSISTENT && pl->opt.graph == 0 && !pl->h_items.empty();
+  const bool graphed = pl->opt.mode == BBTC_MODE_PERSISTENT && pl->opt.graph == 0 && pl->nitems > 0;
   if (!graphed) HIP_TRY(launch_reset(d_per_task, nt, d_total, pl->cursor.ptr, s), "reset");
   CountParams cp;
   cp.one = plan_ctx(pl, d_per_task, d_total);
   cp.many = nullptr;
   cp.items = pl->items.ptr;
-  cp.nitems = (uint32_t)pl->h_items.size();
+  cp.nitems = (uint32_t)pl->nitems;
   cp.cursor = pl->cursor.ptr;
   one_queue(cp);
   if (pl->opt.mode == BBTC_MODE_PERSISTENT) {
