@@ -893,15 +893,7 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
                       pl->longrows.ptr, pl->err.ptr + 4, pl->hugerows.ptr, pl->err.ptr + 5,
                       (const uint32_t*)pl->keys_b.ptr, pl->od.ptr, pl->idg.ptr, s),
           "fill");
-  // acol is not built yet: its m entries serve as the huge-row sort scratch
-  HIP_TRY(pl->acol.ensure((size_t)m), "alloc active columns");
-  HIP_TRY(pl->midrows.ensure((size_t)n), "alloc");
-  HIP_TRY(hipMemsetAsync(pl->err.ptr, 0, 12, s), "memset");
-  HIP_TRY(launch_segsort(pl->orow.ptr, pl->ocol.ptr, n, pl->idbits, pl->midrows.ptr, pl->longrows.ptr,
-                         pl->hugerows.ptr, pl->err.ptr, pl->acol.ptr, s),
-          "sort out-rows");
-
-  // ---- cut vector (Sec. 4.1) ----
+  // ---- cut vector (Sec. 4.1): it needs only orow ----
   int32_t p = opt.p;
   if (p == 0) {  // p near the average degree (Sec. 7.2)
     double avg = 2.0 * (double)m / (double)n;
@@ -912,11 +904,30 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   pl->opt.p = p;
   HIP_TRY(pl->cuts.ensure((size_t)p + 1), "alloc cuts");
   HIP_TRY(launch_cuts(pl->orow.ptr, n, p, opt.cut_mode, pl->cuts.ptr, s), "cuts");
-  // in-rows: grouped by the part of each in-neighbour (all the counting needs)
-  HIP_TRY(hipMemsetAsync(pl->err.ptr, 0, 12, s), "memset");
-  HIP_TRY(launch_inrows(pl->irow.ptr, pl->icol.ptr, n, pl->midrows.ptr, pl->longrows.ptr, pl->hugerows.ptr,
-                        pl->err.ptr, pl->acol.ptr, pl->cuts.ptr, p, s),
+
+  // ---- rows: out-rows sorted on s, in-rows grouped by part on side[2], at once ----
+  // acol is not built yet: its m entries serve as the long/huge-row scratch of
+  // both chains, one after the other.  The in-row lists use od, idg and keys_a
+  // (free after the fill) and the counters err[5..7].
+  HIP_TRY(pl->acol.ensure((size_t)m), "alloc active columns");
+  HIP_TRY(pl->midrows.ensure((size_t)n), "alloc");
+  hipStream_t si = pl->side[2];
+  HIP_TRY(hipMemsetAsync(pl->err.ptr, 0, 32, s), "memset");
+  HIP_TRY(hipEventRecord(pl->ev_fork, s), "event");
+  HIP_TRY(hipStreamWaitEvent(si, pl->ev_fork, 0), "wait");
+  HIP_TRY(launch_inrows_sort(pl->irow.ptr, pl->icol.ptr, n, pl->od.ptr, pl->idg.ptr, (uint32_t*)pl->keys_a.ptr,
+                             pl->err.ptr + 5, si),
+          "sort in-rows");
+  HIP_TRY(launch_segsort(pl->orow.ptr, pl->ocol.ptr, n, pl->idbits, pl->midrows.ptr, pl->longrows.ptr,
+                         pl->hugerows.ptr, pl->err.ptr, pl->acol.ptr, s),
+          "sort out-rows");
+  HIP_TRY(hipEventRecord(pl->ev_join[0], s), "event");  // the out-rows are done with the scratch
+  HIP_TRY(hipStreamWaitEvent(si, pl->ev_join[0], 0), "wait");
+  HIP_TRY(launch_inrows_group(pl->irow.ptr, pl->icol.ptr, pl->idg.ptr, (const uint32_t*)pl->keys_a.ptr,
+                              pl->err.ptr + 5, pl->acol.ptr, pl->cuts.ptr, p, si),
           "group in-rows");
+  HIP_TRY(hipEventRecord(pl->ev_join[2], si), "event");
+  HIP_TRY(hipStreamWaitEvent(s, pl->ev_join[2], 0), "wait");
   pl->h_cuts.assign((size_t)p + 1, 0);
   HIP_TRY(hipMemcpyAsync(pl->h_cuts.data(), pl->cuts.ptr, sizeof(int32_t) * (p + 1), hipMemcpyDeviceToHost, s),
           "D2H cuts");
@@ -995,8 +1006,13 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   bb.heavy = pl->heavy.ptr;
   bb.nheavy = pl->err.ptr + 2;
   bb.heavy_cap = (uint32_t)hcap;
+  // out side on s, in side on side[2], at once
+  HIP_TRY(hipEventRecord(pl->ev_fork, s), "event");
+  HIP_TRY(hipStreamWaitEvent(si, pl->ev_fork, 0), "wait");
+  HIP_TRY(launch_tbot(bb, si), "block column index");
   HIP_TRY(launch_bot(bb, s), "block row index");
-  HIP_TRY(launch_tbot(bb, s), "block column index");
+  HIP_TRY(hipEventRecord(pl->ev_join[2], si), "event");
+  HIP_TRY(hipStreamWaitEvent(s, pl->ev_join[2], 0), "wait");
   HIP_TRY(scan_u32(pl->ccnt.ptr, pl->ccoff.ptr, cc, pl->partial.ptr, s), "scan chunk counters");
   HIP_TRY(launch_acol(bb, s), "active columns");
   std::vector<unsigned long long> hn((size_t)nb), hz((size_t)nb), hc((size_t)nb);

@@ -145,11 +145,14 @@ hipError_t launch_fill(const void* rowptr, int rp64, const int32_t* colidx, int6
 // scratch needs rp[nrows] entries.
 hipError_t launch_segsort(const uint32_t* rp, int32_t* col, int64_t nrows, int bits, uint32_t* midrows,
                           uint32_t* longrows, uint32_t* hugerows, uint32_t* q, int32_t* scratch, hipStream_t s);
-// In-rows grouped by part (short rows fully sorted, long ones by a counting
-// pass over the parts of cuts[0..p]).
-hipError_t launch_inrows(const uint32_t* rp, int32_t* col, int64_t nrows, uint32_t* midrows, uint32_t* longrows,
-                         uint32_t* hugerows, uint32_t* q, int32_t* scratch, const int32_t* cuts, int32_t p,
-                         hipStream_t s);
+// In-rows grouped by part: short rows fully sorted (launch_inrows_sort, which
+// lists the long and huge rows and counts them in q[0], q[1], q[2]), long
+// and huge ones by a counting pass over the parts of cuts[0..p] with
+// scratch[] (m words) (launch_inrows_group).
+hipError_t launch_inrows_sort(const uint32_t* rp, int32_t* col, int64_t nrows, uint32_t* midrows, uint32_t* longrows,
+                              uint32_t* hugerows, uint32_t* q, hipStream_t s);
+hipError_t launch_inrows_group(const uint32_t* rp, int32_t* col, const uint32_t* longrows, const uint32_t* hugerows,
+                               const uint32_t* q, int32_t* scratch, const int32_t* cuts, int32_t p, hipStream_t s);
 hipError_t launch_cuts(const uint32_t* orow, int64_t n, int32_t p, int mode, int32_t* cuts, hipStream_t s);
 
 struct BlockBuild {

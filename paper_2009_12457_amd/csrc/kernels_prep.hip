@@ -1286,18 +1286,20 @@ hipError_t launch_cuts(const uint32_t* orow, int64_t n, int32_t p, int mode, int
   return hipGetLastError();
 }
 
-hipError_t launch_inrows(const uint32_t* rp, int32_t* col, int64_t nrows, uint32_t* midrows, uint32_t* longrows,
-                         uint32_t* hugerows, uint32_t* q, int32_t* scratch, const int32_t* cuts, int32_t p,
-                         hipStream_t s) {
+hipError_t launch_inrows_sort(const uint32_t* rp, int32_t* col, int64_t nrows, uint32_t* midrows, uint32_t* longrows,
+                              uint32_t* hugerows, uint32_t* q, hipStream_t s) {
   if (nrows == 0) return hipSuccess;
   hipLaunchKernelGGL(k_segsort, dim3(grid_for((uint64_t)nrows, kThreads, kRowGrid)), dim3(kThreads), 0, s, rp, col,
                      nrows, midrows, longrows, hugerows, q);
   hipLaunchKernelGGL(k_segsort_mid, dim3(kRowGrid), dim3(kThreads), 0, s, rp, col, (const uint32_t*)midrows,
                      (const uint32_t*)q);
-  hipLaunchKernelGGL(k_group_parts<kThreads>, dim3(1024), dim3(kThreads), 0, s, rp, col, scratch,
-                     (const uint32_t*)longrows, (const uint32_t*)q, cuts, p);
-  hipLaunchKernelGGL(k_group_parts<1024>, dim3(256), dim3(1024), 0, s, rp, col, scratch, (const uint32_t*)hugerows,
-                     (const uint32_t*)(q + 1), cuts, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_inrows_group(const uint32_t* rp, int32_t* col, const uint32_t* longrows, const uint32_t* hugerows,
+                               const uint32_t* q, int32_t* scratch, const int32_t* cuts, int32_t p, hipStream_t s) {
+  hipLaunchKernelGGL(k_group_parts<kThreads>, dim3(1024), dim3(kThreads), 0, s, rp, col, scratch, longrows, q, cuts, p);
+  hipLaunchKernelGGL(k_group_parts<1024>, dim3(256), dim3(1024), 0, s, rp, col, scratch, hugerows, q + 1, cuts, p);
   return hipGetLastError();
 }
 
