@@ -77,6 +77,27 @@ int bits_for(uint64_t maxval) {  // bits to hold values 0..maxval
 
 }  // namespace
 
+// Pinned host staging for the small transfers of a partition (sizes, cut
+// vector, block statistics, task list): copies to and from pinned memory
+// are asynchronous DMA, copies to pageable memory each cost a round trip.
+struct PinnedStage {
+  char* ptr = nullptr;
+  size_t cap = 0;
+  hipError_t ensure(size_t bytes) {
+    if (ptr && bytes <= cap) return hipSuccess;
+    if (ptr) (void)hipHostFree(ptr);
+    ptr = nullptr;
+    cap = 0;
+    const size_t want = std::max<size_t>(bytes, 1 << 16);
+    hipError_t e = hipHostMalloc((void**)&ptr, want, hipHostMallocDefault);
+    if (e == hipSuccess) cap = want; else ptr = nullptr;
+    return e;
+  }
+  ~PinnedStage() {
+    if (ptr) (void)hipHostFree(ptr);
+  }
+};
+
 struct bbtc_plan {
   int64_t n = 0, m = 0;
   int32_t p = 0;
@@ -103,6 +124,7 @@ struct bbtc_plan {
   std::vector<DevTask> h_dtasks;   // same order
   std::vector<int32_t> h_work;     // plan-order indices of WORK tasks
   std::vector<DevItem> h_items;
+  PinnedStage stage;
   DevItem* h_xq = nullptr;         // pinned: queue x = h_xq[qbeg[x], qbeg[x] + qlen[x])
   size_t xq_cap = 0;
   uint32_t nq = 1, qbeg[kMaxQueues] = {0}, qlen[kMaxQueues] = {0};
@@ -874,7 +896,8 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
           "degrees");
   HIP_TRY(scan_u32(pl->od.ptr, pl->orow.ptr, (uint64_t)n, pl->partial.ptr, s), "scan out-degrees");
   HIP_TRY(scan_u32(pl->idg.ptr, pl->irow.ptr, (uint64_t)n, pl->partial.ptr, s), "scan in-degrees");
-  uint32_t mm[3] = {0, 0, 0};
+  HIP_TRY(pl->stage.ensure(64), "pinned alloc");
+  uint32_t* mm = (uint32_t*)pl->stage.ptr;
   HIP_TRY(hipMemcpyAsync(&mm[0], pl->orow.ptr + n, 4, hipMemcpyDeviceToHost, s), "D2H m");
   HIP_TRY(hipMemcpyAsync(&mm[1], pl->irow.ptr + n, 4, hipMemcpyDeviceToHost, s), "D2H m");
   HIP_TRY(hipMemcpyAsync(&mm[2], pl->err.ptr, 4, hipMemcpyDeviceToHost, s), "D2H err");
@@ -886,9 +909,8 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   // + 4: the counting kernels read out-rows in aligned 16-byte blocks
   HIP_TRY(pl->ocol.ensure((size_t)m + 4), "alloc ocol");
   HIP_TRY(pl->icol.ensure((size_t)m), "alloc icol");
-  // od/idg are consumed (scanned): reuse them as the huge rows' fill cursors
-  HIP_TRY(hipMemsetAsync(pl->od.ptr, 0, sizeof(uint32_t) * n, s), "memset");
-  HIP_TRY(hipMemsetAsync(pl->idg.ptr, 0, sizeof(uint32_t) * n, s), "memset");
+  // od/idg are consumed (scanned): their first entries become the huge rows'
+  // fill cursors (zeroed by launch_fill)
   HIP_TRY(launch_fill(rowptr, rp64, col, n, pl->perm.ptr, pl->orow.ptr, pl->irow.ptr, pl->ocol.ptr, pl->icol.ptr,
                       pl->longrows.ptr, pl->err.ptr + 4, pl->hugerows.ptr, pl->err.ptr + 5,
                       (const uint32_t*)pl->keys_b.ptr, pl->od.ptr, pl->idg.ptr, s),
@@ -928,10 +950,11 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
           "group in-rows");
   HIP_TRY(hipEventRecord(pl->ev_join[2], si), "event");
   HIP_TRY(hipStreamWaitEvent(s, pl->ev_join[2], 0), "wait");
-  pl->h_cuts.assign((size_t)p + 1, 0);
-  HIP_TRY(hipMemcpyAsync(pl->h_cuts.data(), pl->cuts.ptr, sizeof(int32_t) * (p + 1), hipMemcpyDeviceToHost, s),
+  HIP_TRY(pl->stage.ensure(sizeof(int32_t) * (p + 1)), "pinned alloc");
+  HIP_TRY(hipMemcpyAsync(pl->stage.ptr, pl->cuts.ptr, sizeof(int32_t) * (p + 1), hipMemcpyDeviceToHost, s),
           "D2H cuts");
   HIP_TRY(hipStreamSynchronize(s), "sync");
+  pl->h_cuts.assign((const int32_t*)pl->stage.ptr, (const int32_t*)pl->stage.ptr + p + 1);
 
   // ---- block row index (out side) and active columns (in side) ----
   const int64_t nb = (int64_t)p * (p + 1) / 2;
@@ -969,10 +992,19 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   HIP_TRY(pl->ccoff.ensure((size_t)cc + 1), "alloc");
   HIP_TRY(pl->dmax.ensure(2), "alloc");
   if (pl->partial.cap < scan_partial_entries(cc)) HIP_TRY(pl->partial.ensure(scan_partial_entries(cc) + 4096), "alloc");
-  HIP_TRY(hipMemcpyAsync(pl->chunk0.ptr, chunk0.data(), sizeof(int32_t) * (p + 1), hipMemcpyHostToDevice, s), "H2D");
-  HIP_TRY(hipMemcpyAsync(pl->ccbase.ptr, ccbase.data(), sizeof(uint64_t) * (p + 1), hipMemcpyHostToDevice, s), "H2D");
-  HIP_TRY(hipMemcpyAsync(pl->botp.ptr, botp.data(), sizeof(uint64_t) * (p + 1), hipMemcpyHostToDevice, s), "H2D");
-  HIP_TRY(hipMemcpyAsync(pl->tbotp.ptr, tbotp.data(), sizeof(uint64_t) * (p + 1), hipMemcpyHostToDevice, s), "H2D");
+  {  // through the pinned stage (the D2H below is ordered after these copies on s)
+    const size_t w = sizeof(uint64_t) * (p + 1);
+    HIP_TRY(pl->stage.ensure(4 * w), "pinned alloc");
+    char* st = pl->stage.ptr;
+    std::memcpy(st, chunk0.data(), sizeof(int32_t) * (p + 1));
+    std::memcpy(st + w, ccbase.data(), w);
+    std::memcpy(st + 2 * w, botp.data(), w);
+    std::memcpy(st + 3 * w, tbotp.data(), w);
+    HIP_TRY(hipMemcpyAsync(pl->chunk0.ptr, st, sizeof(int32_t) * (p + 1), hipMemcpyHostToDevice, s), "H2D");
+    HIP_TRY(hipMemcpyAsync(pl->ccbase.ptr, st + w, w, hipMemcpyHostToDevice, s), "H2D");
+    HIP_TRY(hipMemcpyAsync(pl->botp.ptr, st + 2 * w, w, hipMemcpyHostToDevice, s), "H2D");
+    HIP_TRY(hipMemcpyAsync(pl->tbotp.ptr, st + 3 * w, w, hipMemcpyHostToDevice, s), "H2D");
+  }
   HIP_TRY(hipMemsetAsync(pl->bnnz.ptr, 0, sizeof(unsigned long long) * nb, s), "memset");
   HIP_TRY(hipMemsetAsync(pl->bnzr.ptr, 0, sizeof(unsigned long long) * nb, s), "memset");
   HIP_TRY(hipMemsetAsync(pl->bnzc.ptr, 0, sizeof(unsigned long long) * nb, s), "memset");
@@ -1015,24 +1047,34 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   HIP_TRY(hipStreamWaitEvent(s, pl->ev_join[2], 0), "wait");
   HIP_TRY(scan_u32(pl->ccnt.ptr, pl->ccoff.ptr, cc, pl->partial.ptr, s), "scan chunk counters");
   HIP_TRY(launch_acol(bb, s), "active columns");
-  std::vector<unsigned long long> hn((size_t)nb), hz((size_t)nb), hc((size_t)nb);
   uint32_t hd[2] = {0, 0};
   uint32_t nheavy = 0;
-  HIP_TRY(hipMemcpyAsync(&nheavy, pl->err.ptr + 2, 4, hipMemcpyDeviceToHost, s), "D2H");
-  HIP_TRY(hipMemcpyAsync(hn.data(), pl->bnnz.ptr, sizeof(unsigned long long) * nb, hipMemcpyDeviceToHost, s), "D2H");
-  HIP_TRY(hipMemcpyAsync(hz.data(), pl->bnzr.ptr, sizeof(unsigned long long) * nb, hipMemcpyDeviceToHost, s), "D2H");
-  HIP_TRY(hipMemcpyAsync(hc.data(), pl->bnzc.ptr, sizeof(unsigned long long) * nb, hipMemcpyDeviceToHost, s), "D2H");
-  HIP_TRY(hipMemcpyAsync(hd, pl->dmax.ptr, sizeof(uint32_t) * 2, hipMemcpyDeviceToHost, s), "D2H");
-  HIP_TRY(hipStreamSynchronize(s), "sync");
-  pl->h_nnz.assign(hn.begin(), hn.end());
-  pl->h_nzr.assign(hz.begin(), hz.end());
-  pl->h_nzc.assign(hc.begin(), hc.end());
+  {  // block statistics through the pinned stage: [nheavy, dmax x2, pad] then bnnz, bnzr, bnzc
+    const size_t wb = sizeof(unsigned long long) * (size_t)nb;
+    HIP_TRY(pl->stage.ensure(16 + 3 * wb), "pinned alloc");
+    char* st = pl->stage.ptr;
+    uint32_t* sc = (uint32_t*)st;
+    const unsigned long long* sb = (const unsigned long long*)(st + 16);
+    HIP_TRY(hipMemcpyAsync(sc, pl->err.ptr + 2, 4, hipMemcpyDeviceToHost, s), "D2H");
+    HIP_TRY(hipMemcpyAsync(sc + 1, pl->dmax.ptr, sizeof(uint32_t) * 2, hipMemcpyDeviceToHost, s), "D2H");
+    HIP_TRY(hipMemcpyAsync(st + 16, pl->bnnz.ptr, wb, hipMemcpyDeviceToHost, s), "D2H");
+    HIP_TRY(hipMemcpyAsync(st + 16 + wb, pl->bnzr.ptr, wb, hipMemcpyDeviceToHost, s), "D2H");
+    HIP_TRY(hipMemcpyAsync(st + 16 + 2 * wb, pl->bnzc.ptr, wb, hipMemcpyDeviceToHost, s), "D2H");
+    HIP_TRY(hipStreamSynchronize(s), "sync");
+    nheavy = sc[0];
+    hd[0] = sc[1];
+    hd[1] = sc[2];
+    pl->h_nnz.assign(sb, sb + nb);
+    pl->h_nzr.assign(sb + nb, sb + 2 * nb);
+    pl->h_nzc.assign(sb + 2 * nb, sb + 3 * nb);
+  }
   if (nheavy > hcap) return fail(BBTC_EDEVICE, "hub column list overflow");
   pl->h_heavy.resize(nheavy);
   if (nheavy) {
-    HIP_TRY(hipMemcpyAsync(pl->h_heavy.data(), pl->heavy.ptr, sizeof(HeavyCol) * nheavy, hipMemcpyDeviceToHost, s),
-            "D2H");
+    HIP_TRY(pl->stage.ensure(sizeof(HeavyCol) * nheavy), "pinned alloc");
+    HIP_TRY(hipMemcpyAsync(pl->stage.ptr, pl->heavy.ptr, sizeof(HeavyCol) * nheavy, hipMemcpyDeviceToHost, s), "D2H");
     HIP_TRY(hipStreamSynchronize(s), "sync");
+    std::memcpy(pl->h_heavy.data(), pl->stage.ptr, sizeof(HeavyCol) * nheavy);
   }
 
   // ---- tasks (Alg. 4) and work items ----
@@ -1053,8 +1095,14 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   HIP_TRY(pl->tasks.ensure((size_t)nt), "alloc tasks");
   HIP_TRY((queued ? pl->xitems : pl->items).ensure(pl->nitems), "alloc items");
   HIP_TRY(pl->cursor.ensure(kMaxQueues), "alloc");
-  HIP_TRY(hipMemcpyAsync(pl->acp.ptr, acp.data(), sizeof(uint64_t) * (nb + 1), hipMemcpyHostToDevice, s), "H2D");
-  HIP_TRY(hipMemcpyAsync(pl->tasks.ptr, pl->h_dtasks.data(), sizeof(DevTask) * nt, hipMemcpyHostToDevice, s), "H2D");
+  {  // through the pinned stage; the final synchronisation below covers these copies
+    const size_t wa = sizeof(uint64_t) * (size_t)(nb + 1), wt = sizeof(DevTask) * (size_t)nt;
+    HIP_TRY(pl->stage.ensure(wa + wt), "pinned alloc");
+    std::memcpy(pl->stage.ptr, acp.data(), wa);
+    std::memcpy(pl->stage.ptr + wa, pl->h_dtasks.data(), wt);
+    HIP_TRY(hipMemcpyAsync(pl->acp.ptr, pl->stage.ptr, wa, hipMemcpyHostToDevice, s), "H2D");
+    HIP_TRY(hipMemcpyAsync(pl->tasks.ptr, pl->stage.ptr + wa, wt, hipMemcpyHostToDevice, s), "H2D");
+  }
   if (pl->nitems) {
     if (queued)
       HIP_TRY(hipMemcpyAsync(pl->xitems.ptr, pl->h_xq, sizeof(DevItem) * pl->nitems, hipMemcpyHostToDevice, s),

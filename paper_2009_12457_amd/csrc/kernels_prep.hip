@@ -593,6 +593,13 @@ __device__ __forceinline__ void scatter_run(const int32_t* __restrict__ colidx, 
   }
 }
 
+// Zeroes a[0..*count) and b[0..*count) (the huge rows' fill cursors).
+__global__ __launch_bounds__(kThreads) void k_zero2(uint32_t* __restrict__ a, uint32_t* __restrict__ b,
+                                                    const uint32_t* __restrict__ count) {
+  const uint32_t c = *count;
+  for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < c; x += gridDim.x * blockDim.x) a[x] = b[x] = 0;
+}
+
 // Listed rows: one wavefront per row (ballot compaction keeps input order).
 // Huge rows: chunks reserve their slots with atomics on per-row cursors
 // (cur_o/cur_i, zeroed, indexed by position in hlist), so the order inside
@@ -1253,6 +1260,7 @@ hipError_t launch_fill(const void* rowptr, int rp64, const int32_t* colidx, int6
                        uint32_t* cur_o, uint32_t* cur_i, hipStream_t s) {
   if (n == 0) return hipSuccess;
   const unsigned g = grid_for((uint64_t)n, kThreads, 65536);
+  hipLaunchKernelGGL(k_zero2, dim3(64), dim3(kThreads), 0, s, cur_o, cur_i, nhlist);
   if (rp64) {
     hipLaunchKernelGGL(k_fill_lane<int64_t>, dim3(g), dim3(kThreads), 0, s, (const int64_t*)rowptr, colidx, n, perm,
                        orow, irow, ocol, icol);
