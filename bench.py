@@ -30,6 +30,8 @@ WORKLOADS = {
     "er2000": ("er2000", 4, "Erdos-Renyi G(2000, 0.005), seed 1; p=4"),
     "rmat24": ("rmat24", 64, "R-MAT scale 24, edge factor 16, (a,b,c,d)=(.57,.19,.19,.05), seed 24; p=64"),
     "er24": ("er24", 64, "Erdos-Renyi n=2^24, average degree 32, seed 2; p=64"),
+    "rmat27": ("rmat27", 32, "R-MAT scale 27, edge factor 16, (a,b,c,d)=(.57,.19,.19,.05), seed 27; p=32; count "
+                             "under a device budget"),
 }
 PMC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2009_12457_amd", "csrc", "kernels_count.hip")
@@ -159,6 +161,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="rmat20", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-task baselines")
+    ap.add_argument("--device-budget-gb", type=float, default=0.0,
+                    help="device budget of the count phase (streams row stripes from pinned host memory)")
+    ap.add_argument("--oracle-check", action="store_true",
+                    help="also count the whole graph with the CPU oracle (all host threads) and compare totals")
     ap.add_argument("--profile-only", action="store_true", help="only the timed steps (for rocprofv3 runs)")
     ap.add_argument("--autotune", choices=["auto", "on", "off"], default="auto",
                     help="pick p and the row-mapping knobs with bbtc_autotune (auto: on for the 2^24 workloads)")
@@ -194,7 +201,8 @@ def main():
     n, rp, ci = bb.csr_of(g, "cuda")
     stream = torch.cuda.current_stream()
     sync = torch.cuda.synchronize
-    opt = bb.bbtc_options_default(p=p, mode=bb.BBTC_MODE_PERSISTENT)
+    opt = bb.bbtc_options_default(p=p, mode=bb.BBTC_MODE_PERSISTENT,
+                                  device_budget_bytes=int(args.device_budget_gb * (1 << 30)))
     tuned = None
     if args.autotune == "on" or (args.autotune == "auto" and args.workload in ("rmat24", "er24")):
         t = time.perf_counter()
@@ -244,7 +252,8 @@ def main():
 
     # ---- unbatched baselines: one launch per task (Intersect, HMap)
     plain = {}
-    for name, mode in (("plain_intersect", bb.BBTC_MODE_PLAIN_INTERSECT), ("plain_hmap", bb.BBTC_MODE_PLAIN_HMAP)):
+    for name, mode in () if args.no_plain else (("plain_intersect", bb.BBTC_MODE_PLAIN_INTERSECT),
+                                                 ("plain_hmap", bb.BBTC_MODE_PLAIN_HMAP)):
         o2 = bb.bbtc_options_default(p=p, mode=mode, wave_min=opt.wave_min)
         pl2 = bb.bbtc_partition(n, rp, ci, options=o2, trusted=True)
         pt2, tt2 = bb.bbtc_count(pl2)
@@ -284,6 +293,16 @@ def main():
                "sample": f"whole {args.workload} graph once: canonicalise, degree order, orient and per-task count "
                          f"(p={p}), {dt:.2f} s"}
 
+    oracle_check = None
+    if args.oracle_check:
+        import oracle
+        t = time.perf_counter()
+        otot = oracle.OracleGraph.from_graph(g).total(threads=oracle.max_threads())
+        oracle_check = {"oracle_total": int(otot), "match": int(otot) == triangles,
+                        "seconds": round(time.perf_counter() - t, 1), "threads": oracle.max_threads()}
+        if int(otot) != triangles:
+            raise SystemExit(f"oracle disagrees: {otot} vs {triangles}")
+
     serving = serving_bench(args.serving) if args.serving != "off" else None
 
     out = {
@@ -309,6 +328,10 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "serving": serving,
+        "oracle_check": oracle_check,
+        "streamed": {"device_budget_bytes": int(opt.device_budget_bytes),
+                     "footprint": int(st["footprint"]), "stripe_slots": int(st["stripe_slots"]),
+                     "stripe_uploads": int(st["stripe_uploads"])} if st["streamed"] else None,
         "paper_context": "paper Table 4, scale20 R-MAT (different generator/seed): 0.079 s copy-included on "
                          "2x20-core Xeon + up to 8x V100 = 2.0e8 edges/s; context only",
     }
