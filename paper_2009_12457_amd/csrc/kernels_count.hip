@@ -102,12 +102,27 @@ struct TaskCtx {
   const int32_t* ac;        // active columns of block (i,j)
 };
 
+// Read through the constant address space: with a wave-uniform address this
+// is a scalar load into scalar registers.  Only for data that no kernel
+// writes while the count runs (plan tables, items, graph arrays).
+template <class T>
+__device__ __forceinline__ T ld_const(const T* p) {
+  static_assert(sizeof(T) % 4 == 0, "word-sized records only");
+  typedef const __attribute__((address_space(4))) uint32_t* cword;
+  const cword q = (cword)p;
+  T r;
+  uint32_t* d = reinterpret_cast<uint32_t*>(&r);
+#pragma unroll
+  for (uint32_t x = 0; x < sizeof(T) / 4; ++x) d[x] = q[x];
+  return r;
+}
+
 __device__ __forceinline__ TaskCtx make_ctx(const GraphView& g, const DevTask& t) {
   TaskCtx c;
-  c.ci = g.cuts[t.i];
-  c.cj = g.cuts[t.j];
-  c.ck = g.cuts[t.k];
-  c.ck1 = g.cuts[t.k + 1];
+  c.ci = ld_const(g.cuts + t.i);
+  c.cj = ld_const(g.cuts + t.j);
+  c.ck = ld_const(g.cuts + t.k);
+  c.ck1 = ld_const(g.cuts + t.k + 1);
   c.i = t.i;
   c.dk = t.k - t.i;
   c.dkj = t.k - t.j;
@@ -122,14 +137,14 @@ __device__ __forceinline__ TaskCtx make_ctx(const GraphView& g, const DevTask& t
     c.colj = g.colJ;
     c.icolj = g.icolJ;
   } else {
-    c.boti = g.bot + g.botp[t.i];
-    c.botj = g.bot + g.botp[t.j];
-    c.tbotj = g.tbot + g.tbotp[t.j];
+    c.boti = g.bot + ld_const(g.botp + t.i);
+    c.botj = g.bot + ld_const(g.botp + t.j);
+    c.tbotj = g.tbot + ld_const(g.tbotp + t.j);
     c.coli = g.ocol;
     c.colj = g.ocol;
     c.icolj = g.icol;
   }
-  c.ac = g.acol + g.acp[col_block_id(t.i, t.j)];
+  c.ac = g.acol + ld_const(g.acp + col_block_id(t.i, t.j));
   return c;
 }
 
@@ -388,6 +403,19 @@ __device__ __forceinline__ void col_bounds(const TaskCtx& c, uint32_t x, uint32_
   i1 = tr[c.i + 1];
 }
 
+// col_bounds for a column index that is the same on every lane: scalar loads.
+__device__ __forceinline__ void col_bounds_uniform(const TaskCtx& c, uint32_t x, uint32_t& c0, uint32_t& c1,
+                                                   uint32_t& i0, uint32_t& i1) {
+  x = __builtin_amdgcn_readfirstlane(x);
+  const int32_t v = ld_const(c.ac + x);
+  const uint32_t* vr = c.botj + (uint64_t)(v - c.cj) * c.strj;
+  const uint32_t* tr = c.tbotj + (uint64_t)(v - c.cj) * c.tstrj;
+  c0 = ld_const(vr + c.dkj);
+  c1 = ld_const(vr + c.dkj + 1);
+  i0 = ld_const(tr + c.i);
+  i1 = ld_const(tr + c.i + 1);
+}
+
 // 1 if w is in the sorted run buf[lo, hi).
 __device__ __forceinline__ uint32_t run_has(const uint32_t* buf, uint32_t lo, uint32_t hi, uint32_t w) {
   const uint32_t end = hi;
@@ -524,7 +552,7 @@ __device__ uint64_t process_cols(const PlanCtx& cp, const TaskCtx& c, uint32_t l
     const uint32_t nq = s.qn;
     for (uint32_t h = w; h < nq; h += 4) {
       uint32_t qc0, qc1, qi0, qi1;
-      col_bounds(c, s.q[h], qc0, qc1, qi0, qi1);
+      col_bounds_uniform(c, s.q[h], qc0, qc1, qi0, qi1);
       const bool use_hash = cp.hash_min >= 0 && (qc1 - qc0) >= (uint32_t)cp.hash_min;
       cnt += wave_col(c, qi0, qi1, qc0, qc1, use_hash, s.abuf[w], s.w.sa0[w], s.w.sa1[w], s.w.sex[w]);
     }
@@ -548,7 +576,7 @@ __device__ uint64_t process_cols(const PlanCtx& cp, const TaskCtx& c, uint32_t l
     const uint32_t nwide = s.qw;
     for (uint32_t h = 0; h < nwide; ++h) {
       uint32_t qc0, qc1, qi0, qi1;
-      col_bounds(c, s.q[kThreads - 1 - h], qc0, qc1, qi0, qi1);
+      col_bounds_uniform(c, s.q[kThreads - 1 - h], qc0, qc1, qi0, qi1);
       cnt += group_col(cp, c, qi0, qi1, qc0, qc1, s);
     }
     if (t == 0) s.qn = s.qw = 0;
@@ -588,9 +616,9 @@ __device__ uint64_t group_col(const PlanCtx& cp, const TaskCtx& c, uint32_t i0, 
 __device__ uint64_t hub_chunk(const PlanCtx& cp, const TaskCtx& c, int32_t v, uint32_t lo, uint32_t hi,
                               CountLds& s) {
   const uint32_t* vr = c.botj + (uint64_t)(v - c.cj) * c.strj;
-  const uint32_t c0 = vr[c.dkj], c1 = vr[c.dkj + 1];
+  const uint32_t c0 = ld_const(vr + c.dkj), c1 = ld_const(vr + c.dkj + 1);
   const uint32_t* tr = c.tbotj + (uint64_t)(v - c.cj) * c.tstrj;
-  const uint32_t ib = tr[c.i], ie = tr[c.i + 1];
+  const uint32_t ib = ld_const(tr + c.i), ie = ld_const(tr + c.i + 1);
   const uint32_t i0 = min(ib + lo, ie), i1 = min(ib + hi, ie);
   if (c1 <= c0 || i1 <= i0) return 0;  // uniform across the workgroup
   return group_col(cp, c, i0, i1, c0, c1, s);
@@ -612,7 +640,7 @@ __device__ __forceinline__ void flush(const PlanCtx& cp, int32_t out, uint64_t c
 }
 
 __device__ __forceinline__ uint64_t run_item(const PlanCtx& pc, const DevItem& item, CountLds& s, int32_t* out) {
-  const DevTask t = pc.tasks[item.task];
+  const DevTask t = ld_const(pc.tasks + item.task);
   const TaskCtx c = make_ctx(pc.g, t);
   *out = t.out;
   if (item.v >= 0) return hub_chunk(pc, c, item.v, item.lo, item.hi, s);
@@ -627,7 +655,7 @@ BBTC_COUNT_KERNEL void k_count_items(CountParams cp, uint32_t first) {
   __shared__ CountLds s;
   init_lds(s);
   const PlanCtx& pc = cp.one;
-  const DevItem item = cp.items[first + blockIdx.x];
+  const DevItem item = ld_const(cp.items + first + blockIdx.x);
   int32_t out = 0;
   const uint64_t cnt = run_item(pc, item, s, &out);
   flush(pc, out, cnt, s);
@@ -656,11 +684,12 @@ BBTC_COUNT_KERNEL void k_count_persistent(CountParams cp) {
       s.item = it;
     }
     __syncthreads();
-    const uint32_t it = s.item;
+    // the claimed item is uniform: keep it (and all that derives from it) in scalar registers
+    const uint32_t it = __builtin_amdgcn_readfirstlane(s.item);
     __syncthreads();
     if (it >= cp.nitems) break;
-    const DevItem item = cp.items[it];
-    const PlanCtx pc = MULTI ? cp.many[item.plan] : cp.one;
+    const DevItem item = ld_const(cp.items + it);
+    const PlanCtx pc = MULTI ? ld_const(cp.many + item.plan) : cp.one;
     int32_t out = 0;
     const uint64_t cnt = run_item(pc, item, s, &out);
     flush(pc, out, cnt, s);
