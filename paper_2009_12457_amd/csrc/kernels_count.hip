@@ -416,21 +416,12 @@ __device__ __forceinline__ void col_bounds_uniform(const TaskCtx& c, uint32_t x,
   i1 = ld_const(tr + c.i + 1);
 }
 
-// 1 if w is in the sorted run buf[lo, hi).
-__device__ __forceinline__ uint32_t run_has(const uint32_t* buf, uint32_t lo, uint32_t hi, uint32_t w) {
-  const uint32_t end = hi;
-  while (lo < hi) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (buf[mid] < w) lo = mid + 1; else hi = mid;
-  }
-  return (lo < end && buf[lo] == w) ? 1u : 0u;
-}
-
 // Packed short columns [a0, b0) of a pass (bounds in c0s/i0s, prefixes in
 // soff/ioff), by one wavefront, window by window: a window is the longest run
 // of columns whose lists fit the wavefront's stage together.  The lists are
 // copied, sorted, side by side; every probe is a binary search in its own
-// column's run.
+// column's run, in fixed halving steps from the window's longest run so that
+// the eight searches of a segment advance together.
 __device__ uint64_t short_cols(const TaskCtx& c, CountLds& s, uint32_t a0, uint32_t b0, int w) {
   const int32_t* __restrict__ colj = c.colj;
   const int32_t* __restrict__ coli = c.coli;
@@ -450,6 +441,10 @@ __device__ uint64_t short_cols(const TaskCtx& c, CountLds& s, uint32_t a0, uint3
       if (s.soff[mid] - sbase <= (uint32_t)kABuf) b = mid; else hi = mid - 1;
     }
     const uint32_t span = s.soff[b] - sbase;
+    uint32_t mx = 0;
+    for (uint32_t k = a + l; k < b; k += kWave) mx = max(mx, s.soff[k + 1] - s.soff[k]);
+    mx = wave_max_u32(mx);
+    const uint32_t top = mx > 1 ? 1u << (31 - __clz(mx - 1)) : 0u;  // 2*top > longest run - 1
     for (uint32_t g = l; g < span; g += kWave) {
       const uint32_t k = owner_of(s.soff, a, b, sbase + g);
       stage[g] = (uint32_t)colj[s.c0s[k] + (sbase + g - s.soff[k])];
@@ -483,10 +478,20 @@ __device__ uint64_t short_cols(const TaskCtx& c, CountLds& s, uint32_t a0, uint3
           const uint32_t lo = s.soff[k2] - sbase, hi2 = s.soff[k2 + 1] - sbase;
           uint32_t wv[kSegW];
           load_seg_w(coli, sa0[o], sa1[o], q - sex[o], wv);
-          const uint32_t wmin = stage[lo], wmax = stage[hi2 - 1];
+          // pos: the last position of the run whose value is <= w (lo if none is);
+          // padding entries (all ones) are never in a run
+          uint32_t pos[kSegW];
 #pragma unroll
-          for (uint32_t x = 0; x < kSegW; ++x)
-            if (wv[x] >= wmin && wv[x] <= wmax) lc += run_has(stage, lo, hi2, wv[x]);
+          for (uint32_t x = 0; x < kSegW; ++x) pos[x] = lo;
+          for (uint32_t step = top; step > 0; step >>= 1) {
+#pragma unroll
+            for (uint32_t x = 0; x < kSegW; ++x) {
+              const uint32_t nx = pos[x] + step;
+              if (nx < hi2 && stage[nx] <= wv[x]) pos[x] = nx;
+            }
+          }
+#pragma unroll
+          for (uint32_t x = 0; x < kSegW; ++x) lc += stage[pos[x]] == wv[x] ? 1u : 0u;
         }
       }
       cnt += lc;
