@@ -90,6 +90,7 @@ struct CountLds {
 
 struct TaskCtx {
   int32_t ci, cj, ck, ck1;
+  int32_t kb;               // bitmap origin: ck rounded down to a multiple of 32
   int32_t i, dk, dkj;       // i, k-i, k-j
   uint32_t stri, strj;      // out-side row strides of parts i and j
   uint32_t tstrj;           // in-side row stride of part j
@@ -123,6 +124,7 @@ __device__ __forceinline__ TaskCtx make_ctx(const GraphView& g, const DevTask& t
   c.cj = ld_const(g.cuts + t.j);
   c.ck = ld_const(g.cuts + t.k);
   c.ck1 = ld_const(g.cuts + t.k + 1);
+  c.kb = c.ck & ~31;
   c.i = t.i;
   c.dk = t.k - t.i;
   c.dkj = t.k - t.j;
@@ -184,7 +186,7 @@ template <uint32_t NW>
 __device__ __forceinline__ Stage pick_stage(const TaskCtx& c, bool use_hash, uint32_t len) {
   constexpr int hb = log2i((int)NW);
   if (!use_hash) return Stage{0, NW, NW, hb};
-  if ((uint32_t)(c.ck1 - c.ck) <= NW * 32u) return Stage{1, len, NW, hb};
+  if ((uint32_t)(c.ck1 - c.kb) <= NW * 32u) return Stage{1, len, NW, hb};
   return Stage{2, NW / 2, NW, hb};
 }
 
@@ -197,12 +199,12 @@ __device__ __forceinline__ uint32_t pieces(const TaskCtx& c, bool use_hash, uint
 
 // Fills buf with col[lo, lo+sn) by `nthr` cooperating threads numbered tid.
 __device__ __forceinline__ void stage_fill(const Stage& st, uint32_t* buf, const int32_t* __restrict__ col,
-                                           uint32_t lo, uint32_t sn, int32_t ck, uint32_t tid, uint32_t nthr) {
+                                           uint32_t lo, uint32_t sn, int32_t kb, uint32_t tid, uint32_t nthr) {
   if (st.mode == 0) {
     for (uint32_t t = tid; t < sn; t += nthr) buf[t] = (uint32_t)col[lo + t];
-  } else if (st.mode == 1) {
+  } else if (st.mode == 1) {  // bit w - kb
     for (uint32_t t = tid; t < sn; t += nthr) {
-      const uint32_t x = (uint32_t)(col[lo + t] - ck);
+      const uint32_t x = (uint32_t)(col[lo + t] - kb);
       atomicOr(&buf[x >> 5], 1u << (x & 31));
     }
   } else {
@@ -216,39 +218,14 @@ __device__ __forceinline__ void stage_fill(const Stage& st, uint32_t* buf, const
 
 // Restores the all-zero buffer after stage_fill.
 __device__ __forceinline__ void stage_clear(const Stage& st, uint32_t* buf, const int32_t* __restrict__ col,
-                                            uint32_t lo, uint32_t sn, int32_t ck, uint32_t tid, uint32_t nthr) {
+                                            uint32_t lo, uint32_t sn, int32_t kb, uint32_t tid, uint32_t nthr) {
   if (st.mode == 0) {
     for (uint32_t t = tid; t < sn; t += nthr) buf[t] = 0;
   } else if (st.mode == 1) {
-    for (uint32_t t = tid; t < sn; t += nthr) buf[(uint32_t)(col[lo + t] - ck) >> 5] = 0;
+    for (uint32_t t = tid; t < sn; t += nthr) buf[(uint32_t)(col[lo + t] - kb) >> 5] = 0;
   } else {
     for (uint32_t t = tid; t < st.nw; t += nthr) buf[t] = 0;
   }
-}
-
-__device__ __forceinline__ uint32_t stage_has(const Stage& st, const uint32_t* buf, uint32_t sn, int32_t w,
-                                              int32_t ck) {
-  if (st.mode == 0) {
-    uint32_t x = 0, y = sn;
-    while (x < y) {
-      const uint32_t mid = (x + y) >> 1;
-      if (buf[mid] < (uint32_t)w) x = mid + 1; else y = mid;
-    }
-    return (x < sn && buf[x] == (uint32_t)w) ? 1u : 0u;
-  }
-  if (st.mode == 1) {
-    const uint32_t x = (uint32_t)(w - ck);
-    return (buf[x >> 5] >> (x & 31)) & 1u;
-  }
-  const uint32_t key = (uint32_t)w + 1u;
-  uint32_t s = hash_slot((uint32_t)w, st.hbits);
-  for (uint32_t guard = 0; guard < st.nw; ++guard) {
-    const uint32_t kk = buf[s];
-    if (kk == key) return 1u;
-    if (kk == 0u) return 0u;
-    s = (s + 1) & (st.nw - 1);
-  }
-  return 0u;
 }
 
 // Wavefront probes use wider segments: kSegW entries, two aligned 16-byte
@@ -259,8 +236,11 @@ __device__ __forceinline__ uint32_t seg_count_w(uint32_t a0, uint32_t a1) {
   return a1 > a0 ? (a1 - (a0 & ~(kSeg - 1)) + kSegW - 1) / kSegW : 0u;
 }
 
-__device__ __forceinline__ void load_seg_w(const int32_t* __restrict__ col, uint32_t a0, uint32_t a1, uint32_t q,
-                                           uint32_t w[kSegW]) {
+// Segment q of the list col[a0, a1) as read, entries outside the list
+// included (neighbouring rows, or all ones where the second block is not
+// read); returns the mask of the positions that belong to the list.
+__device__ __forceinline__ uint32_t load_seg_raw(const int32_t* __restrict__ col, uint32_t a0, uint32_t a1,
+                                                 uint32_t q, uint32_t w[kSegW]) {
   const uint32_t s0 = (a0 & ~(kSeg - 1)) + q * kSegW;
   const int4 v0 = *reinterpret_cast<const int4*>(col + s0);
   int4 v1 = make_int4(-1, -1, -1, -1);
@@ -273,9 +253,15 @@ __device__ __forceinline__ void load_seg_w(const int32_t* __restrict__ col, uint
   w[5] = (uint32_t)v1.y;
   w[6] = (uint32_t)v1.z;
   w[7] = (uint32_t)v1.w;
-  // valid positions of the segment as a bit mask: [a0 - s0, a1 - s0) within [0, 8)
+  // [a0 - s0, a1 - s0) within [0, 8)
   const uint32_t lo = a0 > s0 ? a0 - s0 : 0u, hi = min(a1 - s0, kSegW);
-  const uint32_t vm = ((1u << hi) - 1u) & ~((1u << lo) - 1u);
+  return ((1u << hi) - 1u) & ~((1u << lo) - 1u);
+}
+
+// The same with the positions outside the list set to all ones.
+__device__ __forceinline__ void load_seg_w(const int32_t* __restrict__ col, uint32_t a0, uint32_t a1, uint32_t q,
+                                           uint32_t w[kSegW]) {
+  const uint32_t vm = load_seg_raw(col, a0, a1, q, w);
 #pragma unroll
   for (uint32_t x = 0; x < kSegW; ++x)
     if (!((vm >> x) & 1u)) w[x] = 0xFFFFFFFFu;
@@ -284,28 +270,45 @@ __device__ __forceinline__ void load_seg_w(const int32_t* __restrict__ col, uint
 // The probe rounds of one batch: segment q of the batch goes to lane q mod 64;
 // its owner (the in-neighbour whose list holds it) is found by binary search
 // over the batch's exclusive prefix of segment counts.  MODE is the stage
-// form, fixed for the whole loop: 1 = bitmap over V_k (every list entry lies
-// in V_k, so the only test is the masked tail), 2 = hash, 0 = sorted copy;
-// for 0 and 2 entries outside [smin, smax] cannot match and are skipped.
+// form, fixed for the whole loop: 1 = bitmap over V_k, 2 = hash, 0 = sorted
+// copy; for 0 and 2 entries outside [smin, smax] cannot match and are
+// skipped.  The bitmap tests all eight positions without branches (every
+// list entry lies in V_k; the others are clamped into the bitmap) and keeps
+// the hits of the list's own positions.
 template <int MODE>
 __device__ __forceinline__ uint32_t probe_rounds(const int32_t* __restrict__ col, uint32_t tot, const uint32_t* sa0,
                                                  const uint32_t* sa1, const uint32_t* sex, const Stage& st,
                                                  const uint32_t* buf, uint32_t sn, uint32_t smin, uint32_t smax,
-                                                 int32_t ck, uint32_t width) {
+                                                 uint32_t kb, uint32_t klast) {
   const uint32_t l = (uint32_t)lane_id();
   uint32_t cnt = 0;
   for (uint32_t qb = 0; qb < tot; qb += kWave) {
     const uint32_t q = qb + l;
-    if (q < tot) {
+    if (q < tot && MODE == 1) {
+      const uint32_t o = owner64(sex, q);
+      uint32_t w[kSegW];
+      const uint32_t vm = load_seg_raw(col, sa0[o], sa1[o], q - sex[o], w);
+      // bit w - kb of the bitmap (kb is a multiple of 32, so the bit within
+      // its word is w mod 32); positions outside the list are clamped into
+      // [kb, klast] and their hits dropped by the mask
+      const uint32_t kw = kb >> 5;
+      uint32_t wd[kSegW];
+#pragma unroll
+      for (uint32_t t = 0; t < kSegW; ++t) {
+        w[t] = min(max(w[t], kb), klast);
+        wd[t] = buf[(w[t] >> 5) - kw];
+      }
+      uint32_t hit = 0;
+#pragma unroll
+      for (uint32_t t = 0; t < kSegW; ++t) hit |= __builtin_amdgcn_ubfe(wd[t], w[t], 1u) << t;  // offset taken mod 32
+      cnt += __popc(hit & vm);
+    } else if (q < tot) {
       const uint32_t o = owner64(sex, q);
       uint32_t w[kSegW];
       load_seg_w(col, sa0[o], sa1[o], q - sex[o], w);
 #pragma unroll
       for (uint32_t t = 0; t < kSegW; ++t) {
-        if (MODE == 1) {
-          const uint32_t x = w[t] - (uint32_t)ck;
-          if (x < width) cnt += (buf[x >> 5] >> (x & 31)) & 1u;
-        } else if (w[t] >= smin && w[t] <= smax) {
+        if (w[t] >= smin && w[t] <= smax) {
           if (MODE == 2) {
             const uint32_t key = w[t] + 1u;
             uint32_t h = hash_slot(w[t], st.hbits);
@@ -343,7 +346,7 @@ __device__ uint64_t probe_flat(const TaskCtx& c, uint32_t i0, uint32_t i1, const
   const int32_t* __restrict__ col = c.coli;
   const int32_t* __restrict__ icol = c.icolj;
   const uint32_t l = (uint32_t)lane_id();
-  const uint32_t width = (uint32_t)(c.ck1 - c.ck);
+  const uint32_t kb = (uint32_t)c.kb, klast = (uint32_t)(c.ck1 - 1);
   uint64_t cnt = 0;
   for (uint32_t eb = i0; eb < i1; eb += kWave) {
     const uint32_t e = eb + l;
@@ -362,11 +365,11 @@ __device__ uint64_t probe_flat(const TaskCtx& c, uint32_t i0, uint32_t i1, const
     sex[l] = inc - nseg;
     wave_sync();
     if (st.mode == 1)
-      cnt += probe_rounds<1>(col, tot, sa0, sa1, sex, st, buf, sn, (uint32_t)smin, (uint32_t)smax, c.ck, width);
+      cnt += probe_rounds<1>(col, tot, sa0, sa1, sex, st, buf, sn, (uint32_t)smin, (uint32_t)smax, kb, klast);
     else if (st.mode == 2)
-      cnt += probe_rounds<2>(col, tot, sa0, sa1, sex, st, buf, sn, (uint32_t)smin, (uint32_t)smax, c.ck, width);
+      cnt += probe_rounds<2>(col, tot, sa0, sa1, sex, st, buf, sn, (uint32_t)smin, (uint32_t)smax, kb, klast);
     else
-      cnt += probe_rounds<0>(col, tot, sa0, sa1, sex, st, buf, sn, (uint32_t)smin, (uint32_t)smax, c.ck, width);
+      cnt += probe_rounds<0>(col, tot, sa0, sa1, sex, st, buf, sn, (uint32_t)smin, (uint32_t)smax, kb, klast);
     wave_sync();
   }
   return cnt;
@@ -381,10 +384,10 @@ __device__ uint64_t wave_col(const TaskCtx& c, uint32_t i0, uint32_t i1, uint32_
   const Stage st = pick_stage<kABuf>(c, use_hash, c1 - c0);
   for (uint32_t s_lo = c0; s_lo < c1; s_lo += st.piece) {
     const uint32_t sn = min(st.piece, c1 - s_lo);
-    stage_fill(st, abuf, col, s_lo, sn, c.ck, l, kWave);
+    stage_fill(st, abuf, col, s_lo, sn, c.kb, l, kWave);
     wave_sync();
     cnt += probe_flat(c, i0, i1, st, abuf, sn, col[s_lo], col[s_lo + sn - 1], sa0, sa1, sex);
-    stage_clear(st, abuf, col, s_lo, sn, c.ck, l, kWave);
+    stage_clear(st, abuf, col, s_lo, sn, c.kb, l, kWave);
     wave_sync();
   }
   return cnt;
@@ -477,9 +480,8 @@ __device__ uint64_t short_cols(const TaskCtx& c, CountLds& s, uint32_t a0, uint3
           const uint32_t k2 = scol[o];
           const uint32_t lo = s.soff[k2] - sbase, hi2 = s.soff[k2 + 1] - sbase;
           uint32_t wv[kSegW];
-          load_seg_w(coli, sa0[o], sa1[o], q - sex[o], wv);
-          // pos: the last position of the run whose value is <= w (lo if none is);
-          // padding entries (all ones) are never in a run
+          const uint32_t vm = load_seg_raw(coli, sa0[o], sa1[o], q - sex[o], wv);
+          // pos: the last position of the run whose value is <= w (lo if none is)
           uint32_t pos[kSegW];
 #pragma unroll
           for (uint32_t x = 0; x < kSegW; ++x) pos[x] = lo;
@@ -490,8 +492,10 @@ __device__ uint64_t short_cols(const TaskCtx& c, CountLds& s, uint32_t a0, uint3
               if (nx < hi2 && stage[nx] <= wv[x]) pos[x] = nx;
             }
           }
+          uint32_t hit = 0;
 #pragma unroll
-          for (uint32_t x = 0; x < kSegW; ++x) lc += stage[pos[x]] == wv[x] ? 1u : 0u;
+          for (uint32_t x = 0; x < kSegW; ++x) hit |= (stage[pos[x]] == wv[x] ? 1u : 0u) << x;
+          lc += __popc(hit & vm);
         }
       }
       cnt += lc;
@@ -606,12 +610,12 @@ __device__ uint64_t group_col(const PlanCtx& cp, const TaskCtx& c, uint32_t i0, 
   uint32_t* buf = &s.abuf[0][0];
   for (uint32_t s_lo = c0; s_lo < c1; s_lo += st.piece) {
     const uint32_t sn = min(st.piece, c1 - s_lo);
-    stage_fill(st, buf, col, s_lo, sn, c.ck, threadIdx.x, kThreads);
+    stage_fill(st, buf, col, s_lo, sn, c.kb, threadIdx.x, kThreads);
     __syncthreads();
     cnt += probe_flat(c, w0, w1, st, buf, sn, col[s_lo], col[s_lo + sn - 1], s.w.sa0[w], s.w.sa1[w],
                       s.w.sex[w]);
     __syncthreads();
-    stage_clear(st, buf, col, s_lo, sn, c.ck, threadIdx.x, kThreads);
+    stage_clear(st, buf, col, s_lo, sn, c.kb, threadIdx.x, kThreads);
     __syncthreads();
   }
   return cnt;
