@@ -117,6 +117,7 @@ struct bbtc_plan {
   DevBuf<DevItem> items;
   DevBuf<DevItem> xitems;          // the same items as per-XCD queues (persistent launches)
   DevBuf<HeavyCol> heavy;
+  DevBuf<char> emit;               // inputs of the item-emission kernel
   // host
   std::vector<int32_t> h_cuts;
   std::vector<int64_t> h_nnz, h_nzr, h_nzc;  // nzc in column-major block order
@@ -125,13 +126,13 @@ struct bbtc_plan {
   std::vector<int32_t> h_work;     // plan-order indices of WORK tasks
   std::vector<DevItem> h_items;
   PinnedStage stage;
-  DevItem* h_xq = nullptr;         // pinned: queue x = h_xq[qbeg[x], qbeg[x] + qlen[x])
-  size_t xq_cap = 0;
+  std::vector<ItemRun> h_runs;     // the per-XCD queues as runs of task items (sorted by position)
   uint32_t nq = 1, qbeg[kMaxQueues] = {0}, qlen[kMaxQueues] = {0};
   std::vector<HeavyCol> h_heavy;   // hub columns, sorted by (block, column)
   std::vector<int64_t> h_hub_first, h_hub_count;  // per plan-order task: its range of h_items
-  // per plan-order task: work items, columns per range item; hub records per block
-  std::vector<uint32_t> h_nitem, h_nper;
+  // per plan-order task: work items, columns per range item, hub-chunk items;
+  // hub records per block
+  std::vector<uint32_t> h_nitem, h_nper, h_nhub;
   std::vector<int64_t> h_hstart;
   size_t nitems = 0;                // work items of the plan (either layout)
   uint32_t split = 0;              // in-slice length above which a column is a hub
@@ -199,7 +200,6 @@ struct bbtc_plan {
   ~bbtc_plan() {
     drop_graph();
     drop_stream();
-    if (h_xq) (void)hipHostFree(h_xq);
     for (int q = 0; q < 4; ++q) {
       if (side[q]) (void)hipStreamDestroy(side[q]);
       if (ev_join[q]) (void)hipEventDestroy(ev_join[q]);
@@ -213,6 +213,7 @@ struct bbtc_plan {
     bot.release(); tbot.release(); ccnt.release(); ccoff.release(); dmax.release(); cursor.release();
     err.release(); ccbase.release(); botp.release(); tbotp.release(); acp.release(); bnnz.release();
     bnzr.release(); bnzc.release(); tasks.release(); items.release(); xitems.release(); heavy.release();
+    emit.release();
   }
 
   size_t footprint() const {
@@ -222,7 +223,8 @@ struct bbtc_plan {
            hugerows.bytes() + bot.bytes() +
            tbot.bytes() + ccnt.bytes() + ccoff.bytes() + dmax.bytes() + cursor.bytes() + err.bytes() +
            ccbase.bytes() + botp.bytes() + tbotp.bytes() + acp.bytes() + bnnz.bytes() + bnzr.bytes() +
-           bnzc.bytes() + tasks.bytes() + items.bytes() + xitems.bytes() + heavy.bytes() + cache.bytes();
+           bnzc.bytes() + tasks.bytes() + items.bytes() + xitems.bytes() + heavy.bytes() + emit.bytes() +
+           cache.bytes();
   }
 };
 
@@ -334,6 +336,7 @@ PlanCtx plan_ctx(const bbtc_plan* pl, uint64_t* per_task, uint64_t* total) {
   c.g.acol = pl->acol.ptr;
   c.tasks = pl->tasks.ptr;
   c.ntasks = (int64_t)pl->h_tasks.size();
+  c.items = pl->opt.mode == BBTC_MODE_PERSISTENT && !pl->streamed ? pl->xitems.ptr : pl->items.ptr;
   c.per_task = per_task;
   c.total = total;
   c.wave_min = eff_wave_min(pl->opt);
@@ -400,6 +403,7 @@ void compose_tasks(bbtc_plan* pl) {
   const double target = est_sum / (double)std::max<int64_t>(1, (int64_t)pl->blocks_per_cu * pl->ncu * kItemsPerBlock);
   pl->h_nitem.assign(all.size(), 0);
   pl->h_nper.assign(all.size(), 0);
+  pl->h_nhub.assign(all.size(), 0);
   pl->nitems = 0;
   for (int32_t q : pl->h_work) {
     const bbtc_task& t = pl->h_tasks[q];
@@ -407,6 +411,7 @@ void compose_tasks(bbtc_plan* pl) {
     uint32_t c = 0;
     for (int64_t r = pl->h_hstart[cid]; r < pl->h_hstart[cid + 1]; ++r)
       c += (pl->h_heavy[r].cnt + kHubChunk - 1) / kHubChunk;
+    pl->h_nhub[q] = c;
     const uint32_t cols = (uint32_t)pl->h_nzc[cid];
     const double per_col = cols ? t.est / (double)cols : 0.0;
     uint32_t nper = step;
@@ -457,7 +462,6 @@ void compose_plan_order(bbtc_plan* pl) {
 bbtc_status compose_queues(bbtc_plan* pl) {
   const int X = kMaxQueues;
   const int64_t p = pl->p;
-  const size_t ni = pl->nitems;
   double total = 0;
   for (int32_t q : pl->h_work) total += pl->h_tasks[q].est;
   const double fair = total / X;
@@ -500,14 +504,6 @@ bbtc_status compose_queues(bbtc_plan* pl) {
     group_cnt[x] += gitems[g];
     load[x] += gload[g];
   }
-  if (pl->xq_cap < std::max<size_t>(ni, 1)) {
-    if (pl->h_xq) (void)hipHostFree(pl->h_xq);
-    pl->h_xq = nullptr;
-    pl->xq_cap = 0;
-    const size_t cap = std::max<size_t>(ni, 1) + ni / 4;
-    HIP_TRY(hipHostMalloc((void**)&pl->h_xq, sizeof(DevItem) * cap, hipHostMallocDefault), "pinned alloc");
-    pl->xq_cap = cap;
-  }
   // queue x: its share of the wide tasks' items, then its groups in order
   std::vector<size_t> at(2 * X, 0);
   size_t pos = 0;
@@ -520,25 +516,37 @@ bbtc_status compose_queues(bbtc_plan* pl) {
     pos += group_cnt[x];
     pl->qlen[x] = (uint32_t)(pos - pl->qbeg[x]);
   }
+  // The queues as runs of task items, queue by queue (so the runs come in
+  // position order); a wide task's share of a queue is one contiguous piece.
+  std::vector<std::vector<ItemRun>> qr(X);
   std::fill(load.begin(), load.end(), 0.0);  // replay the dealing of the wide items
-  std::vector<DevItem> tmp;
+  std::vector<uint32_t> share(X);
   for (int32_t q : wide) {
     const uint32_t c = pl->h_nitem[q];
-    tmp.resize(c);
-    emit_items(pl, q, tmp.data());
     const double w = pl->h_tasks[q].est / (double)c;
+    std::fill(share.begin(), share.end(), 0u);
     for (uint32_t r = 0; r < c; ++r) {
       const int x = least();
-      pl->h_xq[at[x]++] = tmp[r];
+      share[x]++;
       load[x] += w;
     }
+    uint32_t r0 = 0;
+    for (int x = 0; x < X; ++x)
+      if (share[x]) {
+        qr[x].push_back(ItemRun{q, r0, share[x], (uint32_t)at[x]});
+        at[x] += share[x];
+        r0 += share[x];
+      }
   }
   for (int64_t g : gs)
     for (int64_t q = gfirst[g]; q >= 0; q = gnext[q]) {
-      const int x = gq[g] + X;
-      emit_items(pl, (int32_t)q, pl->h_xq + at[x]);
-      at[x] += pl->h_nitem[q];
+      const int x = gq[g];
+      if (pl->h_nitem[q] == 0) continue;
+      qr[x].push_back(ItemRun{(int32_t)q, 0, pl->h_nitem[q], (uint32_t)at[x + X]});
+      at[x + X] += pl->h_nitem[q];
     }
+  pl->h_runs.clear();
+  for (int x = 0; x < X; ++x) pl->h_runs.insert(pl->h_runs.end(), qr[x].begin(), qr[x].end());
   return BBTC_OK;
 }
 
@@ -1097,21 +1105,53 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   HIP_TRY(pl->cursor.ensure(kMaxQueues), "alloc");
   {  // through the pinned stage; the final synchronisation below covers these copies
     const size_t wa = sizeof(uint64_t) * (size_t)(nb + 1), wt = sizeof(DevTask) * (size_t)nt;
-    HIP_TRY(pl->stage.ensure(wa + wt), "pinned alloc");
-    std::memcpy(pl->stage.ptr, acp.data(), wa);
-    std::memcpy(pl->stage.ptr + wa, pl->h_dtasks.data(), wt);
-    HIP_TRY(hipMemcpyAsync(pl->acp.ptr, pl->stage.ptr, wa, hipMemcpyHostToDevice, s), "H2D");
-    HIP_TRY(hipMemcpyAsync(pl->tasks.ptr, pl->stage.ptr + wa, wt, hipMemcpyHostToDevice, s), "H2D");
+    // persistent launches: the work items are written on the device from
+    // runs of task items (a few per task) instead of being uploaded
+    const size_t nr = queued ? pl->h_runs.size() : 0, nh = queued ? pl->h_heavy.size() : 0;
+    const size_t o_runs = 0, o_ti = align16(o_runs + sizeof(ItemRun) * nr),
+                 o_hs = align16(o_ti + sizeof(TaskItems) * (size_t)nt),
+                 o_hr = align16(o_hs + sizeof(uint32_t) * (size_t)(nb + 1)),
+                 o_hc = align16(o_hr + sizeof(HeavyCol) * nh), we = align16(o_hc + sizeof(uint32_t) * nh);
+    const size_t e0 = align16(wa + wt);
+    HIP_TRY(pl->stage.ensure(e0 + (queued ? we : 0)), "pinned alloc");
+    char* st = pl->stage.ptr;
+    std::memcpy(st, acp.data(), wa);
+    std::memcpy(st + wa, pl->h_dtasks.data(), wt);
+    HIP_TRY(hipMemcpyAsync(pl->acp.ptr, st, wa, hipMemcpyHostToDevice, s), "H2D");
+    HIP_TRY(hipMemcpyAsync(pl->tasks.ptr, st + wa, wt, hipMemcpyHostToDevice, s), "H2D");
+    if (queued && pl->nitems) {
+      char* e = st + e0;
+      std::memcpy(e + o_runs, pl->h_runs.data(), sizeof(ItemRun) * nr);
+      TaskItems* ti = (TaskItems*)(e + o_ti);
+      for (int64_t q = 0; q < nt; ++q) {
+        const bbtc_task& t = pl->h_tasks[q];
+        const int64_t cid = col_block_id(t.i, t.j);
+        ti[q] = TaskItems{pl->h_nhub[q], pl->h_nper[q], (uint32_t)pl->h_nzc[cid], (uint32_t)cid};
+      }
+      uint32_t* hs = (uint32_t*)(e + o_hs);
+      for (int64_t b = 0; b <= nb; ++b) hs[b] = (uint32_t)pl->h_hstart[b];
+      std::memcpy(e + o_hr, pl->h_heavy.data(), sizeof(HeavyCol) * nh);
+      uint32_t* hc = (uint32_t*)(e + o_hc);  // first chunk number of each record within its block
+      for (int64_t b = 0; b < nb; ++b) {
+        uint32_t c = 0;
+        for (int64_t r = pl->h_hstart[b]; r < pl->h_hstart[b + 1]; ++r) {
+          hc[r] = c;
+          c += (pl->h_heavy[r].cnt + kHubChunk - 1) / kHubChunk;
+        }
+      }
+      HIP_TRY(pl->emit.ensure(we), "alloc");
+      HIP_TRY(hipMemcpyAsync(pl->emit.ptr, e, we, hipMemcpyHostToDevice, s), "H2D");
+      const char* d = pl->emit.ptr;
+      HIP_TRY(launch_emit_items((const ItemRun*)(d + o_runs), (int32_t)nr, (const TaskItems*)(d + o_ti),
+                                (const uint32_t*)(d + o_hs), (const HeavyCol*)(d + o_hr), (const uint32_t*)(d + o_hc),
+                                kHubChunk, pl->xitems.ptr, (uint32_t)pl->nitems, s),
+              "emit work items");
+    }
   }
-  if (pl->nitems) {
-    if (queued)
-      HIP_TRY(hipMemcpyAsync(pl->xitems.ptr, pl->h_xq, sizeof(DevItem) * pl->nitems, hipMemcpyHostToDevice, s),
-              "H2D");
-    else
-      HIP_TRY(hipMemcpyAsync(pl->items.ptr, pl->h_items.data(), sizeof(DevItem) * pl->h_items.size(),
-                             hipMemcpyHostToDevice, s),
-              "H2D");
-  }
+  if (pl->nitems && !queued)
+    HIP_TRY(hipMemcpyAsync(pl->items.ptr, pl->h_items.data(), sizeof(DevItem) * pl->h_items.size(),
+                           hipMemcpyHostToDevice, s),
+            "H2D");
   HIP_TRY(hipStreamSynchronize(s), "sync");
 
   // ---- statistics (Sec. 4.4 quantities and the byte model) ----
@@ -1149,17 +1189,16 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   return BBTC_OK;
 }
 
-// State of multi-plan launches: device copies of the plan contexts and of the
-// merged work list, filled from pinned host staging.  A ring of slots lets
-// several shared launches be in flight at once (on different streams); a slot
-// is reused only after the launch that last used it has finished.
+// State of multi-plan launches: device copies of the plan contexts (each
+// pointing at its plan's own device work items) and of their item offsets in
+// the combined index space, filled from pinned host staging.  A ring of slots
+// lets several shared launches be in flight at once (on different streams); a
+// slot is reused only after the launch that last used it has finished.
 struct MultiSlot {
-  DevBuf<PlanCtx> ctxs;
-  DevBuf<DevItem> items;
+  DevBuf<char> dev;  // PlanCtx[nplans], then uint32_t plan_off[nplans]
   DevBuf<uint32_t> cursor;
-  PlanCtx* h_ctx = nullptr;
-  DevItem* h_items = nullptr;
-  size_t cap_ctx = 0, cap_items = 0;
+  char* h = nullptr;
+  size_t cap = 0;
   hipEvent_t done = nullptr;
   bool used = false;
 };
@@ -1181,17 +1220,14 @@ bbtc_status count_multi_impl(bbtc_plan* const* plans, int32_t nplans, hipStream_
   if (S.used) HIP_TRY(hipEventSynchronize(S.done), "event sync");  // staging and buffers are free again
   size_t nitems = 0;
   for (int32_t q = 0; q < nplans; ++q) nitems += plans[q]->nitems;
-  if (S.cap_ctx < (size_t)nplans) {
-    if (S.h_ctx) (void)hipHostFree(S.h_ctx);
-    S.h_ctx = nullptr;
-    HIP_TRY(hipHostMalloc((void**)&S.h_ctx, sizeof(PlanCtx) * nplans, hipHostMallocDefault), "pinned alloc");
-    S.cap_ctx = (size_t)nplans;
-  }
-  if (S.cap_items < nitems) {
-    if (S.h_items) (void)hipHostFree(S.h_items);
-    S.h_items = nullptr;
-    HIP_TRY(hipHostMalloc((void**)&S.h_items, sizeof(DevItem) * nitems, hipHostMallocDefault), "pinned alloc");
-    S.cap_items = nitems;
+  if (nitems > 0xFFFFFFFFull) return fail(BBTC_EINVAL, "too many work items for one shared launch");
+  const size_t wc = align16(sizeof(PlanCtx) * (size_t)nplans), wbytes = wc + sizeof(uint32_t) * (size_t)nplans;
+  if (S.cap < wbytes) {
+    if (S.h) (void)hipHostFree(S.h);
+    S.h = nullptr;
+    S.cap = 0;
+    HIP_TRY(hipHostMalloc((void**)&S.h, wbytes, hipHostMallocDefault), "pinned alloc");
+    S.cap = wbytes;
   }
   // heavier plans first (sum of task estimates), each plan's items in its own order
   std::vector<std::pair<double, int32_t>> order;
@@ -1201,28 +1237,27 @@ bbtc_status count_multi_impl(bbtc_plan* const* plans, int32_t nplans, hipStream_
     order.push_back({-w, q});
   }
   std::stable_sort(order.begin(), order.end());
-  size_t at = 0;
-  for (int32_t q = 0; q < nplans; ++q) S.h_ctx[q] = plan_ctx(plans[q], d_per_task[q], d_totals + q);
-  for (const auto& pr : order) {
-    const bbtc_plan* pq = plans[pr.second];
-    const DevItem* src = pq->h_items.size() == pq->nitems ? pq->h_items.data() : pq->h_xq;
-    for (size_t r = 0; r < pq->nitems; ++r) {
-      DevItem it = src[r];
-      it.plan = pr.second;
-      S.h_items[at++] = it;
-    }
+  PlanCtx* hc = (PlanCtx*)S.h;
+  uint32_t* ho = (uint32_t*)(S.h + wc);
+  uint32_t at = 0;
+  for (int32_t r = 0; r < nplans; ++r) {
+    const int32_t q = order[r].second;
+    hc[r] = plan_ctx(plans[q], d_per_task[q], d_totals + q);
+    ho[r] = at;
+    at += (uint32_t)plans[q]->nitems;
   }
-  HIP_TRY(S.ctxs.ensure((size_t)nplans), "alloc");
-  HIP_TRY(S.items.ensure(std::max<size_t>(nitems, 1)), "alloc");
+  HIP_TRY(S.dev.ensure(wbytes), "alloc");
   HIP_TRY(S.cursor.ensure(kMaxQueues), "alloc");
-  HIP_TRY(hipMemcpyAsync(S.ctxs.ptr, S.h_ctx, sizeof(PlanCtx) * nplans, hipMemcpyHostToDevice, s), "H2D");
-  if (nitems) HIP_TRY(hipMemcpyAsync(S.items.ptr, S.h_items, sizeof(DevItem) * nitems, hipMemcpyHostToDevice, s), "H2D");
-  HIP_TRY(launch_reset_multi(S.ctxs.ptr, nplans, S.cursor.ptr, s), "reset");
+  HIP_TRY(hipMemcpyAsync(S.dev.ptr, S.h, wbytes, hipMemcpyHostToDevice, s), "H2D");
+  const PlanCtx* d_ctx = (const PlanCtx*)S.dev.ptr;
+  HIP_TRY(launch_reset_multi(d_ctx, nplans, S.cursor.ptr, s), "reset");
   if (nitems) {
     CountParams cp;
     std::memset(&cp, 0, sizeof(cp));
-    cp.many = S.ctxs.ptr;
-    cp.items = S.items.ptr;
+    cp.many = d_ctx;
+    cp.plan_off = (const uint32_t*)(S.dev.ptr + wc);
+    cp.nplans = nplans;
+    cp.items = nullptr;
     cp.nitems = (uint32_t)nitems;
     cp.cursor = S.cursor.ptr;
     one_queue(cp);

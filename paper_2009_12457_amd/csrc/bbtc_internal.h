@@ -92,6 +92,7 @@ struct PlanCtx {
   int32_t hash_min;  // < 0: never
   uint32_t split;    // columns with longer in-slices come as split items
   int32_t pad;
+  const DevItem* items;  // the plan's work items on the device (multi-plan launches)
 };
 
 // Work queues of a persistent launch: one per XCD (8 on MI355X, each with its
@@ -100,7 +101,11 @@ constexpr int kMaxQueues = 8;
 
 struct CountParams {
   PlanCtx one;            // the plan of a single-plan launch
-  const PlanCtx* many;    // device array, indexed by DevItem::plan (multi-plan launch)
+  // multi-plan launch: many[q] holds the items [plan_off[q], plan_off[q+1])
+  // of the combined index space (nplans entries, non-decreasing from 0)
+  const PlanCtx* many;
+  const uint32_t* plan_off;
+  int32_t nplans;
   const DevItem* items;
   uint32_t nitems;
   uint32_t* cursor;       // kMaxQueues claim counters, zeroed by the reset kernels
@@ -184,6 +189,23 @@ struct BlockBuild {
 hipError_t launch_bot(const BlockBuild& bb, hipStream_t s);
 hipError_t launch_tbot(const BlockBuild& bb, hipStream_t s);
 hipError_t launch_acol(const BlockBuild& bb, hipStream_t s);
+
+// Work-item emission on the device.  A run sends items [r0, r0 + n) of
+// plan-order task `task` to out[dst, dst + n); the runs are sorted by dst,
+// non-empty, and tile [0, nitems).  Item r of a task is its r-th hub chunk
+// while r < nhub (chunks of `chunk` in-neighbours, hub records of block cid
+// in hrec[hstart[cid], hstart[cid+1]) with their first chunk numbers in
+// hcum), else active columns [(r - nhub) * nper, +nper) clipped to cols.
+struct ItemRun {
+  int32_t task;
+  uint32_t r0, n, dst;
+};
+struct TaskItems {
+  uint32_t nhub, nper, cols, cid;
+};
+hipError_t launch_emit_items(const ItemRun* runs, int32_t nruns, const TaskItems* ti, const uint32_t* hstart,
+                             const HeavyCol* hrec, const uint32_t* hcum, uint32_t chunk, DevItem* out,
+                             uint32_t nitems, hipStream_t s);
 
 // ---- launchers (kernels_count.hip) ----
 hipError_t launch_reset(uint64_t* per_task, int64_t ntasks, uint64_t* total, uint32_t* cursor, hipStream_t s);

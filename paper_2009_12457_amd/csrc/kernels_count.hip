@@ -671,7 +671,8 @@ BBTC_COUNT_KERNEL void k_count_items(CountParams cp, uint32_t first) {
 }
 
 // Persistent work-stealing form: every workgroup claims work items from a
-// global cursor until none are left.  MULTI: items of several plans.
+// global cursor until none are left.  MULTI: items of several plans, each
+// read from its own plan's item list.
 template <bool MULTI>
 BBTC_COUNT_KERNEL void k_count_persistent(CountParams cp) {
   __shared__ CountLds s;
@@ -697,8 +698,20 @@ BBTC_COUNT_KERNEL void k_count_persistent(CountParams cp) {
     const uint32_t it = __builtin_amdgcn_readfirstlane(s.item);
     __syncthreads();
     if (it >= cp.nitems) break;
-    const DevItem item = ld_const(cp.items + it);
-    const PlanCtx pc = MULTI ? ld_const(cp.many + item.plan) : cp.one;
+    DevItem item;
+    PlanCtx pc;
+    if constexpr (MULTI) {
+      uint32_t a = 0, b = (uint32_t)cp.nplans - 1;  // the plan whose item range holds it
+      while (a < b) {
+        const uint32_t mid = (a + b + 1) >> 1;
+        if (ld_const(cp.plan_off + mid) <= it) a = mid; else b = mid - 1;
+      }
+      pc = ld_const(cp.many + a);
+      item = ld_const(pc.items + (it - ld_const(cp.plan_off + a)));
+    } else {
+      pc = cp.one;
+      item = ld_const(cp.items + it);
+    }
     int32_t out = 0;
     const uint64_t cnt = run_item(pc, item, s, &out);
     flush(pc, out, cnt, s);

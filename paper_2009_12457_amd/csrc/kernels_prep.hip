@@ -1329,4 +1329,56 @@ hipError_t launch_acol(const BlockBuild& bb, hipStream_t s) {
   return hipGetLastError();
 }
 
+namespace {
+
+// One thread per emitted item.
+__global__ __launch_bounds__(kThreads) void k_emit_items(const ItemRun* __restrict__ runs, int32_t nruns,
+                                                         const TaskItems* __restrict__ ti,
+                                                         const uint32_t* __restrict__ hstart,
+                                                         const HeavyCol* __restrict__ hrec,
+                                                         const uint32_t* __restrict__ hcum, uint32_t chunk,
+                                                         DevItem* __restrict__ out, uint32_t nitems) {
+  const uint32_t pos = blockIdx.x * kThreads + threadIdx.x;
+  if (pos >= nitems) return;
+  int32_t a = 0, b = nruns - 1;  // the last run starting at or before pos
+  while (a < b) {
+    const int32_t mid = (a + b + 1) >> 1;
+    if (runs[mid].dst <= pos) a = mid; else b = mid - 1;
+  }
+  const ItemRun ru = runs[a];
+  const uint32_t r = ru.r0 + (pos - ru.dst);
+  const TaskItems t = ti[ru.task];
+  DevItem it;
+  it.plan = 0;
+  it.task = ru.task;
+  it.pad = 0;
+  if (r < t.nhub) {
+    uint32_t x = hstart[t.cid], y = hstart[t.cid + 1] - 1;  // the record whose chunks hold r
+    while (x < y) {
+      const uint32_t mid = (x + y + 1) >> 1;
+      if (hcum[mid] <= r) x = mid; else y = mid - 1;
+    }
+    const HeavyCol hc = hrec[x];
+    it.lo = (r - hcum[x]) * chunk;
+    it.hi = min(hc.cnt, it.lo + chunk);
+    it.v = hc.v;
+  } else {
+    it.lo = (r - t.nhub) * t.nper;
+    it.hi = min(t.cols, it.lo + t.nper);
+    it.v = -1;
+  }
+  out[pos] = it;
+}
+
+}  // namespace
+
+hipError_t launch_emit_items(const ItemRun* runs, int32_t nruns, const TaskItems* ti, const uint32_t* hstart,
+                             const HeavyCol* hrec, const uint32_t* hcum, uint32_t chunk, DevItem* out,
+                             uint32_t nitems, hipStream_t s) {
+  if (nitems == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_emit_items, dim3((nitems + kThreads - 1) / kThreads), dim3(kThreads), 0, s, runs, nruns, ti,
+                     hstart, hrec, hcum, chunk, out, nitems);
+  return hipGetLastError();
+}
+
 }  // namespace bbtc
