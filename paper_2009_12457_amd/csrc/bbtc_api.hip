@@ -109,10 +109,18 @@ struct bbtc_plan {
   DevBuf<int32_t> in_col;
   DevBuf<uint64_t> keys_a, keys_b;
   DevBuf<uint32_t> hist, partial;
-  DevBuf<int32_t> perm, order, ocol, icol, cuts, chunk0, acol;
-  DevBuf<uint32_t> od, idg, orow, irow, midrows, longrows, hugerows, bot, tbot, ccnt, ccoff, dmax, cursor, err;
-  DevBuf<uint64_t> ccbase, botp, tbotp, acp;
-  DevBuf<unsigned long long> bnnz, bnzr, bnzc;
+  DevBuf<int32_t> perm, order, ocol, icol, cuts, acol;
+  DevBuf<uint32_t> od, idg, orow, irow, midrows, longrows, hugerows, bot, tbot, ccnt, ccoff, cursor, err;
+  DevBuf<uint64_t> acp;
+  // Per-part index tables (uploaded together) and per-block statistics with
+  // their counters (cleared and read back together), in one allocation:
+  // chunk0[p+1] | ccbase, botp, tbotp [p+1] | head[4] = {hub records, dmax x2,
+  // -} | bnnz, bnzr, bnzc [nb]
+  DevBuf<char> blk;
+  int32_t* chunk0 = nullptr;
+  uint64_t *ccbase = nullptr, *botp = nullptr, *tbotp = nullptr;
+  uint32_t* head = nullptr;
+  unsigned long long *bnnz = nullptr, *bnzr = nullptr, *bnzc = nullptr;
   DevBuf<DevTask> tasks;
   DevBuf<DevItem> items;
   DevBuf<DevItem> xitems;          // the same items as per-XCD queues (persistent launches)
@@ -206,24 +214,22 @@ struct bbtc_plan {
     }
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     in_rowptr.release(); in_col.release(); keys_a.release(); keys_b.release(); hist.release(); partial.release();
-    perm.release(); order.release(); ocol.release(); icol.release(); cuts.release(); chunk0.release();
+    perm.release(); order.release(); ocol.release(); icol.release(); cuts.release(); blk.release();
     acol.release(); od.release(); idg.release(); orow.release(); irow.release(); midrows.release();
     longrows.release();
     hugerows.release();
-    bot.release(); tbot.release(); ccnt.release(); ccoff.release(); dmax.release(); cursor.release();
-    err.release(); ccbase.release(); botp.release(); tbotp.release(); acp.release(); bnnz.release();
-    bnzr.release(); bnzc.release(); tasks.release(); items.release(); xitems.release(); heavy.release();
+    bot.release(); tbot.release(); ccnt.release(); ccoff.release(); cursor.release();
+    err.release(); acp.release(); tasks.release(); items.release(); xitems.release(); heavy.release();
     emit.release();
   }
 
   size_t footprint() const {
     return in_rowptr.bytes() + in_col.bytes() + keys_a.bytes() + keys_b.bytes() + hist.bytes() + partial.bytes() +
-           perm.bytes() + order.bytes() + ocol.bytes() + icol.bytes() + cuts.bytes() + chunk0.bytes() +
+           perm.bytes() + order.bytes() + ocol.bytes() + icol.bytes() + cuts.bytes() + blk.bytes() +
            acol.bytes() + od.bytes() + idg.bytes() + orow.bytes() + irow.bytes() + midrows.bytes() + longrows.bytes() +
            hugerows.bytes() + bot.bytes() +
-           tbot.bytes() + ccnt.bytes() + ccoff.bytes() + dmax.bytes() + cursor.bytes() + err.bytes() +
-           ccbase.bytes() + botp.bytes() + tbotp.bytes() + acp.bytes() + bnnz.bytes() + bnzr.bytes() +
-           bnzc.bytes() + tasks.bytes() + items.bytes() + xitems.bytes() + heavy.bytes() + emit.bytes() +
+           tbot.bytes() + ccnt.bytes() + ccoff.bytes() + cursor.bytes() + err.bytes() + acp.bytes() +
+           tasks.bytes() + items.bytes() + xitems.bytes() + heavy.bytes() + emit.bytes() +
            cache.bytes();
   }
 };
@@ -308,7 +314,7 @@ constexpr int kDefaultHashMin = 16;
 constexpr int kDefaultItemRows = 256;
 constexpr uint32_t kHubSplit = 256;   // in-slice length above which a column is split
 constexpr uint32_t kHubChunk = 1024;  // in-neighbours per hub work item
-constexpr int kItemsPerBlock = 32;    // work items per resident workgroup (by estimated work)
+constexpr int kItemsPerBlock = 24;    // work items per resident workgroup (by estimated work)
 
 int eff_wave_min(const bbtc_options& o) { return o.wave_min > 0 ? o.wave_min : kDefaultWaveMin; }
 int eff_hash_min(const bbtc_options& o) {
@@ -326,10 +332,10 @@ PlanCtx plan_ctx(const bbtc_plan* pl, uint64_t* per_task, uint64_t* total) {
   c.g.colI = c.g.colJ = c.g.icolJ = nullptr;
   c.g.botI = c.g.botJ = c.g.tbotJ = nullptr;
   c.g.cuts = pl->cuts.ptr;
-  c.g.botp = pl->botp.ptr;
+  c.g.botp = pl->botp;
   c.g.bot = pl->bot.ptr;
   c.g.ocol = pl->ocol.ptr;
-  c.g.tbotp = pl->tbotp.ptr;
+  c.g.tbotp = pl->tbotp;
   c.g.tbot = pl->tbot.ptr;
   c.g.icol = pl->icol.ptr;
   c.g.acp = pl->acp.ptr;
@@ -603,8 +609,8 @@ bbtc_status stream_setup(bbtc_plan* pl, hipStream_t s) {
   }
   pl->h_botp.assign(p + 1, 0);
   pl->h_tbotp.assign(p + 1, 0);
-  HIP_TRY(hipMemcpyAsync(pl->h_botp.data(), pl->botp.ptr, 8 * (p + 1), hipMemcpyDeviceToHost, s), "D2H");
-  HIP_TRY(hipMemcpyAsync(pl->h_tbotp.data(), pl->tbotp.ptr, 8 * (p + 1), hipMemcpyDeviceToHost, s), "D2H");
+  HIP_TRY(hipMemcpyAsync(pl->h_botp.data(), pl->botp, 8 * (p + 1), hipMemcpyDeviceToHost, s), "D2H");
+  HIP_TRY(hipMemcpyAsync(pl->h_tbotp.data(), pl->tbotp, 8 * (p + 1), hipMemcpyDeviceToHost, s), "D2H");
   HIP_TRY(hipStreamSynchronize(s), "sync");
   size_t slot = 0;
   for (int key = 0; key < 2 * p; ++key) slot = std::max(slot, stripe_bytes(pl, key));
@@ -622,8 +628,7 @@ bbtc_status stream_setup(bbtc_plan* pl, hipStream_t s) {
   pl->keys_a.release(); pl->keys_b.release(); pl->hist.release(); pl->partial.release();
   pl->od.release(); pl->idg.release(); pl->orow.release(); pl->irow.release(); pl->order.release();
   pl->longrows.release(); pl->hugerows.release(); pl->ccnt.release(); pl->ccoff.release();
-  pl->in_rowptr.release(); pl->in_col.release(); pl->heavy.release(); pl->chunk0.release(); pl->ccbase.release();
-  pl->bnnz.release(); pl->bnzr.release(); pl->bnzc.release();
+  pl->in_rowptr.release(); pl->in_col.release(); pl->heavy.release();
   {  // keep only the used part of the active-column array (its capacity was m)
     size_t used = 0;
     for (int64_t v : pl->h_nzc) used += (size_t)v;
@@ -987,64 +992,59 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   botp[p] = bp;
   tbotp[p] = tp;
   pl->ccount = (int64_t)cc;
-  HIP_TRY(pl->chunk0.ensure((size_t)p + 1), "alloc");
-  HIP_TRY(pl->ccbase.ensure((size_t)p + 1), "alloc");
-  HIP_TRY(pl->botp.ensure((size_t)p + 1), "alloc");
-  HIP_TRY(pl->tbotp.ensure((size_t)p + 1), "alloc");
+  const size_t w8 = sizeof(uint64_t) * (size_t)(p + 1), wb = sizeof(unsigned long long) * (size_t)nb;
+  const size_t o_cb = align16(sizeof(int32_t) * (size_t)(p + 1)), o_hd = align16(o_cb + 3 * w8);
+  HIP_TRY(pl->blk.ensure(o_hd + 16 + 3 * wb), "alloc");
+  pl->chunk0 = (int32_t*)pl->blk.ptr;
+  pl->ccbase = (uint64_t*)(pl->blk.ptr + o_cb);
+  pl->botp = pl->ccbase + (p + 1);
+  pl->tbotp = pl->botp + (p + 1);
+  pl->head = (uint32_t*)(pl->blk.ptr + o_hd);
+  pl->bnnz = (unsigned long long*)(pl->blk.ptr + o_hd + 16);
+  pl->bnzr = pl->bnnz + nb;
+  pl->bnzc = pl->bnzr + nb;
   HIP_TRY(pl->bot.ensure((size_t)bp), "alloc block row index");
   HIP_TRY(pl->tbot.ensure((size_t)tp), "alloc block column index");
-  HIP_TRY(pl->bnnz.ensure((size_t)nb), "alloc");
-  HIP_TRY(pl->bnzr.ensure((size_t)nb), "alloc");
-  HIP_TRY(pl->bnzc.ensure((size_t)nb), "alloc");
   HIP_TRY(pl->ccnt.ensure((size_t)cc + 1), "alloc");
   HIP_TRY(pl->ccoff.ensure((size_t)cc + 1), "alloc");
-  HIP_TRY(pl->dmax.ensure(2), "alloc");
   if (pl->partial.cap < scan_partial_entries(cc)) HIP_TRY(pl->partial.ensure(scan_partial_entries(cc) + 4096), "alloc");
-  {  // through the pinned stage (the D2H below is ordered after these copies on s)
-    const size_t w = sizeof(uint64_t) * (p + 1);
-    HIP_TRY(pl->stage.ensure(4 * w), "pinned alloc");
+  {  // the index tables through the pinned stage, one copy (the D2H below is ordered after it on s)
+    HIP_TRY(pl->stage.ensure(o_hd), "pinned alloc");
     char* st = pl->stage.ptr;
     std::memcpy(st, chunk0.data(), sizeof(int32_t) * (p + 1));
-    std::memcpy(st + w, ccbase.data(), w);
-    std::memcpy(st + 2 * w, botp.data(), w);
-    std::memcpy(st + 3 * w, tbotp.data(), w);
-    HIP_TRY(hipMemcpyAsync(pl->chunk0.ptr, st, sizeof(int32_t) * (p + 1), hipMemcpyHostToDevice, s), "H2D");
-    HIP_TRY(hipMemcpyAsync(pl->ccbase.ptr, st + w, w, hipMemcpyHostToDevice, s), "H2D");
-    HIP_TRY(hipMemcpyAsync(pl->botp.ptr, st + 2 * w, w, hipMemcpyHostToDevice, s), "H2D");
-    HIP_TRY(hipMemcpyAsync(pl->tbotp.ptr, st + 3 * w, w, hipMemcpyHostToDevice, s), "H2D");
+    std::memcpy(st + o_cb, ccbase.data(), w8);
+    std::memcpy(st + o_cb + w8, botp.data(), w8);
+    std::memcpy(st + o_cb + 2 * w8, tbotp.data(), w8);
+    HIP_TRY(hipMemcpyAsync(pl->blk.ptr, st, o_hd, hipMemcpyHostToDevice, s), "H2D");
   }
-  HIP_TRY(hipMemsetAsync(pl->bnnz.ptr, 0, sizeof(unsigned long long) * nb, s), "memset");
-  HIP_TRY(hipMemsetAsync(pl->bnzr.ptr, 0, sizeof(unsigned long long) * nb, s), "memset");
-  HIP_TRY(hipMemsetAsync(pl->bnzc.ptr, 0, sizeof(unsigned long long) * nb, s), "memset");
-  HIP_TRY(hipMemsetAsync(pl->dmax.ptr, 0, sizeof(uint32_t) * 2, s), "memset");
+  HIP_TRY(hipMemsetAsync(pl->head, 0, 16 + 3 * wb, s), "memset");  // counters and block statistics
   BlockBuild bb;
   bb.p = p;
   bb.nchunks = (int32_t)nch;
   bb.cuts = pl->cuts.ptr;
-  bb.chunk0 = pl->chunk0.ptr;
-  bb.ccbase = pl->ccbase.ptr;
+  bb.chunk0 = pl->chunk0;
+  bb.ccbase = pl->ccbase;
   bb.orow = pl->orow.ptr;
   bb.ocol = pl->ocol.ptr;
-  bb.botp = pl->botp.ptr;
+  bb.botp = pl->botp;
   bb.bot = pl->bot.ptr;
   bb.irow = pl->irow.ptr;
   bb.icol = pl->icol.ptr;
-  bb.tbotp = pl->tbotp.ptr;
+  bb.tbotp = pl->tbotp;
   bb.tbot = pl->tbot.ptr;
-  bb.bnnz = pl->bnnz.ptr;
-  bb.bnzr = pl->bnzr.ptr;
-  bb.bnzc = pl->bnzc.ptr;
+  bb.bnnz = pl->bnnz;
+  bb.bnzr = pl->bnzr;
+  bb.bnzc = pl->bnzc;
   bb.ccnt = pl->ccnt.ptr;
-  bb.dmax_block = pl->dmax.ptr;
+  bb.dmax_block = pl->head + 1;
   bb.ccoff = pl->ccoff.ptr;
   bb.acol = pl->acol.ptr;
   pl->split = kHubSplit;
   const uint64_t hcap = m / kHubSplit + 1;
   HIP_TRY(pl->heavy.ensure((size_t)hcap), "alloc");
-  HIP_TRY(hipMemsetAsync(pl->err.ptr + 2, 0, 4, s), "memset");
   bb.split = pl->split;
   bb.heavy = pl->heavy.ptr;
-  bb.nheavy = pl->err.ptr + 2;
+  bb.nheavy = pl->head;
   bb.heavy_cap = (uint32_t)hcap;
   // out side on s, in side on side[2], at once
   HIP_TRY(hipEventRecord(pl->ev_fork, s), "event");
@@ -1057,17 +1057,12 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   HIP_TRY(launch_acol(bb, s), "active columns");
   uint32_t hd[2] = {0, 0};
   uint32_t nheavy = 0;
-  {  // block statistics through the pinned stage: [nheavy, dmax x2, pad] then bnnz, bnzr, bnzc
-    const size_t wb = sizeof(unsigned long long) * (size_t)nb;
+  {  // block statistics through the pinned stage, one copy: [nheavy, dmax x2, -] then bnnz, bnzr, bnzc
     HIP_TRY(pl->stage.ensure(16 + 3 * wb), "pinned alloc");
     char* st = pl->stage.ptr;
-    uint32_t* sc = (uint32_t*)st;
+    const uint32_t* sc = (const uint32_t*)st;
     const unsigned long long* sb = (const unsigned long long*)(st + 16);
-    HIP_TRY(hipMemcpyAsync(sc, pl->err.ptr + 2, 4, hipMemcpyDeviceToHost, s), "D2H");
-    HIP_TRY(hipMemcpyAsync(sc + 1, pl->dmax.ptr, sizeof(uint32_t) * 2, hipMemcpyDeviceToHost, s), "D2H");
-    HIP_TRY(hipMemcpyAsync(st + 16, pl->bnnz.ptr, wb, hipMemcpyDeviceToHost, s), "D2H");
-    HIP_TRY(hipMemcpyAsync(st + 16 + wb, pl->bnzr.ptr, wb, hipMemcpyDeviceToHost, s), "D2H");
-    HIP_TRY(hipMemcpyAsync(st + 16 + 2 * wb, pl->bnzc.ptr, wb, hipMemcpyDeviceToHost, s), "D2H");
+    HIP_TRY(hipMemcpyAsync(st, pl->head, 16 + 3 * wb, hipMemcpyDeviceToHost, s), "D2H");
     HIP_TRY(hipStreamSynchronize(s), "sync");
     nheavy = sc[0];
     hd[0] = sc[1];
