@@ -60,6 +60,27 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
   return v;
 }
 
+// Inclusive running maximum over the 64 lanes of a wavefront, by DPP moves:
+// shifts by 1, 2, 4 and 8 lanes within each row of 16, then the last lane of
+// row 0 into row 1 and of row 2 into row 3, then lane 31 into rows 2 and 3
+// (lanes a move does not reach take 0, the identity for unsigned maximum).
+__device__ __forceinline__ uint32_t wave_incl_max_u32(uint32_t v) {
+  uint32_t t;
+  t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);  // row_shr:1
+  v = t > v ? t : v;
+  t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);  // row_shr:2
+  v = t > v ? t : v;
+  t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);  // row_shr:4
+  v = t > v ? t : v;
+  t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);  // row_shr:8
+  v = t > v ? t : v;
+  t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  v = t > v ? t : v;
+  t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  v = t > v ? t : v;
+  return v;
+}
+
 // Exclusive scan of one value per thread over a 256-thread workgroup.
 // `lds` needs 4 slots.  Contains barriers: call from uniform control flow.
 template <typename T>

@@ -72,6 +72,7 @@ struct WaveScratch {        // per wave: one batch of 64 in-neighbours
   uint32_t sa1[4][kWave];   // end of N(G_ik,u)
   uint32_t sex[4][kWave];   // exclusive prefix of the segment counts
   uint32_t scol[4][kWave];  // short columns: the packed column of u
+  uint32_t sown[4][kWave];  // owner marks of a probe round
 };
 
 struct CountLds {
@@ -162,16 +163,6 @@ __device__ __forceinline__ uint32_t owner_of(const uint32_t* off, uint32_t a, ui
   return lo;
 }
 
-// Largest o in [0, 64) with off[o] <= x (off non-decreasing, off[0] <= x):
-// six fixed halving steps, no data-dependent loop.
-__device__ __forceinline__ uint32_t owner64(const uint32_t* off, uint32_t x) {
-  uint32_t lo = 0;
-#pragma unroll
-  for (uint32_t step = kWave / 2; step > 0; step >>= 1)
-    if (off[lo + step] <= x) lo += step;
-  return lo;
-}
-
 // How a stage of N(G_jk,v) is held in a buffer of nw words (a power of
 // two): 0 sorted copy, 1 bitmap over V_k, 2 open-addressing hash at load at
 // most 1/2.
@@ -242,6 +233,11 @@ __device__ __forceinline__ uint32_t seg_count_w(uint32_t a0, uint32_t a1) {
 __device__ __forceinline__ uint32_t load_seg_raw(const int32_t* __restrict__ col, uint32_t a0, uint32_t a1,
                                                  uint32_t q, uint32_t w[kSegW]) {
   const uint32_t s0 = (a0 & ~(kSeg - 1)) + q * kSegW;
+  if (s0 >= a1) {  // not a segment of this list: nothing is read
+#pragma unroll
+    for (uint32_t x = 0; x < kSegW; ++x) w[x] = 0xFFFFFFFFu;
+    return 0u;
+  }
   const int4 v0 = *reinterpret_cast<const int4*>(col + s0);
   int4 v1 = make_int4(-1, -1, -1, -1);
   if (s0 + kSeg < a1) v1 = *reinterpret_cast<const int4*>(col + s0 + kSeg);
@@ -267,9 +263,23 @@ __device__ __forceinline__ void load_seg_w(const int32_t* __restrict__ col, uint
     if (!((vm >> x) & 1u)) w[x] = 0xFFFFFFFFu;
 }
 
-// The probe rounds of one batch: segment q of the batch goes to lane q mod 64;
-// its owner (the in-neighbour whose list holds it) is found by binary search
-// over the batch's exclusive prefix of segment counts.  MODE is the stage
+// The owner of segment qb + lane in a round of a batch (lane l of the batch
+// holds in-neighbour l, its segments [sx, sx + ns) of the batch): every
+// in-neighbour whose segments meet the round marks its first position in it
+// with (round number, l + 1), and the running maximum over the positions is
+// the owner's mark (marks of earlier rounds are smaller; position 0 is always
+// marked).  sown is cleared when the batch counter rnd starts.
+__device__ __forceinline__ uint32_t round_owner(uint32_t* sown, uint32_t sx, uint32_t ns, uint32_t qb, uint32_t rnd,
+                                                uint32_t l) {
+  if (ns && sx < qb + kWave && sx + ns > qb) sown[sx > qb ? sx - qb : 0u] = (rnd << 7) | (l + 1u);
+  wave_sync();
+  const uint32_t o = ((wave_incl_max_u32(sown[l]) & 127u) - 1u) & (kWave - 1);
+  wave_sync();
+  return o;
+}
+
+// The probe rounds of one batch: segment q of the batch goes to lane q mod 64,
+// its owner (the in-neighbour whose list holds it) from round_owner.  MODE is the stage
 // form, fixed for the whole loop: 1 = bitmap over V_k, 2 = hash, 0 = sorted
 // copy; for 0 and 2 entries outside [smin, smax] cannot match and are
 // skipped.  The bitmap tests all eight positions without branches (every
@@ -277,15 +287,16 @@ __device__ __forceinline__ void load_seg_w(const int32_t* __restrict__ col, uint
 // the hits of the list's own positions.
 template <int MODE>
 __device__ __forceinline__ uint32_t probe_rounds(const int32_t* __restrict__ col, uint32_t tot, const uint32_t* sa0,
-                                                 const uint32_t* sa1, const uint32_t* sex, const Stage& st,
+                                                 const uint32_t* sa1, const uint32_t* sex, uint32_t* sown, uint32_t sx,
+                                                 uint32_t ns, uint32_t& rnd, const Stage& st,
                                                  const uint32_t* buf, uint32_t sn, uint32_t smin, uint32_t smax,
                                                  uint32_t kb, uint32_t klast) {
   const uint32_t l = (uint32_t)lane_id();
   uint32_t cnt = 0;
   for (uint32_t qb = 0; qb < tot; qb += kWave) {
+    const uint32_t o = round_owner(sown, sx, ns, qb, ++rnd, l);
     const uint32_t q = qb + l;
     if (q < tot && MODE == 1) {
-      const uint32_t o = owner64(sex, q);
       uint32_t w[kSegW];
       const uint32_t vm = load_seg_raw(col, sa0[o], sa1[o], q - sex[o], w);
       // bit w - kb of the bitmap (kb is a multiple of 32, so the bit within
@@ -303,7 +314,6 @@ __device__ __forceinline__ uint32_t probe_rounds(const int32_t* __restrict__ col
       for (uint32_t t = 0; t < kSegW; ++t) hit |= __builtin_amdgcn_ubfe(wd[t], w[t], 1u) << t;  // offset taken mod 32
       cnt += __popc(hit & vm);
     } else if (q < tot) {
-      const uint32_t o = owner64(sex, q);
       uint32_t w[kSegW];
       load_seg_w(col, sa0[o], sa1[o], q - sex[o], w);
 #pragma unroll
@@ -342,12 +352,15 @@ __device__ __forceinline__ uint32_t probe_rounds(const int32_t* __restrict__ col
 // the segment counts of 64 in-neighbours at a time lets all lanes share the
 // segments, however unequal the lists are.
 __device__ uint64_t probe_flat(const TaskCtx& c, uint32_t i0, uint32_t i1, const Stage& st, const uint32_t* buf,
-                               uint32_t sn, int32_t smin, int32_t smax, uint32_t* sa0, uint32_t* sa1, uint32_t* sex) {
+                               uint32_t sn, int32_t smin, int32_t smax, uint32_t* sa0, uint32_t* sa1, uint32_t* sex,
+                               uint32_t* sown) {
   const int32_t* __restrict__ col = c.coli;
   const int32_t* __restrict__ icol = c.icolj;
   const uint32_t l = (uint32_t)lane_id();
   const uint32_t kb = (uint32_t)c.kb, klast = (uint32_t)(c.ck1 - 1);
   uint64_t cnt = 0;
+  uint32_t rnd = 0;
+  sown[l] = 0;
   for (uint32_t eb = i0; eb < i1; eb += kWave) {
     const uint32_t e = eb + l;
     uint32_t a0 = 0, a1 = 0;
@@ -365,11 +378,14 @@ __device__ uint64_t probe_flat(const TaskCtx& c, uint32_t i0, uint32_t i1, const
     sex[l] = inc - nseg;
     wave_sync();
     if (st.mode == 1)
-      cnt += probe_rounds<1>(col, tot, sa0, sa1, sex, st, buf, sn, (uint32_t)smin, (uint32_t)smax, kb, klast);
+      cnt += probe_rounds<1>(col, tot, sa0, sa1, sex, sown, inc - nseg, nseg, rnd, st, buf, sn, (uint32_t)smin,
+                               (uint32_t)smax, kb, klast);
     else if (st.mode == 2)
-      cnt += probe_rounds<2>(col, tot, sa0, sa1, sex, st, buf, sn, (uint32_t)smin, (uint32_t)smax, kb, klast);
+      cnt += probe_rounds<2>(col, tot, sa0, sa1, sex, sown, inc - nseg, nseg, rnd, st, buf, sn, (uint32_t)smin,
+                               (uint32_t)smax, kb, klast);
     else
-      cnt += probe_rounds<0>(col, tot, sa0, sa1, sex, st, buf, sn, (uint32_t)smin, (uint32_t)smax, kb, klast);
+      cnt += probe_rounds<0>(col, tot, sa0, sa1, sex, sown, inc - nseg, nseg, rnd, st, buf, sn, (uint32_t)smin,
+                               (uint32_t)smax, kb, klast);
     wave_sync();
   }
   return cnt;
@@ -377,7 +393,7 @@ __device__ uint64_t probe_flat(const TaskCtx& c, uint32_t i0, uint32_t i1, const
 
 // One wavefront: in-slice [i0,i1) of v against N(G_jk,v) = ocol[c0..c1).
 __device__ uint64_t wave_col(const TaskCtx& c, uint32_t i0, uint32_t i1, uint32_t c0, uint32_t c1, bool use_hash,
-                             uint32_t* abuf, uint32_t* sa0, uint32_t* sa1, uint32_t* sex) {
+                             uint32_t* abuf, uint32_t* sa0, uint32_t* sa1, uint32_t* sex, uint32_t* sown) {
   const int32_t* __restrict__ col = c.colj;
   const uint32_t l = (uint32_t)lane_id();
   uint64_t cnt = 0;
@@ -386,7 +402,7 @@ __device__ uint64_t wave_col(const TaskCtx& c, uint32_t i0, uint32_t i1, uint32_
     const uint32_t sn = min(st.piece, c1 - s_lo);
     stage_fill(st, abuf, col, s_lo, sn, c.kb, l, kWave);
     wave_sync();
-    cnt += probe_flat(c, i0, i1, st, abuf, sn, col[s_lo], col[s_lo + sn - 1], sa0, sa1, sex);
+    cnt += probe_flat(c, i0, i1, st, abuf, sn, col[s_lo], col[s_lo + sn - 1], sa0, sa1, sex, sown);
     stage_clear(st, abuf, col, s_lo, sn, c.kb, l, kWave);
     wave_sync();
   }
@@ -435,7 +451,10 @@ __device__ uint64_t short_cols(const TaskCtx& c, CountLds& s, uint32_t a0, uint3
   uint32_t* sa1 = s.w.sa1[w];
   uint32_t* sex = s.w.sex[w];
   uint32_t* scol = s.w.scol[w];
+  uint32_t* sown = s.w.sown[w];
   uint64_t cnt = 0;
+  uint32_t rnd = 0;
+  sown[l] = 0;
   for (uint32_t a = a0; a < b0;) {  // uniform across the wavefront
     const uint32_t sbase = s.soff[a];
     uint32_t b = a + 1, hi = b0;  // largest b in [a+1, b0] with soff[b] - sbase <= kABuf
@@ -474,9 +493,9 @@ __device__ uint64_t short_cols(const TaskCtx& c, CountLds& s, uint32_t a0, uint3
       wave_sync();
       uint32_t lc = 0;
       for (uint32_t qb = 0; qb < tot; qb += kWave) {
+        const uint32_t o = round_owner(sown, inc - nseg, nseg, qb, ++rnd, l);
         const uint32_t q = qb + l;
         if (q < tot) {
-          const uint32_t o = owner64(sex, q);
           const uint32_t k2 = scol[o];
           const uint32_t lo = s.soff[k2] - sbase, hi2 = s.soff[k2 + 1] - sbase;
           uint32_t wv[kSegW];
@@ -563,7 +582,7 @@ __device__ uint64_t process_cols(const PlanCtx& cp, const TaskCtx& c, uint32_t l
       uint32_t qc0, qc1, qi0, qi1;
       col_bounds_uniform(c, s.q[h], qc0, qc1, qi0, qi1);
       const bool use_hash = cp.hash_min >= 0 && (qc1 - qc0) >= (uint32_t)cp.hash_min;
-      cnt += wave_col(c, qi0, qi1, qc0, qc1, use_hash, s.abuf[w], s.w.sa0[w], s.w.sa1[w], s.w.sex[w]);
+      cnt += wave_col(c, qi0, qi1, qc0, qc1, use_hash, s.abuf[w], s.w.sa0[w], s.w.sa1[w], s.w.sex[w], s.w.sown[w]);
     }
     if (ns) {
       // this wavefront's run: the columns whose in-slices start in its quarter
@@ -613,7 +632,7 @@ __device__ uint64_t group_col(const PlanCtx& cp, const TaskCtx& c, uint32_t i0, 
     stage_fill(st, buf, col, s_lo, sn, c.kb, threadIdx.x, kThreads);
     __syncthreads();
     cnt += probe_flat(c, w0, w1, st, buf, sn, col[s_lo], col[s_lo + sn - 1], s.w.sa0[w], s.w.sa1[w],
-                      s.w.sex[w]);
+                      s.w.sex[w], s.w.sown[w]);
     __syncthreads();
     stage_clear(st, buf, col, s_lo, sn, c.kb, threadIdx.x, kThreads);
     __syncthreads();
