@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -475,6 +476,7 @@ bbtc_status compose_queues(bbtc_plan* pl) {
   auto least = [&]() { return (int)(std::min_element(load.begin(), load.end()) - load.begin()); };
   std::vector<size_t> wide_cnt(X, 0), group_cnt(X, 0);
   std::vector<int32_t> wide;  // tasks dealt over all queues, plan order
+  std::vector<std::array<uint32_t, kMaxQueues>> wshare;  // their items per queue
   std::vector<int64_t> gfirst((size_t)(p * (p + 1) / 2), -1), gnext(pl->h_tasks.size(), -1);
   std::vector<int64_t> glast(gfirst.size(), -1);
   std::vector<double> gload(gfirst.size(), 0.0);
@@ -483,14 +485,19 @@ bbtc_status compose_queues(bbtc_plan* pl) {
     const bbtc_task& t = pl->h_tasks[q];
     const uint32_t c = pl->h_nitem[q];
     if (t.est > fair / 2 && c > 1) {
-      // each item to the least loaded queue
+      // the items in about 64 equal pieces, each to the least loaded queue
       wide.push_back(q);
       const double w = t.est / (double)c;
-      for (uint32_t r = 0; r < c; ++r) {
+      const uint32_t piece = std::max<uint32_t>(1, c / 64);
+      std::array<uint32_t, kMaxQueues> sh{};
+      for (uint32_t r = 0; r < c; r += piece) {
+        const uint32_t k = std::min(piece, c - r);
         const int x = least();
-        wide_cnt[x]++;
-        load[x] += w;
+        sh[x] += k;
+        wide_cnt[x] += k;
+        load[x] += w * k;
       }
+      wshare.push_back(sh);
     } else {  // chain the task into its (i,k) group, keeping plan order
       const int64_t g = block_id(p, t.i, t.k);
       if (gfirst[g] < 0) gfirst[g] = q; else gnext[glast[g]] = q;
@@ -525,23 +532,14 @@ bbtc_status compose_queues(bbtc_plan* pl) {
   // The queues as runs of task items, queue by queue (so the runs come in
   // position order); a wide task's share of a queue is one contiguous piece.
   std::vector<std::vector<ItemRun>> qr(X);
-  std::fill(load.begin(), load.end(), 0.0);  // replay the dealing of the wide items
-  std::vector<uint32_t> share(X);
-  for (int32_t q : wide) {
-    const uint32_t c = pl->h_nitem[q];
-    const double w = pl->h_tasks[q].est / (double)c;
-    std::fill(share.begin(), share.end(), 0u);
-    for (uint32_t r = 0; r < c; ++r) {
-      const int x = least();
-      share[x]++;
-      load[x] += w;
-    }
+  for (size_t h = 0; h < wide.size(); ++h) {
+    const int32_t q = wide[h];
     uint32_t r0 = 0;
     for (int x = 0; x < X; ++x)
-      if (share[x]) {
-        qr[x].push_back(ItemRun{q, r0, share[x], (uint32_t)at[x]});
-        at[x] += share[x];
-        r0 += share[x];
+      if (wshare[h][x]) {
+        qr[x].push_back(ItemRun{q, r0, wshare[h][x], (uint32_t)at[x]});
+        at[x] += wshare[h][x];
+        r0 += wshare[h][x];
       }
   }
   for (int64_t g : gs)
