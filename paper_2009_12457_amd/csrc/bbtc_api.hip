@@ -438,10 +438,10 @@ void emit_items(const bbtc_plan* pl, int32_t q, DevItem* out) {
   for (int64_t r = pl->h_hstart[cid]; r < pl->h_hstart[cid + 1]; ++r) {
     const HeavyCol& hc = pl->h_heavy[r];
     for (uint32_t lo = 0; lo < hc.cnt; lo += kHubChunk)
-      out[at++] = DevItem{0, q, lo, std::min(hc.cnt, lo + kHubChunk), hc.v, 0};
+      out[at++] = DevItem{q, lo, std::min(hc.cnt, lo + kHubChunk), hc.v};
   }
   const uint32_t cols = (uint32_t)pl->h_nzc[cid], nper = pl->h_nper[q];
-  for (uint32_t lo = 0; lo < cols; lo += nper) out[at++] = DevItem{0, q, lo, std::min(cols, lo + nper), -1, 0};
+  for (uint32_t lo = 0; lo < cols; lo += nper) out[at++] = DevItem{q, lo, std::min(cols, lo + nper), -1};
 }
 
 // The items in plan order, each task's contiguous (the plain launches and the

@@ -21,18 +21,15 @@ struct DevTask {
   int32_t i, j, k, out;
 };
 
-// One unit of persistent work of task `task` of plan `plan` (plan is 0 for
-// single-plan launches):
+// One unit of persistent work of plan-order task `task` of its plan:
 //   v < 0 : entries [lo, hi) of the active-column list of block (i,j);
 //   v >= 0: in-neighbours [lo, hi) (relative to the start of the in-slice)
 //           of one column v of G_ij whose in-slice is longer than the split
 //           threshold; such columns are skipped by column-range items.
 struct DevItem {
-  int32_t plan;
   int32_t task;
   uint32_t lo, hi;
   int32_t v;
-  int32_t pad;
 };
 
 // A column v of block (a,b) whose in-slice from V_a has more than `split`

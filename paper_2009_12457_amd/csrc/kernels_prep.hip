@@ -1349,9 +1349,7 @@ __global__ __launch_bounds__(kThreads) void k_emit_items(const ItemRun* __restri
   const uint32_t r = ru.r0 + (pos - ru.dst);
   const TaskItems t = ti[ru.task];
   DevItem it;
-  it.plan = 0;
   it.task = ru.task;
-  it.pad = 0;
   if (r < t.nhub) {
     uint32_t x = hstart[t.cid], y = hstart[t.cid + 1] - 1;  // the record whose chunks hold r
     while (x < y) {
