@@ -135,6 +135,7 @@ struct bbtc_plan {
   std::vector<int32_t> h_work;     // plan-order indices of WORK tasks
   std::vector<DevItem> h_items;
   PinnedStage stage;
+  PinnedStage cstage;              // the cut vector, read back while the rows are sorted
   std::vector<ItemRun> h_runs;     // the per-XCD queues as runs of task items (sorted by position)
   uint32_t nq = 1, qbeg[kMaxQueues] = {0}, qlen[kMaxQueues] = {0};
   std::vector<HeavyCol> h_heavy;   // hub columns, sorted by (block, column)
@@ -149,6 +150,7 @@ struct bbtc_plan {
   int ncu = 0, blocks_per_cu = 0;
   hipStream_t side[4] = {nullptr, nullptr, nullptr, nullptr};
   hipEvent_t ev_fork = nullptr, ev_join[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev_cuts = nullptr;  // the cut vector has reached the host (cstage)
   // ---- budgeted streaming of the count phase (see stream_setup)
   bool streamed = false;
   int32_t* h_ocol = nullptr;     // pinned host copies of the count-phase arrays
@@ -214,6 +216,7 @@ struct bbtc_plan {
       if (ev_join[q]) (void)hipEventDestroy(ev_join[q]);
     }
     if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_cuts) (void)hipEventDestroy(ev_cuts);
     in_rowptr.release(); in_col.release(); keys_a.release(); keys_b.release(); hist.release(); partial.release();
     perm.release(); order.release(); ocol.release(); icol.release(); cuts.release(); blk.release();
     acol.release(); od.release(); idg.release(); orow.release(); irow.release(); midrows.release();
@@ -840,6 +843,7 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
       HIP_TRY(hipEventCreateWithFlags(&pl->ev_join[q], hipEventDisableTiming), "hipEventCreate");
     }
     HIP_TRY(hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming), "hipEventCreate");
+    HIP_TRY(hipEventCreateWithFlags(&pl->ev_cuts, hipEventDisableTiming), "hipEventCreate");
   }
 
   const size_t rp_bytes = (size_t)(n + 1) * (rp64 ? 8 : 4);
@@ -937,6 +941,12 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   pl->opt.p = p;
   HIP_TRY(pl->cuts.ensure((size_t)p + 1), "alloc cuts");
   HIP_TRY(launch_cuts(pl->orow.ptr, n, p, opt.cut_mode, pl->cuts.ptr, s), "cuts");
+  // the cut vector goes to the host at once: the block tables it sizes are
+  // computed while the rows are sorted
+  HIP_TRY(pl->cstage.ensure(sizeof(int32_t) * (p + 1)), "pinned alloc");
+  HIP_TRY(hipMemcpyAsync(pl->cstage.ptr, pl->cuts.ptr, sizeof(int32_t) * (p + 1), hipMemcpyDeviceToHost, s),
+          "D2H cuts");
+  HIP_TRY(hipEventRecord(pl->ev_cuts, s), "event");
 
   // ---- rows: out-rows sorted on s, in-rows grouped by part on side[2], at once ----
   // acol is not built yet: its m entries serve as the long/huge-row scratch of
@@ -959,15 +969,11 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   HIP_TRY(launch_inrows_group(pl->irow.ptr, pl->icol.ptr, pl->idg.ptr, (const uint32_t*)pl->keys_a.ptr,
                               pl->err.ptr + 5, pl->acol.ptr, pl->cuts.ptr, p, si),
           "group in-rows");
-  HIP_TRY(hipEventRecord(pl->ev_join[2], si), "event");
-  HIP_TRY(hipStreamWaitEvent(s, pl->ev_join[2], 0), "wait");
-  HIP_TRY(pl->stage.ensure(sizeof(int32_t) * (p + 1)), "pinned alloc");
-  HIP_TRY(hipMemcpyAsync(pl->stage.ptr, pl->cuts.ptr, sizeof(int32_t) * (p + 1), hipMemcpyDeviceToHost, s),
-          "D2H cuts");
-  HIP_TRY(hipStreamSynchronize(s), "sync");
-  pl->h_cuts.assign((const int32_t*)pl->stage.ptr, (const int32_t*)pl->stage.ptr + p + 1);
+  HIP_TRY(hipEventSynchronize(pl->ev_cuts), "sync");
+  pl->h_cuts.assign((const int32_t*)pl->cstage.ptr, (const int32_t*)pl->cstage.ptr + p + 1);
 
-  // ---- block row index (out side) and active columns (in side) ----
+  // ---- block row index (out side, on s after the out-row sort) and active
+  // columns (in side, on side[2] after the in-row grouping) ----
   const int64_t nb = (int64_t)p * (p + 1) / 2;
   std::vector<int32_t> chunk0((size_t)p + 1);
   std::vector<uint64_t> ccbase((size_t)p + 1), botp((size_t)p + 1), tbotp((size_t)p + 1);
@@ -1006,8 +1012,9 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   HIP_TRY(pl->ccnt.ensure((size_t)cc + 1), "alloc");
   HIP_TRY(pl->ccoff.ensure((size_t)cc + 1), "alloc");
   if (pl->partial.cap < scan_partial_entries(cc)) HIP_TRY(pl->partial.ensure(scan_partial_entries(cc) + 4096), "alloc");
-  {  // the index tables through the pinned stage, one copy (the D2H below is ordered after it on s)
-    HIP_TRY(pl->stage.ensure(o_hd), "pinned alloc");
+  {  // the index tables through the pinned stage, one copy (the D2H below is ordered after it on s;
+     // the stage is sized for that D2H too, so it is not reallocated under this copy)
+    HIP_TRY(pl->stage.ensure(std::max(o_hd, 16 + 3 * wb)), "pinned alloc");
     char* st = pl->stage.ptr;
     std::memcpy(st, chunk0.data(), sizeof(int32_t) * (p + 1));
     std::memcpy(st + o_cb, ccbase.data(), w8);
@@ -1044,7 +1051,7 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   bb.heavy = pl->heavy.ptr;
   bb.nheavy = pl->head;
   bb.heavy_cap = (uint32_t)hcap;
-  // out side on s, in side on side[2], at once
+  // out side on s, in side on side[2] once the tables are there, at once
   HIP_TRY(hipEventRecord(pl->ev_fork, s), "event");
   HIP_TRY(hipStreamWaitEvent(si, pl->ev_fork, 0), "wait");
   HIP_TRY(launch_tbot(bb, si), "block column index");
