@@ -878,7 +878,6 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
 
   // ---- degree order (Sec. 4.1): sort keys (degree, id) ----
   pl->idbits = bits_for((uint64_t)(n - 1));
-  const int kbits = 2 * pl->idbits;
   const uint64_t mmax = (uint64_t)nnz / 2;
   HIP_TRY(pl->keys_a.ensure((size_t)n), "alloc keys");
   HIP_TRY(pl->keys_b.ensure((size_t)n), "alloc keys");
@@ -898,7 +897,9 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   HIP_TRY(hipMemsetAsync(pl->err.ptr, 0, 8 * sizeof(uint32_t), s), "memset");
   uint64_t* sorted = nullptr;
   HIP_TRY(launch_degkey(rowptr, rp64, n, pl->idbits, pl->keys_a.ptr, s), "degkey");
-  HIP_TRY(radix_sort_u64(pl->keys_a.ptr, pl->keys_b.ptr, (uint64_t)n, kbits, pl->hist.ptr, pl->partial.ptr, &sorted, s),
+  // the keys start in id order and the sort is stable: the degree bits alone decide
+  HIP_TRY(radix_sort_u64(pl->keys_a.ptr, pl->keys_b.ptr, (uint64_t)n, pl->idbits, 2 * pl->idbits, pl->hist.ptr,
+                         pl->partial.ptr, &sorted, s),
           "degree sort");
   HIP_TRY(launch_perm(sorted, n, pl->idbits, pl->order.ptr, pl->perm.ptr, s), "perm");
 

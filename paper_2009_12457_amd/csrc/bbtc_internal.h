@@ -125,11 +125,12 @@ hipError_t launch_validate(const void* rowptr, int rp64, const int32_t* colidx, 
                            int symmetric, uint32_t* err, uint32_t* list, uint32_t* nlist, uint32_t* hlist,
                            uint32_t* nhlist, uint32_t* hpref, hipStream_t s);
 hipError_t launch_degkey(const void* rowptr, int rp64, int64_t n, int idbits, uint64_t* keys, hipStream_t s);
-// Sorts keys[0..count) by their low `bits` bits; the result ends in *result
-// (one of a or b).  hist/partial are scratch sized by radix_scratch_*().
+// Stable sort of keys[0..count) by their bits [lo, hi) (LSD, 8 bits a pass);
+// the result ends in *result (one of a or b).  hist/partial are scratch
+// sized by radix_hist_entries() and scan_partial_entries().
 size_t radix_hist_entries(uint64_t count);
 size_t scan_partial_entries(uint64_t count);
-hipError_t radix_sort_u64(uint64_t* a, uint64_t* b, uint64_t count, int bits, uint32_t* hist,
+hipError_t radix_sort_u64(uint64_t* a, uint64_t* b, uint64_t count, int lo, int hi, uint32_t* hist,
                           uint32_t* partial, uint64_t** result, hipStream_t s);
 // out[0..count] = exclusive scan of in[0..count), out[count] = total.
 hipError_t scan_u32(const uint32_t* in, uint32_t* out, uint64_t count, uint32_t* partial, hipStream_t s);

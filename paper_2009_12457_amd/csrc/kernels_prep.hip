@@ -1201,13 +1201,13 @@ hipError_t scan_u32(const uint32_t* in, uint32_t* out, uint64_t count, uint32_t*
   return hipGetLastError();
 }
 
-hipError_t radix_sort_u64(uint64_t* a, uint64_t* b, uint64_t count, int bits, uint32_t* hist, uint32_t* partial,
-                          uint64_t** result, hipStream_t s) {
+hipError_t radix_sort_u64(uint64_t* a, uint64_t* b, uint64_t count, int lo, int hi, uint32_t* hist,
+                          uint32_t* partial, uint64_t** result, hipStream_t s) {
   uint64_t* src = a;
   uint64_t* dst = b;
   if (count > 1) {
     const uint64_t ntiles = (count + kRadixTile - 1) / kRadixTile;
-    for (int shift = 0; shift < bits; shift += 8) {
+    for (int shift = lo; shift < hi; shift += 8) {
       hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)ntiles), dim3(kThreads), 0, s, src, count, shift, hist,
                          (uint32_t)ntiles);
       hipError_t e = scan_u32(hist, hist, 256 * ntiles, partial, s);
