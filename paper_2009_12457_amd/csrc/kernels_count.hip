@@ -12,9 +12,9 @@
 //     workgroup are packed and split into four runs, one per wavefront; a
 //     wavefront copies the sorted lists of a window of its columns side by
 //     side into its LDS stage and flattens the probes of all their
-//     in-neighbours over its 64 lanes (segments of kSegW entries, owners
-//     found by binary search over LDS prefix arrays), each probe a binary
-//     search in its own column's run;
+//     in-neighbours over its 64 lanes (segments of kSegW entries, each
+//     lane's owner from per-round start marks and a DPP running maximum),
+//     each probe a binary search in its own column's run;
 //   * long columns: one 64-lane wavefront per v stages N(G_jk,v) alone and
 //     the lanes share the probes of all in-neighbours u (the same segments,
 //     handed out by a wavefront prefix sum);
@@ -42,30 +42,10 @@ constexpr uint32_t kGroupWords = 4 * kABuf;   // the four wavefront buffers as o
 constexpr int log2i(int x) { return x <= 1 ? 0 : 1 + log2i(x / 2); }
 static_assert((1 << log2i(kABuf)) == kABuf, "stage size must be a power of two");
 
-// Probes per flattened work unit: one 16-byte aligned block of an out-row,
-// read by a single 128-bit load (the blocks of N(G_ik,u) are aligned on the
-// absolute positions of the oriented CSR, whose base is 16-byte aligned).
+// Out-rows are read in 16-byte aligned blocks of kSeg entries, by single
+// 128-bit loads (the blocks of N(G_ik,u) are aligned on the absolute
+// positions of the oriented CSR, whose base is 16-byte aligned).
 constexpr uint32_t kSeg = 4;
-
-// Segments covering the aligned blocks of col[a0, a1).
-__device__ __forceinline__ uint32_t seg_count(uint32_t a0, uint32_t a1) {
-  return a1 > a0 ? (a1 - (a0 & ~(kSeg - 1)) + kSeg - 1) / kSeg : 0u;
-}
-
-// Segment q of col[a0, a1): entries whose position is outside [a0, a1) come
-// back as 0xFFFFFFFF, above every vertex id.
-__device__ __forceinline__ void load_seg(const int32_t* __restrict__ col, uint32_t a0, uint32_t a1, uint32_t q,
-                                         uint32_t w[kSeg]) {
-  const uint32_t s0 = (a0 & ~(kSeg - 1)) + q * kSeg;
-  const int4 v = *reinterpret_cast<const int4*>(col + s0);
-  w[0] = (uint32_t)v.x;
-  w[1] = (uint32_t)v.y;
-  w[2] = (uint32_t)v.z;
-  w[3] = (uint32_t)v.w;
-#pragma unroll
-  for (uint32_t x = 0; x < kSeg; ++x)
-    if (s0 + x < a0 || s0 + x >= a1) w[x] = 0xFFFFFFFFu;
-}
 
 struct WaveScratch {        // per wave: one batch of 64 in-neighbours
   uint32_t sa0[4][kWave];   // start of N(G_ik,u)
@@ -228,19 +208,19 @@ __device__ __forceinline__ uint32_t seg_count_w(uint32_t a0, uint32_t a1) {
 }
 
 // Segment q of the list col[a0, a1) as read, entries outside the list
-// included (neighbouring rows, or all ones where the second block is not
-// read); returns the mask of the positions that belong to the list.
+// included (neighbouring rows); returns the mask of the positions that belong
+// to the list.  Both 16-byte blocks are always read, without branches: the
+// second block is the first one again when the list ends inside the first,
+// and a q past the list (which the owner search never yields) reads the
+// list's first block under an empty mask.
 __device__ __forceinline__ uint32_t load_seg_raw(const int32_t* __restrict__ col, uint32_t a0, uint32_t a1,
                                                  uint32_t q, uint32_t w[kSegW]) {
-  const uint32_t s0 = (a0 & ~(kSeg - 1)) + q * kSegW;
-  if (s0 >= a1) {  // not a segment of this list: nothing is read
-#pragma unroll
-    for (uint32_t x = 0; x < kSegW; ++x) w[x] = 0xFFFFFFFFu;
-    return 0u;
-  }
+  const uint32_t s = (a0 & ~(kSeg - 1)) + q * kSegW;
+  const bool in = s < a1;
+  const uint32_t s0 = in ? s : (a0 & ~(kSeg - 1));
+  const uint32_t s1 = s0 + kSeg < a1 ? s0 + kSeg : s0;
   const int4 v0 = *reinterpret_cast<const int4*>(col + s0);
-  int4 v1 = make_int4(-1, -1, -1, -1);
-  if (s0 + kSeg < a1) v1 = *reinterpret_cast<const int4*>(col + s0 + kSeg);
+  const int4 v1 = *reinterpret_cast<const int4*>(col + s1);
   w[0] = (uint32_t)v0.x;
   w[1] = (uint32_t)v0.y;
   w[2] = (uint32_t)v0.z;
@@ -251,7 +231,7 @@ __device__ __forceinline__ uint32_t load_seg_raw(const int32_t* __restrict__ col
   w[7] = (uint32_t)v1.w;
   // [a0 - s0, a1 - s0) within [0, 8)
   const uint32_t lo = a0 > s0 ? a0 - s0 : 0u, hi = min(a1 - s0, kSegW);
-  return ((1u << hi) - 1u) & ~((1u << lo) - 1u);
+  return in ? ((1u << hi) - 1u) & ~((1u << lo) - 1u) : 0u;
 }
 
 // The same with the positions outside the list set to all ones.
