@@ -24,16 +24,22 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
   return (uint32_t)__popcll(mask & __lanemask_lt());
 }
 
-// Inclusive prefix sum over the 64 lanes of a wavefront.
+// Inclusive prefix sum over the 64 lanes of a wavefront, by DPP moves (the
+// pattern of wave_incl_max_u32 below: shifts by 1, 2, 4, 8 within rows of
+// 16, then the row totals of lanes 15/47 and 31 into the rows above; lanes a
+// move does not reach add 0).
 __device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v) {
-  const int l = lane_id();
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    uint32_t t = __shfl_up(v, o, kWave);
-    if (l >= o) v += t;
-  }
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);  // row_shr:1
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);  // row_shr:2
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);  // row_shr:4
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);  // row_shr:8
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
   return v;
 }
+
+// The value of lane 63 (a wave total after an inclusive scan), uniform.
+__device__ __forceinline__ uint32_t last_lane(uint32_t v) { return (uint32_t)__builtin_amdgcn_readlane((int)v, kWave - 1); }
 
 __device__ __forceinline__ unsigned long long wave_incl_scan_u64(unsigned long long v) {
   const int l = lane_id();

@@ -352,7 +352,7 @@ __device__ uint64_t probe_flat(const TaskCtx& c, uint32_t i0, uint32_t i1, const
     }
     const uint32_t nseg = seg_count_w(a0, a1);
     const uint32_t inc = wave_incl_scan_u32(nseg);
-    const uint32_t tot = __shfl(inc, kWave - 1, kWave);
+    const uint32_t tot = last_lane(inc);
     sa0[l] = a0;
     sa1[l] = a1;
     sex[l] = inc - nseg;
@@ -465,7 +465,7 @@ __device__ uint64_t short_cols(const TaskCtx& c, CountLds& s, uint32_t a0, uint3
       }
       const uint32_t nseg = seg_count_w(u0, u1);
       const uint32_t inc = wave_incl_scan_u32(nseg);
-      const uint32_t tot = __shfl(inc, kWave - 1, kWave);
+      const uint32_t tot = last_lane(inc);
       sa0[l] = u0;
       sa1[l] = u1;
       sex[l] = inc - nseg;

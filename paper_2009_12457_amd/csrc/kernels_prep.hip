@@ -379,7 +379,7 @@ __global__ __launch_bounds__(kThreads) void k_degs_lane(const RP* __restrict__ r
     }
     const uint32_t len = mine ? (uint32_t)(e - b) : 0u;
     const uint32_t inc = wave_incl_scan_u32(len);
-    const uint32_t tot = __shfl(inc, kWave - 1, kWave);
+    const uint32_t tot = last_lane(inc);
     F.off[l] = inc - len;
     F.beg[l] = b;
     F.rank[l] = r;
@@ -515,7 +515,7 @@ __global__ __launch_bounds__(kThreads) void k_fill_lane(const RP* __restrict__ r
     }
     const uint32_t len = mine ? (uint32_t)(e - b) : 0u;
     const uint32_t inc = wave_incl_scan_u32(len);
-    const uint32_t tot = __shfl(inc, kWave - 1, kWave);
+    const uint32_t tot = last_lane(inc);
     F.off[l] = inc - len;
     F.beg[l] = b;
     F.rank[l] = r;
