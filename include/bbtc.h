@@ -84,7 +84,8 @@ typedef struct bbtc_csr {
  *   p             blocks per side, 1 <= p <= min(n, 2048); 0 = p from the
  *                 average degree (Sec. 7.2 suggests p near the average degree).
  *   wave_min      a column v of G_ij whose list N(G_jk,v) has at least
- *                 wave_min entries (capped at 4096) is staged alone and
+ *                 wave_min entries (default 32; capped at the 512-word
+ *                 wavefront stage) is staged alone and
  *                 probed by a whole 64-lane wavefront; shorter lists of the
  *                 columns a workgroup holds are staged together, sorted, and
  *                 probed by binary search by all its lanes.
@@ -191,7 +192,7 @@ bbtc_status bbtc_count_multi(bbtc_plan* const* plans, int32_t nplans, void* stre
  * one warm-up) by coordinate descent: first p over {p0/4, p0/2, p0, 2*p0}
  * (p0 = base->p, or the average degree when base->p is 0: Sec. 7.2 of the
  * paper suggests p near the average degree), then wave_min over
- * {64, 256, 1024, 4096}, then hash_min over {-1, 1, 32, 256}.  The other fields of
+ * {32, 64, 256, 1024, 4096}, then hash_min over {-1, 1, 32, 256}.  The other fields of
  * *base are kept.  Every candidate gives identical counts; only time differs.
  * On success *out holds the chosen options and *best_ms (if not NULL) the
  * count time with them.  Synchronises `stream`.

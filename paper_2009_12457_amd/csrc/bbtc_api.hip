@@ -313,12 +313,12 @@ void fill_defaults(bbtc_options* o) {
   o->cut_mode = BBTC_CUT_BALANCED;
 }
 
-constexpr int kDefaultWaveMin = 64;
+constexpr int kDefaultWaveMin = 32;
 constexpr int kDefaultHashMin = 16;
 constexpr int kDefaultItemRows = 256;
 constexpr uint32_t kHubSplit = 256;   // in-slice length above which a column is split
 constexpr uint32_t kHubChunk = 1024;  // in-neighbours per hub work item
-constexpr int kItemsPerBlock = 24;    // work items per resident workgroup (by estimated work)
+constexpr int kItemsPerBlock = 20;    // work items per resident workgroup (by estimated work)
 
 int eff_wave_min(const bbtc_options& o) { return o.wave_min > 0 ? o.wave_min : kDefaultWaveMin; }
 int eff_hash_min(const bbtc_options& o) {
@@ -1461,7 +1461,7 @@ bbtc_status bbtc_autotune(const bbtc_csr* g, const bbtc_options* base, int32_t r
       if (st != BBTC_OK) break;
       if (ms < best) { best = ms; best_opt = o; }
     }
-    for (int32_t wm : {64, 256, 1024, 4096}) {
+    for (int32_t wm : {32, 64, 256, 1024, 4096}) {
       if (st != BBTC_OK) break;
       bbtc_options o = best_opt;
       o.wave_min = wm;
