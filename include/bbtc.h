@@ -181,7 +181,12 @@ bbtc_status bbtc_count(bbtc_plan* plan, void* stream, uint64_t* d_per_task, uint
 /*
  * Several plans counted by shared persistent launches (continuous batching).
  * d_per_task[q] and d_totals + q receive plan q's results, exactly as
- * bbtc_count would.  Plans must not be in use on another stream.
+ * bbtc_count would.  The launch reads every plan's own device buffers (its
+ * work items included), so plans must not be in use on another stream or
+ * re-partitioned until `stream` has completed it.  BBTC_ESTATE for a plan
+ * that is not ready or that streams under a device budget; BBTC_EINVAL for
+ * null arguments or more than 2^32 - 1 work items in total.  Asynchronous,
+ * like bbtc_count.
  */
 bbtc_status bbtc_count_multi(bbtc_plan* const* plans, int32_t nplans, void* stream,
                              uint64_t* const* d_per_task, uint64_t* d_totals);
