@@ -41,13 +41,22 @@ __device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v) {
 // The value of lane 63 (a wave total after an inclusive scan), uniform.
 __device__ __forceinline__ uint32_t last_lane(uint32_t v) { return (uint32_t)__builtin_amdgcn_readlane((int)v, kWave - 1); }
 
+// The 64-bit form: both halves of the source lane's value move by the same
+// DPP pattern, and the sums are 64-bit.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ unsigned long long dpp_move_u64(unsigned long long v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, ROW_MASK, 0xf, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, ROW_MASK, 0xf, false);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
 __device__ __forceinline__ unsigned long long wave_incl_scan_u64(unsigned long long v) {
-  const int l = lane_id();
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    unsigned long long t = __shfl_up(v, o, kWave);
-    if (l >= o) v += t;
-  }
+  v += dpp_move_u64<0x111, 0xf>(v);  // row_shr:1
+  v += dpp_move_u64<0x112, 0xf>(v);  // row_shr:2
+  v += dpp_move_u64<0x114, 0xf>(v);  // row_shr:4
+  v += dpp_move_u64<0x118, 0xf>(v);  // row_shr:8
+  v += dpp_move_u64<0x142, 0xa>(v);  // row_bcast:15
+  v += dpp_move_u64<0x143, 0xc>(v);  // row_bcast:31
   return v;
 }
 
