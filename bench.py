@@ -34,12 +34,18 @@ WORKLOADS = {
                              "under a device budget"),
 }
 PMC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2009_12457_amd", "csrc", "kernels_count.hip")
+# the sources the counting kernel is compiled from: a traffic record applies
+# only to the kernel built from exactly these
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2009_12457_amd", "csrc", f)
+               for f in ("kernels_count.hip", "dev_common.h", "bbtc_internal.h")]
 
 
 def kernel_hash():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def timed(fn, reps, sync):
