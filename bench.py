@@ -3,14 +3,20 @@
 One step = the whole hot path on a device-resident symmetric CSR: degree
 ordering, orientation, the p x p symmetric rectilinear cut, block row index
 and task list (bbtc_partition), then the batched persistent count of every
-task (bbtc_count).  `value` = undirected edges per second of that step.
+task (bbtc_count).  `value` = undirected edges per second of that step on the
+headline workload, R-MAT scale 24 (edge factor 16) with p and the row-mapping
+knobs picked by the autotuner; Erdos-Renyi n = 2^24 (average degree 32) is
+measured the same way beside it.
 
 Also reported, from the same run: the count alone for the batched
 (persistent, work-stealing) kernel and for the unbatched one-launch-per-task
-Intersect and HMap forms; the roofline of the dominant kernel; and the CPU
-oracle timed on the host (a baseline, not the target).
+Intersect and HMap forms; the step with the upload from pinned host memory
+included; the roofline of the dominant kernel; the CPU oracle timed on the
+host on a bounded sample (a baseline, not the target); the smaller
+configurations (Erdos-Renyi G(2000, 0.005) at p=4, R-MAT scale 20 at p=16)
+with the oracle on one thread and on all; and the serving mix.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rmat20]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rmat24]
 """
 import argparse
 import hashlib
@@ -25,14 +31,16 @@ sys.path.insert(0, ROOT)
 METRIC = "edges/s + HBM GB/s fraction, batched vs plain bbTC; p99 request latency"
 HBM_PEAK_GBS = 8000.0
 WORKLOADS = {
-    # name: (generator key, p, description)
-    "rmat20": ("rmat20", 16, "R-MAT scale 20, edge factor 16, (a,b,c,d)=(.57,.19,.19,.05), seed 20; p=16"),
+    # name: (generator key, base p, description)
     "er2000": ("er2000", 4, "Erdos-Renyi G(2000, 0.005), seed 1; p=4"),
-    "rmat24": ("rmat24", 64, "R-MAT scale 24, edge factor 16, (a,b,c,d)=(.57,.19,.19,.05), seed 24; p=64"),
-    "er24": ("er24", 64, "Erdos-Renyi n=2^24, average degree 32, seed 2; p=64"),
-    "rmat27": ("rmat27", 32, "R-MAT scale 27, edge factor 16, (a,b,c,d)=(.57,.19,.19,.05), seed 27; p=32; count "
-                             "under a device budget"),
+    "rmat20": ("rmat20", 16, "R-MAT scale 20, edge factor 16, (a,b,c,d)=(.57,.19,.19,.05), seed 20; p=16"),
+    "rmat24": ("rmat24", 64, "R-MAT scale 24, edge factor 16, (a,b,c,d)=(.57,.19,.19,.05), seed 24; "
+                             "autotuned p from a base of 64"),
+    "er24": ("er24", 64, "Erdos-Renyi n=2^24, average degree 32, seed 2; autotuned p from a base of 64"),
+    "rmat27": ("rmat27", 128, "R-MAT scale 27, edge factor 16, (a,b,c,d)=(.57,.19,.19,.05), seed 27; p=128; "
+                              "under a device budget"),
 }
+AUTOTUNED = ("rmat24", "er24")
 PMC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
 # the sources the counting kernel is compiled from: a traffic record applies
 # only to the kernel built from exactly these
@@ -48,6 +56,10 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
+def pmc_key(workload, opt):
+    return f"{workload}-p{opt.p}-w{opt.wave_min}-h{opt.hash_min}"
+
+
 def timed(fn, reps, sync):
     ts = []
     for _ in range(reps):
@@ -60,10 +72,12 @@ def timed(fn, reps, sync):
 
 
 SERVING = {
-    # kind: (pool graphs, R-MAT scales, ER log10 n range, requests, warm-up requests)
-    "mix": (64, (12, 22), (4.0, 6.0), 400, 50),
-    "quick": (32, (10, 16), (4.0, 5.0), 600, 100),
+    # kind: (pool graphs, R-MAT scales, ER log10 n range, requests, warm-up requests, plain requests)
+    "mix": (128, (12, 22), (4.0, 6.0), 2200, 200, 600),
+    "quick": (32, (10, 16), (4.0, 5.0), 600, 100, 600),
 }
+# request size bands (undirected edges) for the latency breakdown
+BANDS = ((0, 1 << 20), (1 << 20, 10 << 20), (10 << 20, 50 << 20), (50 << 20, 1 << 40))
 
 
 def serving_pool(kind, seed=5):
@@ -75,7 +89,7 @@ def serving_pool(kind, seed=5):
     import numpy as np
 
     import graphgen
-    size, scales, nlog, _, _ = SERVING[kind]
+    size, scales, nlog = SERVING[kind][:3]
     rng = np.random.default_rng(seed)
     specs = []
     for q in range(size):
@@ -114,7 +128,7 @@ def serving_bench(kind):
     t_gen = time.perf_counter()
     pool = serving_pool(kind)
     t_gen = time.perf_counter() - t_gen
-    _, _, _, nreq, warm = SERVING[kind]
+    _, _, _, nreq, warm, nplain = SERVING[kind]
     rng = np.random.default_rng(5)
     gaps = rng.exponential(1.0 / 200.0, size=nreq)
     offs = np.cumsum(gaps) - gaps[0]
@@ -145,18 +159,276 @@ def serving_bench(kind):
     for r, q in zip(res, pick):
         if r.total != alone[int(q)]:
             raise SystemExit(f"served result differs from the alone count for pool graph {int(q)}")
+    bands = {}
+    m_of = [len(t[3]) // 2 for t in trace]
+    for lo, hi in BANDS:
+        sel = [r for q, r in enumerate(res) if q >= warm and lo <= m_of[q] < hi]
+        if sel:
+            lat = np.array([r.latency for r in sel]) * 1e3
+            bands[f"{lo >> 20}M-{hi >> 20}M edges" if hi < (1 << 40) else f">={lo >> 20}M edges"] = {
+                "requests": len(sel), "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99))}
     out["batched"] = dict(serve.latency_summary(res, warm), edges_per_s=edges / span, launches=srv.launches,
                           plans_created=srv.plans_created, plans_released=srv.pool.released,
                           partition_workers=len(srv.workers), stages=serve.stage_summary(res, warm),
-                          wall_s=time.perf_counter() - t0)
+                          by_size=bands, wall_s=time.perf_counter() - t0)
+    # the plain baseline on the first requests of the same trace: at this
+    # arrival rate its queue grows without bound (offered load above its
+    # throughput), so its latency measures the queue, not a service time
     t0 = time.perf_counter()
-    res_p = serve.serve_plain(trace)
-    span_p = max(r.done for r in res_p[warm:]) - min(r.arrival for r in res_p[warm:])
+    ptrace = trace[:nplain]
+    pwarm = min(warm, nplain // 4)
+    res_p = serve.serve_plain(ptrace)
+    span_p = max(r.done for r in res_p[pwarm:]) - min(r.arrival for r in res_p[pwarm:])
     for r, q in zip(res_p, pick):
         if r.total != alone[int(q)]:
             raise SystemExit(f"plain result differs from the alone count for pool graph {int(q)}")
-    out["plain"] = dict(serve.latency_summary(res_p, warm), edges_per_s=edges / span_p,
+    pedges = sum(len(t[3]) // 2 for t in ptrace[pwarm:])
+    offered = pedges / max(ptrace[-1][0] - ptrace[pwarm][0], 1e-9)
+    out["plain"] = dict(serve.latency_summary(res_p, pwarm), edges_per_s=pedges / span_p,
+                        requests_run=len(ptrace), warmup=pwarm, offered_edges_per_s=offered,
+                        regime="overloaded" if offered > pedges / span_p else "within capacity",
                         wall_s=time.perf_counter() - t0)
+    return out
+
+
+def count_event_ms(bb, plan, per, tot, stream, reps):
+    """Median time of the batched count alone, HIP events on its stream."""
+    import numpy as np
+    import torch
+    ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
+    ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
+    bb.bbtc_count(plan, per, tot, stream=stream)
+    for r in range(reps):
+        ev0[r].record(stream)
+        bb.bbtc_count(plan, per, tot, stream=stream)
+        ev1[r].record(stream)
+    torch.cuda.synchronize()
+    return float(np.median([a.elapsed_time(b) for a, b in zip(ev0, ev1)]))
+
+
+def measure(args, name, g, opt, tuned, plain_modes, stream):
+    """Steps (partition + batched count) on a device-resident CSR, the count
+    alone, the partition alone, the step from pinned host memory, and the
+    plain per-task-launch counts.  Returns (record, plan, triangles)."""
+    import numpy as np
+    import torch
+
+    import paper_2009_12457_amd as bb
+    sync = torch.cuda.synchronize
+    n, rp, ci = bb.csr_of(g, "cuda")
+    plan = bb.bbtc_partition(n, rp, ci, options=opt, trusted=True, stream=stream)
+    per, tot = bb.bbtc_count(plan, stream=stream)
+    sync()
+
+    def step():
+        bb.bbtc_partition(n, rp, ci, options=opt, trusted=True, plan=plan, stream=stream)
+        bb.bbtc_count(plan, per, tot, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    sync()
+    elapsed = time.perf_counter() - t0
+    triangles = int(tot.item())
+    st = plan.stats()
+    m = int(st["m"])
+    rec = {"workload": WORKLOADS[name][2], "n": int(st["n"]), "m": m, "p": int(st["p"]),
+           "tasks": int(st["ntasks"]), "work_items": int(st["nitems"]), "triangles": triangles,
+           "lambda": round(st["lambda"], 3), "c": round(st["c"], 3), "wedges": int(st["wedges"]),
+           "ms_per_step": elapsed * 1e3 / args.steps, "edges_per_s": m * args.steps / elapsed,
+           "autotuned": tuned}
+    count_ms = count_event_ms(bb, plan, per, tot, stream, max(args.steps, 5))
+    part_ms = float(np.median(timed(lambda: bb.bbtc_partition(n, rp, ci, options=opt, trusted=True, plan=plan,
+                                                               stream=stream), 5, sync))) * 1e3
+    rec["step_breakdown_ms"] = {"partition": part_ms, "count_batched": count_ms}
+    rec["count_only_edges_per_s"] = m / (count_ms * 1e-3)
+    # the same step from pinned host memory: the upload is part of bbtc_partition
+    hrp = torch.from_numpy(g.rowptr).pin_memory().numpy()
+    hci = torch.from_numpy(g.colidx).pin_memory().numpy()
+    hplan = bb.bbtc_partition(n, hrp, hci, options=opt, trusted=True, stream=stream)
+
+    def host_step():
+        bb.bbtc_partition(n, hrp, hci, options=opt, trusted=True, plan=hplan, stream=stream)
+        bb.bbtc_count(hplan, per, tot, stream=stream)
+
+    host_step()
+    hms = float(np.median(timed(host_step, 3, sync))) * 1e3
+    if int(tot.item()) != triangles:
+        raise SystemExit(f"{name}: host-input count disagrees")
+    hplan.destroy()
+    del hrp, hci
+    rec["copy_included"] = {"ms_per_step": hms, "edges_per_s": m / (hms * 1e-3),
+                            "what": "H2D of the symmetric CSR from pinned host memory + partition + batched count"}
+    rec["bytes_total"] = int(st["bytes_total"])
+    plain = {}
+    for pname, mode in plain_modes:
+        o2 = bb.bbtc_options_default(p=int(st["p"]), mode=mode)
+        pl2 = bb.bbtc_partition(n, rp, ci, options=o2, trusted=True, stream=stream)
+        pt2, tt2 = bb.bbtc_count(pl2, stream=stream)
+        sync()
+        ts = timed(lambda: bb.bbtc_count(pl2, pt2, tt2, stream=stream), 3, sync)
+        if int(tt2.item()) != triangles:
+            raise SystemExit(f"{name} {pname} disagrees: {int(tt2.item())} vs {triangles}")
+        med = float(np.median(ts))
+        plain[pname] = {"count_ms": med * 1e3, "edges_per_s": m / med}
+        pl2.destroy()
+    rec["plain"] = plain
+    if plain:
+        rec["batched_vs_plain"] = {k: v["count_ms"] / count_ms for k, v in plain.items()}
+    del rp, ci
+    return rec, plan, triangles
+
+
+def measure_budgeted(args, name, g, stream):
+    """The device-budget configuration: input in pinned host memory, the
+    partition in pieces within the budget and the count streaming row
+    stripes and blocks from pinned host memory; each step = partition + count
+    (both timed, the count also with HIP events); then the same at a quarter
+    of the plan's full device footprint (the count's cache then holds a small
+    part of the stripes).  Results are checked against the oracle's stored
+    per-task vector (tests/golden/full_size.json) when it is there."""
+    import hashlib
+
+    import numpy as np
+    import torch
+
+    import paper_2009_12457_amd as bb
+    sync = torch.cuda.synchronize
+    t = time.perf_counter()
+    rp = torch.from_numpy(g.rowptr).pin_memory().numpy()
+    ci = torch.from_numpy(g.colidx).pin_memory().numpy()
+    pin_s = time.perf_counter() - t
+    gold = None
+    gpath = os.path.join(ROOT, "tests", "golden", "full_size.json")
+    if os.path.exists(gpath):
+        gold = json.load(open(gpath)).get(name)
+    runs = {}
+    budgets = [("budget", int(args.device_budget_gb * (1 << 30)))]
+    for label, budget in budgets:
+        opt = bb.bbtc_options_default(p=args.p or WORKLOADS[name][1], device_budget_bytes=budget)
+        t = time.perf_counter()
+        plan = bb.bbtc_partition(g.n, rp, ci, options=opt, trusted=True, stream=stream)
+        sync()
+        part_s = time.perf_counter() - t
+        st = plan.stats()
+        per = torch.empty(int(st["ntasks"]), dtype=torch.int64, device="cuda")
+        tot = torch.empty(1, dtype=torch.int64, device="cuda")
+        cms = []
+        for _ in range(max(1, args.steps)):
+            t = time.perf_counter()
+            bb.bbtc_count(plan, per, tot, stream=stream)
+            sync()
+            cms.append((time.perf_counter() - t) * 1e3)
+        st = plan.stats()
+        m = int(st["m"])
+        rec = {"device_budget_bytes": budget, "streamed": int(st["streamed"]), "footprint": int(st["footprint"]),
+               "stripe_slots": int(st["stripe_slots"]), "stripe_bytes": int(st["stripe_bytes"]),
+               "uploads_per_count": int(st["stripe_uploads"]), "partition_s": part_s,
+               "count_ms": float(np.median(cms)), "step_edges_per_s": m / (part_s + float(np.median(cms)) * 1e-3),
+               "count_edges_per_s": m / (float(np.median(cms)) * 1e-3), "triangles": int(tot.item())}
+        if gold and gold.get("p") == int(st["p"]):
+            tasks = plan.tasks()
+            got = np.zeros(len(tasks), np.uint64)
+            base = np.zeros((int(st["p"]),) * 2, np.int64)
+            q = 0
+            for i in range(int(st["p"])):
+                for j in range(i, int(st["p"])):
+                    base[i, j] = q
+                    q += int(st["p"]) - j
+            got[base[tasks["i"], tasks["j"]] + (tasks["k"] - tasks["j"])] = per.cpu().numpy().view(np.uint64)
+            rec["oracle_match"] = (int(tot.item()) == gold["total"] and
+                                   hashlib.sha256(got.astype("<u8").tobytes()).hexdigest() == gold["per_task_sha256"])
+            if not rec["oracle_match"]:
+                raise SystemExit(f"{name}: count differs from the oracle's stored result")
+        runs[label] = rec
+        rec["resident_bytes"] = int(st["resident_bytes"])
+        if label == "budget":
+            budgets.append(("quarter_footprint", int(st["resident_bytes"]) // 4))
+        plan.destroy()
+        torch.cuda.empty_cache()
+    return {"workload": WORKLOADS[name][2], "n": g.n, "m": int(g.m), "pin_s": pin_s, "runs": runs}
+
+
+def options_for(args, name, stream, g):
+    """The options of a workload: the autotuner's pick for the 2^24 graphs
+    (unless switched off or fixed on the command line), else the base p."""
+    import paper_2009_12457_amd as bb
+    _, p, _ = WORKLOADS[name]
+    opt = bb.bbtc_options_default(p=args.p or p, mode=bb.BBTC_MODE_PERSISTENT,
+                                  device_budget_bytes=int(args.device_budget_gb * (1 << 30)))
+    if args.wave_min:
+        opt.wave_min = args.wave_min
+    if args.hash_min:
+        opt.hash_min = args.hash_min
+    tuned = None
+    if args.autotune == "on" or (args.autotune == "auto" and name in AUTOTUNED and not args.p):
+        n, rp, ci = bb.csr_of(g, "cuda")
+        t = time.perf_counter()
+        opt, tuned_ms = bb.bbtc_autotune(n, rp, ci, base=opt, reps=3, trusted=True, stream=stream)
+        tuned = {"p": opt.p, "wave_min": opt.wave_min, "hash_min": opt.hash_min, "count_ms": tuned_ms,
+                 "tuning_s": round(time.perf_counter() - t, 2)}
+        del rp, ci
+    return opt, tuned
+
+
+def cpu_sample(g, m, target_s=15.0):
+    """The oracle's count (Alg. 2 with Alg. 1) timed on a bounded sample of
+    rows: every k-th block of 64 consecutive ranks, so that the sample spreads
+    evenly over the rank range (the work per edge grows with rank), with k
+    set by a short calibration run for about target_s seconds; edges/s =
+    oriented edges of the sampled rows per second.  The canonicalisation and
+    degree order are not timed."""
+    import numpy as np
+
+    import oracle
+    threads = oracle.max_threads()
+    og = oracle.OracleGraph.from_graph(g)
+    orow, _ = og.oriented()
+    n = og.n
+    d = np.diff(orow)
+
+    def run(stride):
+        rows = np.nonzero((np.arange(n, dtype=np.int64) // 64) % stride == 0)[0]
+        t = time.perf_counter()
+        og.total_rows(rows, threads=threads)
+        return time.perf_counter() - t, int(d[rows].sum()), stride
+
+    stride = 1024
+    dt, edges, _ = run(stride)
+    stride = max(1, int(stride * max(dt, 1e-3) / target_s))
+    if stride < 1024:
+        dt, edges, stride = run(stride)
+    rec = {"value": edges / dt, "unit": "edges/s", "cores": threads, "kind": "oracle",
+           "sample": f"Alg. 2 count over every {stride}-th block of 64 consecutive ranks ({edges} of {m} oriented "
+                     f"edges, {100.0 * edges / max(m, 1):.2f}%), {dt:.2f} s on {threads} threads; canonicalisation "
+                     f"and degree order not timed"}
+    del og
+    return rec
+
+
+def cpu_small(name, g, triangles):
+    """The oracle's count phase (Alg. 2) on a whole small graph: median of 5
+    on all host threads, and one thread (median of 3 below a million edges,
+    one run above)."""
+    import numpy as np
+
+    import oracle
+    og = oracle.OracleGraph.from_graph(g)
+    out = {}
+    for label, threads, reps in (("all_threads", oracle.max_threads(), 5),
+                                 ("one_thread", 1, 3 if og.m < 1000000 else 1)):
+        ts = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            tot = og.total(threads=threads)
+            ts.append(time.perf_counter() - t)
+            if tot != triangles:
+                raise SystemExit(f"oracle disagrees on {name}: {tot} vs {triangles}")
+        med = float(np.median(ts))
+        out[label] = {"count_s": med, "edges_per_s": og.m / med, "cores": threads}
     return out
 
 
@@ -165,19 +437,25 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="rmat20", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="rmat24", choices=sorted(WORKLOADS))
+    ap.add_argument("--p", type=int, default=0, help="fix p (no autotuning)")
+    ap.add_argument("--wave-min", type=int, default=0)
+    ap.add_argument("--hash-min", type=int, default=0)
+    ap.add_argument("--no-companion", action="store_true",
+                    help="skip Erdos-Renyi 2^24 beside R-MAT scale 24 (the headline configuration has both)")
+    ap.add_argument("--no-small", action="store_true", help="skip the 2000-vertex and scale-20 configurations")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-task baselines")
     ap.add_argument("--device-budget-gb", type=float, default=0.0,
-                    help="device budget of the count phase (streams row stripes from pinned host memory)")
+                    help="device budget (streams row stripes from pinned host memory)")
     ap.add_argument("--oracle-check", action="store_true",
                     help="also count the whole graph with the CPU oracle (all host threads) and compare totals")
     ap.add_argument("--profile-only", action="store_true", help="only the timed steps (for rocprofv3 runs)")
     ap.add_argument("--autotune", choices=["auto", "on", "off"], default="auto",
-                    help="pick p and the row-mapping knobs with bbtc_autotune (auto: on for the 2^24 workloads)")
+                    help="pick p and the row-mapping knobs with bbtc_autotune (auto: on for the 2^24 workloads "
+                         "unless --p is given)")
     ap.add_argument("--serving", choices=["mix", "quick", "off"], default="mix",
-                    help="serving measurement: mix (64-graph pool of R-MAT scale 12-22 / ER n=1e4-1e6, 400 "
-                         "requests after 50 warm-up), quick (small graphs) or off")
+                    help="serving measurement: mix (R-MAT scale 12-22 / ER n=1e4-1e6 pool) or quick (small graphs)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run 10 plain device-to-device copies of BYTES bytes (counter calibration)")
     args = ap.parse_args()
@@ -202,102 +480,71 @@ def main():
     import graphgen
     import paper_2009_12457_amd as bb
 
-    gname, p, desc = WORKLOADS[args.workload]
-    g = graphgen.workload(gname)
-    n, rp, ci = bb.csr_of(g, "cuda")
     stream = torch.cuda.current_stream()
     sync = torch.cuda.synchronize
-    opt = bb.bbtc_options_default(p=p, mode=bb.BBTC_MODE_PERSISTENT,
-                                  device_budget_bytes=int(args.device_budget_gb * (1 << 30)))
-    tuned = None
-    if args.autotune == "on" or (args.autotune == "auto" and args.workload in ("rmat24", "er24")):
-        t = time.perf_counter()
-        opt, tuned_ms = bb.bbtc_autotune(n, rp, ci, base=opt, reps=3, trusted=True)
-        tuned = {"p": opt.p, "wave_min": opt.wave_min, "hash_min": opt.hash_min, "count_ms": tuned_ms,
-                 "tuning_s": time.perf_counter() - t}
-        p = opt.p
-    plan = bb.bbtc_partition(n, rp, ci, options=opt, trusted=True)
-    per, tot = bb.bbtc_count(plan)
-    sync()
-
-    def step():
-        bb.bbtc_partition(n, rp, ci, options=opt, trusted=True, plan=plan)
-        bb.bbtc_count(plan, per, tot)
-
-    for _ in range(args.warmup):
-        step()
-    sync()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    sync()
-    elapsed = time.perf_counter() - t0
-    triangles = int(tot.item())
-    st = plan.stats()
-    m = int(st["m"])
-    ms_per_step = elapsed * 1e3 / args.steps
-    value = m * args.steps / elapsed
+    name = args.workload
+    t_gen = time.perf_counter()
+    g = graphgen.workload(WORKLOADS[name][0])
+    t_gen = time.perf_counter() - t_gen
+    if name == "rmat27":  # the device-budget configuration
+        if not args.device_budget_gb:
+            args.device_budget_gb = 24.0
+        rec = measure_budgeted(args, name, g, stream)
+        b = rec["runs"]["budget"]
+        print(json.dumps({
+            "metric": METRIC, "value": b["step_edges_per_s"], "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": 0, "ms_per_step": b["partition_s"] * 1e3 + b["count_ms"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+            "config": {"workload": rec["workload"], "n": rec["n"], "m": rec["m"], "p": args.p or WORKLOADS[name][1],
+                       "device_budget_bytes": b["device_budget_bytes"], "parallelism": "single GPU",
+                       "generation_s": round(t_gen, 1)},
+            "budgeted": rec}))
+        return
+    opt, tuned = options_for(args, name, stream, g)
     if args.profile_only:
-        print(json.dumps({"workload": args.workload, "ms_per_step": ms_per_step, "triangles": triangles}))
+        n, rp, ci = bb.csr_of(g, "cuda")
+        plan = bb.bbtc_partition(n, rp, ci, options=opt, trusted=True, stream=stream)
+        per, tot = bb.bbtc_count(plan, stream=stream)
+        for _ in range(args.warmup):
+            bb.bbtc_count(plan, per, tot, stream=stream)
+        sync()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            bb.bbtc_partition(n, rp, ci, options=opt, trusted=True, plan=plan, stream=stream)
+            bb.bbtc_count(plan, per, tot, stream=stream)
+        sync()
+        dt = time.perf_counter() - t0
+        print(json.dumps({"workload": name, "pmc_key": pmc_key(name, opt), "ms_per_step": dt * 1e3 / args.steps,
+                          "count_ms": count_event_ms(bb, plan, per, tot, stream, 5), "triangles": int(tot.item())}))
         return
 
-    # ---- count alone: batched persistent kernel timed with HIP events on its stream
-    reps = max(args.steps, 5)
-    ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
-    ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
-    bb.bbtc_count(plan, per, tot)
-    for r in range(reps):
-        ev0[r].record(stream)
-        bb.bbtc_count(plan, per, tot)
-        ev1[r].record(stream)
-    sync()
-    count_ms = [a.elapsed_time(b) for a, b in zip(ev0, ev1)]
-    count_ms_med = float(np.median(count_ms))
-    part_ms = [float(x) * 1e3 for x in timed(lambda: bb.bbtc_partition(n, rp, ci, options=opt, trusted=True,
-                                                                         plan=plan), 5, sync)]
-
-    # ---- unbatched baselines: one launch per task (Intersect, HMap)
-    plain = {}
-    for name, mode in () if args.no_plain else (("plain_intersect", bb.BBTC_MODE_PLAIN_INTERSECT),
-                                                 ("plain_hmap", bb.BBTC_MODE_PLAIN_HMAP)):
-        o2 = bb.bbtc_options_default(p=p, mode=mode, wave_min=opt.wave_min)
-        pl2 = bb.bbtc_partition(n, rp, ci, options=o2, trusted=True)
-        pt2, tt2 = bb.bbtc_count(pl2)
-        sync()
-        ts = timed(lambda: bb.bbtc_count(pl2, pt2, tt2), 3, sync)
-        if int(tt2.item()) != triangles:
-            raise SystemExit(f"{name} disagrees: {int(tt2.item())} vs {triangles}")
-        plain[name] = {"count_ms": float(np.median(ts)) * 1e3, "edges_per_s": m / float(np.median(ts))}
-        pl2.destroy()
+    plain_modes = () if args.no_plain else (("plain_intersect", bb.BBTC_MODE_PLAIN_INTERSECT),
+                                            ("plain_hmap", bb.BBTC_MODE_PLAIN_HMAP))
+    head, plan, triangles = measure(args, name, g, opt, tuned, plain_modes, stream)
+    st = plan.stats()
+    m = head["m"]
+    count_ms = head["step_breakdown_ms"]["count_batched"]
 
     # ---- roofline of the dominant kernel (the persistent count)
     alg_bytes = int(st["bytes_total"])
-    achieved = alg_bytes / (count_ms_med * 1e-3) / 1e9
+    achieved = alg_bytes / (count_ms * 1e-3) / 1e9
     traffic = None
     if os.path.exists(PMC_FILE):
         try:
-            rec = json.load(open(PMC_FILE)).get(args.workload)
+            rec = json.load(open(PMC_FILE)).get(pmc_key(name, opt))
             if rec and rec.get("kernel_sha") == kernel_hash():
                 traffic = rec["hbm_bytes_per_launch"]
         except Exception:
             traffic = None
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic}
+    lds_rate = {"wedges_per_s": int(st["wedges"]) / (count_ms * 1e-3),
+                "what": "probe volume W (sum over oriented edges (u,v) of d+(v)) per second of the batched count"}
+    plan.destroy()
 
-    # ---- CPU oracle on the host (a baseline, not the target)
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        threads = oracle.max_threads()
-        t = time.perf_counter()
-        og = oracle.OracleGraph.from_graph(g)
-        otot, _, _ = og.tasks(p, og.cuts(p), threads=threads)
-        dt = time.perf_counter() - t
-        if otot != triangles:
-            raise SystemExit(f"oracle disagrees: {otot} vs {triangles}")
-        cpu = {"value": m / dt, "unit": "edges/s", "cores": threads, "kind": "oracle",
-               "sample": f"whole {args.workload} graph once: canonicalise, degree order, orient and per-task count "
-                         f"(p={p}), {dt:.2f} s"}
+        cpu = cpu_sample(g, m)
 
     oracle_check = None
     if args.oracle_check:
@@ -308,38 +555,66 @@ def main():
                         "seconds": round(time.perf_counter() - t, 1), "threads": oracle.max_threads()}
         if int(otot) != triangles:
             raise SystemExit(f"oracle disagrees: {otot} vs {triangles}")
+    del g
+
+    companion = None
+    if name == "rmat24" and not args.no_companion:
+        g2 = graphgen.workload("er24")
+        o2, t2 = options_for(args, "er24", stream, g2)
+        companion, pl2, _ = measure(args, "er24", g2, o2, t2, plain_modes, stream)
+        pl2.destroy()
+        del g2
+        torch.cuda.empty_cache()
+
+    small = None
+    if not args.no_small and name not in ("er2000", "rmat20"):
+        small = {}
+        for sname in ("er2000", "rmat20"):
+            gs = graphgen.workload(sname)
+            os_, _ = options_for(args, sname, stream, gs)
+            rec, pls, tri = measure(args, sname, gs, os_, None, plain_modes, stream)
+            pls.destroy()
+            if not args.no_cpu_baseline:
+                rec["cpu_oracle"] = cpu_small(sname, gs, tri)
+            small[sname] = rec
 
     serving = serving_bench(args.serving) if args.serving != "off" else None
 
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": head["edges_per_s"],
         "unit": "edges/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": desc, "n": int(st["n"]), "m": m, "p": int(st["p"]), "tasks": int(st["ntasks"]),
-                   "work_items": int(st["nitems"]), "triangles": triangles, "lambda": round(st["lambda"], 3),
-                   "c": round(st["c"], 3), "parallelism": "single GPU"},
-        "step_breakdown_ms": {"partition": float(np.median(part_ms)), "count_batched": count_ms_med},
+        "config": {"workload": head["workload"], "n": head["n"], "m": m, "p": head["p"], "tasks": head["tasks"],
+                   "work_items": head["work_items"], "triangles": triangles, "lambda": head["lambda"],
+                   "c": head["c"], "parallelism": "single GPU"},
+        "step_breakdown_ms": head["step_breakdown_ms"],
         "autotuned": tuned,
-        "batched_count_edges_per_s": m / (count_ms_med * 1e-3),
-        "plain": plain,
+        "batched_count_edges_per_s": head["count_only_edges_per_s"],
+        "copy_included": head["copy_included"],
+        "plain": head["plain"],
+        "batched_vs_plain": head.get("batched_vs_plain"),
         "roofline": roofline,
+        "lds_side_rate": lds_rate,
         "cpu_baseline": cpu,
+        "companion": companion,
+        "small_configs": small,
         "serving": serving,
         "oracle_check": oracle_check,
         "streamed": {"device_budget_bytes": int(opt.device_budget_bytes),
                      "footprint": int(st["footprint"]), "stripe_slots": int(st["stripe_slots"]),
                      "stripe_uploads": int(st["stripe_uploads"])} if st["streamed"] else None,
-        "paper_context": "paper Table 4, scale20 R-MAT (different generator/seed): 0.079 s copy-included on "
-                         "2x20-core Xeon + up to 8x V100 = 2.0e8 edges/s; context only",
+        "paper_context": "paper Table 4 (different generator and seed; copy included; 2x20-core Xeon + up to "
+                         "8x V100): scale24 R-MAT 1.154 s = 2.3e8 edges/s, scale20 0.079 s = 2.0e8 edges/s; "
+                         "context only",
     }
     print(json.dumps(out))
 

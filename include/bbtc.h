@@ -71,8 +71,11 @@ typedef struct bbtc_csr {
 
 /* bbtc_options.mode */
 #define BBTC_MODE_PERSISTENT 0      /* one work-stealing launch over all tasks */
-#define BBTC_MODE_PLAIN_INTERSECT 1 /* one launch per task, list intersection */
-#define BBTC_MODE_PLAIN_HMAP 2      /* one launch per task, LDS hash/bitmap */
+#define BBTC_MODE_PLAIN_INTERSECT 1 /* one launch per task, every list probed by
+                                       binary search in a sorted LDS copy */
+#define BBTC_MODE_PLAIN_HMAP 2      /* one launch per task, every list staged
+                                       alone as an LDS bitmap or hash (wave_min
+                                       and hash_min are ignored) */
 
 /* bbtc_options.cut_mode */
 #define BBTC_CUT_BALANCED 0 /* parts of ~m/p oriented entries each */
@@ -82,7 +85,7 @@ typedef struct bbtc_csr {
  * Tuning knobs.  None of them changes any result: every choice counts each
  * triangle exactly once.  Zero selects the library default.
  *   p             blocks per side, 1 <= p <= min(n, 2048); 0 = p from the
- *                 average degree (Sec. 7.2 suggests p near the average degree).
+ *                 average degree (Sec. 7.3 suggests p near the average degree).
  *   wave_min      a column v of G_ij whose list N(G_jk,v) has at least
  *                 wave_min entries (default 32; capped at the 512-word
  *                 wavefront stage) is staged alone and
@@ -105,6 +108,13 @@ typedef struct bbtc_csr {
  *                 needs only its three blocks).  bbtc_partition itself runs
  *                 with the whole graph on the device.  Fewer than three slots
  *                 within the budget: BBTC_EBUDGET.
+ *   bound_min_deg the block row index (Sec. 4.1) stores, for a vertex of
+ *                 undirected degree above bound_min_deg, the position of each
+ *                 block's slice in its out-row and in-row; rows of lower
+ *                 degree (a prefix of the degree order) store nothing and the
+ *                 counting kernels find their slices by scanning the short
+ *                 row.  The stored index then stays small for any p.
+ *                 0 = default (32); -1 = store every row.
  */
 typedef struct bbtc_options {
   int32_t p;
@@ -116,6 +126,7 @@ typedef struct bbtc_options {
   int32_t item_rows;
   int32_t graph;
   int64_t device_budget_bytes;
+  int32_t bound_min_deg;
 } bbtc_options;
 
 /* Task kinds: EMPTY tasks have an empty block and count 0 without work. */
@@ -152,7 +163,8 @@ typedef struct bbtc_stats {
   int64_t streamed;     /* 1: over the device budget, stripes stream from pinned host memory */
   int64_t stripe_slots; /* stripes the device cache holds (streamed plans) */
   int64_t stripe_bytes; /* bytes per stripe slot */
-  int64_t stripe_uploads; /* stripe uploads by the last bbtc_count (streamed plans) */
+  int64_t stripe_uploads; /* stripe and block uploads by the last bbtc_count (streamed plans) */
+  int64_t resident_bytes; /* device bytes of the count phase with every stripe and block resident */
 } bbtc_stats;
 
 typedef struct bbtc_plan bbtc_plan;
@@ -192,12 +204,41 @@ bbtc_status bbtc_count_multi(bbtc_plan* const* plans, int32_t nplans, void* stre
                              uint64_t* const* d_per_task, uint64_t* d_totals);
 
 /*
+ * Hybrid execution (Sec. 5, Alg. 5-7; Sec. 7.8): the GPU and host threads
+ * count the plan's tasks together.  Tasks are in the plan's order
+ * (non-increasing estimate); the GPU counts the tasks before `cutoff` (plan
+ * order index) with the persistent kernel, host threads take tasks one at a
+ * time from the back of the list and never below `cutoff`, and once its
+ * first share is done the GPU claims half of the tasks still between the two
+ * sides at a time until they meet.  Host threads count by list intersection
+ * (Alg. 1) over host copies of the plan's tables, made on the first call
+ * for a plan build (O(m) host memory).  cutoff -1 = |T|/2; cutoff |T| = the
+ * GPU alone.  cpu_threads 0 = the hardware threads minus one.  Results as
+ * bbtc_count, but the call is synchronous: it returns when they are in
+ * d_per_task/d_total (`stream` is synchronised).  Not for streamed plans
+ * (BBTC_ESTATE).  `stats` (may be NULL) reports the split.
+ */
+typedef struct bbtc_hybrid_stats {
+  int64_t gpu_tasks, cpu_tasks;  /* non-empty tasks counted by each side */
+  int64_t gpu_launches;          /* persistent launches of the GPU side */
+  int64_t cutoff;                /* the cut-off used */
+  int64_t split;                 /* the host threads counted tasks [split, |T|) */
+  int32_t cpu_threads;
+  int32_t pad;
+  double cpu_ms;                 /* longest busy time of a host thread */
+  double total_ms;               /* wall time of the call */
+  uint64_t cpu_triangles;        /* triangles counted by the host threads */
+} bbtc_hybrid_stats;
+bbtc_status bbtc_count_hybrid(bbtc_plan* plan, void* stream, uint64_t* d_per_task, uint64_t* d_total,
+                              int32_t cpu_threads, int64_t cutoff, bbtc_hybrid_stats* stats);
+
+/*
  * Autotuner.  Picks p, wave_min and hash_min for this graph by timing the
  * persistent count (HIP events on `stream`, median of `reps` launches after
  * one warm-up) by coordinate descent: first p over {p0/4, p0/2, p0, 2*p0}
- * (p0 = base->p, or the average degree when base->p is 0: Sec. 7.2 of the
+ * (p0 = base->p, or the average degree when base->p is 0: Sec. 7.3 of the
  * paper suggests p near the average degree), then wave_min over
- * {32, 64, 256, 1024, 4096}, then hash_min over {-1, 1, 32, 256}.  The other fields of
+ * {16, 32, 64, 128, 256, 512}, then hash_min over {-1, 1, 32, 256}.  The other fields of
  * *base are kept.  Every candidate gives identical counts; only time differs.
  * On success *out holds the chosen options and *best_ms (if not NULL) the
  * count time with them.  Synchronises `stream`.
@@ -222,6 +263,48 @@ bbtc_status bbtc_plan_copy_perm(const bbtc_plan* plan, int32_t* dst, void* strea
 bbtc_status bbtc_plan_copy_oriented(const bbtc_plan* plan, uint32_t* orow, int32_t* ocol, void* stream);
 
 void bbtc_plan_destroy(bbtc_plan* plan);
+
+/*
+ * Diagnostics: consistency of the block tables the counting kernels index
+ * (Sec. 4.1's blocks in the layout described below), checked on the host
+ * against their definitions from the oriented CSR.
+ *
+ * bbtc_tables: host arrays of one plan.  n vertices, m oriented edges, p
+ * parts, cut vector cuts[p+1]; out-rows orow[n+1]/ocol[m] (ranks above the
+ * row's rank, ascending).  Ranks below rT store no block boundaries; part a
+ * stores the rows max(cuts[a], rT) .. cuts[a+1]-1, p-a+1 positions per
+ * stored row from botp[a] on (entry b-a = first position of the out-row
+ * with a column >= cuts[b], entry p-a = row end).  The in side is
+ * block-major: per block (a,b) in column-major order cid = b(b+1)/2 + a,
+ * acol lists from acp[cid] on the columns v of V_b with an in-neighbour in
+ * V_a, ascending, and active column x's in-neighbours in V_a (in any order)
+ * are icolb[aoff[x] .. aoff[x+1]); the slices lie back to back from 0 to m.
+ * Returns BBTC_OK, or BBTC_EINVAL with the first violation in
+ * bbtc_last_error().  Pure host code: no device is needed.
+ */
+typedef struct bbtc_tables {
+  int64_t n, m;
+  int32_t p, rT;
+  const int32_t* cuts;
+  const uint32_t* orow;
+  const int32_t* ocol;
+  const uint64_t* botp;
+  const uint32_t* bot;
+  const uint64_t* acp;
+  const int32_t* acol;
+  const uint32_t* aoff;
+  const int32_t* icolb;
+} bbtc_tables;
+bbtc_status bbtc_check_tables(const bbtc_tables* tables);
+
+/*
+ * Copies a plan's tables and work items to the host (synchronising `stream`)
+ * and checks them: the tables as bbtc_check_tables, and every work item
+ * within its task's active columns or hub in-slice, the items of each task
+ * covering its columns exactly once.  BBTC_EDEVICE names the first
+ * violation.  O(m + p^2 + items) host work, for tests and debugging.
+ */
+bbtc_status bbtc_plan_verify(const bbtc_plan* plan, void* stream);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* bbtc_last_error(void);

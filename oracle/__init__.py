@@ -8,6 +8,7 @@ this file only marshals numpy arrays.
 Functions follow arXiv 2009.12457:
   * ``total``        -- Alg. 2 (TC-Intersect) over the degree-ordered,
                         oriented graph, with Alg. 1 as the list intersection.
+  * ``total_rows``   -- Alg. 2 over a list of rows (bounded timing samples).
   * ``total_hmap``   -- Alg. 3 (TC-HMap), a second, independent count.
   * ``cuts``         -- the cut rule used for the p x p symmetric rectilinear
                         partition (the paper's partitioner is not described in
@@ -63,6 +64,8 @@ def _load():
         L.or_oriented.argtypes = [vp, P64, P32]
         L.or_total.argtypes = [vp, ctypes.c_int]
         L.or_total.restype = ctypes.c_uint64
+        L.or_total_rows.argtypes = [vp, P64, i64, ctypes.c_int]
+        L.or_total_rows.restype = ctypes.c_uint64
         L.or_total_hmap.argtypes = [vp, ctypes.c_int]
         L.or_total_hmap.restype = ctypes.c_uint64
         L.or_cuts.argtypes = [vp, i32, ctypes.c_int, P32]
@@ -135,6 +138,14 @@ class OracleGraph:
 
     def total(self, threads: int = 0) -> int:
         return int(_load().or_total(self._h, threads or max_threads()))
+
+    def total_rows(self, rows, threads: int = 0) -> int:
+        """Alg. 2 over the listed rows (ranks) only."""
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        r = int(_load().or_total_rows(self._h, _p(rows, ctypes.c_int64), len(rows), threads or max_threads()))
+        if r == (1 << 64) - 1:
+            raise ValueError("oracle: row out of range")
+        return r
 
     def total_hmap(self, threads: int = 0) -> int:
         return int(_load().or_total_hmap(self._h, threads or max_threads()))

@@ -210,6 +210,27 @@ uint64_t or_total(const or_graph* g, int nthreads) {
   return tau;
 }
 
+/* Alg. 2 restricted to the listed rows (ranks) rows[0..nrows): the
+   triangles whose lowest-ranked vertex is listed.  Summed over lists that
+   partition [0, n) it gives the total; used to time the count on a bounded
+   sample of rows.  Returns (uint64_t)-1 if a row is out of range. */
+uint64_t or_total_rows(const or_graph* g, const int64_t* rows, int64_t nrows, int nthreads) {
+  uint64_t tau = 0;
+  const int64_t* R = g->orow;
+  const int32_t* C = g->ocol;
+  for (int64_t q = 0; q < nrows; ++q)
+    if (rows[q] < 0 || rows[q] >= g->n) return (uint64_t)-1;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : tau) num_threads(nthreads)
+  for (int64_t q = 0; q < nrows; ++q) {
+    const int64_t u = rows[q];
+    for (int64_t e = R[u]; e < R[u + 1]; ++e) {
+      int32_t v = C[e];
+      tau += (uint64_t)n_intersect(C + R[u], R[u + 1] - R[u], C + R[v], R[v + 1] - R[v]);
+    }
+  }
+  return tau;
+}
+
 /* Alg. 3: stamp H[v] <- u for v in N(u), then count H[w] = u over w in N(v). */
 uint64_t or_total_hmap(const or_graph* g, int nthreads) {
   uint64_t tau = 0;

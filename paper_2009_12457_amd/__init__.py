@@ -49,7 +49,7 @@ class bbtc_options(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int32), ("cut_mode", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("wave_min", ctypes.c_int32), ("hash_min", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("item_rows", ctypes.c_int32), ("graph", ctypes.c_int32),
-                ("device_budget_bytes", ctypes.c_int64)]
+                ("device_budget_bytes", ctypes.c_int64), ("bound_min_deg", ctypes.c_int32)]
 
 
 class bbtc_task(ctypes.Structure):
@@ -65,7 +65,21 @@ class bbtc_stats(ctypes.Structure):
                 ("bytes_colidx", ctypes.c_int64), ("bytes_rowidx", ctypes.c_int64),
                 ("bytes_total", ctypes.c_int64), ("footprint", ctypes.c_int64), ("partition_ms", ctypes.c_double),
                 ("streamed", ctypes.c_int64), ("stripe_slots", ctypes.c_int64), ("stripe_bytes", ctypes.c_int64),
-                ("stripe_uploads", ctypes.c_int64)]
+                ("stripe_uploads", ctypes.c_int64), ("resident_bytes", ctypes.c_int64)]
+
+
+class bbtc_hybrid_stats(ctypes.Structure):
+    _fields_ = [("gpu_tasks", ctypes.c_int64), ("cpu_tasks", ctypes.c_int64), ("gpu_launches", ctypes.c_int64),
+                ("cutoff", ctypes.c_int64), ("split", ctypes.c_int64), ("cpu_threads", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("cpu_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
+                ("cpu_triangles", ctypes.c_uint64)]
+
+
+class bbtc_tables(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("p", ctypes.c_int32), ("rT", ctypes.c_int32),
+                ("cuts", ctypes.c_void_p), ("orow", ctypes.c_void_p), ("ocol", ctypes.c_void_p),
+                ("botp", ctypes.c_void_p), ("bot", ctypes.c_void_p), ("acp", ctypes.c_void_p),
+                ("acol", ctypes.c_void_p), ("aoff", ctypes.c_void_p), ("icolb", ctypes.c_void_p)]
 
 
 TASK_DTYPE = np.dtype([("i", np.int32), ("j", np.int32), ("k", np.int32), ("kind", np.int32), ("est", np.float64)])
@@ -78,6 +92,8 @@ _SIGS = {
                                         ctypes.POINTER(_P)]),
     "bbtc_count": (ctypes.c_int32, [_P, _P, _P, _P]),
     "bbtc_count_multi": (ctypes.c_int32, [ctypes.POINTER(_P), ctypes.c_int32, _P, ctypes.POINTER(_P), _P]),
+    "bbtc_count_hybrid": (ctypes.c_int32, [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int64,
+                                           ctypes.POINTER(bbtc_hybrid_stats)]),
     "bbtc_autotune": (ctypes.c_int32, [ctypes.POINTER(bbtc_csr), ctypes.POINTER(bbtc_options), ctypes.c_int32, _P,
                                        ctypes.POINTER(bbtc_options), ctypes.POINTER(ctypes.c_double)]),
     "bbtc_plan_tasks": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.POINTER(bbtc_task)),
@@ -90,6 +106,8 @@ _SIGS = {
     "bbtc_plan_copy_perm": (ctypes.c_int32, [_P, _P, _P]),
     "bbtc_plan_copy_oriented": (ctypes.c_int32, [_P, _P, _P, _P]),
     "bbtc_plan_destroy": (None, [_P]),
+    "bbtc_check_tables": (ctypes.c_int32, [ctypes.POINTER(bbtc_tables)]),
+    "bbtc_plan_verify": (ctypes.c_int32, [_P, _P]),
     "bbtc_last_error": (ctypes.c_char_p, []),
 }
 
@@ -237,6 +255,12 @@ class Plan:
         torch.cuda.synchronize()
         return orow.cpu().numpy().view(np.uint32), ocol.cpu().numpy()[:int(st["m"])]
 
+    def verify(self, stream=None):
+        """bbtc_plan_verify: the plan's tables and work items are consistent
+        (raises BbtcError naming the first violation otherwise)."""
+        self._need()
+        _check(_lib.bbtc_plan_verify(self._h, _stream_handle(stream)), "bbtc_plan_verify")
+
     def destroy(self):
         if self._h.value:
             _lib.bbtc_plan_destroy(self._h)
@@ -263,24 +287,43 @@ def _csr_struct(n, rowptr, colidx, trusted):
     return g, (keep_rp, keep_ci)
 
 
+_TUNED = ("p", "wave_min", "hash_min")  # the fields the autotuner chooses
+
+
+def _library_digest() -> str:
+    """Digest of the loaded library file: cached timings are only valid for
+    the kernels they were measured with."""
+    import hashlib
+    h = hashlib.sha256()
+    with open(LIB_PATH, "rb") as f:
+        for chunk in iter(lambda: f.read(1 << 20), b""):
+            h.update(chunk)
+    return h.hexdigest()[:16]
+
+
 def bbtc_autotune(n, rowptr, colidx, base=None, reps: int = 3, stream=None, trusted: bool = False,
                   cache_path: str | None = None):
     """Chosen options (and count ms) for this graph; optionally cached in a
-    JSON file keyed by a signature of the graph (n, nnz, degree moments)."""
+    JSON file keyed by a signature of the graph (n, nnz, degree moments),
+    every field of `base` and the library build.  A cache hit copies only the
+    tuned fields (p, wave_min, hash_min) onto `base`."""
     import json
     key = None
+    base_opts = base if base is not None else bbtc_options_default()
     if cache_path:
-        import torch
         rp = rowptr if isinstance(rowptr, np.ndarray) else rowptr.detach().cpu().numpy()
         deg = np.diff(rp.astype(np.int64))
         key = f"n{int(n)}-nnz{int(rp[-1])}-d2{int((deg * deg).sum())}-dmax{int(deg.max()) if len(deg) else 0}"
-        if base is not None:
-            key += f"-p{base.p}-cut{base.cut_mode}"
+        key += "-" + "-".join(f"{f}{getattr(base_opts, f)}" for f, _ in bbtc_options._fields_)
+        key += "-lib" + _library_digest()
         if os.path.exists(cache_path):
             cache = json.load(open(cache_path))
             if key in cache:
                 rec = cache[key]
-                return bbtc_options_default(**rec["options"]), rec["ms"]
+                out = bbtc_options_default(**{f: getattr(base_opts, f) for f, _ in bbtc_options._fields_})
+                for f in _TUNED:
+                    setattr(out, f, int(rec["options"][f]))
+                return out, rec["ms"]
     g, keep = _csr_struct(n, rowptr, colidx, trusted)
     out = bbtc_options()
     ms = ctypes.c_double()
@@ -326,7 +369,24 @@ def bbtc_count(plan: Plan, per_task=None, total=None, stream=None):
     return per_task, total
 
 
+def bbtc_count_hybrid(plan: Plan, per_task=None, total=None, stream=None, cpu_threads: int = 0, cutoff: int = -1):
+    """GPU and host threads count the plan together (synchronous).  Returns
+    (per_task, total, stats) with per_task/total as bbtc_count's."""
+    import torch
+    nt = plan.ntasks
+    if per_task is None:
+        per_task = torch.empty(max(nt, 1), dtype=torch.int64, device="cuda")
+    if total is None:
+        total = torch.empty(1, dtype=torch.int64, device="cuda")
+    st = bbtc_hybrid_stats()
+    _check(_lib.bbtc_count_hybrid(plan.handle, _stream_handle(stream), ctypes.c_void_p(per_task.data_ptr()),
+                                  ctypes.c_void_p(total.data_ptr()), int(cpu_threads), int(cutoff),
+                                  ctypes.byref(st)), "bbtc_count_hybrid")
+    return per_task, total, {f: getattr(st, f) for f, _ in bbtc_hybrid_stats._fields_ if f != "pad"}
+
+
 def bbtc_count_multi(plans, per_task_list=None, totals=None, stream=None):
+    """Shared persistent launch over several plans (continuous batching)."""
     import torch
     k = len(plans)
     if per_task_list is None:
@@ -338,6 +398,19 @@ def bbtc_count_multi(plans, per_task_list=None, totals=None, stream=None):
     _check(_lib.bbtc_count_multi(arr, k, _stream_handle(stream), outs, ctypes.c_void_p(totals.data_ptr())),
            "bbtc_count_multi")
     return per_task_list, totals
+
+
+def bbtc_check_tables(n, m, p, rT, cuts, orow, ocol, botp, bot, acp, acol, aoff, icolb):
+    """bbtc_check_tables on host numpy arrays (dtypes as the header states)."""
+    want = {"cuts": np.int32, "orow": np.uint32, "ocol": np.int32, "botp": np.uint64, "bot": np.uint32,
+            "acp": np.uint64, "acol": np.int32, "aoff": np.uint32, "icolb": np.int32}
+    loc = dict(cuts=cuts, orow=orow, ocol=ocol, botp=botp, bot=bot, acp=acp, acol=acol, aoff=aoff, icolb=icolb)
+    arrs = {}
+    for k, dt in want.items():
+        a = np.ascontiguousarray(loc[k], dtype=dt)
+        arrs[k] = a if a.size else np.zeros(1, dt)
+    t = bbtc_tables(n=int(n), m=int(m), p=int(p), rT=int(rT), **{k: a.ctypes.data for k, a in arrs.items()})
+    _check(_lib.bbtc_check_tables(ctypes.byref(t)), "bbtc_check_tables")
 
 
 def csr_of(graph, device=None):

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["bbtc_api.hip", "kernels_prep.hip", "kernels_count.hip"]
+SOURCES = ["bbtc_api.hip", "kernels_prep.hip", "kernels_count.hip", "cpu_count.cpp"]
 OUT = os.path.join(HERE, "libbbtc.so")
 ARCH = os.environ.get("BBTC_OFFLOAD_ARCH", "gfx950")
 

@@ -21,6 +21,8 @@
 #include <vector>
 
 #include "bbtc_internal.h"
+#include "cpu_count.h"
+#include "plan_check.h"
 
 using namespace bbtc;
 
@@ -104,6 +106,7 @@ struct bbtc_plan {
   int32_t p = 0;
   bbtc_options opt{};
   int idbits = 1;
+  int64_t rT = 0;  // first rank with stored block boundaries
   bool ready = false;
   // device
   DevBuf<char> in_rowptr;
@@ -111,15 +114,16 @@ struct bbtc_plan {
   DevBuf<uint64_t> keys_a, keys_b;
   DevBuf<uint32_t> hist, partial;
   DevBuf<int32_t> perm, order, ocol, icol, cuts, acol;
-  DevBuf<uint32_t> od, idg, orow, irow, midrows, longrows, hugerows, bot, tbot, ccnt, ccoff, cursor, err;
+  DevBuf<uint32_t> od, idg, orow, irow, midrows, longrows, hugerows, bot, ccnt, ccoff, cursor, err, aoff, asrc;
+  DevBuf<int32_t> icolb;  // the block-major in side (icol is the vertex-major one it is built from)
   DevBuf<uint64_t> acp;
   // Per-part index tables (uploaded together) and per-block statistics with
   // their counters (cleared and read back together), in one allocation:
-  // chunk0[p+1] | ccbase, botp, tbotp [p+1] | head[4] = {hub records, dmax x2,
+  // chunk0[p+1] | ccbase, botp [p+1] | head[4] = {hub records, dmax x2,
   // -} | bnnz, bnzr, bnzc [nb]
   DevBuf<char> blk;
   int32_t* chunk0 = nullptr;
-  uint64_t *ccbase = nullptr, *botp = nullptr, *tbotp = nullptr;
+  uint64_t *ccbase = nullptr, *botp = nullptr;
   uint32_t* head = nullptr;
   unsigned long long *bnnz = nullptr, *bnzr = nullptr, *bnzc = nullptr;
   DevBuf<DevTask> tasks;
@@ -145,6 +149,7 @@ struct bbtc_plan {
   std::vector<uint32_t> h_nitem, h_nper, h_nhub;
   std::vector<int64_t> h_hstart;
   size_t nitems = 0;                // work items of the plan (either layout)
+  double est_sum = 0;               // sum of the task estimates (orders plans in shared launches)
   uint32_t split = 0;              // in-slice length above which a column is a hub
   int64_t ccount = 0;              // number of chunk counters
   int ncu = 0, blocks_per_cu = 0;
@@ -153,41 +158,59 @@ struct bbtc_plan {
   hipEvent_t ev_cuts = nullptr;  // the cut vector has reached the host (cstage)
   // ---- budgeted streaming of the count phase (see stream_setup)
   bool streamed = false;
-  int32_t* h_ocol = nullptr;     // pinned host copies of the count-phase arrays
-  int32_t* h_icol = nullptr;
+  // pinned host copies of the count-phase arrays: out-rows and their stored
+  // boundaries, the block-major in side with its active columns
+  int32_t* h_ocol = nullptr;
   uint32_t* h_bot = nullptr;
-  uint32_t* h_tbot = nullptr;
   uint32_t* h_orow = nullptr;
-  std::vector<uint64_t> h_botp, h_tbotp, ocut, icut;  // part offsets; orow/irow at the cuts
-  DevBuf<char> cache;            // nslots stripes of slot_bytes each
-  size_t slot_bytes = 0;
+  int32_t* h_acol = nullptr;
+  uint32_t* h_aoff = nullptr;
+  int32_t* h_icolb = nullptr;
+  std::vector<uint64_t> h_botp, ocut, h_acp;  // part offsets; orow at the cuts; active-column offsets
+  DevBuf<char> cache;            // out-stripe slots, then the two in-block slots
+  size_t slot_bytes = 0, block_bytes = 0;
   struct Slot {
-    int key = -1;                // 2a: out-stripe of part a, 2a+1: in-stripe of part a
+    int key = -1;                // out-stripe of part `key` (block slots: unused)
     uint64_t last = 0;
     bool used = false;           // a kernel has read it (released is recorded)
     hipEvent_t ready = nullptr, released = nullptr;
   };
-  std::vector<Slot> slots;
+  std::vector<Slot> slots;       // out-stripe slots
+  Slot bslot[2];                 // in-block slots, alternating between block pairs
   uint64_t clock = 0;
-  std::vector<std::pair<int32_t, int32_t>> groups;  // block pairs (i,j), i-major
+  std::vector<std::pair<int32_t, int32_t>> groups;  // block pairs (i,j), i-major, j alternating direction
   std::vector<int64_t> group_first, group_count;    // their ranges of the item list
-  int64_t copies = 0;            // stripe uploads by the last streamed count
+  int64_t copies = 0;            // stripe and block uploads by the last streamed count
+  int64_t resident_bytes = 0;    // count-phase bytes with every stripe and block resident
   void drop_stream() {
     for (auto& s : slots) {
       if (s.ready) (void)hipEventDestroy(s.ready);
       if (s.released) (void)hipEventDestroy(s.released);
     }
     slots.clear();
+    for (auto& s : bslot) {
+      if (s.ready) (void)hipEventDestroy(s.ready);
+      if (s.released) (void)hipEventDestroy(s.released);
+      s = Slot();
+    }
     cache.release();
-    if (h_ocol) (void)hipHostFree(h_ocol);
-    if (h_icol) (void)hipHostFree(h_icol);
-    if (h_bot) (void)hipHostFree(h_bot);
-    if (h_tbot) (void)hipHostFree(h_tbot);
-    if (h_orow) (void)hipHostFree(h_orow);
-    h_ocol = h_icol = nullptr;
-    h_bot = h_tbot = h_orow = nullptr;
+    for (void* h : {(void*)h_ocol, (void*)h_bot, (void*)h_orow, (void*)h_acol, (void*)h_aoff, (void*)h_icolb})
+      if (h) (void)hipHostFree(h);
+    h_ocol = h_acol = h_icolb = nullptr;
+    h_bot = h_orow = h_aoff = nullptr;
     streamed = false;
   }
+  // ---- hybrid execution (see count_hybrid_impl): host copies of the
+  // count-phase tables and the plan-order work items, made on first use
+  struct HybridHost {
+    bool ready = false;
+    std::vector<uint32_t> orow, bot, aoff;
+    std::vector<int32_t> ocol, acol, icolb;
+    std::vector<uint64_t> botp, acp;
+    std::vector<int64_t> istart;  // plan-order item index of each task, |T|+1
+    HostTables t{};
+  } hy;
+  bool plan_order_items = false;  // `items` holds the plan-order layout
   // captured persistent count, valid for the output pointers it was made with
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -222,7 +245,7 @@ struct bbtc_plan {
     acol.release(); od.release(); idg.release(); orow.release(); irow.release(); midrows.release();
     longrows.release();
     hugerows.release();
-    bot.release(); tbot.release(); ccnt.release(); ccoff.release(); cursor.release();
+    bot.release(); ccnt.release(); ccoff.release(); cursor.release(); aoff.release(); asrc.release(); icolb.release();
     err.release(); acp.release(); tasks.release(); items.release(); xitems.release(); heavy.release();
     emit.release();
   }
@@ -232,7 +255,8 @@ struct bbtc_plan {
            perm.bytes() + order.bytes() + ocol.bytes() + icol.bytes() + cuts.bytes() + blk.bytes() +
            acol.bytes() + od.bytes() + idg.bytes() + orow.bytes() + irow.bytes() + midrows.bytes() + longrows.bytes() +
            hugerows.bytes() + bot.bytes() +
-           tbot.bytes() + ccnt.bytes() + ccoff.bytes() + cursor.bytes() + err.bytes() + acp.bytes() +
+           ccnt.bytes() + ccoff.bytes() + cursor.bytes() + err.bytes() + acp.bytes() + aoff.bytes() + asrc.bytes() +
+           icolb.bytes() +
            tasks.bytes() + items.bytes() + xitems.bytes() + heavy.bytes() + emit.bytes() +
            cache.bytes();
   }
@@ -320,7 +344,17 @@ constexpr uint32_t kHubSplit = 256;   // in-slice length above which a column is
 constexpr uint32_t kHubChunk = 1024;  // in-neighbours per hub work item
 constexpr int kItemsPerBlock = 20;    // work items per resident workgroup (by estimated work)
 
-int eff_wave_min(const bbtc_options& o) { return o.wave_min > 0 ? o.wave_min : kDefaultWaveMin; }
+// The plain HMap mode is the paper's per-task HMap throughout: every live
+// column stages its list alone as a bitmap or hash (no shared sorted stage).
+int eff_wave_min(const bbtc_options& o) {
+  if (o.mode == BBTC_MODE_PLAIN_HMAP) return 1;
+  return o.wave_min > 0 ? o.wave_min : kDefaultWaveMin;
+}
+// Rows of undirected degree at most this keep no stored block boundaries.
+constexpr int kDefaultBoundMinDeg = 32;
+int64_t eff_bound_min_deg(const bbtc_options& o) {
+  return o.bound_min_deg == 0 ? kDefaultBoundMinDeg : (int64_t)o.bound_min_deg;
+}
 int eff_hash_min(const bbtc_options& o) {
   if (o.mode == BBTC_MODE_PLAIN_INTERSECT) return -1;
   if (o.mode == BBTC_MODE_PLAIN_HMAP) return 1;
@@ -333,17 +367,21 @@ PlanCtx plan_ctx(const bbtc_plan* pl, uint64_t* per_task, uint64_t* total) {
   c.g.p = pl->p;
   c.g.m = (uint32_t)pl->m;
   c.g.gi = c.g.gj = -1;
+  c.g.rT = (int32_t)pl->rT;
+  c.g.pad = 0;
+  c.g.orow = pl->orow.ptr;
   c.g.colI = c.g.colJ = c.g.icolJ = nullptr;
-  c.g.botI = c.g.botJ = c.g.tbotJ = nullptr;
+  c.g.acolJ = nullptr;
+  c.g.aoffJ = nullptr;
+  c.g.botI = c.g.botJ = nullptr;
   c.g.cuts = pl->cuts.ptr;
   c.g.botp = pl->botp;
   c.g.bot = pl->bot.ptr;
   c.g.ocol = pl->ocol.ptr;
-  c.g.tbotp = pl->tbotp;
-  c.g.tbot = pl->tbot.ptr;
-  c.g.icol = pl->icol.ptr;
   c.g.acp = pl->acp.ptr;
   c.g.acol = pl->acol.ptr;
+  c.g.aoff = pl->aoff.ptr;
+  c.g.icol = pl->icolb.ptr;
   c.tasks = pl->tasks.ptr;
   c.ntasks = (int64_t)pl->h_tasks.size();
   c.items = pl->opt.mode == BBTC_MODE_PERSISTENT && !pl->streamed ? pl->xitems.ptr : pl->items.ptr;
@@ -410,6 +448,7 @@ void compose_tasks(bbtc_plan* pl) {
   const uint32_t step = (uint32_t)(pl->opt.item_rows > 0 ? pl->opt.item_rows : kDefaultItemRows);
   double est_sum = 0;
   for (int32_t q : pl->h_work) est_sum += pl->h_tasks[q].est;
+  pl->est_sum = est_sum;
   const double target = est_sum / (double)std::max<int64_t>(1, (int64_t)pl->blocks_per_cu * pl->ncu * kItemsPerBlock);
   pl->h_nitem.assign(all.size(), 0);
   pl->h_nper.assign(all.size(), 0);
@@ -441,7 +480,7 @@ void emit_items(const bbtc_plan* pl, int32_t q, DevItem* out) {
   for (int64_t r = pl->h_hstart[cid]; r < pl->h_hstart[cid + 1]; ++r) {
     const HeavyCol& hc = pl->h_heavy[r];
     for (uint32_t lo = 0; lo < hc.cnt; lo += kHubChunk)
-      out[at++] = DevItem{q, lo, std::min(hc.cnt, lo + kHubChunk), hc.v};
+      out[at++] = DevItem{q, lo, std::min(hc.cnt, lo + kHubChunk), (int32_t)hc.x};
   }
   const uint32_t cols = (uint32_t)pl->h_nzc[cid], nper = pl->h_nper[q];
   for (uint32_t lo = 0; lo < cols; lo += nper) out[at++] = DevItem{q, lo, std::min(cols, lo + nper), -1};
@@ -451,6 +490,7 @@ void emit_items(const bbtc_plan* pl, int32_t q, DevItem* out) {
 // streamed walk use this layout).
 void compose_plan_order(bbtc_plan* pl) {
   pl->h_items.resize(pl->nitems);
+  pl->plan_order_items = false;  // set once they are uploaded to `items`
   pl->h_hub_first.assign(pl->h_tasks.size(), 0);
   pl->h_hub_count.assign(pl->h_tasks.size(), 0);
   size_t at = 0;
@@ -565,14 +605,15 @@ void one_queue(CountParams& cp) {
 }
 
 // ------------------------------------------------------------ streaming
-// The count phase needs, for the tasks of block pair (i,j), only three row
-// stripes: the out-rows of V_i and of V_j with their block boundaries, and
-// the in-rows of V_j with theirs (plus the active columns of G_ij, which stay
-// resident).  When the plan exceeds the device budget, those arrays move to
-// pinned host memory, the device keeps a cache of equal-size stripe slots
-// within the budget, and bbtc_count walks the block pairs i-major (the out-
-// stripe of V_i stays cached across its pairs), uploading stripes on a side
-// stream, gated by events, one pair ahead of the kernels.
+// The tasks of block pair (i,j) read the out-rows of V_i and V_j with their
+// stored block boundaries (two out-stripes) and the in side of block (i,j)
+// (its active columns, in-slice offsets and in-slices), nothing else.  When
+// the plan exceeds the device budget these arrays live in pinned host
+// memory; the device keeps a cache of out-stripe slots (least recently used
+// goes) and two in-block slots, and bbtc_count walks the block pairs i-major
+// with j alternating direction from one i to the next (the out-stripes of
+// the last pairs are still cached for the next), uploading on a side stream
+// gated by events, ahead of the kernels.
 template <typename T>
 bbtc_status to_pinned(T** dst, const T* src, size_t n, hipStream_t s) {
   HIP_TRY(hipHostMalloc((void**)dst, std::max<size_t>(n, 1) * sizeof(T), hipHostMallocDefault), "pinned alloc");
@@ -584,116 +625,153 @@ size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
 // An out-stripe starts (ocut & 3) words into its slot, so that positions that
 // are multiples of 4 in the whole oriented CSR stay 16-byte aligned (the
-// counting kernels read out-rows in aligned 16-byte blocks).
+// counting kernels read out-rows in aligned 16-byte blocks); its rows are
+// padded to a multiple of 16 bytes, then come the part's stored boundaries.
 size_t out_head(const bbtc_plan* pl, int a) { return (size_t)(pl->ocut[a] & 3); }
 
-size_t stripe_bytes(const bbtc_plan* pl, int key) {
-  const int a = key >> 1;
-  if ((key & 1) == 0)
-    return align16(4 * (out_head(pl, a) + pl->ocut[a + 1] - pl->ocut[a])) + 4 * (pl->h_botp[a + 1] - pl->h_botp[a]);
-  return align16(4 * (pl->icut[a + 1] - pl->icut[a])) + 4 * (pl->h_tbotp[a + 1] - pl->h_tbotp[a]);
+size_t stripe_bytes(const bbtc_plan* pl, int a) {
+  return align16(4 * (out_head(pl, a) + pl->ocut[a + 1] - pl->ocut[a])) + 4 * (pl->h_botp[a + 1] - pl->h_botp[a]);
 }
 
-bbtc_status stream_setup(bbtc_plan* pl, hipStream_t s) {
+// In-block slot of block cid: active columns | in-slice offsets (one more) |
+// in-slices, each padded to 16 bytes.
+struct BlockSpan {
+  uint64_t x0, nx, e0, ne;  // active columns [x0, x0+nx), entries [e0, e0+ne)
+  size_t o_aoff, o_icol, bytes;
+};
+BlockSpan block_span(const bbtc_plan* pl, int64_t cid) {
+  BlockSpan b;
+  b.x0 = pl->h_acp[cid];
+  b.nx = pl->h_acp[cid + 1] - b.x0;
+  b.e0 = pl->h_aoff[b.x0];
+  b.ne = pl->h_aoff[b.x0 + b.nx] - b.e0;
+  b.o_aoff = align16(4 * b.nx);
+  b.o_icol = b.o_aoff + align16(4 * (b.nx + 1));
+  b.bytes = b.o_icol + align16(4 * b.ne);
+  return b;
+}
+
+// Groups the plan-order work items by block pair, in the walk order, and
+// sets up the slots within the budget.  Needs the pinned arrays in place.
+bbtc_status stream_finish(bbtc_plan* pl, hipStream_t s) {
   const int32_t p = pl->p;
-  const int64_t n = pl->n;
-  // orow/irow at the cut points
-  std::vector<uint32_t> oro(n + 1), iro(n + 1);
-  HIP_TRY(hipMemcpyAsync(oro.data(), pl->orow.ptr, 4 * (n + 1), hipMemcpyDeviceToHost, s), "D2H");
-  HIP_TRY(hipMemcpyAsync(iro.data(), pl->irow.ptr, 4 * (n + 1), hipMemcpyDeviceToHost, s), "D2H");
-  HIP_TRY(hipStreamSynchronize(s), "sync");
-  pl->ocut.assign(p + 1, 0);
-  pl->icut.assign(p + 1, 0);
-  for (int32_t a = 0; a <= p; ++a) {
-    pl->ocut[a] = oro[pl->h_cuts[a]];
-    pl->icut[a] = iro[pl->h_cuts[a]];
-  }
-  pl->h_botp.assign(p + 1, 0);
-  pl->h_tbotp.assign(p + 1, 0);
-  HIP_TRY(hipMemcpyAsync(pl->h_botp.data(), pl->botp, 8 * (p + 1), hipMemcpyDeviceToHost, s), "D2H");
-  HIP_TRY(hipMemcpyAsync(pl->h_tbotp.data(), pl->tbotp, 8 * (p + 1), hipMemcpyDeviceToHost, s), "D2H");
-  HIP_TRY(hipStreamSynchronize(s), "sync");
-  size_t slot = 0;
-  for (int key = 0; key < 2 * p; ++key) slot = std::max(slot, stripe_bytes(pl, key));
-  pl->slot_bytes = align16(std::max<size_t>(slot, 16));
-  bbtc_status st;
-  if ((st = to_pinned(&pl->h_ocol, pl->ocol.ptr, (size_t)pl->m, s)) != BBTC_OK) return st;
-  if ((st = to_pinned(&pl->h_icol, pl->icol.ptr, (size_t)pl->m, s)) != BBTC_OK) return st;
-  if ((st = to_pinned(&pl->h_bot, pl->bot.ptr, (size_t)pl->h_botp[p], s)) != BBTC_OK) return st;
-  if ((st = to_pinned(&pl->h_tbot, pl->tbot.ptr, (size_t)pl->h_tbotp[p], s)) != BBTC_OK) return st;
-  if ((st = to_pinned(&pl->h_orow, pl->orow.ptr, (size_t)n + 1, s)) != BBTC_OK) return st;
-  HIP_TRY(hipStreamSynchronize(s), "sync");
-  pl->streamed = true;
-  // release everything the count phase does not read
-  pl->ocol.release(); pl->icol.release(); pl->bot.release(); pl->tbot.release();
-  pl->keys_a.release(); pl->keys_b.release(); pl->hist.release(); pl->partial.release();
-  pl->od.release(); pl->idg.release(); pl->orow.release(); pl->irow.release(); pl->order.release();
-  pl->longrows.release(); pl->hugerows.release(); pl->ccnt.release(); pl->ccoff.release();
-  pl->in_rowptr.release(); pl->in_col.release(); pl->heavy.release();
-  {  // keep only the used part of the active-column array (its capacity was m)
-    size_t used = 0;
-    for (int64_t v : pl->h_nzc) used += (size_t)v;
-    DevBuf<int32_t> exact;
-    HIP_TRY(exact.ensure(used), "alloc active columns");
-    if (used) HIP_TRY(hipMemcpyAsync(exact.ptr, pl->acol.ptr, 4 * used, hipMemcpyDeviceToDevice, s), "D2D");
-    HIP_TRY(hipStreamSynchronize(s), "sync");
-    pl->acol.release();
-    pl->acol = exact;
-    exact.ptr = nullptr;
-    exact.cap = 0;
-  }
-  // group the work items by block pair, i-major
+  const int64_t nb = (int64_t)p * (p + 1) / 2;
+  pl->h_acp.assign((size_t)nb + 1, 0);
+  for (int64_t b = 0; b < nb; ++b) pl->h_acp[b + 1] = pl->h_acp[b] + (uint64_t)pl->h_nzc[b];
+  pl->heavy.release();  // the hub records were read back by the partition
   if (pl->h_items.size() != pl->nitems) compose_plan_order(pl);
   std::vector<DevItem> items = pl->h_items;
-  auto pair_of = [&](const DevItem& it) {
+  // walk order: i ascending; j ascending for even i, descending for odd i
+  auto walk_key = [&](const DevItem& it) {
     const bbtc_task& t = pl->h_tasks[it.task];
-    return (int64_t)t.i * p + t.j;
+    const int64_t jj = (t.i & 1) ? (p - 1 - t.j) : t.j;
+    return (int64_t)t.i * p + jj;
   };
   std::stable_sort(items.begin(), items.end(),
-                   [&](const DevItem& x, const DevItem& y) { return pair_of(x) < pair_of(y); });
+                   [&](const DevItem& x, const DevItem& y) { return walk_key(x) < walk_key(y); });
   pl->groups.clear();
   pl->group_first.clear();
   pl->group_count.clear();
+  int64_t last = -1;
   for (size_t q = 0; q < items.size(); ++q) {
-    const int64_t key = pair_of(items[q]);
-    if (pl->groups.empty() || (int64_t)pl->groups.back().first * p + pl->groups.back().second != key) {
-      pl->groups.push_back({(int32_t)(key / p), (int32_t)(key % p)});
+    const int64_t key = walk_key(items[q]);
+    if (key != last) {
+      const bbtc_task& t = pl->h_tasks[items[q].task];
+      pl->groups.push_back({t.i, t.j});
       pl->group_first.push_back((int64_t)q);
       pl->group_count.push_back(0);
+      last = key;
     }
     pl->group_count.back()++;
   }
   pl->h_items = items;
   pl->xitems.release();  // streamed launches walk the plan order, pair by pair
   HIP_TRY(pl->items.ensure(items.size()), "alloc items");
-  HIP_TRY(hipMemcpyAsync(pl->items.ptr, items.data(), sizeof(DevItem) * items.size(), hipMemcpyHostToDevice, s),
-          "H2D");
+  if (!items.empty())
+    HIP_TRY(hipMemcpyAsync(pl->items.ptr, items.data(), sizeof(DevItem) * items.size(), hipMemcpyHostToDevice, s),
+            "H2D");
   HIP_TRY(hipStreamSynchronize(s), "sync");
-  // the stripe cache takes what the budget leaves
+  size_t slot = 16, blk = 16;
+  for (int a = 0; a < p; ++a) slot = std::max(slot, stripe_bytes(pl, a));
+  for (const auto& g : pl->groups) blk = std::max(blk, block_span(pl, col_block_id(g.first, g.second)).bytes);
+  pl->slot_bytes = align16(slot);
+  pl->block_bytes = align16(blk);
+  {  // every stripe and block resident
+    int64_t all = (int64_t)pl->footprint();
+    for (int a = 0; a < p; ++a) all += (int64_t)stripe_bytes(pl, a);
+    for (int64_t c = 0; c < nb; ++c) all += (int64_t)block_span(pl, c).bytes;
+    pl->resident_bytes = all;
+  }
+  // the cache takes what the budget leaves: two block slots, then out-stripes
   const int64_t fixed = (int64_t)pl->footprint();
-  const int64_t room = pl->opt.device_budget_bytes - fixed;
+  const int64_t room = pl->opt.device_budget_bytes - fixed - 2 * (int64_t)pl->block_bytes;
   const int64_t nslots = room > 0 ? room / (int64_t)pl->slot_bytes : 0;
-  if (nslots < 3)
-    return fail(BBTC_EBUDGET, "device budget holds " + std::to_string(nslots) + " stripe slots of " +
-                                  std::to_string(pl->slot_bytes) + " B besides " + std::to_string(fixed) +
-                                  " B of resident data; a block pair needs 3");
-  const int64_t use = std::min<int64_t>(nslots, 2 * p);
-  HIP_TRY(pl->cache.ensure((size_t)use * pl->slot_bytes), "alloc stripe cache");
+  if (nslots < 2)
+    return fail(BBTC_EBUDGET, "device budget holds " + std::to_string(nslots) + " out-stripe slots of " +
+                                  std::to_string(pl->slot_bytes) + " B besides two block slots of " +
+                                  std::to_string(pl->block_bytes) + " B and " + std::to_string(fixed) +
+                                  " B of resident data; a block pair needs 2");
+  const int64_t use = std::min<int64_t>(nslots, p);
+  HIP_TRY(pl->cache.ensure((size_t)use * pl->slot_bytes + 2 * pl->block_bytes), "alloc stripe cache");
   pl->slots.assign((size_t)use, bbtc_plan::Slot());
   for (auto& sl : pl->slots) {
     HIP_TRY(hipEventCreateWithFlags(&sl.ready, hipEventDisableTiming), "event");
     HIP_TRY(hipEventCreateWithFlags(&sl.released, hipEventDisableTiming), "event");
   }
+  for (auto& sl : pl->bslot) {
+    HIP_TRY(hipEventCreateWithFlags(&sl.ready, hipEventDisableTiming), "event");
+    HIP_TRY(hipEventCreateWithFlags(&sl.released, hipEventDisableTiming), "event");
+  }
+  pl->streamed = true;
   return BBTC_OK;
 }
 
-// Returns the slot holding stripe `key`, uploading it (on `cs`) if needed,
+// A resident build over the budget: the count-phase arrays move to pinned
+// host memory and every device array the count does not read is released.
+bbtc_status stream_setup(bbtc_plan* pl, hipStream_t s) {
+  const int32_t p = pl->p;
+  const int64_t n = pl->n, nb = (int64_t)p * (p + 1) / 2;
+  std::vector<uint32_t> oro(n + 1);
+  HIP_TRY(hipMemcpyAsync(oro.data(), pl->orow.ptr, 4 * (n + 1), hipMemcpyDeviceToHost, s), "D2H");
+  pl->h_botp.assign(p + 1, 0);
+  HIP_TRY(hipMemcpyAsync(pl->h_botp.data(), pl->botp, 8 * (p + 1), hipMemcpyDeviceToHost, s), "D2H");
+  HIP_TRY(hipStreamSynchronize(s), "sync");
+  pl->ocut.assign(p + 1, 0);
+  for (int32_t a = 0; a <= p; ++a) pl->ocut[a] = oro[pl->h_cuts[a]];
+  size_t ncols = 0;
+  for (int64_t b = 0; b < nb; ++b) ncols += (size_t)pl->h_nzc[b];
+  bbtc_status st;
+  if ((st = to_pinned(&pl->h_ocol, pl->ocol.ptr, (size_t)pl->m, s)) != BBTC_OK) return st;
+  if ((st = to_pinned(&pl->h_bot, pl->bot.ptr, (size_t)pl->h_botp[p], s)) != BBTC_OK) return st;
+  if ((st = to_pinned(&pl->h_orow, pl->orow.ptr, (size_t)n + 1, s)) != BBTC_OK) return st;
+  if ((st = to_pinned(&pl->h_acol, pl->acol.ptr, ncols, s)) != BBTC_OK) return st;
+  if ((st = to_pinned(&pl->h_aoff, pl->aoff.ptr, ncols + 1, s)) != BBTC_OK) return st;
+  if ((st = to_pinned(&pl->h_icolb, pl->icolb.ptr, (size_t)pl->m, s)) != BBTC_OK) return st;
+  HIP_TRY(hipStreamSynchronize(s), "sync");
+  // release everything the count phase does not read (the out-row pointers
+  // stay: the slices of rows without stored boundaries are found by scanning)
+  pl->ocol.release(); pl->icol.release(); pl->bot.release(); pl->acol.release(); pl->aoff.release();
+  pl->asrc.release(); pl->icolb.release(); pl->irow.release();
+  pl->keys_a.release(); pl->keys_b.release(); pl->hist.release(); pl->partial.release();
+  pl->od.release(); pl->idg.release(); pl->order.release();
+  pl->longrows.release(); pl->hugerows.release(); pl->midrows.release(); pl->ccnt.release(); pl->ccoff.release();
+  pl->in_rowptr.release(); pl->in_col.release(); pl->heavy.release(); pl->emit.release();
+  return stream_finish(pl, s);
+}
+
+// Enqueues on `cs` the upload of `bytes` host bytes into a slot once the
+// kernels that read the slot's previous contents are done.
+hipError_t upload_after(bbtc_plan::Slot& sl, hipStream_t cs) {
+  return sl.used ? hipStreamWaitEvent(cs, sl.released, 0) : hipSuccess;
+}
+
+// Returns the slot holding out-stripe a, uploading it (on `cs`) if needed,
 // never evicting a slot listed in `keep`.  -1 if every slot is kept.
-int stripe_slot(bbtc_plan* pl, int key, const std::vector<int>& keep, hipStream_t cs, bbtc_status* st) {
+int stripe_slot(bbtc_plan* pl, int a, const std::vector<int>& keep, hipStream_t cs, bbtc_status* st) {
   *st = BBTC_OK;
   int victim = -1;
   for (size_t q = 0; q < pl->slots.size(); ++q)
-    if (pl->slots[q].key == key) {
+    if (pl->slots[q].key == a) {
       pl->slots[q].last = ++pl->clock;
       return (int)q;
     }
@@ -703,34 +781,41 @@ int stripe_slot(bbtc_plan* pl, int key, const std::vector<int>& keep, hipStream_
   }
   if (victim < 0) return -1;
   bbtc_plan::Slot& sl = pl->slots[victim];
-  hipError_t e = hipSuccess;
-  if (sl.used) e = hipStreamWaitEvent(cs, sl.released, 0);  // kernels reading the old stripe are done
+  hipError_t e = upload_after(sl, cs);
   char* base = pl->cache.ptr + (size_t)victim * pl->slot_bytes;
-  const int a = key >> 1;
-  if (e == hipSuccess) {
-    if ((key & 1) == 0) {
-      const size_t nc = pl->ocut[a + 1] - pl->ocut[a], nb = pl->h_botp[a + 1] - pl->h_botp[a];
-      const size_t hd = out_head(pl, a);
-      if (nc) e = hipMemcpyAsync(base + 4 * hd, pl->h_ocol + pl->ocut[a], 4 * nc, hipMemcpyHostToDevice, cs);
-      if (e == hipSuccess && nb)
-        e = hipMemcpyAsync(base + align16(4 * (hd + nc)), pl->h_bot + pl->h_botp[a], 4 * nb, hipMemcpyHostToDevice,
-                           cs);
-    } else {
-      const size_t nc = pl->icut[a + 1] - pl->icut[a], nb = pl->h_tbotp[a + 1] - pl->h_tbotp[a];
-      if (nc) e = hipMemcpyAsync(base, pl->h_icol + pl->icut[a], 4 * nc, hipMemcpyHostToDevice, cs);
-      if (e == hipSuccess && nb)
-        e = hipMemcpyAsync(base + align16(4 * nc), pl->h_tbot + pl->h_tbotp[a], 4 * nb, hipMemcpyHostToDevice, cs);
-    }
-  }
+  const size_t nc = pl->ocut[a + 1] - pl->ocut[a], nb = pl->h_botp[a + 1] - pl->h_botp[a];
+  const size_t hd = out_head(pl, a);
+  if (e == hipSuccess && nc)
+    e = hipMemcpyAsync(base + 4 * hd, pl->h_ocol + pl->ocut[a], 4 * nc, hipMemcpyHostToDevice, cs);
+  if (e == hipSuccess && nb)
+    e = hipMemcpyAsync(base + align16(4 * (hd + nc)), pl->h_bot + pl->h_botp[a], 4 * nb, hipMemcpyHostToDevice, cs);
   if (e == hipSuccess) e = hipEventRecord(sl.ready, cs);
   if (e != hipSuccess) {
     *st = hip_fail(e, "stripe upload");
     return -1;
   }
-  sl.key = key;
+  sl.key = a;
   sl.last = ++pl->clock;
   pl->copies++;
   return victim;
+}
+
+// Uploads block cid's in side into block slot r (on `cs`).
+bbtc_status block_upload(bbtc_plan* pl, int r, int64_t cid, hipStream_t cs) {
+  bbtc_plan::Slot& sl = pl->bslot[r];
+  const BlockSpan b = block_span(pl, cid);
+  char* base = pl->cache.ptr + pl->slots.size() * pl->slot_bytes + (size_t)r * pl->block_bytes;
+  HIP_TRY(upload_after(sl, cs), "wait");
+  if (b.nx) {
+    HIP_TRY(hipMemcpyAsync(base, pl->h_acol + b.x0, 4 * b.nx, hipMemcpyHostToDevice, cs), "block upload");
+    HIP_TRY(hipMemcpyAsync(base + b.o_aoff, pl->h_aoff + b.x0, 4 * (b.nx + 1), hipMemcpyHostToDevice, cs),
+            "block upload");
+  }
+  if (b.ne) HIP_TRY(hipMemcpyAsync(base + b.o_icol, pl->h_icolb + b.e0, 4 * b.ne, hipMemcpyHostToDevice, cs), "block upload");
+  HIP_TRY(hipEventRecord(sl.ready, cs), "event");
+  sl.key = (int)cid;
+  pl->copies++;
+  return BBTC_OK;
 }
 
 bbtc_status count_streamed(bbtc_plan* pl, hipStream_t s, uint64_t* d_per_task, uint64_t* d_total) {
@@ -738,33 +823,27 @@ bbtc_status count_streamed(bbtc_plan* pl, hipStream_t s, uint64_t* d_per_task, u
   HIP_TRY(launch_reset(d_per_task, nt, d_total, pl->cursor.ptr, s), "reset");
   hipStream_t cs = pl->side[1];
   pl->copies = 0;
-  // earlier uploads may still be pending against an older count
+  // uploads start after the reset (and anything earlier on s) is enqueued
+  HIP_TRY(hipEventRecord(pl->ev_fork, s), "event");
+  HIP_TRY(hipStreamWaitEvent(cs, pl->ev_fork, 0), "wait");
   const int grid_max = pl->blocks_per_cu * pl->ncu;
   for (size_t g = 0; g < pl->groups.size(); ++g) {
     const int32_t i = pl->groups[g].first, j = pl->groups[g].second;
-    const int need[3] = {2 * i, 2 * j, 2 * j + 1};
+    const int64_t cid = col_block_id(i, j);
     std::vector<int> keep;
-    int slot[3];
+    int slot[2];
+    const int need[2] = {i, j};
     bbtc_status st = BBTC_OK;
-    for (int q = 0; q < 3; ++q) {
+    for (int q = 0; q < 2; ++q) {
       slot[q] = stripe_slot(pl, need[q], keep, cs, &st);
       if (st != BBTC_OK) return st;
       if (slot[q] < 0) return fail(BBTC_EBUDGET, "stripe cache too small for one block pair");
       keep.push_back(slot[q]);
     }
-    for (int q = 0; q < 3; ++q) HIP_TRY(hipStreamWaitEvent(s, pl->slots[slot[q]].ready, 0), "wait");
-    // prefetch the next pair's stripes into slots this pair does not use
-    if (g + 1 < pl->groups.size()) {
-      const int32_t i2 = pl->groups[g + 1].first, j2 = pl->groups[g + 1].second;
-      const int nx[3] = {2 * i2, 2 * j2, 2 * j2 + 1};
-      std::vector<int> keep2 = keep;
-      for (int q = 0; q < 3; ++q) {
-        const int sl = stripe_slot(pl, nx[q], keep2, cs, &st);
-        if (st != BBTC_OK) return st;
-        if (sl < 0) break;
-        keep2.push_back(sl);
-      }
-    }
+    const int r = (int)(g & 1);
+    if ((st = block_upload(pl, r, cid, cs)) != BBTC_OK) return st;
+    for (int q = 0; q < 2; ++q) HIP_TRY(hipStreamWaitEvent(s, pl->slots[slot[q]].ready, 0), "wait");
+    HIP_TRY(hipStreamWaitEvent(s, pl->bslot[r].ready, 0), "wait");
     CountParams cp;
     std::memset(&cp, 0, sizeof(cp));
     cp.one = plan_ctx(pl, d_per_task, d_total);
@@ -772,15 +851,17 @@ bbtc_status count_streamed(bbtc_plan* pl, hipStream_t s, uint64_t* d_per_task, u
     cp.one.g.gj = j;
     auto base = [&](int q) { return pl->cache.ptr + (size_t)slot[q] * pl->slot_bytes; };
     const size_t nci = pl->ocut[i + 1] - pl->ocut[i], ncj = pl->ocut[j + 1] - pl->ocut[j];
-    const size_t nij = pl->icut[j + 1] - pl->icut[j];
-    // shifted so that absolute positions index the cached stripe
     const size_t hi = out_head(pl, i), hj = out_head(pl, j);
+    // shifted so that absolute positions and indices land in the slots
     cp.one.g.colI = (const int32_t*)base(0) + hi - pl->ocut[i];
     cp.one.g.botI = (const uint32_t*)(base(0) + align16(4 * (hi + nci)));
     cp.one.g.colJ = (const int32_t*)base(1) + hj - pl->ocut[j];
     cp.one.g.botJ = (const uint32_t*)(base(1) + align16(4 * (hj + ncj)));
-    cp.one.g.icolJ = (const int32_t*)base(2) - pl->icut[j];
-    cp.one.g.tbotJ = (const uint32_t*)(base(2) + align16(4 * nij));
+    const BlockSpan b = block_span(pl, cid);
+    const char* bb = pl->cache.ptr + pl->slots.size() * pl->slot_bytes + (size_t)r * pl->block_bytes;
+    cp.one.g.acolJ = (const int32_t*)bb - b.x0;
+    cp.one.g.aoffJ = (const uint32_t*)(bb + b.o_aoff) - b.x0;
+    cp.one.g.icolJ = (const int32_t*)(bb + b.o_icol) - b.e0;
     cp.items = pl->items.ptr + pl->group_first[g];
     cp.nitems = (uint32_t)pl->group_count[g];
     cp.cursor = pl->cursor.ptr;
@@ -788,12 +869,634 @@ bbtc_status count_streamed(bbtc_plan* pl, hipStream_t s, uint64_t* d_per_task, u
     HIP_TRY(launch_reset(nullptr, 0, nullptr, pl->cursor.ptr, s), "cursor");  // cursor only
     const int grid = (int)std::min<int64_t>(grid_max, (int64_t)cp.nitems);
     HIP_TRY(launch_count_persistent(cp, grid, false, s), "count");
-    for (int q = 0; q < 3; ++q) {
+    for (int q = 0; q < 2; ++q) {
       HIP_TRY(hipEventRecord(pl->slots[slot[q]].released, s), "event");
       pl->slots[slot[q]].used = true;
     }
+    HIP_TRY(hipEventRecord(pl->bslot[r].released, s), "event");
+    pl->bslot[r].used = true;
   }
   return BBTC_OK;
+}
+
+// Block statistics and hub records from the device, the task list and work
+// items (Alg. 4, Sec. 5's estimate), their upload and the plan statistics;
+// then the streaming set-up of a plan over the device budget.  `budgeted`:
+// the count-phase arrays are already in pinned host memory.
+bbtc_status finish_partition(bbtc_plan* pl, hipStream_t s, uint64_t m, uint64_t wedges, uint64_t hcap, bool budgeted,
+                             std::chrono::steady_clock::time_point t0) {
+  const bbtc_options& opt = pl->opt;
+  const int64_t n = pl->n;
+  const int32_t p = pl->p;
+  const int64_t nb = (int64_t)p * (p + 1) / 2;
+  const size_t wb = sizeof(unsigned long long) * (size_t)nb;
+  uint32_t hd[2] = {0, 0};
+  uint32_t nheavy = 0;
+  {  // block statistics through the pinned stage, one copy: [nheavy, dmax x2, -] then bnnz, bnzr, bnzc
+    HIP_TRY(pl->stage.ensure(16 + 3 * wb), "pinned alloc");
+    char* st = pl->stage.ptr;
+    const uint32_t* sc = (const uint32_t*)st;
+    const unsigned long long* sb = (const unsigned long long*)(st + 16);
+    HIP_TRY(hipMemcpyAsync(st, pl->head, 16 + 3 * wb, hipMemcpyDeviceToHost, s), "D2H");
+    HIP_TRY(hipStreamSynchronize(s), "sync");
+    nheavy = sc[0];
+    hd[0] = sc[1];
+    hd[1] = sc[2];
+    pl->h_nnz.assign(sb, sb + nb);
+    pl->h_nzr.assign(sb + nb, sb + 2 * nb);
+    pl->h_nzc.assign(sb + 2 * nb, sb + 3 * nb);
+  }
+  if (nheavy > hcap) return fail(BBTC_EDEVICE, "hub column list overflow");
+  {
+    uint64_t ncols = 0;
+    for (int64_t v : pl->h_nzc) ncols += (uint64_t)v;
+    if (ncols >= (1ull << 31)) return fail(BBTC_EINVAL, "more than 2^31-1 active columns");
+  }
+  pl->h_heavy.resize(nheavy);
+  if (nheavy) {
+    HIP_TRY(pl->stage.ensure(sizeof(HeavyCol) * nheavy), "pinned alloc");
+    HIP_TRY(hipMemcpyAsync(pl->stage.ptr, pl->heavy.ptr, sizeof(HeavyCol) * nheavy, hipMemcpyDeviceToHost, s), "D2H");
+    HIP_TRY(hipStreamSynchronize(s), "sync");
+    std::memcpy(pl->h_heavy.data(), pl->stage.ptr, sizeof(HeavyCol) * nheavy);
+  }
+
+  // ---- tasks (Alg. 4) and work items ----
+  std::vector<uint64_t> acp((size_t)nb + 1);
+  acp[0] = 0;
+  for (int64_t b = 0; b < nb; ++b) acp[b + 1] = acp[b] + (uint64_t)pl->h_nzc[b];
+  compose_tasks(pl);
+  // the persistent launch reads the per-XCD queues, the plain one the plan order
+  const bool queued = opt.mode == BBTC_MODE_PERSISTENT && !budgeted;
+  if (queued) {
+    bbtc_status qst = compose_queues(pl);
+    if (qst != BBTC_OK) return qst;
+  } else {
+    compose_plan_order(pl);
+  }
+  const int64_t nt = (int64_t)pl->h_tasks.size();
+  HIP_TRY(pl->acp.ensure((size_t)nb + 1), "alloc");
+  HIP_TRY(pl->tasks.ensure((size_t)nt), "alloc tasks");
+  HIP_TRY((queued ? pl->xitems : pl->items).ensure(pl->nitems), "alloc items");
+  HIP_TRY(pl->cursor.ensure(kMaxQueues), "alloc");
+  {  // through the pinned stage; the final synchronisation below covers these copies
+    const size_t wa = sizeof(uint64_t) * (size_t)(nb + 1), wt = sizeof(DevTask) * (size_t)nt;
+    // persistent launches: the work items are written on the device from
+    // runs of task items (a few per task) instead of being uploaded
+    const size_t nr = queued ? pl->h_runs.size() : 0, nh = queued ? pl->h_heavy.size() : 0;
+    const size_t o_runs = 0, o_ti = align16(o_runs + sizeof(ItemRun) * nr),
+                 o_hs = align16(o_ti + sizeof(TaskItems) * (size_t)nt),
+                 o_hr = align16(o_hs + sizeof(uint32_t) * (size_t)(nb + 1)),
+                 o_hc = align16(o_hr + sizeof(HeavyCol) * nh), we = align16(o_hc + sizeof(uint32_t) * nh);
+    const size_t e0 = align16(wa + wt);
+    HIP_TRY(pl->stage.ensure(e0 + (queued ? we : 0)), "pinned alloc");
+    char* st = pl->stage.ptr;
+    std::memcpy(st, acp.data(), wa);
+    std::memcpy(st + wa, pl->h_dtasks.data(), wt);
+    HIP_TRY(hipMemcpyAsync(pl->acp.ptr, st, wa, hipMemcpyHostToDevice, s), "H2D");
+    HIP_TRY(hipMemcpyAsync(pl->tasks.ptr, st + wa, wt, hipMemcpyHostToDevice, s), "H2D");
+    if (queued && pl->nitems) {
+      char* e = st + e0;
+      std::memcpy(e + o_runs, pl->h_runs.data(), sizeof(ItemRun) * nr);
+      TaskItems* ti = (TaskItems*)(e + o_ti);
+      for (int64_t q = 0; q < nt; ++q) {
+        const bbtc_task& t = pl->h_tasks[q];
+        const int64_t cid = col_block_id(t.i, t.j);
+        ti[q] = TaskItems{pl->h_nhub[q], pl->h_nper[q], (uint32_t)pl->h_nzc[cid], (uint32_t)cid};
+      }
+      uint32_t* hs = (uint32_t*)(e + o_hs);
+      for (int64_t b = 0; b <= nb; ++b) hs[b] = (uint32_t)pl->h_hstart[b];
+      std::memcpy(e + o_hr, pl->h_heavy.data(), sizeof(HeavyCol) * nh);
+      uint32_t* hc = (uint32_t*)(e + o_hc);  // first chunk number of each record within its block
+      for (int64_t b = 0; b < nb; ++b) {
+        uint32_t c = 0;
+        for (int64_t r = pl->h_hstart[b]; r < pl->h_hstart[b + 1]; ++r) {
+          hc[r] = c;
+          c += (pl->h_heavy[r].cnt + kHubChunk - 1) / kHubChunk;
+        }
+      }
+      HIP_TRY(pl->emit.ensure(we), "alloc");
+      HIP_TRY(hipMemcpyAsync(pl->emit.ptr, e, we, hipMemcpyHostToDevice, s), "H2D");
+      const char* d = pl->emit.ptr;
+      HIP_TRY(launch_emit_items((const ItemRun*)(d + o_runs), (int32_t)nr, (const TaskItems*)(d + o_ti),
+                                (const uint32_t*)(d + o_hs), (const HeavyCol*)(d + o_hr), (const uint32_t*)(d + o_hc),
+                                kHubChunk, pl->xitems.ptr, (uint32_t)pl->nitems, s),
+              "emit work items");
+    }
+  }
+  if (pl->nitems && !queued)
+    HIP_TRY(hipMemcpyAsync(pl->items.ptr, pl->h_items.data(), sizeof(DevItem) * pl->h_items.size(),
+                           hipMemcpyHostToDevice, s),
+            "H2D");
+  pl->plan_order_items = !queued;
+  HIP_TRY(hipStreamSynchronize(s), "sync");
+
+  // ---- statistics (Sec. 4.4 quantities and the byte model) ----
+  bbtc_stats& st = pl->stats;
+  std::memset(&st, 0, sizeof(st));
+  st.n = n;
+  st.m = (int64_t)m;
+  st.p = p;
+  st.ntasks = nt;
+  st.work_tasks = (int64_t)pl->h_work.size();
+  st.nitems = (int64_t)pl->nitems;
+  for (auto v : pl->h_nnz) st.m_max = std::max<int64_t>(st.m_max, v);
+  st.m_avg = 2.0 * (double)m / ((double)p * (double)(p + 1));
+  st.lambda = st.m_avg > 0 ? (double)st.m_max / st.m_avg : 0.0;
+  st.d_max_block = hd[0];
+  st.d_max = hd[1];
+  st.c = st.d_max_block > 0 ? (double)st.d_max / (double)st.d_max_block : 0.0;
+  st.wedges = (int64_t)wedges;
+  st.bytes_colidx = 4 * (int64_t)(p + 2) * (int64_t)m;
+  int64_t rowidx = 0;
+  for (const auto& t : pl->h_tasks)
+    rowidx += 12 * (pl->h_nzr[block_id(p, t.i, t.j)] + pl->h_nzr[block_id(p, t.j, t.k)] +
+                    pl->h_nzr[block_id(p, t.i, t.k)]);
+  st.bytes_rowidx = rowidx;
+  st.bytes_total = st.bytes_colidx + st.bytes_rowidx + 8 * nt;
+  if (budgeted) {
+    bbtc_status sst = stream_finish(pl, s);
+    if (sst != BBTC_OK) return sst;
+  } else if (opt.device_budget_bytes > 0 && (int64_t)pl->footprint() > opt.device_budget_bytes) {
+    bbtc_status sst = stream_setup(pl, s);
+    if (sst != BBTC_OK) return sst;
+  }
+  st.footprint = (int64_t)pl->footprint();
+  st.partition_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  pl->ready = true;
+  return BBTC_OK;
+}
+
+// ------------------------------------------------------------ budgeted partition
+// A graph whose resident partition would exceed the device budget is
+// partitioned from its CSR (host or device memory) in pieces, within the
+// budget: the degree order from the row pointers; the out- and in-degrees
+// chunk by chunk of input rows; then, group of parts by group of parts, the
+// out-rows (sorted, with their stored block boundaries) and, separately, the
+// in side (in-rows grouped by part, then the block-major in side), each
+// group from one pass over the input chunks, copied to pinned host memory.
+// Groups are as large as the budget allows; a single part whose build does
+// not fit is BBTC_EBUDGET.  The count then streams (stream_finish).
+
+// Upper bound of the device bytes of a resident partition.
+int64_t resident_estimate(int64_t n, int64_t nnz, int32_t p, int64_t bound_deg, bool host_input, int64_t rpb) {
+  const int64_t m = nnz / 2;
+  const int64_t stored = bound_deg < 0 ? n : std::min<int64_t>(n, nnz / (bound_deg + 1));
+  int64_t b = (host_input ? rpb * (n + 1) + 4 * nnz : 0);
+  b += 16 * n + 8 * n + 8 * n + 8 * (n + 1) + 12 * n;  // keys, perm/order, degrees, row pointers, row lists
+  b += 4 * (m + 4) * 2 + 4 * m * 4 + 4;                // ocol, icol, acol, aoff, asrc, icolb
+  b += 4 * (int64_t)(p + 1) * stored;                  // stored block boundaries
+  b += 16 * ((int64_t)p * (n / kPrepRows + p) + 1);    // chunk counters and their scans
+  b += 12 * (m / 256 + 1) + (int64_t)p * (p + 1) * (p + 2) / 6 * 48 + (64 << 20);  // hubs, tasks, items, slack
+  return b;
+}
+
+struct InChunk {
+  int64_t x0, x1, e0, e1;
+};
+
+struct BudgetBuild {
+  bbtc_plan* pl;
+  const bbtc_csr* g;
+  hipStream_t s;
+  bool on_device;
+  int rp64;
+  size_t rpb;
+  std::vector<int64_t> hrp;   // row pointers on the host (64-bit)
+  std::vector<InChunk> chunks;
+  DevBuf<char> crp;           // a chunk's row pointers (host input)
+  DevBuf<int32_t> ccol;       // a chunk's entries (host input)
+  DevBuf<uint32_t> hpref, cur_o, cur_i, q;
+  uint64_t max_rows = 0, max_ent = 0;
+
+  const int64_t* rp_host() const { return hrp.data(); }
+  // Device pointers of chunk c: its row pointers (at row x0) and entries
+  // (shifted so that absolute positions index them).
+  bbtc_status load(size_t c, const void** rp, const int32_t** col) {
+    const InChunk& k = chunks[c];
+    if (on_device) {
+      *rp = (const char*)g->rowptr + (size_t)k.x0 * rpb;
+      *col = g->colidx;
+      return BBTC_OK;
+    }
+    HIP_TRY(hipMemcpyAsync(crp.ptr, (const char*)g->rowptr + (size_t)k.x0 * rpb, (size_t)(k.x1 - k.x0 + 1) * rpb,
+                           hipMemcpyHostToDevice, s),
+            "H2D rows");
+    if (k.e1 > k.e0)
+      HIP_TRY(hipMemcpyAsync(ccol.ptr, g->colidx + k.e0, 4 * (size_t)(k.e1 - k.e0), hipMemcpyHostToDevice, s),
+              "H2D entries");
+    *rp = crp.ptr;
+    *col = ccol.ptr - k.e0;
+    return BBTC_OK;
+  }
+  // One pass of the degree kernels over every chunk: od != nullptr counts
+  // the out-/in-degrees (with the entry checks of trusted input when check),
+  // otherwise only the row lists are made and the fill of the ranks
+  // [rlo, rhi) writes ocol/icol (either may be null).
+  bbtc_status pass(uint32_t* od, uint32_t* idg, int check, int32_t rlo, int32_t rhi, int32_t* ocol, int32_t* icol) {
+    bbtc_plan* P = pl;
+    for (size_t c = 0; c < chunks.size(); ++c) {
+      const InChunk& k = chunks[c];
+      const void* rp;
+      const int32_t* col;
+      bbtc_status st = load(c, &rp, &col);
+      if (st != BBTC_OK) return st;
+      HIP_TRY(hipMemsetAsync(P->err.ptr + 4, 0, 8, s), "memset");
+      const RowRange rr{k.x0, P->n, k.e0, k.e1, rlo, rhi};
+      const int64_t nr = k.x1 - k.x0;
+      HIP_TRY(launch_degs(rp, rp64, col, nr, rr, P->perm.ptr, od, idg, P->longrows.ptr, P->err.ptr + 4,
+                          P->hugerows.ptr, P->err.ptr + 5, hpref.ptr, P->err.ptr, check, s),
+              "degrees");
+      if (!od)
+        HIP_TRY(launch_fill(rp, rp64, col, nr, rr, P->perm.ptr, P->orow.ptr, P->irow.ptr, ocol, icol, P->longrows.ptr,
+                            P->err.ptr + 4, P->hugerows.ptr, P->err.ptr + 5, hpref.ptr, cur_o.ptr, cur_i.ptr, s),
+                "fill");
+    }
+    return BBTC_OK;
+  }
+};
+
+bbtc_status partition_budgeted(const bbtc_csr* g, hipStream_t s, bbtc_plan* pl,
+                               std::chrono::steady_clock::time_point t0) {
+  const bbtc_options& opt = pl->opt;
+  const int64_t n = g->n, nnz = g->nnz, budget = opt.device_budget_bytes;
+  BudgetBuild B;
+  B.pl = pl;
+  B.g = g;
+  B.s = s;
+  B.on_device = (g->flags & BBTC_CSR_DEVICE) != 0;
+  B.rp64 = g->rowptr_bits == 64;
+  B.rpb = B.rp64 ? 8 : 4;
+  const bool symmetric_check = (g->flags & BBTC_CSR_TRUSTED) == 0;
+  {  // the per-vertex arrays of the degree order must fit at least
+    const int64_t fixed = 24 * n + (B.on_device ? 0 : (int64_t)B.rpb * (n + 1)) + (8 << 20);
+    if (fixed > budget)
+      return fail(BBTC_EBUDGET, "device budget below the " + std::to_string(fixed) +
+                                    " B that ordering the vertices needs");
+  }
+  // row pointers on the host, chunks of input rows (at most max_ent entries
+  // and max_rows rows each; a longer row is a chunk of its own)
+  B.hrp.resize((size_t)n + 1);
+  if (B.on_device) {
+    std::vector<char> tmp((size_t)(n + 1) * B.rpb);
+    HIP_TRY(hipMemcpy(tmp.data(), g->rowptr, tmp.size(), hipMemcpyDeviceToHost), "D2H rowptr");
+    for (int64_t x = 0; x <= n; ++x)
+      B.hrp[x] = B.rp64 ? ((const int64_t*)tmp.data())[x] : (int64_t)((const int32_t*)tmp.data())[x];
+  } else {
+    for (int64_t x = 0; x <= n; ++x)
+      B.hrp[x] = B.rp64 ? ((const int64_t*)g->rowptr)[x] : (int64_t)((const int32_t*)g->rowptr)[x];
+  }
+  // a chunk's entries take at most 1/32 of the budget
+  const uint64_t ent_cap = (uint64_t)std::max<int64_t>(4096, std::min<int64_t>(1 << 28, budget / 128));
+  const uint64_t row_cap = std::min<uint64_t>(1 << 23, std::max<uint64_t>(4096, ent_cap / 4));
+  for (int64_t x0 = 0; x0 < n;) {
+    int64_t x1 = x0 + 1;
+    while (x1 < n && (uint64_t)(x1 + 1 - x0) <= row_cap && (uint64_t)(B.hrp[x1 + 1] - B.hrp[x0]) <= ent_cap) ++x1;
+    B.chunks.push_back(InChunk{x0, x1, B.hrp[x0], B.hrp[x1]});
+    B.max_rows = std::max<uint64_t>(B.max_rows, (uint64_t)(x1 - x0));
+    B.max_ent = std::max<uint64_t>(B.max_ent, (uint64_t)(B.hrp[x1] - B.hrp[x0]));
+    x0 = x1;
+  }
+  if (!B.on_device) {
+    HIP_TRY(B.crp.ensure((B.max_rows + 1) * B.rpb), "alloc chunk rows");
+    HIP_TRY(B.ccol.ensure(B.max_ent), "alloc chunk entries");
+  }
+  HIP_TRY(pl->err.ensure(8), "alloc");
+  HIP_TRY(pl->longrows.ensure(B.max_rows), "alloc");
+  HIP_TRY(pl->hugerows.ensure(B.max_rows), "alloc");
+  HIP_TRY(B.hpref.ensure(B.max_rows + 1), "alloc");
+  HIP_TRY(B.cur_o.ensure(B.max_rows), "alloc");
+  HIP_TRY(B.cur_i.ensure(B.max_rows), "alloc");
+  HIP_TRY(hipMemsetAsync(pl->err.ptr, 0, 8 * sizeof(uint32_t), s), "memset");
+  if (B.on_device && symmetric_check) {  // untrusted device input: the validation kernels, on the whole input
+    HIP_TRY(pl->irow.ensure((size_t)n + 1), "alloc");
+    DevBuf<uint32_t> l1, l2;
+    HIP_TRY(l1.ensure((size_t)n), "alloc");
+    HIP_TRY(l2.ensure((size_t)n), "alloc");
+    HIP_TRY(launch_validate(g->rowptr, B.rp64, g->colidx, n, nnz, 1, pl->err.ptr, l1.ptr, pl->err.ptr + 4, l2.ptr,
+                            pl->err.ptr + 5, pl->irow.ptr, s),
+            "validate");
+    uint32_t e = 0;
+    HIP_TRY(hipMemcpyAsync(&e, pl->err.ptr, 4, hipMemcpyDeviceToHost, s), "D2H err");
+    HIP_TRY(hipStreamSynchronize(s), "sync");
+    l1.release();
+    l2.release();
+    if (e) return decode_device_err(e);
+    HIP_TRY(hipMemsetAsync(pl->err.ptr, 0, 8 * sizeof(uint32_t), s), "memset");
+  }
+  // trusted input: the degree pass checks the entries (untrusted input was
+  // checked above, on the host or by the validation kernels)
+  const int check_in_degs = symmetric_check ? 0 : 1;
+
+  // ---- degree order (Sec. 4.1) from the row pointers alone ----
+  pl->idbits = bits_for((uint64_t)(n - 1));
+  {
+    DevBuf<char> drp;
+    const void* rp = g->rowptr;
+    if (!B.on_device) {
+      HIP_TRY(drp.ensure((size_t)(n + 1) * B.rpb), "alloc rowptr");
+      HIP_TRY(hipMemcpyAsync(drp.ptr, g->rowptr, (size_t)(n + 1) * B.rpb, hipMemcpyHostToDevice, s), "H2D rowptr");
+      rp = drp.ptr;
+    }
+    HIP_TRY(pl->keys_a.ensure((size_t)n), "alloc keys");
+    HIP_TRY(pl->keys_b.ensure((size_t)n), "alloc keys");
+    HIP_TRY(pl->hist.ensure(radix_hist_entries((uint64_t)n)), "alloc hist");
+    HIP_TRY(pl->partial.ensure(scan_partial_entries(std::max<uint64_t>(radix_hist_entries((uint64_t)n), (uint64_t)n + 1)) +
+                               4096),
+            "alloc partial");
+    HIP_TRY(pl->perm.ensure((size_t)n), "alloc perm");
+    HIP_TRY(pl->order.ensure((size_t)n), "alloc order");
+    uint64_t* sorted = nullptr;
+    HIP_TRY(launch_degkey(rp, B.rp64, n, pl->idbits, pl->keys_a.ptr, s), "degkey");
+    HIP_TRY(radix_sort_u64(pl->keys_a.ptr, pl->keys_b.ptr, (uint64_t)n, pl->idbits, 2 * pl->idbits, pl->hist.ptr,
+                           pl->partial.ptr, &sorted, s),
+            "degree sort");
+    HIP_TRY(launch_perm(sorted, n, pl->idbits, pl->order.ptr, pl->perm.ptr, s), "perm");
+    HIP_TRY(hipStreamSynchronize(s), "sync");
+    pl->keys_a.release();
+    pl->keys_b.release();
+    pl->hist.release();
+    pl->order.release();
+  }
+
+  // ---- out- and in-degrees, chunk by chunk ----
+  HIP_TRY(pl->od.ensure((size_t)n), "alloc od");
+  HIP_TRY(pl->idg.ensure((size_t)n), "alloc idg");
+  bbtc_status st = B.pass(pl->od.ptr, pl->idg.ptr, check_in_degs, 0, (int32_t)n, nullptr, nullptr);
+  if (st != BBTC_OK) return st;
+  unsigned long long* d_wedges = (unsigned long long*)(pl->err.ptr + 6);
+  HIP_TRY(launch_degree_stats(pl->od.ptr, pl->idg.ptr, n, eff_bound_min_deg(opt), d_wedges, pl->err.ptr + 1, s),
+          "degree statistics");
+  HIP_TRY(pl->orow.ensure((size_t)n + 1), "alloc orow");
+  HIP_TRY(pl->irow.ensure((size_t)n + 1), "alloc irow");
+  HIP_TRY(scan_u32(pl->od.ptr, pl->orow.ptr, (uint64_t)n, pl->partial.ptr, s), "scan out-degrees");
+  HIP_TRY(scan_u32(pl->idg.ptr, pl->irow.ptr, (uint64_t)n, pl->partial.ptr, s), "scan in-degrees");
+  std::vector<uint32_t> horow((size_t)n + 1), hirow((size_t)n + 1);
+  uint32_t eb[4] = {0, 0, 0, 0};
+  uint64_t wedges = 0;
+  HIP_TRY(hipMemcpyAsync(horow.data(), pl->orow.ptr, 4 * (n + 1), hipMemcpyDeviceToHost, s), "D2H orow");
+  HIP_TRY(hipMemcpyAsync(hirow.data(), pl->irow.ptr, 4 * (n + 1), hipMemcpyDeviceToHost, s), "D2H irow");
+  HIP_TRY(hipMemcpyAsync(eb, pl->err.ptr, 8, hipMemcpyDeviceToHost, s), "D2H err");
+  HIP_TRY(hipMemcpyAsync(&wedges, d_wedges, 8, hipMemcpyDeviceToHost, s), "D2H wedges");
+  HIP_TRY(hipStreamSynchronize(s), "sync");
+  if (eb[0]) return decode_device_err(eb[0]);
+  pl->rT = (int64_t)eb[1];
+  const uint64_t m = horow[n];
+  if (m > (uint64_t)nnz / 2 || hirow[n] != horow[n]) return fail(BBTC_EINVAL, "input is not symmetric");
+  pl->m = (int64_t)m;
+  pl->od.release();
+  pl->idg.release();
+  // ---- cut vector (Sec. 4.1) ----
+  int32_t p = opt.p;
+  if (p == 0) {  // p near the average degree (Sec. 7.3)
+    p = (int32_t)std::lround(2.0 * (double)m / (double)n);
+    p = std::max(1, std::min<int32_t>(p, (int32_t)std::min<int64_t>(n, 256)));
+  }
+  pl->p = p;
+  pl->opt.p = p;
+  HIP_TRY(pl->cuts.ensure((size_t)p + 1), "alloc cuts");
+  HIP_TRY(launch_cuts(pl->orow.ptr, n, p, opt.cut_mode, pl->cuts.ptr, s), "cuts");
+  pl->h_cuts.assign((size_t)p + 1, 0);
+  HIP_TRY(hipMemcpyAsync(pl->h_cuts.data(), pl->cuts.ptr, 4 * (p + 1), hipMemcpyDeviceToHost, s), "D2H cuts");
+  HIP_TRY(hipStreamSynchronize(s), "sync");
+  const std::vector<int32_t>& cuts = pl->h_cuts;
+  const int64_t nb = (int64_t)p * (p + 1) / 2;
+  pl->ocut.assign(p + 1, 0);
+  std::vector<uint64_t> icut(p + 1, 0);
+  for (int32_t a = 0; a <= p; ++a) {
+    pl->ocut[a] = horow[cuts[a]];
+    icut[a] = hirow[cuts[a]];
+  }
+  // chunk tables and stored-boundary offsets of every part (as partition_impl)
+  std::vector<int32_t> chunk0((size_t)p + 1);
+  std::vector<uint64_t> ccbase((size_t)p + 1), botp((size_t)p + 1);
+  int64_t nch = 0;
+  uint64_t cc = 0, bp = 0;
+  for (int32_t a = 0; a < p; ++a) {
+    const int64_t va = cuts[a + 1] - cuts[a];
+    const int64_t ca = (va + kPrepRows - 1) / kPrepRows;
+    const int64_t sa = std::max<int64_t>(0, cuts[a + 1] - std::max<int64_t>(cuts[a], pl->rT));
+    chunk0[a] = (int32_t)nch;
+    ccbase[a] = cc;
+    botp[a] = bp;
+    nch += ca;
+    cc += (uint64_t)(a + 1) * (uint64_t)ca;
+    bp += (uint64_t)(p - a + 1) * (uint64_t)sa;
+  }
+  chunk0[p] = (int32_t)nch;
+  ccbase[p] = cc;
+  botp[p] = bp;
+  pl->ccount = (int64_t)cc;
+  pl->h_botp = botp;
+  const size_t w8 = sizeof(uint64_t) * (size_t)(p + 1), wb = sizeof(unsigned long long) * (size_t)nb;
+  const size_t o_cb = align16(sizeof(int32_t) * (size_t)(p + 1)), o_hd = align16(o_cb + 2 * w8);
+  HIP_TRY(pl->blk.ensure(o_hd + 16 + 3 * wb), "alloc");
+  pl->chunk0 = (int32_t*)pl->blk.ptr;
+  pl->ccbase = (uint64_t*)(pl->blk.ptr + o_cb);
+  pl->botp = pl->ccbase + (p + 1);
+  pl->head = (uint32_t*)(pl->blk.ptr + o_hd);
+  pl->bnnz = (unsigned long long*)(pl->blk.ptr + o_hd + 16);
+  pl->bnzr = pl->bnnz + nb;
+  pl->bnzc = pl->bnzr + nb;
+  {
+    HIP_TRY(pl->stage.ensure(std::max(o_hd, 16 + 3 * wb)), "pinned alloc");
+    char* stg = pl->stage.ptr;
+    std::memcpy(stg, chunk0.data(), sizeof(int32_t) * (p + 1));
+    std::memcpy(stg + o_cb, ccbase.data(), w8);
+    std::memcpy(stg + o_cb + w8, botp.data(), w8);
+    HIP_TRY(hipMemcpyAsync(pl->blk.ptr, stg, o_hd, hipMemcpyHostToDevice, s), "H2D");
+    HIP_TRY(hipMemsetAsync(pl->head, 0, 16 + 3 * wb, s), "memset");
+    HIP_TRY(hipStreamSynchronize(s), "sync");
+  }
+  pl->split = kHubSplit;
+  const uint64_t hcap = m / kHubSplit + 1;
+  HIP_TRY(pl->heavy.ensure((size_t)hcap), "alloc");
+  // pinned host arrays of the count phase (active columns: at most m)
+  HIP_TRY(hipHostMalloc((void**)&pl->h_ocol, 4 * std::max<uint64_t>(m, 1), hipHostMallocDefault), "pinned alloc");
+  HIP_TRY(hipHostMalloc((void**)&pl->h_bot, 4 * std::max<uint64_t>(bp, 1), hipHostMallocDefault), "pinned alloc");
+  HIP_TRY(hipHostMalloc((void**)&pl->h_orow, 4 * ((size_t)n + 1), hipHostMallocDefault), "pinned alloc");
+  HIP_TRY(hipHostMalloc((void**)&pl->h_acol, 4 * std::max<uint64_t>(m, 1), hipHostMallocDefault), "pinned alloc");
+  HIP_TRY(hipHostMalloc((void**)&pl->h_aoff, 4 * (m + 1), hipHostMallocDefault), "pinned alloc");
+  HIP_TRY(hipHostMalloc((void**)&pl->h_icolb, 4 * std::max<uint64_t>(m, 1), hipHostMallocDefault), "pinned alloc");
+  std::memcpy(pl->h_orow, horow.data(), 4 * ((size_t)n + 1));
+
+  BlockBuild bb;
+  std::memset(&bb, 0, sizeof(bb));
+  bb.p = p;
+  bb.rT = (int32_t)pl->rT;
+  bb.nchunks = (int32_t)nch;
+  bb.cuts = pl->cuts.ptr;
+  bb.chunk0 = pl->chunk0;
+  bb.ccbase = pl->ccbase;
+  bb.orow = pl->orow.ptr;
+  bb.botp = pl->botp;
+  bb.irow = pl->irow.ptr;
+  bb.bnnz = pl->bnnz;
+  bb.bnzr = pl->bnzr;
+  bb.bnzc = pl->bnzc;
+  bb.dmax_block = pl->head + 1;
+  bb.split = pl->split;
+  bb.heavy = pl->heavy.ptr;
+  bb.nheavy = pl->head;
+  bb.heavy_cap = (uint32_t)hcap;
+  HIP_TRY(B.q.ensure(4), "alloc");
+  // what stays on the device meanwhile; groups take the rest of the budget
+  auto room = [&]() { return budget - (int64_t)pl->footprint() - (int64_t)(B.crp.bytes() + B.ccol.bytes() +
+                                                                          B.hpref.bytes() + B.cur_o.bytes() +
+                                                                          B.cur_i.bytes() + B.q.bytes()); };
+  DevBuf<int32_t> ga, gb;  // group rows and scratch
+  DevBuf<uint32_t> gbot, gacol, gaoff, gasrc, gcc;
+
+  // ---- out side, group by group: out-rows sorted, stored boundaries ----
+  // group buffers (rows, scratch, boundaries) and the row lists of a group
+  // are allocated per group and released after it, so each group may use
+  // all of room()
+  auto drop_lists = [&]() {
+    pl->midrows.release();
+    pl->longrows.release();
+    pl->hugerows.release();
+  };
+  for (int32_t a0 = 0; a0 < p;) {
+    int32_t a1 = a0;
+    int64_t need = 0;
+    drop_lists();
+    const int64_t avail = room();
+    while (a1 < p) {
+      const int64_t e = (int64_t)(pl->ocut[a1 + 1] - pl->ocut[a0]), rows = cuts[a1 + 1] - cuts[a0];
+      const int64_t want = 8 * (e + 8) + 4 * (int64_t)(botp[a1 + 1] - botp[a0]) + 12 * rows + 1024;
+      if (a1 > a0 && want > avail) break;
+      need = want;
+      ++a1;
+    }
+    if (need > avail)
+      return fail(BBTC_EBUDGET, "device budget too small to build the out-rows of part " + std::to_string(a0) + " (" +
+                                    std::to_string(need) + " B needed, " + std::to_string(room()) + " B free)");
+    const int64_t R0 = cuts[a0], R1 = cuts[a1];
+    const uint64_t o0 = pl->ocut[a0], ne = pl->ocut[a1] - o0;
+    HIP_TRY(ga.ensure(ne + 8), "alloc group rows");
+    HIP_TRY(gb.ensure(ne + 8), "alloc group scratch");
+    HIP_TRY(gbot.ensure(botp[a1] - botp[a0]), "alloc group boundaries");
+    HIP_TRY(pl->midrows.ensure((size_t)(R1 - R0)), "alloc");
+    HIP_TRY(pl->longrows.ensure(std::max<size_t>((size_t)(R1 - R0), B.max_rows)), "alloc");
+    HIP_TRY(pl->hugerows.ensure(std::max<size_t>((size_t)(R1 - R0), B.max_rows)), "alloc");
+    if ((st = B.pass(nullptr, nullptr, 0, (int32_t)R0, (int32_t)R1, ga.ptr - o0, nullptr)) != BBTC_OK) return st;
+    HIP_TRY(hipMemsetAsync(B.q.ptr, 0, 16, s), "memset");
+    HIP_TRY(launch_segsort(pl->orow.ptr + R0, ga.ptr - o0, R1 - R0, pl->idbits, pl->midrows.ptr, pl->longrows.ptr,
+                           pl->hugerows.ptr, B.q.ptr, gb.ptr - o0, s),
+            "sort out-rows");
+    bb.chunk_base = chunk0[a0];
+    bb.ocol = ga.ptr - o0;
+    bb.bot = gbot.ptr - botp[a0];
+    HIP_TRY(launch_bot(bb, chunk0[a1] - chunk0[a0], s), "block row index");
+    if (ne) HIP_TRY(hipMemcpyAsync(pl->h_ocol + o0, ga.ptr, 4 * ne, hipMemcpyDeviceToHost, s), "D2H");
+    if (botp[a1] > botp[a0])
+      HIP_TRY(hipMemcpyAsync(pl->h_bot + botp[a0], gbot.ptr, 4 * (botp[a1] - botp[a0]), hipMemcpyDeviceToHost, s),
+              "D2H");
+    HIP_TRY(hipStreamSynchronize(s), "sync");
+    ga.release();
+    gb.release();
+    gbot.release();
+    a0 = a1;
+  }
+
+  // ---- in side, group by group: in-rows grouped by part, block-major ----
+  uint64_t xbase = 0;
+  uint32_t hdone = 0;  // hub records written by earlier groups
+  for (int32_t a0 = 0; a0 < p;) {
+    int32_t a1 = a0;
+    int64_t need = 0;
+    drop_lists();
+    const int64_t avail = room();
+    while (a1 < p) {
+      const int64_t e = (int64_t)(icut[a1 + 1] - icut[a0]), rows = cuts[a1 + 1] - cuts[a0];
+      const int64_t cols = std::min<int64_t>(e, rows * (int64_t)(a1 + 1));  // active columns, at most
+      const int64_t want =
+          8 * (e + 8) + 12 * (cols + 1) + 12 * rows + 16 * (int64_t)(ccbase[a1 + 1] - ccbase[a0] + 1) + 1024;
+      if (a1 > a0 && want > avail) break;
+      need = want;
+      ++a1;
+    }
+    if (need > avail)
+      return fail(BBTC_EBUDGET, "device budget too small to build the in side of part " + std::to_string(a0) + " (" +
+                                    std::to_string(need) + " B needed, " + std::to_string(room()) + " B free)");
+    const int64_t R0 = cuts[a0], R1 = cuts[a1];
+    const uint64_t i0 = icut[a0], ne = icut[a1] - i0, c0 = ccbase[a0], ncc = ccbase[a1] - c0;
+    HIP_TRY(ga.ensure(ne + 8), "alloc group in-rows");
+    HIP_TRY(gb.ensure(ne + 8), "alloc group scratch");
+    HIP_TRY(gcc.ensure(4 * (ncc + 1)), "alloc group counters");
+    HIP_TRY(pl->midrows.ensure((size_t)(R1 - R0)), "alloc");
+    HIP_TRY(pl->longrows.ensure(std::max<size_t>((size_t)(R1 - R0), B.max_rows)), "alloc");
+    HIP_TRY(pl->hugerows.ensure(std::max<size_t>((size_t)(R1 - R0), B.max_rows)), "alloc");
+    if (pl->partial.cap < scan_partial_entries(ncc)) HIP_TRY(pl->partial.ensure(scan_partial_entries(ncc) + 4096), "alloc");
+    if ((st = B.pass(nullptr, nullptr, 0, (int32_t)R0, (int32_t)R1, nullptr, ga.ptr - i0)) != BBTC_OK) return st;
+    HIP_TRY(hipMemsetAsync(B.q.ptr, 0, 16, s), "memset");
+    HIP_TRY(launch_inrows_sort(pl->irow.ptr + R0, ga.ptr - i0, R1 - R0, pl->midrows.ptr, pl->longrows.ptr,
+                               pl->hugerows.ptr, B.q.ptr, s),
+            "sort in-rows");
+    HIP_TRY(launch_inrows_group(pl->irow.ptr + R0, ga.ptr - i0, pl->longrows.ptr, pl->hugerows.ptr, B.q.ptr,
+                                gb.ptr - i0, pl->cuts.ptr, p, s),
+            "group in-rows");
+    uint32_t* ccnt = gcc.ptr;                   // [ncc] column counts, [ncc] entry counts,
+    uint32_t* ecnt = gcc.ptr + (ncc + 1);       // then their scans
+    uint32_t* ccoff = gcc.ptr + 2 * (ncc + 1);
+    uint32_t* ecoff = gcc.ptr + 3 * (ncc + 1);
+    bb.chunk_base = chunk0[a0];
+    bb.icol = ga.ptr - i0;
+    bb.ccnt = ccnt - c0;
+    bb.ecnt = ecnt - c0;
+    HIP_TRY(launch_acount(bb, chunk0[a1] - chunk0[a0], s), "active-column counts");
+    HIP_TRY(scan_u32(ccnt, ccoff, ncc, pl->partial.ptr, s), "scan column counters");
+    HIP_TRY(scan_u32(ecnt, ecoff, ncc, pl->partial.ptr, s), "scan entry counters");
+    uint32_t ncols = 0;
+    HIP_TRY(hipMemcpyAsync(&ncols, ccoff + ncc, 4, hipMemcpyDeviceToHost, s), "D2H");
+    HIP_TRY(hipStreamSynchronize(s), "sync");
+    HIP_TRY(gacol.ensure((size_t)ncols + 1), "alloc group active columns");
+    HIP_TRY(gaoff.ensure((size_t)ncols + 1), "alloc group offsets");
+    HIP_TRY(gasrc.ensure((size_t)ncols + 1), "alloc group sources");
+    bb.ccoff = ccoff - c0;
+    bb.ecoff = ecoff - c0;
+    bb.acol = (int32_t*)gacol.ptr;
+    bb.aoff = gaoff.ptr;
+    bb.asrc = gasrc.ptr;
+    bb.ebase = (uint32_t)i0;
+    bb.xbase = xbase;
+    HIP_TRY(launch_acol(bb, chunk0[a1] - chunk0[a0], s), "active columns");
+    HIP_TRY(launch_set_at(gaoff.ptr, ccoff + ncc, (uint32_t)icut[a1], s), "in-slice sentinel");
+    HIP_TRY(launch_icolb(gaoff.ptr, gasrc.ptr, ga.ptr - i0, gb.ptr - i0, ccoff + ncc, ncols, pl->split,
+                         pl->heavy.ptr, hdone, pl->head, (uint32_t)hcap, xbase, s),
+            "block-major in side");
+    if (ncols) {
+      HIP_TRY(hipMemcpyAsync(pl->h_acol + xbase, gacol.ptr, 4 * (size_t)ncols, hipMemcpyDeviceToHost, s), "D2H");
+      HIP_TRY(hipMemcpyAsync(pl->h_aoff + xbase, gaoff.ptr, 4 * ((size_t)ncols + 1), hipMemcpyDeviceToHost, s), "D2H");
+    }
+    if (ne) HIP_TRY(hipMemcpyAsync(pl->h_icolb + i0, gb.ptr, 4 * ne, hipMemcpyDeviceToHost, s), "D2H");
+    HIP_TRY(hipMemcpyAsync(&hdone, pl->head, 4, hipMemcpyDeviceToHost, s), "D2H");
+    HIP_TRY(hipStreamSynchronize(s), "sync");
+    hdone = std::min<uint32_t>(hdone, (uint32_t)hcap);
+    xbase += ncols;
+    ga.release();
+    gb.release();
+    gacol.release();
+    gaoff.release();
+    gasrc.release();
+    gcc.release();
+    a0 = a1;
+  }
+  pl->h_aoff[xbase] = (uint32_t)m;
+  // only what the count reads stays on the device: perm, orow, the plan
+  // tables; the rest is released
+  pl->irow.release();
+  pl->midrows.release();
+  pl->longrows.release();
+  pl->hugerows.release();
+  pl->partial.release();
+  B.crp.release();
+  B.ccol.release();
+  B.hpref.release();
+  B.cur_o.release();
+  B.cur_i.release();
+  B.q.release();
+  return finish_partition(pl, s, m, wedges, hcap, true, t0);
 }
 
 bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStream_t s, bbtc_plan* pl) {
@@ -810,7 +1513,8 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   if (opt.p < 0 || opt.p > kMaxP || opt.p > n) return fail(BBTC_EINVAL, "p must be in [0, min(n, 2048)]");
   if (opt.cut_mode != BBTC_CUT_BALANCED && opt.cut_mode != BBTC_CUT_UNIFORM) return fail(BBTC_EINVAL, "bad cut_mode");
   if (opt.mode < BBTC_MODE_PERSISTENT || opt.mode > BBTC_MODE_PLAIN_HMAP) return fail(BBTC_EINVAL, "bad mode");
-  if (opt.wave_min < 0 || opt.grid < 0 || opt.item_rows < 0 || opt.device_budget_bytes < 0 || opt.hash_min < -1)
+  if (opt.wave_min < 0 || opt.grid < 0 || opt.item_rows < 0 || opt.device_budget_bytes < 0 || opt.hash_min < -1 ||
+      opt.bound_min_deg < -1)
     return fail(BBTC_EINVAL, "negative option");
   if (opt.graph != 0 && opt.graph != -1) return fail(BBTC_EINVAL, "graph must be 0 or -1");
   const bool on_device = (g->flags & BBTC_CSR_DEVICE) != 0;
@@ -829,6 +1533,8 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   pl->ready = false;
   pl->drop_graph();
   pl->drop_stream();
+  pl->hy = bbtc_plan::HybridHost();
+  pl->plan_order_items = false;
   pl->opt = opt;
   pl->n = n;
   if (!pl->ncu) {
@@ -844,6 +1550,12 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
     }
     HIP_TRY(hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming), "hipEventCreate");
     HIP_TRY(hipEventCreateWithFlags(&pl->ev_cuts, hipEventDisableTiming), "hipEventCreate");
+  }
+  // over the device budget even to partition: partition in pieces
+  if (opt.device_budget_bytes > 0) {
+    const int32_t pe = opt.p > 0 ? opt.p : 256;
+    if (resident_estimate(n, nnz, pe, eff_bound_min_deg(opt), !on_device, rp64 ? 8 : 4) > opt.device_budget_bytes)
+      return partition_budgeted(g, s, pl, t0);
   }
 
   const size_t rp_bytes = (size_t)(n + 1) * (rp64 ? 8 : 4);
@@ -906,10 +1618,15 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   // ---- orientation: out-rows (higher ranks) and in-rows (lower ranks) ----
   // err[4]: rows too long for one lane, listed in longrows by launch_degs
   // err[4], err[5]: rows too long for one lane / huge rows, listed by launch_degs
-  HIP_TRY(launch_degs(rowptr, rp64, col, n, nnz, pl->perm.ptr, pl->od.ptr, pl->idg.ptr, pl->longrows.ptr,
+  HIP_TRY(launch_degs(rowptr, rp64, col, n, whole_rows(n, nnz), pl->perm.ptr, pl->od.ptr, pl->idg.ptr, pl->longrows.ptr,
                       pl->err.ptr + 4, pl->hugerows.ptr, pl->err.ptr + 5, (uint32_t*)pl->keys_b.ptr, pl->err.ptr,
                       check_in_degs, s),
           "degrees");
+  // while od/idg are degrees: the wedge count W (Sec. 4.4's work measure)
+  // and the first rank whose block boundaries are stored
+  unsigned long long* d_wedges = (unsigned long long*)(pl->err.ptr + 6);
+  HIP_TRY(launch_degree_stats(pl->od.ptr, pl->idg.ptr, n, eff_bound_min_deg(opt), d_wedges, pl->err.ptr + 1, s),
+          "degree statistics");
   HIP_TRY(scan_u32(pl->od.ptr, pl->orow.ptr, (uint64_t)n, pl->partial.ptr, s), "scan out-degrees");
   HIP_TRY(scan_u32(pl->idg.ptr, pl->irow.ptr, (uint64_t)n, pl->partial.ptr, s), "scan in-degrees");
   HIP_TRY(pl->stage.ensure(64), "pinned alloc");
@@ -917,23 +1634,28 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   HIP_TRY(hipMemcpyAsync(&mm[0], pl->orow.ptr + n, 4, hipMemcpyDeviceToHost, s), "D2H m");
   HIP_TRY(hipMemcpyAsync(&mm[1], pl->irow.ptr + n, 4, hipMemcpyDeviceToHost, s), "D2H m");
   HIP_TRY(hipMemcpyAsync(&mm[2], pl->err.ptr, 4, hipMemcpyDeviceToHost, s), "D2H err");
+  HIP_TRY(hipMemcpyAsync(&mm[4], d_wedges, 8, hipMemcpyDeviceToHost, s), "D2H wedges");
+  HIP_TRY(hipMemcpyAsync(&mm[3], pl->err.ptr + 1, 4, hipMemcpyDeviceToHost, s), "D2H short rows");
   HIP_TRY(hipStreamSynchronize(s), "sync");
   if (mm[2]) return decode_device_err(mm[2]);
+  pl->rT = (int64_t)mm[3];
+  uint64_t wedges = 0;
+  std::memcpy(&wedges, &mm[4], 8);
   const uint64_t m = mm[0];
   if (m > mmax || mm[1] != mm[0]) return fail(BBTC_EINVAL, "input is not symmetric");
   pl->m = (int64_t)m;
   // + 4: the counting kernels read out-rows in aligned 16-byte blocks
   HIP_TRY(pl->ocol.ensure((size_t)m + 4), "alloc ocol");
-  HIP_TRY(pl->icol.ensure((size_t)m), "alloc icol");
+  HIP_TRY(pl->icol.ensure((size_t)m + 4), "alloc icol");
   // od/idg are consumed (scanned): their first entries become the huge rows'
   // fill cursors (zeroed by launch_fill)
-  HIP_TRY(launch_fill(rowptr, rp64, col, n, pl->perm.ptr, pl->orow.ptr, pl->irow.ptr, pl->ocol.ptr, pl->icol.ptr,
+  HIP_TRY(launch_fill(rowptr, rp64, col, n, whole_rows(n, nnz), pl->perm.ptr, pl->orow.ptr, pl->irow.ptr, pl->ocol.ptr, pl->icol.ptr,
                       pl->longrows.ptr, pl->err.ptr + 4, pl->hugerows.ptr, pl->err.ptr + 5,
                       (const uint32_t*)pl->keys_b.ptr, pl->od.ptr, pl->idg.ptr, s),
           "fill");
   // ---- cut vector (Sec. 4.1): it needs only orow ----
   int32_t p = opt.p;
-  if (p == 0) {  // p near the average degree (Sec. 7.2)
+  if (p == 0) {  // p near the average degree (Sec. 7.3)
     double avg = 2.0 * (double)m / (double)n;
     p = (int32_t)std::lround(avg);
     p = std::max(1, std::min<int32_t>(p, (int32_t)std::min<int64_t>(n, 256)));
@@ -973,45 +1695,47 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   HIP_TRY(hipEventSynchronize(pl->ev_cuts), "sync");
   pl->h_cuts.assign((const int32_t*)pl->cstage.ptr, (const int32_t*)pl->cstage.ptr + p + 1);
 
-  // ---- block row index (out side, on s after the out-row sort) and active
-  // columns (in side, on side[2] after the in-row grouping) ----
+  // ---- block row index (out side, on s after the out-row sort) and the
+  // block-major in side (on side[2] after the in-row grouping) ----
   const int64_t nb = (int64_t)p * (p + 1) / 2;
   std::vector<int32_t> chunk0((size_t)p + 1);
-  std::vector<uint64_t> ccbase((size_t)p + 1), botp((size_t)p + 1), tbotp((size_t)p + 1);
+  std::vector<uint64_t> ccbase((size_t)p + 1), botp((size_t)p + 1);
   int64_t nch = 0;
-  uint64_t cc = 0, bp = 0, tp = 0;
+  uint64_t cc = 0, bp = 0;
   for (int32_t a = 0; a < p; ++a) {
     const int64_t va = pl->h_cuts[a + 1] - pl->h_cuts[a];
     const int64_t ca = (va + kPrepRows - 1) / kPrepRows;
+    // stored rows of part a: max(c_a, rT) .. c_{a+1}-1
+    const int64_t sa = std::max<int64_t>(0, pl->h_cuts[a + 1] - std::max<int64_t>(pl->h_cuts[a], pl->rT));
     chunk0[a] = (int32_t)nch;
     ccbase[a] = cc;
     botp[a] = bp;
-    tbotp[a] = tp;
     nch += ca;
     cc += (uint64_t)(a + 1) * (uint64_t)ca;
-    bp += (uint64_t)(p - a + 1) * (uint64_t)va;
-    tp += (uint64_t)(a + 2) * (uint64_t)va;
+    bp += (uint64_t)(p - a + 1) * (uint64_t)sa;
   }
   chunk0[p] = (int32_t)nch;
   ccbase[p] = cc;
   botp[p] = bp;
-  tbotp[p] = tp;
   pl->ccount = (int64_t)cc;
   const size_t w8 = sizeof(uint64_t) * (size_t)(p + 1), wb = sizeof(unsigned long long) * (size_t)nb;
-  const size_t o_cb = align16(sizeof(int32_t) * (size_t)(p + 1)), o_hd = align16(o_cb + 3 * w8);
+  const size_t o_cb = align16(sizeof(int32_t) * (size_t)(p + 1)), o_hd = align16(o_cb + 2 * w8);
   HIP_TRY(pl->blk.ensure(o_hd + 16 + 3 * wb), "alloc");
   pl->chunk0 = (int32_t*)pl->blk.ptr;
   pl->ccbase = (uint64_t*)(pl->blk.ptr + o_cb);
   pl->botp = pl->ccbase + (p + 1);
-  pl->tbotp = pl->botp + (p + 1);
   pl->head = (uint32_t*)(pl->blk.ptr + o_hd);
   pl->bnnz = (unsigned long long*)(pl->blk.ptr + o_hd + 16);
   pl->bnzr = pl->bnnz + nb;
   pl->bnzc = pl->bnzr + nb;
   HIP_TRY(pl->bot.ensure((size_t)bp), "alloc block row index");
-  HIP_TRY(pl->tbot.ensure((size_t)tp), "alloc block column index");
-  HIP_TRY(pl->ccnt.ensure((size_t)cc + 1), "alloc");
-  HIP_TRY(pl->ccoff.ensure((size_t)cc + 1), "alloc");
+  HIP_TRY(pl->ccnt.ensure(2 * ((size_t)cc + 1)), "alloc");   // column counts, then entry counts
+  HIP_TRY(pl->ccoff.ensure(2 * ((size_t)cc + 1)), "alloc");  // their scans
+  HIP_TRY(pl->aoff.ensure((size_t)m + 1), "alloc in-slice offsets");
+  HIP_TRY(pl->asrc.ensure((size_t)m), "alloc");
+  HIP_TRY(pl->icolb.ensure((size_t)m), "alloc block-major in side");
+  uint32_t* ecnt = pl->ccnt.ptr + cc + 1;
+  uint32_t* ecoff = pl->ccoff.ptr + cc + 1;
   if (pl->partial.cap < scan_partial_entries(cc)) HIP_TRY(pl->partial.ensure(scan_partial_entries(cc) + 4096), "alloc");
   {  // the index tables through the pinned stage, one copy (the D2H below is ordered after it on s;
      // the stage is sized for that D2H too, so it is not reallocated under this copy)
@@ -1020,13 +1744,15 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
     std::memcpy(st, chunk0.data(), sizeof(int32_t) * (p + 1));
     std::memcpy(st + o_cb, ccbase.data(), w8);
     std::memcpy(st + o_cb + w8, botp.data(), w8);
-    std::memcpy(st + o_cb + 2 * w8, tbotp.data(), w8);
     HIP_TRY(hipMemcpyAsync(pl->blk.ptr, st, o_hd, hipMemcpyHostToDevice, s), "H2D");
   }
   HIP_TRY(hipMemsetAsync(pl->head, 0, 16 + 3 * wb, s), "memset");  // counters and block statistics
   BlockBuild bb;
+  std::memset(&bb, 0, sizeof(bb));
   bb.p = p;
+  bb.rT = (int32_t)pl->rT;
   bb.nchunks = (int32_t)nch;
+  bb.chunk_base = 0;
   bb.cuts = pl->cuts.ptr;
   bb.chunk0 = pl->chunk0;
   bb.ccbase = pl->ccbase;
@@ -1036,15 +1762,19 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   bb.bot = pl->bot.ptr;
   bb.irow = pl->irow.ptr;
   bb.icol = pl->icol.ptr;
-  bb.tbotp = pl->tbotp;
-  bb.tbot = pl->tbot.ptr;
   bb.bnnz = pl->bnnz;
   bb.bnzr = pl->bnzr;
   bb.bnzc = pl->bnzc;
   bb.ccnt = pl->ccnt.ptr;
+  bb.ecnt = ecnt;
   bb.dmax_block = pl->head + 1;
   bb.ccoff = pl->ccoff.ptr;
+  bb.ecoff = ecoff;
   bb.acol = pl->acol.ptr;
+  bb.aoff = pl->aoff.ptr;
+  bb.asrc = pl->asrc.ptr;
+  bb.ebase = 0;
+  bb.xbase = 0;
   pl->split = kHubSplit;
   const uint64_t hcap = m / kHubSplit + 1;
   HIP_TRY(pl->heavy.ensure((size_t)hcap), "alloc");
@@ -1055,139 +1785,19 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   // out side on s, in side on side[2] once the tables are there, at once
   HIP_TRY(hipEventRecord(pl->ev_fork, s), "event");
   HIP_TRY(hipStreamWaitEvent(si, pl->ev_fork, 0), "wait");
-  HIP_TRY(launch_tbot(bb, si), "block column index");
-  HIP_TRY(launch_bot(bb, s), "block row index");
+  HIP_TRY(launch_acount(bb, (int)nch, si), "active-column counts");
+  HIP_TRY(launch_bot(bb, (int)nch, s), "block row index");
   HIP_TRY(hipEventRecord(pl->ev_join[2], si), "event");
   HIP_TRY(hipStreamWaitEvent(s, pl->ev_join[2], 0), "wait");
-  HIP_TRY(scan_u32(pl->ccnt.ptr, pl->ccoff.ptr, cc, pl->partial.ptr, s), "scan chunk counters");
-  HIP_TRY(launch_acol(bb, s), "active columns");
-  uint32_t hd[2] = {0, 0};
-  uint32_t nheavy = 0;
-  {  // block statistics through the pinned stage, one copy: [nheavy, dmax x2, -] then bnnz, bnzr, bnzc
-    HIP_TRY(pl->stage.ensure(16 + 3 * wb), "pinned alloc");
-    char* st = pl->stage.ptr;
-    const uint32_t* sc = (const uint32_t*)st;
-    const unsigned long long* sb = (const unsigned long long*)(st + 16);
-    HIP_TRY(hipMemcpyAsync(st, pl->head, 16 + 3 * wb, hipMemcpyDeviceToHost, s), "D2H");
-    HIP_TRY(hipStreamSynchronize(s), "sync");
-    nheavy = sc[0];
-    hd[0] = sc[1];
-    hd[1] = sc[2];
-    pl->h_nnz.assign(sb, sb + nb);
-    pl->h_nzr.assign(sb + nb, sb + 2 * nb);
-    pl->h_nzc.assign(sb + 2 * nb, sb + 3 * nb);
-  }
-  if (nheavy > hcap) return fail(BBTC_EDEVICE, "hub column list overflow");
-  pl->h_heavy.resize(nheavy);
-  if (nheavy) {
-    HIP_TRY(pl->stage.ensure(sizeof(HeavyCol) * nheavy), "pinned alloc");
-    HIP_TRY(hipMemcpyAsync(pl->stage.ptr, pl->heavy.ptr, sizeof(HeavyCol) * nheavy, hipMemcpyDeviceToHost, s), "D2H");
-    HIP_TRY(hipStreamSynchronize(s), "sync");
-    std::memcpy(pl->h_heavy.data(), pl->stage.ptr, sizeof(HeavyCol) * nheavy);
-  }
-
-  // ---- tasks (Alg. 4) and work items ----
-  std::vector<uint64_t> acp((size_t)nb + 1);
-  acp[0] = 0;
-  for (int64_t b = 0; b < nb; ++b) acp[b + 1] = acp[b] + (uint64_t)pl->h_nzc[b];
-  compose_tasks(pl);
-  // the persistent launch reads the per-XCD queues, the plain one the plan order
-  const bool queued = opt.mode == BBTC_MODE_PERSISTENT;
-  if (queued) {
-    bbtc_status qst = compose_queues(pl);
-    if (qst != BBTC_OK) return qst;
-  } else {
-    compose_plan_order(pl);
-  }
-  const int64_t nt = (int64_t)pl->h_tasks.size();
-  HIP_TRY(pl->acp.ensure((size_t)nb + 1), "alloc");
-  HIP_TRY(pl->tasks.ensure((size_t)nt), "alloc tasks");
-  HIP_TRY((queued ? pl->xitems : pl->items).ensure(pl->nitems), "alloc items");
-  HIP_TRY(pl->cursor.ensure(kMaxQueues), "alloc");
-  {  // through the pinned stage; the final synchronisation below covers these copies
-    const size_t wa = sizeof(uint64_t) * (size_t)(nb + 1), wt = sizeof(DevTask) * (size_t)nt;
-    // persistent launches: the work items are written on the device from
-    // runs of task items (a few per task) instead of being uploaded
-    const size_t nr = queued ? pl->h_runs.size() : 0, nh = queued ? pl->h_heavy.size() : 0;
-    const size_t o_runs = 0, o_ti = align16(o_runs + sizeof(ItemRun) * nr),
-                 o_hs = align16(o_ti + sizeof(TaskItems) * (size_t)nt),
-                 o_hr = align16(o_hs + sizeof(uint32_t) * (size_t)(nb + 1)),
-                 o_hc = align16(o_hr + sizeof(HeavyCol) * nh), we = align16(o_hc + sizeof(uint32_t) * nh);
-    const size_t e0 = align16(wa + wt);
-    HIP_TRY(pl->stage.ensure(e0 + (queued ? we : 0)), "pinned alloc");
-    char* st = pl->stage.ptr;
-    std::memcpy(st, acp.data(), wa);
-    std::memcpy(st + wa, pl->h_dtasks.data(), wt);
-    HIP_TRY(hipMemcpyAsync(pl->acp.ptr, st, wa, hipMemcpyHostToDevice, s), "H2D");
-    HIP_TRY(hipMemcpyAsync(pl->tasks.ptr, st + wa, wt, hipMemcpyHostToDevice, s), "H2D");
-    if (queued && pl->nitems) {
-      char* e = st + e0;
-      std::memcpy(e + o_runs, pl->h_runs.data(), sizeof(ItemRun) * nr);
-      TaskItems* ti = (TaskItems*)(e + o_ti);
-      for (int64_t q = 0; q < nt; ++q) {
-        const bbtc_task& t = pl->h_tasks[q];
-        const int64_t cid = col_block_id(t.i, t.j);
-        ti[q] = TaskItems{pl->h_nhub[q], pl->h_nper[q], (uint32_t)pl->h_nzc[cid], (uint32_t)cid};
-      }
-      uint32_t* hs = (uint32_t*)(e + o_hs);
-      for (int64_t b = 0; b <= nb; ++b) hs[b] = (uint32_t)pl->h_hstart[b];
-      std::memcpy(e + o_hr, pl->h_heavy.data(), sizeof(HeavyCol) * nh);
-      uint32_t* hc = (uint32_t*)(e + o_hc);  // first chunk number of each record within its block
-      for (int64_t b = 0; b < nb; ++b) {
-        uint32_t c = 0;
-        for (int64_t r = pl->h_hstart[b]; r < pl->h_hstart[b + 1]; ++r) {
-          hc[r] = c;
-          c += (pl->h_heavy[r].cnt + kHubChunk - 1) / kHubChunk;
-        }
-      }
-      HIP_TRY(pl->emit.ensure(we), "alloc");
-      HIP_TRY(hipMemcpyAsync(pl->emit.ptr, e, we, hipMemcpyHostToDevice, s), "H2D");
-      const char* d = pl->emit.ptr;
-      HIP_TRY(launch_emit_items((const ItemRun*)(d + o_runs), (int32_t)nr, (const TaskItems*)(d + o_ti),
-                                (const uint32_t*)(d + o_hs), (const HeavyCol*)(d + o_hr), (const uint32_t*)(d + o_hc),
-                                kHubChunk, pl->xitems.ptr, (uint32_t)pl->nitems, s),
-              "emit work items");
-    }
-  }
-  if (pl->nitems && !queued)
-    HIP_TRY(hipMemcpyAsync(pl->items.ptr, pl->h_items.data(), sizeof(DevItem) * pl->h_items.size(),
-                           hipMemcpyHostToDevice, s),
-            "H2D");
-  HIP_TRY(hipStreamSynchronize(s), "sync");
-
-  // ---- statistics (Sec. 4.4 quantities and the byte model) ----
-  bbtc_stats& st = pl->stats;
-  std::memset(&st, 0, sizeof(st));
-  st.n = n;
-  st.m = (int64_t)m;
-  st.p = p;
-  st.ntasks = nt;
-  st.work_tasks = (int64_t)pl->h_work.size();
-  st.nitems = (int64_t)pl->nitems;
-  for (auto v : pl->h_nnz) st.m_max = std::max<int64_t>(st.m_max, v);
-  st.m_avg = 2.0 * (double)m / ((double)p * (double)(p + 1));
-  st.lambda = st.m_avg > 0 ? (double)st.m_max / st.m_avg : 0.0;
-  st.d_max_block = hd[0];
-  st.d_max = hd[1];
-  st.c = st.d_max_block > 0 ? (double)st.d_max / (double)st.d_max_block : 0.0;
-  st.wedges = -1;
-  st.bytes_colidx = 4 * (int64_t)(p + 2) * (int64_t)m;
-  int64_t rowidx = 0;
-  for (const auto& t : pl->h_tasks)
-    rowidx += 12 * (pl->h_nzr[block_id(p, t.i, t.j)] + pl->h_nzr[block_id(p, t.j, t.k)] +
-                    pl->h_nzr[block_id(p, t.i, t.k)]);
-  st.bytes_rowidx = rowidx;
-  st.bytes_total = st.bytes_colidx + st.bytes_rowidx + 8 * nt;
-  st.footprint = (int64_t)pl->footprint();
-  if (opt.device_budget_bytes > 0 && st.footprint > opt.device_budget_bytes) {
-    bbtc_status sst = stream_setup(pl, s);
-    if (sst != BBTC_OK) return sst;
-    st.footprint = (int64_t)pl->footprint();
-  }
-  st.partition_ms =
-      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  pl->ready = true;
-  return BBTC_OK;
+  HIP_TRY(scan_u32(pl->ccnt.ptr, pl->ccoff.ptr, cc, pl->partial.ptr, s), "scan column counters");
+  HIP_TRY(scan_u32(ecnt, ecoff, cc, pl->partial.ptr, s), "scan entry counters");
+  HIP_TRY(launch_acol(bb, (int)nch, s), "active columns");
+  // aoff[number of active columns] = m closes the last slice; then the slices
+  HIP_TRY(launch_set_at(pl->aoff.ptr, pl->ccoff.ptr + cc, (uint32_t)m, s), "in-slice sentinel");
+  HIP_TRY(launch_icolb(pl->aoff.ptr, pl->asrc.ptr, pl->icol.ptr, pl->icolb.ptr, pl->ccoff.ptr + cc, (uint64_t)m,
+                       pl->split, pl->heavy.ptr, 0, pl->head, (uint32_t)hcap, 0, s),
+          "block-major in side");
+  return finish_partition(pl, s, m, wedges, hcap, false, t0);
 }
 
 // State of multi-plan launches: device copies of the plan contexts (each
@@ -1268,6 +1878,160 @@ bbtc_status count_multi_impl(bbtc_plan* const* plans, int32_t nplans, hipStream_
   }
   HIP_TRY(hipEventRecord(S.done, s), "event");
   S.used = true;
+  return BBTC_OK;
+}
+
+// ------------------------------------------------------------ hybrid execution
+// Sec. 5 (Alg. 5-7): the tasks are in non-increasing order of their estimate;
+// the GPU takes heavy tasks from the front, host threads light ones from the
+// back, towards each other, and the host threads never go below the cut-off.
+// Here the GPU's share is counted by the persistent kernel over contiguous
+// task ranges (plan-order items are contiguous per task): first the tasks
+// below the cut-off, then, in competition with the host threads, half of
+// what is left at a time.  The host threads claim one task at a time from the
+// back and count it with the Intersect form (cpu_count_task) over host
+// copies of the plan's tables.  The host threads' tasks form the tail
+// [back, |T|); their counts are copied into the per-task output at the end.
+bbtc_status hybrid_prepare(bbtc_plan* pl, hipStream_t s) {
+  auto& h = pl->hy;
+  if (h.ready) return BBTC_OK;
+  const int64_t n = pl->n, m = pl->m, p = pl->p, nb = p * (p + 1) / 2, nt = (int64_t)pl->h_tasks.size();
+  if (!pl->plan_order_items) {
+    compose_plan_order(pl);
+    HIP_TRY(pl->items.ensure(pl->nitems), "alloc items");
+    if (pl->nitems)
+      HIP_TRY(hipMemcpyAsync(pl->items.ptr, pl->h_items.data(), sizeof(DevItem) * pl->nitems, hipMemcpyHostToDevice, s),
+              "H2D");
+    pl->plan_order_items = true;
+  }
+  h.istart.assign((size_t)nt + 1, 0);
+  for (int64_t q = 0; q < nt; ++q)
+    h.istart[q + 1] = h.istart[q] + (pl->h_tasks[q].kind == BBTC_TASK_WORK ? (int64_t)pl->h_nitem[q] : 0);
+  h.botp.resize(p + 1);
+  h.acp.resize(nb + 1);
+  h.orow.resize(n + 1);
+  HIP_TRY(hipMemcpyAsync(h.botp.data(), pl->botp, 8 * (p + 1), hipMemcpyDeviceToHost, s), "D2H");
+  HIP_TRY(hipMemcpyAsync(h.acp.data(), pl->acp.ptr, 8 * (nb + 1), hipMemcpyDeviceToHost, s), "D2H");
+  HIP_TRY(hipMemcpyAsync(h.orow.data(), pl->orow.ptr, 4 * (n + 1), hipMemcpyDeviceToHost, s), "D2H");
+  HIP_TRY(hipStreamSynchronize(s), "sync");
+  h.ocol.resize(m + 1);
+  h.icolb.resize(m + 1);
+  h.bot.resize(h.botp[p] + 1);
+  h.acol.resize(h.acp[nb] + 1);
+  h.aoff.resize(h.acp[nb] + 1);
+  HIP_TRY(hipMemcpyAsync(h.ocol.data(), pl->ocol.ptr, 4 * m, hipMemcpyDeviceToHost, s), "D2H");
+  HIP_TRY(hipMemcpyAsync(h.icolb.data(), pl->icolb.ptr, 4 * m, hipMemcpyDeviceToHost, s), "D2H");
+  HIP_TRY(hipMemcpyAsync(h.bot.data(), pl->bot.ptr, 4 * h.botp[p], hipMemcpyDeviceToHost, s), "D2H");
+  HIP_TRY(hipMemcpyAsync(h.acol.data(), pl->acol.ptr, 4 * h.acp[nb], hipMemcpyDeviceToHost, s), "D2H");
+  HIP_TRY(hipMemcpyAsync(h.aoff.data(), pl->aoff.ptr, 4 * (h.acp[nb] + 1), hipMemcpyDeviceToHost, s), "D2H");
+  HIP_TRY(hipStreamSynchronize(s), "sync");
+  h.t = HostTables{(int32_t)p, (int32_t)pl->rT, pl->h_cuts.data(), h.orow.data(), h.ocol.data(), h.botp.data(),
+                   h.bot.data(), h.acp.data(), h.acol.data(), h.aoff.data(), h.icolb.data()};
+  h.ready = true;
+  return BBTC_OK;
+}
+
+bbtc_status count_hybrid_impl(bbtc_plan* pl, hipStream_t s, uint64_t* d_per_task, uint64_t* d_total,
+                              int32_t nthreads, int64_t cutoff, bbtc_hybrid_stats* out) {
+  const auto t0 = std::chrono::steady_clock::now();
+  bbtc_status st = hybrid_prepare(pl, s);
+  if (st != BBTC_OK) return st;
+  const auto& h = pl->hy;
+  const int64_t nt = (int64_t)pl->h_tasks.size();
+  if (cutoff < 0) cutoff = nt / 2;
+  cutoff = std::min<int64_t>(cutoff, nt);
+  if (nthreads <= 0) nthreads = (int32_t)std::max(1u, std::thread::hardware_concurrency() - 1);
+  HIP_TRY(launch_reset(d_per_task, nt, d_total, pl->cursor.ptr, s), "reset");
+  const int grid_max = pl->blocks_per_cu * pl->ncu;
+  int64_t launches = 0;
+  // one persistent launch over the items of tasks [a, b) (plan order)
+  auto gpu_range = [&](int64_t a, int64_t b) -> bbtc_status {
+    const int64_t i0 = h.istart[a], i1 = h.istart[b];
+    if (i1 <= i0) return BBTC_OK;
+    CountParams cp;
+    std::memset(&cp, 0, sizeof(cp));
+    cp.one = plan_ctx(pl, d_per_task, d_total);
+    cp.one.items = pl->items.ptr;
+    cp.items = pl->items.ptr + i0;
+    cp.nitems = (uint32_t)(i1 - i0);
+    cp.cursor = pl->cursor.ptr;
+    one_queue(cp);
+    HIP_TRY(launch_reset(nullptr, 0, nullptr, pl->cursor.ptr, s), "cursor");
+    HIP_TRY(launch_count_persistent(cp, (int)std::min<int64_t>(grid_max, cp.nitems), false, s), "count");
+    ++launches;
+    return BBTC_OK;
+  };
+  std::mutex mu;
+  int64_t front = cutoff, back = nt;  // GPU claims [front, ...), host threads back-1, back-2, ...
+  std::vector<uint64_t> cpu_per((size_t)nt, 0);
+  std::vector<double> busy((size_t)nthreads, 0.0);
+  std::vector<int64_t> done((size_t)nthreads, 0);
+  auto worker = [&](int w) {
+    const auto b0 = std::chrono::steady_clock::now();
+    for (;;) {
+      int64_t t;
+      {
+        std::lock_guard<std::mutex> lock(mu);
+        if (back <= front || back <= cutoff) break;
+        t = --back;
+      }
+      const bbtc_task& tk = pl->h_tasks[t];
+      if (tk.kind != BBTC_TASK_WORK) continue;
+      cpu_per[t] = cpu_count_task(h.t, tk.i, tk.j, tk.k);
+      done[w]++;
+    }
+    busy[w] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - b0).count();
+  };
+  // the tasks below the cut-off go to the GPU at once; the host threads start
+  // from the back meanwhile
+  if ((st = gpu_range(0, cutoff)) != BBTC_OK) return st;
+  std::vector<std::thread> th;
+  for (int w = 0; w < nthreads; ++w) th.emplace_back(worker, w);
+  hipError_t herr = hipSuccess;
+  for (;;) {
+    herr = hipStreamSynchronize(s);
+    if (herr != hipSuccess) break;
+    int64_t a, b;
+    {
+      std::lock_guard<std::mutex> lock(mu);
+      if (front >= back) break;
+      a = front;
+      b = front + std::max<int64_t>(1, (back - front) / 2);
+      front = b;
+    }
+    if ((st = gpu_range(a, b)) != BBTC_OK) break;
+  }
+  if (herr == hipSuccess && st == BBTC_OK) herr = hipStreamSynchronize(s);
+  {  // no new claims; the host threads finish their current task
+    std::lock_guard<std::mutex> lock(mu);
+    front = std::max(front, back);
+  }
+  for (auto& x : th) x.join();
+  if (herr != hipSuccess) return hip_fail(herr, "hybrid count");
+  if (st != BBTC_OK) return st;
+  // the host threads' tasks are the tail [back, nt): their counts into the
+  // per-task output, their sum onto the total
+  uint64_t cpu_sum = 0;
+  for (int64_t t = back; t < nt; ++t) cpu_sum += cpu_per[t];
+  if (back < nt) {
+    HIP_TRY(hipMemcpyAsync(d_per_task + back, cpu_per.data() + back, sizeof(uint64_t) * (size_t)(nt - back),
+                           hipMemcpyHostToDevice, s),
+            "H2D");
+    HIP_TRY(launch_add_u64(d_total, cpu_sum, s), "add host counts");
+  }
+  HIP_TRY(hipStreamSynchronize(s), "sync");
+  if (out) {
+    std::memset(out, 0, sizeof(*out));
+    for (int64_t t = 0; t < nt; ++t)
+      if (pl->h_tasks[t].kind == BBTC_TASK_WORK) (t < back ? out->gpu_tasks : out->cpu_tasks)++;
+    out->gpu_launches = launches;
+    out->cpu_threads = nthreads;
+    out->cutoff = cutoff;
+    out->split = back;
+    for (double b : busy) out->cpu_ms = std::max(out->cpu_ms, b);
+    out->cpu_triangles = cpu_sum;
+    out->total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
   return BBTC_OK;
 }
 
@@ -1393,6 +2157,23 @@ bbtc_status bbtc_count_multi(bbtc_plan* const* plans, int32_t nplans, void* stre
   }
 }
 
+bbtc_status bbtc_count_hybrid(bbtc_plan* pl, void* stream, uint64_t* d_per_task, uint64_t* d_total,
+                              int32_t cpu_threads, int64_t cutoff, bbtc_hybrid_stats* stats) {
+  g_err.clear();
+  if (!pl || !pl->ready) return fail(BBTC_ESTATE, "plan is not ready");
+  if (pl->streamed) return fail(BBTC_ESTATE, "a streamed (over-budget) plan is counted by bbtc_count only");
+  if (!d_total || (!d_per_task && !pl->h_tasks.empty())) return fail(BBTC_EINVAL, "null output");
+  if (cpu_threads < 0 || cpu_threads > 1024) return fail(BBTC_EINVAL, "cpu_threads must be in [0, 1024]");
+  if (cutoff < -1 || cutoff > (int64_t)pl->h_tasks.size()) return fail(BBTC_EINVAL, "cutoff must be in [-1, |T|]");
+  try {
+    return count_hybrid_impl(pl, (hipStream_t)stream, d_per_task, d_total, cpu_threads, cutoff, stats);
+  } catch (const std::bad_alloc&) {
+    return fail(BBTC_ENOMEM, "host allocation failed");
+  } catch (const std::system_error&) {
+    return fail(BBTC_EDEVICE, "could not start host threads");
+  }
+}
+
 bbtc_status bbtc_autotune(const bbtc_csr* g, const bbtc_options* base, int32_t reps, void* stream, bbtc_options* out,
                           double* best_ms) {
   g_err.clear();
@@ -1461,7 +2242,7 @@ bbtc_status bbtc_autotune(const bbtc_csr* g, const bbtc_options* base, int32_t r
       if (st != BBTC_OK) break;
       if (ms < best) { best = ms; best_opt = o; }
     }
-    for (int32_t wm : {32, 64, 256, 1024, 4096}) {
+    for (int32_t wm : {16, 32, 64, 128, 256, 512}) {  // 512: the whole wavefront stage
       if (st != BBTC_OK) break;
       bbtc_options o = best_opt;
       o.wave_min = wm;
@@ -1488,6 +2269,104 @@ bbtc_status bbtc_autotune(const bbtc_csr* g, const bbtc_options* base, int32_t r
   if (st != BBTC_OK) return fail(st, msg);
   *out = best_opt;
   if (best_ms) *best_ms = best;
+  return BBTC_OK;
+}
+
+bbtc_status bbtc_check_tables(const bbtc_tables* t) {
+  g_err.clear();
+  if (!t || !t->cuts || !t->orow || !t->botp || !t->acp) return fail(BBTC_EINVAL, "null argument");
+  if (t->n < 1 || t->n > 2147483647LL || t->p < 1 || t->p > kMaxP || t->m < 0) return fail(BBTC_EINVAL, "bad sizes");
+  TableView v{t->n, t->m, t->p, t->rT, t->cuts, t->orow, t->ocol, t->botp, t->bot, t->acp, t->acol, t->aoff, t->icolb};
+  try {
+    const std::string msg = check_tables(v);
+    if (!msg.empty()) return fail(BBTC_EINVAL, msg);
+  } catch (const std::bad_alloc&) {
+    return fail(BBTC_ENOMEM, "host allocation failed");
+  }
+  return BBTC_OK;
+}
+
+bbtc_status bbtc_plan_verify(const bbtc_plan* pl, void* stream) {
+  g_err.clear();
+  if (!pl || !pl->ready) return fail(BBTC_ESTATE, "plan is not ready");
+  hipStream_t s = (hipStream_t)stream;
+  try {
+    const int64_t n = pl->n, m = pl->m, p = pl->p, nb = p * (p + 1) / 2;
+    std::vector<uint32_t> orow(n + 1), bot, aoff;
+    std::vector<int32_t> ocol(m + 1), icolb(m + 1), acol;
+    std::vector<uint64_t> botp(p + 1), acp(nb + 1);
+    HIP_TRY(hipMemcpyAsync(orow.data(), pl->orow.ptr, 4 * (n + 1), hipMemcpyDeviceToHost, s), "D2H");
+    HIP_TRY(hipMemcpyAsync(botp.data(), pl->botp, 8 * (p + 1), hipMemcpyDeviceToHost, s), "D2H");
+    HIP_TRY(hipMemcpyAsync(acp.data(), pl->acp.ptr, 8 * (nb + 1), hipMemcpyDeviceToHost, s), "D2H");
+    HIP_TRY(hipStreamSynchronize(s), "sync");
+    bot.resize(botp[p] + 1);
+    acol.resize(acp[nb] + 1);
+    aoff.resize(acp[nb] + 1);
+    if (pl->streamed) {
+      std::memcpy(ocol.data(), pl->h_ocol, 4 * m);
+      std::memcpy(icolb.data(), pl->h_icolb, 4 * m);
+      std::memcpy(bot.data(), pl->h_bot, 4 * botp[p]);
+      std::memcpy(acol.data(), pl->h_acol, 4 * acp[nb]);
+      std::memcpy(aoff.data(), pl->h_aoff, 4 * (acp[nb] + 1));
+    } else {
+      HIP_TRY(hipMemcpyAsync(ocol.data(), pl->ocol.ptr, 4 * m, hipMemcpyDeviceToHost, s), "D2H");
+      HIP_TRY(hipMemcpyAsync(icolb.data(), pl->icolb.ptr, 4 * m, hipMemcpyDeviceToHost, s), "D2H");
+      HIP_TRY(hipMemcpyAsync(bot.data(), pl->bot.ptr, 4 * botp[p], hipMemcpyDeviceToHost, s), "D2H");
+      HIP_TRY(hipMemcpyAsync(acol.data(), pl->acol.ptr, 4 * acp[nb], hipMemcpyDeviceToHost, s), "D2H");
+      HIP_TRY(hipMemcpyAsync(aoff.data(), pl->aoff.ptr, 4 * (acp[nb] + 1), hipMemcpyDeviceToHost, s), "D2H");
+    }
+    // work items, in the layout the count launches read
+    const bool queued = pl->opt.mode == BBTC_MODE_PERSISTENT && !pl->streamed;
+    std::vector<DevItem> items(pl->nitems + 1);
+    HIP_TRY(hipMemcpyAsync(items.data(), queued ? pl->xitems.ptr : pl->items.ptr, sizeof(DevItem) * pl->nitems,
+                           hipMemcpyDeviceToHost, s),
+            "D2H");
+    HIP_TRY(hipStreamSynchronize(s), "sync");
+    TableView v{n, m, (int32_t)p, (int32_t)pl->rT, pl->h_cuts.data(), orow.data(), ocol.data(), botp.data(),
+                bot.data(), acp.data(), acol.data(), aoff.data(), icolb.data()};
+    std::string msg = check_tables(v);
+    if (!msg.empty()) return fail(BBTC_EDEVICE, "plan tables: " + msg);
+    // every item within its task's active columns or hub in-slice; the
+    // column items of a task cover its columns exactly once, hub columns
+    // (in-slices longer than the split) excluded
+    const int64_t nt = (int64_t)pl->h_tasks.size();
+    std::vector<std::vector<std::pair<int64_t, int64_t>>> cover((size_t)nt);
+    for (size_t q = 0; q < pl->nitems; ++q) {
+      const DevItem& it = items[q];
+      const std::string at = "work item " + std::to_string(q);
+      if (it.task < 0 || it.task >= nt) return fail(BBTC_EDEVICE, at + ": bad task");
+      const bbtc_task& tk = pl->h_tasks[it.task];
+      if (tk.kind != BBTC_TASK_WORK) return fail(BBTC_EDEVICE, at + " of an empty task");
+      const int64_t cid = col_block_id(tk.i, tk.j);
+      if (it.lo >= it.hi) return fail(BBTC_EDEVICE, at + " is empty");
+      if (it.v < 0) {
+        if ((int64_t)it.hi > (int64_t)(acp[cid + 1] - acp[cid])) return fail(BBTC_EDEVICE, at + " past the active columns");
+        cover[it.task].push_back({(int64_t)it.lo, (int64_t)it.hi});
+      } else {
+        const uint64_t x = (uint64_t)it.v;
+        if (x < acp[cid] || x >= acp[cid + 1]) return fail(BBTC_EDEVICE, at + ": hub column outside block (i,j)");
+        const uint32_t len = aoff[x + 1] - aoff[x];
+        if (len <= pl->split || it.hi > len) return fail(BBTC_EDEVICE, at + ": not a hub or past its in-slice");
+      }
+    }
+    for (int64_t q = 0; q < nt; ++q) {
+      auto& c = cover[q];
+      std::sort(c.begin(), c.end());
+      int64_t next = 0;
+      for (const auto& r : c) {
+        if (r.first != next) return fail(BBTC_EDEVICE, "work items of task " + std::to_string(q) + " leave a gap");
+        next = r.second;
+      }
+      const bbtc_task& tk = pl->h_tasks[q];
+      if (tk.kind == BBTC_TASK_WORK) {
+        const int64_t cid = col_block_id(tk.i, tk.j);
+        if (next != (int64_t)(acp[cid + 1] - acp[cid]))
+          return fail(BBTC_EDEVICE, "work items of task " + std::to_string(q) + " miss columns");
+      }
+    }
+  } catch (const std::bad_alloc&) {
+    return fail(BBTC_ENOMEM, "host allocation failed");
+  }
   return BBTC_OK;
 }
 
@@ -1523,6 +2402,7 @@ bbtc_status bbtc_plan_stats(const bbtc_plan* pl, bbtc_stats* out) {
   out->stripe_slots = (int64_t)pl->slots.size();
   out->stripe_bytes = (int64_t)pl->slot_bytes;
   out->stripe_uploads = pl->copies;
+  out->resident_bytes = pl->streamed ? pl->resident_bytes : pl->stats.footprint;
   return BBTC_OK;
 }
 

@@ -24,58 +24,69 @@ struct DevTask {
 // One unit of persistent work of plan-order task `task` of its plan:
 //   v < 0 : entries [lo, hi) of the active-column list of block (i,j);
 //   v >= 0: in-neighbours [lo, hi) (relative to the start of the in-slice)
-//           of one column v of G_ij whose in-slice is longer than the split
-//           threshold; such columns are skipped by column-range items.
+//           of the hub column with absolute active-column index v (its
+//           in-slice is longer than the split threshold); such columns are
+//           skipped by column-range items.
 struct DevItem {
   int32_t task;
   uint32_t lo, hi;
   int32_t v;
 };
 
-// A column v of block (a,b) whose in-slice from V_a has more than `split`
-// entries (collected while the active columns are written).
+// An active column of block (a,b) whose in-slice from V_a has more than
+// `split` entries (collected while the active columns are written).
 struct HeavyCol {
   uint32_t cid;  // column-major block id of (a,b)
-  int32_t v;
+  uint32_t x;    // absolute active-column index (acol[x] is the vertex)
   uint32_t cnt;  // in-slice length
 };
 
 // Device view of the blocked graph (stripe layout plus block row index).
-//   ocol  : oriented CSR columns in rank space, every row ascending.
-//   bot   : for a row u in part a, (p-a+1) absolute positions in ocol; entry
-//           b-a is the first position of N(G,u) whose column is >= cuts[b],
-//           so N(G_ab,u) = ocol[bot[b-a] .. bot[b-a+1]).  Rows of part a start
-//           at element botp[a] and are (p-a+1) entries apart.
-//   icol  : in-rows: for each rank v, the ranks u < v adjacent to v, ascending.
-//   tbot  : for v in part b, (b+2) positions in icol; entry a is the first
-//           in-neighbour of rank >= cuts[a], so the in-slice of v in block
-//           (a,b) is icol[tbot[a] .. tbot[a+1]).  Part b starts at tbotp[b].
+//   orow/ocol : oriented CSR in rank space, every row ascending; ocol is
+//           16-byte aligned on absolute positions and padded by four
+//           entries, so rows can be read in aligned 16-byte blocks.
+//   rT    : ranks below rT (undirected degree <= the plan's bound_min_deg,
+//           a prefix of the degree order) have no stored boundaries; their
+//           block slices are found by scanning the row.  A part a stores
+//           rows max(cuts[a], rT) .. cuts[a+1]-1.
+//   bot   : for a stored row u in part a, (p-a+1) absolute positions in
+//           ocol; entry b-a is the first position of N(G,u) whose column is
+//           >= cuts[b], so N(G_ab,u) = ocol[bot[b-a] .. bot[b-a+1]).  Stored
+//           rows of part a start at element botp[a], (p-a+1) entries apart.
 //   acol  : per block (a,b), the columns v of V_b with a non-empty in-slice
-//           in increasing order, starting at acp[cid(a,b)], cid = b(b+1)/2+a.
+//           in increasing order, starting at acp[cid(a,b)], cid = b(b+1)/2+a
+//           (column-major block order).
+//   aoff/icol : the in-side, block-major: active column x's in-slice (its
+//           in-neighbours in V_a) is icol[aoff[x] .. aoff[x+1]).
 struct GraphView {
   int32_t p;
   uint32_t m;  // entries of ocol (and of icol)
+  int32_t rT;
+  int32_t pad;
+  const uint32_t* orow;
   // Streamed launches cover the tasks of one block pair (gi, gj) and read the
-  // rows of parts gi and gj from cached stripes: colI/colJ/icolJ are shifted
-  // so that the absolute positions held in bot/tbot index them, botI/botJ and
-  // tbotJ point at the first block-boundary row of the part.  gi < 0: the
-  // whole graph is resident and the fields below are used instead.
+  // out-rows of parts gi and gj from cached stripes and block (gi,gj)'s
+  // in-side from a staged copy: colI/colJ are shifted so that the absolute
+  // positions of orow and bot index them, botI/botJ point at the first stored
+  // boundary row of the part, acolJ/aoffJ/icolJ are shifted so that absolute
+  // active-column indices and entry positions index them.  gi < 0: the whole
+  // graph is resident and the fields below are used instead.
   int32_t gi, gj;
   const int32_t* colI;
   const int32_t* colJ;
-  const int32_t* icolJ;
   const uint32_t* botI;
   const uint32_t* botJ;
-  const uint32_t* tbotJ;
+  const int32_t* acolJ;
+  const uint32_t* aoffJ;
+  const int32_t* icolJ;
   const int32_t* cuts;
   const uint64_t* botp;
   const uint32_t* bot;
   const int32_t* ocol;
-  const uint64_t* tbotp;
-  const uint32_t* tbot;
-  const int32_t* icol;
-  const uint64_t* acp;   // column-major block order
+  const uint64_t* acp;
   const int32_t* acol;
+  const uint32_t* aoff;
+  const int32_t* icol;
 };
 
 // Everything a counting kernel needs about one plan.
@@ -125,6 +136,15 @@ hipError_t launch_validate(const void* rowptr, int rp64, const int32_t* colidx, 
                            int symmetric, uint32_t* err, uint32_t* list, uint32_t* nlist, uint32_t* hlist,
                            uint32_t* nhlist, uint32_t* hpref, hipStream_t s);
 hipError_t launch_degkey(const void* rowptr, int rp64, int64_t n, int idbits, uint64_t* keys, hipStream_t s);
+// A range of input rows for the degree and fill passes: local row x is
+// original vertex x0 + x; the graph has ntot vertices; the range's row
+// pointers lie in [nnz_lo, nnz_hi]; the fill writes only rows whose rank is
+// in [rlo, rhi).
+struct RowRange {
+  int64_t x0, ntot, nnz_lo, nnz_hi;
+  int32_t rlo, rhi;
+};
+inline RowRange whole_rows(int64_t n, int64_t nnz) { return RowRange{0, n, 0, nnz, 0, (int32_t)n}; }
 // Stable sort of keys[0..count) by their bits [lo, hi) (LSD, 8 bits a pass);
 // the result ends in *result (one of a or b).  hist/partial are scratch
 // sized by radix_hist_entries() and scan_partial_entries().
@@ -135,11 +155,13 @@ hipError_t radix_sort_u64(uint64_t* a, uint64_t* b, uint64_t count, int lo, int 
 // out[0..count] = exclusive scan of in[0..count), out[count] = total.
 hipError_t scan_u32(const uint32_t* in, uint32_t* out, uint64_t count, uint32_t* partial, hipStream_t s);
 hipError_t launch_perm(const uint64_t* keys, int64_t n, int idbits, int32_t* order, int32_t* perm, hipStream_t s);
-hipError_t launch_degs(const void* rowptr, int rp64, const int32_t* colidx, int64_t n, int64_t nnz,
+// od == nullptr: list the long and huge rows only (no degrees).
+hipError_t launch_degs(const void* rowptr, int rp64, const int32_t* colidx, int64_t n, const RowRange& rr,
                        const int32_t* perm, uint32_t* od, uint32_t* idg, uint32_t* list, uint32_t* nlist,
                        uint32_t* hlist, uint32_t* nhlist, uint32_t* hpref, uint32_t* err, int check, hipStream_t s);
 // cur_o/cur_i: zeroed fill cursors of the huge rows (indexed by position in hlist).
-hipError_t launch_fill(const void* rowptr, int rp64, const int32_t* colidx, int64_t n, const int32_t* perm,
+hipError_t launch_fill(const void* rowptr, int rp64, const int32_t* colidx, int64_t n, const RowRange& rr,
+                       const int32_t* perm,
                        const uint32_t* orow, const uint32_t* irow, int32_t* ocol, int32_t* icol, const uint32_t* list,
                        const uint32_t* nlist, const uint32_t* hlist, const uint32_t* nhlist, const uint32_t* hpref,
                        uint32_t* cur_o, uint32_t* cur_i, hipStream_t s);
@@ -156,11 +178,17 @@ hipError_t launch_inrows_sort(const uint32_t* rp, int32_t* col, int64_t nrows, u
                               uint32_t* hugerows, uint32_t* q, hipStream_t s);
 hipError_t launch_inrows_group(const uint32_t* rp, int32_t* col, const uint32_t* longrows, const uint32_t* hugerows,
                                const uint32_t* q, int32_t* scratch, const int32_t* cuts, int32_t p, hipStream_t s);
+// *wedges += sum over r < n of od[r] * idg[r] (the wedge count W) and
+// *nshort += #{r : od[r] + idg[r] <= max_deg} (max_deg < 0: none).
+hipError_t launch_degree_stats(const uint32_t* od, const uint32_t* idg, int64_t n, int64_t max_deg,
+                               unsigned long long* wedges, uint32_t* nshort, hipStream_t s);
 hipError_t launch_cuts(const uint32_t* orow, int64_t n, int32_t p, int mode, int32_t* cuts, hipStream_t s);
 
 struct BlockBuild {
   int32_t p;
+  int32_t rT;                // first rank with stored boundaries (see GraphView)
   int32_t nchunks;           // total row chunks (kPrepRows rows each, within one part)
+  int32_t chunk_base;        // chunk of the launch's first workgroup
   const int32_t* cuts;       // p+1
   const int32_t* chunk0;     // p+1: first chunk of each part
   const uint64_t* ccbase;    // p+1: start of part b's chunk counters (in side)
@@ -168,32 +196,47 @@ struct BlockBuild {
   const int32_t* ocol;
   const uint64_t* botp;
   uint32_t* bot;
-  const uint32_t* irow;
+  const uint32_t* irow;       // in-rows (grouped by part) of the columns built
   const int32_t* icol;
-  const uint64_t* tbotp;
-  uint32_t* tbot;
   unsigned long long* bnnz;  // nb, row-major block order
   unsigned long long* bnzr;  // nb, row-major block order
   unsigned long long* bnzc;  // nb, column-major block order cid(a,b) = b(b+1)/2 + a
   uint32_t* ccnt;            // per (part b, block (a,b), chunk) active-column counts
+  uint32_t* ecnt;            // the same for their in-slice entries
   uint32_t* dmax_block;      // [0] longest block slice, [1] longest oriented row
-  const uint32_t* ccoff;     // exclusive scan of ccnt
-  int32_t* acol;             // active columns, column-major block order
+  const uint32_t* ccoff;     // exclusive scans of ccnt and ecnt (indexed like them)
+  const uint32_t* ecoff;
+  int32_t* acol;             // active columns, column-major block order (indexed by ccoff)
+  uint32_t* aoff;            // their in-slice offsets in the block-major in-side
+  uint32_t* asrc;            // their in-slice starts in icol
+  uint32_t ebase;            // block-major entry offset of the first column built
+  uint64_t xbase;            // absolute active-column index of acol[0]
   uint32_t split;            // in-slice length above which a column is recorded as heavy
   HeavyCol* heavy;           // room for m/split + 1 records
   uint32_t* nheavy;
   uint32_t heavy_cap;
 };
-hipError_t launch_bot(const BlockBuild& bb, hipStream_t s);
-hipError_t launch_tbot(const BlockBuild& bb, hipStream_t s);
-hipError_t launch_acol(const BlockBuild& bb, hipStream_t s);
+// Chunks [bb.chunk_base, bb.chunk_base + nchunks) of the parts.
+hipError_t launch_bot(const BlockBuild& bb, int nchunks, hipStream_t s);
+hipError_t launch_acount(const BlockBuild& bb, int nchunks, hipStream_t s);
+hipError_t launch_acol(const BlockBuild& bb, int nchunks, hipStream_t s);
+// Copies the in-slices of *ncolsp active columns (at most ncols_max;
+// aoff/asrc/icol/icolb shifted as in k_acol) into the block-major in side;
+// hub records [h0, min(*h1p, cap)) (absolute indices, xbase = absolute index
+// of aoff[0]) by one workgroup each.
+hipError_t launch_icolb(const uint32_t* aoff, const uint32_t* asrc, const int32_t* icol, int32_t* icolb,
+                        const uint32_t* ncolsp, uint64_t ncols_max, uint32_t split, const HeavyCol* heavy, uint32_t h0,
+                        const uint32_t* h1p, uint32_t cap, uint64_t xbase, hipStream_t s);
+// arr[*idx] = value (one thread).
+hipError_t launch_set_at(uint32_t* arr, const uint32_t* idx, uint32_t value, hipStream_t s);
 
 // Work-item emission on the device.  A run sends items [r0, r0 + n) of
 // plan-order task `task` to out[dst, dst + n); the runs are sorted by dst,
 // non-empty, and tile [0, nitems).  Item r of a task is its r-th hub chunk
 // while r < nhub (chunks of `chunk` in-neighbours, hub records of block cid
 // in hrec[hstart[cid], hstart[cid+1]) with their first chunk numbers in
-// hcum), else active columns [(r - nhub) * nper, +nper) clipped to cols.
+// hcum; the item's v is the record's active-column index), else active
+// columns [(r - nhub) * nper, +nper) clipped to cols.
 struct ItemRun {
   int32_t task;
   uint32_t r0, n, dst;
@@ -213,5 +256,7 @@ hipError_t launch_count_persistent(const CountParams& cp, int grid, bool multi, 
 // Items [first, first+count) of cp.items, one workgroup each.
 hipError_t launch_count_items(const CountParams& cp, uint32_t first, uint32_t count, hipStream_t s);
 int count_persistent_blocks_per_cu();
+// *x += v (one thread).
+hipError_t launch_add_u64(uint64_t* x, uint64_t v, hipStream_t s);
 
 }  // namespace bbtc

@@ -70,18 +70,21 @@ struct CountLds {
 };
 
 struct TaskCtx {
-  int32_t ci, cj, ck, ck1;
+  int32_t ci, ci1, cj, ck, ck1;
   int32_t kb;               // bitmap origin: ck rounded down to a multiple of 32
   int32_t i, dk, dkj;       // i, k-i, k-j
+  int32_t si, sj;           // first rows of parts i and j with stored boundaries
   uint32_t stri, strj;      // out-side row strides of parts i and j
-  uint32_t tstrj;           // in-side row stride of part j
-  const uint32_t* boti;
-  const uint32_t* botj;
-  const uint32_t* tbotj;
+  const uint32_t* boti;     // stored row si of part i
+  const uint32_t* botj;     // stored row sj of part j
+  const uint32_t* orow;
   const int32_t* coli;      // out-rows of part i (N(G_ik,u)), absolute positions
   const int32_t* colj;      // out-rows of part j (N(G_jk,v)), absolute positions
-  const int32_t* icolj;     // in-rows of part j, absolute positions
-  const int32_t* ac;        // active columns of block (i,j)
+  const int32_t* icolj;     // block-major in-side, absolute positions
+  const int32_t* acb;       // active columns, absolute indices
+  const uint32_t* aob;      // their in-slice offsets, absolute indices
+  const int32_t* ac;        // active columns of block (i,j): acb + acp[cid(i,j)]
+  const uint32_t* ao;       // their in-slice offsets (one more entry than columns)
 };
 
 // Read through the constant address space: with a wave-uniform address this
@@ -102,6 +105,7 @@ __device__ __forceinline__ T ld_const(const T* p) {
 __device__ __forceinline__ TaskCtx make_ctx(const GraphView& g, const DevTask& t) {
   TaskCtx c;
   c.ci = ld_const(g.cuts + t.i);
+  c.ci1 = ld_const(g.cuts + t.i + 1);
   c.cj = ld_const(g.cuts + t.j);
   c.ck = ld_const(g.cuts + t.k);
   c.ck1 = ld_const(g.cuts + t.k + 1);
@@ -111,27 +115,86 @@ __device__ __forceinline__ TaskCtx make_ctx(const GraphView& g, const DevTask& t
   c.dkj = t.k - t.j;
   c.stri = (uint32_t)(g.p - t.i + 1);
   c.strj = (uint32_t)(g.p - t.j + 1);
-  c.tstrj = (uint32_t)(t.j + 2);
+  c.si = max(c.ci, g.rT);
+  c.sj = max(c.cj, g.rT);
+  c.orow = g.orow;
   if (g.gi >= 0) {  // streamed: the launch's parts come from cached stripes
     c.boti = g.botI;
     c.botj = g.botJ;
-    c.tbotj = g.tbotJ;
     c.coli = g.colI;
     c.colj = g.colJ;
     c.icolj = g.icolJ;
+    c.acb = g.acolJ;
+    c.aob = g.aoffJ;
   } else {
     c.boti = g.bot + ld_const(g.botp + t.i);
     c.botj = g.bot + ld_const(g.botp + t.j);
-    c.tbotj = g.tbot + ld_const(g.tbotp + t.j);
     c.coli = g.ocol;
     c.colj = g.ocol;
     c.icolj = g.icol;
+    c.acb = g.acol;
+    c.aob = g.aoff;
   }
-  c.ac = g.acol + ld_const(g.acp + col_block_id(t.i, t.j));
+  const uint64_t a0 = ld_const(g.acp + col_block_id(t.i, t.j));
+  c.ac = c.acb + a0;
+  c.ao = c.aob + a0;
   return c;
 }
 
 __device__ __forceinline__ uint32_t hash_slot(uint32_t w, int hbits) { return (w * 0x9E3779B1u) >> (32 - hbits); }
+
+// Rows up to this many entries are scanned for their block slices, longer
+// ones searched.
+constexpr uint32_t kScanRow = 32;
+
+// First position in col[rb, re) whose entry is >= key, for a row in which
+// "entry < key" holds on a prefix (sorted out-rows; in-rows grouped by part,
+// with key a cut point).
+__device__ __forceinline__ uint32_t first_at_least(const int32_t* __restrict__ col, uint32_t rb, uint32_t re,
+                                                   int32_t key) {
+  while (rb < re) {
+    const uint32_t mid = (rb + re) >> 1;
+    if (col[mid] < key) rb = mid + 1; else re = mid;
+  }
+  return rb;
+}
+
+// The slice [a0, a1) of the row col[rb, re) with entries in [k0, k1), for a
+// row without stored boundaries.  Short rows are counted in aligned 16-byte
+// blocks (positions outside the row are masked; the arrays are aligned on
+// absolute positions and padded), longer ones searched.
+__device__ __forceinline__ void row_slice(const int32_t* __restrict__ col, uint32_t rb, uint32_t re, int32_t k0,
+                                          int32_t k1, uint32_t& a0, uint32_t& a1) {
+  if (re - rb <= kScanRow) {
+    uint32_t n0 = 0, n1 = 0;
+    for (uint32_t q = rb & ~3u; q < re; q += 4) {
+      const int4 v = *reinterpret_cast<const int4*>(col + q);
+      const int32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (uint32_t t = 0; t < 4; ++t) {
+        const bool in = q + t >= rb && q + t < re;
+        n0 += (in && w[t] < k0) ? 1u : 0u;
+        n1 += (in && w[t] < k1) ? 1u : 0u;
+      }
+    }
+    a0 = rb + n0;
+    a1 = rb + n1;
+  } else {
+    a0 = first_at_least(col, rb, re, k0);
+    a1 = first_at_least(col, a0, re, k1);
+  }
+}
+
+// N(G_ik,u) = coli[a0, a1) for an in-neighbour u in V_i.
+__device__ __forceinline__ void out_slice_i(const TaskCtx& c, int32_t u, uint32_t& a0, uint32_t& a1) {
+  if (u >= c.si) {
+    const uint32_t* ur = c.boti + (uint64_t)(u - c.si) * c.stri;
+    a0 = ur[c.dk];
+    a1 = ur[c.dk + 1];
+  } else {
+    row_slice(c.coli, c.orow[u], c.orow[u + 1], c.ck, c.ck1, a0, a1);
+  }
+}
 
 // Largest k in [a, b) with off[k] <= x (off non-decreasing, off[a] <= x).
 __device__ __forceinline__ uint32_t owner_of(const uint32_t* off, uint32_t a, uint32_t b, uint32_t x) {
@@ -344,12 +407,7 @@ __device__ uint64_t probe_flat(const TaskCtx& c, uint32_t i0, uint32_t i1, const
   for (uint32_t eb = i0; eb < i1; eb += kWave) {
     const uint32_t e = eb + l;
     uint32_t a0 = 0, a1 = 0;
-    if (e < i1) {
-      const int32_t u = icol[e];
-      const uint32_t* ur = c.boti + (uint64_t)(u - c.ci) * c.stri;
-      a0 = ur[c.dk];
-      a1 = ur[c.dk + 1];
-    }
+    if (e < i1) out_slice_i(c, icol[e], a0, a1);
     const uint32_t nseg = seg_count_w(a0, a1);
     const uint32_t inc = wave_incl_scan_u32(nseg);
     const uint32_t tot = last_lane(inc);
@@ -391,15 +449,22 @@ __device__ uint64_t wave_col(const TaskCtx& c, uint32_t i0, uint32_t i1, uint32_
 
 // Bounds of active column x of block (i,j): N(G_jk,v) = col[c0,c1) and the
 // in-slice [i0,i1) of v in V_i.
+// N(G_jk,v) = colj[c0, c1) for a column v in V_j.
+__device__ __forceinline__ void out_slice_j(const TaskCtx& c, int32_t v, uint32_t& c0, uint32_t& c1) {
+  if (v >= c.sj) {
+    const uint32_t* vr = c.botj + (uint64_t)(v - c.sj) * c.strj;
+    c0 = vr[c.dkj];
+    c1 = vr[c.dkj + 1];
+  } else {
+    row_slice(c.colj, c.orow[v], c.orow[v + 1], c.ck, c.ck1, c0, c1);
+  }
+}
+
 __device__ __forceinline__ void col_bounds(const TaskCtx& c, uint32_t x, uint32_t& c0, uint32_t& c1, uint32_t& i0,
                                            uint32_t& i1) {
-  const int32_t v = c.ac[x];
-  const uint32_t* vr = c.botj + (uint64_t)(v - c.cj) * c.strj;
-  const uint32_t* tr = c.tbotj + (uint64_t)(v - c.cj) * c.tstrj;
-  c0 = vr[c.dkj];
-  c1 = vr[c.dkj + 1];
-  i0 = tr[c.i];
-  i1 = tr[c.i + 1];
+  out_slice_j(c, c.ac[x], c0, c1);
+  i0 = c.ao[x];
+  i1 = c.ao[x + 1];
 }
 
 // col_bounds for a column index that is the same on every lane: scalar loads.
@@ -407,12 +472,17 @@ __device__ __forceinline__ void col_bounds_uniform(const TaskCtx& c, uint32_t x,
                                                    uint32_t& i0, uint32_t& i1) {
   x = __builtin_amdgcn_readfirstlane(x);
   const int32_t v = ld_const(c.ac + x);
-  const uint32_t* vr = c.botj + (uint64_t)(v - c.cj) * c.strj;
-  const uint32_t* tr = c.tbotj + (uint64_t)(v - c.cj) * c.tstrj;
-  c0 = ld_const(vr + c.dkj);
-  c1 = ld_const(vr + c.dkj + 1);
-  i0 = ld_const(tr + c.i);
-  i1 = ld_const(tr + c.i + 1);
+  i0 = ld_const(c.ao + x);
+  i1 = ld_const(c.ao + x + 1);
+  if (v >= c.sj) {
+    const uint32_t* vr = c.botj + (uint64_t)(v - c.sj) * c.strj;
+    c0 = ld_const(vr + c.dkj);
+    c1 = ld_const(vr + c.dkj + 1);
+  } else {
+    out_slice_j(c, v, c0, c1);
+    c0 = __builtin_amdgcn_readfirstlane(c0);
+    c1 = __builtin_amdgcn_readfirstlane(c1);
+  }
 }
 
 // Packed short columns [a0, b0) of a pass (bounds in c0s/i0s, prefixes in
@@ -458,10 +528,7 @@ __device__ uint64_t short_cols(const TaskCtx& c, CountLds& s, uint32_t a0, uint3
       uint32_t u0 = 0, u1 = 0, k = a;
       if (e < iend) {
         k = owner_of(s.ioff, a, b, e);
-        const int32_t u = icol[s.i0s[k] + (e - s.ioff[k])];
-        const uint32_t* ur = c.boti + (uint64_t)(u - c.ci) * c.stri;
-        u0 = ur[c.dk];
-        u1 = ur[c.dk + 1];
+        out_slice_i(c, icol[s.i0s[k] + (e - s.ioff[k])], u0, u1);
       }
       const uint32_t nseg = seg_count_w(u0, u1);
       const uint32_t inc = wave_incl_scan_u32(nseg);
@@ -620,13 +687,16 @@ __device__ uint64_t group_col(const PlanCtx& cp, const TaskCtx& c, uint32_t i0, 
   return cnt;
 }
 
-// One chunk [lo, hi) of the in-slice of hub column v, by the whole workgroup.
-__device__ uint64_t hub_chunk(const PlanCtx& cp, const TaskCtx& c, int32_t v, uint32_t lo, uint32_t hi,
+// One chunk [lo, hi) of the in-slice of the hub column with absolute
+// active-column index x, by the whole workgroup.
+__device__ uint64_t hub_chunk(const PlanCtx& cp, const TaskCtx& c, uint32_t x, uint32_t lo, uint32_t hi,
                               CountLds& s) {
-  const uint32_t* vr = c.botj + (uint64_t)(v - c.cj) * c.strj;
-  const uint32_t c0 = ld_const(vr + c.dkj), c1 = ld_const(vr + c.dkj + 1);
-  const uint32_t* tr = c.tbotj + (uint64_t)(v - c.cj) * c.tstrj;
-  const uint32_t ib = ld_const(tr + c.i), ie = ld_const(tr + c.i + 1);
+  const int32_t v = ld_const(c.acb + x);
+  const uint32_t ib = ld_const(c.aob + x), ie = ld_const(c.aob + x + 1);
+  uint32_t c0, c1;
+  out_slice_j(c, v, c0, c1);
+  c0 = __builtin_amdgcn_readfirstlane(c0);
+  c1 = __builtin_amdgcn_readfirstlane(c1);
   const uint32_t i0 = min(ib + lo, ie), i1 = min(ib + hi, ie);
   if (c1 <= c0 || i1 <= i0) return 0;  // uniform across the workgroup
   return group_col(cp, c, i0, i1, c0, c1, s);
@@ -651,7 +721,7 @@ __device__ __forceinline__ uint64_t run_item(const PlanCtx& pc, const DevItem& i
   const DevTask t = ld_const(pc.tasks + item.task);
   const TaskCtx c = make_ctx(pc.g, t);
   *out = t.out;
-  if (item.v >= 0) return hub_chunk(pc, c, item.v, item.lo, item.hi, s);
+  if (item.v >= 0) return hub_chunk(pc, c, (uint32_t)item.v, item.lo, item.hi, s);
   return process_cols(pc, c, item.lo, item.hi, s);
 }
 
@@ -736,7 +806,16 @@ __global__ __launch_bounds__(kThreads) void k_reset_multi(const PlanCtx* ctxs, i
   if (blockIdx.x == 0 && threadIdx.x < kMaxQueues) cursor[threadIdx.x] = 0;
 }
 
+__global__ void k_add_u64(uint64_t* __restrict__ x, uint64_t v) {
+  if (threadIdx.x == 0) *x += v;
+}
+
 }  // namespace
+
+hipError_t launch_add_u64(uint64_t* x, uint64_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_u64, dim3(1), dim3(64), 0, s, x, v);
+  return hipGetLastError();
+}
 
 hipError_t launch_reset_multi(const PlanCtx* ctxs, int32_t nplans, uint32_t* cursor, hipStream_t s) {
   hipLaunchKernelGGL(k_reset_multi, dim3(nplans > 0 ? (nplans < 1024 ? nplans : 1024) : 1), dim3(kThreads), 0, s, ctxs,

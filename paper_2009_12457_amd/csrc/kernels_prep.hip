@@ -339,9 +339,16 @@ __device__ __forceinline__ uint64_t run_mask(uint64_t heads, int l) {
   return upto & ~((1ull << first) - 1);
 }
 
+// Row kernels work on a range of the input rows: local row x is original
+// vertex rr.x0 + x (its rank perm[rr.x0 + x]), the row pointers passed in
+// start at that row and hold absolute positions, which index the column
+// pointer passed in (shifted when only the range's entries are resident).
+// Entries are checked against rr.ntot vertices and the row pointers against
+// [rr.nnz_lo, rr.nnz_hi].  With od == nullptr the degree pass only lists the
+// long and huge rows (for a later fill of the same range).
 template <typename RP>
 __global__ __launch_bounds__(kThreads) void k_degs_lane(const RP* __restrict__ rowptr,
-                                                        const int32_t* __restrict__ colidx, int64_t n, int64_t nnz,
+                                                        const int32_t* __restrict__ colidx, int64_t n, RowRange rr,
                                                         const int32_t* __restrict__ perm, uint32_t* __restrict__ od,
                                                         uint32_t* __restrict__ idg, uint32_t* list, uint32_t* nlist,
                                                         uint32_t* hlist, uint32_t* nhlist, uint32_t* err, int check) {
@@ -350,9 +357,10 @@ __global__ __launch_bounds__(kThreads) void k_degs_lane(const RP* __restrict__ r
   FlatRows& F = fr[threadIdx.x / kWave];
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  const bool count = od != nullptr;
   uint32_t bad = 0;
   if (check && blockIdx.x == 0 && threadIdx.x == 0) {
-    if ((int64_t)rowptr[0] != 0 || (int64_t)rowptr[n] != nnz) bad |= 8;
+    if ((int64_t)rowptr[0] != rr.nnz_lo || (int64_t)rowptr[n] != rr.nnz_hi) bad |= 8;
   }
   for (int64_t x0 = wave * kWave; x0 < n; x0 += nwaves * kWave) {  // uniform per wavefront
     const int64_t x = x0 + l;
@@ -360,20 +368,20 @@ __global__ __launch_bounds__(kThreads) void k_degs_lane(const RP* __restrict__ r
     int64_t b = 0, e = 0;
     bool mine = false;  // a lane row: counted by this group
     if (x < n) {
-      r = perm[x];
+      r = perm[rr.x0 + x];
       b = (int64_t)rowptr[x];
       e = (int64_t)rowptr[x + 1];
-      if (r >= 0 && r < n) {
-        if (check && (b < 0 || e < b || e > nnz)) {
+      if (r >= 0 && r < rr.ntot) {
+        if (check && (b < rr.nnz_lo || e < b || e > rr.nnz_hi)) {
           bad |= 8;
-          od[r] = idg[r] = 0;
+          if (count) od[r] = idg[r] = 0;
         } else if (e - b > kWaveRow) {
-          od[r] = idg[r] = 0;
+          if (count) od[r] = idg[r] = 0;
           hlist[atomicAdd(nhlist, 1u)] = (uint32_t)x;
         } else if (e - b > kLaneRow) {
           list[atomicAdd(nlist, 1u)] = (uint32_t)x;
         } else {
-          mine = true;
+          mine = count;
         }
       }
     }
@@ -395,7 +403,7 @@ __global__ __launch_bounds__(kThreads) void k_degs_lane(const RP* __restrict__ r
         const int64_t rb = F.beg[o], q = rb + (f - F.off[o]);
         const int32_t y = colidx[q];
         uint32_t fl = 0;
-        if (check) fl = entry_flags<RP>(colidx, n, x0 + o, rb, q, y);
+        if (check) fl = entry_flags<RP>(colidx, rr.ntot, rr.x0 + x0 + o, rb, q, y);
         bad |= fl;
         up = !(fl & 1) && perm[y] > F.rank[o];
       }
@@ -448,7 +456,7 @@ __device__ __forceinline__ uint32_t count_up(const int32_t* __restrict__ colidx,
 // wavefronts and added to od/idg, which k_degs_lane zeroed for them.
 template <typename RP>
 __global__ __launch_bounds__(kThreads) void k_degs_wave(const RP* __restrict__ rowptr,
-                                                        const int32_t* __restrict__ colidx, int64_t n,
+                                                        const int32_t* __restrict__ colidx, RowRange rr,
                                                         const int32_t* __restrict__ perm, uint32_t* __restrict__ od,
                                                         uint32_t* __restrict__ idg, const uint32_t* list,
                                                         const uint32_t* nlist, const uint32_t* hlist,
@@ -461,9 +469,10 @@ __global__ __launch_bounds__(kThreads) void k_degs_wave(const RP* __restrict__ r
   const int64_t cnt = *nlist;
   for (int64_t i = wave; i < cnt; i += nwaves) {
     const int64_t x = list[i];
-    const int32_t r = perm[x];
+    const int32_t r = perm[rr.x0 + x];
     const int64_t b = (int64_t)rowptr[x], e = (int64_t)rowptr[x + 1];
-    const uint32_t c = (uint32_t)wave_sum_u64(count_up<RP>(colidx, n, perm, x, r, b, b, e, check, &bad));
+    const uint32_t c =
+        (uint32_t)wave_sum_u64(count_up<RP>(colidx, rr.ntot, perm, rr.x0 + x, r, b, b, e, check, &bad));
     if (l == 0) {
       od[r] = c;
       idg[r] = (uint32_t)(e - b) - c;
@@ -475,9 +484,10 @@ __global__ __launch_bounds__(kThreads) void k_degs_wave(const RP* __restrict__ r
     uint32_t li;
     int64_t x, b, e;
     unit_of(rowptr, hlist, hpref, hcnt, u, &li, &x, &b, &e);
-    const int32_t r = perm[x];
+    const int32_t r = perm[rr.x0 + x];
     const int64_t rb = (int64_t)rowptr[x];
-    const uint32_t c = (uint32_t)wave_sum_u64(count_up<RP>(colidx, n, perm, x, r, rb, b, e, check, &bad));
+    const uint32_t c =
+        (uint32_t)wave_sum_u64(count_up<RP>(colidx, rr.ntot, perm, rr.x0 + x, r, rb, b, e, check, &bad));
     if (l == 0) {
       atomicAdd(&od[r], c);
       atomicAdd(&idg[r], (uint32_t)(e - b) - c);
@@ -488,10 +498,11 @@ __global__ __launch_bounds__(kThreads) void k_degs_wave(const RP* __restrict__ r
 
 // Scatters rank ids into the out- and in-rows (order within a row follows the
 // input row; rows are sorted afterwards).  Writes are bounded by the row
-// extents computed from the same predicate.
+// extents computed from the same predicate; a null ocol or icol skips that
+// side.
 template <typename RP>
 __global__ __launch_bounds__(kThreads) void k_fill_lane(const RP* __restrict__ rowptr,
-                                                        const int32_t* __restrict__ colidx, int64_t n,
+                                                        const int32_t* __restrict__ colidx, int64_t n, RowRange rr,
                                                         const int32_t* __restrict__ perm,
                                                         const uint32_t* __restrict__ orow,
                                                         const uint32_t* __restrict__ irow, int32_t* __restrict__ ocol,
@@ -508,10 +519,11 @@ __global__ __launch_bounds__(kThreads) void k_fill_lane(const RP* __restrict__ r
     int64_t b = 0, e = 0;
     bool mine = false;
     if (x < n) {
-      r = perm[x];
+      r = perm[rr.x0 + x];
       b = (int64_t)rowptr[x];
       e = (int64_t)rowptr[x + 1];
-      mine = r >= 0 && r < n && e - b >= 0 && e - b <= kLaneRow;  // listed rows: k_fill_wave
+      // listed rows: k_fill_wave; rows of ranks outside [rlo, rhi): not this pass
+      mine = r >= rr.rlo && r < rr.rhi && e - b >= 0 && e - b <= kLaneRow;
     }
     const uint32_t len = mine ? (uint32_t)(e - b) : 0u;
     const uint32_t inc = wave_incl_scan_u32(len);
@@ -542,10 +554,10 @@ __global__ __launch_bounds__(kThreads) void k_fill_lane(const RP* __restrict__ r
         const uint64_t before = run & ((1ull << l) - 1);  // lanes of my run below me
         if (up) {
           const uint32_t d = F.c0[o] + (uint32_t)__popcll(ups & before);
-          if (d < lim[w][0][o]) ocol[d] = ry;
+          if (ocol && d < lim[w][0][o]) ocol[d] = ry;
         } else {
           const uint32_t d = F.c1[o] + (uint32_t)__popcll(downs & before);
-          if (d < lim[w][1][o]) icol[d] = ry;
+          if (icol && d < lim[w][1][o]) icol[d] = ry;
         }
       }
       wave_sync();  // every lane has read the counters before the heads advance them
@@ -585,8 +597,8 @@ __device__ __forceinline__ void scatter_run(const int32_t* __restrict__ colidx, 
       const bool down = q < e && !up;
       const uint64_t mu = ballot(up), md = ballot(down);
       const uint32_t du = po + lanes_below(mu), dd = pi + lanes_below(md);
-      if (up && du < po_end) ocol[du] = ry[k];
-      if (down && dd < pi_end) icol[dd] = ry[k];
+      if (ocol && up && du < po_end) ocol[du] = ry[k];
+      if (icol && down && dd < pi_end) icol[dd] = ry[k];
       po += (uint32_t)__popcll(mu);
       pi += (uint32_t)__popcll(md);
     }
@@ -607,7 +619,7 @@ __global__ __launch_bounds__(kThreads) void k_zero2(uint32_t* __restrict__ a, ui
 // the result exact and deterministic.
 template <typename RP>
 __global__ __launch_bounds__(kThreads) void k_fill_wave(const RP* __restrict__ rowptr,
-                                                        const int32_t* __restrict__ colidx,
+                                                        const int32_t* __restrict__ colidx, RowRange rr,
                                                         const int32_t* __restrict__ perm,
                                                         const uint32_t* __restrict__ orow,
                                                         const uint32_t* __restrict__ irow, int32_t* __restrict__ ocol,
@@ -621,7 +633,8 @@ __global__ __launch_bounds__(kThreads) void k_fill_wave(const RP* __restrict__ r
   const int64_t cnt = *nlist;
   for (int64_t i = wave; i < cnt; i += nwaves) {
     const int64_t x = list[i];
-    const int32_t r = perm[x];
+    const int32_t r = perm[rr.x0 + x];
+    if (r < rr.rlo || r >= rr.rhi) continue;
     const int64_t b = (int64_t)rowptr[x], e = (int64_t)rowptr[x + 1];
     scatter_run(colidx, perm, r, b, e, orow[r], irow[r], orow[r + 1], irow[r + 1], ocol, icol);
   }
@@ -631,12 +644,13 @@ __global__ __launch_bounds__(kThreads) void k_fill_wave(const RP* __restrict__ r
     uint32_t li;
     int64_t x, b, e;
     unit_of(rowptr, hlist, hpref, hcnt, u, &li, &x, &b, &e);
-    const int32_t r = perm[x];
+    const int32_t r = perm[rr.x0 + x];
+    if (r < rr.rlo || r >= rr.rhi) continue;
     const uint32_t ob = orow[r], ib = irow[r];
     const uint32_t po_end = orow[r + 1], pi_end = irow[r + 1];
     uint32_t nb = 0;
     const uint32_t nu =
-        (uint32_t)wave_sum_u64(count_up<RP>(colidx, 0, perm, x, r, b, b, e, 0, &nb));
+        (uint32_t)wave_sum_u64(count_up<RP>(colidx, 0, perm, rr.x0 + x, r, b, b, e, 0, &nb));
     uint32_t po = 0, pi = 0;
     if (l == 0) {
       po = ob + atomicAdd(&cur_o[li], nu);
@@ -1033,15 +1047,17 @@ __device__ __forceinline__ uint32_t seek(const int32_t* __restrict__ col, uint32
   return ptr;
 }
 
-// Out side: the row of u in part a gets its block boundaries for b = a..p;
-// per block the entries, the non-empty rows and the longest slice are counted.
+// Out side: the row of u in part a gets its block boundaries for b = a..p
+// (written for stored rows, u >= rT, only); per block the entries, the
+// non-empty rows and the longest slice are counted for every row.
 __global__ __launch_bounds__(kThreads) void k_bot(BlockBuild bb) {
   __shared__ uint32_t s_nnz[kMaxP];
   __shared__ uint32_t s_nzr[kMaxP];
   __shared__ uint32_t s_dmax, s_dfull;
   const int32_t p = bb.p;
-  const int a = chunk_part(bb.chunk0, p, blockIdx.x);
-  const int lc = blockIdx.x - bb.chunk0[a];
+  const int chunk = (int)blockIdx.x + bb.chunk_base;
+  const int a = chunk_part(bb.chunk0, p, chunk);
+  const int lc = chunk - bb.chunk0[a];
   const int nb = p - a;  // blocks (a,a)..(a,p-1)
   for (int b = threadIdx.x; b < nb; b += kThreads) s_nnz[b] = s_nzr[b] = 0;
   if (threadIdx.x == 0) s_dmax = s_dfull = 0;
@@ -1050,12 +1066,13 @@ __global__ __launch_bounds__(kThreads) void k_bot(BlockBuild bb) {
   const int64_t u = ca + (int64_t)lc * kPrepRows + threadIdx.x;
   if (u < bb.cuts[a + 1]) {
     const uint32_t rb = bb.orow[u], re = bb.orow[u + 1];
-    uint32_t* out = bb.bot + bb.botp[a] + (uint64_t)(u - ca) * (uint64_t)(nb + 1);
-    out[0] = rb;
+    const int64_t sa = ca > bb.rT ? ca : (int64_t)bb.rT;  // first stored row of part a
+    uint32_t* out = u >= sa ? bb.bot + bb.botp[a] + (uint64_t)(u - sa) * (uint64_t)(nb + 1) : nullptr;
+    if (out) out[0] = rb;
     uint32_t ptr = rb, prev = rb, dmax = 0;
     for (int b = a + 1; b <= p; ++b) {
       ptr = (b == p) ? re : seek(bb.ocol, ptr, re, bb.cuts[b]);
-      out[b - a] = ptr;
+      if (out) out[b - a] = ptr;
       const uint32_t len = ptr - prev;
       if (len) {
         atomicAdd(&s_nnz[b - 1 - a], len);
@@ -1081,73 +1098,190 @@ __global__ __launch_bounds__(kThreads) void k_bot(BlockBuild bb) {
   }
 }
 
-// In side: the in-row of v in part b gets its boundaries for parts a = 0..b+1
-// (entry a = first in-neighbour of rank >= cuts[a]); per block (a,b) the
-// columns with a non-empty in-slice are counted, per chunk as well.
-__global__ __launch_bounds__(kThreads) void k_tbot(BlockBuild bb) {
+// ------------------------------------------------------------ in side
+// The in-side of the count is block-major: for block (a,b), in column-major
+// block order, its active columns (v in V_b with an in-neighbour in V_a,
+// ascending) in acol, and for active column x the in-slice of v from V_a at
+// icolb[aoff[x] .. aoff[x+1]) (the block G_ab in compressed-column form with
+// only its non-empty columns indexed).  Built from the in-rows (grouped by
+// part): k_acount counts, per block and chunk of columns, the active columns
+// and their entries; after two scans k_acol writes acol, aoff and the source
+// position of each slice (asrc), and lists the hub columns (slices longer
+// than `split`); k_icolb copies the slices.
+
+// The in-slice [lo, hi) of in-row v from part a, given lo (the slice of part
+// a starts where the one of part a-1 ended).
+__device__ __forceinline__ uint32_t in_slice_end(const BlockBuild& bb, uint32_t lo, uint32_t re, int a, int na) {
+  return (a + 1 == na) ? re : seek(bb.icol, lo, re, bb.cuts[a + 1]);
+}
+
+__global__ __launch_bounds__(kThreads) void k_acount(BlockBuild bb) {
   __shared__ uint32_t s_nzc[kMaxP];
+  __shared__ uint32_t s_ent[kMaxP];
   const int32_t p = bb.p;
-  const int b = chunk_part(bb.chunk0, p, blockIdx.x);
-  const int lc = blockIdx.x - bb.chunk0[b];
+  const int chunk = (int)blockIdx.x + bb.chunk_base;
+  const int b = chunk_part(bb.chunk0, p, chunk);
+  const int lc = chunk - bb.chunk0[b];
   const int nch = bb.chunk0[b + 1] - bb.chunk0[b];
   const int na = b + 1;  // blocks (0,b)..(b,b)
-  for (int a = threadIdx.x; a < na; a += kThreads) s_nzc[a] = 0;
+  for (int a = threadIdx.x; a < na; a += kThreads) s_nzc[a] = s_ent[a] = 0;
   __syncthreads();
   const int64_t cb = bb.cuts[b];
   const int64_t v = cb + (int64_t)lc * kPrepRows + threadIdx.x;
   if (v < bb.cuts[b + 1]) {
-    const uint32_t rb = bb.irow[v], re = bb.irow[v + 1];
-    uint32_t* out = bb.tbot + bb.tbotp[b] + (uint64_t)(v - cb) * (uint64_t)(na + 1);
-    out[0] = rb;
-    uint32_t ptr = rb, prev = rb;
-    for (int a = 1; a <= na; ++a) {
-      ptr = (a == na) ? re : seek(bb.icol, ptr, re, bb.cuts[a]);
-      out[a] = ptr;
-      if (ptr > prev) atomicAdd(&s_nzc[a - 1], 1u);
-      prev = ptr;
+    const uint32_t re = bb.irow[v + 1];
+    uint32_t lo = bb.irow[v];
+    for (int a = 0; a < na && lo < re; ++a) {
+      const uint32_t hi = in_slice_end(bb, lo, re, a, na);
+      if (hi > lo) {
+        atomicAdd(&s_nzc[a], 1u);
+        atomicAdd(&s_ent[a], hi - lo);
+      }
+      lo = hi;
     }
   }
   __syncthreads();
   const int64_t cid0 = (int64_t)b * (b + 1) / 2;
   for (int a = threadIdx.x; a < na; a += kThreads) {
     if (s_nzc[a]) atomicAdd(&bb.bnzc[cid0 + a], (unsigned long long)s_nzc[a]);
-    bb.ccnt[bb.ccbase[b] + (uint64_t)a * nch + lc] = s_nzc[a];
+    const uint64_t q = bb.ccbase[b] + (uint64_t)a * nch + lc;
+    bb.ccnt[q] = s_nzc[a];
+    bb.ecnt[q] = s_ent[a];
   }
 }
 
-// Writes, for every block (a,b), its columns v with a non-empty in-slice in
-// increasing order at the offsets given by the scanned chunk counters.
+// Writes, for every block (a,b), its active columns in increasing order at
+// the offsets of the scanned chunk counters (ccoff: columns, ecoff: entries);
+// positions are absolute in the plan's acol/aoff/icolb arrays (the arrays
+// passed in are shifted accordingly when only some columns are resident).
 __global__ __launch_bounds__(kThreads) void k_acol(BlockBuild bb) {
   __shared__ uint32_t lds[4];
   const int32_t p = bb.p;
-  const int b = chunk_part(bb.chunk0, p, blockIdx.x);
-  const int lc = blockIdx.x - bb.chunk0[b];
+  const int chunk = (int)blockIdx.x + bb.chunk_base;
+  const int b = chunk_part(bb.chunk0, p, chunk);
+  const int lc = chunk - bb.chunk0[b];
   const int nch = bb.chunk0[b + 1] - bb.chunk0[b];
   const int na = b + 1;
   const int64_t cb = bb.cuts[b];
   const int64_t v = cb + (int64_t)lc * kPrepRows + threadIdx.x;
   const bool valid = v < bb.cuts[b + 1];
-  const uint32_t* row = bb.tbot + bb.tbotp[b] + (uint64_t)(valid ? v - cb : 0) * (uint64_t)(na + 1);
-  uint32_t lo = valid ? row[0] : 0u;
+  const uint32_t re = valid ? bb.irow[v + 1] : 0u;
+  uint32_t lo = valid ? bb.irow[v] : 0u;
   for (int a = 0; a < na; ++a) {
-    const uint32_t hi = valid ? row[a + 1] : 0u;
-    const uint32_t f = (valid && hi > lo) ? 1u : 0u;
+    const uint32_t hi = (valid && lo < re) ? in_slice_end(bb, lo, re, a, na) : lo;
+    const uint32_t f = hi > lo ? 1u : 0u, len = hi - lo;
     uint32_t tot;
     const uint32_t off = block256_excl_scan<uint32_t>(f, lds, &tot);
+    const uint32_t eoff = block256_excl_scan<uint32_t>(len, lds, &tot);
     if (f) {
-      bb.acol[bb.ccoff[bb.ccbase[b] + (uint64_t)a * nch + lc] + off] = (int32_t)v;
-      if (bb.split && hi - lo > bb.split) {
+      const uint64_t q = bb.ccbase[b] + (uint64_t)a * nch + lc;
+      const uint64_t x = (uint64_t)bb.ccoff[q] + off;
+      bb.acol[x] = (int32_t)v;
+      bb.aoff[x] = bb.ebase + bb.ecoff[q] + eoff;
+      bb.asrc[x] = lo;
+      if (len > bb.split) {
         const uint32_t r = atomicAdd(bb.nheavy, 1u);
-        if (r < bb.heavy_cap) bb.heavy[r] = HeavyCol{(uint32_t)col_block_id(a, b), (int32_t)v, hi - lo};
+        if (r < bb.heavy_cap) bb.heavy[r] = HeavyCol{(uint32_t)col_block_id(a, b), (uint32_t)(bb.xbase + x), len};
       }
     }
     lo = hi;
   }
 }
 
+// Copies the in-slices of active columns [0, *ncolsp) (relative to the
+// arrays passed in) into icolb: 64 columns per wavefront, their entries
+// flattened over the lanes; slices longer than `split` are left to
+// k_icolb_heavy.
+__global__ __launch_bounds__(kThreads) void k_icolb(const uint32_t* __restrict__ aoff,
+                                                    const uint32_t* __restrict__ asrc,
+                                                    const int32_t* __restrict__ icol, int32_t* __restrict__ icolb,
+                                                    const uint32_t* __restrict__ ncolsp, uint32_t split) {
+  const uint64_t ncols = *ncolsp;
+  __shared__ uint32_t off[kThreads / kWave][kWave + 1];
+  __shared__ uint32_t src[kThreads / kWave][kWave];
+  __shared__ uint32_t dst[kThreads / kWave][kWave];
+  const int l = lane_id(), w = threadIdx.x / kWave;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  for (int64_t x0 = wave * kWave; x0 < (int64_t)ncols; x0 += nwaves * kWave) {  // uniform per wavefront
+    const int64_t x = x0 + l;
+    uint32_t len = 0, d0 = 0;
+    if (x < (int64_t)ncols) {
+      d0 = aoff[x];
+      len = aoff[x + 1] - d0;
+      if (len > split) len = 0;
+    }
+    const uint32_t inc = wave_incl_scan_u32(len);
+    const uint32_t tot = last_lane(inc);
+    off[w][l] = inc - len;
+    src[w][l] = len ? asrc[x] : 0u;
+    dst[w][l] = d0;
+    wave_sync();
+    for (uint32_t fb = 0; fb < tot; fb += kWave) {
+      const uint32_t f = fb + l;
+      if (f < tot) {
+        const uint32_t o = owner_lane(off[w], f);
+        const uint32_t t = f - off[w][o];
+        icolb[dst[w][o] + t] = icol[src[w][o] + t];
+      }
+    }
+    wave_sync();
+  }
+}
+
+// One workgroup per hub column (slice longer than `split`), records
+// [h0, min(*h1p, cap)): x is its absolute active-column index; xbase is the
+// index of the first column of the arrays passed in.
+__global__ __launch_bounds__(kThreads) void k_icolb_heavy(const HeavyCol* __restrict__ heavy, uint32_t h0,
+                                                          const uint32_t* __restrict__ h1p, uint32_t cap,
+                                                          uint64_t xbase, const uint32_t* __restrict__ aoff,
+                                                          const uint32_t* __restrict__ asrc,
+                                                          const int32_t* __restrict__ icol,
+                                                          int32_t* __restrict__ icolb) {
+  const uint32_t h1 = min(*h1p, cap);
+  for (uint32_t h = h0 + blockIdx.x; h < h1; h += gridDim.x) {
+    const uint64_t x = heavy[h].x - xbase;
+    const uint32_t d = aoff[x], len = aoff[x + 1] - d, sp = asrc[x];
+    for (uint32_t t = threadIdx.x; t < len; t += kThreads) icolb[d + t] = icol[sp + t];
+  }
+}
+
+// W = sum over ranks r of in-degree(r) * out-degree(r): the number of
+// oriented two-paths x -> r -> y, i.e. the probe volume of a per-vertex
+// list count over the degree-ordered graph (the work measure of Sec. 4.4);
+// and the number of ranks whose undirected degree is at most max_deg, which
+// is where stored block boundaries start (degrees rise with rank).  Integer,
+// so the order of the atomic additions does not matter.
+__global__ __launch_bounds__(kThreads) void k_degree_stats(const uint32_t* __restrict__ od,
+                                                           const uint32_t* __restrict__ idg, int64_t n,
+                                                           int64_t max_deg, unsigned long long* __restrict__ wedges,
+                                                           uint32_t* __restrict__ nshort) {
+  __shared__ unsigned long long red[4];
+  unsigned long long acc = 0, cnt = 0;
+  for (int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x; r < n; r += (int64_t)gridDim.x * kThreads) {
+    const uint32_t o = od[r], i = idg[r];
+    acc += (unsigned long long)o * (unsigned long long)i;
+    cnt += ((int64_t)o + (int64_t)i <= max_deg) ? 1ull : 0ull;
+  }
+  acc = block256_sum_u64(acc, red);
+  cnt = block256_sum_u64(cnt, red);
+  if (threadIdx.x == 0) {
+    if (acc) atomicAdd(wedges, acc);
+    if (cnt) atomicAdd(nshort, (uint32_t)cnt);
+  }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------ launchers
+hipError_t launch_degree_stats(const uint32_t* od, const uint32_t* idg, int64_t n, int64_t max_deg,
+                               unsigned long long* wedges, uint32_t* nshort, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_degree_stats, dim3(grid_for((uint64_t)n, kThreads, 2048)), dim3(kThreads), 0, s, od, idg, n,
+                     max_deg, wedges, nshort);
+  return hipGetLastError();
+}
+
 hipError_t launch_validate(const void* rowptr, int rp64, const int32_t* colidx, int64_t n, int64_t nnz,
                            int symmetric, uint32_t* err, uint32_t* list, uint32_t* nlist, uint32_t* hlist,
                            uint32_t* nhlist, uint32_t* hpref, hipStream_t s) {
@@ -1229,32 +1363,35 @@ hipError_t launch_perm(const uint64_t* keys, int64_t n, int idbits, int32_t* ord
   return hipGetLastError();
 }
 
-hipError_t launch_degs(const void* rowptr, int rp64, const int32_t* colidx, int64_t n, int64_t nnz,
+hipError_t launch_degs(const void* rowptr, int rp64, const int32_t* colidx, int64_t n, const RowRange& rr,
                        const int32_t* perm, uint32_t* od, uint32_t* idg, uint32_t* list, uint32_t* nlist,
                        uint32_t* hlist, uint32_t* nhlist, uint32_t* hpref, uint32_t* err, int check, hipStream_t s) {
   if (n == 0) return hipSuccess;
   const unsigned g = grid_for((uint64_t)n, kThreads, 65536);
   if (rp64) {
-    hipLaunchKernelGGL(k_degs_lane<int64_t>, dim3(g), dim3(kThreads), 0, s, (const int64_t*)rowptr, colidx, n, nnz,
+    hipLaunchKernelGGL(k_degs_lane<int64_t>, dim3(g), dim3(kThreads), 0, s, (const int64_t*)rowptr, colidx, n, rr,
                        perm, od, idg, list, nlist, hlist, nhlist, err, check);
     hipLaunchKernelGGL(k_hprefix<int64_t>, dim3(1), dim3(kThreads), 0, s, (const int64_t*)rowptr, (const uint32_t*)hlist,
                        (const uint32_t*)nhlist, hpref);
-    hipLaunchKernelGGL(k_degs_wave<int64_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int64_t*)rowptr, colidx, n,
-                       perm, od, idg, (const uint32_t*)list, (const uint32_t*)nlist, (const uint32_t*)hlist,
-                       (const uint32_t*)nhlist, (const uint32_t*)hpref, err, check);
+    if (od)
+      hipLaunchKernelGGL(k_degs_wave<int64_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int64_t*)rowptr, colidx,
+                         rr, perm, od, idg, (const uint32_t*)list, (const uint32_t*)nlist, (const uint32_t*)hlist,
+                         (const uint32_t*)nhlist, (const uint32_t*)hpref, err, check);
   } else {
-    hipLaunchKernelGGL(k_degs_lane<int32_t>, dim3(g), dim3(kThreads), 0, s, (const int32_t*)rowptr, colidx, n, nnz,
+    hipLaunchKernelGGL(k_degs_lane<int32_t>, dim3(g), dim3(kThreads), 0, s, (const int32_t*)rowptr, colidx, n, rr,
                        perm, od, idg, list, nlist, hlist, nhlist, err, check);
     hipLaunchKernelGGL(k_hprefix<int32_t>, dim3(1), dim3(kThreads), 0, s, (const int32_t*)rowptr, (const uint32_t*)hlist,
                        (const uint32_t*)nhlist, hpref);
-    hipLaunchKernelGGL(k_degs_wave<int32_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int32_t*)rowptr, colidx, n,
-                       perm, od, idg, (const uint32_t*)list, (const uint32_t*)nlist, (const uint32_t*)hlist,
-                       (const uint32_t*)nhlist, (const uint32_t*)hpref, err, check);
+    if (od)
+      hipLaunchKernelGGL(k_degs_wave<int32_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int32_t*)rowptr, colidx,
+                         rr, perm, od, idg, (const uint32_t*)list, (const uint32_t*)nlist, (const uint32_t*)hlist,
+                         (const uint32_t*)nhlist, (const uint32_t*)hpref, err, check);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_fill(const void* rowptr, int rp64, const int32_t* colidx, int64_t n, const int32_t* perm,
+hipError_t launch_fill(const void* rowptr, int rp64, const int32_t* colidx, int64_t n, const RowRange& rr,
+                       const int32_t* perm,
                        const uint32_t* orow, const uint32_t* irow, int32_t* ocol, int32_t* icol, const uint32_t* list,
                        const uint32_t* nlist, const uint32_t* hlist, const uint32_t* nhlist, const uint32_t* hpref,
                        uint32_t* cur_o, uint32_t* cur_i, hipStream_t s) {
@@ -1262,15 +1399,15 @@ hipError_t launch_fill(const void* rowptr, int rp64, const int32_t* colidx, int6
   const unsigned g = grid_for((uint64_t)n, kThreads, 65536);
   hipLaunchKernelGGL(k_zero2, dim3(64), dim3(kThreads), 0, s, cur_o, cur_i, nhlist);
   if (rp64) {
-    hipLaunchKernelGGL(k_fill_lane<int64_t>, dim3(g), dim3(kThreads), 0, s, (const int64_t*)rowptr, colidx, n, perm,
-                       orow, irow, ocol, icol);
-    hipLaunchKernelGGL(k_fill_wave<int64_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int64_t*)rowptr, colidx, perm,
-                       orow, irow, ocol, icol, list, nlist, hlist, nhlist, hpref, cur_o, cur_i);
+    hipLaunchKernelGGL(k_fill_lane<int64_t>, dim3(g), dim3(kThreads), 0, s, (const int64_t*)rowptr, colidx, n, rr,
+                       perm, orow, irow, ocol, icol);
+    hipLaunchKernelGGL(k_fill_wave<int64_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int64_t*)rowptr, colidx, rr,
+                       perm, orow, irow, ocol, icol, list, nlist, hlist, nhlist, hpref, cur_o, cur_i);
   } else {
-    hipLaunchKernelGGL(k_fill_lane<int32_t>, dim3(g), dim3(kThreads), 0, s, (const int32_t*)rowptr, colidx, n, perm,
-                       orow, irow, ocol, icol);
-    hipLaunchKernelGGL(k_fill_wave<int32_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int32_t*)rowptr, colidx, perm,
-                       orow, irow, ocol, icol, list, nlist, hlist, nhlist, hpref, cur_o, cur_i);
+    hipLaunchKernelGGL(k_fill_lane<int32_t>, dim3(g), dim3(kThreads), 0, s, (const int32_t*)rowptr, colidx, n, rr,
+                       perm, orow, irow, ocol, icol);
+    hipLaunchKernelGGL(k_fill_wave<int32_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int32_t*)rowptr, colidx, rr,
+                       perm, orow, irow, ocol, icol, list, nlist, hlist, nhlist, hpref, cur_o, cur_i);
   }
   return hipGetLastError();
 }
@@ -1311,21 +1448,42 @@ hipError_t launch_inrows_group(const uint32_t* rp, int32_t* col, const uint32_t*
   return hipGetLastError();
 }
 
-hipError_t launch_bot(const BlockBuild& bb, hipStream_t s) {
-  if (bb.nchunks == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_bot, dim3(bb.nchunks), dim3(kThreads), 0, s, bb);
+hipError_t launch_bot(const BlockBuild& bb, int nchunks, hipStream_t s) {
+  if (nchunks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bot, dim3(nchunks), dim3(kThreads), 0, s, bb);
   return hipGetLastError();
 }
 
-hipError_t launch_tbot(const BlockBuild& bb, hipStream_t s) {
-  if (bb.nchunks == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_tbot, dim3(bb.nchunks), dim3(kThreads), 0, s, bb);
+hipError_t launch_acount(const BlockBuild& bb, int nchunks, hipStream_t s) {
+  if (nchunks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_acount, dim3(nchunks), dim3(kThreads), 0, s, bb);
   return hipGetLastError();
 }
 
-hipError_t launch_acol(const BlockBuild& bb, hipStream_t s) {
-  if (bb.nchunks == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_acol, dim3(bb.nchunks), dim3(kThreads), 0, s, bb);
+hipError_t launch_acol(const BlockBuild& bb, int nchunks, hipStream_t s) {
+  if (nchunks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_acol, dim3(nchunks), dim3(kThreads), 0, s, bb);
+  return hipGetLastError();
+}
+
+hipError_t launch_icolb(const uint32_t* aoff, const uint32_t* asrc, const int32_t* icol, int32_t* icolb,
+                        const uint32_t* ncolsp, uint64_t ncols_max, uint32_t split, const HeavyCol* heavy, uint32_t h0,
+                        const uint32_t* h1p, uint32_t cap, uint64_t xbase, hipStream_t s) {
+  if (ncols_max > 0)
+    hipLaunchKernelGGL(k_icolb, dim3(grid_for(ncols_max, kThreads, kRowGrid)), dim3(kThreads), 0, s, aoff, asrc, icol,
+                       icolb, ncolsp, split);
+  if (cap > h0)
+    hipLaunchKernelGGL(k_icolb_heavy, dim3(1024), dim3(kThreads), 0, s, heavy, h0, h1p, cap, xbase, aoff, asrc, icol,
+                       icolb);
+  return hipGetLastError();
+}
+
+__global__ void k_set_at(uint32_t* __restrict__ arr, const uint32_t* __restrict__ idx, uint32_t value) {
+  if (threadIdx.x == 0) arr[*idx] = value;
+}
+
+hipError_t launch_set_at(uint32_t* arr, const uint32_t* idx, uint32_t value, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_at, dim3(1), dim3(64), 0, s, arr, idx, value);
   return hipGetLastError();
 }
 
@@ -1359,7 +1517,7 @@ __global__ __launch_bounds__(kThreads) void k_emit_items(const ItemRun* __restri
     const HeavyCol hc = hrec[x];
     it.lo = (r - hcum[x]) * chunk;
     it.hi = min(hc.cnt, it.lo + chunk);
-    it.v = hc.v;
+    it.v = (int32_t)hc.x;
   } else {
     it.lo = (r - t.nhub) * t.nper;
     it.hi = min(t.cols, it.lo + t.nper);

@@ -42,11 +42,13 @@ from . import (BBTC_EBUDGET, BBTC_MODE_PERSISTENT, BBTC_MODE_PLAIN_INTERSECT, Bb
 def footprint_estimate(n: int, nnz: int, p: int) -> int:
     """Upper bound of a plan's device bytes (the layout of bbtc_partition):
     the uploaded input, out/in rows and active columns 12 B per edge,
-    per-vertex arrays, the two block row indices (at most p+1 entries per
-    vertex each), tasks and items."""
+    per-vertex arrays, the two block row indices (at most p+1 entries each
+    for the vertices of degree above 32, of which there are at most
+    nnz/33), tasks and items."""
     m = nnz // 2
     ntasks = p * (p + 1) * (p + 2) // 6
-    return 12 * m + 4 * nnz + 72 * n + 8 * (p + 1) * n + 64 * ntasks + (1 << 20)
+    stored = min(int(n), int(nnz) // 33)
+    return 12 * m + 4 * nnz + 72 * n + 8 * (p + 1) * stored + 64 * ntasks + (1 << 20)
 
 
 def default_p(n: int, nnz: int) -> int:

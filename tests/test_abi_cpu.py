@@ -30,7 +30,8 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(bb.bbtc_csr) == 40
-    assert ctypes.sizeof(bb.bbtc_options) == 40
+    assert ctypes.sizeof(bb.bbtc_options) == 48
+    assert bb.bbtc_options.device_budget_bytes.offset == 32 and bb.bbtc_options.bound_min_deg.offset == 40
     assert ctypes.sizeof(bb.bbtc_task) == 24
 
 

@@ -2,7 +2,8 @@
 Erdos-Renyi average degree 32) at p = 64, against oracle results stored by
 tests/golden/make_goldens.py (total, SHA-256 of the whole per-task vector in
 Alg. 4 order, every 97th per-task entry, SHA-256 of the cut vector); and the
-autotuner's choice, which must give the same total."""
+autotuner's choice, whose per-task vector must equal the oracle's for the p
+it picks."""
 import hashlib
 import json
 import os
@@ -13,6 +14,7 @@ import torch
 
 import graphgen
 import paper_2009_12457_amd as bb
+from helpers import in_alg4_order
 
 pytestmark = pytest.mark.gpu
 
@@ -60,12 +62,19 @@ def test_full_size_per_task_parity(workload, mode):
     plan.destroy()
 
 
-def test_autotuned_total(workload):
+def test_autotuned_per_task(workload):
+    """The autotuner's choice (p from {16, 32, 64, 128} and the row-mapping
+    knobs) gives the oracle's per-task vector for that p, stored by
+    tests/golden/make_goldens.py."""
     name, g, n, rp, ci = workload
     opt, ms = bb.bbtc_autotune(n, rp, ci, base=bb.bbtc_options_default(p=GOLD[name]["p"]), reps=2, trusted=True)
-    assert opt.p >= 1 and ms > 0
+    assert ms > 0
+    gold = GOLD[name]["by_p"][str(opt.p)]
     plan = bb.bbtc_partition(n, rp, ci, options=opt, trusted=True)
     per, tot = bb.bbtc_count(plan)
     torch.cuda.synchronize()
-    assert int(tot.item()) == GOLD[name]["total"]
-    assert int(per[:plan.ntasks].sum().item()) == GOLD[name]["total"]
+    assert hashlib.sha256(plan.cuts().astype("<i4").tobytes()).hexdigest() == gold["cuts_sha256"]
+    assert int(tot.item()) == gold["total"]
+    got = in_alg4_order(opt.p, plan.tasks(), per.cpu().numpy().view(np.uint64))
+    assert hashlib.sha256(got.astype("<u8").tobytes()).hexdigest() == gold["per_task_sha256"]
+    plan.destroy()

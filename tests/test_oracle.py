@@ -250,6 +250,48 @@ def test_balanced_cut_properties(name, p):
             assert orow[c[i] - 1] < target  # ... and is the first to do so
 
 
+def uniform_part_of(x, n, p):
+    """Part of vertex x under an even split, vertex by vertex: the unit cell
+    (x, x+1] of the interval (0, n] belongs to the part a whose share
+    (a*n/p, (a+1)*n/p] holds its right end, i.e. a*n < (x+1)*p <= (a+1)*n."""
+    return -(-(x + 1) * p // n) - 1
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 7, 10, 16, 31, 40, 97])
+def test_uniform_cut_rule(n):
+    """The uniform cut (Sec. 4.1 partitions V into p contiguous parts; the
+    uniform reading splits the rank range evenly).  Pinned without the cut
+    formula: (1) every part has floor(n/p) or ceil(n/p) vertices, exactly
+    n mod p of them the larger size, in the order that integer rounding of
+    a*n/p gives; (2) the part of each vertex, computed vertex by vertex from
+    (x+1)*p/n, agrees with the cut vector; (3) the clamps into
+    [c_{i-1}+1, n-(p-i)] never bind for p <= n (floor(i*n/p) rises by at
+    least floor(n/p) >= 1 per step and i*n/p <= n-(p-i) iff p <= n), so the
+    rule is the plain even split for every valid p."""
+    g = graphgen.from_edges(n, np.zeros(0, np.int32), np.zeros(0, np.int32))
+    og = oracle.OracleGraph.from_graph(g)
+    for p in range(1, n + 1):
+        c = og.cuts(p, oracle.CUT_UNIFORM).astype(np.int64)
+        sizes = np.diff(c)
+        q = n // p
+        assert c[0] == 0 and c[-1] == n
+        assert set(sizes.tolist()) <= {q, q + 1}
+        assert int((sizes == q + 1).sum()) == n % p
+        part = np.array([uniform_part_of(x, n, p) for x in range(n)])
+        assert np.array_equal(np.searchsorted(c, np.arange(n), side="right") - 1, part)
+    with pytest.raises(ValueError):
+        og.cuts(n + 1, oracle.CUT_UNIFORM)
+
+
+def test_uniform_cut_on_edge_graph_ignores_edges():
+    """The uniform rule depends on n and p only: adding edges moves no cut."""
+    g = graphgen.workload("rmat10")
+    og = oracle.OracleGraph.from_graph(g)
+    empty = oracle.OracleGraph.from_graph(graphgen.from_edges(g.n, np.zeros(0, np.int32), np.zeros(0, np.int32)))
+    for p in (1, 3, 16, 100, g.n):
+        assert np.array_equal(og.cuts(p, oracle.CUT_UNIFORM), empty.cuts(p, oracle.CUT_UNIFORM))
+
+
 # ------------------------------------------------------- per-task counts
 def brute_per_task(A, rank, cuts, p):
     part = np.searchsorted(cuts, np.arange(A.shape[0]), side="right") - 1
@@ -352,3 +394,34 @@ def test_er_statistics_smoke():
     """Not parity: G(2000, 0.005) should land near C(n,3) p^3 ~ 166 triangles."""
     og = oracle.OracleGraph.from_graph(graphgen.workload("er2000"))
     assert 60 < og.total() < 320
+
+
+@pytest.mark.parametrize("name", ["er2000", "rmat12"])
+def test_total_rows_tiles_the_total(name):
+    """Row-list counts (used for bounded CPU timing samples) over lists that
+    partition the ranks add up to the total, and each equals the
+    brute-force count of triangles whose lowest-ranked vertex is listed
+    (checked on the 2000-vertex graph by dense enumeration over ranks)."""
+    g = graphgen.workload(name)
+    og = oracle.OracleGraph.from_graph(g)
+    tot = og.total()
+    rng = np.random.default_rng(3)
+    lab = rng.integers(0, 4, size=og.n)
+    lists = [np.nonzero(lab == c)[0] for c in range(4)]
+    parts = [og.total_rows(r) for r in lists]
+    assert sum(parts) == tot
+    assert og.total_rows(np.zeros(0, np.int64)) == 0
+    with pytest.raises(ValueError):
+        og.total_rows([og.n])
+    if name == "er2000":
+        rank = og.rank()
+        A = np.zeros((og.n, og.n), bool)
+        u, v = g.edges()
+        A[rank[u], rank[v]] = A[rank[v], rank[u]] = True
+        low = np.zeros(og.n, np.int64)
+        for a in range(og.n):
+            nb = np.nonzero(A[a, a + 1:])[0] + a + 1
+            for x in range(len(nb)):
+                low[a] += int(A[nb[x], nb[x + 1:]].sum())
+        for r, got in zip(lists, parts):
+            assert got == int(low[r].sum())
