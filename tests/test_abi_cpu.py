@@ -35,6 +35,32 @@ def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(bb.bbtc_task) == 24
 
 
+def test_every_struct_matches_the_c_layout(tmp_path):
+    """Size and field offsets of every struct the binding passes, against the
+    C compiler's layout of include/bbtc.h (a binding struct shorter than the
+    C one would let the library write past a Python-owned buffer)."""
+    structs = {"bbtc_csr": bb.bbtc_csr, "bbtc_options": bb.bbtc_options, "bbtc_stats": bb.bbtc_stats,
+               "bbtc_hybrid_stats": bb.bbtc_hybrid_stats, "bbtc_tables": bb.bbtc_tables}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "bbtc.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            lines.append(f'  printf("{name}.{f} %zu\\n", offsetof({name}, {f.rstrip("_")}));')
+    lines.append('  printf("bbtc_task %zu\\n", sizeof(bbtc_task));')
+    lines.append("  return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    got = dict(line.split() for line in subprocess.check_output([str(exe)], text=True).splitlines())
+    for name, cls in structs.items():
+        assert int(got[name]) == ctypes.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert int(got[f"{name}.{f}"]) == getattr(cls, f).offset, (name, f)
+    assert int(got["bbtc_task"]) == bb.TASK_DTYPE.itemsize
+
+
 def test_options_default():
     o = bb.bbtc_options_default()
     assert (o.p, o.mode, o.cut_mode, o.wave_min, o.hash_min, o.device_budget_bytes) == (0, 0, 0, 0, 0, 0)
