@@ -42,6 +42,7 @@ WORKLOADS = {
 }
 AUTOTUNED = ("rmat24", "er24")
 PMC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+HYBRID_THREADS = 15  # host threads of the co-scheduled count: the CPU share of one GPU, less the main thread
 # the sources the counting kernel is compiled from: a traffic record applies
 # only to the kernel built from exactly these
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2009_12457_amd", "csrc", f)
@@ -206,6 +207,32 @@ def count_event_ms(bb, plan, per, tot, stream, reps):
     return float(np.median([a.elapsed_time(b) for a, b in zip(ev0, ev1)]))
 
 
+def measure_hybrid(bb, plan, per, tot, stream, count_ms, triangles, sync):
+    """CPU+GPU co-scheduling (Sec. 5, Alg. 5-7) against the GPU alone: the
+    synchronous hybrid call at cut-offs |T|/2, 3|T|/4, 7|T|/8 and |T| (the
+    GPU alone through the same call), median of three, with HYBRID_THREADS
+    host threads (the CPU share of one GPU here).  The first call, which
+    copies the plan's tables to host memory, is not timed."""
+    import numpy as np
+    nt = plan.ntasks
+    _, _, first = bb.bbtc_count_hybrid(plan, per, tot, stream=stream, cpu_threads=HYBRID_THREADS, cutoff=nt)
+    out = {"cpu_threads": HYBRID_THREADS, "gpu_alone_count_ms": count_ms, "first_call_ms": first["total_ms"],
+           "cutoffs": {}}
+    for label, cut in (("1/2", nt // 2), ("3/4", 3 * nt // 4), ("7/8", 7 * nt // 8), ("1", nt)):
+        runs = []
+        for _ in range(3):
+            _, _, hs = bb.bbtc_count_hybrid(plan, per, tot, stream=stream, cpu_threads=HYBRID_THREADS, cutoff=cut)
+            if int(tot.item()) != triangles:
+                raise SystemExit(f"hybrid count at cut-off {label} disagrees: {int(tot.item())} vs {triangles}")
+            runs.append(hs)
+        med = sorted(runs, key=lambda h: h["total_ms"])[1]
+        out["cutoffs"][label] = {"cutoff": cut, "ms": med["total_ms"], "cpu_tasks": med["cpu_tasks"],
+                                 "gpu_tasks": med["gpu_tasks"], "gpu_launches": med["gpu_launches"],
+                                 "cpu_busy_ms": med["cpu_ms"], "cpu_triangles": med["cpu_triangles"]}
+    sync()
+    return out
+
+
 def measure(args, name, g, opt, tuned, plain_modes, stream):
     """Steps (partition + batched count) on a device-resident CSR, the count
     alone, the partition alone, the step from pinned host memory, and the
@@ -263,6 +290,8 @@ def measure(args, name, g, opt, tuned, plain_modes, stream):
     rec["copy_included"] = {"ms_per_step": hms, "edges_per_s": m / (hms * 1e-3),
                             "what": "H2D of the symmetric CSR from pinned host memory + partition + batched count"}
     rec["bytes_total"] = int(st["bytes_total"])
+    if not args.no_hybrid:
+        rec["hybrid"] = measure_hybrid(bb, plan, per, tot, stream, count_ms, triangles, sync)
     plain = {}
     for pname, mode in plain_modes:
         o2 = bb.bbtc_options_default(p=int(st["p"]), mode=mode)
@@ -446,6 +475,7 @@ def main():
     ap.add_argument("--no-small", action="store_true", help="skip the 2000-vertex and scale-20 configurations")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-task baselines")
+    ap.add_argument("--no-hybrid", action="store_true", help="skip the CPU+GPU co-scheduled counts")
     ap.add_argument("--device-budget-gb", type=float, default=0.0,
                     help="device budget (streams row stripes from pinned host memory)")
     ap.add_argument("--oracle-check", action="store_true",
@@ -601,6 +631,7 @@ def main():
         "batched_count_edges_per_s": head["count_only_edges_per_s"],
         "copy_included": head["copy_included"],
         "plain": head["plain"],
+        "hybrid": head.get("hybrid"),
         "batched_vs_plain": head.get("batched_vs_plain"),
         "roofline": roofline,
         "lds_side_rate": lds_rate,

@@ -100,14 +100,19 @@ typedef struct bbtc_csr {
  *   item_rows     active columns of G_ij per persistent work item.
  *   graph         0: the persistent count (reset + launch) is captured once
  *                 in a hipGraph and replayed; -1: launched directly.
- *   device_budget_bytes  upper bound on the device memory of the count phase
- *                 (0 = none).  A plan over the budget keeps its rows in pinned
- *                 host memory and streams, per block pair (i,j), the three row
- *                 stripes its tasks read (out-rows of V_i and V_j, in-rows of
- *                 V_j) into a device cache of stripe slots (Sec. 4.1: a task
- *                 needs only its three blocks).  bbtc_partition itself runs
- *                 with the whole graph on the device.  Fewer than three slots
- *                 within the budget: BBTC_EBUDGET.
+ *   device_budget_bytes  upper bound on the device memory a plan holds for
+ *                 the count (0 = none).  A plan over the budget keeps its
+ *                 count-phase arrays in pinned host memory and streams, per
+ *                 block pair (i,j), what its tasks read (Sec. 4.1: a task
+ *                 needs only its three blocks): the out-rows of V_i and V_j
+ *                 with their stored block boundaries (two out-stripes, cached
+ *                 least recently used first) and block (i,j)'s in side.  When
+ *                 the resident partition itself would not fit, bbtc_partition
+ *                 builds the plan in pieces (input rows in chunks, parts in
+ *                 groups as large as the budget allows) straight into pinned
+ *                 host memory.  BBTC_EBUDGET when the budget cannot hold the
+ *                 degree order, the build of a single part, or two out-stripes
+ *                 beside two in-block slots.
  *   bound_min_deg the block row index (Sec. 4.1) stores, for a vertex of
  *                 undirected degree above bound_min_deg, the position of each
  *                 block's slice in its out-row and in-row; rows of lower
@@ -213,7 +218,7 @@ bbtc_status bbtc_count_multi(bbtc_plan* const* plans, int32_t nplans, void* stre
  * sides at a time until they meet.  Host threads count by list intersection
  * (Alg. 1) over host copies of the plan's tables, made on the first call
  * for a plan build (O(m) host memory).  cutoff -1 = |T|/2; cutoff |T| = the
- * GPU alone.  cpu_threads 0 = the hardware threads minus one.  Results as
+ * GPU alone.  cpu_threads 0 = the hardware threads minus one, at most 16.  Results as
  * bbtc_count, but the call is synchronous: it returns when they are in
  * d_per_task/d_total (`stream` is synchronised).  Not for streamed plans
  * (BBTC_ESTATE).  `stats` (may be NULL) reports the split.

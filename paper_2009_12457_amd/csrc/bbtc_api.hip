@@ -341,6 +341,7 @@ constexpr int kDefaultWaveMin = 32;
 constexpr int kDefaultHashMin = 16;
 constexpr int kDefaultItemRows = 256;
 constexpr uint32_t kHubSplit = 256;   // in-slice length above which a column is split
+constexpr unsigned kHybridMaxThreads = 16;  // default host threads of the hybrid count, at most
 constexpr uint32_t kHubChunk = 1024;  // in-neighbours per hub work item
 constexpr int kItemsPerBlock = 20;    // work items per resident workgroup (by estimated work)
 
@@ -1128,8 +1129,13 @@ bbtc_status partition_budgeted(const bbtc_csr* g, hipStream_t s, bbtc_plan* pl,
   B.rp64 = g->rowptr_bits == 64;
   B.rpb = B.rp64 ? 8 : 4;
   const bool symmetric_check = (g->flags & BBTC_CSR_TRUSTED) == 0;
-  {  // the per-vertex arrays of the degree order must fit at least
-    const int64_t fixed = 24 * n + (B.on_device ? 0 : (int64_t)B.rpb * (n + 1)) + (8 << 20);
+  {  // the arrays of the degree order must fit at least: keys (two), perm,
+     // order, the radix histogram and scan partials, the row pointers of
+     // host input, and a little room for the small tables
+    const uint64_t hist = radix_hist_entries((uint64_t)n);
+    const uint64_t part = scan_partial_entries(std::max<uint64_t>(hist, (uint64_t)n + 1)) + 4096;
+    const int64_t fixed = 24 * n + 4 * (int64_t)(hist + part) + (B.on_device ? 0 : (int64_t)B.rpb * (n + 1)) +
+                          (1 << 20);
     if (fixed > budget)
       return fail(BBTC_EBUDGET, "device budget below the " + std::to_string(fixed) +
                                     " B that ordering the vertices needs");
@@ -1940,7 +1946,8 @@ bbtc_status count_hybrid_impl(bbtc_plan* pl, hipStream_t s, uint64_t* d_per_task
   const int64_t nt = (int64_t)pl->h_tasks.size();
   if (cutoff < 0) cutoff = nt / 2;
   cutoff = std::min<int64_t>(cutoff, nt);
-  if (nthreads <= 0) nthreads = (int32_t)std::max(1u, std::thread::hardware_concurrency() - 1);
+  if (nthreads <= 0)
+    nthreads = (int32_t)std::max(1u, std::min(kHybridMaxThreads, std::thread::hardware_concurrency() - 1));
   HIP_TRY(launch_reset(d_per_task, nt, d_total, pl->cursor.ptr, s), "reset");
   const int grid_max = pl->blocks_per_cu * pl->ncu;
   int64_t launches = 0;
