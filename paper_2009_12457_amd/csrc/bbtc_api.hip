@@ -1129,17 +1129,6 @@ bbtc_status partition_budgeted(const bbtc_csr* g, hipStream_t s, bbtc_plan* pl,
   B.rp64 = g->rowptr_bits == 64;
   B.rpb = B.rp64 ? 8 : 4;
   const bool symmetric_check = (g->flags & BBTC_CSR_TRUSTED) == 0;
-  {  // the arrays of the degree order must fit at least: keys (two), perm,
-     // order, the radix histogram and scan partials, the row pointers of
-     // host input, and a little room for the small tables
-    const uint64_t hist = radix_hist_entries((uint64_t)n);
-    const uint64_t part = scan_partial_entries(std::max<uint64_t>(hist, (uint64_t)n + 1)) + 4096;
-    const int64_t fixed = 24 * n + 4 * (int64_t)(hist + part) + (B.on_device ? 0 : (int64_t)B.rpb * (n + 1)) +
-                          (1 << 20);
-    if (fixed > budget)
-      return fail(BBTC_EBUDGET, "device budget below the " + std::to_string(fixed) +
-                                    " B that ordering the vertices needs");
-  }
   // row pointers on the host, chunks of input rows (at most max_ent entries
   // and max_rows rows each; a longer row is a chunk of its own)
   B.hrp.resize((size_t)n + 1);
@@ -1189,6 +1178,18 @@ bbtc_status partition_budgeted(const bbtc_csr* g, hipStream_t s, bbtc_plan* pl,
     l2.release();
     if (e) return decode_device_err(e);
     HIP_TRY(hipMemsetAsync(pl->err.ptr, 0, 8 * sizeof(uint32_t), s), "memset");
+  }
+  {  // (after validation, so that bad input is EINVAL whatever the budget) the
+     // arrays of the degree order must fit at least: keys (two), perm,
+     // order, the radix histogram and scan partials, the row pointers of
+     // host input, and a little room for the small tables
+    const uint64_t hist = radix_hist_entries((uint64_t)n);
+    const uint64_t part = scan_partial_entries(std::max<uint64_t>(hist, (uint64_t)n + 1)) + 4096;
+    const int64_t fixed = 24 * n + 4 * (int64_t)(hist + part) + (B.on_device ? 0 : (int64_t)B.rpb * (n + 1)) +
+                          (1 << 20);
+    if (fixed > budget)
+      return fail(BBTC_EBUDGET, "device budget below the " + std::to_string(fixed) +
+                                    " B that ordering the vertices needs");
   }
   // trusted input: the degree pass checks the entries (untrusted input was
   // checked above, on the host or by the validation kernels)
