@@ -14,6 +14,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <condition_variable>
 #include <mutex>
 #include <new>
 #include <string>
@@ -1974,12 +1975,15 @@ bbtc_status count_hybrid_impl(bbtc_plan* pl, hipStream_t s, uint64_t* d_per_task
   std::vector<uint64_t> cpu_per((size_t)nt, 0);
   std::vector<double> busy((size_t)nthreads, 0.0);
   std::vector<int64_t> done((size_t)nthreads, 0);
+  int32_t started = 0;  // host threads that have made their first claim
+  std::condition_variable all_started;
   auto worker = [&](int w) {
     const auto b0 = std::chrono::steady_clock::now();
-    for (;;) {
+    for (bool first = true;; first = false) {
       int64_t t;
       {
         std::lock_guard<std::mutex> lock(mu);
+        if (first && ++started == nthreads) all_started.notify_one();
         if (back <= front || back <= cutoff) break;
         t = --back;
       }
@@ -1994,14 +1998,28 @@ bbtc_status count_hybrid_impl(bbtc_plan* pl, hipStream_t s, uint64_t* d_per_task
   // from the back meanwhile
   if ((st = gpu_range(0, cutoff)) != BBTC_OK) return st;
   std::vector<std::thread> th;
-  for (int w = 0; w < nthreads; ++w) th.emplace_back(worker, w);
+  try {
+    for (int w = 0; w < nthreads; ++w) th.emplace_back(worker, w);
+  } catch (const std::exception&) {  // no thread could be started: stop the ones that were
+    {
+      std::lock_guard<std::mutex> lock(mu);
+      front = back;
+    }
+    for (auto& x : th) x.join();
+    (void)hipStreamSynchronize(s);
+    return fail(BBTC_ENOMEM, "could not start the host threads");
+  }
   hipError_t herr = hipSuccess;
-  for (;;) {
+  for (bool first = true;; first = false) {
     herr = hipStreamSynchronize(s);
     if (herr != hipSuccess) break;
     int64_t a, b;
     {
-      std::lock_guard<std::mutex> lock(mu);
+      std::unique_lock<std::mutex> lock(mu);
+      // the GPU competes for the tasks past the cut-off only once every host
+      // thread has made its first claim (a thread that starts late would
+      // otherwise find the list taken on small plans)
+      if (first) all_started.wait(lock, [&] { return started == nthreads; });
       if (front >= back) break;
       a = front;
       b = front + std::max<int64_t>(1, (back - front) / 2);
