@@ -57,6 +57,11 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
+def note(msg):
+    """One progress line per finished stage, on stderr."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def pmc_key(workload, opt):
     return f"{workload}-p{opt.p}-w{opt.wave_min}-h{opt.hash_min}"
 
@@ -145,6 +150,7 @@ def serving_bench(kind):
         torch.cuda.synchronize()
         alone[q] = int(tot.item())
     plan.destroy()
+    note(f"serving pool of {len(pool)} graphs generated and counted alone")
     sizes = np.array([len(g.colidx) // 2 for g in pool])
     edges = sum(len(t[3]) // 2 for t in trace[warm:])
     out = {"pool": kind, "pool_graphs": len(pool), "pool_edges_min": int(sizes.min()),
@@ -156,6 +162,7 @@ def serving_bench(kind):
         res = serve.run_trace(srv, trace)
     finally:
         srv.close()
+    note(f"batched serving of {nreq} requests done")
     span = max(r.done for r in res[warm:]) - min(r.arrival for r in res[warm:])
     for r, q in zip(res, pick):
         if r.total != alone[int(q)]:
@@ -179,6 +186,7 @@ def serving_bench(kind):
     ptrace = trace[:nplain]
     pwarm = min(warm, nplain // 4)
     res_p = serve.serve_plain(ptrace)
+    note(f"plain serving of {len(ptrace)} requests done")
     span_p = max(r.done for r in res_p[pwarm:]) - min(r.arrival for r in res_p[pwarm:])
     for r, q in zip(res_p, pick):
         if r.total != alone[int(q)]:
@@ -290,8 +298,10 @@ def measure(args, name, g, opt, tuned, plain_modes, stream):
     rec["copy_included"] = {"ms_per_step": hms, "edges_per_s": m / (hms * 1e-3),
                             "what": "H2D of the symmetric CSR from pinned host memory + partition + batched count"}
     rec["bytes_total"] = int(st["bytes_total"])
+    note(f"{name}: steps, count, partition and host-input step timed")
     if not args.no_hybrid:
         rec["hybrid"] = measure_hybrid(bb, plan, per, tot, stream, count_ms, triangles, sync)
+        note(f"{name}: hybrid counts timed")
     plain = {}
     for pname, mode in plain_modes:
         o2 = bb.bbtc_options_default(p=int(st["p"]), mode=mode)
@@ -305,6 +315,8 @@ def measure(args, name, g, opt, tuned, plain_modes, stream):
         plain[pname] = {"count_ms": med * 1e3, "edges_per_s": m / med}
         pl2.destroy()
     rec["plain"] = plain
+    if plain:
+        note(f"{name}: plain counts timed")
     if plain:
         rec["batched_vs_plain"] = {k: v["count_ms"] / count_ms for k, v in plain.items()}
     del rp, ci
@@ -330,6 +342,7 @@ def measure_budgeted(args, name, g, stream):
     rp = torch.from_numpy(g.rowptr).pin_memory().numpy()
     ci = torch.from_numpy(g.colidx).pin_memory().numpy()
     pin_s = time.perf_counter() - t
+    note(f"{name} input pinned in {pin_s:.1f} s")
     gold = None
     gpath = os.path.join(ROOT, "tests", "golden", "full_size.json")
     if os.path.exists(gpath):
@@ -343,21 +356,25 @@ def measure_budgeted(args, name, g, stream):
         sync()
         part_s = time.perf_counter() - t
         st = plan.stats()
+        note(f"{name} {label}: partitioned within {budget} B in {part_s:.1f} s (footprint {st['footprint']} B, "
+             f"resident {st['resident_bytes']} B, {st['stripe_slots']} stripe slots)")
         per = torch.empty(int(st["ntasks"]), dtype=torch.int64, device="cuda")
         tot = torch.empty(1, dtype=torch.int64, device="cuda")
         cms = []
-        for _ in range(max(1, args.steps)):
+        for _ in range(max(1, min(args.steps, 3))):  # each streamed count takes seconds here
             t = time.perf_counter()
             bb.bbtc_count(plan, per, tot, stream=stream)
             sync()
             cms.append((time.perf_counter() - t) * 1e3)
+            note(f"{name} {label}: counted in {cms[-1]:.0f} ms")
         st = plan.stats()
         m = int(st["m"])
         rec = {"device_budget_bytes": budget, "streamed": int(st["streamed"]), "footprint": int(st["footprint"]),
                "stripe_slots": int(st["stripe_slots"]), "stripe_bytes": int(st["stripe_bytes"]),
                "uploads_per_count": int(st["stripe_uploads"]), "partition_s": part_s,
                "count_ms": float(np.median(cms)), "step_edges_per_s": m / (part_s + float(np.median(cms)) * 1e-3),
-               "count_edges_per_s": m / (float(np.median(cms)) * 1e-3), "triangles": int(tot.item())}
+               "count_edges_per_s": m / (float(np.median(cms)) * 1e-3), "triangles": int(tot.item()),
+               "counts_timed": len(cms)}
         if gold and gold.get("p") == int(st["p"]):
             tasks = plan.tasks()
             got = np.zeros(len(tasks), np.uint64)
@@ -516,13 +533,14 @@ def main():
     t_gen = time.perf_counter()
     g = graphgen.workload(WORKLOADS[name][0])
     t_gen = time.perf_counter() - t_gen
+    note(f"{name} generated in {t_gen:.1f} s")
     if name == "rmat27":  # the device-budget configuration
         if not args.device_budget_gb:
             args.device_budget_gb = 24.0
         rec = measure_budgeted(args, name, g, stream)
         b = rec["runs"]["budget"]
         print(json.dumps({
-            "metric": METRIC, "value": b["step_edges_per_s"], "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
+            "metric": METRIC, "value": b["step_edges_per_s"], "unit": "edges/s", "n_gpus": 1, "steps": b["counts_timed"],
             "warmup": 0, "ms_per_step": b["partition_s"] * 1e3 + b["count_ms"], "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
             "config": {"workload": rec["workload"], "n": rec["n"], "m": rec["m"], "p": args.p or WORKLOADS[name][1],
@@ -531,6 +549,7 @@ def main():
             "budgeted": rec}))
         return
     opt, tuned = options_for(args, name, stream, g)
+    note(f"{name} options p={opt.p} wave_min={opt.wave_min} hash_min={opt.hash_min}")
     if args.profile_only:
         n, rp, ci = bb.csr_of(g, "cuda")
         plan = bb.bbtc_partition(n, rp, ci, options=opt, trusted=True, stream=stream)
@@ -551,6 +570,7 @@ def main():
     plain_modes = () if args.no_plain else (("plain_intersect", bb.BBTC_MODE_PLAIN_INTERSECT),
                                             ("plain_hmap", bb.BBTC_MODE_PLAIN_HMAP))
     head, plan, triangles = measure(args, name, g, opt, tuned, plain_modes, stream)
+    note(f"{name} measured: {head['ms_per_step']:.2f} ms per step")
     st = plan.stats()
     m = head["m"]
     count_ms = head["step_breakdown_ms"]["count_batched"]
@@ -575,6 +595,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_sample(g, m)
+        note("cpu baseline sampled")
 
     oracle_check = None
     if args.oracle_check:
@@ -592,6 +613,7 @@ def main():
         g2 = graphgen.workload("er24")
         o2, t2 = options_for(args, "er24", stream, g2)
         companion, pl2, _ = measure(args, "er24", g2, o2, t2, plain_modes, stream)
+        note("er24 measured")
         pl2.destroy()
         del g2
         torch.cuda.empty_cache()
@@ -607,6 +629,7 @@ def main():
             if not args.no_cpu_baseline:
                 rec["cpu_oracle"] = cpu_small(sname, gs, tri)
             small[sname] = rec
+            note(f"{sname} measured")
 
     serving = serving_bench(args.serving) if args.serving != "off" else None
 

@@ -23,6 +23,7 @@
  * keeps the result exact G(n,p) and independent of thread count.
  */
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 #include <math.h>
@@ -226,16 +227,27 @@ static void source_pass(const edge_source* s, int pass, int64_t* cnt, int32_t* c
  * int32 (at least twice the number of raw pairs).  Returns the number of
  * entries kept, or a negative error code.
  */
+/* Large builds report each finished phase on stderr (they take minutes). */
+static void phase_done(const edge_source* s, const char* what, double t0) {
+  if (s->n >= (1LL << 25)) {
+    fprintf(stderr, "graphgen: n=%lld %s after %.1f s\n", (long long)s->n, what, omp_get_wtime() - t0);
+    fflush(stderr);
+  }
+}
+
 static int64_t build_csr(const edge_source* s, int64_t* rowptr, int32_t* col, int64_t cap) {
   const int64_t n = s->n;
+  const double t0 = omp_get_wtime();
   int64_t* cnt = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
   if (!cnt) return -2;
   source_pass(s, 0, cnt, NULL);
+  phase_done(s, "pairs counted", t0);
   int64_t tot = 0;
   for (int64_t x = 0; x < n; ++x) { int64_t c = cnt[x]; cnt[x] = tot; rowptr[x] = tot; tot += c; }
   rowptr[n] = tot;
   if (tot > cap) { free(cnt); return -3; }
   source_pass(s, 1, cnt, col);
+  phase_done(s, "pairs placed", t0);
   /* sort + unique each row; record new lengths in cnt */
 #pragma omp parallel for schedule(dynamic, 1024)
   for (int64_t x = 0; x < n; ++x) {
@@ -247,6 +259,7 @@ static int64_t build_csr(const edge_source* s, int64_t* rowptr, int32_t* col, in
       if (w == 0 || col[b + t] != col[b + w - 1]) col[b + w++] = col[b + t];
     cnt[x] = w;
   }
+  phase_done(s, "rows sorted", t0);
   /* compact in place: new offsets never exceed old ones */
   int64_t pos = 0;
   for (int64_t x = 0; x < n; ++x) {
