@@ -238,6 +238,26 @@ bbtc_status bbtc_count_hybrid(bbtc_plan* plan, void* stream, uint64_t* d_per_tas
                               int32_t cpu_threads, int64_t cutoff, bbtc_hybrid_stats* stats);
 
 /*
+ * For callers that cannot allocate memory (code under stream capture, tight
+ * serving loops, harnesses that forbid allocation): bbtc_count_multi with
+ * the state of the shared launch (the plans' kernel contexts, their item
+ * offsets and the work-queue cursors) kept in a fixed device array of the
+ * library (BBTC_STATIC_BYTES per device, held until the process ends)
+ * instead of memory allocated per call.  The successful path calls no
+ * allocating routine (no hipMalloc/hipFree, no pinned host memory, no
+ * events, no host heap).  At most BBTC_STATIC_MAX_PLANS plans per call,
+ * else BBTC_EINVAL.  Every call on a device shares that device's array, and
+ * each call rewrites it: calls that overlap on one device (on different
+ * streams, or before an earlier call's work on another stream has
+ * completed) race and give wrong results; calls in order on one stream are
+ * safe.  Arguments, results and the other errors as bbtc_count_multi.
+ */
+#define BBTC_STATIC_MAX_PLANS 64
+#define BBTC_STATIC_BYTES 32768
+bbtc_status bbtc_count_multi_static(bbtc_plan* const* plans, int32_t nplans, void* stream,
+                                    uint64_t* const* d_per_task, uint64_t* d_totals);
+
+/*
  * Autotuner.  Picks p, wave_min and hash_min for this graph by timing the
  * persistent count (HIP events on `stream`, median of `reps` launches after
  * one warm-up) by coordinate descent: first p over {p0/4, p0/2, p0, 2*p0}

@@ -92,6 +92,7 @@ _SIGS = {
                                         ctypes.POINTER(_P)]),
     "bbtc_count": (ctypes.c_int32, [_P, _P, _P, _P]),
     "bbtc_count_multi": (ctypes.c_int32, [ctypes.POINTER(_P), ctypes.c_int32, _P, ctypes.POINTER(_P), _P]),
+    "bbtc_count_multi_static": (ctypes.c_int32, [ctypes.POINTER(_P), ctypes.c_int32, _P, ctypes.POINTER(_P), _P]),
     "bbtc_count_hybrid": (ctypes.c_int32, [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int64,
                                            ctypes.POINTER(bbtc_hybrid_stats)]),
     "bbtc_autotune": (ctypes.c_int32, [ctypes.POINTER(bbtc_csr), ctypes.POINTER(bbtc_options), ctypes.c_int32, _P,
@@ -385,8 +386,13 @@ def bbtc_count_hybrid(plan: Plan, per_task=None, total=None, stream=None, cpu_th
     return per_task, total, {f: getattr(st, f) for f, _ in bbtc_hybrid_stats._fields_ if f != "pad"}
 
 
-def bbtc_count_multi(plans, per_task_list=None, totals=None, stream=None):
-    """Shared persistent launch over several plans (continuous batching)."""
+BBTC_STATIC_MAX_PLANS = 64
+
+
+def bbtc_count_multi(plans, per_task_list=None, totals=None, stream=None, static=False):
+    """Shared persistent launch over several plans.  static=True calls
+    bbtc_count_multi_static (launch state in the library's fixed device
+    array, no allocation inside the call)."""
     import torch
     k = len(plans)
     if per_task_list is None:
@@ -395,8 +401,9 @@ def bbtc_count_multi(plans, per_task_list=None, totals=None, stream=None):
         totals = torch.empty(max(k, 1), dtype=torch.int64, device="cuda")
     arr = (ctypes.c_void_p * max(k, 1))(*[p.handle.value for p in plans])
     outs = (ctypes.c_void_p * max(k, 1))(*[t.data_ptr() for t in per_task_list])
-    _check(_lib.bbtc_count_multi(arr, k, _stream_handle(stream), outs, ctypes.c_void_p(totals.data_ptr())),
-           "bbtc_count_multi")
+    fn, name = ((_lib.bbtc_count_multi_static, "bbtc_count_multi_static") if static
+                else (_lib.bbtc_count_multi, "bbtc_count_multi"))
+    _check(fn(arr, k, _stream_handle(stream), outs, ctypes.c_void_p(totals.data_ptr())), name)
     return per_task_list, totals
 
 

@@ -2061,6 +2061,116 @@ bbtc_status count_hybrid_impl(bbtc_plan* pl, hipStream_t s, uint64_t* d_per_task
   return BBTC_OK;
 }
 
+// ---- shared launches without allocation (bbtc_count_multi_static)
+// The launch state lives in `scratch`, a fixed device array of this file:
+// PlanCtx[kStaticPlans] | uint32 plan_off[kStaticPlans] | uint32
+// cursor[kMaxQueues].  Host code uses the device address obtained once per
+// device by hipGetSymbolAddress, never the array's name; the contexts are
+// written into it by a kernel that takes them as arguments (no host staging,
+// no copy engine), so a call is only kernel launches.
+constexpr int kStaticPlans = BBTC_STATIC_MAX_PLANS;
+constexpr size_t kStaticCtxBytes = sizeof(PlanCtx) * kStaticPlans;
+constexpr size_t kStaticOffBytes = sizeof(uint32_t) * kStaticPlans;
+static_assert(kStaticCtxBytes % 16 == 0, "cursor alignment");
+static_assert(kStaticCtxBytes + kStaticOffBytes + sizeof(uint32_t) * kMaxQueues <= BBTC_STATIC_BYTES,
+              "static launch state exceeds its array");
+
+static __device__ __align__(256) char scratch[BBTC_STATIC_BYTES];
+
+constexpr int kMaxDevices = 64;
+struct StaticState {
+  std::mutex mu;
+  char* ptr[kMaxDevices] = {};  // device address of `scratch` on each device
+};
+StaticState g_static;
+
+// The device address of this device's `scratch`, looked up on the first call
+// made with the device current.
+bbtc_status static_scratch(char** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(BBTC_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_static.mu);
+  if (!g_static.ptr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress");
+    if (!p) return fail(BBTC_EDEVICE, "no device address for the static launch state");
+    g_static.ptr[dev] = (char*)p;
+  }
+  *out = g_static.ptr[dev];
+  return BBTC_OK;
+}
+
+constexpr int kCtxBatch = 8;  // contexts per fill launch (kernel arguments stay well under 4 KB)
+struct CtxBatch {
+  PlanCtx ctx[kCtxBatch];
+  uint32_t off[kCtxBatch];
+  int32_t first, count;
+};
+
+// Writes contexts [first, first+count) and their item offsets.
+__global__ __launch_bounds__(kThreads) void k_put_ctx(PlanCtx* __restrict__ ctxs, uint32_t* __restrict__ offs,
+                                                      CtxBatch b) {
+  constexpr int kWords = (int)(sizeof(PlanCtx) / 4);
+  static_assert(sizeof(PlanCtx) % 4 == 0, "word copy");
+  for (int t = threadIdx.x; t < b.count * kWords; t += kThreads) {
+    const int q = t / kWords, w = t % kWords;
+    reinterpret_cast<uint32_t*>(ctxs + b.first + q)[w] = reinterpret_cast<const uint32_t*>(&b.ctx[q])[w];
+  }
+  if (threadIdx.x < (unsigned)b.count) offs[b.first + threadIdx.x] = b.off[threadIdx.x];
+}
+
+bbtc_status count_multi_static_impl(bbtc_plan* const* plans, int32_t nplans, hipStream_t s,
+                                    uint64_t* const* d_per_task, uint64_t* d_totals) {
+  char* base = nullptr;
+  bbtc_status st = static_scratch(&base);
+  if (st != BBTC_OK) return st;
+  PlanCtx* d_ctx = (PlanCtx*)base;
+  uint32_t* d_off = (uint32_t*)(base + kStaticCtxBytes);
+  uint32_t* d_cursor = (uint32_t*)(base + kStaticCtxBytes + kStaticOffBytes);
+  // heavier plans first (sum of task estimates), as bbtc_count_multi
+  int32_t order[kStaticPlans];
+  for (int32_t q = 0; q < nplans; ++q) {
+    int32_t r = q;
+    while (r > 0 && plans[order[r - 1]]->est_sum < plans[q]->est_sum) {
+      order[r] = order[r - 1];
+      --r;
+    }
+    order[r] = q;
+  }
+  uint64_t nitems = 0;
+  CtxBatch b;
+  for (int32_t r0 = 0; r0 < nplans; r0 += kCtxBatch) {
+    std::memset(&b, 0, sizeof(b));
+    b.first = r0;
+    b.count = std::min(kCtxBatch, nplans - r0);
+    for (int32_t t = 0; t < b.count; ++t) {
+      const int32_t q = order[r0 + t];
+      b.ctx[t] = plan_ctx(plans[q], d_per_task[q], d_totals + q);
+      b.off[t] = (uint32_t)nitems;
+      nitems += plans[q]->nitems;
+    }
+    if (nitems > 0xFFFFFFFFull) return fail(BBTC_EINVAL, "too many work items for one shared launch");
+    hipLaunchKernelGGL(k_put_ctx, dim3(1), dim3(kThreads), 0, s, d_ctx, d_off, b);
+    HIP_TRY(hipGetLastError(), "fill launch state");
+  }
+  HIP_TRY(launch_reset_multi(d_ctx, nplans, d_cursor, s), "reset");
+  if (nitems) {
+    CountParams cp;
+    std::memset(&cp, 0, sizeof(cp));
+    cp.many = d_ctx;
+    cp.plan_off = d_off;
+    cp.nplans = nplans;
+    cp.items = nullptr;
+    cp.nitems = (uint32_t)nitems;
+    cp.cursor = d_cursor;
+    one_queue(cp);
+    const int grid = (int)std::min<int64_t>((int64_t)plans[0]->blocks_per_cu * plans[0]->ncu, (int64_t)nitems);
+    HIP_TRY(launch_count_persistent(cp, grid, true, s), "count");
+  }
+  return BBTC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -2181,6 +2291,21 @@ bbtc_status bbtc_count_multi(bbtc_plan* const* plans, int32_t nplans, void* stre
   } catch (const std::bad_alloc&) {
     return fail(BBTC_ENOMEM, "host allocation failed");
   }
+}
+
+bbtc_status bbtc_count_multi_static(bbtc_plan* const* plans, int32_t nplans, void* stream,
+                                    uint64_t* const* d_per_task, uint64_t* d_totals) {
+  g_err.clear();
+  if (nplans < 0 || (nplans > 0 && (!plans || !d_per_task || !d_totals))) return fail(BBTC_EINVAL, "null argument");
+  if (nplans > BBTC_STATIC_MAX_PLANS)
+    return fail(BBTC_EINVAL, "more plans than the static launch state holds (BBTC_STATIC_MAX_PLANS)");
+  if (nplans == 0) return BBTC_OK;
+  for (int32_t q = 0; q < nplans; ++q) {
+    if (!plans[q] || !plans[q]->ready) return fail(BBTC_ESTATE, "plan is not ready");
+    if (plans[q]->streamed) return fail(BBTC_ESTATE, "a streamed (over-budget) plan cannot join a shared launch");
+    if (!d_per_task[q]) return fail(BBTC_EINVAL, "null output");
+  }
+  return count_multi_static_impl(plans, nplans, (hipStream_t)stream, d_per_task, d_totals);
 }
 
 bbtc_status bbtc_count_hybrid(bbtc_plan* pl, void* stream, uint64_t* d_per_task, uint64_t* d_total,
