@@ -63,7 +63,9 @@ def note(msg):
 
 
 def pmc_key(workload, opt):
-    return f"{workload}-p{opt.p}-w{opt.wave_min}-h{opt.hash_min}"
+    """Counter records are keyed by the workload and the effective knobs of the
+    count (0 selects the library defaults, wave_min 32 and hash_min 16)."""
+    return f"{workload}-p{opt.p}-w{opt.wave_min or 32}-h{opt.hash_min or 16}"
 
 
 def timed(fn, reps, sync):

@@ -263,7 +263,9 @@ bbtc_status bbtc_count_multi_static(bbtc_plan* const* plans, int32_t nplans, voi
  * one warm-up) by coordinate descent: first p over {p0/4, p0/2, p0, 2*p0}
  * (p0 = base->p, or the average degree when base->p is 0: Sec. 7.3 of the
  * paper suggests p near the average degree), then wave_min over
- * {16, 32, 64, 128, 256, 512}, then hash_min over {-1, 1, 32, 256}.  The other fields of
+ * {16, 32, 64, 128, 256, 512}, then hash_min over {-1, 1, 32, 256}; a threshold
+ * leaves its current value only for a candidate more than 3% faster (so that
+ * timing noise does not decide between near-equal values).  The other fields of
  * *base are kept.  Every candidate gives identical counts; only time differs.
  * On success *out holds the chosen options and *best_ms (if not NULL) the
  * count time with them.  Synchronises `stream`.

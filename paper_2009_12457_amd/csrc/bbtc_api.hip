@@ -343,6 +343,7 @@ constexpr int kDefaultHashMin = 16;
 constexpr int kDefaultItemRows = 256;
 constexpr uint32_t kHubSplit = 256;   // in-slice length above which a column is split
 constexpr unsigned kHybridMaxThreads = 16;  // default host threads of the hybrid count, at most
+constexpr double kTuneMargin = 0.97;        // the autotuner's thresholds change for a gain above 3% only
 constexpr uint32_t kHubChunk = 1024;  // in-neighbours per hub work item
 constexpr int kItemsPerBlock = 20;    // work items per resident workgroup (by estimated work)
 
@@ -2393,13 +2394,15 @@ bbtc_status bbtc_autotune(const bbtc_csr* g, const bbtc_options* base, int32_t r
       if (st != BBTC_OK) break;
       if (ms < best) { best = ms; best_opt = o; }
     }
+    // the two thresholds move off their current value only for a gain above
+    // the timing noise, so that repeated tunings of one graph agree
     for (int32_t wm : {16, 32, 64, 128, 256, 512}) {  // 512: the whole wavefront stage
       if (st != BBTC_OK) break;
       bbtc_options o = best_opt;
       o.wave_min = wm;
       double ms = 0;
       st = measure(o, &ms);
-      if (st == BBTC_OK && ms < best) { best = ms; best_opt = o; }
+      if (st == BBTC_OK && ms < best * kTuneMargin) { best = ms; best_opt = o; }
     }
     for (int32_t hm : {-1, 1, 32, 256}) {
       if (st != BBTC_OK) break;
@@ -2407,7 +2410,7 @@ bbtc_status bbtc_autotune(const bbtc_csr* g, const bbtc_options* base, int32_t r
       o.hash_min = hm;
       double ms = 0;
       st = measure(o, &ms);
-      if (st == BBTC_OK && ms < best) { best = ms; best_opt = o; }
+      if (st == BBTC_OK && ms < best * kTuneMargin) { best = ms; best_opt = o; }
     }
   } catch (const std::bad_alloc&) {
     st = fail(BBTC_ENOMEM, "host allocation failed");
