@@ -56,6 +56,8 @@ struct WaveScratch {        // per wave: one batch of 64 in-neighbours
 };
 
 struct CountLds {
+  // first member, and the struct aligned to 4 kGroupWords bytes: every stage
+  // buffer starts at a multiple of its own size (bitmap loads OR their offset in)
   uint32_t abuf[4][kABuf];         // per wave: sorted copy / bitmap / hash; all-zero between uses
   WaveScratch w;
   uint32_t c0s[kThreads];          // short columns of a pass, packed: start of N(G_jk,v)
@@ -71,7 +73,7 @@ struct CountLds {
 
 struct TaskCtx {
   int32_t ci, ci1, cj, ck, ck1;
-  int32_t kb;               // bitmap origin: ck rounded down to a multiple of 32
+  int32_t kb;               // ck rounded down to a multiple of 32 (the bitmap covers [kb, ck1))
   int32_t i, dk, dkj;       // i, k-i, k-j
   int32_t si, sj;           // first rows of parts i and j with stored boundaries
   uint32_t stri, strj;      // out-side row strides of parts i and j
@@ -142,6 +144,11 @@ __device__ __forceinline__ TaskCtx make_ctx(const GraphView& g, const DevTask& t
 }
 
 __device__ __forceinline__ uint32_t hash_slot(uint32_t w, int hbits) { return (w * 0x9E3779B1u) >> (32 - hbits); }
+
+// LDS byte address of a pointer into shared memory, and a load from one.
+typedef __attribute__((address_space(3))) const uint32_t* lds_cptr;
+__device__ __forceinline__ uint32_t lds_addr(const uint32_t* p) { return (uint32_t)(uintptr_t)(lds_cptr)p; }
+__device__ __forceinline__ uint32_t lds_load(uint32_t a) { return *(lds_cptr)(uintptr_t)a; }
 
 // Rows up to this many entries are scanned for their block slices, longer
 // ones searched.
@@ -233,13 +240,13 @@ __device__ __forceinline__ uint32_t pieces(const TaskCtx& c, bool use_hash, uint
 
 // Fills buf with col[lo, lo+sn) by `nthr` cooperating threads numbered tid.
 __device__ __forceinline__ void stage_fill(const Stage& st, uint32_t* buf, const int32_t* __restrict__ col,
-                                           uint32_t lo, uint32_t sn, int32_t kb, uint32_t tid, uint32_t nthr) {
+                                           uint32_t lo, uint32_t sn, uint32_t tid, uint32_t nthr) {
   if (st.mode == 0) {
     for (uint32_t t = tid; t < sn; t += nthr) buf[t] = (uint32_t)col[lo + t];
-  } else if (st.mode == 1) {  // bit w - kb
+  } else if (st.mode == 1) {  // bit w mod 32 of word (w / 32) mod nw
     for (uint32_t t = tid; t < sn; t += nthr) {
-      const uint32_t x = (uint32_t)(col[lo + t] - kb);
-      atomicOr(&buf[x >> 5], 1u << (x & 31));
+      const uint32_t x = (uint32_t)col[lo + t];
+      atomicOr(&buf[(x >> 5) & (st.nw - 1)], 1u << (x & 31));
     }
   } else {
     for (uint32_t t = tid; t < sn; t += nthr) {
@@ -252,11 +259,11 @@ __device__ __forceinline__ void stage_fill(const Stage& st, uint32_t* buf, const
 
 // Restores the all-zero buffer after stage_fill.
 __device__ __forceinline__ void stage_clear(const Stage& st, uint32_t* buf, const int32_t* __restrict__ col,
-                                            uint32_t lo, uint32_t sn, int32_t kb, uint32_t tid, uint32_t nthr) {
+                                            uint32_t lo, uint32_t sn, uint32_t tid, uint32_t nthr) {
   if (st.mode == 0) {
     for (uint32_t t = tid; t < sn; t += nthr) buf[t] = 0;
   } else if (st.mode == 1) {
-    for (uint32_t t = tid; t < sn; t += nthr) buf[(uint32_t)(col[lo + t] - kb) >> 5] = 0;
+    for (uint32_t t = tid; t < sn; t += nthr) buf[((uint32_t)col[lo + t] >> 5) & (st.nw - 1)] = 0;
   } else {
     for (uint32_t t = tid; t < st.nw; t += nthr) buf[t] = 0;
   }
@@ -326,14 +333,13 @@ __device__ __forceinline__ uint32_t round_owner(uint32_t* sown, uint32_t sx, uin
 // form, fixed for the whole loop: 1 = bitmap over V_k, 2 = hash, 0 = sorted
 // copy; for 0 and 2 entries outside [smin, smax] cannot match and are
 // skipped.  The bitmap tests all eight positions without branches (every
-// list entry lies in V_k; the others are clamped into the bitmap) and keeps
-// the hits of the list's own positions.
+// position indexes some word of the buffer) and keeps the hits of the list's
+// own positions.
 template <int MODE>
 __device__ __forceinline__ uint32_t probe_rounds(const int32_t* __restrict__ col, uint32_t tot, const uint32_t* sa0,
                                                  const uint32_t* sa1, const uint32_t* sex, uint32_t* sown, uint32_t sx,
                                                  uint32_t ns, uint32_t& rnd, const Stage& st,
-                                                 const uint32_t* buf, uint32_t sn, uint32_t smin, uint32_t smax,
-                                                 uint32_t kb, uint32_t klast) {
+                                                 const uint32_t* buf, uint32_t sn, uint32_t smin, uint32_t smax) {
   const uint32_t l = (uint32_t)lane_id();
   uint32_t cnt = 0;
   for (uint32_t qb = 0; qb < tot; qb += kWave) {
@@ -342,16 +348,16 @@ __device__ __forceinline__ uint32_t probe_rounds(const int32_t* __restrict__ col
     if (q < tot && MODE == 1) {
       uint32_t w[kSegW];
       const uint32_t vm = load_seg_raw(col, sa0[o], sa1[o], q - sex[o], w);
-      // bit w - kb of the bitmap (kb is a multiple of 32, so the bit within
-      // its word is w mod 32); positions outside the list are clamped into
-      // [kb, klast] and their hits dropped by the mask
-      const uint32_t kw = kb >> 5;
+      // bit w mod 32 of word (w / 32) mod nw: one word per 32 consecutive
+      // ids, distinct for the list's ids (all within 32 nw consecutive ids
+      // from a multiple of 32); the other positions read some word of the
+      // buffer and the mask drops their hits
+      // LDS byte address of the word: the buffer's base (aligned to its size)
+      // ORed with the word offset, two instructions per position
+      const uint32_t base = lds_addr(buf), omask = (st.nw - 1) << 2;
       uint32_t wd[kSegW];
 #pragma unroll
-      for (uint32_t t = 0; t < kSegW; ++t) {
-        w[t] = min(max(w[t], kb), klast);
-        wd[t] = buf[(w[t] >> 5) - kw];
-      }
+      for (uint32_t t = 0; t < kSegW; ++t) wd[t] = lds_load(base | ((w[t] >> 3) & omask));
       uint32_t hit = 0;
 #pragma unroll
       for (uint32_t t = 0; t < kSegW; ++t) hit |= __builtin_amdgcn_ubfe(wd[t], w[t], 1u) << t;  // offset taken mod 32
@@ -400,7 +406,6 @@ __device__ uint64_t probe_flat(const TaskCtx& c, uint32_t i0, uint32_t i1, const
   const int32_t* __restrict__ col = c.coli;
   const int32_t* __restrict__ icol = c.icolj;
   const uint32_t l = (uint32_t)lane_id();
-  const uint32_t kb = (uint32_t)c.kb, klast = (uint32_t)(c.ck1 - 1);
   uint64_t cnt = 0;
   uint32_t rnd = 0;
   sown[l] = 0;
@@ -417,13 +422,13 @@ __device__ uint64_t probe_flat(const TaskCtx& c, uint32_t i0, uint32_t i1, const
     wave_sync();
     if (st.mode == 1)
       cnt += probe_rounds<1>(col, tot, sa0, sa1, sex, sown, inc - nseg, nseg, rnd, st, buf, sn, (uint32_t)smin,
-                               (uint32_t)smax, kb, klast);
+                               (uint32_t)smax);
     else if (st.mode == 2)
       cnt += probe_rounds<2>(col, tot, sa0, sa1, sex, sown, inc - nseg, nseg, rnd, st, buf, sn, (uint32_t)smin,
-                               (uint32_t)smax, kb, klast);
+                               (uint32_t)smax);
     else
       cnt += probe_rounds<0>(col, tot, sa0, sa1, sex, sown, inc - nseg, nseg, rnd, st, buf, sn, (uint32_t)smin,
-                               (uint32_t)smax, kb, klast);
+                               (uint32_t)smax);
     wave_sync();
   }
   return cnt;
@@ -438,10 +443,10 @@ __device__ uint64_t wave_col(const TaskCtx& c, uint32_t i0, uint32_t i1, uint32_
   const Stage st = pick_stage<kABuf>(c, use_hash, c1 - c0);
   for (uint32_t s_lo = c0; s_lo < c1; s_lo += st.piece) {
     const uint32_t sn = min(st.piece, c1 - s_lo);
-    stage_fill(st, abuf, col, s_lo, sn, c.kb, l, kWave);
+    stage_fill(st, abuf, col, s_lo, sn, l, kWave);
     wave_sync();
     cnt += probe_flat(c, i0, i1, st, abuf, sn, col[s_lo], col[s_lo + sn - 1], sa0, sa1, sex, sown);
-    stage_clear(st, abuf, col, s_lo, sn, c.kb, l, kWave);
+    stage_clear(st, abuf, col, s_lo, sn, l, kWave);
     wave_sync();
   }
   return cnt;
@@ -676,12 +681,12 @@ __device__ uint64_t group_col(const PlanCtx& cp, const TaskCtx& c, uint32_t i0, 
   uint32_t* buf = &s.abuf[0][0];
   for (uint32_t s_lo = c0; s_lo < c1; s_lo += st.piece) {
     const uint32_t sn = min(st.piece, c1 - s_lo);
-    stage_fill(st, buf, col, s_lo, sn, c.kb, threadIdx.x, kThreads);
+    stage_fill(st, buf, col, s_lo, sn, threadIdx.x, kThreads);
     __syncthreads();
     cnt += probe_flat(c, w0, w1, st, buf, sn, col[s_lo], col[s_lo + sn - 1], s.w.sa0[w], s.w.sa1[w],
                       s.w.sex[w], s.w.sown[w]);
     __syncthreads();
-    stage_clear(st, buf, col, s_lo, sn, c.kb, threadIdx.x, kThreads);
+    stage_clear(st, buf, col, s_lo, sn, threadIdx.x, kThreads);
     __syncthreads();
   }
   return cnt;
@@ -730,7 +735,7 @@ __device__ __forceinline__ uint64_t run_item(const PlanCtx& pc, const DevItem& i
 #define BBTC_COUNT_KERNEL __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8)))
 
 BBTC_COUNT_KERNEL void k_count_items(CountParams cp, uint32_t first) {
-  __shared__ CountLds s;
+  __shared__ __attribute__((aligned(kGroupWords * 4))) CountLds s;
   init_lds(s);
   const PlanCtx& pc = cp.one;
   const DevItem item = ld_const(cp.items + first + blockIdx.x);
@@ -744,7 +749,7 @@ BBTC_COUNT_KERNEL void k_count_items(CountParams cp, uint32_t first) {
 // read from its own plan's item list.
 template <bool MULTI>
 BBTC_COUNT_KERNEL void k_count_persistent(CountParams cp) {
-  __shared__ CountLds s;
+  __shared__ __attribute__((aligned(kGroupWords * 4))) CountLds s;
   init_lds(s);
   // workgroups are dispatched to the XCDs round robin: start on this one's queue
   uint32_t x = blockIdx.x % cp.nq, tried = 0;
