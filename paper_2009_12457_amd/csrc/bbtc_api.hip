@@ -117,6 +117,7 @@ struct bbtc_plan {
   DevBuf<int32_t> perm, order, ocol, icol, cuts, acol;
   DevBuf<uint32_t> od, idg, orow, irow, midrows, longrows, hugerows, bot, ccnt, ccoff, cursor, err, aoff, asrc;
   DevBuf<int32_t> icolb;  // the block-major in side (icol is the vertex-major one it is built from)
+  DevBuf<uint16_t> ocol16;  // out-rows relative to the part of each entry (resident plans)
   DevBuf<uint64_t> acp;
   // Per-part index tables (uploaded together) and per-block statistics with
   // their counters (cleared and read back together), in one allocation:
@@ -179,7 +180,8 @@ struct bbtc_plan {
   std::vector<Slot> slots;       // out-stripe slots
   Slot bslot[2];                 // in-block slots, alternating between block pairs
   uint64_t clock = 0;
-  std::vector<std::pair<int32_t, int32_t>> groups;  // block pairs (i,j), i-major, j alternating direction
+  std::vector<std::pair<int32_t, int32_t>> groups;  // block pairs (i,j) in the walk order (stream_finish)
+  std::vector<std::vector<int64_t>> stripe_uses;    // per part: the walk positions of the pairs reading it
   std::vector<int64_t> group_first, group_count;    // their ranges of the item list
   int64_t copies = 0;            // stripe and block uploads by the last streamed count
   int64_t resident_bytes = 0;    // count-phase bytes with every stripe and block resident
@@ -247,6 +249,7 @@ struct bbtc_plan {
     longrows.release();
     hugerows.release();
     bot.release(); ccnt.release(); ccoff.release(); cursor.release(); aoff.release(); asrc.release(); icolb.release();
+    ocol16.release();
     err.release(); acp.release(); tasks.release(); items.release(); xitems.release(); heavy.release();
     emit.release();
   }
@@ -257,7 +260,7 @@ struct bbtc_plan {
            acol.bytes() + od.bytes() + idg.bytes() + orow.bytes() + irow.bytes() + midrows.bytes() + longrows.bytes() +
            hugerows.bytes() + bot.bytes() +
            ccnt.bytes() + ccoff.bytes() + cursor.bytes() + err.bytes() + acp.bytes() + aoff.bytes() + asrc.bytes() +
-           icolb.bytes() +
+           icolb.bytes() + ocol16.bytes() +
            tasks.bytes() + items.bytes() + xitems.bytes() + heavy.bytes() + emit.bytes() +
            cache.bytes();
   }
@@ -381,6 +384,7 @@ PlanCtx plan_ctx(const bbtc_plan* pl, uint64_t* per_task, uint64_t* total) {
   c.g.botp = pl->botp;
   c.g.bot = pl->bot.ptr;
   c.g.ocol = pl->ocol.ptr;
+  c.g.ocol16 = pl->streamed ? nullptr : pl->ocol16.ptr;
   c.g.acp = pl->acp.ptr;
   c.g.acol = pl->acol.ptr;
   c.g.aoff = pl->aoff.ptr;
@@ -612,11 +616,10 @@ void one_queue(CountParams& cp) {
 // stored block boundaries (two out-stripes) and the in side of block (i,j)
 // (its active columns, in-slice offsets and in-slices), nothing else.  When
 // the plan exceeds the device budget these arrays live in pinned host
-// memory; the device keeps a cache of out-stripe slots (least recently used
-// goes) and two in-block slots, and bbtc_count walks the block pairs i-major
-// with j alternating direction from one i to the next (the out-stripes of
-// the last pairs are still cached for the next), uploading on a side stream
-// gated by events, ahead of the kernels.
+// memory; the device keeps a cache of out-stripe slots (the stripe needed
+// farthest ahead goes) and two in-block slots, and bbtc_count walks the block pairs in
+// column chunks that the cache holds (stream_finish), uploading on a side
+// stream gated by events, ahead of the kernels.
 template <typename T>
 bbtc_status to_pinned(T** dst, const T* src, size_t n, hipStream_t s) {
   HIP_TRY(hipHostMalloc((void**)dst, std::max<size_t>(n, 1) * sizeof(T), hipHostMallocDefault), "pinned alloc");
@@ -654,8 +657,13 @@ BlockSpan block_span(const bbtc_plan* pl, int64_t cid) {
   return b;
 }
 
-// Groups the plan-order work items by block pair, in the walk order, and
-// sets up the slots within the budget.  Needs the pinned arrays in place.
+// Sizes the slots within the budget, then groups the plan-order work items
+// by block pair in the walk order.  The walk takes the columns j in chunks
+// of S = slots - 1 parts: a chunk's out-stripes stay cached while i runs over
+// every part up to the chunk's end (one more slot holds the stripe of an i
+// outside the chunk), so each stripe is uploaded about once per chunk to its
+// right plus once for its own chunk, instead of once per row pass.  Needs
+// the pinned arrays in place.
 bbtc_status stream_finish(bbtc_plan* pl, hipStream_t s) {
   const int32_t p = pl->p;
   const int64_t nb = (int64_t)p * (p + 1) / 2;
@@ -663,12 +671,42 @@ bbtc_status stream_finish(bbtc_plan* pl, hipStream_t s) {
   for (int64_t b = 0; b < nb; ++b) pl->h_acp[b + 1] = pl->h_acp[b] + (uint64_t)pl->h_nzc[b];
   pl->heavy.release();  // the hub records were read back by the partition
   if (pl->h_items.size() != pl->nitems) compose_plan_order(pl);
+  // slot sizes: the largest out-stripe, the largest in-block of a pair with work
+  size_t slot = 16, blk = 16;
+  for (int a = 0; a < p; ++a) slot = std::max(slot, stripe_bytes(pl, a));
+  for (int32_t q : pl->h_work) {
+    const bbtc_task& t = pl->h_tasks[q];
+    blk = std::max(blk, block_span(pl, col_block_id(t.i, t.j)).bytes);
+  }
+  pl->slot_bytes = align16(slot);
+  pl->block_bytes = align16(blk);
+  pl->xitems.release();  // streamed launches walk the plan order, pair by pair
+  {  // every stripe and block resident
+    int64_t all = (int64_t)pl->footprint();
+    for (int a = 0; a < p; ++a) all += (int64_t)stripe_bytes(pl, a);
+    for (int64_t c = 0; c < nb; ++c) all += (int64_t)block_span(pl, c).bytes;
+    pl->resident_bytes = all;
+  }
+  // the cache takes what the budget leaves: two block slots, then out-stripes
+  // (with the item list as it will be once uploaded below)
+  const size_t items_after = pl->items.ptr && pl->items.cap >= pl->nitems
+                                 ? pl->items.bytes()
+                                 : sizeof(DevItem) * std::max<size_t>(pl->nitems, 1);
+  const int64_t fixed = (int64_t)(pl->footprint() - pl->items.bytes() + items_after);
+  const int64_t room = pl->opt.device_budget_bytes - fixed - 2 * (int64_t)pl->block_bytes;
+  const int64_t nslots = room > 0 ? room / (int64_t)pl->slot_bytes : 0;
+  if (nslots < 2)
+    return fail(BBTC_EBUDGET, "device budget holds " + std::to_string(nslots) + " out-stripe slots of " +
+                                  std::to_string(pl->slot_bytes) + " B besides two block slots of " +
+                                  std::to_string(pl->block_bytes) + " B and " + std::to_string(fixed) +
+                                  " B of resident data; a block pair needs 2");
+  const int64_t use = std::min<int64_t>(nslots, p);
+  const int64_t chunk = std::max<int64_t>(1, use - 1);
   std::vector<DevItem> items = pl->h_items;
-  // walk order: i ascending; j ascending for even i, descending for odd i
+  // walk order: column chunk, then i ascending, then j ascending
   auto walk_key = [&](const DevItem& it) {
     const bbtc_task& t = pl->h_tasks[it.task];
-    const int64_t jj = (t.i & 1) ? (p - 1 - t.j) : t.j;
-    return (int64_t)t.i * p + jj;
+    return ((int64_t)(t.j / chunk) * p + t.i) * p + t.j;
   };
   std::stable_sort(items.begin(), items.end(),
                    [&](const DevItem& x, const DevItem& y) { return walk_key(x) < walk_key(y); });
@@ -687,34 +725,17 @@ bbtc_status stream_finish(bbtc_plan* pl, hipStream_t s) {
     }
     pl->group_count.back()++;
   }
+  pl->stripe_uses.assign((size_t)p, {});
+  for (size_t g = 0; g < pl->groups.size(); ++g) {
+    pl->stripe_uses[(size_t)pl->groups[g].first].push_back((int64_t)g);
+    if (pl->groups[g].second != pl->groups[g].first) pl->stripe_uses[(size_t)pl->groups[g].second].push_back((int64_t)g);
+  }
   pl->h_items = items;
-  pl->xitems.release();  // streamed launches walk the plan order, pair by pair
   HIP_TRY(pl->items.ensure(items.size()), "alloc items");
   if (!items.empty())
     HIP_TRY(hipMemcpyAsync(pl->items.ptr, items.data(), sizeof(DevItem) * items.size(), hipMemcpyHostToDevice, s),
             "H2D");
   HIP_TRY(hipStreamSynchronize(s), "sync");
-  size_t slot = 16, blk = 16;
-  for (int a = 0; a < p; ++a) slot = std::max(slot, stripe_bytes(pl, a));
-  for (const auto& g : pl->groups) blk = std::max(blk, block_span(pl, col_block_id(g.first, g.second)).bytes);
-  pl->slot_bytes = align16(slot);
-  pl->block_bytes = align16(blk);
-  {  // every stripe and block resident
-    int64_t all = (int64_t)pl->footprint();
-    for (int a = 0; a < p; ++a) all += (int64_t)stripe_bytes(pl, a);
-    for (int64_t c = 0; c < nb; ++c) all += (int64_t)block_span(pl, c).bytes;
-    pl->resident_bytes = all;
-  }
-  // the cache takes what the budget leaves: two block slots, then out-stripes
-  const int64_t fixed = (int64_t)pl->footprint();
-  const int64_t room = pl->opt.device_budget_bytes - fixed - 2 * (int64_t)pl->block_bytes;
-  const int64_t nslots = room > 0 ? room / (int64_t)pl->slot_bytes : 0;
-  if (nslots < 2)
-    return fail(BBTC_EBUDGET, "device budget holds " + std::to_string(nslots) + " out-stripe slots of " +
-                                  std::to_string(pl->slot_bytes) + " B besides two block slots of " +
-                                  std::to_string(pl->block_bytes) + " B and " + std::to_string(fixed) +
-                                  " B of resident data; a block pair needs 2");
-  const int64_t use = std::min<int64_t>(nslots, p);
   HIP_TRY(pl->cache.ensure((size_t)use * pl->slot_bytes + 2 * pl->block_bytes), "alloc stripe cache");
   pl->slots.assign((size_t)use, bbtc_plan::Slot());
   for (auto& sl : pl->slots) {
@@ -754,7 +775,7 @@ bbtc_status stream_setup(bbtc_plan* pl, hipStream_t s) {
   // release everything the count phase does not read (the out-row pointers
   // stay: the slices of rows without stored boundaries are found by scanning)
   pl->ocol.release(); pl->icol.release(); pl->bot.release(); pl->acol.release(); pl->aoff.release();
-  pl->asrc.release(); pl->icolb.release(); pl->irow.release();
+  pl->asrc.release(); pl->icolb.release(); pl->irow.release(); pl->ocol16.release();
   pl->keys_a.release(); pl->keys_b.release(); pl->hist.release(); pl->partial.release();
   pl->od.release(); pl->idg.release(); pl->order.release();
   pl->longrows.release(); pl->hugerows.release(); pl->midrows.release(); pl->ccnt.release(); pl->ccoff.release();
@@ -768,9 +789,12 @@ hipError_t upload_after(bbtc_plan::Slot& sl, hipStream_t cs) {
   return sl.used ? hipStreamWaitEvent(cs, sl.released, 0) : hipSuccess;
 }
 
-// Returns the slot holding out-stripe a, uploading it (on `cs`) if needed,
-// never evicting a slot listed in `keep`.  -1 if every slot is kept.
-int stripe_slot(bbtc_plan* pl, int a, const std::vector<int>& keep, hipStream_t cs, bbtc_status* st) {
+// Returns the slot holding out-stripe a for the pair at walk position g,
+// uploading it (on `cs`) if needed, never evicting a slot listed in `keep`.
+// The victim is the stripe whose next use in the walk is farthest away (the
+// whole walk is known in advance), ties broken by least recent use.  -1 if
+// every slot is kept.
+int stripe_slot(bbtc_plan* pl, int a, int64_t g, const std::vector<int>& keep, hipStream_t cs, bbtc_status* st) {
   *st = BBTC_OK;
   int victim = -1;
   for (size_t q = 0; q < pl->slots.size(); ++q)
@@ -778,9 +802,20 @@ int stripe_slot(bbtc_plan* pl, int a, const std::vector<int>& keep, hipStream_t 
       pl->slots[q].last = ++pl->clock;
       return (int)q;
     }
+  auto next_use = [&](int key) -> int64_t {
+    if (key < 0) return INT64_MAX;  // empty slot
+    const std::vector<int64_t>& u = pl->stripe_uses[(size_t)key];
+    const auto it = std::lower_bound(u.begin(), u.end(), g);
+    return it == u.end() ? INT64_MAX : *it;
+  };
+  int64_t far = -1;
   for (size_t q = 0; q < pl->slots.size(); ++q) {
     if (std::find(keep.begin(), keep.end(), (int)q) != keep.end()) continue;
-    if (victim < 0 || pl->slots[q].last < pl->slots[victim].last) victim = (int)q;
+    const int64_t nu = next_use(pl->slots[q].key);
+    if (victim < 0 || nu > far || (nu == far && pl->slots[q].last < pl->slots[victim].last)) {
+      victim = (int)q;
+      far = nu;
+    }
   }
   if (victim < 0) return -1;
   bbtc_plan::Slot& sl = pl->slots[victim];
@@ -838,7 +873,7 @@ bbtc_status count_streamed(bbtc_plan* pl, hipStream_t s, uint64_t* d_per_task, u
     const int need[2] = {i, j};
     bbtc_status st = BBTC_OK;
     for (int q = 0; q < 2; ++q) {
-      slot[q] = stripe_slot(pl, need[q], keep, cs, &st);
+      slot[q] = stripe_slot(pl, need[q], (int64_t)g, keep, cs, &st);
       if (st != BBTC_OK) return st;
       if (slot[q] < 0) return fail(BBTC_EBUDGET, "stripe cache too small for one block pair");
       keep.push_back(slot[q]);
@@ -1047,7 +1082,7 @@ int64_t resident_estimate(int64_t n, int64_t nnz, int32_t p, int64_t bound_deg, 
   const int64_t stored = bound_deg < 0 ? n : std::min<int64_t>(n, nnz / (bound_deg + 1));
   int64_t b = (host_input ? rpb * (n + 1) + 4 * nnz : 0);
   b += 16 * n + 8 * n + 8 * n + 8 * (n + 1) + 12 * n;  // keys, perm/order, degrees, row pointers, row lists
-  b += 4 * (m + 4) * 2 + 4 * m * 4 + 4;                // ocol, icol, acol, aoff, asrc, icolb
+  b += 4 * (m + 4) * 2 + 4 * m * 4 + 4 + 2 * (m + 16);  // ocol, icol, acol, aoff, asrc, icolb, ocol16
   b += 4 * (int64_t)(p + 1) * stored;                  // stored block boundaries
   b += 16 * ((int64_t)p * (n / kPrepRows + p) + 1);    // chunk counters and their scans
   b += 12 * (m / 256 + 1) + (int64_t)p * (p + 1) * (p + 2) / 6 * 48 + (64 << 20);  // hubs, tasks, items, slack
@@ -1563,8 +1598,10 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   // over the device budget even to partition: partition in pieces
   if (opt.device_budget_bytes > 0) {
     const int32_t pe = opt.p > 0 ? opt.p : 256;
-    if (resident_estimate(n, nnz, pe, eff_bound_min_deg(opt), !on_device, rp64 ? 8 : 4) > opt.device_budget_bytes)
+    if (resident_estimate(n, nnz, pe, eff_bound_min_deg(opt), !on_device, rp64 ? 8 : 4) > opt.device_budget_bytes) {
+      pl->ocol16.release();  // streamed counts read the four-byte rows
       return partition_budgeted(g, s, pl, t0);
+    }
   }
 
   const size_t rp_bytes = (size_t)(n + 1) * (rp64 ? 8 : 4);
@@ -1796,6 +1833,8 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   HIP_TRY(hipStreamWaitEvent(si, pl->ev_fork, 0), "wait");
   HIP_TRY(launch_acount(bb, (int)nch, si), "active-column counts");
   HIP_TRY(launch_bot(bb, (int)nch, s), "block row index");
+  HIP_TRY(pl->ocol16.ensure((size_t)((m + 7) / 8 * 8 + 8)), "alloc 16-bit out-rows");
+  HIP_TRY(launch_ocol16(pl->ocol.ptr, m, pl->cuts.ptr, p, pl->ocol16.ptr, s), "16-bit out-rows");
   HIP_TRY(hipEventRecord(pl->ev_join[2], si), "event");
   HIP_TRY(hipStreamWaitEvent(s, pl->ev_join[2], 0), "wait");
   HIP_TRY(scan_u32(pl->ccnt.ptr, pl->ccoff.ptr, cc, pl->partial.ptr, s), "scan column counters");

@@ -83,6 +83,10 @@ struct GraphView {
   const uint64_t* botp;
   const uint32_t* bot;
   const int32_t* ocol;
+  // ocol16[e] = ocol[e] - c_k for the part k holding ocol[e] (16 bits; used
+  // only for parts of at most 65536 vertices), same positions, padded to a
+  // multiple of 8 entries; nullptr: not built (streamed plans)
+  const uint16_t* ocol16;
   const uint64_t* acp;
   const int32_t* acol;
   const uint32_t* aoff;
@@ -183,6 +187,10 @@ hipError_t launch_inrows_group(const uint32_t* rp, int32_t* col, const uint32_t*
 hipError_t launch_degree_stats(const uint32_t* od, const uint32_t* idg, int64_t n, int64_t max_deg,
                                unsigned long long* wedges, uint32_t* nshort, hipStream_t s);
 hipError_t launch_cuts(const uint32_t* orow, int64_t n, int32_t p, int mode, int32_t* cuts, hipStream_t s);
+// ocol16[e] = ocol[e] - (first vertex of the part holding ocol[e]) for e < m,
+// zero up to the next multiple of 8.
+hipError_t launch_ocol16(const int32_t* ocol, uint64_t m, const int32_t* cuts, int32_t p, uint16_t* ocol16,
+                         hipStream_t s);
 
 struct BlockBuild {
   int32_t p;

@@ -85,6 +85,7 @@ struct TaskCtx {
   const int32_t* icolj;     // block-major in-side, absolute positions
   const int32_t* acb;       // active columns, absolute indices
   const uint32_t* aob;      // their in-slice offsets, absolute indices
+  const uint16_t* col16;    // resident plans with |V_k| <= 65536: out-rows relative to c_k (else null)
   const int32_t* ac;        // active columns of block (i,j): acb + acp[cid(i,j)]
   const uint32_t* ao;       // their in-slice offsets (one more entry than columns)
 };
@@ -137,6 +138,7 @@ __device__ __forceinline__ TaskCtx make_ctx(const GraphView& g, const DevTask& t
     c.acb = g.acol;
     c.aob = g.aoff;
   }
+  c.col16 = (g.gi < 0 && g.ocol16 != nullptr && c.ck1 - c.ck <= 65536) ? g.ocol16 : nullptr;
   const uint64_t a0 = ld_const(g.acp + col_block_id(t.i, t.j));
   c.ac = c.acb + a0;
   c.ao = c.aob + a0;
@@ -215,7 +217,10 @@ __device__ __forceinline__ uint32_t owner_of(const uint32_t* off, uint32_t a, ui
 
 // How a stage of N(G_jk,v) is held in a buffer of nw words (a power of
 // two): 0 sorted copy, 1 bitmap over V_k, 2 open-addressing hash at load at
-// most 1/2.
+// most 1/2.  The bitmap holds id x at bit x mod 32 of word (x / 32) mod nw,
+// with x = w - c_k when the task reads the 16-bit out-rows (col16) and x = w
+// otherwise; either way the list's ids map to distinct bits when they span
+// at most 32 nw consecutive values from a multiple of 32 (or from c_k).
 struct Stage {
   int mode;
   uint32_t piece;  // entries staged at a time
@@ -227,7 +232,8 @@ template <uint32_t NW>
 __device__ __forceinline__ Stage pick_stage(const TaskCtx& c, bool use_hash, uint32_t len) {
   constexpr int hb = log2i((int)NW);
   if (!use_hash) return Stage{0, NW, NW, hb};
-  if ((uint32_t)(c.ck1 - c.kb) <= NW * 32u) return Stage{1, len, NW, hb};
+  const uint32_t span = c.col16 ? (uint32_t)(c.ck1 - c.ck) : (uint32_t)(c.ck1 - c.kb);
+  if (span <= NW * 32u) return Stage{1, len, NW, hb};
   return Stage{2, NW / 2, NW, hb};
 }
 
@@ -238,14 +244,16 @@ __device__ __forceinline__ uint32_t pieces(const TaskCtx& c, bool use_hash, uint
   return (len + st.piece - 1) / st.piece;
 }
 
-// Fills buf with col[lo, lo+sn) by `nthr` cooperating threads numbered tid.
+// Fills buf with col[lo, lo+sn) by `nthr` cooperating threads numbered tid
+// (a bitmap from the 16-bit copy col16 of the same positions when given).
 __device__ __forceinline__ void stage_fill(const Stage& st, uint32_t* buf, const int32_t* __restrict__ col,
-                                           uint32_t lo, uint32_t sn, uint32_t tid, uint32_t nthr) {
+                                           const uint16_t* __restrict__ col16, uint32_t lo, uint32_t sn,
+                                           uint32_t tid, uint32_t nthr) {
   if (st.mode == 0) {
     for (uint32_t t = tid; t < sn; t += nthr) buf[t] = (uint32_t)col[lo + t];
-  } else if (st.mode == 1) {  // bit w mod 32 of word (w / 32) mod nw
+  } else if (st.mode == 1) {  // bit x mod 32 of word (x / 32) mod nw
     for (uint32_t t = tid; t < sn; t += nthr) {
-      const uint32_t x = (uint32_t)col[lo + t];
+      const uint32_t x = col16 ? (uint32_t)col16[lo + t] : (uint32_t)col[lo + t];
       atomicOr(&buf[(x >> 5) & (st.nw - 1)], 1u << (x & 31));
     }
   } else {
@@ -259,11 +267,15 @@ __device__ __forceinline__ void stage_fill(const Stage& st, uint32_t* buf, const
 
 // Restores the all-zero buffer after stage_fill.
 __device__ __forceinline__ void stage_clear(const Stage& st, uint32_t* buf, const int32_t* __restrict__ col,
-                                            uint32_t lo, uint32_t sn, uint32_t tid, uint32_t nthr) {
+                                            const uint16_t* __restrict__ col16, uint32_t lo, uint32_t sn,
+                                            uint32_t tid, uint32_t nthr) {
   if (st.mode == 0) {
     for (uint32_t t = tid; t < sn; t += nthr) buf[t] = 0;
   } else if (st.mode == 1) {
-    for (uint32_t t = tid; t < sn; t += nthr) buf[((uint32_t)col[lo + t] >> 5) & (st.nw - 1)] = 0;
+    for (uint32_t t = tid; t < sn; t += nthr) {
+      const uint32_t x = col16 ? (uint32_t)col16[lo + t] : (uint32_t)col[lo + t];
+      buf[(x >> 5) & (st.nw - 1)] = 0;
+    }
   } else {
     for (uint32_t t = tid; t < st.nw; t += nthr) buf[t] = 0;
   }
@@ -395,6 +407,64 @@ __device__ __forceinline__ uint32_t probe_rounds(const int32_t* __restrict__ col
   return cnt;
 }
 
+// Segments of the 16-bit out-rows: 8 entries, one aligned 16-byte block.
+__device__ __forceinline__ uint32_t seg_count16(uint32_t a0, uint32_t a1) {
+  return a1 > a0 ? (a1 - (a0 & ~7u) + 7u) / 8u : 0u;
+}
+
+// Segment q of the list col16[a0, a1) as four words of two entries each
+// (entry 2h in the low half of x[h]); returns the mask of the positions that
+// belong to the list.  A q past the list reads its first block under an
+// empty mask.
+__device__ __forceinline__ uint32_t load_seg16(const uint16_t* __restrict__ col, uint32_t a0, uint32_t a1, uint32_t q,
+                                               uint32_t x[4]) {
+  const uint32_t s = (a0 & ~7u) + q * 8u;
+  const bool in = s < a1;
+  const uint32_t s0 = in ? s : (a0 & ~7u);
+  const uint4 v = *reinterpret_cast<const uint4*>(col + s0);
+  x[0] = v.x;
+  x[1] = v.y;
+  x[2] = v.z;
+  x[3] = v.w;
+  const uint32_t lo = a0 > s0 ? a0 - s0 : 0u, hi = min(a1 - s0, 8u);
+  return in ? ((1u << hi) - 1u) & ~((1u << lo) - 1u) : 0u;
+}
+
+// probe_rounds<1> over the 16-bit out-rows: the bitmap holds x = w - c_k, and
+// a segment is one 16-byte load.  Word (x / 32) mod nw as a byte address:
+// bits 5.. of the entry shifted to bits 2.. (low half: x >> 3, high half:
+// x >> 19), masked and ORed into the aligned base; the bit is x mod 32.
+__device__ __forceinline__ uint32_t probe_rounds16(const uint16_t* __restrict__ col, uint32_t tot, const uint32_t* sa0,
+                                                   const uint32_t* sa1, const uint32_t* sex, uint32_t* sown,
+                                                   uint32_t sx, uint32_t ns, uint32_t& rnd, const Stage& st,
+                                                   const uint32_t* buf) {
+  const uint32_t l = (uint32_t)lane_id();
+  const uint32_t base = lds_addr(buf), omask = (st.nw - 1) << 2;
+  uint32_t cnt = 0;
+  for (uint32_t qb = 0; qb < tot; qb += kWave) {
+    const uint32_t o = round_owner(sown, sx, ns, qb, ++rnd, l);
+    const uint32_t q = qb + l;
+    if (q < tot) {
+      uint32_t x[4];
+      const uint32_t vm = load_seg16(col, sa0[o], sa1[o], q - sex[o], x);
+      uint32_t wl[4], wh[4];
+#pragma unroll
+      for (uint32_t h = 0; h < 4; ++h) {
+        wl[h] = lds_load(base | ((x[h] >> 3) & omask));
+        wh[h] = lds_load(base | ((x[h] >> 19) & omask));
+      }
+      uint32_t hit = 0;
+#pragma unroll
+      for (uint32_t h = 0; h < 4; ++h) {
+        hit |= __builtin_amdgcn_ubfe(wl[h], x[h], 1u) << (2 * h);
+        hit |= __builtin_amdgcn_ubfe(wh[h], x[h] >> 16, 1u) << (2 * h + 1);
+      }
+      cnt += __popc(hit & vm);
+    }
+  }
+  return cnt;
+}
+
 // One wavefront tests every w of N(G_ik,u), for the in-neighbours
 // u = icol[i0..i1), against the stage.  The probe space is cut into segments
 // of kSegW consecutive entries of one N(G_ik,u); a wavefront prefix sum over
@@ -406,6 +476,8 @@ __device__ uint64_t probe_flat(const TaskCtx& c, uint32_t i0, uint32_t i1, const
   const int32_t* __restrict__ col = c.coli;
   const int32_t* __restrict__ icol = c.icolj;
   const uint32_t l = (uint32_t)lane_id();
+  // a bitmap stage probed with the 16-bit out-rows: 8 entries per 16 bytes
+  const bool c16 = c.col16 != nullptr && st.mode == 1;
   uint64_t cnt = 0;
   uint32_t rnd = 0;
   sown[l] = 0;
@@ -413,14 +485,16 @@ __device__ uint64_t probe_flat(const TaskCtx& c, uint32_t i0, uint32_t i1, const
     const uint32_t e = eb + l;
     uint32_t a0 = 0, a1 = 0;
     if (e < i1) out_slice_i(c, icol[e], a0, a1);
-    const uint32_t nseg = seg_count_w(a0, a1);
+    const uint32_t nseg = c16 ? seg_count16(a0, a1) : seg_count_w(a0, a1);
     const uint32_t inc = wave_incl_scan_u32(nseg);
     const uint32_t tot = last_lane(inc);
     sa0[l] = a0;
     sa1[l] = a1;
     sex[l] = inc - nseg;
     wave_sync();
-    if (st.mode == 1)
+    if (c16)
+      cnt += probe_rounds16(c.col16, tot, sa0, sa1, sex, sown, inc - nseg, nseg, rnd, st, buf);
+    else if (st.mode == 1)
       cnt += probe_rounds<1>(col, tot, sa0, sa1, sex, sown, inc - nseg, nseg, rnd, st, buf, sn, (uint32_t)smin,
                                (uint32_t)smax);
     else if (st.mode == 2)
@@ -443,10 +517,10 @@ __device__ uint64_t wave_col(const TaskCtx& c, uint32_t i0, uint32_t i1, uint32_
   const Stage st = pick_stage<kABuf>(c, use_hash, c1 - c0);
   for (uint32_t s_lo = c0; s_lo < c1; s_lo += st.piece) {
     const uint32_t sn = min(st.piece, c1 - s_lo);
-    stage_fill(st, abuf, col, s_lo, sn, l, kWave);
+    stage_fill(st, abuf, col, c.col16, s_lo, sn, l, kWave);
     wave_sync();
     cnt += probe_flat(c, i0, i1, st, abuf, sn, col[s_lo], col[s_lo + sn - 1], sa0, sa1, sex, sown);
-    stage_clear(st, abuf, col, s_lo, sn, l, kWave);
+    stage_clear(st, abuf, col, c.col16, s_lo, sn, l, kWave);
     wave_sync();
   }
   return cnt;
@@ -681,12 +755,12 @@ __device__ uint64_t group_col(const PlanCtx& cp, const TaskCtx& c, uint32_t i0, 
   uint32_t* buf = &s.abuf[0][0];
   for (uint32_t s_lo = c0; s_lo < c1; s_lo += st.piece) {
     const uint32_t sn = min(st.piece, c1 - s_lo);
-    stage_fill(st, buf, col, s_lo, sn, threadIdx.x, kThreads);
+    stage_fill(st, buf, col, c.col16, s_lo, sn, threadIdx.x, kThreads);
     __syncthreads();
     cnt += probe_flat(c, w0, w1, st, buf, sn, col[s_lo], col[s_lo + sn - 1], s.w.sa0[w], s.w.sa1[w],
                       s.w.sex[w], s.w.sown[w]);
     __syncthreads();
-    stage_clear(st, buf, col, s_lo, sn, threadIdx.x, kThreads);
+    stage_clear(st, buf, col, c.col16, s_lo, sn, threadIdx.x, kThreads);
     __syncthreads();
   }
   return cnt;

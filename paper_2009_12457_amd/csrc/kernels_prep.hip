@@ -923,6 +923,42 @@ __global__ __launch_bounds__(kThreads) void k_cuts(const uint32_t* __restrict__ 
   }
 }
 
+// ------------------------------------------------------------ 16-bit out-rows
+// Each column index relative to the first vertex of its part: for parts of
+// at most 65536 vertices the counting kernels gather these two-byte entries
+// instead of the four-byte ones.  Eight entries (one 16-byte store) per
+// thread; the part by binary search in the cut vector, staged in LDS.
+__global__ __launch_bounds__(kThreads) void k_ocol16(const int32_t* __restrict__ ocol, uint64_t m,
+                                                     const int32_t* __restrict__ cuts, int32_t p,
+                                                     uint16_t* __restrict__ ocol16) {
+  __shared__ int32_t sc[kMaxP + 1];
+  for (int a = threadIdx.x; a <= p; a += kThreads) sc[a] = cuts[a];
+  __syncthreads();
+  const uint64_t stride = (uint64_t)gridDim.x * kThreads * 8;
+  for (uint64_t e0 = ((uint64_t)blockIdx.x * kThreads + threadIdx.x) * 8; e0 < m; e0 += stride) {
+    uint32_t h[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      h[t] = 0;
+      if (e0 + t < m) {
+        const int32_t w = ocol[e0 + t];
+        int lo = 0, hi = p;  // largest a with cuts[a] <= w
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (sc[mid] <= w) lo = mid; else hi = mid;
+        }
+        h[t] = (uint32_t)(w - sc[lo]) & 0xFFFFu;
+      }
+    }
+    uint4 v;
+    v.x = h[0] | (h[1] << 16);
+    v.y = h[2] | (h[3] << 16);
+    v.z = h[4] | (h[5] << 16);
+    v.w = h[6] | (h[7] << 16);
+    *reinterpret_cast<uint4*>(ocol16 + e0) = v;
+  }
+}
+
 // ------------------------------------------------------------ in-rows by part
 // The counting kernels need an in-row only grouped by the part of each entry
 // (parts in increasing order), not sorted.  Listed rows (the long and huge
@@ -1480,6 +1516,15 @@ hipError_t launch_icolb(const uint32_t* aoff, const uint32_t* asrc, const int32_
 
 __global__ void k_set_at(uint32_t* __restrict__ arr, const uint32_t* __restrict__ idx, uint32_t value) {
   if (threadIdx.x == 0) arr[*idx] = value;
+}
+
+hipError_t launch_ocol16(const int32_t* ocol, uint64_t m, const int32_t* cuts, int32_t p, uint16_t* ocol16,
+                         hipStream_t s) {
+  if (m == 0) return hipSuccess;
+  const uint64_t groups = (m + 8ull * kThreads - 1) / (8ull * kThreads);
+  hipLaunchKernelGGL(k_ocol16, dim3((unsigned)std::min<uint64_t>(groups, 65536)), dim3(kThreads), 0, s, ocol, m, cuts,
+                     p, ocol16);
+  return hipGetLastError();
 }
 
 hipError_t launch_set_at(uint32_t* arr, const uint32_t* idx, uint32_t value, hipStream_t s) {
