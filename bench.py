@@ -411,6 +411,8 @@ def options_for(args, name, stream, g):
         opt.wave_min = args.wave_min
     if args.hash_min:
         opt.hash_min = args.hash_min
+    if args.bound_min_deg:
+        opt.bound_min_deg = args.bound_min_deg
     tuned = None
     if args.autotune == "on" or (args.autotune == "auto" and name in AUTOTUNED and not args.p):
         n, rp, ci = bb.csr_of(g, "cuda")
@@ -489,6 +491,8 @@ def main():
     ap.add_argument("--p", type=int, default=0, help="fix p (no autotuning)")
     ap.add_argument("--wave-min", type=int, default=0)
     ap.add_argument("--hash-min", type=int, default=0)
+    ap.add_argument("--bound-min-deg", type=int, default=0,
+                    help="rows of undirected degree above this store block boundaries (-1: every row)")
     ap.add_argument("--no-companion", action="store_true",
                     help="skip Erdos-Renyi 2^24 beside R-MAT scale 24 (the headline configuration has both)")
     ap.add_argument("--no-small", action="store_true", help="skip the 2000-vertex and scale-20 configurations")

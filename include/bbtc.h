@@ -115,11 +115,15 @@ typedef struct bbtc_csr {
  *                 beside two in-block slots.
  *   bound_min_deg the block row index (Sec. 4.1) stores, for a vertex of
  *                 undirected degree above bound_min_deg, the position of each
- *                 block's slice in its out-row and in-row; rows of lower
- *                 degree (a prefix of the degree order) store nothing and the
- *                 counting kernels find their slices by scanning the short
- *                 row.  The stored index then stays small for any p.
- *                 0 = default (32); -1 = store every row.
+ *                 block's slice in its out-row; rows of lower degree (a
+ *                 prefix of the degree order) store nothing and the counting
+ *                 kernels find their slices by scanning the short row.  The
+ *                 stored index then stays small for any p.  0 = automatic:
+ *                 the smallest of {0, 8, 16, 32} whose stored boundaries take
+ *                 at most 4m bytes (the size of the out-rows), else 32 (and
+ *                 32 for plans partitioned in pieces within a device budget,
+ *                 whose boundaries stream with the out-rows); -1 = store
+ *                 every row.
  */
 typedef struct bbtc_options {
   int32_t p;
@@ -170,6 +174,8 @@ typedef struct bbtc_stats {
   int64_t stripe_bytes; /* bytes per stripe slot */
   int64_t stripe_uploads; /* stripe and block uploads by the last bbtc_count (streamed plans) */
   int64_t resident_bytes; /* device bytes of the count phase with every stripe and block resident */
+  int64_t stored_rows;    /* rows with stored block boundaries (ranks n - stored_rows .. n-1) */
+  int64_t bound_bytes;    /* bytes of the stored block boundaries */
 } bbtc_stats;
 
 typedef struct bbtc_plan bbtc_plan;

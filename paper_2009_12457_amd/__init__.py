@@ -65,7 +65,8 @@ class bbtc_stats(ctypes.Structure):
                 ("bytes_colidx", ctypes.c_int64), ("bytes_rowidx", ctypes.c_int64),
                 ("bytes_total", ctypes.c_int64), ("footprint", ctypes.c_int64), ("partition_ms", ctypes.c_double),
                 ("streamed", ctypes.c_int64), ("stripe_slots", ctypes.c_int64), ("stripe_bytes", ctypes.c_int64),
-                ("stripe_uploads", ctypes.c_int64), ("resident_bytes", ctypes.c_int64)]
+                ("stripe_uploads", ctypes.c_int64), ("resident_bytes", ctypes.c_int64),
+                ("stored_rows", ctypes.c_int64), ("bound_bytes", ctypes.c_int64)]
 
 
 class bbtc_hybrid_stats(ctypes.Structure):

@@ -356,11 +356,40 @@ int eff_wave_min(const bbtc_options& o) {
   if (o.mode == BBTC_MODE_PLAIN_HMAP) return 1;
   return o.wave_min > 0 ? o.wave_min : kDefaultWaveMin;
 }
-// Rows of undirected degree at most this keep no stored block boundaries.
-constexpr int kDefaultBoundMinDeg = 32;
-int64_t eff_bound_min_deg(const bbtc_options& o) {
-  return o.bound_min_deg == 0 ? kDefaultBoundMinDeg : (int64_t)o.bound_min_deg;
+// Rows of undirected degree at most the threshold keep no stored block
+// boundaries.  Automatic (bound_min_deg 0): the smallest of kAutoBound whose
+// stored boundaries take at most the 4m bytes of the out-rows (a probe of a
+// row with stored boundaries reads one cache line of them; a short row
+// without them is scanned, which reads its row pointers and the row), else
+// the largest.
+constexpr int kAutoBound[4] = {0, 8, 16, 32};
+DegThresholds bound_thresholds(const bbtc_options& o) {
+  DegThresholds th;
+  for (int q = 0; q < 4; ++q) th.t[q] = o.bound_min_deg == 0 ? kAutoBound[q] : (int64_t)o.bound_min_deg;
+  return th;
 }
+// Bytes of stored boundaries when ranks from rT on store them.
+uint64_t bound_bytes(const std::vector<int32_t>& cuts, int32_t p, int64_t rT) {
+  uint64_t b = 0;
+  for (int32_t a = 0; a < p; ++a) {
+    const int64_t sa = std::max<int64_t>(0, cuts[a + 1] - std::max<int64_t>(cuts[a], rT));
+    b += 4ull * (uint64_t)(p - a + 1) * (uint64_t)sa;
+  }
+  return b;
+}
+// The first rank with stored boundaries, from the four counts of
+// k_degree_stats and the cut vector.  Plans built within a device budget
+// stream their out-stripes with the boundaries, so there the automatic
+// threshold stays at the largest candidate.
+int64_t choose_rT(const bbtc_options& o, const uint32_t cnt[4], const std::vector<int32_t>& cuts, int32_t p,
+                  uint64_t m, bool budgeted) {
+  if (o.bound_min_deg != 0) return cnt[0];
+  if (budgeted) return cnt[3];
+  for (int q = 0; q < 4; ++q)
+    if (bound_bytes(cuts, p, cnt[q]) <= 4 * m) return cnt[q];
+  return cnt[3];
+}
+
 int eff_hash_min(const bbtc_options& o) {
   if (o.mode == BBTC_MODE_PLAIN_INTERSECT) return -1;
   if (o.mode == BBTC_MODE_PLAIN_HMAP) return 1;
@@ -1044,6 +1073,8 @@ bbtc_status finish_partition(bbtc_plan* pl, hipStream_t s, uint64_t m, uint64_t 
   st.d_max = hd[1];
   st.c = st.d_max_block > 0 ? (double)st.d_max / (double)st.d_max_block : 0.0;
   st.wedges = (int64_t)wedges;
+  st.stored_rows = n - pl->rT;
+  st.bound_bytes = (int64_t)bound_bytes(pl->h_cuts, p, pl->rT);
   st.bytes_colidx = 4 * (int64_t)(p + 2) * (int64_t)m;
   int64_t rowidx = 0;
   for (const auto& t : pl->h_tasks)
@@ -1079,7 +1110,9 @@ bbtc_status finish_partition(bbtc_plan* pl, hipStream_t s, uint64_t m, uint64_t 
 // Upper bound of the device bytes of a resident partition.
 int64_t resident_estimate(int64_t n, int64_t nnz, int32_t p, int64_t bound_deg, bool host_input, int64_t rpb) {
   const int64_t m = nnz / 2;
-  const int64_t stored = bound_deg < 0 ? n : std::min<int64_t>(n, nnz / (bound_deg + 1));
+  const int64_t bd = bound_deg == 0 ? kAutoBound[3] : bound_deg;  // 0: automatic (at most 4m bytes, or as at 32)
+  int64_t stored = bd < 0 ? n : std::min<int64_t>(n, nnz / (bd + 1));
+  if (bound_deg == 0) stored = std::max<int64_t>(stored, m / (p + 1));
   int64_t b = (host_input ? rpb * (n + 1) + 4 * nnz : 0);
   b += 16 * n + 8 * n + 8 * n + 8 * (n + 1) + 12 * n;  // keys, perm/order, degrees, row pointers, row lists
   b += 4 * (m + 4) * 2 + 4 * m * 4 + 4 + 2 * (m + 16);  // ocol, icol, acol, aoff, asrc, icolb, ocol16
@@ -1193,7 +1226,7 @@ bbtc_status partition_budgeted(const bbtc_csr* g, hipStream_t s, bbtc_plan* pl,
     HIP_TRY(B.crp.ensure((B.max_rows + 1) * B.rpb), "alloc chunk rows");
     HIP_TRY(B.ccol.ensure(B.max_ent), "alloc chunk entries");
   }
-  HIP_TRY(pl->err.ensure(8), "alloc");
+  HIP_TRY(pl->err.ensure(16), "alloc");
   HIP_TRY(pl->longrows.ensure(B.max_rows), "alloc");
   HIP_TRY(pl->hugerows.ensure(B.max_rows), "alloc");
   HIP_TRY(B.hpref.ensure(B.max_rows + 1), "alloc");
@@ -1269,22 +1302,23 @@ bbtc_status partition_budgeted(const bbtc_csr* g, hipStream_t s, bbtc_plan* pl,
   bbtc_status st = B.pass(pl->od.ptr, pl->idg.ptr, check_in_degs, 0, (int32_t)n, nullptr, nullptr);
   if (st != BBTC_OK) return st;
   unsigned long long* d_wedges = (unsigned long long*)(pl->err.ptr + 6);
-  HIP_TRY(launch_degree_stats(pl->od.ptr, pl->idg.ptr, n, eff_bound_min_deg(opt), d_wedges, pl->err.ptr + 1, s),
+  HIP_TRY(hipMemsetAsync(pl->err.ptr + 8, 0, 16, s), "memset");
+  HIP_TRY(launch_degree_stats(pl->od.ptr, pl->idg.ptr, n, bound_thresholds(opt), d_wedges, pl->err.ptr + 8, s),
           "degree statistics");
   HIP_TRY(pl->orow.ensure((size_t)n + 1), "alloc orow");
   HIP_TRY(pl->irow.ensure((size_t)n + 1), "alloc irow");
   HIP_TRY(scan_u32(pl->od.ptr, pl->orow.ptr, (uint64_t)n, pl->partial.ptr, s), "scan out-degrees");
   HIP_TRY(scan_u32(pl->idg.ptr, pl->irow.ptr, (uint64_t)n, pl->partial.ptr, s), "scan in-degrees");
   std::vector<uint32_t> horow((size_t)n + 1), hirow((size_t)n + 1);
-  uint32_t eb[4] = {0, 0, 0, 0};
+  uint32_t eb[12] = {0};
   uint64_t wedges = 0;
   HIP_TRY(hipMemcpyAsync(horow.data(), pl->orow.ptr, 4 * (n + 1), hipMemcpyDeviceToHost, s), "D2H orow");
   HIP_TRY(hipMemcpyAsync(hirow.data(), pl->irow.ptr, 4 * (n + 1), hipMemcpyDeviceToHost, s), "D2H irow");
-  HIP_TRY(hipMemcpyAsync(eb, pl->err.ptr, 8, hipMemcpyDeviceToHost, s), "D2H err");
+  HIP_TRY(hipMemcpyAsync(eb, pl->err.ptr, sizeof(eb), hipMemcpyDeviceToHost, s), "D2H err");
   HIP_TRY(hipMemcpyAsync(&wedges, d_wedges, 8, hipMemcpyDeviceToHost, s), "D2H wedges");
   HIP_TRY(hipStreamSynchronize(s), "sync");
   if (eb[0]) return decode_device_err(eb[0]);
-  pl->rT = (int64_t)eb[1];
+  const uint32_t* nshort = eb + 8;  // ranks at or below each degree threshold
   const uint64_t m = horow[n];
   if (m > (uint64_t)nnz / 2 || hirow[n] != horow[n]) return fail(BBTC_EINVAL, "input is not symmetric");
   pl->m = (int64_t)m;
@@ -1302,6 +1336,8 @@ bbtc_status partition_budgeted(const bbtc_csr* g, hipStream_t s, bbtc_plan* pl,
   HIP_TRY(launch_cuts(pl->orow.ptr, n, p, opt.cut_mode, pl->cuts.ptr, s), "cuts");
   pl->h_cuts.assign((size_t)p + 1, 0);
   HIP_TRY(hipMemcpyAsync(pl->h_cuts.data(), pl->cuts.ptr, 4 * (p + 1), hipMemcpyDeviceToHost, s), "D2H cuts");
+  HIP_TRY(hipStreamSynchronize(s), "sync");
+  pl->rT = choose_rT(opt, nshort, pl->h_cuts, p, m, true);
   HIP_TRY(hipStreamSynchronize(s), "sync");
   const std::vector<int32_t>& cuts = pl->h_cuts;
   const int64_t nb = (int64_t)p * (p + 1) / 2;
@@ -1598,7 +1634,7 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   // over the device budget even to partition: partition in pieces
   if (opt.device_budget_bytes > 0) {
     const int32_t pe = opt.p > 0 ? opt.p : 256;
-    if (resident_estimate(n, nnz, pe, eff_bound_min_deg(opt), !on_device, rp64 ? 8 : 4) > opt.device_budget_bytes) {
+    if (resident_estimate(n, nnz, pe, opt.bound_min_deg, !on_device, rp64 ? 8 : 4) > opt.device_budget_bytes) {
       pl->ocol16.release();  // streamed counts read the four-byte rows
       return partition_budgeted(g, s, pl, t0);
     }
@@ -1620,7 +1656,7 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   // Trusted input (host or device): the degree pass checks the rest below.
   const int check_in_degs = symmetric_check ? 0 : 1;
   if (on_device && symmetric_check) {
-    HIP_TRY(pl->err.ensure(8), "alloc");
+    HIP_TRY(pl->err.ensure(16), "alloc");
     HIP_TRY(pl->longrows.ensure((size_t)n), "alloc");
     HIP_TRY(pl->hugerows.ensure((size_t)n), "alloc");
     HIP_TRY(pl->irow.ensure((size_t)n + 1), "alloc");  // chunk-prefix scratch for the validation kernels
@@ -1651,7 +1687,7 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   HIP_TRY(pl->irow.ensure((size_t)n + 1), "alloc irow");
   HIP_TRY(pl->longrows.ensure((size_t)n), "alloc");
   HIP_TRY(pl->hugerows.ensure((size_t)n), "alloc");
-  HIP_TRY(pl->err.ensure(8), "alloc");
+  HIP_TRY(pl->err.ensure(16), "alloc");
   HIP_TRY(hipMemsetAsync(pl->err.ptr, 0, 8 * sizeof(uint32_t), s), "memset");
   uint64_t* sorted = nullptr;
   HIP_TRY(launch_degkey(rowptr, rp64, n, pl->idbits, pl->keys_a.ptr, s), "degkey");
@@ -1671,7 +1707,8 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   // while od/idg are degrees: the wedge count W (Sec. 4.4's work measure)
   // and the first rank whose block boundaries are stored
   unsigned long long* d_wedges = (unsigned long long*)(pl->err.ptr + 6);
-  HIP_TRY(launch_degree_stats(pl->od.ptr, pl->idg.ptr, n, eff_bound_min_deg(opt), d_wedges, pl->err.ptr + 1, s),
+  HIP_TRY(hipMemsetAsync(pl->err.ptr + 8, 0, 16, s), "memset");
+  HIP_TRY(launch_degree_stats(pl->od.ptr, pl->idg.ptr, n, bound_thresholds(opt), d_wedges, pl->err.ptr + 8, s),
           "degree statistics");
   HIP_TRY(scan_u32(pl->od.ptr, pl->orow.ptr, (uint64_t)n, pl->partial.ptr, s), "scan out-degrees");
   HIP_TRY(scan_u32(pl->idg.ptr, pl->irow.ptr, (uint64_t)n, pl->partial.ptr, s), "scan in-degrees");
@@ -1681,10 +1718,11 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   HIP_TRY(hipMemcpyAsync(&mm[1], pl->irow.ptr + n, 4, hipMemcpyDeviceToHost, s), "D2H m");
   HIP_TRY(hipMemcpyAsync(&mm[2], pl->err.ptr, 4, hipMemcpyDeviceToHost, s), "D2H err");
   HIP_TRY(hipMemcpyAsync(&mm[4], d_wedges, 8, hipMemcpyDeviceToHost, s), "D2H wedges");
-  HIP_TRY(hipMemcpyAsync(&mm[3], pl->err.ptr + 1, 4, hipMemcpyDeviceToHost, s), "D2H short rows");
+  HIP_TRY(hipMemcpyAsync(&mm[8], pl->err.ptr + 8, 16, hipMemcpyDeviceToHost, s), "D2H short rows");
   HIP_TRY(hipStreamSynchronize(s), "sync");
   if (mm[2]) return decode_device_err(mm[2]);
-  pl->rT = (int64_t)mm[3];
+  uint32_t nshort[4];  // ranks at or below each degree threshold
+  std::memcpy(nshort, &mm[8], sizeof(nshort));
   uint64_t wedges = 0;
   std::memcpy(&wedges, &mm[4], 8);
   const uint64_t m = mm[0];
@@ -1740,6 +1778,7 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
           "group in-rows");
   HIP_TRY(hipEventSynchronize(pl->ev_cuts), "sync");
   pl->h_cuts.assign((const int32_t*)pl->cstage.ptr, (const int32_t*)pl->cstage.ptr + p + 1);
+  pl->rT = choose_rT(opt, nshort, pl->h_cuts, p, m, false);
 
   // ---- block row index (out side, on s after the out-row sort) and the
   // block-major in side (on side[2] after the in-row grouping) ----

@@ -182,9 +182,13 @@ hipError_t launch_inrows_sort(const uint32_t* rp, int32_t* col, int64_t nrows, u
                               uint32_t* hugerows, uint32_t* q, hipStream_t s);
 hipError_t launch_inrows_group(const uint32_t* rp, int32_t* col, const uint32_t* longrows, const uint32_t* hugerows,
                                const uint32_t* q, int32_t* scratch, const int32_t* cuts, int32_t p, hipStream_t s);
+// Four degree thresholds (a negative one counts no rank).
+struct DegThresholds {
+  int64_t t[4];
+};
 // *wedges += sum over r < n of od[r] * idg[r] (the wedge count W) and
-// *nshort += #{r : od[r] + idg[r] <= max_deg} (max_deg < 0: none).
-hipError_t launch_degree_stats(const uint32_t* od, const uint32_t* idg, int64_t n, int64_t max_deg,
+// nshort[q] += #{r : od[r] + idg[r] <= th.t[q]} for q < 4.
+hipError_t launch_degree_stats(const uint32_t* od, const uint32_t* idg, int64_t n, const DegThresholds& th,
                                unsigned long long* wedges, uint32_t* nshort, hipStream_t s);
 hipError_t launch_cuts(const uint32_t* orow, int64_t n, int32_t p, int mode, int32_t* cuts, hipStream_t s);
 // ocol16[e] = ocol[e] - (first vertex of the part holding ocol[e]) for e < m,

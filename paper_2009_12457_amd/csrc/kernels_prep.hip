@@ -1285,36 +1285,42 @@ __global__ __launch_bounds__(kThreads) void k_icolb_heavy(const HeavyCol* __rest
 // W = sum over ranks r of in-degree(r) * out-degree(r): the number of
 // oriented two-paths x -> r -> y, i.e. the probe volume of a per-vertex
 // list count over the degree-ordered graph (the work measure of Sec. 4.4);
-// and the number of ranks whose undirected degree is at most max_deg, which
-// is where stored block boundaries start (degrees rise with rank).  Integer,
-// so the order of the atomic additions does not matter.
+// and, for each of four degree thresholds, the number of ranks whose
+// undirected degree is at most it, which is where stored block boundaries
+// start for that threshold (degrees rise with rank).  Integer, so the order
+// of the atomic additions does not matter.
 __global__ __launch_bounds__(kThreads) void k_degree_stats(const uint32_t* __restrict__ od,
-                                                           const uint32_t* __restrict__ idg, int64_t n,
-                                                           int64_t max_deg, unsigned long long* __restrict__ wedges,
+                                                           const uint32_t* __restrict__ idg, int64_t n, DegThresholds th,
+                                                           unsigned long long* __restrict__ wedges,
                                                            uint32_t* __restrict__ nshort) {
   __shared__ unsigned long long red[4];
-  unsigned long long acc = 0, cnt = 0;
+  unsigned long long acc = 0, cnt[4] = {0, 0, 0, 0};
   for (int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x; r < n; r += (int64_t)gridDim.x * kThreads) {
     const uint32_t o = od[r], i = idg[r];
     acc += (unsigned long long)o * (unsigned long long)i;
-    cnt += ((int64_t)o + (int64_t)i <= max_deg) ? 1ull : 0ull;
+    const int64_t d = (int64_t)o + (int64_t)i;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) cnt[t] += d <= th.t[t] ? 1ull : 0ull;
   }
   acc = block256_sum_u64(acc, red);
-  cnt = block256_sum_u64(cnt, red);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) cnt[t] = block256_sum_u64(cnt[t], red);
   if (threadIdx.x == 0) {
     if (acc) atomicAdd(wedges, acc);
-    if (cnt) atomicAdd(nshort, (uint32_t)cnt);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      if (cnt[t]) atomicAdd(nshort + t, (uint32_t)cnt[t]);
   }
 }
 
 }  // namespace
 
 // ------------------------------------------------------------ launchers
-hipError_t launch_degree_stats(const uint32_t* od, const uint32_t* idg, int64_t n, int64_t max_deg,
+hipError_t launch_degree_stats(const uint32_t* od, const uint32_t* idg, int64_t n, const DegThresholds& th,
                                unsigned long long* wedges, uint32_t* nshort, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_degree_stats, dim3(grid_for((uint64_t)n, kThreads, 2048)), dim3(kThreads), 0, s, od, idg, n,
-                     max_deg, wedges, nshort);
+                     th, wedges, nshort);
   return hipGetLastError();
 }
 

@@ -366,18 +366,32 @@ def test_plan_stats_wedges():
         assert plan.stats()["wedges"] == want
 
 
-@pytest.mark.parametrize("bound_min_deg", [-1, 1, 8, 32, 1 << 30])
+@pytest.mark.parametrize("bound_min_deg", [-1, 0, 1, 8, 32, 1 << 30])
 def test_block_boundary_layouts_are_exact(bound_min_deg):
     """Rows of degree at most bound_min_deg keep no stored block boundaries
     and the kernels scan or search them instead: every split, from all rows
-    stored (-1) to none (2^30, where hub rows are searched too), gives the
-    oracle's per-task counts, with uniform and balanced cuts, in the
-    persistent and both plain modes."""
+    stored (-1) to none (2^30, where hub rows are searched too), and the
+    automatic choice (0), gives the oracle's per-task counts, with uniform
+    and balanced cuts, in the persistent and both plain modes."""
     for name, p in (("rmat13", 3), ("rmat13", 64), ("rmat12_ef32", 20)):
         g = graphgen.workload(name)
+        og = oracle_for(g)
+        deg = np.sort(og.degree())  # degrees in rank order
         for mode in MODES.values():
             plan, per, tot = run(g, p=p, mode=mode, bound_min_deg=bound_min_deg)
             check(g, plan, per, tot, deep=False)
+            st = plan.stats()
+            rT = st["n"] - st["stored_rows"]
+            cuts = plan.cuts().astype(np.int64)
+            want_bytes = sum(4 * (p - a + 1) * max(0, cuts[a + 1] - max(cuts[a], rT)) for a in range(p))
+            assert st["bound_bytes"] == want_bytes
+            if bound_min_deg > 0 or bound_min_deg == -1:  # explicit: the ranks of degree at most the threshold
+                assert rT == (int(np.searchsorted(deg, bound_min_deg, side="right")) if bound_min_deg > 0 else 0)
+            else:  # automatic: the smallest threshold of {0, 8, 16, 32} within 4m bytes, else 32
+                fits = [t for t in (0, 8, 16, 32) if sum(4 * (p - a + 1) * max(0, cuts[a + 1] - max(
+                    cuts[a], int(np.searchsorted(deg, t, side="right")))) for a in range(p)) <= 4 * st["m"]]
+                t = fits[0] if fits else 32
+                assert rT == int(np.searchsorted(deg, t, side="right"))
         plan, per, tot = run(g, p=p, cut_mode=bb.BBTC_CUT_UNIFORM, bound_min_deg=bound_min_deg)
         check(g, plan, per, tot, cut_mode=bb.BBTC_CUT_UNIFORM, deep=False)
     # hub columns split into chunk items, with the hub row stored or searched
