@@ -305,9 +305,10 @@ void bbtc_plan_destroy(bbtc_plan* plan);
  * bbtc_tables: host arrays of one plan.  n vertices, m oriented edges, p
  * parts, cut vector cuts[p+1]; out-rows orow[n+1]/ocol[m] (ranks above the
  * row's rank, ascending).  Ranks below rT store no block boundaries; part a
- * stores the rows max(cuts[a], rT) .. cuts[a+1]-1, p-a+1 positions per
- * stored row from botp[a] on (entry b-a = first position of the out-row
- * with a column >= cuts[b], entry p-a = row end).  The in side is
+ * stores the s_a = cuts[a+1] - max(cuts[a], rT) rows max(cuts[a], rT) ..
+ * cuts[a+1]-1, p-a+1 positions per stored row, column-major from botp[a] on:
+ * entry b-a of stored row r (the first position of the out-row with a column
+ * >= cuts[b]; entry p-a = the row end) at botp[a] + (b-a) s_a + r.  The in side is
  * block-major: per block (a,b) in column-major order cid = b(b+1)/2 + a,
  * acol lists from acp[cid] on the columns v of V_b with an in-neighbour in
  * V_a, ascending, and active column x's in-neighbours in V_a (in any order)

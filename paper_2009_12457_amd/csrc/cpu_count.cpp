@@ -17,10 +17,11 @@ namespace {
 // binary search below.
 inline void out_slice(const HostTables& t, int32_t u, int32_t a, int32_t k, uint32_t& lo, uint32_t& hi) {
   const int64_t sa = std::max<int64_t>(t.cuts[a], t.rT);
-  if (u >= sa) {
-    const uint32_t* row = t.bot + t.botp[a] + (uint64_t)(u - sa) * (uint64_t)(t.p - a + 1);
-    lo = row[k - a];
-    hi = row[k - a + 1];
+  if (u >= sa) {  // column-major per part: column b - a, row u - sa
+    const uint64_t ns = (uint64_t)(t.cuts[a + 1] - sa);
+    const uint32_t* col = t.bot + t.botp[a] + (uint64_t)(u - sa);
+    lo = col[(uint64_t)(k - a) * ns];
+    hi = col[(uint64_t)(k - a + 1) * ns];
     return;
   }
   const int32_t* b = t.ocol + t.orow[u];

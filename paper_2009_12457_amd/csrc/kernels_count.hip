@@ -76,9 +76,14 @@ struct TaskCtx {
   int32_t kb;               // ck rounded down to a multiple of 32 (the bitmap covers [kb, ck1))
   int32_t i, dk, dkj;       // i, k-i, k-j
   int32_t si, sj;           // first rows of parts i and j with stored boundaries
-  uint32_t stri, strj;      // out-side row strides of parts i and j
-  const uint32_t* boti;     // stored row si of part i
-  const uint32_t* botj;     // stored row sj of part j
+  // stored boundaries, column-major per part: column b holds, for every
+  // stored row, the first position of block b; column k and k+1 of part i
+  // (bik0, bik1) bound N(G_ik,u), those of part j (bjk0, bjk1) N(G_jk,v),
+  // indexed by the row's rank minus si (sj)
+  const uint32_t* bik0;
+  const uint32_t* bik1;
+  const uint32_t* bjk0;
+  const uint32_t* bjk1;
   const uint32_t* orow;
   const int32_t* coli;      // out-rows of part i (N(G_ik,u)), absolute positions
   const int32_t* colj;      // out-rows of part j (N(G_jk,v)), absolute positions
@@ -116,28 +121,32 @@ __device__ __forceinline__ TaskCtx make_ctx(const GraphView& g, const DevTask& t
   c.i = t.i;
   c.dk = t.k - t.i;
   c.dkj = t.k - t.j;
-  c.stri = (uint32_t)(g.p - t.i + 1);
-  c.strj = (uint32_t)(g.p - t.j + 1);
   c.si = max(c.ci, g.rT);
   c.sj = max(c.cj, g.rT);
+  // stored rows of parts i and j: the column length of their boundary tables
+  const uint32_t ni = (uint32_t)max(c.ci1 - c.si, 0), nj = (uint32_t)max(ld_const(g.cuts + t.j + 1) - c.sj, 0);
   c.orow = g.orow;
   if (g.gi >= 0) {  // streamed: the launch's parts come from cached stripes
-    c.boti = g.botI;
-    c.botj = g.botJ;
+    c.bik0 = g.botI;
+    c.bjk0 = g.botJ;
     c.coli = g.colI;
     c.colj = g.colJ;
     c.icolj = g.icolJ;
     c.acb = g.acolJ;
     c.aob = g.aoffJ;
   } else {
-    c.boti = g.bot + ld_const(g.botp + t.i);
-    c.botj = g.bot + ld_const(g.botp + t.j);
+    c.bik0 = g.bot + ld_const(g.botp + t.i);
+    c.bjk0 = g.bot + ld_const(g.botp + t.j);
     c.coli = g.ocol;
     c.colj = g.ocol;
     c.icolj = g.icol;
     c.acb = g.acol;
     c.aob = g.aoff;
   }
+  c.bik0 += (uint64_t)c.dk * ni;
+  c.bik1 = c.bik0 + ni;
+  c.bjk0 += (uint64_t)c.dkj * nj;
+  c.bjk1 = c.bjk0 + nj;
   c.col16 = (g.gi < 0 && g.ocol16 != nullptr && c.ck1 - c.ck <= 65536) ? g.ocol16 : nullptr;
   const uint64_t a0 = ld_const(g.acp + col_block_id(t.i, t.j));
   c.ac = c.acb + a0;
@@ -197,9 +206,8 @@ __device__ __forceinline__ void row_slice(const int32_t* __restrict__ col, uint3
 // N(G_ik,u) = coli[a0, a1) for an in-neighbour u in V_i.
 __device__ __forceinline__ void out_slice_i(const TaskCtx& c, int32_t u, uint32_t& a0, uint32_t& a1) {
   if (u >= c.si) {
-    const uint32_t* ur = c.boti + (uint64_t)(u - c.si) * c.stri;
-    a0 = ur[c.dk];
-    a1 = ur[c.dk + 1];
+    a0 = c.bik0[u - c.si];
+    a1 = c.bik1[u - c.si];
   } else {
     row_slice(c.coli, c.orow[u], c.orow[u + 1], c.ck, c.ck1, a0, a1);
   }
@@ -531,9 +539,8 @@ __device__ uint64_t wave_col(const TaskCtx& c, uint32_t i0, uint32_t i1, uint32_
 // N(G_jk,v) = colj[c0, c1) for a column v in V_j.
 __device__ __forceinline__ void out_slice_j(const TaskCtx& c, int32_t v, uint32_t& c0, uint32_t& c1) {
   if (v >= c.sj) {
-    const uint32_t* vr = c.botj + (uint64_t)(v - c.sj) * c.strj;
-    c0 = vr[c.dkj];
-    c1 = vr[c.dkj + 1];
+    c0 = c.bjk0[v - c.sj];
+    c1 = c.bjk1[v - c.sj];
   } else {
     row_slice(c.colj, c.orow[v], c.orow[v + 1], c.ck, c.ck1, c0, c1);
   }
@@ -554,9 +561,8 @@ __device__ __forceinline__ void col_bounds_uniform(const TaskCtx& c, uint32_t x,
   i0 = ld_const(c.ao + x);
   i1 = ld_const(c.ao + x + 1);
   if (v >= c.sj) {
-    const uint32_t* vr = c.botj + (uint64_t)(v - c.sj) * c.strj;
-    c0 = ld_const(vr + c.dkj);
-    c1 = ld_const(vr + c.dkj + 1);
+    c0 = ld_const(c.bjk0 + (v - c.sj));
+    c1 = ld_const(c.bjk1 + (v - c.sj));
   } else {
     out_slice_j(c, v, c0, c1);
     c0 = __builtin_amdgcn_readfirstlane(c0);

@@ -1103,12 +1103,14 @@ __global__ __launch_bounds__(kThreads) void k_bot(BlockBuild bb) {
   if (u < bb.cuts[a + 1]) {
     const uint32_t rb = bb.orow[u], re = bb.orow[u + 1];
     const int64_t sa = ca > bb.rT ? ca : (int64_t)bb.rT;  // first stored row of part a
-    uint32_t* out = u >= sa ? bb.bot + bb.botp[a] + (uint64_t)(u - sa) * (uint64_t)(nb + 1) : nullptr;
+    // column-major per part: entry b-a of row u at column (b-a), row u - sa
+    const uint64_t ns = (uint64_t)(bb.cuts[a + 1] - sa);  // stored rows of part a
+    uint32_t* out = u >= sa ? bb.bot + bb.botp[a] + (uint64_t)(u - sa) : nullptr;
     if (out) out[0] = rb;
     uint32_t ptr = rb, prev = rb, dmax = 0;
     for (int b = a + 1; b <= p; ++b) {
       ptr = (b == p) ? re : seek(bb.ocol, ptr, re, bb.cuts[b]);
-      if (out) out[b - a] = ptr;
+      if (out) out[(uint64_t)(b - a) * ns] = ptr;
       const uint32_t len = ptr - prev;
       if (len) {
         atomicAdd(&s_nnz[b - 1 - a], len);

@@ -68,19 +68,20 @@ inline std::string check_tables(const TableView& t) {
     const uint64_t d1 = (uint64_t)(t.orow[r + 1] - t.orow[r]) + (indeg[(size_t)r + 1] - indeg[(size_t)r]);
     if (d1 < d0) return fmt("degree decreases with rank at", r, (int64_t)d1);
   }
-  // stored block boundaries: rows max(c_a, rT) .. c_{a+1}-1 of each part
+  // stored block boundaries: rows max(c_a, rT) .. c_{a+1}-1 of each part,
+  // column-major (column b-a holds entry b-a of every stored row)
   if (t.botp[0] != 0) return fmt("boundary table must start at 0", (int64_t)t.botp[0], 0);
   for (int32_t a = 0; a < p; ++a) {
     const int64_t sa = t.cuts[a] > t.rT ? t.cuts[a] : t.rT;
     const int64_t stored = t.cuts[a + 1] > sa ? t.cuts[a + 1] - sa : 0;
     if (t.botp[a + 1] - t.botp[a] != (uint64_t)(stored * (p - a + 1))) return fmt("botp step wrong at part", a, stored);
-    for (int64_t u = sa; u < t.cuts[a + 1]; ++u) {
-      const uint32_t* br = t.bot + t.botp[a] + (uint64_t)(u - sa) * (uint64_t)(p - a + 1);
+    for (int64_t u = sa; u < t.cuts[a + 1]; ++u) {  // column-major: column b-a, row u-sa
+      const uint32_t* br = t.bot + t.botp[a] + (uint64_t)(u - sa);
       uint32_t e = t.orow[u];
       for (int32_t b = a; b <= p; ++b) {  // entry b-a: first position with a column >= cuts[b]
         while (b < p && e < t.orow[u + 1] && t.ocol[e] < t.cuts[b]) ++e;
         const uint32_t want = b == p ? t.orow[u + 1] : e;
-        if (br[b - a] != want) return fmt("out-side boundary wrong for row", u, b);
+        if (br[(uint64_t)(b - a) * (uint64_t)stored] != want) return fmt("out-side boundary wrong for row", u, b);
       }
     }
   }

@@ -28,11 +28,12 @@ def reference_tables(g, p, T):
     deg = np.diff(orow) + np.diff(irow)
     rT = int((deg <= T).sum()) if T >= 0 else 0
     botp, bot = [0], []
-    for a in range(p):
+    for a in range(p):  # column-major per part: column b-a lists entry b-a of every stored row
         sa = max(cuts[a], rT)
-        for u in range(sa, cuts[a + 1]):
-            row = ocol[orow[u]:orow[u + 1]]
-            bot += [orow[u] + int(np.searchsorted(row, cuts[b])) for b in range(a, p)] + [orow[u + 1]]
+        rows = [[orow[u] + int(np.searchsorted(ocol[orow[u]:orow[u + 1]], cuts[b])) for b in range(a, p)]
+                + [orow[u + 1]] for u in range(sa, cuts[a + 1])]
+        for col in range(p - a + 1):
+            bot += [r[col] for r in rows]
         botp.append(botp[-1] + max(0, cuts[a + 1] - sa) * (p - a + 1))
     slices = {}
     for v in range(n):
