@@ -118,6 +118,7 @@ struct bbtc_plan {
   DevBuf<uint32_t> od, idg, orow, irow, midrows, longrows, hugerows, bot, ccnt, ccoff, cursor, err, aoff, asrc;
   DevBuf<int32_t> icolb;  // the block-major in side (icol is the vertex-major one it is built from)
   DevBuf<uint16_t> ocol16;  // out-rows relative to the part of each entry (resident plans)
+  DevBuf<int32_t> rc;       // rank of each input entry's vertex, between the degree pass and the fill
   DevBuf<uint64_t> acp;
   // Per-part index tables (uploaded together) and per-block statistics with
   // their counters (cleared and read back together), in one allocation:
@@ -249,7 +250,7 @@ struct bbtc_plan {
     longrows.release();
     hugerows.release();
     bot.release(); ccnt.release(); ccoff.release(); cursor.release(); aoff.release(); asrc.release(); icolb.release();
-    ocol16.release();
+    ocol16.release(); rc.release();
     err.release(); acp.release(); tasks.release(); items.release(); xitems.release(); heavy.release();
     emit.release();
   }
@@ -260,7 +261,7 @@ struct bbtc_plan {
            acol.bytes() + od.bytes() + idg.bytes() + orow.bytes() + irow.bytes() + midrows.bytes() + longrows.bytes() +
            hugerows.bytes() + bot.bytes() +
            ccnt.bytes() + ccoff.bytes() + cursor.bytes() + err.bytes() + acp.bytes() + aoff.bytes() + asrc.bytes() +
-           icolb.bytes() + ocol16.bytes() +
+           icolb.bytes() + ocol16.bytes() + rc.bytes() +
            tasks.bytes() + items.bytes() + xitems.bytes() + heavy.bytes() + emit.bytes() +
            cache.bytes();
   }
@@ -804,7 +805,7 @@ bbtc_status stream_setup(bbtc_plan* pl, hipStream_t s) {
   // release everything the count phase does not read (the out-row pointers
   // stay: the slices of rows without stored boundaries are found by scanning)
   pl->ocol.release(); pl->icol.release(); pl->bot.release(); pl->acol.release(); pl->aoff.release();
-  pl->asrc.release(); pl->icolb.release(); pl->irow.release(); pl->ocol16.release();
+  pl->asrc.release(); pl->icolb.release(); pl->irow.release(); pl->ocol16.release(); pl->rc.release();
   pl->keys_a.release(); pl->keys_b.release(); pl->hist.release(); pl->partial.release();
   pl->od.release(); pl->idg.release(); pl->order.release();
   pl->longrows.release(); pl->hugerows.release(); pl->midrows.release(); pl->ccnt.release(); pl->ccoff.release();
@@ -1115,7 +1116,7 @@ int64_t resident_estimate(int64_t n, int64_t nnz, int32_t p, int64_t bound_deg, 
   if (bound_deg == 0) stored = std::max<int64_t>(stored, m / (p + 1));
   int64_t b = (host_input ? rpb * (n + 1) + 4 * nnz : 0);
   b += 16 * n + 8 * n + 8 * n + 8 * (n + 1) + 12 * n;  // keys, perm/order, degrees, row pointers, row lists
-  b += 4 * (m + 4) * 2 + 4 * m * 4 + 4 + 2 * (m + 16);  // ocol, icol, acol, aoff, asrc, icolb, ocol16
+  b += 4 * (m + 4) * 2 + 4 * m * 4 + 4 + 2 * (m + 16) + 4 * nnz;  // ocol, icol, acol, aoff, asrc, icolb, ocol16, ranks
   b += 4 * (int64_t)(p + 1) * stored;                  // stored block boundaries
   b += 16 * ((int64_t)p * (n / kPrepRows + p) + 1);    // chunk counters and their scans
   b += 12 * (m / 256 + 1) + (int64_t)p * (p + 1) * (p + 2) / 6 * 48 + (64 << 20);  // hubs, tasks, items, slack
@@ -1176,11 +1177,12 @@ struct BudgetBuild {
       const RowRange rr{k.x0, P->n, k.e0, k.e1, rlo, rhi};
       const int64_t nr = k.x1 - k.x0;
       HIP_TRY(launch_degs(rp, rp64, col, nr, rr, P->perm.ptr, od, idg, P->longrows.ptr, P->err.ptr + 4,
-                          P->hugerows.ptr, P->err.ptr + 5, hpref.ptr, P->err.ptr, check, s),
+                          P->hugerows.ptr, P->err.ptr + 5, hpref.ptr, P->err.ptr, check, nullptr, s),
               "degrees");
       if (!od)
         HIP_TRY(launch_fill(rp, rp64, col, nr, rr, P->perm.ptr, P->orow.ptr, P->irow.ptr, ocol, icol, P->longrows.ptr,
-                            P->err.ptr + 4, P->hugerows.ptr, P->err.ptr + 5, hpref.ptr, cur_o.ptr, cur_i.ptr, s),
+                            P->err.ptr + 4, P->hugerows.ptr, P->err.ptr + 5, hpref.ptr, cur_o.ptr, cur_i.ptr, nullptr,
+                            s),
                 "fill");
     }
     return BBTC_OK;
@@ -1636,6 +1638,7 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
     const int32_t pe = opt.p > 0 ? opt.p : 256;
     if (resident_estimate(n, nnz, pe, opt.bound_min_deg, !on_device, rp64 ? 8 : 4) > opt.device_budget_bytes) {
       pl->ocol16.release();  // streamed counts read the four-byte rows
+      pl->rc.release();
       return partition_budgeted(g, s, pl, t0);
     }
   }
@@ -1700,9 +1703,11 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   // ---- orientation: out-rows (higher ranks) and in-rows (lower ranks) ----
   // err[4]: rows too long for one lane, listed in longrows by launch_degs
   // err[4], err[5]: rows too long for one lane / huge rows, listed by launch_degs
+  // the rank of every entry's vertex, gathered once here and read by the fill
+  HIP_TRY(pl->rc.ensure((size_t)nnz), "alloc entry ranks");
   HIP_TRY(launch_degs(rowptr, rp64, col, n, whole_rows(n, nnz), pl->perm.ptr, pl->od.ptr, pl->idg.ptr, pl->longrows.ptr,
                       pl->err.ptr + 4, pl->hugerows.ptr, pl->err.ptr + 5, (uint32_t*)pl->keys_b.ptr, pl->err.ptr,
-                      check_in_degs, s),
+                      check_in_degs, pl->rc.ptr, s),
           "degrees");
   // while od/idg are degrees: the wedge count W (Sec. 4.4's work measure)
   // and the first rank whose block boundaries are stored
@@ -1735,7 +1740,7 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   // fill cursors (zeroed by launch_fill)
   HIP_TRY(launch_fill(rowptr, rp64, col, n, whole_rows(n, nnz), pl->perm.ptr, pl->orow.ptr, pl->irow.ptr, pl->ocol.ptr, pl->icol.ptr,
                       pl->longrows.ptr, pl->err.ptr + 4, pl->hugerows.ptr, pl->err.ptr + 5,
-                      (const uint32_t*)pl->keys_b.ptr, pl->od.ptr, pl->idg.ptr, s),
+                      (const uint32_t*)pl->keys_b.ptr, pl->od.ptr, pl->idg.ptr, pl->rc.ptr, s),
           "fill");
   // ---- cut vector (Sec. 4.1): it needs only orow ----
   int32_t p = opt.p;

@@ -159,16 +159,20 @@ hipError_t radix_sort_u64(uint64_t* a, uint64_t* b, uint64_t count, int lo, int 
 // out[0..count] = exclusive scan of in[0..count), out[count] = total.
 hipError_t scan_u32(const uint32_t* in, uint32_t* out, uint64_t count, uint32_t* partial, hipStream_t s);
 hipError_t launch_perm(const uint64_t* keys, int64_t n, int idbits, int32_t* order, int32_t* perm, hipStream_t s);
-// od == nullptr: list the long and huge rows only (no degrees).
+// od == nullptr: list the long and huge rows only (no degrees).  rc (may be
+// null): receives, at each input position, the rank of that entry's vertex,
+// which the fill then reads instead of gathering it again.
 hipError_t launch_degs(const void* rowptr, int rp64, const int32_t* colidx, int64_t n, const RowRange& rr,
                        const int32_t* perm, uint32_t* od, uint32_t* idg, uint32_t* list, uint32_t* nlist,
-                       uint32_t* hlist, uint32_t* nhlist, uint32_t* hpref, uint32_t* err, int check, hipStream_t s);
-// cur_o/cur_i: zeroed fill cursors of the huge rows (indexed by position in hlist).
+                       uint32_t* hlist, uint32_t* nhlist, uint32_t* hpref, uint32_t* err, int check, int32_t* rc,
+                       hipStream_t s);
+// cur_o/cur_i: zeroed fill cursors of the huge rows (indexed by position in
+// hlist); rc: the ranks written by launch_degs over the same rows, or null.
 hipError_t launch_fill(const void* rowptr, int rp64, const int32_t* colidx, int64_t n, const RowRange& rr,
                        const int32_t* perm,
                        const uint32_t* orow, const uint32_t* irow, int32_t* ocol, int32_t* icol, const uint32_t* list,
                        const uint32_t* nlist, const uint32_t* hlist, const uint32_t* nhlist, const uint32_t* hpref,
-                       uint32_t* cur_o, uint32_t* cur_i, hipStream_t s);
+                       uint32_t* cur_o, uint32_t* cur_i, const int32_t* rc, hipStream_t s);
 // Sorts every row of a CSR in place; values have at most `bits` bits.
 // longrows and hugerows need nrows entries each, q[0..1] must be zero, and
 // scratch needs rp[nrows] entries.

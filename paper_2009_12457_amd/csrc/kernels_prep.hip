@@ -351,7 +351,8 @@ __global__ __launch_bounds__(kThreads) void k_degs_lane(const RP* __restrict__ r
                                                         const int32_t* __restrict__ colidx, int64_t n, RowRange rr,
                                                         const int32_t* __restrict__ perm, uint32_t* __restrict__ od,
                                                         uint32_t* __restrict__ idg, uint32_t* list, uint32_t* nlist,
-                                                        uint32_t* hlist, uint32_t* nhlist, uint32_t* err, int check) {
+                                                        uint32_t* hlist, uint32_t* nhlist, uint32_t* err, int check,
+                                                        int32_t* __restrict__ rc) {
   __shared__ FlatRows fr[kThreads / kWave];
   const int l = lane_id();
   FlatRows& F = fr[threadIdx.x / kWave];
@@ -405,7 +406,11 @@ __global__ __launch_bounds__(kThreads) void k_degs_lane(const RP* __restrict__ r
         uint32_t fl = 0;
         if (check) fl = entry_flags<RP>(colidx, rr.ntot, rr.x0 + x0 + o, rb, q, y);
         bad |= fl;
-        up = !(fl & 1) && perm[y] > F.rank[o];
+        if (!(fl & 1)) {
+          const int32_t ry = perm[y];
+          if (rc) rc[q] = ry;
+          up = ry > F.rank[o];
+        }
       }
       const uint64_t heads = ballot(act && (l == 0 || f == F.off[o]));
       const uint64_t ups = ballot(up);
@@ -429,7 +434,8 @@ constexpr int kUnroll = 4;  // 64-entry chunks of a row in flight per wavefront 
 template <typename RP>
 __device__ __forceinline__ uint32_t count_up(const int32_t* __restrict__ colidx, int64_t n,
                                              const int32_t* __restrict__ perm, int64_t x, int32_t r, int64_t rb,
-                                             int64_t b, int64_t e, int check, uint32_t* bad) {
+                                             int64_t b, int64_t e, int check, uint32_t* bad,
+                                             int32_t* __restrict__ rcout, const int32_t* __restrict__ rcin) {
   const int l = lane_id();
   uint32_t c = 0;
   for (int64_t base = b; base < e; base += kUnroll * kWave) {
@@ -437,7 +443,7 @@ __device__ __forceinline__ uint32_t count_up(const int32_t* __restrict__ colidx,
 #pragma unroll
     for (int k = 0; k < kUnroll; ++k) {
       const int64_t q = base + k * kWave + l;
-      y[k] = q < e ? colidx[q] : -1;
+      y[k] = q < e ? (rcin ? rcin[q] : colidx[q]) : -1;
     }
 #pragma unroll
     for (int k = 0; k < kUnroll; ++k) {
@@ -445,7 +451,11 @@ __device__ __forceinline__ uint32_t count_up(const int32_t* __restrict__ colidx,
       if (q < e) {
         const uint32_t f = check ? entry_flags<RP>(colidx, n, x, rb, q, y[k]) : 0u;
         *bad |= f;
-        if (!(f & 1) && perm[y[k]] > r) ++c;
+        if (!(f & 1)) {
+          const int32_t ry = rcin ? y[k] : perm[y[k]];
+          if (rcout) rcout[q] = ry;
+          if (ry > r) ++c;
+        }
       }
     }
   }
@@ -461,7 +471,7 @@ __global__ __launch_bounds__(kThreads) void k_degs_wave(const RP* __restrict__ r
                                                         uint32_t* __restrict__ idg, const uint32_t* list,
                                                         const uint32_t* nlist, const uint32_t* hlist,
                                                         const uint32_t* nhlist, const uint32_t* hpref, uint32_t* err,
-                                                        int check) {
+                                                        int check, int32_t* __restrict__ rc) {
   const int l = lane_id();
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
@@ -472,7 +482,7 @@ __global__ __launch_bounds__(kThreads) void k_degs_wave(const RP* __restrict__ r
     const int32_t r = perm[rr.x0 + x];
     const int64_t b = (int64_t)rowptr[x], e = (int64_t)rowptr[x + 1];
     const uint32_t c =
-        (uint32_t)wave_sum_u64(count_up<RP>(colidx, rr.ntot, perm, rr.x0 + x, r, b, b, e, check, &bad));
+        (uint32_t)wave_sum_u64(count_up<RP>(colidx, rr.ntot, perm, rr.x0 + x, r, b, b, e, check, &bad, rc, nullptr));
     if (l == 0) {
       od[r] = c;
       idg[r] = (uint32_t)(e - b) - c;
@@ -487,7 +497,7 @@ __global__ __launch_bounds__(kThreads) void k_degs_wave(const RP* __restrict__ r
     const int32_t r = perm[rr.x0 + x];
     const int64_t rb = (int64_t)rowptr[x];
     const uint32_t c =
-        (uint32_t)wave_sum_u64(count_up<RP>(colidx, rr.ntot, perm, rr.x0 + x, r, rb, b, e, check, &bad));
+        (uint32_t)wave_sum_u64(count_up<RP>(colidx, rr.ntot, perm, rr.x0 + x, r, rb, b, e, check, &bad, rc, nullptr));
     if (l == 0) {
       atomicAdd(&od[r], c);
       atomicAdd(&idg[r], (uint32_t)(e - b) - c);
@@ -506,7 +516,7 @@ __global__ __launch_bounds__(kThreads) void k_fill_lane(const RP* __restrict__ r
                                                         const int32_t* __restrict__ perm,
                                                         const uint32_t* __restrict__ orow,
                                                         const uint32_t* __restrict__ irow, int32_t* __restrict__ ocol,
-                                                        int32_t* __restrict__ icol) {
+                                                        int32_t* __restrict__ icol, const int32_t* __restrict__ rc) {
   __shared__ FlatRows fr[kThreads / kWave];
   __shared__ uint32_t lim[kThreads / kWave][2][kWave];  // per row: end of its out- and in-row
   const int l = lane_id(), w = threadIdx.x / kWave;
@@ -544,7 +554,8 @@ __global__ __launch_bounds__(kThreads) void k_fill_lane(const RP* __restrict__ r
       bool up = false;
       if (act) {
         o = owner_lane(F.off, f);
-        ry = perm[colidx[F.beg[o] + (f - F.off[o])]];
+        const int64_t q = F.beg[o] + (f - F.off[o]);
+        ry = rc ? rc[q] : perm[colidx[q]];
         up = ry > F.rank[o];
       }
       const uint64_t heads = ballot(act && (l == 0 || f == F.off[o]));
@@ -579,17 +590,19 @@ __global__ __launch_bounds__(kThreads) void k_fill_lane(const RP* __restrict__ r
 __device__ __forceinline__ void scatter_run(const int32_t* __restrict__ colidx, const int32_t* __restrict__ perm,
                                             int32_t r, int64_t b, int64_t e, uint32_t po, uint32_t pi,
                                             uint32_t po_end, uint32_t pi_end, int32_t* __restrict__ ocol,
-                                            int32_t* __restrict__ icol) {
+                                            int32_t* __restrict__ icol, const int32_t* __restrict__ rc) {
   const int l = lane_id();
   for (int64_t base = b; base < e; base += kUnroll * kWave) {
     int32_t ry[kUnroll];
 #pragma unroll
     for (int k = 0; k < kUnroll; ++k) {
       const int64_t q = base + k * kWave + l;
-      ry[k] = q < e ? colidx[q] : -1;
+      ry[k] = q < e ? (rc ? rc[q] : colidx[q]) : -1;
     }
+    if (!rc) {
 #pragma unroll
-    for (int k = 0; k < kUnroll; ++k) ry[k] = ry[k] >= 0 ? perm[ry[k]] : -1;
+      for (int k = 0; k < kUnroll; ++k) ry[k] = ry[k] >= 0 ? perm[ry[k]] : -1;
+    }
 #pragma unroll
     for (int k = 0; k < kUnroll; ++k) {
       const int64_t q = base + k * kWave + l;
@@ -626,7 +639,7 @@ __global__ __launch_bounds__(kThreads) void k_fill_wave(const RP* __restrict__ r
                                                         int32_t* __restrict__ icol, const uint32_t* list,
                                                         const uint32_t* nlist, const uint32_t* hlist,
                                                         const uint32_t* nhlist, const uint32_t* hpref, uint32_t* cur_o,
-                                                        uint32_t* cur_i) {
+                                                        uint32_t* cur_i, const int32_t* __restrict__ rc) {
   const int l = lane_id();
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
@@ -636,7 +649,7 @@ __global__ __launch_bounds__(kThreads) void k_fill_wave(const RP* __restrict__ r
     const int32_t r = perm[rr.x0 + x];
     if (r < rr.rlo || r >= rr.rhi) continue;
     const int64_t b = (int64_t)rowptr[x], e = (int64_t)rowptr[x + 1];
-    scatter_run(colidx, perm, r, b, e, orow[r], irow[r], orow[r + 1], irow[r + 1], ocol, icol);
+    scatter_run(colidx, perm, r, b, e, orow[r], irow[r], orow[r + 1], irow[r + 1], ocol, icol, rc);
   }
   const uint32_t hcnt = *nhlist;
   const uint32_t units = hcnt ? hpref[hcnt] : 0u;
@@ -650,7 +663,7 @@ __global__ __launch_bounds__(kThreads) void k_fill_wave(const RP* __restrict__ r
     const uint32_t po_end = orow[r + 1], pi_end = irow[r + 1];
     uint32_t nb = 0;
     const uint32_t nu =
-        (uint32_t)wave_sum_u64(count_up<RP>(colidx, 0, perm, rr.x0 + x, r, b, b, e, 0, &nb));
+        (uint32_t)wave_sum_u64(count_up<RP>(colidx, 0, perm, rr.x0 + x, r, b, b, e, 0, &nb, nullptr, rc));
     uint32_t po = 0, pi = 0;
     if (l == 0) {
       po = ob + atomicAdd(&cur_o[li], nu);
@@ -658,7 +671,7 @@ __global__ __launch_bounds__(kThreads) void k_fill_wave(const RP* __restrict__ r
     }
     po = __shfl(po, 0, kWave);
     pi = __shfl(pi, 0, kWave);
-    scatter_run(colidx, perm, r, b, e, po, pi, po_end, pi_end, ocol, icol);
+    scatter_run(colidx, perm, r, b, e, po, pi, po_end, pi_end, ocol, icol, rc);
   }
 }
 
@@ -1409,27 +1422,28 @@ hipError_t launch_perm(const uint64_t* keys, int64_t n, int idbits, int32_t* ord
 
 hipError_t launch_degs(const void* rowptr, int rp64, const int32_t* colidx, int64_t n, const RowRange& rr,
                        const int32_t* perm, uint32_t* od, uint32_t* idg, uint32_t* list, uint32_t* nlist,
-                       uint32_t* hlist, uint32_t* nhlist, uint32_t* hpref, uint32_t* err, int check, hipStream_t s) {
+                       uint32_t* hlist, uint32_t* nhlist, uint32_t* hpref, uint32_t* err, int check, int32_t* rc,
+                       hipStream_t s) {
   if (n == 0) return hipSuccess;
   const unsigned g = grid_for((uint64_t)n, kThreads, 65536);
   if (rp64) {
     hipLaunchKernelGGL(k_degs_lane<int64_t>, dim3(g), dim3(kThreads), 0, s, (const int64_t*)rowptr, colidx, n, rr,
-                       perm, od, idg, list, nlist, hlist, nhlist, err, check);
+                       perm, od, idg, list, nlist, hlist, nhlist, err, check, rc);
     hipLaunchKernelGGL(k_hprefix<int64_t>, dim3(1), dim3(kThreads), 0, s, (const int64_t*)rowptr, (const uint32_t*)hlist,
                        (const uint32_t*)nhlist, hpref);
     if (od)
       hipLaunchKernelGGL(k_degs_wave<int64_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int64_t*)rowptr, colidx,
                          rr, perm, od, idg, (const uint32_t*)list, (const uint32_t*)nlist, (const uint32_t*)hlist,
-                         (const uint32_t*)nhlist, (const uint32_t*)hpref, err, check);
+                         (const uint32_t*)nhlist, (const uint32_t*)hpref, err, check, rc);
   } else {
     hipLaunchKernelGGL(k_degs_lane<int32_t>, dim3(g), dim3(kThreads), 0, s, (const int32_t*)rowptr, colidx, n, rr,
-                       perm, od, idg, list, nlist, hlist, nhlist, err, check);
+                       perm, od, idg, list, nlist, hlist, nhlist, err, check, rc);
     hipLaunchKernelGGL(k_hprefix<int32_t>, dim3(1), dim3(kThreads), 0, s, (const int32_t*)rowptr, (const uint32_t*)hlist,
                        (const uint32_t*)nhlist, hpref);
     if (od)
       hipLaunchKernelGGL(k_degs_wave<int32_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int32_t*)rowptr, colidx,
                          rr, perm, od, idg, (const uint32_t*)list, (const uint32_t*)nlist, (const uint32_t*)hlist,
-                         (const uint32_t*)nhlist, (const uint32_t*)hpref, err, check);
+                         (const uint32_t*)nhlist, (const uint32_t*)hpref, err, check, rc);
   }
   return hipGetLastError();
 }
@@ -1438,20 +1452,20 @@ hipError_t launch_fill(const void* rowptr, int rp64, const int32_t* colidx, int6
                        const int32_t* perm,
                        const uint32_t* orow, const uint32_t* irow, int32_t* ocol, int32_t* icol, const uint32_t* list,
                        const uint32_t* nlist, const uint32_t* hlist, const uint32_t* nhlist, const uint32_t* hpref,
-                       uint32_t* cur_o, uint32_t* cur_i, hipStream_t s) {
+                       uint32_t* cur_o, uint32_t* cur_i, const int32_t* rc, hipStream_t s) {
   if (n == 0) return hipSuccess;
   const unsigned g = grid_for((uint64_t)n, kThreads, 65536);
   hipLaunchKernelGGL(k_zero2, dim3(64), dim3(kThreads), 0, s, cur_o, cur_i, nhlist);
   if (rp64) {
     hipLaunchKernelGGL(k_fill_lane<int64_t>, dim3(g), dim3(kThreads), 0, s, (const int64_t*)rowptr, colidx, n, rr,
-                       perm, orow, irow, ocol, icol);
+                       perm, orow, irow, ocol, icol, rc);
     hipLaunchKernelGGL(k_fill_wave<int64_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int64_t*)rowptr, colidx, rr,
-                       perm, orow, irow, ocol, icol, list, nlist, hlist, nhlist, hpref, cur_o, cur_i);
+                       perm, orow, irow, ocol, icol, list, nlist, hlist, nhlist, hpref, cur_o, cur_i, rc);
   } else {
     hipLaunchKernelGGL(k_fill_lane<int32_t>, dim3(g), dim3(kThreads), 0, s, (const int32_t*)rowptr, colidx, n, rr,
-                       perm, orow, irow, ocol, icol);
+                       perm, orow, irow, ocol, icol, rc);
     hipLaunchKernelGGL(k_fill_wave<int32_t>, dim3(kRowGrid), dim3(kThreads), 0, s, (const int32_t*)rowptr, colidx, rr,
-                       perm, orow, irow, ocol, icol, list, nlist, hlist, nhlist, hpref, cur_o, cur_i);
+                       perm, orow, irow, ocol, icol, list, nlist, hlist, nhlist, hpref, cur_o, cur_i, rc);
   }
   return hipGetLastError();
 }

@@ -41,9 +41,10 @@ from . import (BBTC_EBUDGET, BBTC_MODE_PERSISTENT, BBTC_MODE_PLAIN_INTERSECT, Bb
 
 def footprint_estimate(n: int, nnz: int, p: int) -> int:
     """Upper bound of a plan's device bytes (the layout of bbtc_partition):
-    the uploaded input (8 B per edge), out-rows, in-rows, active columns,
-    in-slice offsets and sources, block-major in-slices (24 B per edge) and
-    the 16-bit out-rows (2 B per edge), per-vertex arrays, the stored block
+    the uploaded input and the rank of each of its entries (16 B per edge),
+    out-rows, in-rows, active columns, in-slice offsets and sources,
+    block-major in-slices (24 B per edge) and the 16-bit out-rows (2 B per
+    edge), per-vertex arrays, the stored block
     boundaries (at most p+1 entries per stored row; the automatic threshold
     keeps them within the 4 B per edge of the out-rows unless even rows of
     degree above 32, at most nnz/33 of them, need more), tasks and items."""
@@ -51,7 +52,7 @@ def footprint_estimate(n: int, nnz: int, p: int) -> int:
     ntasks = p * (p + 1) * (p + 2) // 6
     stored = min(int(n), int(nnz) // 33)
     bounds = max(4 * (p + 1) * stored, 4 * m)
-    return 34 * m + 72 * n + bounds + 64 * ntasks + (1 << 20)
+    return 42 * m + 72 * n + bounds + 64 * ntasks + (1 << 20)
 
 
 def default_p(n: int, nnz: int) -> int:

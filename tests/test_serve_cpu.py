@@ -114,7 +114,7 @@ def test_footprint_estimate_and_p_prior():
     # the out-rows' 4 B per edge, so only the per-edge bytes grow
     a = footprint_estimate(1 << 16, 1 << 22, 16)
     b = footprint_estimate(1 << 16, 1 << 23, 16)
-    assert b - a == (34 + 4) * (1 << 21)
+    assert b - a == (42 + 4) * (1 << 21)
     # sparse graphs at large p: stored boundary rows are bounded by nnz/33
     c = footprint_estimate(1 << 20, 1 << 20, 64)
     assert c - footprint_estimate(1 << 20, 1 << 20, 1) <= 4 * 65 * ((1 << 20) // 33) + 64 * 64 * 65 * 66 // 6
