@@ -415,33 +415,41 @@ __device__ __forceinline__ uint32_t probe_rounds(const int32_t* __restrict__ col
   return cnt;
 }
 
-// Segments of the 16-bit out-rows: 8 entries, one aligned 16-byte block.
+// Segments of the 16-bit out-rows: kSeg16 entries, aligned 16-byte blocks
+// of 8 entries each (the owner search and the segment bounds of a probe
+// round are paid once per segment).
+constexpr uint32_t kSeg16 = 16;
 __device__ __forceinline__ uint32_t seg_count16(uint32_t a0, uint32_t a1) {
-  return a1 > a0 ? (a1 - (a0 & ~7u) + 7u) / 8u : 0u;
+  return a1 > a0 ? (a1 - (a0 & ~7u) + kSeg16 - 1u) / kSeg16 : 0u;
 }
 
-// Segment q of the list col16[a0, a1) as four words of two entries each
+// Segment q of the list col16[a0, a1) as kSeg16/2 words of two entries each
 // (entry 2h in the low half of x[h]); returns the mask of the positions that
-// belong to the list.  A q past the list reads its first block under an
-// empty mask.
+// belong to the list.  A block past the list end rereads the segment's first
+// block, and a q past the list reads the list's first block, both under an
+// empty mask for those positions.
 __device__ __forceinline__ uint32_t load_seg16(const uint16_t* __restrict__ col, uint32_t a0, uint32_t a1, uint32_t q,
-                                               uint32_t x[4]) {
-  const uint32_t s = (a0 & ~7u) + q * 8u;
+                                               uint32_t x[kSeg16 / 2]) {
+  const uint32_t s = (a0 & ~7u) + q * kSeg16;
   const bool in = s < a1;
   const uint32_t s0 = in ? s : (a0 & ~7u);
-  const uint4 v = *reinterpret_cast<const uint4*>(col + s0);
-  x[0] = v.x;
-  x[1] = v.y;
-  x[2] = v.z;
-  x[3] = v.w;
-  const uint32_t lo = a0 > s0 ? a0 - s0 : 0u, hi = min(a1 - s0, 8u);
-  return in ? ((1u << hi) - 1u) & ~((1u << lo) - 1u) : 0u;
+#pragma unroll
+  for (uint32_t h = 0; h < kSeg16 / 8; ++h) {
+    const uint32_t sh = s0 + 8 * h < a1 ? s0 + 8 * h : s0;
+    const uint4 v = *reinterpret_cast<const uint4*>(col + sh);
+    x[4 * h + 0] = v.x;
+    x[4 * h + 1] = v.y;
+    x[4 * h + 2] = v.z;
+    x[4 * h + 3] = v.w;
+  }
+  const uint32_t lo = a0 > s0 ? a0 - s0 : 0u, hi = min(a1 - s0, kSeg16);
+  return in ? ((hi >= 32u ? 0xFFFFFFFFu : (1u << hi) - 1u) & ~((1u << lo) - 1u)) : 0u;
 }
 
-// probe_rounds<1> over the 16-bit out-rows: the bitmap holds x = w - c_k, and
-// a segment is one 16-byte load.  Word (x / 32) mod nw as a byte address:
-// bits 5.. of the entry shifted to bits 2.. (low half: x >> 3, high half:
-// x >> 19), masked and ORed into the aligned base; the bit is x mod 32.
+// probe_rounds<1> over the 16-bit out-rows: the bitmap holds x = w - c_k.
+// Word (x / 32) mod nw as a byte address: bits 5.. of the entry shifted to
+// bits 2.. (low half: x >> 3, high half: x >> 19), masked and ORed into the
+// aligned base; the bit is x mod 32.
 __device__ __forceinline__ uint32_t probe_rounds16(const uint16_t* __restrict__ col, uint32_t tot, const uint32_t* sa0,
                                                    const uint32_t* sa1, const uint32_t* sex, uint32_t* sown,
                                                    uint32_t sx, uint32_t ns, uint32_t& rnd, const Stage& st,
@@ -453,17 +461,17 @@ __device__ __forceinline__ uint32_t probe_rounds16(const uint16_t* __restrict__ 
     const uint32_t o = round_owner(sown, sx, ns, qb, ++rnd, l);
     const uint32_t q = qb + l;
     if (q < tot) {
-      uint32_t x[4];
+      uint32_t x[kSeg16 / 2];
       const uint32_t vm = load_seg16(col, sa0[o], sa1[o], q - sex[o], x);
-      uint32_t wl[4], wh[4];
+      uint32_t wl[kSeg16 / 2], wh[kSeg16 / 2];
 #pragma unroll
-      for (uint32_t h = 0; h < 4; ++h) {
+      for (uint32_t h = 0; h < kSeg16 / 2; ++h) {
         wl[h] = lds_load(base | ((x[h] >> 3) & omask));
         wh[h] = lds_load(base | ((x[h] >> 19) & omask));
       }
       uint32_t hit = 0;
 #pragma unroll
-      for (uint32_t h = 0; h < 4; ++h) {
+      for (uint32_t h = 0; h < kSeg16 / 2; ++h) {
         hit |= __builtin_amdgcn_ubfe(wl[h], x[h], 1u) << (2 * h);
         hit |= __builtin_amdgcn_ubfe(wh[h], x[h] >> 16, 1u) << (2 * h + 1);
       }
