@@ -65,7 +65,12 @@ def note(msg):
 def pmc_key(workload, opt):
     """Counter records are keyed by the workload and the effective knobs of the
     count (0 selects the library defaults, wave_min 32 and hash_min 16)."""
-    return f"{workload}-p{opt.p}-w{opt.wave_min or 32}-h{opt.hash_min or 16}"
+    key = f"{workload}-p{opt.p}-w{opt.wave_min or 32}-h{opt.hash_min or 16}"
+    if opt.bound_min_deg:
+        key += f"-b{opt.bound_min_deg}"
+    if opt.item_rows:
+        key += f"-r{opt.item_rows}"
+    return key
 
 
 def timed(fn, reps, sync):
@@ -413,6 +418,8 @@ def options_for(args, name, stream, g):
         opt.hash_min = args.hash_min
     if args.bound_min_deg:
         opt.bound_min_deg = args.bound_min_deg
+    if args.item_rows:
+        opt.item_rows = args.item_rows
     tuned = None
     if args.autotune == "on" or (args.autotune == "auto" and name in AUTOTUNED and not args.p):
         n, rp, ci = bb.csr_of(g, "cuda")
@@ -493,6 +500,8 @@ def main():
     ap.add_argument("--hash-min", type=int, default=0)
     ap.add_argument("--bound-min-deg", type=int, default=0,
                     help="rows of undirected degree above this store block boundaries (-1: every row)")
+    ap.add_argument("--item-rows", type=int, default=0,
+                    help="active columns per persistent work item at most (0: library default)")
     ap.add_argument("--no-companion", action="store_true",
                     help="skip Erdos-Renyi 2^24 beside R-MAT scale 24 (the headline configuration has both)")
     ap.add_argument("--no-small", action="store_true", help="skip the 2000-vertex and scale-20 configurations")
@@ -569,8 +578,10 @@ def main():
             bb.bbtc_count(plan, per, tot, stream=stream)
         sync()
         dt = time.perf_counter() - t0
+        st = plan.stats()
         print(json.dumps({"workload": name, "pmc_key": pmc_key(name, opt), "ms_per_step": dt * 1e3 / args.steps,
-                          "count_ms": count_event_ms(bb, plan, per, tot, stream, 5), "triangles": int(tot.item())}))
+                          "count_ms": count_event_ms(bb, plan, per, tot, stream, 5), "triangles": int(tot.item()),
+                          "nitems": st["nitems"]}))
         return
 
     plain_modes = () if args.no_plain else (("plain_intersect", bb.BBTC_MODE_PLAIN_INTERSECT),

@@ -268,7 +268,8 @@ bbtc_status bbtc_count_multi_static(bbtc_plan* const* plans, int32_t nplans, voi
  * persistent count (HIP events on `stream`, median of `reps` launches after
  * one warm-up) by coordinate descent: first p over {p0/4, p0/2, p0, 2*p0}
  * (p0 = base->p, or the average degree when base->p is 0: Sec. 7.3 of the
- * paper suggests p near the average degree), then wave_min over
+ * paper suggests p near the average degree), continuing by halving below
+ * p0/4 (doubling above 2*p0) while the count gets faster, then wave_min over
  * {16, 32, 64, 128, 256, 512}, then hash_min over {-1, 1, 32, 256}; a threshold
  * leaves its current value only for a candidate more than 3% faster (so that
  * timing noise does not decide between near-equal values).  The other fields of

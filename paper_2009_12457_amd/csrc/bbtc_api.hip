@@ -134,6 +134,7 @@ struct bbtc_plan {
   DevBuf<DevItem> xitems;          // the same items as per-XCD queues (persistent launches)
   DevBuf<HeavyCol> heavy;
   DevBuf<char> emit;               // inputs of the item-emission kernel
+  DevBuf<char> grp;                // chunk list and part counters of the chunked in-row grouping (partition only)
   // host
   std::vector<int32_t> h_cuts;
   std::vector<int64_t> h_nnz, h_nzr, h_nzc;  // nzc in column-major block order
@@ -252,7 +253,7 @@ struct bbtc_plan {
     bot.release(); ccnt.release(); ccoff.release(); cursor.release(); aoff.release(); asrc.release(); icolb.release();
     ocol16.release(); rc.release();
     err.release(); acp.release(); tasks.release(); items.release(); xitems.release(); heavy.release();
-    emit.release();
+    emit.release(); grp.release();
   }
 
   size_t footprint() const {
@@ -262,7 +263,7 @@ struct bbtc_plan {
            hugerows.bytes() + bot.bytes() +
            ccnt.bytes() + ccoff.bytes() + cursor.bytes() + err.bytes() + acp.bytes() + aoff.bytes() + asrc.bytes() +
            icolb.bytes() + ocol16.bytes() + rc.bytes() +
-           tasks.bytes() + items.bytes() + xitems.bytes() + heavy.bytes() + emit.bytes() +
+           tasks.bytes() + items.bytes() + xitems.bytes() + heavy.bytes() + emit.bytes() + grp.bytes() +
            cache.bytes();
   }
 };
@@ -350,6 +351,8 @@ constexpr unsigned kHybridMaxThreads = 16;  // default host threads of the hybri
 constexpr double kTuneMargin = 0.97;        // the autotuner's thresholds change for a gain above 3% only
 constexpr uint32_t kHubChunk = 1024;  // in-neighbours per hub work item
 constexpr int kItemsPerBlock = 20;    // work items per resident workgroup (by estimated work)
+constexpr int64_t kGroupRowCap = 1 << 17;      // long/huge in-rows grouped in chunks, at most
+constexpr uint64_t kGroupCounters = 1u << 22;  // their per-part counters, at most (words)
 
 // The plain HMap mode is the paper's per-task HMap throughout: every live
 // column stages its list alone as a bitmap or hash (no shared sorted stage).
@@ -809,7 +812,7 @@ bbtc_status stream_setup(bbtc_plan* pl, hipStream_t s) {
   pl->keys_a.release(); pl->keys_b.release(); pl->hist.release(); pl->partial.release();
   pl->od.release(); pl->idg.release(); pl->order.release();
   pl->longrows.release(); pl->hugerows.release(); pl->midrows.release(); pl->ccnt.release(); pl->ccoff.release();
-  pl->in_rowptr.release(); pl->in_col.release(); pl->heavy.release(); pl->emit.release();
+  pl->in_rowptr.release(); pl->in_col.release(); pl->heavy.release(); pl->emit.release(); pl->grp.release();
   return stream_finish(pl, s);
 }
 
@@ -1516,7 +1519,7 @@ bbtc_status partition_budgeted(const bbtc_csr* g, hipStream_t s, bbtc_plan* pl,
                                pl->hugerows.ptr, B.q.ptr, s),
             "sort in-rows");
     HIP_TRY(launch_inrows_group(pl->irow.ptr + R0, ga.ptr - i0, pl->longrows.ptr, pl->hugerows.ptr, B.q.ptr,
-                                gb.ptr - i0, pl->cuts.ptr, p, s),
+                                gb.ptr - i0, pl->cuts.ptr, p, GroupChunks{0, nullptr, nullptr, nullptr}, s),
             "group in-rows");
     uint32_t* ccnt = gcc.ptr;                   // [ncc] column counts, [ncc] entry counts,
     uint32_t* ecnt = gcc.ptr + (ncc + 1);       // then their scans
@@ -1778,8 +1781,20 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
           "sort out-rows");
   HIP_TRY(hipEventRecord(pl->ev_join[0], s), "event");  // the out-rows are done with the scratch
   HIP_TRY(hipStreamWaitEvent(si, pl->ev_join[0], 0), "wait");
+  GroupChunks gc{0, nullptr, nullptr, nullptr};
+  {  // the first rows of the long/huge list are grouped in chunks over the whole chip
+    gc.cap = (uint32_t)std::min<int64_t>(kGroupRowCap, (int64_t)(kGroupCounters / (uint64_t)p));
+    const size_t nck = (size_t)(m / kGroupChunkEntries) + gc.cap + 1;
+    const size_t o_cnt = align16(8 * nck + 16), bytes = o_cnt + 4 * (size_t)gc.cap * (size_t)p;
+    HIP_TRY(pl->grp.ensure(bytes), "alloc in-row chunks");
+    gc.chunks = (uint2*)pl->grp.ptr;
+    gc.nchunks = (uint32_t*)(pl->grp.ptr + 8 * nck);
+    gc.cnt = (uint32_t*)(pl->grp.ptr + o_cnt);
+    HIP_TRY(hipMemsetAsync(gc.nchunks, 0, 16, si), "memset");
+    HIP_TRY(hipMemsetAsync(gc.cnt, 0, bytes - o_cnt, si), "memset");
+  }
   HIP_TRY(launch_inrows_group(pl->irow.ptr, pl->icol.ptr, pl->idg.ptr, (const uint32_t*)pl->keys_a.ptr,
-                              pl->err.ptr + 5, pl->acol.ptr, pl->cuts.ptr, p, si),
+                              pl->err.ptr + 5, pl->acol.ptr, pl->cuts.ptr, p, gc, si),
           "group in-rows");
   HIP_TRY(hipEventSynchronize(pl->ev_cuts), "sync");
   pl->h_cuts.assign((const int32_t*)pl->cstage.ptr, (const int32_t*)pl->cstage.ptr + p + 1);
@@ -2476,6 +2491,20 @@ bbtc_status bbtc_autotune(const bbtc_csr* g, const bbtc_options* base, int32_t r
       st = measure(o, &ms);
       if (st != BBTC_OK) break;
       if (ms < best) { best = ms; best_opt = o; }
+    }
+    // past the ends of the candidates: halve (double) p while the count gets faster
+    for (int dir = 0; dir < 2 && st == BBTC_OK; ++dir) {
+      const int32_t edge = dir == 0 ? ps.front() : ps.back();
+      if (best_opt.p != edge) continue;
+      for (int32_t q = dir == 0 ? edge / 2 : 2 * edge; q >= 1 && q <= pmax; q = dir == 0 ? q / 2 : 2 * q) {
+        bbtc_options o = cur;
+        o.p = q;
+        double ms = 0;
+        st = measure(o, &ms);
+        if (st != BBTC_OK || ms >= best) break;
+        best = ms;
+        best_opt = o;
+      }
     }
     // the two thresholds move off their current value only for a gain above
     // the timing noise, so that repeated tunings of one graph agree

@@ -184,8 +184,20 @@ hipError_t launch_segsort(const uint32_t* rp, int32_t* col, int64_t nrows, int b
 // scratch[] (m words) (launch_inrows_group).
 hipError_t launch_inrows_sort(const uint32_t* rp, int32_t* col, int64_t nrows, uint32_t* midrows, uint32_t* longrows,
                               uint32_t* hugerows, uint32_t* q, hipStream_t s);
+// The first `cap` rows of the combined list (huge rows, then long ones) are
+// grouped in chunks spread over the chip: chunks holds room for m / 4096 +
+// cap entries, *nchunks and cnt (cap * p words) are zero on entry.  cap = 0:
+// every listed row by one workgroup.
+struct GroupChunks {
+  uint32_t cap;
+  uint2* chunks;
+  uint32_t* nchunks;
+  uint32_t* cnt;
+};
+constexpr uint32_t kGroupChunkEntries = 4096;
 hipError_t launch_inrows_group(const uint32_t* rp, int32_t* col, const uint32_t* longrows, const uint32_t* hugerows,
-                               const uint32_t* q, int32_t* scratch, const int32_t* cuts, int32_t p, hipStream_t s);
+                               const uint32_t* q, int32_t* scratch, const int32_t* cuts, int32_t p,
+                               const GroupChunks& gc, hipStream_t s);
 // Four degree thresholds (a negative one counts no rank).
 struct DegThresholds {
   int64_t t[4];

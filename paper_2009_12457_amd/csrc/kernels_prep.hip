@@ -765,41 +765,77 @@ __global__ __launch_bounds__(kThreads) void k_segsort(const uint32_t* __restrict
   }
 }
 
-// Wavefront per queued row of up to kSegWave entries: bitonic sort across the
-// lanes' registers for rows of up to 64 entries, in LDS beyond.
+// Bitonic sort of 64*E values held by one wavefront, E consecutive values
+// per lane (value i in register i mod E of lane i / E): exchanges at
+// distances below E stay in registers, longer ones pair lane l with lane
+// l ^ (distance / E) through a lane shuffle; no LDS.
+template <int E>
+__device__ __forceinline__ void bitonic_wave(int32_t (&v)[E], uint32_t l) {
+#pragma unroll
+  for (uint32_t k = 2; k <= 64u * E; k <<= 1) {
+#pragma unroll
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      if (j < (uint32_t)E) {
+#pragma unroll
+        for (uint32_t r = 0; r < (uint32_t)E; ++r) {
+          const uint32_t o = r ^ j;
+          if (o > r) {
+            const bool up = ((l * E + r) & k) == 0;
+            const int32_t a = v[r], b = v[o];
+            v[r] = up ? min(a, b) : max(a, b);
+            v[o] = up ? max(a, b) : min(a, b);
+          }
+        }
+      } else {
+        const int lj = (int)(j / E);
+        const bool low = (l & (uint32_t)lj) == 0;
+#pragma unroll
+        for (uint32_t r = 0; r < (uint32_t)E; ++r) {
+          const int32_t y = __shfl_xor(v[r], lj, kWave);
+          const bool up = ((l * E + r) & k) == 0;
+          v[r] = (low == up) ? min(v[r], y) : max(v[r], y);
+        }
+      }
+    }
+  }
+}
+
+// col[s, s+len) sorted by one wavefront in registers, len <= 64*E.
+template <int E>
+__device__ __forceinline__ void sort_row_wave(int32_t* __restrict__ col, uint32_t s, uint32_t len, uint32_t l) {
+  int32_t v[E];
+#pragma unroll
+  for (uint32_t r = 0; r < (uint32_t)E; ++r) {
+    const uint32_t t = l * E + r;
+    v[r] = t < len ? col[s + t] : 0x7FFFFFFF;
+  }
+  bitonic_wave<E>(v, l);
+#pragma unroll
+  for (uint32_t r = 0; r < (uint32_t)E; ++r) {
+    const uint32_t t = l * E + r;
+    if (t < len) col[s + t] = v[r];
+  }
+}
+
+// Wavefront per queued row of up to kSegWave entries, sorted in the lanes'
+// registers (bitonic_wave) at the power of two that holds it.
 __global__ __launch_bounds__(kThreads) void k_segsort_mid(const uint32_t* __restrict__ rp, int32_t* __restrict__ col,
                                                           const uint32_t* __restrict__ midrows,
                                                           const uint32_t* __restrict__ q) {
-  __shared__ int32_t buf[4][kSegWave];
-  const int l = lane_id(), w = threadIdx.x / kWave;
+  static_assert(kSegWave == 16 * kWave, "rows of up to 16 entries per lane");
+  const uint32_t l = (uint32_t)lane_id();
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
-  int32_t* b = buf[w];
   const uint32_t cnt = q[2];
   for (int64_t i = wave; i < cnt; i += nwaves) {
     const uint32_t r = midrows[i];
     const uint32_t s = rp[r], len = rp[r + 1] - s;
     if (len > kSegWave) continue;
-    if (len <= (uint32_t)kWave) {  // one entry per lane: bitonic network over the lanes
-      int32_t x = (uint32_t)l < len ? col[s + l] : 0x7FFFFFFF;
-#pragma unroll
-      for (uint32_t k = 2; k <= (uint32_t)kWave; k <<= 1) {
-#pragma unroll
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-          const int32_t y = __shfl_xor(x, (int)j, kWave);
-          const bool up = ((uint32_t)l & k) == 0, low = ((uint32_t)l & j) == 0;
-          x = (low == up) ? min(x, y) : max(x, y);
-        }
-      }
-      if ((uint32_t)l < len) col[s + l] = x;
-      continue;
-    }
-    const uint32_t N = pow2_at_least(len);
-    for (uint32_t t = l; t < N; t += kWave) b[t] = t < len ? col[s + t] : 0x7FFFFFFF;
-    wave_sync();
-    bitonic_lds(b, N, (uint32_t)l, kWave, wave_sync);
-    for (uint32_t t = l; t < len; t += kWave) col[s + t] = b[t];
-    wave_sync();
+    if (len <= 64u) sort_row_wave<1>(col, s, len, l);
+    else if (len <= 128u) sort_row_wave<2>(col, s, len, l);
+    else if (len <= 256u) sort_row_wave<4>(col, s, len, l);
+    else if (len <= 512u) sort_row_wave<8>(col, s, len, l);
+    else sort_row_wave<16>(col, s, len, l);
   }
 }
 
@@ -1009,20 +1045,26 @@ __device__ __forceinline__ uint32_t block_excl_scan_n(uint32_t v, uint32_t* lds,
 
 constexpr int kGroupUnroll = 4;  // entries per thread in flight in k_group_parts
 
+// Rows whose combined list index (the huge rows, then the long ones after
+// the *before huge rows) is below `taken` were grouped by the chunked
+// kernels and are skipped.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_group_parts(const uint32_t* __restrict__ rp, int32_t* __restrict__ col,
                                                     int32_t* __restrict__ scratch, const uint32_t* __restrict__ rows,
                                                     const uint32_t* __restrict__ nrows,
-                                                    const int32_t* __restrict__ cuts, int32_t p) {
+                                                    const int32_t* __restrict__ cuts, int32_t p,
+                                                    const uint32_t* __restrict__ before, uint32_t taken) {
   __shared__ int32_t scut[kMaxP + 1];
   __shared__ uint32_t bins[kMaxP];
   __shared__ uint32_t lds[NT / kWave];
   const int t = threadIdx.x;
   for (int a = t; a <= p; a += NT) scut[a] = cuts[a];
   const uint32_t cnt = *nrows;
+  const uint32_t b0 = before ? *before : 0u;
+  const uint32_t first = taken > b0 ? taken - b0 : 0u;
   const int per = (p + NT - 1) / NT;  // bins per thread in the scan
   __syncthreads();
-  for (uint32_t qi = blockIdx.x; qi < cnt; qi += gridDim.x) {
+  for (uint32_t qi = first + blockIdx.x; qi < cnt; qi += gridDim.x) {
     const uint32_t r = rows[qi];
     const uint32_t s = rp[r], len = rp[r + 1] - s;
     for (int a = t; a < p; a += NT) bins[a] = 0;
@@ -1070,6 +1112,181 @@ __global__ __launch_bounds__(NT) void k_group_parts(const uint32_t* __restrict__
   }
 }
 
+// Chunked grouping of the long and huge in-rows: a hub's in-row (hundreds of
+// thousands of entries) is cut into chunks of kGroupChunk entries spread
+// over the whole chip instead of one workgroup per row.  The first `cap`
+// rows of the combined list (huge rows, then long rows) take this path:
+//   k_gchunk_list   the chunks (row index, chunk number), one thread per row;
+//   k_gchunk_count  per chunk, the entries of each part (LDS counts, then one
+//                   global add per part into cnt[row * p + part]);
+//   k_gchunk_scan   per row, cnt becomes the exclusive prefix over the parts
+//                   (the start of each part within the row);
+//   k_gchunk_scatter per chunk, recounted; each part's range is reserved by
+//                   one global atomic on cnt and the entries are scattered
+//                   into scratch (order within a part is free);
+//   k_gchunk_copy   the rows back from scratch.
+constexpr uint32_t kGroupChunk = kGroupChunkEntries;
+
+__device__ __forceinline__ uint32_t glist_row(const uint32_t* longrows, const uint32_t* hugerows, uint32_t nhuge,
+                                              uint32_t li) {
+  return li < nhuge ? hugerows[li] : longrows[li - nhuge];
+}
+
+__global__ __launch_bounds__(kThreads) void k_gchunk_list(const uint32_t* __restrict__ rp,
+                                                          const uint32_t* __restrict__ longrows,
+                                                          const uint32_t* __restrict__ hugerows,
+                                                          const uint32_t* __restrict__ q, uint32_t cap,
+                                                          uint2* __restrict__ chunks, uint32_t* __restrict__ nchunks) {
+  const uint32_t nhuge = q[1], nrows = min(q[0] + nhuge, cap);
+  for (uint32_t li = blockIdx.x * kThreads + threadIdx.x; li < nrows; li += gridDim.x * kThreads) {
+    const uint32_t r = glist_row(longrows, hugerows, nhuge, li);
+    const uint32_t len = rp[r + 1] - rp[r];
+    const uint32_t nc = (len + kGroupChunk - 1) / kGroupChunk;
+    const uint32_t at = atomicAdd(nchunks, nc);
+    for (uint32_t c = 0; c < nc; ++c) chunks[at + c] = make_uint2(li, c);
+  }
+}
+
+// Counts the parts of chunk (li, c) into bins (LDS, zero on entry); returns
+// the row's start and length and the chunk's range.
+__device__ __forceinline__ void gchunk_bins(const uint32_t* rp, const int32_t* col, const uint32_t* longrows,
+                                            const uint32_t* hugerows, uint32_t nhuge, uint2 ch, const int32_t* scut,
+                                            int32_t p, uint32_t* bins, uint32_t& s, uint32_t& len, uint32_t& e0,
+                                            uint32_t& e1) {
+  const uint32_t r = glist_row(longrows, hugerows, nhuge, ch.x);
+  s = rp[r];
+  len = rp[r + 1] - s;
+  e0 = ch.y * kGroupChunk;
+  e1 = min(len, e0 + kGroupChunk);
+  for (uint32_t e = e0 + threadIdx.x; e < e1; e += kThreads) atomicAdd(&bins[part_of(scut, p, col[s + e])], 1u);
+}
+
+__global__ __launch_bounds__(kThreads) void k_gchunk_count(const uint32_t* __restrict__ rp,
+                                                           const int32_t* __restrict__ col,
+                                                           const uint32_t* __restrict__ longrows,
+                                                           const uint32_t* __restrict__ hugerows,
+                                                           const uint32_t* __restrict__ q,
+                                                           const uint2* __restrict__ chunks,
+                                                           const uint32_t* __restrict__ nchunks,
+                                                           const int32_t* __restrict__ cuts, int32_t p,
+                                                           uint32_t* __restrict__ cnt) {
+  extern __shared__ uint32_t lds_gc[];
+  int32_t* scut = (int32_t*)lds_gc;  // p + 1
+  uint32_t* bins = lds_gc + p + 1;   // p
+  for (int a = threadIdx.x; a <= p; a += kThreads) scut[a] = cuts[a];
+  const uint32_t nhuge = q[1], nc = *nchunks;
+  for (uint32_t c = blockIdx.x; c < nc; c += gridDim.x) {
+    for (int a = threadIdx.x; a < p; a += kThreads) bins[a] = 0;
+    __syncthreads();
+    const uint2 ch = chunks[c];
+    uint32_t s, len, e0, e1;
+    gchunk_bins(rp, col, longrows, hugerows, nhuge, ch, scut, p, bins, s, len, e0, e1);
+    __syncthreads();
+    for (int a = threadIdx.x; a < p; a += kThreads)
+      if (bins[a]) atomicAdd(&cnt[(uint64_t)ch.x * p + a], bins[a]);
+    __syncthreads();
+  }
+}
+
+// One wavefront per row: cnt[row * p .. +p) becomes its exclusive prefix.
+__global__ __launch_bounds__(kThreads) void k_gchunk_scan(const uint32_t* __restrict__ q, uint32_t cap, int32_t p,
+                                                          uint32_t* __restrict__ cnt) {
+  const uint32_t nrows = min(q[0] + q[1], cap);
+  const uint32_t l = (uint32_t)lane_id();
+  const uint32_t wave = (blockIdx.x * kThreads + threadIdx.x) / kWave, nwaves = gridDim.x * (kThreads / kWave);
+  for (uint32_t li = wave; li < nrows; li += nwaves) {
+    uint32_t* c = cnt + (uint64_t)li * p;
+    uint32_t carry = 0;
+    for (int32_t a0 = 0; a0 < p; a0 += kWave) {
+      const int32_t a = a0 + (int32_t)l;
+      const uint32_t v = a < p ? c[a] : 0u;
+      const uint32_t inc = wave_incl_scan_u32(v);
+      if (a < p) c[a] = carry + inc - v;
+      carry += last_lane(inc);
+    }
+  }
+}
+
+// The chunk's entries are first placed part by part in an LDS buffer, then
+// written out in that order, so that every part's run goes to consecutive
+// positions of the row (coalesced) rather than entry by entry.
+__global__ __launch_bounds__(kThreads) void k_gchunk_scatter(const uint32_t* __restrict__ rp,
+                                                             const int32_t* __restrict__ col,
+                                                             const uint32_t* __restrict__ longrows,
+                                                             const uint32_t* __restrict__ hugerows,
+                                                             const uint32_t* __restrict__ q,
+                                                             const uint2* __restrict__ chunks,
+                                                             const uint32_t* __restrict__ nchunks,
+                                                             const int32_t* __restrict__ cuts, int32_t p,
+                                                             uint32_t* __restrict__ cnt,
+                                                             int32_t* __restrict__ scratch) {
+  extern __shared__ uint32_t lds_gc[];
+  int32_t* scut = (int32_t*)lds_gc;  // p + 1
+  uint32_t* bins = lds_gc + p + 1;   // p: counts, then the next free slot of each part in buf
+  uint32_t* lstart = bins + p;       // p: first slot of each part in buf
+  uint32_t* gbase = lstart + p;      // p: position of the part's run in the row
+  int32_t* buf = (int32_t*)(gbase + p);  // kGroupChunk
+  __shared__ uint32_t red[kThreads / kWave];
+  for (int a = threadIdx.x; a <= p; a += kThreads) scut[a] = cuts[a];
+  const uint32_t nhuge = q[1], nc = *nchunks;
+  const int per = (p + kThreads - 1) / kThreads;  // parts per thread in the scan
+  for (uint32_t c = blockIdx.x; c < nc; c += gridDim.x) {
+    for (int a = threadIdx.x; a < p; a += kThreads) bins[a] = 0;
+    __syncthreads();
+    const uint2 ch = chunks[c];
+    uint32_t s, len, e0, e1;
+    gchunk_bins(rp, col, longrows, hugerows, nhuge, ch, scut, p, bins, s, len, e0, e1);
+    __syncthreads();
+    uint32_t sum = 0;
+    for (int k = 0; k < per; ++k) {
+      const int a = threadIdx.x * per + k;
+      if (a < p) sum += bins[a];
+    }
+    uint32_t tot;
+    uint32_t off = block_excl_scan_n<kThreads>(sum, red, &tot);
+    for (int k = 0; k < per; ++k) {
+      const int a = threadIdx.x * per + k;
+      if (a < p) {
+        const uint32_t n = bins[a];
+        lstart[a] = off;
+        gbase[a] = n ? atomicAdd(&cnt[(uint64_t)ch.x * p + a], n) : 0u;  // this chunk's run of part a
+        bins[a] = off;
+        off += n;
+      }
+    }
+    __syncthreads();
+    for (uint32_t e = e0 + threadIdx.x; e < e1; e += kThreads) {
+      const int32_t v = col[s + e];
+      buf[atomicAdd(&bins[part_of(scut, p, v)], 1u)] = v;
+    }
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < e1 - e0; t += kThreads) {
+      const int32_t v = buf[t];
+      const int32_t a = part_of(scut, p, v);
+      const uint32_t pos = gbase[a] + (t - lstart[a]);
+      if (pos < len) scratch[s + pos] = v;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_gchunk_copy(const uint32_t* __restrict__ rp, int32_t* __restrict__ col,
+                                                          const uint32_t* __restrict__ longrows,
+                                                          const uint32_t* __restrict__ hugerows,
+                                                          const uint32_t* __restrict__ q,
+                                                          const uint2* __restrict__ chunks,
+                                                          const uint32_t* __restrict__ nchunks,
+                                                          const int32_t* __restrict__ scratch) {
+  const uint32_t nhuge = q[1], nc = *nchunks;
+  for (uint32_t c = blockIdx.x; c < nc; c += gridDim.x) {
+    const uint2 ch = chunks[c];
+    const uint32_t r = glist_row(longrows, hugerows, nhuge, ch.x);
+    const uint32_t s = rp[r], len = rp[r + 1] - s;
+    const uint32_t e1 = min(len, (ch.y + 1) * kGroupChunk);
+    for (uint32_t e = ch.y * kGroupChunk + threadIdx.x; e < e1; e += kThreads) col[s + e] = scratch[s + e];
+  }
+}
+
 // ------------------------------------------------------------ block row index
 // Workgroup per chunk of kPrepRows consecutive rows of one part; thread per
 // row.  chunk0[a] is the first chunk of part a.
@@ -1098,54 +1315,176 @@ __device__ __forceinline__ uint32_t seek(const int32_t* __restrict__ col, uint32
 
 // Out side: the row of u in part a gets its block boundaries for b = a..p
 // (written for stored rows, u >= rT, only); per block the entries, the
-// non-empty rows and the longest slice are counted for every row.
-__global__ __launch_bounds__(kThreads) void k_bot(BlockBuild bb) {
-  __shared__ uint32_t s_nnz[kMaxP];
-  __shared__ uint32_t s_nzr[kMaxP];
-  __shared__ uint32_t s_dmax, s_dfull;
+// non-empty rows and the longest slice are counted for every row.  A row of
+// at most kBotLane entries is walked by its own thread; longer rows are
+// queued and taken by whole wavefronts (part_bounds_wave below; the row is
+// sorted, so the boundary of block b is its first entry of a block >= b).
+// Workgroups take chunks of kPrepRows rows in turn (grid-stride) and add
+// their block counters to the global ones when their part changes and at the
+// end.  LDS (dynamic, sized by p): per-block entry and row counters, the cut
+// vector, one boundary row per wavefront and the long-row queue.
+constexpr uint32_t kBotLane = 32;
+
+// One wavefront: the slice boundaries of a row col[rb, re) whose entries lie
+// in parts [first, last) in non-decreasing part order.  pos[x - first] is the
+// first position holding a part >= x, for x in [first, last] (pos[0] = rb,
+// pos[last - first] = re).  Rows of up to kWalkRow entries are walked 64
+// entries at a time: the entry where the part changes is the boundary of
+// every part in between.  Longer rows (a hub's in-row has hundreds of
+// thousands of entries) are searched instead, one part per lane: the entries
+// below c_x form a prefix of the row.  Ends with the wavefront's writes
+// visible to it.
+constexpr uint32_t kWalkRow = 1024;
+
+__device__ __forceinline__ void part_bounds_wave(const int32_t* __restrict__ col, uint32_t rb, uint32_t re,
+                                                 int32_t first, int32_t last, const int32_t* scut, int32_t p,
+                                                 uint32_t* pos) {
+  const int l = lane_id();
+  if (re - rb <= kWalkRow) {
+    int32_t carry = first;  // part of the entry before the current 64
+    for (uint32_t q = rb; q < re; q += kWave) {
+      const uint32_t e = q + (uint32_t)l;
+      const int32_t pe = e < re ? part_of(scut, p, col[e]) : last;
+      int32_t prv = __shfl_up(pe, 1, kWave);
+      if (l == 0) prv = carry;
+      for (int32_t x = prv + 1; x <= pe; ++x) pos[x - first] = e;  // e = re for the first lane past the row
+      carry = __shfl(pe, kWave - 1, kWave);
+    }
+    for (int32_t x = carry + 1 + l; x <= last; x += kWave) pos[x - first] = re;  // rows ending on a multiple of 64
+  } else {
+    for (int32_t x = first + 1 + l; x < last; x += kWave) {
+      const int32_t key = scut[x];
+      uint32_t lo = rb, hi = re;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (col[mid] < key) lo = mid + 1; else hi = mid;
+      }
+      pos[x - first] = lo;
+    }
+    if (l == 0) pos[last - first] = re;
+  }
+  if (l == 0) pos[0] = rb;
+  wave_sync();
+}
+
+__host__ __device__ constexpr size_t bot_lds_words(int32_t p) {
+  return 2 * (size_t)p + (size_t)(p + 1) + 4 * (size_t)(p + 2) + kThreads + 4;
+}
+
+__global__ __launch_bounds__(kThreads) void k_bot(BlockBuild bb, int nchunks) {
+  extern __shared__ uint32_t lds_bot[];
   const int32_t p = bb.p;
-  const int chunk = (int)blockIdx.x + bb.chunk_base;
-  const int a = chunk_part(bb.chunk0, p, chunk);
-  const int lc = chunk - bb.chunk0[a];
-  const int nb = p - a;  // blocks (a,a)..(a,p-1)
-  for (int b = threadIdx.x; b < nb; b += kThreads) s_nnz[b] = s_nzr[b] = 0;
-  if (threadIdx.x == 0) s_dmax = s_dfull = 0;
+  uint32_t* s_nnz = lds_bot;                      // p
+  uint32_t* s_nzr = s_nnz + p;                    // p
+  int32_t* s_cut = (int32_t*)(s_nzr + p);         // p + 1
+  uint32_t* s_pos = (uint32_t*)(s_cut + p + 1);   // 4 x (p + 2)
+  uint32_t* s_q = s_pos + 4 * (p + 2);            // kThreads
+  uint32_t* s_misc = s_q + kThreads;              // dmax, dfull, queue length
+  for (int b = threadIdx.x; b < p; b += kThreads) s_nnz[b] = s_nzr[b] = 0;
+  for (int b = threadIdx.x; b <= p; b += kThreads) s_cut[b] = bb.cuts[b];
+  if (threadIdx.x < 3) s_misc[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t ca = bb.cuts[a];
-  const int64_t u = ca + (int64_t)lc * kPrepRows + threadIdx.x;
-  if (u < bb.cuts[a + 1]) {
-    const uint32_t rb = bb.orow[u], re = bb.orow[u + 1];
+  // the block counters of part `held` go out when the part changes (a
+  // workgroup's chunks come in increasing part order) and at the end: one
+  // global add per workgroup and block instead of one per chunk
+  int held = -1;
+  auto flush = [&]() {
+    const int64_t bid0 = block_id(p, held, held);
+    for (int b = threadIdx.x; b < p - held; b += kThreads) {
+      if (s_nnz[b]) {
+        atomicAdd(&bb.bnnz[bid0 + b], (unsigned long long)s_nnz[b]);
+        atomicAdd(&bb.bnzr[bid0 + b], (unsigned long long)s_nzr[b]);
+      }
+      s_nnz[b] = s_nzr[b] = 0;
+    }
+  };
+  const int w = threadIdx.x / kWave, l = lane_id();
+  uint32_t* pos = s_pos + w * (p + 2);  // pos[b - a]: boundary of block b, b = a..p
+  for (int ci = blockIdx.x; ci < nchunks; ci += gridDim.x) {
+    const int chunk = ci + bb.chunk_base;
+    const int a = chunk_part(bb.chunk0, p, chunk);
+    if (a != held) {
+      if (held >= 0) flush();
+      held = a;
+      __syncthreads();
+    }
+    const int lc = chunk - bb.chunk0[a];
+    const int64_t ca = s_cut[a];
     const int64_t sa = ca > bb.rT ? ca : (int64_t)bb.rT;  // first stored row of part a
     // column-major per part: entry b-a of row u at column (b-a), row u - sa
-    const uint64_t ns = (uint64_t)(bb.cuts[a + 1] - sa);  // stored rows of part a
-    uint32_t* out = u >= sa ? bb.bot + bb.botp[a] + (uint64_t)(u - sa) : nullptr;
+    const uint64_t ns = (uint64_t)(s_cut[a + 1] - sa);  // stored rows of part a
+    const int64_t u = ca + (int64_t)lc * kPrepRows + threadIdx.x;
+    const bool live = u < s_cut[a + 1];
+    const uint32_t rb = live ? bb.orow[u] : 0u, re = live ? bb.orow[u + 1] : 0u;
+    const bool walk = live && re - rb <= kBotLane;  // this thread's row; longer ones are queued
+    if (live && !walk) s_q[atomicAdd(&s_misc[2], 1u)] = (uint32_t)threadIdx.x;
+    {
+      const uint32_t dfull = wave_max_u32(re - rb);
+      if (l == 0 && dfull) atomicMax(&s_misc[1], dfull);
+    }
+    // every lane runs the block loop (walk or not) so that the per-block sums
+    // over the wavefront's rows are formed by lane reductions: one LDS atomic
+    // per wavefront and block instead of one per row
+    uint32_t* out = walk && u >= sa ? bb.bot + bb.botp[a] + (uint64_t)(u - sa) : nullptr;
     if (out) out[0] = rb;
+    const uint32_t rw = walk ? re : rb;  // the end of the walk (none for a queued row)
     uint32_t ptr = rb, prev = rb, dmax = 0;
     for (int b = a + 1; b <= p; ++b) {
-      ptr = (b == p) ? re : seek(bb.ocol, ptr, re, bb.cuts[b]);
-      if (out) out[(uint64_t)(b - a) * ns] = ptr;
-      const uint32_t len = ptr - prev;
-      if (len) {
-        atomicAdd(&s_nnz[b - 1 - a], len);
-        atomicAdd(&s_nzr[b - 1 - a], 1u);
-        dmax = len > dmax ? len : dmax;
+      if (b == p) {
+        ptr = rw;
+      } else {
+        const int32_t key = s_cut[b];
+        while (ptr < rw && bb.ocol[ptr] < key) ++ptr;
       }
+      if (out) out[(uint64_t)(b - a) * ns] = ptr;
+      const uint32_t len = walk ? ptr - prev : 0u;
+      const uint32_t rows = (uint32_t)__popcll(ballot(len != 0));
+      if (rows) {
+        const uint32_t sum = last_lane(wave_incl_scan_u32(len));
+        if (l == 0) {
+          atomicAdd(&s_nnz[b - 1 - a], sum);
+          atomicAdd(&s_nzr[b - 1 - a], rows);
+        }
+      }
+      dmax = len > dmax ? len : dmax;
       prev = ptr;
     }
-    if (dmax) atomicMax(&s_dmax, dmax);
-    if (re > rb) atomicMax(&s_dfull, re - rb);
+    dmax = wave_max_u32(dmax);
+    if (l == 0 && dmax) atomicMax(&s_misc[0], dmax);
+    __syncthreads();
+    // long rows, one wavefront each
+    const uint32_t nq = s_misc[2];
+    for (uint32_t h = w; h < nq; h += kThreads / kWave) {
+      const int64_t v = ca + (int64_t)lc * kPrepRows + s_q[h];
+      const uint32_t rb = bb.orow[v], re = bb.orow[v + 1];
+      part_bounds_wave(bb.ocol, rb, re, a, p, s_cut, p, pos);  // entries lie in blocks a..p-1
+      uint32_t* out = v >= sa ? bb.bot + bb.botp[a] + (uint64_t)(v - sa) : nullptr;
+      uint32_t dmax = 0;
+      for (int32_t b = a + l; b <= p; b += kWave) {
+        const uint32_t pb = pos[b - a];
+        if (out) out[(uint64_t)(b - a) * ns] = pb;
+        if (b < p) {
+          const uint32_t len = pos[b + 1 - a] - pb;
+          if (len) {
+            atomicAdd(&s_nnz[b - a], len);
+            atomicAdd(&s_nzr[b - a], 1u);
+            dmax = len > dmax ? len : dmax;
+          }
+        }
+      }
+      dmax = wave_max_u32(dmax);
+      if (l == 0 && dmax) atomicMax(&s_misc[0], dmax);
+      wave_sync();  // pos is rewritten by the next row
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) s_misc[2] = 0;  // the queue of the next chunk
+    __syncthreads();
   }
   __syncthreads();
-  const int64_t bid0 = block_id(p, a, a);
-  for (int b = threadIdx.x; b < nb; b += kThreads) {
-    if (s_nnz[b]) {
-      atomicAdd(&bb.bnnz[bid0 + b], (unsigned long long)s_nnz[b]);
-      atomicAdd(&bb.bnzr[bid0 + b], (unsigned long long)s_nzr[b]);
-    }
-  }
+  if (held >= 0) flush();
   if (threadIdx.x == 0) {
-    if (s_dmax) atomicMax(bb.dmax_block, s_dmax);
-    if (s_dfull) atomicMax(bb.dmax_block + 1, s_dfull);
+    if (s_misc[0]) atomicMax(bb.dmax_block, s_misc[0]);
+    if (s_misc[1]) atomicMax(bb.dmax_block + 1, s_misc[1]);
   }
 }
 
@@ -1166,39 +1505,107 @@ __device__ __forceinline__ uint32_t in_slice_end(const BlockBuild& bb, uint32_t 
   return (a + 1 == na) ? re : seek(bb.icol, lo, re, bb.cuts[a + 1]);
 }
 
-__global__ __launch_bounds__(kThreads) void k_acount(BlockBuild bb) {
-  __shared__ uint32_t s_nzc[kMaxP];
-  __shared__ uint32_t s_ent[kMaxP];
+// Workgroups take chunks of 256 columns in turn (grid-stride), thread per
+// column; in-rows longer than kBotLane are queued and taken by whole
+// wavefronts (part_bounds_wave).  Per chunk the counts go to ccnt/ecnt; the
+// active-column totals per block are summed in LDS and added to bnzc when the
+// workgroup's part changes and at the end.  LDS (dynamic): per-block column,
+// entry and total counters, the cut vector, a boundary row per wavefront, the
+// queue.
+__host__ __device__ constexpr size_t acount_lds_words(int32_t p) {
+  return 3 * (size_t)p + (size_t)(p + 1) + 4 * (size_t)(p + 2) + kThreads + 4;
+}
+
+__global__ __launch_bounds__(kThreads) void k_acount(BlockBuild bb, int nchunks) {
+  extern __shared__ uint32_t lds_ac[];
   const int32_t p = bb.p;
-  const int chunk = (int)blockIdx.x + bb.chunk_base;
-  const int b = chunk_part(bb.chunk0, p, chunk);
-  const int lc = chunk - bb.chunk0[b];
-  const int nch = bb.chunk0[b + 1] - bb.chunk0[b];
-  const int na = b + 1;  // blocks (0,b)..(b,b)
-  for (int a = threadIdx.x; a < na; a += kThreads) s_nzc[a] = s_ent[a] = 0;
+  uint32_t* s_nzc = lds_ac;                       // p: active columns of the chunk per block
+  uint32_t* s_ent = s_nzc + p;                    // p: their entries
+  uint32_t* s_tot = s_ent + p;                    // p: active columns of the held part per block
+  int32_t* s_cut = (int32_t*)(s_tot + p);         // p + 1
+  uint32_t* s_pos = (uint32_t*)(s_cut + p + 1);   // 4 x (p + 2)
+  uint32_t* s_q = s_pos + 4 * (p + 2);            // kThreads
+  uint32_t* s_misc = s_q + kThreads;              // queue length
+  for (int a = threadIdx.x; a < p; a += kThreads) s_nzc[a] = s_ent[a] = s_tot[a] = 0;
+  for (int a = threadIdx.x; a <= p; a += kThreads) s_cut[a] = bb.cuts[a];
+  if (threadIdx.x == 0) s_misc[0] = 0;
   __syncthreads();
-  const int64_t cb = bb.cuts[b];
-  const int64_t v = cb + (int64_t)lc * kPrepRows + threadIdx.x;
-  if (v < bb.cuts[b + 1]) {
-    const uint32_t re = bb.irow[v + 1];
-    uint32_t lo = bb.irow[v];
-    for (int a = 0; a < na && lo < re; ++a) {
-      const uint32_t hi = in_slice_end(bb, lo, re, a, na);
-      if (hi > lo) {
-        atomicAdd(&s_nzc[a], 1u);
-        atomicAdd(&s_ent[a], hi - lo);
+  int held = -1;
+  auto flush = [&]() {
+    const int64_t cid0 = (int64_t)held * (held + 1) / 2;
+    for (int a = threadIdx.x; a <= held; a += kThreads) {
+      if (s_tot[a]) atomicAdd(&bb.bnzc[cid0 + a], (unsigned long long)s_tot[a]);
+      s_tot[a] = 0;
+    }
+  };
+  const int w = threadIdx.x / kWave, l = lane_id();
+  uint32_t* pos = s_pos + w * (p + 2);
+  for (int ci = blockIdx.x; ci < nchunks; ci += gridDim.x) {
+    const int chunk = ci + bb.chunk_base;
+    const int b = chunk_part(bb.chunk0, p, chunk);
+    if (b != held) {
+      if (held >= 0) flush();
+      held = b;
+      __syncthreads();
+    }
+    const int lc = chunk - bb.chunk0[b];
+    const int nch = bb.chunk0[b + 1] - bb.chunk0[b];
+    const int na = b + 1;  // blocks (0,b)..(b,b)
+    const int64_t cb = s_cut[b];
+    const int64_t v = cb + (int64_t)lc * kPrepRows + threadIdx.x;
+    const bool live = v < s_cut[b + 1];
+    uint32_t lo = live ? bb.irow[v] : 0u;
+    const uint32_t re = live ? bb.irow[v + 1] : 0u;
+    const bool walk = live && re - lo <= kBotLane;  // this thread's row; longer ones are queued
+    if (live && !walk) s_q[atomicAdd(&s_misc[0], 1u)] = (uint32_t)threadIdx.x;
+    // the wavefront walks its rows' parts together (until every row is done)
+    // so that the per-block sums are formed by lane reductions: one LDS
+    // atomic per wavefront and block instead of one per column
+    const uint32_t rw = walk ? re : lo;
+    for (int a = 0; a < na && ballot(lo < rw) != 0; ++a) {
+      uint32_t hi = rw;
+      if (a + 1 < na) {
+        const int32_t key = s_cut[a + 1];
+        hi = lo;
+        while (hi < rw && bb.icol[hi] < key) ++hi;
+      }
+      const uint32_t len = hi - lo;
+      const uint32_t cols = (uint32_t)__popcll(ballot(len != 0));
+      if (cols) {
+        const uint32_t sum = last_lane(wave_incl_scan_u32(len));
+        if (l == 0) {
+          atomicAdd(&s_nzc[a], cols);
+          atomicAdd(&s_ent[a], sum);
+        }
       }
       lo = hi;
     }
+    __syncthreads();
+    const uint32_t nq = s_misc[0];
+    for (uint32_t h = w; h < nq; h += kThreads / kWave) {
+      const int64_t x = cb + (int64_t)lc * kPrepRows + s_q[h];
+      part_bounds_wave(bb.icol, bb.irow[x], bb.irow[x + 1], 0, na, s_cut, p, pos);  // in-neighbours in parts 0..b
+      for (int32_t a = l; a < na; a += kWave) {
+        const uint32_t len = pos[a + 1] - pos[a];
+        if (len) {
+          atomicAdd(&s_nzc[a], 1u);
+          atomicAdd(&s_ent[a], len);
+        }
+      }
+      wave_sync();  // pos is rewritten by the next row
+    }
+    __syncthreads();
+    for (int a = threadIdx.x; a < na; a += kThreads) {
+      const uint64_t q = bb.ccbase[b] + (uint64_t)a * nch + lc;
+      bb.ccnt[q] = s_nzc[a];
+      bb.ecnt[q] = s_ent[a];
+      s_tot[a] += s_nzc[a];
+      s_nzc[a] = s_ent[a] = 0;
+    }
+    if (threadIdx.x == 0) s_misc[0] = 0;
+    __syncthreads();
   }
-  __syncthreads();
-  const int64_t cid0 = (int64_t)b * (b + 1) / 2;
-  for (int a = threadIdx.x; a < na; a += kThreads) {
-    if (s_nzc[a]) atomicAdd(&bb.bnzc[cid0 + a], (unsigned long long)s_nzc[a]);
-    const uint64_t q = bb.ccbase[b] + (uint64_t)a * nch + lc;
-    bb.ccnt[q] = s_nzc[a];
-    bb.ecnt[q] = s_ent[a];
-  }
+  if (held >= 0) flush();
 }
 
 // Writes, for every block (a,b), its active columns in increasing order at
@@ -1500,21 +1907,39 @@ hipError_t launch_inrows_sort(const uint32_t* rp, int32_t* col, int64_t nrows, u
 }
 
 hipError_t launch_inrows_group(const uint32_t* rp, int32_t* col, const uint32_t* longrows, const uint32_t* hugerows,
-                               const uint32_t* q, int32_t* scratch, const int32_t* cuts, int32_t p, hipStream_t s) {
-  hipLaunchKernelGGL(k_group_parts<kThreads>, dim3(1024), dim3(kThreads), 0, s, rp, col, scratch, longrows, q, cuts, p);
-  hipLaunchKernelGGL(k_group_parts<1024>, dim3(256), dim3(1024), 0, s, rp, col, scratch, hugerows, q + 1, cuts, p);
+                               const uint32_t* q, int32_t* scratch, const int32_t* cuts, int32_t p,
+                               const GroupChunks& gc, hipStream_t s) {
+  if (gc.cap > 0) {
+    const size_t lds = sizeof(uint32_t) * (2 * (size_t)p + 1);
+    hipLaunchKernelGGL(k_gchunk_list, dim3(64), dim3(kThreads), 0, s, rp, longrows, hugerows, q, gc.cap, gc.chunks,
+                       gc.nchunks);
+    hipLaunchKernelGGL(k_gchunk_count, dim3(2048), dim3(kThreads), lds, s, rp, (const int32_t*)col, longrows, hugerows, q,
+                       (const uint2*)gc.chunks, (const uint32_t*)gc.nchunks, cuts, p, gc.cnt);
+    hipLaunchKernelGGL(k_gchunk_scan, dim3(256), dim3(kThreads), 0, s, q, gc.cap, p, gc.cnt);
+    const size_t lds_s = sizeof(uint32_t) * (4 * (size_t)p + 1 + kGroupChunk);
+    hipLaunchKernelGGL(k_gchunk_scatter, dim3(2048), dim3(kThreads), lds_s, s, rp, (const int32_t*)col, longrows,
+                       hugerows, q, (const uint2*)gc.chunks, (const uint32_t*)gc.nchunks, cuts, p, gc.cnt, scratch);
+    hipLaunchKernelGGL(k_gchunk_copy, dim3(2048), dim3(kThreads), 0, s, rp, col, longrows, hugerows, q,
+                       (const uint2*)gc.chunks, (const uint32_t*)gc.nchunks, (const int32_t*)scratch);
+  }
+  hipLaunchKernelGGL(k_group_parts<kThreads>, dim3(1024), dim3(kThreads), 0, s, rp, col, scratch, longrows, q, cuts, p,
+                     q + 1, gc.cap);
+  hipLaunchKernelGGL(k_group_parts<1024>, dim3(256), dim3(1024), 0, s, rp, col, scratch, hugerows, q + 1, cuts, p,
+                     (const uint32_t*)nullptr, gc.cap);
   return hipGetLastError();
 }
 
 hipError_t launch_bot(const BlockBuild& bb, int nchunks, hipStream_t s) {
   if (nchunks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_bot, dim3(nchunks), dim3(kThreads), 0, s, bb);
+  hipLaunchKernelGGL(k_bot, dim3(nchunks < 2048 ? nchunks : 2048), dim3(kThreads), sizeof(uint32_t) * bot_lds_words(bb.p),
+                     s, bb, nchunks);
   return hipGetLastError();
 }
 
 hipError_t launch_acount(const BlockBuild& bb, int nchunks, hipStream_t s) {
   if (nchunks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_acount, dim3(nchunks), dim3(kThreads), 0, s, bb);
+  hipLaunchKernelGGL(k_acount, dim3(nchunks < 2048 ? nchunks : 2048), dim3(kThreads),
+                     sizeof(uint32_t) * acount_lds_words(bb.p), s, bb, nchunks);
   return hipGetLastError();
 }
 
