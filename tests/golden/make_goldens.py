@@ -5,7 +5,9 @@ balanced cuts).  Calls only the generators and the oracle.
 Stored per workload: n, m, total, the SHA-256 of the per-task vector (uint64
 little-endian, Alg. 4 order) and every 97th per-task entry; under "by_p", the
 total, per-task SHA-256 and cut-vector SHA-256 for every p the autotuner may
-pick from a base of 64 (16, 32, 64, 128).
+pick from a base of 64: its candidates 16, 32, 64, 128 and, past them, the
+halvings down to 1 and the doubling to 256.  Values of p already stored are
+kept unless --all is given.
 
 R-MAT scale 27 (the device-budget workload, p=128) is built by the oracle
 from the raw R-MAT samples (its own canonicalisation; the samples take 17 GB
@@ -31,7 +33,7 @@ import oracle  # noqa: E402
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "full_size.json")
 P = 64
 STRIDE = 97
-TUNER_PS = (16, 32, 64, 128)
+TUNER_PS = (1, 2, 4, 8, 16, 32, 64, 128, 256)
 
 
 def rmat27_entry():
@@ -51,7 +53,7 @@ def rmat27_entry():
             "seconds": round(time.time() - t, 1)}
 
 
-def main(names):
+def main(names, redo):
     data = json.load(open(OUT)) if os.path.exists(OUT) else {}
     for name in names:
         if name == "rmat27":
@@ -64,27 +66,38 @@ def main(names):
         g = graphgen.workload(name)
         og = oracle.OracleGraph.from_graph(g)
         del g
-        cuts = og.cuts(P)
-        tot, per, bn = og.tasks(P, cuts)
-        data[name] = {
-            "n": og.n, "m": og.m, "p": P, "total": tot,
-            "per_task_sha256": hashlib.sha256(per.astype("<u8").tobytes()).hexdigest(),
-            "sample_stride": STRIDE,
-            "per_task_sample": [int(x) for x in per[::STRIDE]],
-            "cuts_sha256": hashlib.sha256(cuts.astype("<i4").tobytes()).hexdigest(),
-        }
-        by_p = {}
+        entry = data.get(name) if not redo else None
+        if entry is None:
+            cuts = og.cuts(P)
+            tot, per, bn = og.tasks(P, cuts)
+            entry = {
+                "n": og.n, "m": og.m, "p": P, "total": tot,
+                "per_task_sha256": hashlib.sha256(per.astype("<u8").tobytes()).hexdigest(),
+                "sample_stride": STRIDE,
+                "per_task_sample": [int(x) for x in per[::STRIDE]],
+                "cuts_sha256": hashlib.sha256(cuts.astype("<i4").tobytes()).hexdigest(),
+                "by_p": {},
+            }
+        by_p = entry.setdefault("by_p", {})
         for q in TUNER_PS:
+            if str(q) in by_p:
+                continue
             qc = og.cuts(q)
             qt, qper, _ = og.tasks(q, qc)
             by_p[str(q)] = {"total": qt, "per_task_sha256": hashlib.sha256(qper.astype("<u8").tobytes()).hexdigest(),
                             "cuts_sha256": hashlib.sha256(qc.astype("<i4").tobytes()).hexdigest()}
-        data[name]["by_p"] = by_p
-        data[name]["seconds"] = round(time.time() - t, 1)
-        print(name, data[name]["total"], data[name]["seconds"], flush=True)
+            print(name, "p", q, qt, round(time.time() - t, 1), flush=True)
+            data[name] = entry
+            with open(OUT, "w") as f:
+                json.dump(data, f, indent=1)
+        entry["by_p"] = {str(q): by_p[str(q)] for q in sorted(int(x) for x in by_p)}
+        entry["seconds"] = round(time.time() - t, 1)
+        data[name] = entry
+        print(name, entry["total"], entry["seconds"], flush=True)
         with open(OUT, "w") as f:
             json.dump(data, f, indent=1)
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or ["rmat24", "er24"])
+    args = [a for a in sys.argv[1:] if a != "--all"]
+    main(args or ["rmat24", "er24"], "--all" in sys.argv[1:])

@@ -63,12 +63,14 @@ def test_full_size_per_task_parity(workload, mode):
 
 
 def test_autotuned_per_task(workload):
-    """The autotuner's choice (p from {16, 32, 64, 128} and the row-mapping
-    knobs) gives the oracle's per-task vector for that p, stored by
-    tests/golden/make_goldens.py."""
+    """The autotuner's choice (p from {16, 32, 64, 128}, or past them by
+    halving down to 1 or doubling, and the row-mapping knobs) gives the
+    oracle's per-task vector for that p, stored by
+    tests/golden/make_goldens.py for p from 1 to 256."""
     name, g, n, rp, ci = workload
     opt, ms = bb.bbtc_autotune(n, rp, ci, base=bb.bbtc_options_default(p=GOLD[name]["p"]), reps=2, trusted=True)
     assert ms > 0
+    assert str(opt.p) in GOLD[name]["by_p"], f"no stored oracle result at p={opt.p}"
     gold = GOLD[name]["by_p"][str(opt.p)]
     plan = bb.bbtc_partition(n, rp, ci, options=opt, trusted=True)
     per, tot = bb.bbtc_count(plan)
