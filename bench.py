@@ -70,6 +70,8 @@ def pmc_key(workload, opt):
         key += f"-b{opt.bound_min_deg}"
     if opt.item_rows:
         key += f"-r{opt.item_rows}"
+    if opt.dense:
+        key += "-nodense"
     return key
 
 
@@ -420,6 +422,8 @@ def options_for(args, name, stream, g):
         opt.bound_min_deg = args.bound_min_deg
     if args.item_rows:
         opt.item_rows = args.item_rows
+    if args.no_dense:
+        opt.dense = -1
     tuned = None
     if args.autotune == "on" or (args.autotune == "auto" and name in AUTOTUNED and not args.p):
         n, rp, ci = bb.csr_of(g, "cuda")
@@ -500,6 +504,7 @@ def main():
     ap.add_argument("--hash-min", type=int, default=0)
     ap.add_argument("--bound-min-deg", type=int, default=0,
                     help="rows of undirected degree above this store block boundaries (-1: every row)")
+    ap.add_argument("--no-dense", action="store_true", help="no dense slices as bitmaps")
     ap.add_argument("--item-rows", type=int, default=0,
                     help="active columns per persistent work item at most (0: library default)")
     ap.add_argument("--no-companion", action="store_true",
@@ -581,7 +586,8 @@ def main():
         st = plan.stats()
         print(json.dumps({"workload": name, "pmc_key": pmc_key(name, opt), "ms_per_step": dt * 1e3 / args.steps,
                           "count_ms": count_event_ms(bb, plan, per, tot, stream, 5), "triangles": int(tot.item()),
-                          "nitems": st["nitems"]}))
+                          "nitems": st["nitems"], "dense_slices": st["dense_slices"],
+                          "dense_bytes": st["dense_bytes"]}))
         return
 
     plain_modes = () if args.no_plain else (("plain_intersect", bb.BBTC_MODE_PLAIN_INTERSECT),

@@ -124,6 +124,8 @@ typedef struct bbtc_csr {
  *                 32 for plans partitioned in pieces within a device budget,
  *                 whose boundaries stream with the out-rows); -1 = store
  *                 every row.
+ *   dense         0: plans held on the device keep the dense slices of their
+ *                 last parts as bitmaps too (see bbtc_partition); -1: none.
  */
 typedef struct bbtc_options {
   int32_t p;
@@ -136,6 +138,7 @@ typedef struct bbtc_options {
   int32_t graph;
   int64_t device_budget_bytes;
   int32_t bound_min_deg;
+  int32_t dense;
 } bbtc_options;
 
 /* Task kinds: EMPTY tasks have an empty block and count 0 without work. */
@@ -176,6 +179,8 @@ typedef struct bbtc_stats {
   int64_t resident_bytes; /* device bytes of the count phase with every stripe and block resident */
   int64_t stored_rows;    /* rows with stored block boundaries (ranks n - stored_rows .. n-1) */
   int64_t bound_bytes;    /* bytes of the stored block boundaries */
+  int64_t dense_slices;   /* slices N(G_ik,u) also held as bitmaps over V_k (see bbtc_partition) */
+  int64_t dense_bytes;    /* bytes of those bitmaps */
 } bbtc_stats;
 
 typedef struct bbtc_plan bbtc_plan;
@@ -189,7 +194,12 @@ void bbtc_options_default(bbtc_options* opt);
  * If *plan is NULL a new plan is created, otherwise it is rebuilt in place,
  * reusing its device buffers when they are large enough.  Returns when the
  * plan is ready (the call synchronises `stream`).  On failure *plan is left
- * as it was (a new plan is not created).
+ * as it was (a new plan is not created).  A plan held on the device also
+ * keeps, for the rows of its last parts (at most 65536 vertices) and the
+ * blocks of those parts, every slice N(G_ik,u) with at least |V_k|/16
+ * entries as a bitmap over V_k as well (no larger than the 16-bit list);
+ * the count probes such a slice word by word against a column's staged
+ * bitmap (bbtc_stats.dense_slices).
  */
 bbtc_status bbtc_partition(const bbtc_csr* g, const bbtc_options* opt, void* stream, bbtc_plan** plan);
 
@@ -334,10 +344,12 @@ bbtc_status bbtc_check_tables(const bbtc_tables* tables);
 
 /*
  * Copies a plan's tables and work items to the host (synchronising `stream`)
- * and checks them: the tables as bbtc_check_tables, and every work item
- * within its task's active columns or hub in-slice, the items of each task
- * covering its columns exactly once.  BBTC_EDEVICE names the first
- * violation.  O(m + p^2 + items) host work, for tests and debugging.
+ * and checks them: the tables as bbtc_check_tables, every dense slice's
+ * bitmap against its slice (and that exactly the slices with at least
+ * |V_k|/16 entries have one), and every work item within its task's active
+ * columns or hub in-slice, the items of each task covering its columns
+ * exactly once.  BBTC_EDEVICE names the first violation.  O(m + p^2 + items
+ * + bitmap words) host work, for tests and debugging.
  */
 bbtc_status bbtc_plan_verify(const bbtc_plan* plan, void* stream);
 

@@ -49,7 +49,8 @@ class bbtc_options(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int32), ("cut_mode", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("wave_min", ctypes.c_int32), ("hash_min", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("item_rows", ctypes.c_int32), ("graph", ctypes.c_int32),
-                ("device_budget_bytes", ctypes.c_int64), ("bound_min_deg", ctypes.c_int32)]
+                ("device_budget_bytes", ctypes.c_int64), ("bound_min_deg", ctypes.c_int32),
+                ("dense", ctypes.c_int32)]
 
 
 class bbtc_task(ctypes.Structure):
@@ -66,7 +67,8 @@ class bbtc_stats(ctypes.Structure):
                 ("bytes_total", ctypes.c_int64), ("footprint", ctypes.c_int64), ("partition_ms", ctypes.c_double),
                 ("streamed", ctypes.c_int64), ("stripe_slots", ctypes.c_int64), ("stripe_bytes", ctypes.c_int64),
                 ("stripe_uploads", ctypes.c_int64), ("resident_bytes", ctypes.c_int64),
-                ("stored_rows", ctypes.c_int64), ("bound_bytes", ctypes.c_int64)]
+                ("stored_rows", ctypes.c_int64), ("bound_bytes", ctypes.c_int64),
+                ("dense_slices", ctypes.c_int64), ("dense_bytes", ctypes.c_int64)]
 
 
 class bbtc_hybrid_stats(ctypes.Structure):

@@ -135,6 +135,11 @@ struct bbtc_plan {
   DevBuf<HeavyCol> heavy;
   DevBuf<char> emit;               // inputs of the item-emission kernel
   DevBuf<char> grp;                // chunk list and part counters of the chunked in-row grouping (partition only)
+  // dense slices of the last parts as bitmaps (GraphView::dslot, dbits) and
+  // their counters {words handed out, slices}
+  DevBuf<uint32_t> dslot, dbits, dcount;
+  int32_t dense_k0 = 0;            // first block with dense slices (p: none)
+  int64_t dense_slices = 0, dense_words = 0;
   // host
   std::vector<int32_t> h_cuts;
   std::vector<int64_t> h_nnz, h_nzr, h_nzc;  // nzc in column-major block order
@@ -253,7 +258,7 @@ struct bbtc_plan {
     bot.release(); ccnt.release(); ccoff.release(); cursor.release(); aoff.release(); asrc.release(); icolb.release();
     ocol16.release(); rc.release();
     err.release(); acp.release(); tasks.release(); items.release(); xitems.release(); heavy.release();
-    emit.release(); grp.release();
+    emit.release(); grp.release(); dslot.release(); dbits.release(); dcount.release();
   }
 
   size_t footprint() const {
@@ -264,6 +269,7 @@ struct bbtc_plan {
            ccnt.bytes() + ccoff.bytes() + cursor.bytes() + err.bytes() + acp.bytes() + aoff.bytes() + asrc.bytes() +
            icolb.bytes() + ocol16.bytes() + rc.bytes() +
            tasks.bytes() + items.bytes() + xitems.bytes() + heavy.bytes() + emit.bytes() + grp.bytes() +
+           dslot.bytes() + dbits.bytes() + dcount.bytes() +
            cache.bytes();
   }
 };
@@ -418,6 +424,11 @@ PlanCtx plan_ctx(const bbtc_plan* pl, uint64_t* per_task, uint64_t* total) {
   c.g.bot = pl->bot.ptr;
   c.g.ocol = pl->ocol.ptr;
   c.g.ocol16 = pl->streamed ? nullptr : pl->ocol16.ptr;
+  const bool dense = !pl->streamed && pl->ocol16.ptr != nullptr && pl->dense_k0 < pl->p && pl->dslot.ptr != nullptr;
+  c.g.dense_k0 = dense ? pl->dense_k0 : pl->p;
+  c.g.dense_u0 = dense ? pl->h_cuts[pl->dense_k0] : 0;
+  c.g.dslot = dense ? pl->dslot.ptr : nullptr;
+  c.g.dbits = dense ? pl->dbits.ptr : nullptr;
   c.g.acp = pl->acp.ptr;
   c.g.acol = pl->acol.ptr;
   c.g.aoff = pl->aoff.ptr;
@@ -813,6 +824,8 @@ bbtc_status stream_setup(bbtc_plan* pl, hipStream_t s) {
   pl->od.release(); pl->idg.release(); pl->order.release();
   pl->longrows.release(); pl->hugerows.release(); pl->midrows.release(); pl->ccnt.release(); pl->ccoff.release();
   pl->in_rowptr.release(); pl->in_col.release(); pl->heavy.release(); pl->emit.release(); pl->grp.release();
+  pl->dslot.release(); pl->dbits.release(); pl->dcount.release();
+  pl->dense_k0 = pl->p;
   return stream_finish(pl, s);
 }
 
@@ -950,6 +963,34 @@ bbtc_status count_streamed(bbtc_plan* pl, hipStream_t s, uint64_t* d_per_task, u
   return BBTC_OK;
 }
 
+// Dense slices as bitmaps (resident plans with the 16-bit out-rows): the
+// rows of the last parts, at most kDenseRows of them, against the blocks of
+// those parts.  The bitmap words are bounded by half the entries of those
+// blocks plus a segment's padding per slice (a dense slice has at least
+// |V_k|/16 entries, i.e. at least two per word).
+bbtc_status build_dense(bbtc_plan* pl, bool budgeted, hipStream_t s) {
+  const int32_t p = pl->p;
+  pl->dense_k0 = p;
+  if (budgeted || pl->ocol16.ptr == nullptr || pl->opt.dense == -1) return BBTC_OK;
+  int32_t k0 = p;
+  while (k0 > 0 && (int64_t)pl->h_cuts[p] - pl->h_cuts[k0 - 1] <= kDenseRows) --k0;
+  if (k0 >= p) return BBTC_OK;
+  const int64_t rows = (int64_t)pl->h_cuts[p] - pl->h_cuts[k0], nk = p - k0;
+  uint64_t ent = 0;
+  for (int32_t a = k0; a < p; ++a)
+    for (int32_t k = a; k < p; ++k) ent += (uint64_t)pl->h_nnz[block_id(p, a, k)];
+  const uint64_t cap = ent / 2 + 8 * (uint64_t)std::min<int64_t>(rows * nk, (int64_t)ent) + 8;
+  HIP_TRY(pl->dslot.ensure((size_t)(rows * nk)), "alloc dense slots");
+  HIP_TRY(pl->dbits.ensure((size_t)cap), "alloc dense bitmaps");
+  HIP_TRY(pl->dcount.ensure(4), "alloc");
+  HIP_TRY(hipMemsetAsync(pl->dcount.ptr, 0, 16, s), "memset");
+  HIP_TRY(launch_dense_build(pl->orow.ptr, pl->ocol.ptr, pl->ocol16.ptr, pl->bot.ptr, pl->botp, pl->cuts.ptr, p,
+                             (int32_t)pl->rT, k0, pl->n, pl->dslot.ptr, pl->dbits.ptr, pl->dcount.ptr, cap, s),
+          "dense slices");
+  pl->dense_k0 = k0;
+  return BBTC_OK;
+}
+
 // Block statistics and hub records from the device, the task list and work
 // items (Alg. 4, Sec. 5's estimate), their upload and the plan statistics;
 // then the streaming set-up of a plan over the device budget.  `budgeted`:
@@ -996,6 +1037,10 @@ bbtc_status finish_partition(bbtc_plan* pl, hipStream_t s, uint64_t m, uint64_t 
   acp[0] = 0;
   for (int64_t b = 0; b < nb; ++b) acp[b + 1] = acp[b] + (uint64_t)pl->h_nzc[b];
   compose_tasks(pl);
+  {
+    const bbtc_status dst = build_dense(pl, budgeted, s);
+    if (dst != BBTC_OK) return dst;
+  }
   // the persistent launch reads the per-XCD queues, the plain one the plan order
   const bool queued = opt.mode == BBTC_MODE_PERSISTENT && !budgeted;
   if (queued) {
@@ -1059,7 +1104,11 @@ bbtc_status finish_partition(bbtc_plan* pl, hipStream_t s, uint64_t m, uint64_t 
                            hipMemcpyHostToDevice, s),
             "H2D");
   pl->plan_order_items = !queued;
+  if (pl->dense_k0 < p)  // the dense-slice counters, through the (now free) cut stage
+    HIP_TRY(hipMemcpyAsync(pl->cstage.ptr, pl->dcount.ptr, 8, hipMemcpyDeviceToHost, s), "D2H");
   HIP_TRY(hipStreamSynchronize(s), "sync");
+  pl->dense_words = pl->dense_k0 < p ? ((const uint32_t*)pl->cstage.ptr)[0] : 0;
+  pl->dense_slices = pl->dense_k0 < p ? ((const uint32_t*)pl->cstage.ptr)[1] : 0;
 
   // ---- statistics (Sec. 4.4 quantities and the byte model) ----
   bbtc_stats& st = pl->stats;
@@ -1079,6 +1128,8 @@ bbtc_status finish_partition(bbtc_plan* pl, hipStream_t s, uint64_t m, uint64_t 
   st.wedges = (int64_t)wedges;
   st.stored_rows = n - pl->rT;
   st.bound_bytes = (int64_t)bound_bytes(pl->h_cuts, p, pl->rT);
+  st.dense_slices = pl->dense_slices;
+  st.dense_bytes = 4 * pl->dense_words;
   st.bytes_colidx = 4 * (int64_t)(p + 2) * (int64_t)m;
   int64_t rowidx = 0;
   for (const auto& t : pl->h_tasks)
@@ -1602,6 +1653,7 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
       opt.bound_min_deg < -1)
     return fail(BBTC_EINVAL, "negative option");
   if (opt.graph != 0 && opt.graph != -1) return fail(BBTC_EINVAL, "graph must be 0 or -1");
+  if (opt.dense != 0 && opt.dense != -1) return fail(BBTC_EINVAL, "dense must be 0 or -1");
   const bool on_device = (g->flags & BBTC_CSR_DEVICE) != 0;
   const bool symmetric_check = (g->flags & BBTC_CSR_TRUSTED) == 0;
   const int rp64 = g->rowptr_bits == 64;
@@ -2592,6 +2644,41 @@ bbtc_status bbtc_plan_verify(const bbtc_plan* pl, void* stream) {
                 bot.data(), acp.data(), acol.data(), aoff.data(), icolb.data()};
     std::string msg = check_tables(v);
     if (!msg.empty()) return fail(BBTC_EDEVICE, "plan tables: " + msg);
+    // dense slices: a (row, block) pair of the region has a bitmap exactly
+    // when its slice holds at least |V_k|/16 entries, and the bitmap holds
+    // the slice's vertices and nothing else (padding included)
+    if (!pl->streamed && pl->dense_k0 < p) {
+      const int32_t k0 = pl->dense_k0;
+      const int64_t u0 = pl->h_cuts[k0], nk = p - k0, npairs = (n - u0) * nk;
+      std::vector<uint32_t> dslot((size_t)npairs), dbits((size_t)pl->dense_words + 1);
+      HIP_TRY(hipMemcpyAsync(dslot.data(), pl->dslot.ptr, 4 * npairs, hipMemcpyDeviceToHost, s), "D2H");
+      HIP_TRY(hipMemcpyAsync(dbits.data(), pl->dbits.ptr, 4 * pl->dense_words, hipMemcpyDeviceToHost, s), "D2H");
+      HIP_TRY(hipStreamSynchronize(s), "sync");
+      int64_t seen = 0;
+      std::vector<uint32_t> want;
+      for (int64_t u = u0; u < n; ++u)
+        for (int32_t k = k0; k < p; ++k) {
+          const int64_t ck = pl->h_cuts[k], ck1 = pl->h_cuts[k + 1];
+          const int32_t* r0 = ocol.data() + orow[u];
+          const int32_t* r1 = ocol.data() + orow[u + 1];
+          const int32_t* a0 = std::lower_bound(r0, r1, (int32_t)ck);
+          const int32_t* a1 = std::lower_bound(a0, r1, (int32_t)ck1);
+          const uint64_t len = (uint64_t)(a1 - a0), vk = (uint64_t)(ck1 - ck);
+          const uint32_t slot = dslot[(u - u0) * nk + (k - k0)];
+          const bool dense = len > 0 && 16 * len >= vk;
+          const std::string at = "dense slice of row " + std::to_string(u) + ", block " + std::to_string(k);
+          if (dense != (slot != 0)) return fail(BBTC_EDEVICE, at + (dense ? " missing" : " not dense"));
+          if (!slot) continue;
+          const uint64_t words = ((vk + 31) / 32 + 7) & ~7ull;
+          if (slot - 1 + words > (uint64_t)pl->dense_words) return fail(BBTC_EDEVICE, at + " past the bitmaps");
+          want.assign(words, 0u);
+          for (const int32_t* e = a0; e < a1; ++e) want[(uint32_t)(*e - ck) >> 5] |= 1u << ((uint32_t)(*e - ck) & 31);
+          if (!std::equal(want.begin(), want.end(), dbits.begin() + (slot - 1)))
+            return fail(BBTC_EDEVICE, at + ": bitmap differs from the slice");
+          ++seen;
+        }
+      if (seen != pl->dense_slices) return fail(BBTC_EDEVICE, "dense slice count differs");
+    }
     // every item within its task's active columns or hub in-slice; the
     // column items of a task cover its columns exactly once, hub columns
     // (in-slices longer than the split) excluded

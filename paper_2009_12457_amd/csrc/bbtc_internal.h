@@ -91,7 +91,17 @@ struct GraphView {
   const int32_t* acol;
   const uint32_t* aoff;
   const int32_t* icol;
+  // Dense slices as bitmaps (resident plans): for the rows u >= dense_u0 (the
+  // last parts, at most kDenseRows vertices) and the blocks k >= dense_k0,
+  // dslot[(u - dense_u0) * (p - dense_k0) + (k - dense_k0)] is 0, or 1 + the
+  // word offset in dbits of N(G_ik,u) as a bitmap over V_k (bit x of word
+  // x / 32 for vertex c_k + x; ceil(|V_k|/32) words rounded up to 8, zero
+  // padded) when the slice holds at least |V_k|/16 entries.  dslot null: none.
+  int32_t dense_u0, dense_k0;
+  const uint32_t* dslot;
+  const uint32_t* dbits;
 };
+constexpr int64_t kDenseRows = 65536;
 
 // Everything a counting kernel needs about one plan.
 struct PlanCtx {
@@ -209,6 +219,12 @@ hipError_t launch_degree_stats(const uint32_t* od, const uint32_t* idg, int64_t 
 hipError_t launch_cuts(const uint32_t* orow, int64_t n, int32_t p, int mode, int32_t* cuts, hipStream_t s);
 // ocol16[e] = ocol[e] - (first vertex of the part holding ocol[e]) for e < m,
 // zero up to the next multiple of 8.
+// Dense slices as bitmaps (see GraphView): one wavefront per (row, block)
+// pair of the rows [cuts[k0], n) and blocks [k0, p); words of dbits are
+// handed out from nwords[0] up to cap, nwords[1] counts the dense slices.
+hipError_t launch_dense_build(const uint32_t* orow, const int32_t* ocol, const uint16_t* ocol16, const uint32_t* bot,
+                              const uint64_t* botp, const int32_t* cuts, int32_t p, int32_t rT, int32_t k0, int64_t n,
+                              uint32_t* dslot, uint32_t* dbits, uint32_t* nwords, uint64_t cap, hipStream_t s);
 hipError_t launch_ocol16(const int32_t* ocol, uint64_t m, const int32_t* cuts, int32_t p, uint16_t* ocol16,
                          hipStream_t s);
 

@@ -91,6 +91,12 @@ struct TaskCtx {
   const int32_t* acb;       // active columns, absolute indices
   const uint32_t* aob;      // their in-slice offsets, absolute indices
   const uint16_t* col16;    // resident plans with |V_k| <= 65536: out-rows relative to c_k (else null)
+  // dense slices of block k as bitmaps over V_k (16-bit tasks only; else
+  // dslot null): slot of row u at dslot[(u - du0) * dnk], dwords words each
+  const uint32_t* dslot;
+  const uint32_t* dbits;
+  int32_t du0;
+  uint32_t dnk, dwords;
   const int32_t* ac;        // active columns of block (i,j): acb + acp[cid(i,j)]
   const uint32_t* ao;       // their in-slice offsets (one more entry than columns)
 };
@@ -148,6 +154,12 @@ __device__ __forceinline__ TaskCtx make_ctx(const GraphView& g, const DevTask& t
   c.bjk0 += (uint64_t)c.dkj * nj;
   c.bjk1 = c.bjk0 + nj;
   c.col16 = (g.gi < 0 && g.ocol16 != nullptr && c.ck1 - c.ck <= 65536) ? g.ocol16 : nullptr;
+  c.dslot = nullptr;
+  c.dbits = g.dbits;
+  c.du0 = g.dense_u0;
+  c.dnk = (uint32_t)(g.p - g.dense_k0);
+  c.dwords = ((uint32_t)(c.ck1 - c.ck + 31) / 32 + 7) & ~7u;
+  if (c.col16 != nullptr && g.dslot != nullptr && t.k >= g.dense_k0) c.dslot = g.dslot + (t.k - g.dense_k0);
   const uint64_t a0 = ld_const(g.acp + col_block_id(t.i, t.j));
   c.ac = c.acb + a0;
   c.ao = c.aob + a0;
@@ -415,6 +427,11 @@ __device__ __forceinline__ uint32_t probe_rounds(const int32_t* __restrict__ col
   return cnt;
 }
 
+// A dense slice (stored as a bitmap over V_k) is marked by sa1 = kDenseMark
+// and probed kDenseSeg words per segment.
+constexpr uint32_t kDenseMark = 0xFFFFFFFFu;
+constexpr uint32_t kDenseSeg = 8;
+
 // Segments of the 16-bit out-rows: kSeg16 entries, aligned 16-byte blocks
 // of 8 entries each (the owner search and the segment bounds of a probe
 // round are paid once per segment).
@@ -450,17 +467,27 @@ __device__ __forceinline__ uint32_t load_seg16(const uint16_t* __restrict__ col,
 // Word (x / 32) mod nw as a byte address: bits 5.. of the entry shifted to
 // bits 2.. (low half: x >> 3, high half: x >> 19), masked and ORed into the
 // aligned base; the bit is x mod 32.
-__device__ __forceinline__ uint32_t probe_rounds16(const uint16_t* __restrict__ col, uint32_t tot, const uint32_t* sa0,
-                                                   const uint32_t* sa1, const uint32_t* sex, uint32_t* sown,
-                                                   uint32_t sx, uint32_t ns, uint32_t& rnd, const Stage& st,
-                                                   const uint32_t* buf) {
+__device__ __forceinline__ uint32_t probe_rounds16(const uint16_t* __restrict__ col,
+                                                   const uint32_t* __restrict__ dbits, uint32_t tot,
+                                                   const uint32_t* sa0, const uint32_t* sa1, const uint32_t* sex,
+                                                   uint32_t* sown, uint32_t sx, uint32_t ns, uint32_t& rnd,
+                                                   const Stage& st, const uint32_t* buf) {
   const uint32_t l = (uint32_t)lane_id();
   const uint32_t base = lds_addr(buf), omask = (st.nw - 1) << 2;
   uint32_t cnt = 0;
   for (uint32_t qb = 0; qb < tot; qb += kWave) {
     const uint32_t o = round_owner(sown, sx, ns, qb, ++rnd, l);
     const uint32_t q = qb + l;
-    if (q < tot) {
+    if (q < tot && sa1[o] == kDenseMark) {
+      // a dense N(G_ik,u): 8 words of its bitmap against the same 8 words of
+      // the staged bitmap of V_k (word t covers c_k + 32t .. c_k + 32t + 31)
+      const uint32_t t0 = (q - sex[o]) * kDenseSeg;
+      const uint4* src = reinterpret_cast<const uint4*>(dbits + sa0[o] + t0);
+      const uint4 x0 = src[0], x1 = src[1];
+      const uint32_t xw[kDenseSeg] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+#pragma unroll
+      for (uint32_t h = 0; h < kDenseSeg; ++h) cnt += __popc(xw[h] & lds_load(base | (((t0 + h) << 2) & omask)));
+    } else if (q < tot) {
       uint32_t x[kSeg16 / 2];
       const uint32_t vm = load_seg16(col, sa0[o], sa1[o], q - sex[o], x);
       uint32_t wl[kSeg16 / 2], wh[kSeg16 / 2];
@@ -497,11 +524,20 @@ __device__ uint64_t probe_flat(const TaskCtx& c, uint32_t i0, uint32_t i1, const
   uint64_t cnt = 0;
   uint32_t rnd = 0;
   sown[l] = 0;
+  const bool dense = c16 && c.dslot != nullptr;
   for (uint32_t eb = i0; eb < i1; eb += kWave) {
     const uint32_t e = eb + l;
     uint32_t a0 = 0, a1 = 0;
-    if (e < i1) out_slice_i(c, icol[e], a0, a1);
-    const uint32_t nseg = c16 ? seg_count16(a0, a1) : seg_count_w(a0, a1);
+    if (e < i1) {
+      const int32_t u = icol[e];
+      const uint32_t slot = dense && u >= c.du0 ? c.dslot[(uint32_t)(u - c.du0) * c.dnk] : 0u;
+      out_slice_i(c, u, a0, a1);
+      if (slot && a1 > a0) {
+        a0 = slot - 1;
+        a1 = kDenseMark;
+      }
+    }
+    const uint32_t nseg = a1 == kDenseMark ? c.dwords / kDenseSeg : (c16 ? seg_count16(a0, a1) : seg_count_w(a0, a1));
     const uint32_t inc = wave_incl_scan_u32(nseg);
     const uint32_t tot = last_lane(inc);
     sa0[l] = a0;
@@ -509,7 +545,7 @@ __device__ uint64_t probe_flat(const TaskCtx& c, uint32_t i0, uint32_t i1, const
     sex[l] = inc - nseg;
     wave_sync();
     if (c16)
-      cnt += probe_rounds16(c.col16, tot, sa0, sa1, sex, sown, inc - nseg, nseg, rnd, st, buf);
+      cnt += probe_rounds16(c.col16, c.dbits, tot, sa0, sa1, sex, sown, inc - nseg, nseg, rnd, st, buf);
     else if (st.mode == 1)
       cnt += probe_rounds<1>(col, tot, sa0, sa1, sex, sown, inc - nseg, nseg, rnd, st, buf, sn, (uint32_t)smin,
                                (uint32_t)smax);

@@ -1974,6 +1974,92 @@ hipError_t launch_ocol16(const int32_t* ocol, uint64_t m, const int32_t* cuts, i
   return hipGetLastError();
 }
 
+// Dense slices as bitmaps: one wavefront per (row u, block k) pair, u in
+// [c_k0, n), k in [k0, p).  The slice N(G_ik,u) comes from the stored
+// boundaries (or two searches of a row without them); a slice of at least
+// |V_k|/16 entries (where a bitmap of V_k is no larger than the 16-bit list)
+// is set bit by bit in the wavefront's LDS words and written out whole.
+__global__ __launch_bounds__(kThreads) void k_dense_build(const uint32_t* __restrict__ orow,
+                                                          const int32_t* __restrict__ ocol,
+                                                          const uint16_t* __restrict__ ocol16,
+                                                          const uint32_t* __restrict__ bot,
+                                                          const uint64_t* __restrict__ botp,
+                                                          const int32_t* __restrict__ cuts, int32_t p, int32_t rT,
+                                                          int32_t k0, int64_t n, uint32_t* __restrict__ dslot,
+                                                          uint32_t* __restrict__ dbits, uint32_t* __restrict__ nwords,
+                                                          uint64_t cap) {
+  __shared__ uint32_t bm[kThreads / kWave][kDenseRows / 32];
+  __shared__ int32_t scut[kMaxP + 1];
+  for (int a = threadIdx.x; a <= p; a += kThreads) scut[a] = cuts[a];
+  __syncthreads();
+  const int w = threadIdx.x / kWave, l = lane_id();
+  uint32_t* b = bm[w];
+  const int64_t u0 = scut[k0], nk = p - k0;
+  const int64_t npairs = (n - u0) * nk;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  for (int64_t x = wave; x < npairs; x += nwaves) {  // uniform per wavefront
+    const int64_t u = u0 + x / nk;
+    const int32_t k = k0 + (int32_t)(x % nk);
+    const int32_t a = part_of(scut, p, (int32_t)u);
+    uint32_t a0 = 0, a1 = 0;
+    if (k >= a) {
+      if (u >= rT) {
+        const int64_t sa = scut[a] > rT ? scut[a] : rT;
+        const uint64_t ns = (uint64_t)(scut[a + 1] - sa);
+        const uint32_t* col0 = bot + botp[a] + (uint64_t)(k - a) * ns + (uint64_t)(u - sa);
+        a0 = col0[0];
+        a1 = col0[ns];
+      } else {
+        const uint32_t re = orow[u + 1];
+        uint32_t lo = orow[u], hi = re;
+        while (lo < hi) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (ocol[mid] < scut[k]) lo = mid + 1; else hi = mid;
+        }
+        a0 = lo;
+        hi = re;
+        while (lo < hi) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (ocol[mid] < scut[k + 1]) lo = mid + 1; else hi = mid;
+        }
+        a1 = lo;
+      }
+    }
+    const uint32_t vk = (uint32_t)(scut[k + 1] - scut[k]);
+    uint32_t slot = 0;
+    if (a1 > a0 && vk <= (uint32_t)kDenseRows && 16ull * (a1 - a0) >= vk) {
+      const uint32_t words = ((vk + 31) / 32 + 7) & ~7u;
+      uint32_t off = 0;
+      if (l == 0) off = atomicAdd(nwords, words);
+      off = __shfl(off, 0, kWave);
+      if ((uint64_t)off + words <= cap) {
+        for (uint32_t t = l; t < words; t += kWave) b[t] = 0;
+        wave_sync();
+        for (uint32_t e = a0 + l; e < a1; e += kWave) {
+          const uint32_t v = ocol16[e];
+          atomicOr(&b[v >> 5], 1u << (v & 31));
+        }
+        wave_sync();
+        for (uint32_t t = l; t < words; t += kWave) dbits[off + t] = b[t];
+        wave_sync();
+        slot = off + 1;
+        if (l == 0) atomicAdd(nwords + 1, 1u);
+      }
+    }
+    if (l == 0) dslot[x] = slot;
+  }
+}
+
+hipError_t launch_dense_build(const uint32_t* orow, const int32_t* ocol, const uint16_t* ocol16, const uint32_t* bot,
+                              const uint64_t* botp, const int32_t* cuts, int32_t p, int32_t rT, int32_t k0, int64_t n,
+                              uint32_t* dslot, uint32_t* dbits, uint32_t* nwords, uint64_t cap, hipStream_t s) {
+  if (k0 >= p) return hipSuccess;
+  hipLaunchKernelGGL(k_dense_build, dim3(1024), dim3(kThreads), 0, s, orow, ocol, ocol16, bot, botp, cuts, p, rT, k0,
+                     n, dslot, dbits, nwords, cap);
+  return hipGetLastError();
+}
+
 hipError_t launch_set_at(uint32_t* arr, const uint32_t* idx, uint32_t value, hipStream_t s) {
   hipLaunchKernelGGL(k_set_at, dim3(1), dim3(64), 0, s, arr, idx, value);
   return hipGetLastError();

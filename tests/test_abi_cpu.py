@@ -32,6 +32,7 @@ def test_struct_sizes_match_header_layout():
     assert ctypes.sizeof(bb.bbtc_csr) == 40
     assert ctypes.sizeof(bb.bbtc_options) == 48
     assert bb.bbtc_options.device_budget_bytes.offset == 32 and bb.bbtc_options.bound_min_deg.offset == 40
+    assert bb.bbtc_options.dense.offset == 44
     assert ctypes.sizeof(bb.bbtc_task) == 24
 
 
@@ -63,7 +64,8 @@ def test_every_struct_matches_the_c_layout(tmp_path):
 
 def test_options_default():
     o = bb.bbtc_options_default()
-    assert (o.p, o.mode, o.cut_mode, o.wave_min, o.hash_min, o.device_budget_bytes) == (0, 0, 0, 0, 0, 0)
+    assert (o.p, o.mode, o.cut_mode, o.wave_min, o.hash_min, o.device_budget_bytes, o.bound_min_deg,
+            o.dense) == (0,) * 8
 
 
 def _expect_einval(n, rowptr, colidx, **opts):
@@ -93,6 +95,7 @@ def test_option_and_size_checks():
     assert "cut_mode" in _expect_einval(3, rp, ci, cut_mode=7)
     assert "mode" in _expect_einval(3, rp, ci, mode=9)
     assert "negative" in _expect_einval(3, rp, ci, wave_min=-3)
+    assert "dense" in _expect_einval(3, rp, ci, dense=1)
     assert "n must" in _expect_einval(0, [0], [])
     assert "even" in _expect_einval(2, [0, 1, 1], [1])
 

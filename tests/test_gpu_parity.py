@@ -433,3 +433,30 @@ def test_hybrid_cpu_gpu_per_task(name, p):
         per, tot, st = bb.bbtc_count_hybrid(plan)
         assert st["cutoff"] == nt // 2 and int(tot.item()) == tot0
         plan.destroy()
+
+
+@pytest.mark.parametrize("name,p", [("rmat14_ef8", 8), ("rmat12", 16), ("er2000", 4), ("K200", 2)])
+def test_dense_slices_are_exact(name, p):
+    """Slices N(G_ik,u) of the last parts with at least |V_k|/16 entries are
+    also held as bitmaps over V_k and probed word by word against a column's
+    staged bitmap.  Per-task counts equal the oracle's and those of the same
+    plan built without bitmaps (dense=-1); the verifier checks every bitmap
+    against its slice and that exactly the dense slices have one."""
+    from math import comb
+    if name == "K200":
+        g = small_graph(200, [(x, y) for x in range(200) for y in range(x + 1, 200)], "K200")
+    else:
+        g = graphgen.workload(name)
+    plan0, per0, tot0 = run(g, p=p, dense=-1)
+    assert plan0.stats()["dense_slices"] == 0
+    for mode in MODES.values():
+        plan, per, tot = run(g, p=p, mode=mode)
+        st = plan.stats()
+        check(g, plan, per, tot, deep=False)
+        assert tot == tot0 and np.array_equal(per, per0)
+        if name in ("rmat12", "K200"):
+            assert st["dense_slices"] > 0 and st["dense_bytes"] > 0, st
+        if name == "K200":
+            assert tot == comb(200, 3)
+        plan.destroy()
+    plan0.destroy()
