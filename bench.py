@@ -246,14 +246,19 @@ def measure_hybrid(bb, plan, per, tot, stream, count_ms, triangles, sync):
         out["cutoffs"][label] = {"cutoff": cut, "ms": med["total_ms"], "cpu_tasks": med["cpu_tasks"],
                                  "gpu_tasks": med["gpu_tasks"], "gpu_launches": med["gpu_launches"],
                                  "cpu_busy_ms": med["cpu_ms"], "cpu_triangles": med["cpu_triangles"]}
+        note(f"hybrid cut-off {label}: {med['total_ms']:.1f} ms")
     sync()
     return out
 
 
-def measure(args, name, g, opt, tuned, plain_modes, stream):
+def measure(args, name, g, opt, tuned, plain_modes, stream, hybrid=True):
     """Steps (partition + batched count) on a device-resident CSR, the count
-    alone, the partition alone, the step from pinned host memory, and the
-    plain per-task-launch counts.  Returns (record, plan, triangles)."""
+    alone, the partition alone, the step from pinned host memory, the hybrid
+    CPU+GPU counts (unless hybrid is False) and the plain per-task-launch
+    counts.  The plain forms run at p >= 16 (below that one task is a
+    sixteenth of the graph or more and a launch per task leaves most of the
+    chip idle for seconds); when that differs from the batched p, a batched
+    count at the same p gives their ratio.  Returns (record, plan, triangles)."""
     import numpy as np
     import torch
 
@@ -308,12 +313,22 @@ def measure(args, name, g, opt, tuned, plain_modes, stream):
                             "what": "H2D of the symmetric CSR from pinned host memory + partition + batched count"}
     rec["bytes_total"] = int(st["bytes_total"])
     note(f"{name}: steps, count, partition and host-input step timed")
-    if not args.no_hybrid:
+    if hybrid and not args.no_hybrid:
         rec["hybrid"] = measure_hybrid(bb, plan, per, tot, stream, count_ms, triangles, sync)
         note(f"{name}: hybrid counts timed")
     plain = {}
+    plain_p = max(int(st["p"]), 16)
+    base_ms = count_ms
+    if plain_modes and plain_p != int(st["p"]):
+        o2 = bb.bbtc_options_default(p=plain_p)
+        pl2 = bb.bbtc_partition(n, rp, ci, options=o2, trusted=True, stream=stream)
+        pt2, tt2 = bb.bbtc_count(pl2, stream=stream)
+        sync()
+        base_ms = float(np.median(timed(lambda: bb.bbtc_count(pl2, pt2, tt2, stream=stream), 3, sync))) * 1e3
+        pl2.destroy()
+        rec["batched_at_plain_p"] = {"p": plain_p, "count_ms": base_ms}
     for pname, mode in plain_modes:
-        o2 = bb.bbtc_options_default(p=int(st["p"]), mode=mode)
+        o2 = bb.bbtc_options_default(p=plain_p, mode=mode)
         pl2 = bb.bbtc_partition(n, rp, ci, options=o2, trusted=True, stream=stream)
         pt2, tt2 = bb.bbtc_count(pl2, stream=stream)
         sync()
@@ -321,13 +336,14 @@ def measure(args, name, g, opt, tuned, plain_modes, stream):
         if int(tt2.item()) != triangles:
             raise SystemExit(f"{name} {pname} disagrees: {int(tt2.item())} vs {triangles}")
         med = float(np.median(ts))
-        plain[pname] = {"count_ms": med * 1e3, "edges_per_s": m / med}
+        plain[pname] = {"count_ms": med * 1e3, "edges_per_s": m / med, "p": plain_p}
         pl2.destroy()
+        note(f"{name}: {pname} at p={plain_p} timed")
     rec["plain"] = plain
     if plain:
         note(f"{name}: plain counts timed")
     if plain:
-        rec["batched_vs_plain"] = {k: v["count_ms"] / count_ms for k, v in plain.items()}
+        rec["batched_vs_plain"] = {k: v["count_ms"] / base_ms for k, v in plain.items()}
     del rp, ci
     return rec, plan, triangles
 
@@ -635,7 +651,7 @@ def main():
     if name == "rmat24" and not args.no_companion:
         g2 = graphgen.workload("er24")
         o2, t2 = options_for(args, "er24", stream, g2)
-        companion, pl2, _ = measure(args, "er24", g2, o2, t2, plain_modes, stream)
+        companion, pl2, _ = measure(args, "er24", g2, o2, t2, plain_modes, stream, hybrid=False)
         note("er24 measured")
         pl2.destroy()
         del g2

@@ -1570,7 +1570,7 @@ bbtc_status partition_budgeted(const bbtc_csr* g, hipStream_t s, bbtc_plan* pl,
                                pl->hugerows.ptr, B.q.ptr, s),
             "sort in-rows");
     HIP_TRY(launch_inrows_group(pl->irow.ptr + R0, ga.ptr - i0, pl->longrows.ptr, pl->hugerows.ptr, B.q.ptr,
-                                gb.ptr - i0, pl->cuts.ptr, p, GroupChunks{0, nullptr, nullptr, nullptr}, s),
+                                gb.ptr - i0, pl->cuts.ptr, p, GroupChunks{0, nullptr, nullptr, nullptr, nullptr}, s),
             "group in-rows");
     uint32_t* ccnt = gcc.ptr;                   // [ncc] column counts, [ncc] entry counts,
     uint32_t* ecnt = gcc.ptr + (ncc + 1);       // then their scans
@@ -1833,7 +1833,7 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
           "sort out-rows");
   HIP_TRY(hipEventRecord(pl->ev_join[0], s), "event");  // the out-rows are done with the scratch
   HIP_TRY(hipStreamWaitEvent(si, pl->ev_join[0], 0), "wait");
-  GroupChunks gc{0, nullptr, nullptr, nullptr};
+  GroupChunks gc{0, nullptr, nullptr, nullptr, nullptr};
   {  // the first rows of the long/huge list are grouped in chunks over the whole chip
     gc.cap = (uint32_t)std::min<int64_t>(kGroupRowCap, (int64_t)(kGroupCounters / (uint64_t)p));
     const size_t nck = (size_t)(m / kGroupChunkEntries) + gc.cap + 1;
@@ -1842,8 +1842,8 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
     gc.chunks = (uint2*)pl->grp.ptr;
     gc.nchunks = (uint32_t*)(pl->grp.ptr + 8 * nck);
     gc.cnt = (uint32_t*)(pl->grp.ptr + o_cnt);
-    HIP_TRY(hipMemsetAsync(gc.nchunks, 0, 16, si), "memset");
-    HIP_TRY(hipMemsetAsync(gc.cnt, 0, bytes - o_cnt, si), "memset");
+    gc.rowmap = pl->od.ptr;  // free once the in-row sort has used it as a row list
+    HIP_TRY(hipMemsetAsync(gc.nchunks, 0, 16, si), "memset");  // k_gchunk_list clears the counters it uses
   }
   HIP_TRY(launch_inrows_group(pl->irow.ptr, pl->icol.ptr, pl->idg.ptr, (const uint32_t*)pl->keys_a.ptr,
                               pl->err.ptr + 5, pl->acol.ptr, pl->cuts.ptr, p, gc, si),
@@ -1939,6 +1939,13 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   bb.heavy = pl->heavy.ptr;
   bb.nheavy = pl->head;
   bb.heavy_cap = (uint32_t)hcap;
+  // the slices of the in-rows grouped in chunks come from their part counters
+  bb.rowmap = gc.rowmap;
+  bb.gcnt = gc.cnt;
+  bb.glong = pl->idg.ptr;
+  bb.ghuge = (const uint32_t*)pl->keys_a.ptr;
+  bb.gq = pl->err.ptr + 5;
+  bb.gcap = gc.cap;
   // out side on s, in side on side[2] once the tables are there, at once
   HIP_TRY(hipEventRecord(pl->ev_fork, s), "event");
   HIP_TRY(hipStreamWaitEvent(si, pl->ev_fork, 0), "wait");

@@ -196,13 +196,14 @@ hipError_t launch_inrows_sort(const uint32_t* rp, int32_t* col, int64_t nrows, u
                               uint32_t* hugerows, uint32_t* q, hipStream_t s);
 // The first `cap` rows of the combined list (huge rows, then long ones) are
 // grouped in chunks spread over the chip: chunks holds room for m / 4096 +
-// cap entries, *nchunks and cnt (cap * p words) are zero on entry.  cap = 0:
-// every listed row by one workgroup.
+// cap entries, *nchunks is zero on entry, cnt has room for cap * p words.
+// cap = 0: every listed row by one workgroup.
 struct GroupChunks {
   uint32_t cap;
   uint2* chunks;
   uint32_t* nchunks;
   uint32_t* cnt;
+  uint32_t* rowmap;  // n words: rowmap[row] = its combined list index, for the rows taken
 };
 constexpr uint32_t kGroupChunkEntries = 4096;
 hipError_t launch_inrows_group(const uint32_t* rp, int32_t* col, const uint32_t* longrows, const uint32_t* hugerows,
@@ -259,6 +260,16 @@ struct BlockBuild {
   HeavyCol* heavy;           // room for m/split + 1 records
   uint32_t* nheavy;
   uint32_t heavy_cap;
+  // In-rows grouped in chunks (launch_inrows_group): rowmap[v] is the
+  // combined list index of row v when it was (checked against the lists,
+  // the value is stale otherwise), gcnt + index * p the ends of its part runs
+  // relative to the row start; rowmap null: none.
+  const uint32_t* rowmap;
+  const uint32_t* gcnt;
+  const uint32_t* glong;
+  const uint32_t* ghuge;
+  const uint32_t* gq;
+  uint32_t gcap;
 };
 // Chunks [bb.chunk_base, bb.chunk_base + nchunks) of the parts.
 hipError_t launch_bot(const BlockBuild& bb, int nchunks, hipStream_t s);

@@ -827,15 +827,30 @@ __global__ __launch_bounds__(kThreads) void k_segsort_mid(const uint32_t* __rest
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
   const uint32_t cnt = q[2];
-  for (int64_t i = wave; i < cnt; i += nwaves) {
+  // the row after next is looked up and the next row's bounds are loaded
+  // while this row is sorted, so that a row costs one round trip to memory
+  // instead of three
+  int64_t i = wave;
+  uint32_t s = 0, len = 0, rn = 0;
+  if (i < cnt) {
     const uint32_t r = midrows[i];
-    const uint32_t s = rp[r], len = rp[r + 1] - s;
-    if (len > kSegWave) continue;
-    if (len <= 64u) sort_row_wave<1>(col, s, len, l);
-    else if (len <= 128u) sort_row_wave<2>(col, s, len, l);
-    else if (len <= 256u) sort_row_wave<4>(col, s, len, l);
-    else if (len <= 512u) sort_row_wave<8>(col, s, len, l);
-    else sort_row_wave<16>(col, s, len, l);
+    s = rp[r];
+    len = rp[r + 1] - s;
+  }
+  if (i + nwaves < cnt) rn = midrows[i + nwaves];
+  for (; i < cnt; i += nwaves) {
+    const uint32_t cs = s, clen = len;
+    if (i + nwaves < cnt) {
+      s = rp[rn];
+      len = rp[rn + 1] - s;
+      if (i + 2 * nwaves < cnt) rn = midrows[i + 2 * nwaves];
+    }
+    if (clen > kSegWave) continue;
+    if (clen <= 64u) sort_row_wave<1>(col, cs, clen, l);
+    else if (clen <= 128u) sort_row_wave<2>(col, cs, clen, l);
+    else if (clen <= 256u) sort_row_wave<4>(col, cs, clen, l);
+    else if (clen <= 512u) sort_row_wave<8>(col, cs, clen, l);
+    else sort_row_wave<16>(col, cs, clen, l);
   }
 }
 
@@ -1116,7 +1131,9 @@ __global__ __launch_bounds__(NT) void k_group_parts(const uint32_t* __restrict__
 // thousands of entries) is cut into chunks of kGroupChunk entries spread
 // over the whole chip instead of one workgroup per row.  The first `cap`
 // rows of the combined list (huge rows, then long rows) take this path:
-//   k_gchunk_list   the chunks (row index, chunk number), one thread per row;
+//   k_gchunk_list   the chunks (row index, chunk number), one thread per row,
+//                   and clears those rows' counters and maps each row to its
+//                   list index;
 //   k_gchunk_count  per chunk, the entries of each part (LDS counts, then one
 //                   global add per part into cnt[row * p + part]);
 //   k_gchunk_scan   per row, cnt becomes the exclusive prefix over the parts
@@ -1125,6 +1142,8 @@ __global__ __launch_bounds__(NT) void k_group_parts(const uint32_t* __restrict__
 //                   one global atomic on cnt and the entries are scattered
 //                   into scratch (order within a part is free);
 //   k_gchunk_copy   the rows back from scratch.
+// Afterwards cnt[row * p + a] is the end of part a's run in the row (the
+// block-major in side reads the slices from there instead of searching).
 constexpr uint32_t kGroupChunk = kGroupChunkEntries;
 
 __device__ __forceinline__ uint32_t glist_row(const uint32_t* longrows, const uint32_t* hugerows, uint32_t nhuge,
@@ -1135,11 +1154,14 @@ __device__ __forceinline__ uint32_t glist_row(const uint32_t* longrows, const ui
 __global__ __launch_bounds__(kThreads) void k_gchunk_list(const uint32_t* __restrict__ rp,
                                                           const uint32_t* __restrict__ longrows,
                                                           const uint32_t* __restrict__ hugerows,
-                                                          const uint32_t* __restrict__ q, uint32_t cap,
-                                                          uint2* __restrict__ chunks, uint32_t* __restrict__ nchunks) {
+                                                          const uint32_t* __restrict__ q, uint32_t cap, int32_t p,
+                                                          uint2* __restrict__ chunks, uint32_t* __restrict__ nchunks,
+                                                          uint32_t* __restrict__ cnt, uint32_t* __restrict__ rowmap) {
   const uint32_t nhuge = q[1], nrows = min(q[0] + nhuge, cap);
+  for (uint64_t x = blockIdx.x * kThreads + threadIdx.x; x < (uint64_t)nrows * p; x += gridDim.x * kThreads) cnt[x] = 0;
   for (uint32_t li = blockIdx.x * kThreads + threadIdx.x; li < nrows; li += gridDim.x * kThreads) {
     const uint32_t r = glist_row(longrows, hugerows, nhuge, li);
+    rowmap[r] = li;
     const uint32_t len = rp[r + 1] - rp[r];
     const uint32_t nc = (len + kGroupChunk - 1) / kGroupChunk;
     const uint32_t at = atomicAdd(nchunks, nc);
@@ -1329,12 +1351,13 @@ constexpr uint32_t kBotLane = 32;
 // in parts [first, last) in non-decreasing part order.  pos[x - first] is the
 // first position holding a part >= x, for x in [first, last] (pos[0] = rb,
 // pos[last - first] = re).  Rows of up to kWalkRow entries are walked 64
-// entries at a time: the entry where the part changes is the boundary of
-// every part in between.  Longer rows (a hub's in-row has hundreds of
+// entries at a time (kWalkUnroll steps loaded at once): the entry where the
+// part changes is the boundary of every part in between.  Longer rows (a hub's in-row has hundreds of
 // thousands of entries) are searched instead, one part per lane: the entries
 // below c_x form a prefix of the row.  Ends with the wavefront's writes
 // visible to it.
-constexpr uint32_t kWalkRow = 1024;
+constexpr uint32_t kWalkRow = 2048;
+constexpr uint32_t kWalkUnroll = 4;  // 64-entry steps of a walk loaded at once
 
 __device__ __forceinline__ void part_bounds_wave(const int32_t* __restrict__ col, uint32_t rb, uint32_t re,
                                                  int32_t first, int32_t last, const int32_t* scut, int32_t p,
@@ -1342,13 +1365,22 @@ __device__ __forceinline__ void part_bounds_wave(const int32_t* __restrict__ col
   const int l = lane_id();
   if (re - rb <= kWalkRow) {
     int32_t carry = first;  // part of the entry before the current 64
-    for (uint32_t q = rb; q < re; q += kWave) {
-      const uint32_t e = q + (uint32_t)l;
-      const int32_t pe = e < re ? part_of(scut, p, col[e]) : last;
-      int32_t prv = __shfl_up(pe, 1, kWave);
-      if (l == 0) prv = carry;
-      for (int32_t x = prv + 1; x <= pe; ++x) pos[x - first] = e;  // e = re for the first lane past the row
-      carry = __shfl(pe, kWave - 1, kWave);
+    for (uint32_t q0 = rb; q0 < re; q0 += kWalkUnroll * kWave) {
+      int32_t val[kWalkUnroll];  // kWalkUnroll loads in flight at once
+#pragma unroll
+      for (uint32_t h = 0; h < kWalkUnroll; ++h) {
+        const uint32_t e = q0 + h * kWave + (uint32_t)l;
+        val[h] = e < re ? col[e] : 0;
+      }
+#pragma unroll
+      for (uint32_t h = 0; h < kWalkUnroll; ++h) {
+        const uint32_t e = q0 + h * kWave + (uint32_t)l;
+        const int32_t pe = e < re ? part_of(scut, p, val[h]) : last;
+        int32_t prv = __shfl_up(pe, 1, kWave);
+        if (l == 0) prv = carry;
+        for (int32_t x = prv + 1; x <= pe; ++x) pos[x - first] = e;  // e = re for the first lane past the row
+        carry = __shfl(pe, kWave - 1, kWave);
+      }
     }
     for (int32_t x = carry + 1 + l; x <= last; x += kWave) pos[x - first] = re;  // rows ending on a multiple of 64
   } else {
@@ -1368,7 +1400,7 @@ __device__ __forceinline__ void part_bounds_wave(const int32_t* __restrict__ col
 }
 
 __host__ __device__ constexpr size_t bot_lds_words(int32_t p) {
-  return 2 * (size_t)p + (size_t)(p + 1) + 4 * (size_t)(p + 2) + kThreads + 4;
+  return 2 * (size_t)p + 2 * (size_t)(p + 1) + 4 * (size_t)(p + 2) + kThreads + 4;
 }
 
 __global__ __launch_bounds__(kThreads) void k_bot(BlockBuild bb, int nchunks) {
@@ -1380,12 +1412,16 @@ __global__ __launch_bounds__(kThreads) void k_bot(BlockBuild bb, int nchunks) {
   uint32_t* s_pos = (uint32_t*)(s_cut + p + 1);   // 4 x (p + 2)
   uint32_t* s_q = s_pos + 4 * (p + 2);            // kThreads
   uint32_t* s_misc = s_q + kThreads;              // dmax, dfull, queue length
+  int32_t* s_c0 = (int32_t*)(s_misc + 4);         // p + 1: first chunk of each part
   for (int b = threadIdx.x; b < p; b += kThreads) s_nnz[b] = s_nzr[b] = 0;
-  for (int b = threadIdx.x; b <= p; b += kThreads) s_cut[b] = bb.cuts[b];
+  for (int b = threadIdx.x; b <= p; b += kThreads) {
+    s_cut[b] = bb.cuts[b];
+    s_c0[b] = bb.chunk0[b];
+  }
   if (threadIdx.x < 3) s_misc[threadIdx.x] = 0;
   __syncthreads();
   // the block counters of part `held` go out when the part changes (a
-  // workgroup's chunks come in increasing part order) and at the end: one
+  // workgroup's chunks come in decreasing part order) and at the end: one
   // global add per workgroup and block instead of one per chunk
   int held = -1;
   auto flush = [&]() {
@@ -1401,14 +1437,16 @@ __global__ __launch_bounds__(kThreads) void k_bot(BlockBuild bb, int nchunks) {
   const int w = threadIdx.x / kWave, l = lane_id();
   uint32_t* pos = s_pos + w * (p + 2);  // pos[b - a]: boundary of block b, b = a..p
   for (int ci = blockIdx.x; ci < nchunks; ci += gridDim.x) {
-    const int chunk = ci + bb.chunk_base;
-    const int a = chunk_part(bb.chunk0, p, chunk);
+    // last chunk first: the last parts hold the hubs, whose long rows take
+    // longest, so they start at once instead of trailing the launch
+    const int chunk = nchunks - 1 - ci + bb.chunk_base;
+    const int a = chunk_part(s_c0, p, chunk);
     if (a != held) {
       if (held >= 0) flush();
       held = a;
       __syncthreads();
     }
-    const int lc = chunk - bb.chunk0[a];
+    const int lc = chunk - s_c0[a];
     const int64_t ca = s_cut[a];
     const int64_t sa = ca > bb.rT ? ca : (int64_t)bb.rT;  // first stored row of part a
     // column-major per part: entry b-a of row u at column (b-a), row u - sa
@@ -1489,6 +1527,17 @@ __global__ __launch_bounds__(kThreads) void k_bot(BlockBuild bb, int nchunks) {
 }
 
 // ------------------------------------------------------------ in side
+// The ends of the part runs of in-row v (relative to its start) when the
+// chunked grouping took the row, else null.
+__device__ __forceinline__ const uint32_t* grouped_ends(const BlockBuild& bb, int64_t v) {
+  if (bb.rowmap == nullptr) return nullptr;
+  const uint32_t li = bb.rowmap[v];
+  const uint32_t nhuge = bb.gq[1], nrows = min(bb.gq[0] + nhuge, bb.gcap);
+  if (li >= nrows) return nullptr;
+  const uint32_t r = li < nhuge ? bb.ghuge[li] : bb.glong[li - nhuge];
+  return r == (uint32_t)v ? bb.gcnt + (uint64_t)li * (uint32_t)bb.p : nullptr;
+}
+
 // The in-side of the count is block-major: for block (a,b), in column-major
 // block order, its active columns (v in V_b with an in-neighbour in V_a,
 // ascending) in acol, and for active column x the in-slice of v from V_a at
@@ -1513,7 +1562,7 @@ __device__ __forceinline__ uint32_t in_slice_end(const BlockBuild& bb, uint32_t 
 // entry and total counters, the cut vector, a boundary row per wavefront, the
 // queue.
 __host__ __device__ constexpr size_t acount_lds_words(int32_t p) {
-  return 3 * (size_t)p + (size_t)(p + 1) + 4 * (size_t)(p + 2) + kThreads + 4;
+  return 3 * (size_t)p + 2 * (size_t)(p + 1) + 4 * (size_t)(p + 2) + kThreads + 4;
 }
 
 __global__ __launch_bounds__(kThreads) void k_acount(BlockBuild bb, int nchunks) {
@@ -1526,8 +1575,12 @@ __global__ __launch_bounds__(kThreads) void k_acount(BlockBuild bb, int nchunks)
   uint32_t* s_pos = (uint32_t*)(s_cut + p + 1);   // 4 x (p + 2)
   uint32_t* s_q = s_pos + 4 * (p + 2);            // kThreads
   uint32_t* s_misc = s_q + kThreads;              // queue length
+  int32_t* s_c0 = (int32_t*)(s_misc + 4);         // p + 1: first chunk of each part
   for (int a = threadIdx.x; a < p; a += kThreads) s_nzc[a] = s_ent[a] = s_tot[a] = 0;
-  for (int a = threadIdx.x; a <= p; a += kThreads) s_cut[a] = bb.cuts[a];
+  for (int a = threadIdx.x; a <= p; a += kThreads) {
+    s_cut[a] = bb.cuts[a];
+    s_c0[a] = bb.chunk0[a];
+  }
   if (threadIdx.x == 0) s_misc[0] = 0;
   __syncthreads();
   int held = -1;
@@ -1541,15 +1594,17 @@ __global__ __launch_bounds__(kThreads) void k_acount(BlockBuild bb, int nchunks)
   const int w = threadIdx.x / kWave, l = lane_id();
   uint32_t* pos = s_pos + w * (p + 2);
   for (int ci = blockIdx.x; ci < nchunks; ci += gridDim.x) {
-    const int chunk = ci + bb.chunk_base;
-    const int b = chunk_part(bb.chunk0, p, chunk);
+    // last chunk first: the last parts hold the hubs, whose long rows take
+    // longest, so they start at once instead of trailing the launch
+    const int chunk = nchunks - 1 - ci + bb.chunk_base;
+    const int b = chunk_part(s_c0, p, chunk);
     if (b != held) {
       if (held >= 0) flush();
       held = b;
       __syncthreads();
     }
-    const int lc = chunk - bb.chunk0[b];
-    const int nch = bb.chunk0[b + 1] - bb.chunk0[b];
+    const int lc = chunk - s_c0[b];
+    const int nch = s_c0[b + 1] - s_c0[b];
     const int na = b + 1;  // blocks (0,b)..(b,b)
     const int64_t cb = s_cut[b];
     const int64_t v = cb + (int64_t)lc * kPrepRows + threadIdx.x;
@@ -1584,7 +1639,15 @@ __global__ __launch_bounds__(kThreads) void k_acount(BlockBuild bb, int nchunks)
     const uint32_t nq = s_misc[0];
     for (uint32_t h = w; h < nq; h += kThreads / kWave) {
       const int64_t x = cb + (int64_t)lc * kPrepRows + s_q[h];
-      part_bounds_wave(bb.icol, bb.irow[x], bb.irow[x + 1], 0, na, s_cut, p, pos);  // in-neighbours in parts 0..b
+      const uint32_t xb = bb.irow[x], xe = bb.irow[x + 1];
+      const uint32_t* ends = xe - xb > kSegWave ? grouped_ends(bb, x) : nullptr;
+      if (ends != nullptr) {  // a row grouped in chunks: its runs are known
+        for (int32_t a = l; a < na; a += kWave) pos[a + 1] = xb + ends[a];
+        if (l == 0) pos[0] = xb;
+        wave_sync();
+      } else {
+        part_bounds_wave(bb.icol, xb, xe, 0, na, s_cut, p, pos);  // in-neighbours in parts 0..b
+      }
       for (int32_t a = l; a < na; a += kWave) {
         const uint32_t len = pos[a + 1] - pos[a];
         if (len) {
@@ -1625,8 +1688,10 @@ __global__ __launch_bounds__(kThreads) void k_acol(BlockBuild bb) {
   const bool valid = v < bb.cuts[b + 1];
   const uint32_t re = valid ? bb.irow[v + 1] : 0u;
   uint32_t lo = valid ? bb.irow[v] : 0u;
+  const uint32_t rb = lo;
+  const uint32_t* ends = valid && re - lo > kSegWave ? grouped_ends(bb, v) : nullptr;
   for (int a = 0; a < na; ++a) {
-    const uint32_t hi = (valid && lo < re) ? in_slice_end(bb, lo, re, a, na) : lo;
+    const uint32_t hi = !(valid && lo < re) ? lo : ends != nullptr ? rb + ends[a] : in_slice_end(bb, lo, re, a, na);
     const uint32_t f = hi > lo ? 1u : 0u, len = hi - lo;
     uint32_t tot;
     const uint32_t off = block256_excl_scan<uint32_t>(f, lds, &tot);
@@ -1911,8 +1976,8 @@ hipError_t launch_inrows_group(const uint32_t* rp, int32_t* col, const uint32_t*
                                const GroupChunks& gc, hipStream_t s) {
   if (gc.cap > 0) {
     const size_t lds = sizeof(uint32_t) * (2 * (size_t)p + 1);
-    hipLaunchKernelGGL(k_gchunk_list, dim3(64), dim3(kThreads), 0, s, rp, longrows, hugerows, q, gc.cap, gc.chunks,
-                       gc.nchunks);
+    hipLaunchKernelGGL(k_gchunk_list, dim3(256), dim3(kThreads), 0, s, rp, longrows, hugerows, q, gc.cap, p,
+                       gc.chunks, gc.nchunks, gc.cnt, gc.rowmap);
     hipLaunchKernelGGL(k_gchunk_count, dim3(2048), dim3(kThreads), lds, s, rp, (const int32_t*)col, longrows, hugerows, q,
                        (const uint2*)gc.chunks, (const uint32_t*)gc.nchunks, cuts, p, gc.cnt);
     hipLaunchKernelGGL(k_gchunk_scan, dim3(256), dim3(kThreads), 0, s, q, gc.cap, p, gc.cnt);
@@ -1974,11 +2039,12 @@ hipError_t launch_ocol16(const int32_t* ocol, uint64_t m, const int32_t* cuts, i
   return hipGetLastError();
 }
 
-// Dense slices as bitmaps: one wavefront per (row u, block k) pair, u in
-// [c_k0, n), k in [k0, p).  The slice N(G_ik,u) comes from the stored
-// boundaries (or two searches of a row without them); a slice of at least
-// |V_k|/16 entries (where a bitmap of V_k is no larger than the 16-bit list)
-// is set bit by bit in the wavefront's LDS words and written out whole.
+// Dense slices as bitmaps over the (row u, block k) pairs, u in [c_k0, n),
+// k in [k0, p), 64 pairs per wavefront, a lane each: the slice N(G_ik,u)
+// comes from the stored boundaries (or two searches of a row without them).
+// A slice of at least |V_k|/16 entries (where a bitmap of V_k is no larger
+// than the 16-bit list) is then built by the whole wavefront, bit by bit in
+// its LDS words, and written out whole.
 __global__ __launch_bounds__(kThreads) void k_dense_build(const uint32_t* __restrict__ orow,
                                                           const int32_t* __restrict__ ocol,
                                                           const uint16_t* __restrict__ ocol16,
@@ -1998,56 +2064,61 @@ __global__ __launch_bounds__(kThreads) void k_dense_build(const uint32_t* __rest
   const int64_t npairs = (n - u0) * nk;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
-  for (int64_t x = wave; x < npairs; x += nwaves) {  // uniform per wavefront
-    const int64_t u = u0 + x / nk;
-    const int32_t k = k0 + (int32_t)(x % nk);
-    const int32_t a = part_of(scut, p, (int32_t)u);
-    uint32_t a0 = 0, a1 = 0;
-    if (k >= a) {
-      if (u >= rT) {
-        const int64_t sa = scut[a] > rT ? scut[a] : rT;
-        const uint64_t ns = (uint64_t)(scut[a + 1] - sa);
-        const uint32_t* col0 = bot + botp[a] + (uint64_t)(k - a) * ns + (uint64_t)(u - sa);
-        a0 = col0[0];
-        a1 = col0[ns];
-      } else {
-        const uint32_t re = orow[u + 1];
-        uint32_t lo = orow[u], hi = re;
-        while (lo < hi) {
-          const uint32_t mid = (lo + hi) >> 1;
-          if (ocol[mid] < scut[k]) lo = mid + 1; else hi = mid;
+  for (int64_t x0 = wave * kWave; x0 < npairs; x0 += nwaves * kWave) {  // uniform per wavefront
+    const int64_t x = x0 + l;
+    uint32_t a0 = 0, a1 = 0, vk = 0;
+    if (x < npairs) {
+      const int64_t u = u0 + x / nk;
+      const int32_t k = k0 + (int32_t)(x % nk);
+      const int32_t a = part_of(scut, p, (int32_t)u);
+      vk = (uint32_t)(scut[k + 1] - scut[k]);
+      if (k >= a) {
+        if (u >= rT) {
+          const int64_t sa = scut[a] > rT ? scut[a] : rT;
+          const uint64_t ns = (uint64_t)(scut[a + 1] - sa);
+          const uint32_t* col0 = bot + botp[a] + (uint64_t)(k - a) * ns + (uint64_t)(u - sa);
+          a0 = col0[0];
+          a1 = col0[ns];
+        } else {
+          const uint32_t re = orow[u + 1];
+          uint32_t lo = orow[u], hi = re;
+          while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (ocol[mid] < scut[k]) lo = mid + 1; else hi = mid;
+          }
+          a0 = lo;
+          hi = re;
+          while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (ocol[mid] < scut[k + 1]) lo = mid + 1; else hi = mid;
+          }
+          a1 = lo;
         }
-        a0 = lo;
-        hi = re;
-        while (lo < hi) {
-          const uint32_t mid = (lo + hi) >> 1;
-          if (ocol[mid] < scut[k + 1]) lo = mid + 1; else hi = mid;
-        }
-        a1 = lo;
       }
     }
-    const uint32_t vk = (uint32_t)(scut[k + 1] - scut[k]);
+    const bool dense = a1 > a0 && vk <= (uint32_t)kDenseRows && 16ull * (a1 - a0) >= vk;
     uint32_t slot = 0;
-    if (a1 > a0 && vk <= (uint32_t)kDenseRows && 16ull * (a1 - a0) >= vk) {
-      const uint32_t words = ((vk + 31) / 32 + 7) & ~7u;
+    for (uint64_t mask = ballot(dense); mask != 0; mask &= mask - 1) {  // the dense pairs in turn
+      const int src = __ffsll((long long)mask) - 1;
+      const uint32_t s0 = __shfl(a0, src, kWave), s1 = __shfl(a1, src, kWave), sv = __shfl(vk, src, kWave);
+      const uint32_t words = ((sv + 31) / 32 + 7) & ~7u;
       uint32_t off = 0;
       if (l == 0) off = atomicAdd(nwords, words);
       off = __shfl(off, 0, kWave);
-      if ((uint64_t)off + words <= cap) {
-        for (uint32_t t = l; t < words; t += kWave) b[t] = 0;
-        wave_sync();
-        for (uint32_t e = a0 + l; e < a1; e += kWave) {
-          const uint32_t v = ocol16[e];
-          atomicOr(&b[v >> 5], 1u << (v & 31));
-        }
-        wave_sync();
-        for (uint32_t t = l; t < words; t += kWave) dbits[off + t] = b[t];
-        wave_sync();
-        slot = off + 1;
-        if (l == 0) atomicAdd(nwords + 1, 1u);
+      if ((uint64_t)off + words > cap) continue;  // the bound holds; never taken
+      for (uint32_t t = l; t < words; t += kWave) b[t] = 0;
+      wave_sync();
+      for (uint32_t e = s0 + l; e < s1; e += kWave) {
+        const uint32_t v = ocol16[e];
+        atomicOr(&b[v >> 5], 1u << (v & 31));
       }
+      wave_sync();
+      for (uint32_t t = l; t < words; t += kWave) dbits[off + t] = b[t];
+      wave_sync();
+      if (l == src) slot = off + 1;
+      if (l == 0) atomicAdd(nwords + 1, 1u);
     }
-    if (l == 0) dslot[x] = slot;
+    if (x < npairs) dslot[x] = slot;
   }
 }
 
