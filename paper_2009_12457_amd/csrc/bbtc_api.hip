@@ -985,7 +985,8 @@ bbtc_status build_dense(bbtc_plan* pl, bool budgeted, hipStream_t s) {
   HIP_TRY(pl->dcount.ensure(4), "alloc");
   HIP_TRY(hipMemsetAsync(pl->dcount.ptr, 0, 16, s), "memset");
   HIP_TRY(launch_dense_build(pl->orow.ptr, pl->ocol.ptr, pl->ocol16.ptr, pl->bot.ptr, pl->botp, pl->cuts.ptr, p,
-                             (int32_t)pl->rT, k0, pl->n, pl->dslot.ptr, pl->dbits.ptr, pl->dcount.ptr, cap, s),
+                             (int32_t)pl->rT, k0, pl->n, rows * nk, pl->dslot.ptr, pl->dbits.ptr, pl->dcount.ptr, cap,
+                             s),
           "dense slices");
   pl->dense_k0 = k0;
   return BBTC_OK;
@@ -1570,7 +1571,8 @@ bbtc_status partition_budgeted(const bbtc_csr* g, hipStream_t s, bbtc_plan* pl,
                                pl->hugerows.ptr, B.q.ptr, s),
             "sort in-rows");
     HIP_TRY(launch_inrows_group(pl->irow.ptr + R0, ga.ptr - i0, pl->longrows.ptr, pl->hugerows.ptr, B.q.ptr,
-                                gb.ptr - i0, pl->cuts.ptr, p, GroupChunks{0, nullptr, nullptr, nullptr, nullptr}, s),
+                                gb.ptr - i0, pl->cuts.ptr, p, GroupChunks{0, nullptr, nullptr, nullptr, nullptr, 0, false},
+                                s),
             "group in-rows");
     uint32_t* ccnt = gcc.ptr;                   // [ncc] column counts, [ncc] entry counts,
     uint32_t* ecnt = gcc.ptr + (ncc + 1);       // then their scans
@@ -1833,10 +1835,14 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
           "sort out-rows");
   HIP_TRY(hipEventRecord(pl->ev_join[0], s), "event");  // the out-rows are done with the scratch
   HIP_TRY(hipStreamWaitEvent(si, pl->ev_join[0], 0), "wait");
-  GroupChunks gc{0, nullptr, nullptr, nullptr, nullptr};
+  GroupChunks gc{0, nullptr, nullptr, nullptr, nullptr, 0, false};
   {  // the first rows of the long/huge list are grouped in chunks over the whole chip
     gc.cap = (uint32_t)std::min<int64_t>(kGroupRowCap, (int64_t)(kGroupCounters / (uint64_t)p));
-    const size_t nck = (size_t)(m / kGroupChunkEntries) + gc.cap + 1;
+    // a listed row has more than 1024 entries: at most m / 1024 of them
+    const uint64_t maxrows = (uint64_t)m / 1024;
+    gc.all_taken = maxrows <= gc.cap;
+    const size_t nck = (size_t)(m / kGroupChunkEntries) + std::min<uint64_t>(gc.cap, maxrows) + 1;
+    gc.max_chunks = (uint32_t)std::min<size_t>(nck, 0xFFFFFFFFu);
     const size_t o_cnt = align16(8 * nck + 16), bytes = o_cnt + 4 * (size_t)gc.cap * (size_t)p;
     HIP_TRY(pl->grp.ensure(bytes), "alloc in-row chunks");
     gc.chunks = (uint2*)pl->grp.ptr;

@@ -204,6 +204,8 @@ struct GroupChunks {
   uint32_t* nchunks;
   uint32_t* cnt;
   uint32_t* rowmap;  // n words: rowmap[row] = its combined list index, for the rows taken
+  uint32_t max_chunks;  // bound on the chunks (sizes the launches)
+  bool all_taken;       // cap holds every row the lists can have (the per-row kernels are skipped)
 };
 constexpr uint32_t kGroupChunkEntries = 4096;
 hipError_t launch_inrows_group(const uint32_t* rp, int32_t* col, const uint32_t* longrows, const uint32_t* hugerows,
@@ -225,7 +227,8 @@ hipError_t launch_cuts(const uint32_t* orow, int64_t n, int32_t p, int mode, int
 // handed out from nwords[0] up to cap, nwords[1] counts the dense slices.
 hipError_t launch_dense_build(const uint32_t* orow, const int32_t* ocol, const uint16_t* ocol16, const uint32_t* bot,
                               const uint64_t* botp, const int32_t* cuts, int32_t p, int32_t rT, int32_t k0, int64_t n,
-                              uint32_t* dslot, uint32_t* dbits, uint32_t* nwords, uint64_t cap, hipStream_t s);
+                              int64_t npairs, uint32_t* dslot, uint32_t* dbits, uint32_t* nwords, uint64_t cap,
+                              hipStream_t s);
 hipError_t launch_ocol16(const int32_t* ocol, uint64_t m, const int32_t* cuts, int32_t p, uint16_t* ocol16,
                          hipStream_t s);
 

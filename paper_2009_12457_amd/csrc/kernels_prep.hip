@@ -1976,16 +1976,19 @@ hipError_t launch_inrows_group(const uint32_t* rp, int32_t* col, const uint32_t*
                                const GroupChunks& gc, hipStream_t s) {
   if (gc.cap > 0) {
     const size_t lds = sizeof(uint32_t) * (2 * (size_t)p + 1);
-    hipLaunchKernelGGL(k_gchunk_list, dim3(256), dim3(kThreads), 0, s, rp, longrows, hugerows, q, gc.cap, p,
+    const unsigned g = gc.max_chunks < 2048u ? (gc.max_chunks > 0 ? gc.max_chunks : 1u) : 2048u;
+    const unsigned gl = gc.cap / kThreads + 1 < 256u ? gc.cap / kThreads + 1 : 256u;
+    hipLaunchKernelGGL(k_gchunk_list, dim3(gl), dim3(kThreads), 0, s, rp, longrows, hugerows, q, gc.cap, p,
                        gc.chunks, gc.nchunks, gc.cnt, gc.rowmap);
-    hipLaunchKernelGGL(k_gchunk_count, dim3(2048), dim3(kThreads), lds, s, rp, (const int32_t*)col, longrows, hugerows, q,
+    hipLaunchKernelGGL(k_gchunk_count, dim3(g), dim3(kThreads), lds, s, rp, (const int32_t*)col, longrows, hugerows, q,
                        (const uint2*)gc.chunks, (const uint32_t*)gc.nchunks, cuts, p, gc.cnt);
-    hipLaunchKernelGGL(k_gchunk_scan, dim3(256), dim3(kThreads), 0, s, q, gc.cap, p, gc.cnt);
+    hipLaunchKernelGGL(k_gchunk_scan, dim3(gl), dim3(kThreads), 0, s, q, gc.cap, p, gc.cnt);
     const size_t lds_s = sizeof(uint32_t) * (4 * (size_t)p + 1 + kGroupChunk);
-    hipLaunchKernelGGL(k_gchunk_scatter, dim3(2048), dim3(kThreads), lds_s, s, rp, (const int32_t*)col, longrows,
+    hipLaunchKernelGGL(k_gchunk_scatter, dim3(g), dim3(kThreads), lds_s, s, rp, (const int32_t*)col, longrows,
                        hugerows, q, (const uint2*)gc.chunks, (const uint32_t*)gc.nchunks, cuts, p, gc.cnt, scratch);
-    hipLaunchKernelGGL(k_gchunk_copy, dim3(2048), dim3(kThreads), 0, s, rp, col, longrows, hugerows, q,
+    hipLaunchKernelGGL(k_gchunk_copy, dim3(g), dim3(kThreads), 0, s, rp, col, longrows, hugerows, q,
                        (const uint2*)gc.chunks, (const uint32_t*)gc.nchunks, (const int32_t*)scratch);
+    if (gc.all_taken) return hipGetLastError();
   }
   hipLaunchKernelGGL(k_group_parts<kThreads>, dim3(1024), dim3(kThreads), 0, s, rp, col, scratch, longrows, q, cuts, p,
                      q + 1, gc.cap);
@@ -2124,9 +2127,11 @@ __global__ __launch_bounds__(kThreads) void k_dense_build(const uint32_t* __rest
 
 hipError_t launch_dense_build(const uint32_t* orow, const int32_t* ocol, const uint16_t* ocol16, const uint32_t* bot,
                               const uint64_t* botp, const int32_t* cuts, int32_t p, int32_t rT, int32_t k0, int64_t n,
-                              uint32_t* dslot, uint32_t* dbits, uint32_t* nwords, uint64_t cap, hipStream_t s) {
-  if (k0 >= p) return hipSuccess;
-  hipLaunchKernelGGL(k_dense_build, dim3(1024), dim3(kThreads), 0, s, orow, ocol, ocol16, bot, botp, cuts, p, rT, k0,
+                              int64_t npairs, uint32_t* dslot, uint32_t* dbits, uint32_t* nwords, uint64_t cap,
+                              hipStream_t s) {
+  if (k0 >= p || npairs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dense_build, dim3((unsigned)std::min<int64_t>(1024, npairs / kThreads + 1)), dim3(kThreads), 0,
+                     s, orow, ocol, ocol16, bot, botp, cuts, p, rT, k0,
                      n, dslot, dbits, nwords, cap);
   return hipGetLastError();
 }
