@@ -124,8 +124,9 @@ typedef struct bbtc_csr {
  *                 32 for plans partitioned in pieces within a device budget,
  *                 whose boundaries stream with the out-rows); -1 = store
  *                 every row.
- *   dense         0: plans held on the device keep the dense slices of their
- *                 last parts as bitmaps too (see bbtc_partition); -1: none.
+ *   dense         plans held on the device keep the dense slices of their
+ *                 last parts as bitmaps too (see bbtc_partition): 0 = for
+ *                 graphs of at least 2^22 edges, 1 = always, -1 = never.
  */
 typedef struct bbtc_options {
   int32_t p;
@@ -194,8 +195,9 @@ void bbtc_options_default(bbtc_options* opt);
  * If *plan is NULL a new plan is created, otherwise it is rebuilt in place,
  * reusing its device buffers when they are large enough.  Returns when the
  * plan is ready (the call synchronises `stream`).  On failure *plan is left
- * as it was (a new plan is not created).  A plan held on the device also
- * keeps, for the rows of its last parts (at most 65536 vertices) and the
+ * as it was (a new plan is not created).  A plan held on the device of a
+ * graph of at least 2^22 edges (bbtc_options.dense) also keeps, for the
+ * rows of its last parts (at most 65536 vertices) and the
  * blocks of those parts, every slice N(G_ik,u) with at least |V_k|/16
  * entries as a bitmap over V_k as well (no larger than the 16-bit list);
  * the count probes such a slice word by word against a column's staged

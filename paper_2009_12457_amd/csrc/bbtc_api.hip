@@ -49,6 +49,11 @@ bbtc_status hip_fail(hipError_t e, const char* what) {
   } while (0)
 
 template <typename T>
+struct DevBuf;
+template <typename T>
+hipError_t ensure_pow2(DevBuf<T>& b, size_t n);
+
+template <typename T>
 struct DevBuf {
   T* ptr = nullptr;
   size_t cap = 0;  // elements
@@ -72,6 +77,17 @@ struct DevBuf {
   }
   size_t bytes() const { return cap * sizeof(T); }
 };
+
+// ensure() rounded up to a power of two: for the buffers whose size follows
+// each graph (a plan rebuilt for graphs of many sizes, as in serving, then
+// rarely reallocates, and hipFree waits for the whole device)
+template <typename T>
+hipError_t ensure_pow2(DevBuf<T>& b, size_t n) {
+  if (b.ptr && n <= b.cap) return hipSuccess;
+  size_t r = 1;
+  while (r < n) r <<= 1;
+  return b.ensure(r);
+}
 
 int bits_for(uint64_t maxval) {  // bits to hold values 0..maxval
   int b = 1;
@@ -358,6 +374,10 @@ constexpr double kTuneMargin = 0.97;        // the autotuner's thresholds change
 constexpr uint32_t kHubChunk = 1024;  // in-neighbours per hub work item
 constexpr int kItemsPerBlock = 20;    // work items per resident workgroup (by estimated work)
 constexpr int64_t kGroupRowCap = 1 << 17;      // long/huge in-rows grouped in chunks, at most
+// Below this many edges a graph's hubs are small enough for one workgroup
+// per row, and the chunked grouping and the dense bitmaps cost more (fixed
+// launches, in many concurrent partitions when serving) than they save.
+constexpr uint64_t kLargeGraphEdges = 1ull << 22;
 constexpr uint64_t kGroupCounters = 1u << 22;  // their per-part counters, at most (words)
 
 // The plain HMap mode is the paper's per-task HMap throughout: every live
@@ -972,6 +992,7 @@ bbtc_status build_dense(bbtc_plan* pl, bool budgeted, hipStream_t s) {
   const int32_t p = pl->p;
   pl->dense_k0 = p;
   if (budgeted || pl->ocol16.ptr == nullptr || pl->opt.dense == -1) return BBTC_OK;
+  if (pl->opt.dense == 0 && (uint64_t)pl->m < kLargeGraphEdges) return BBTC_OK;
   int32_t k0 = p;
   while (k0 > 0 && (int64_t)pl->h_cuts[p] - pl->h_cuts[k0 - 1] <= kDenseRows) --k0;
   if (k0 >= p) return BBTC_OK;
@@ -980,8 +1001,8 @@ bbtc_status build_dense(bbtc_plan* pl, bool budgeted, hipStream_t s) {
   for (int32_t a = k0; a < p; ++a)
     for (int32_t k = a; k < p; ++k) ent += (uint64_t)pl->h_nnz[block_id(p, a, k)];
   const uint64_t cap = ent / 2 + 8 * (uint64_t)std::min<int64_t>(rows * nk, (int64_t)ent) + 8;
-  HIP_TRY(pl->dslot.ensure((size_t)(rows * nk)), "alloc dense slots");
-  HIP_TRY(pl->dbits.ensure((size_t)cap), "alloc dense bitmaps");
+  HIP_TRY(ensure_pow2(pl->dslot, (size_t)(rows * nk)), "alloc dense slots");
+  HIP_TRY(ensure_pow2(pl->dbits, (size_t)cap), "alloc dense bitmaps");
   HIP_TRY(pl->dcount.ensure(4), "alloc");
   HIP_TRY(hipMemsetAsync(pl->dcount.ptr, 0, 16, s), "memset");
   HIP_TRY(launch_dense_build(pl->orow.ptr, pl->ocol.ptr, pl->ocol16.ptr, pl->bot.ptr, pl->botp, pl->cuts.ptr, p,
@@ -1655,7 +1676,7 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
       opt.bound_min_deg < -1)
     return fail(BBTC_EINVAL, "negative option");
   if (opt.graph != 0 && opt.graph != -1) return fail(BBTC_EINVAL, "graph must be 0 or -1");
-  if (opt.dense != 0 && opt.dense != -1) return fail(BBTC_EINVAL, "dense must be 0 or -1");
+  if (opt.dense < -1 || opt.dense > 1) return fail(BBTC_EINVAL, "dense must be -1, 0 or 1");
   const bool on_device = (g->flags & BBTC_CSR_DEVICE) != 0;
   const bool symmetric_check = (g->flags & BBTC_CSR_TRUSTED) == 0;
   const int rp64 = g->rowptr_bits == 64;
@@ -1836,7 +1857,7 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   HIP_TRY(hipEventRecord(pl->ev_join[0], s), "event");  // the out-rows are done with the scratch
   HIP_TRY(hipStreamWaitEvent(si, pl->ev_join[0], 0), "wait");
   GroupChunks gc{0, nullptr, nullptr, nullptr, nullptr, 0, false};
-  {  // the first rows of the long/huge list are grouped in chunks over the whole chip
+  if ((uint64_t)m >= kLargeGraphEdges) {  // the first rows of the long/huge list are grouped in chunks over the whole chip
     gc.cap = (uint32_t)std::min<int64_t>(kGroupRowCap, (int64_t)(kGroupCounters / (uint64_t)p));
     // a listed row has more than 1024 entries: at most m / 1024 of them
     const uint64_t maxrows = (uint64_t)m / 1024;
@@ -1844,7 +1865,7 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
     const size_t nck = (size_t)(m / kGroupChunkEntries) + std::min<uint64_t>(gc.cap, maxrows) + 1;
     gc.max_chunks = (uint32_t)std::min<size_t>(nck, 0xFFFFFFFFu);
     const size_t o_cnt = align16(8 * nck + 16), bytes = o_cnt + 4 * (size_t)gc.cap * (size_t)p;
-    HIP_TRY(pl->grp.ensure(bytes), "alloc in-row chunks");
+    HIP_TRY(ensure_pow2(pl->grp, bytes), "alloc in-row chunks");
     gc.chunks = (uint2*)pl->grp.ptr;
     gc.nchunks = (uint32_t*)(pl->grp.ptr + 8 * nck);
     gc.cnt = (uint32_t*)(pl->grp.ptr + o_cnt);

@@ -95,7 +95,7 @@ def test_option_and_size_checks():
     assert "cut_mode" in _expect_einval(3, rp, ci, cut_mode=7)
     assert "mode" in _expect_einval(3, rp, ci, mode=9)
     assert "negative" in _expect_einval(3, rp, ci, wave_min=-3)
-    assert "dense" in _expect_einval(3, rp, ci, dense=1)
+    assert "dense" in _expect_einval(3, rp, ci, dense=2)
     assert "n must" in _expect_einval(0, [0], [])
     assert "even" in _expect_einval(2, [0, 1, 1], [1])
 

@@ -441,7 +441,8 @@ def test_dense_slices_are_exact(name, p):
     also held as bitmaps over V_k and probed word by word against a column's
     staged bitmap.  Per-task counts equal the oracle's and those of the same
     plan built without bitmaps (dense=-1); the verifier checks every bitmap
-    against its slice and that exactly the dense slices have one."""
+    against its slice and that exactly the dense slices have one.  These
+    graphs are below 2^22 edges, where bitmaps are kept only with dense=1."""
     from math import comb
     if name == "K200":
         g = small_graph(200, [(x, y) for x in range(200) for y in range(x + 1, 200)], "K200")
@@ -450,7 +451,7 @@ def test_dense_slices_are_exact(name, p):
     plan0, per0, tot0 = run(g, p=p, dense=-1)
     assert plan0.stats()["dense_slices"] == 0
     for mode in MODES.values():
-        plan, per, tot = run(g, p=p, mode=mode)
+        plan, per, tot = run(g, p=p, mode=mode, dense=1)  # small graphs keep bitmaps only when asked
         st = plan.stats()
         check(g, plan, per, tot, deep=False)
         assert tot == tot0 and np.array_equal(per, per0)
