@@ -1973,13 +1973,14 @@ bbtc_status partition_impl(const bbtc_csr* g, const bbtc_options* optp, hipStrea
   bb.ghuge = (const uint32_t*)pl->keys_a.ptr;
   bb.gq = pl->err.ptr + 5;
   bb.gcap = gc.cap;
-  // out side on s, in side on side[2] once the tables are there, at once
+  // block boundaries on s; the active-column counts, then the 16-bit
+  // out-rows on side[2] meanwhile
+  HIP_TRY(pl->ocol16.ensure((size_t)((m + 7) / 8 * 8 + 8)), "alloc 16-bit out-rows");
   HIP_TRY(hipEventRecord(pl->ev_fork, s), "event");
   HIP_TRY(hipStreamWaitEvent(si, pl->ev_fork, 0), "wait");
   HIP_TRY(launch_acount(bb, (int)nch, si), "active-column counts");
+  HIP_TRY(launch_ocol16(pl->ocol.ptr, m, pl->cuts.ptr, p, pl->ocol16.ptr, si), "16-bit out-rows");
   HIP_TRY(launch_bot(bb, (int)nch, s), "block row index");
-  HIP_TRY(pl->ocol16.ensure((size_t)((m + 7) / 8 * 8 + 8)), "alloc 16-bit out-rows");
-  HIP_TRY(launch_ocol16(pl->ocol.ptr, m, pl->cuts.ptr, p, pl->ocol16.ptr, s), "16-bit out-rows");
   HIP_TRY(hipEventRecord(pl->ev_join[2], si), "event");
   HIP_TRY(hipStreamWaitEvent(s, pl->ev_join[2], 0), "wait");
   HIP_TRY(scan_u32(pl->ccnt.ptr, pl->ccoff.ptr, cc, pl->partial.ptr, s), "scan column counters");

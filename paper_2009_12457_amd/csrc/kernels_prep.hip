@@ -990,8 +990,9 @@ __global__ __launch_bounds__(kThreads) void k_cuts(const uint32_t* __restrict__ 
 // ------------------------------------------------------------ 16-bit out-rows
 // Each column index relative to the first vertex of its part: for parts of
 // at most 65536 vertices the counting kernels gather these two-byte entries
-// instead of the four-byte ones.  Eight entries (one 16-byte store) per
-// thread; the part by binary search in the cut vector, staged in LDS.
+// instead of the four-byte ones.  Eight entries (two 16-byte loads, one
+// 16-byte store) per thread; the part by binary search in the cut vector,
+// staged in LDS.
 __global__ __launch_bounds__(kThreads) void k_ocol16(const int32_t* __restrict__ ocol, uint64_t m,
                                                      const int32_t* __restrict__ cuts, int32_t p,
                                                      uint16_t* __restrict__ ocol16) {
@@ -1000,12 +1001,22 @@ __global__ __launch_bounds__(kThreads) void k_ocol16(const int32_t* __restrict__
   __syncthreads();
   const uint64_t stride = (uint64_t)gridDim.x * kThreads * 8;
   for (uint64_t e0 = ((uint64_t)blockIdx.x * kThreads + threadIdx.x) * 8; e0 < m; e0 += stride) {
+    int32_t x[8];
+    if (e0 + 8 <= m) {  // e0 is a multiple of 8: the loads are 32-byte aligned
+      const int4 a0 = *reinterpret_cast<const int4*>(ocol + e0);
+      const int4 a1 = *reinterpret_cast<const int4*>(ocol + e0 + 4);
+      x[0] = a0.x; x[1] = a0.y; x[2] = a0.z; x[3] = a0.w;
+      x[4] = a1.x; x[5] = a1.y; x[6] = a1.z; x[7] = a1.w;
+    } else {
+#pragma unroll
+      for (int t = 0; t < 8; ++t) x[t] = e0 + t < m ? ocol[e0 + t] : -1;
+    }
     uint32_t h[8];
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
       h[t] = 0;
-      if (e0 + t < m) {
-        const int32_t w = ocol[e0 + t];
+      if (x[t] >= 0) {
+        const int32_t w = x[t];
         int lo = 0, hi = p;  // largest a with cuts[a] <= w
         while (hi - lo > 1) {
           const int mid = (lo + hi) >> 1;
