@@ -817,40 +817,83 @@ __device__ __forceinline__ void sort_row_wave(int32_t* __restrict__ col, uint32_
   }
 }
 
-// Wavefront per queued row of up to kSegWave entries, sorted in the lanes'
-// registers (bitonic_wave) at the power of two that holds it.
+// Bitonic sort of one value per lane within each group of W aligned lanes
+// (W a power of two up to 64), every group ascending: the network of
+// bitonic_wave<1> stopped at width W, its last merge ascending everywhere.
+template <uint32_t W>
+__device__ __forceinline__ void bitonic_groups(int32_t& v, uint32_t l) {
+#pragma unroll
+  for (uint32_t k = 2; k <= W; k <<= 1) {
+#pragma unroll
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      const int32_t y = __shfl_xor(v, (int)j, kWave);
+      const bool up = k == W || (l & k) == 0;
+      const bool low = (l & j) == 0;
+      v = (low == up) ? min(v, y) : max(v, y);
+    }
+  }
+}
+
+// col[s, s+len) sorted by one wavefront at the power of two that holds it.
+__device__ __forceinline__ void sort_mid_row(int32_t* __restrict__ col, uint32_t s, uint32_t len, uint32_t l) {
+  if (len > kSegWave) return;
+  if (len <= 64u) sort_row_wave<1>(col, s, len, l);
+  else if (len <= 128u) sort_row_wave<2>(col, s, len, l);
+  else if (len <= 256u) sort_row_wave<4>(col, s, len, l);
+  else if (len <= 512u) sort_row_wave<8>(col, s, len, l);
+  else sort_row_wave<16>(col, s, len, l);
+}
+
+// Wavefront per pair of queued rows of up to kSegWave entries, sorted in the
+// lanes' registers (bitonic_wave) at the power of two that holds each; two
+// rows of at most 32 entries are sorted together, one per half-wavefront.
 __global__ __launch_bounds__(kThreads) void k_segsort_mid(const uint32_t* __restrict__ rp, int32_t* __restrict__ col,
                                                           const uint32_t* __restrict__ midrows,
                                                           const uint32_t* __restrict__ q) {
   static_assert(kSegWave == 16 * kWave, "rows of up to 16 entries per lane");
   const uint32_t l = (uint32_t)lane_id();
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
-  const uint32_t cnt = q[2];
-  // the row after next is looked up and the next row's bounds are loaded
-  // while this row is sorted, so that a row costs one round trip to memory
+  const int64_t step = 2 * (((int64_t)gridDim.x * blockDim.x) / kWave);
+  const int64_t cnt = q[2];
+  // the pair after next is looked up and the next pair's bounds are loaded
+  // while this pair is sorted, so that a pair costs one round trip to memory
   // instead of three
-  int64_t i = wave;
-  uint32_t s = 0, len = 0, rn = 0;
+  int64_t i = 2 * wave;
+  uint32_t sa = 0, la = 0, sb = 0, lb = 0, na = 0, nb = 0;
   if (i < cnt) {
     const uint32_t r = midrows[i];
-    s = rp[r];
-    len = rp[r + 1] - s;
+    sa = rp[r];
+    la = rp[r + 1] - sa;
   }
-  if (i + nwaves < cnt) rn = midrows[i + nwaves];
-  for (; i < cnt; i += nwaves) {
-    const uint32_t cs = s, clen = len;
-    if (i + nwaves < cnt) {
-      s = rp[rn];
-      len = rp[rn + 1] - s;
-      if (i + 2 * nwaves < cnt) rn = midrows[i + 2 * nwaves];
+  if (i + 1 < cnt) {
+    const uint32_t r = midrows[i + 1];
+    sb = rp[r];
+    lb = rp[r + 1] - sb;
+  }
+  if (i + step < cnt) na = midrows[i + step];
+  if (i + step + 1 < cnt) nb = midrows[i + step + 1];
+  for (; i < cnt; i += step) {
+    const uint32_t csa = sa, cla = la, csb = sb, clb = i + 1 < cnt ? lb : 0u;
+    if (i + step < cnt) {
+      sa = rp[na];
+      la = rp[na + 1] - sa;
+      if (i + step + 1 < cnt) {
+        sb = rp[nb];
+        lb = rp[nb + 1] - sb;
+      }
+      if (i + 2 * step < cnt) na = midrows[i + 2 * step];
+      if (i + 2 * step + 1 < cnt) nb = midrows[i + 2 * step + 1];
     }
-    if (clen > kSegWave) continue;
-    if (clen <= 64u) sort_row_wave<1>(col, cs, clen, l);
-    else if (clen <= 128u) sort_row_wave<2>(col, cs, clen, l);
-    else if (clen <= 256u) sort_row_wave<4>(col, cs, clen, l);
-    else if (clen <= 512u) sort_row_wave<8>(col, cs, clen, l);
-    else sort_row_wave<16>(col, cs, clen, l);
+    if (cla <= 32u && clb <= 32u) {
+      const uint32_t hl = l & 31u;
+      const uint32_t s = l < 32u ? csa : csb, len = l < 32u ? cla : clb;
+      int32_t v = hl < len ? col[s + hl] : 0x7FFFFFFF;
+      bitonic_groups<32>(v, l);
+      if (hl < len) col[s + hl] = v;
+    } else {
+      sort_mid_row(col, csa, cla, l);
+      if (clb) sort_mid_row(col, csb, clb, l);
+    }
   }
 }
 
