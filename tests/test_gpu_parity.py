@@ -138,6 +138,18 @@ def test_random_small_graphs(seed):
         check(g, plan, per, tot, deep=(p == 2))
 
 
+@pytest.mark.parametrize("avg,seed", [(40.0, 1), (64.0, 2), (90.0, 3)])
+def test_rows_of_17_to_64_entries_sorted(avg, seed):
+    """Degree-ordered ER graphs whose out- and in-rows mostly hold 17-64
+    entries: the rows sorted two per wavefront (up to 32 entries each) and one
+    per wavefront, with odd and even numbers of such rows; the oriented CSR
+    is compared with the oracle's entry by entry."""
+    g = graphgen.er_avgdeg(3000 + seed, avg, seed)
+    for p in (1, 2, 7):
+        plan, per, tot = run(g, p=p)
+        check(g, plan, per, tot, deep=True)
+
+
 # ---------------------------------------------------------------- R-MAT sweeps
 @pytest.mark.parametrize("name", ["rmat10", "rmat12", "rmat14_ef8"])
 @pytest.mark.parametrize("p", [1, 4, 16, 61])
